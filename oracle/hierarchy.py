@@ -1,0 +1,166 @@
+"""Aggregation hierarchies {A_l, P_l, R_l} with orthonormal P and R = P^H.
+
+Test infrastructure (see the package docstring).
+
+Sec. 4.1 defines the hierarchy: coarse operators A_{l+1} = R_l A_l P_l
+(Petrov-Galerkin), P_l = R_l^* for Hermitian A.  Remark 4.3 treats the case
+R_l P_l = I of aggregation with orthonormal columns, which is what every
+hierarchy here is:
+* 2D: 2x2 blocks of grid points form an aggregate; P has entry 1/2 in each of
+  the four rows of an aggregate (orthonormal piecewise constants).
+* 3D: 2x2x2 blocks, entries 1/sqrt(8).
+* Wilson: b x b blocks of lattice sites form an aggregate; P restricted to one
+  aggregate is an orthonormal basis of the span of n_vec near-null test
+  vectors restricted to that aggregate (Example 4.3, the aggregation sketch:
+  components of approximate small eigenvectors assembled over aggregates and
+  orthogonalised).
+The Galerkin product is formed here as a plain sparse product R A P.
+"""
+import numpy as np
+import scipy.sparse as sp
+
+from . import philox
+
+
+def aggregation_2d(N):
+    """Orthonormal 2x2 aggregation P in R^{N^2 x (N/2)^2} (index iy*N + ix)."""
+    assert N % 2 == 0
+    Nc = N // 2
+    iy, ix = np.divmod(np.arange(N * N), N)
+    cols = (iy // 2) * Nc + (ix // 2)
+    return sp.csr_matrix((np.full(N * N, 0.5), (np.arange(N * N), cols)),
+                         shape=(N * N, Nc * Nc))
+
+
+def aggregation_3d(N):
+    """Orthonormal 2x2x2 aggregation P in R^{N^3 x (N/2)^3}."""
+    assert N % 2 == 0
+    Nc = N // 2
+    i = np.arange(N ** 3)
+    z, rem = np.divmod(i, N * N)
+    y, x = np.divmod(rem, N)
+    cols = ((z // 2) * Nc + (y // 2)) * Nc + (x // 2)
+    return sp.csr_matrix((np.full(N ** 3, 1.0 / np.sqrt(8.0)), (i, cols)),
+                         shape=(N ** 3, Nc ** 3))
+
+
+def galerkin(A, P):
+    """A_{l+1} = R_l A_l P_l with R_l = P_l^H (Sec. 4.1)."""
+    return (P.conj().T @ A @ P).tocsr()
+
+
+def poisson_hierarchy(N, levels, diag=4.0, off=1.0):
+    """A_1..A_levels and P_1..P_{levels-1} for the 2D Poisson operator."""
+    from .operators import poisson2d
+    A = [poisson2d(N, diag, off)]
+    P = []
+    n = N
+    for _ in range(levels - 1):
+        P.append(aggregation_2d(n))
+        A.append(galerkin(A[-1], P[-1]))
+        n //= 2
+    return A, P
+
+
+def varcoef_hierarchy(N, k, shift, levels):
+    """A_1..A_levels and P_1..P_{levels-1} for the 3D diffusion operator."""
+    from .operators import varcoef3d
+    A = [varcoef3d(N, k, shift)]
+    P = []
+    n = N
+    for _ in range(levels - 1):
+        P.append(aggregation_3d(n))
+        A.append(galerkin(A[-1], P[-1]))
+        n //= 2
+    return A, P
+
+
+# ---------------------------------------------------------------------------
+# Wilson: test-vector aggregation
+# ---------------------------------------------------------------------------
+
+def site_coloring(N):
+    """Red (0) / black (1) colour of each site of an N x N lattice: (x+y) mod 2."""
+    y, x = np.divmod(np.arange(N * N), N)
+    return (x + y) % 2
+
+
+def block_rbgs_sweep(A, v, N, dof, b=None):
+    """One red-black block Gauss-Seidel sweep for A v = b (b = 0 by default).
+
+    Sites of colour 0 are updated first, then colour 1; each site's dof x dof
+    diagonal block is solved exactly: v_S <- A_SS^{-1} (b_S - A_{S,rest} v_rest).
+    """
+    n = A.shape[0]
+    if b is None:
+        b = np.zeros(n, dtype=A.dtype)
+    colour = np.repeat(site_coloring(N), dof)
+    A = A.tocsr()
+    for c in (0, 1):
+        m = colour == c
+        Amm = A[m][:, m]       # block diagonal (a site has no same-colour neighbour)
+        rhs = b[m] - A[m][:, ~m] @ v[~m]
+        v = v.copy()
+        v[m] = sp.linalg.spsolve(Amm.tocsc(), rhs)
+    return v
+
+
+def orthonormal_basis(V):
+    """Q of V = Q R with R upper triangular and a real positive diagonal."""
+    Q, R = np.linalg.qr(V)
+    d = np.diag(R)
+    phase = d / np.abs(d)
+    return Q * np.conj(phase)[None, :]
+
+
+def testvector_aggregation(A, N, dof, block, n_vec, sweeps, seed, level):
+    """Aggregation P for a lattice operator with `dof` unknowns per site.
+
+    Test vectors: n_vec Z4 start vectors (stream 2, sample j, this level), then
+    `sweeps` red-black block Gauss-Seidel sweeps on A v = 0.  Aggregates are
+    block x block site squares; within each, the n_vec restricted vectors are
+    orthonormalised (QR with positive diagonal).  Coarse site S = Y*Nc + X,
+    coarse unknown S*n_vec + j.
+    """
+    n = A.shape[0]
+    assert n == N * N * dof and N % block == 0
+    V = np.empty((n, n_vec), dtype=np.complex128)
+    for j in range(n_vec):
+        v = philox.z4(n, seed, j, level, stream=philox.STREAM_TESTVEC)
+        for _ in range(sweeps):
+            v = block_rbgs_sweep(A, v, N, dof)
+        V[:, j] = v
+    Nc = N // block
+    rows, cols, vals = [], [], []
+    for Y in range(Nc):
+        for X in range(Nc):
+            S = Y * Nc + X
+            idx = []
+            for yy in range(block):
+                for xx in range(block):
+                    s = (Y * block + yy) * N + (X * block + xx)
+                    idx += [s * dof + a for a in range(dof)]
+            Q = orthonormal_basis(V[idx, :])
+            for r, i in enumerate(idx):
+                for j in range(n_vec):
+                    rows.append(i)
+                    cols.append(S * n_vec + j)
+                    vals.append(Q[r, j])
+    P = sp.csr_matrix((np.array(vals), (rows, cols)), shape=(n, Nc * Nc * n_vec))
+    return P, V
+
+
+def wilson_hierarchy(N, theta, m0, levels, block=4, n_vec=8, sweeps=20, seed=1):
+    """A_1..A_levels, P_1..P_{levels-1} for the Wilson operator (Example 4.3)."""
+    from .operators import wilson2d
+    A = [wilson2d(N, theta, m0)]
+    P = []
+    n_side, dof = N, 2
+    for lvl in range(1, levels):
+        Pl, _ = testvector_aggregation(A[-1], n_side, dof, block, n_vec, sweeps,
+                                       seed, lvl)
+        P.append(Pl)
+        A.append(galerkin(A[-1], Pl))
+        n_side //= block
+        dof = n_vec
+    return A, P

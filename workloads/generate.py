@@ -1,0 +1,71 @@
+"""Seeded synthetic operator data and workload parameter sets.
+
+Stand-ins for the paper's matrices (Sec. 5): the Laplace example is generated
+exactly; the thermalized Schwinger configuration and the pyAMG gauge-Laplacian
+generator are not available, so U(1) link phases are drawn i.i.d. Gaussian;
+the 3D diffusion batch uses log-normal face coefficients.
+"""
+import json
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def gauge_field(N, sigma=0.5, seed=1):
+    """Link phases theta[mu, y, x] ~ N(0, sigma^2) i.i.d. on an N x N lattice."""
+    rng = np.random.default_rng(np.random.SeedSequence([0x6A09E667, 3, seed, N]))
+    return rng.normal(0.0, sigma, size=(2, N, N))
+
+
+def varcoef_faces(N, sigma=1.0, seed=1000):
+    """Face coefficients k = exp(g), g ~ N(0, sigma^2), shape [3, N, N, N+1]."""
+    rng = np.random.default_rng(np.random.SeedSequence([0x6A09E667, 4, seed, N]))
+    return np.exp(rng.normal(0.0, sigma, size=(3, N, N, N + 1)))
+
+
+def batch_problem_sizes(count=32, lo=32, hi=128, step=8, seed=7):
+    """Grid sides drawn uniformly from the multiples of `step` in [lo, hi]."""
+    rng = np.random.default_rng(np.random.SeedSequence([0x6A09E667, 6, seed]))
+    choices = np.arange(lo, hi + 1, step)
+    return [int(v) for v in rng.choice(choices, size=count)]
+
+
+def wilson_mass(N):
+    """m0 for the Wilson workload at lattice side N (tuned on the CPU so that the
+    smallest |eigenvalue| is about 1e-2), or None if not tuned yet."""
+    path = os.path.join(_HERE, "wilson_mass.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        table = json.load(f)
+    v = table.get(str(N))
+    return None if v is None else float(v["m0"])
+
+
+# Workload parameter sets.  Level counts are L_mlmc (levels of the trace
+# decomposition) and L_solver (levels of the multigrid solver).
+WORKLOADS = {
+    "poisson64_fp64": dict(
+        kind="poisson2d", N=64, levels_mlmc=3, levels_solver=3, nb=128,
+        precision="fp64", eps=1e-2, solve_tol=1e-12, seeds=[1, 2, 3, 4, 5]),
+    "poisson1024_fp32ir": dict(
+        kind="poisson2d", N=1024, levels_mlmc=6, levels_solver=6, nb=128,
+        precision="fp32_ir64", eps=1e-3, solve_tol=1e-10, seeds=[1, 2, 3, 4, 5]),
+    "wilson256_c64ir": dict(
+        kind="wilson2d", N=256, levels_mlmc=3, levels_solver=3, nb=128,
+        precision="fp32_ir64", eps=1e-3, solve_tol=1e-10, block=4, n_vec=8,
+        setup_sweeps=20, theta_sigma=0.5, gauge_seed=1),
+    "varcoef3d_batch32": dict(
+        kind="varcoef3d", count=32, lo=32, hi=128, nb=64, precision="fp32_ir64",
+        shift=1e-3, coef_sigma=1.0, solve_tol=1e-10),
+    "wilson512_learned": dict(
+        kind="wilson2d", N=512, levels_mlmc=3, levels_solver=4, nb=128,
+        precision="fp32_ir64", eps=1e-3, solve_tol=1e-10, block=4, n_vec=8,
+        setup_sweeps=20, theta_sigma=0.5, gauge_seed=1, learned=True),
+}
+
+
+def workload(name):
+    return dict(WORKLOADS[name])
