@@ -1,0 +1,249 @@
+/*
+ * mlmc.h -- C ABI of the MI355X (gfx950) library for multilevel Monte-Carlo
+ * estimation of tr(A^{-1}) over an aggregation multigrid hierarchy.
+ *
+ * Method: Frommer, Nasr Khalil, Ramirez-Hidalgo, "A Multilevel Approach to
+ * Variance Reduction in the Stochastic Estimation of the Trace of a Matrix"
+ * (arXiv 2108.11281).  The operator A = A_1 is known only through products
+ * (Sec. 3, opening paragraph); a hierarchy {A_l, P_l, R_l} with
+ * A_{l+1} = R_l A_l P_l is built (Sec. 4.1); with orthonormal aggregation
+ * (R_l = P_l^H, R_l P_l = I) the trace splits as in Remark 4.3:
+ *   tr(A^{-1}) = sum_{l<L} [tr(A_l^{-1}) - tr(P_l A_{l+1}^{-1} R_l)] + tr(A_L^{-1}),
+ * each bracket estimated from samples x^H A_l^{-1} x - (R_l x)^H A_{l+1}^{-1} (R_l x)
+ * and the last term computed directly by inverting A_L (Remark 4.2).
+ *
+ * Conventions (all entry points):
+ *  - Every function returns an int status: MLMC_OK (0) or a negative error
+ *    code.  Nothing aborts and no C++ exception crosses the ABI.  After an
+ *    error on a context, mlmc_last_error() describes it.
+ *  - Levels are 1-based as in the paper: level 1 is the given operator.
+ *  - Pointers named *_dev are device pointers on the context's device;
+ *    everything else is host memory.  The caller owns every buffer it passes;
+ *    the library copies what it keeps (operator data is copied at setup).
+ *  - Complex vectors are interleaved (re, im) doubles; a block of nrhs vectors
+ *    of length n is stored vector after vector ("RHS-major"):
+ *    element i of vector k is at [k*n + i].
+ *  - All work runs on the HIP stream given to mlmc_setup (NULL = default
+ *    stream).  One context must not be used from two threads at once.
+ *  - Sample k of level l for seed s is a pure function of (s, l, k): a
+ *    Philox4x64-10 counter RNG gives the probe entries (Rademacher for real
+ *    operators, Z4 for complex ones; Sec. 3, eqs. iid_components1/2).
+ */
+#ifndef MLMC_H
+#define MLMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum mlmc_status {
+  MLMC_OK = 0,
+  MLMC_EINVAL = -1,       /* invalid argument or descriptor */
+  MLMC_ENOMEM = -2,       /* device or host allocation failed */
+  MLMC_EDEVICE = -3,      /* HIP runtime error (no device, launch failure) */
+  MLMC_ENOCONV = -4,      /* a solve or the estimator did not converge */
+  MLMC_ESTATE = -5,       /* call not valid in the context's state */
+  MLMC_EUNSUPPORTED = -6  /* combination not implemented */
+};
+
+enum mlmc_kind {
+  MLMC_POISSON2D = 0,  /* A = diag*I - off*(4 grid neighbours), N x N, Dirichlet
+                          (Example 4.1 with diag = 4, off = 1) */
+  MLMC_WILSON2D = 1,   /* (m0+2) I - 1/2 sum_mu [(I - s_mu) U_mu(x) d_{x+mu}
+                          + (I + s_mu) U_mu(x-mu)^* d_{x-mu}], 2 spins, N x N
+                          periodic (Example 4.3 halved, m0 = m/2) */
+  MLMC_VARCOEF3D = 2   /* 7-point diffusion with face coefficients, N^3,
+                          Dirichlet faces, plus shift*I */
+};
+
+enum mlmc_precision {
+  MLMC_FP64 = 0,       /* every solve in FP64 (plain FP64 MLMC) */
+  MLMC_FP32_IR64 = 1   /* FP32 (complex64) Krylov + V-cycle inside FP64
+                          iterative refinement; FP64 residual decides */
+};
+
+enum mlmc_alloc {
+  MLMC_ALLOC_EQUAL = 0,   /* rho_l^2 = (eps tau)^2/(L-1)  (Sec. 5 default) */
+  MLMC_ALLOC_WEIGHTS = 1, /* rho_l^2 = w_l (eps tau)^2, given w (Example 4.3) */
+  MLMC_ALLOC_GILES = 2    /* optimal N_l ~ sqrt(V_l/C_l) (Sec. 2), V_l from the
+                             samples so far, C_l = n_l + n_{l+1} */
+};
+
+/* Operator A = A_1.  Host data, copied at setup. */
+typedef struct mlmc_operator {
+  int kind;           /* enum mlmc_kind */
+  int n_side;         /* grid / lattice side N (all directions) */
+  double diag, off;   /* POISSON2D coefficients (Example 4.1: 4, 1) */
+  double mass;        /* WILSON2D: m0 */
+  double shift;       /* VARCOEF3D: shift (>= 0) */
+  const double* field;/* WILSON2D: link phases theta[2][N][N] (mu, y, x);
+                         VARCOEF3D: face coefficients k[3][N][N][N+1]
+                         (x-faces [z][y][f], y-faces [z][x][f], z-faces [y][x][f],
+                          face f between cells f-1 and f); unused for POISSON2D */
+} mlmc_operator;
+
+/* Hierarchy description (Sec. 4.1; solver levels may exceed MLMC levels, Sec. 5). */
+typedef struct mlmc_hierarchy {
+  int levels_solver;  /* L_s: levels of the multigrid solver (>= 2) */
+  int levels_mlmc;    /* L <= L_s: levels of the trace decomposition (>= 2) */
+  int block;          /* WILSON2D: aggregate side in sites (4) */
+  int n_vec;          /* WILSON2D: test vectors = coarse dofs per site (8) */
+  int setup_sweeps;   /* WILSON2D: smoothing sweeps on A v = 0 per test vector */
+  uint64_t setup_seed;/* WILSON2D: seed of the test-vector start vectors */
+} mlmc_hierarchy;
+
+typedef struct mlmc_options {
+  int precision;      /* enum mlmc_precision */
+  int nb;             /* maximum right-hand sides per launch (1..1024) */
+  int nu_pre, nu_post;/* red-black Gauss-Seidel sweeps before/after the coarse
+                         correction in the V-cycle */
+  double omega;       /* coarse-correction scaling in the V-cycle (1 = none) */
+  int alloc;          /* enum mlmc_alloc */
+  const double* rho_weights; /* MLMC_ALLOC_WEIGHTS: L-1 weights (host) */
+  double solve_tol;   /* per-column FP64 relative residual |b-Ay|/|b| target */
+  double inner_tol;   /* FP32 inner solve: relative residual reduction per
+                         refinement step */
+  int max_iter;       /* Krylov iterations per solve (per refinement step) */
+  int max_refine;     /* refinement steps (MLMC_FP32_IR64) */
+  int krylov_restart; /* FGMRES restart length (complex operators) */
+  int min_samples;    /* minimum estimates per level difference (5) */
+  int64_t max_samples;/* per-level cap; exceeding it returns MLMC_ENOCONV */
+  double tau;         /* > 0: use this tau instead of the 5-sample pilot */
+  int learned;        /* 1: learned smoother (WILSON2D), 0: plain */
+} mlmc_options;
+
+#define MLMC_MAX_LEVELS 16
+
+typedef struct mlmc_result {
+  double trace[2];            /* estimate of tr(A^{-1}) (re, im) */
+  double rmsd;                /* sqrt(sum_l V_l/N_l) */
+  double tau;                 /* pilot value used for the target eps*tau */
+  double coarse_trace[2];     /* tr(A_L^{-1}) */
+  int levels;                 /* L */
+  int64_t n_samples[MLMC_MAX_LEVELS];   /* N_l, l = 1..L-1 at [l-1] */
+  double level_mean[MLMC_MAX_LEVELS][2];
+  double level_var[MLMC_MAX_LEVELS];
+  double level_cost[MLMC_MAX_LEVELS];   /* cost model C_l */
+  int64_t solves;             /* right-hand sides solved, all levels */
+  int64_t iterations;         /* Krylov iterations x RHS columns, all solves */
+  double seconds;             /* wall time of the call */
+  double max_stated_error;    /* largest stated FP64 error of any sample */
+} mlmc_result;
+
+/* Fill *opt with defaults: FP32_IR64, nb 128, 1+1 sweeps, omega 1.8, EQUAL,
+ * solve_tol 1e-10, inner_tol 1e-5, max_iter 200, max_refine 8, restart 16,
+ * min_samples 5, max_samples 2^22, tau 0, learned 0. */
+int mlmc_default_options(mlmc_options* opt);
+
+/* Build the hierarchy on the device: copies the operator data, forms the
+ * aggregation P_l and Galerkin A_{l+1} = P_l^H A_l P_l (Sec. 4.1), and inverts
+ * the coarsest operators in FP64 (the MLMC level L for the direct trace term of
+ * Remark 4.2, the solver level L_s for the V-cycle).  hip_stream: a
+ * hipStream_t or NULL.  On success *out owns device memory until
+ * mlmc_destroy.  Errors: EINVAL for inconsistent sizes (a grid side that is not
+ * divisible by the aggregate side at every level, L > L_s, nb out of range),
+ * EDEVICE/ENOMEM from the runtime. */
+int mlmc_setup(const mlmc_operator* A, const mlmc_hierarchy* h,
+               const mlmc_options* opt, void* hip_stream, void** out_ctx);
+
+/* MLMC estimate of tr(A^{-1}) to relative accuracy tol (Sec. 5): tau from five
+ * pilot Hutchinson estimates (or opt.tau), per-level RMSD targets rho_l with
+ * sum rho_l^2 = (tol*tau)^2, at least min_samples per level difference,
+ * batches of at most nb samples, coarsest term exact.  Fills *out. */
+int mlmc_trace(void* ctx, double tol, uint64_t seed, mlmc_result* out);
+
+/* Plain Hutchinson estimate (eq. plain_tr_estimate) on level 1 with the same
+ * tau rule and batch rule, for comparison.  Fills trace, rmsd, tau,
+ * n_samples[0], solves, seconds. */
+int mlmc_hutchinson(void* ctx, double tol, uint64_t seed, mlmc_result* out);
+
+/* Level-difference samples s_{l,k}, k = first .. first+nsamples-1:
+ *   s = x^H A_l^{-1} x - (R_l x)^H A_{l+1}^{-1} (R_l x),  x = probe(seed, l, k),
+ * 1 <= level < L (level L is not sampled: use mlmc_coarse_trace).
+ * out: host, nsamples x 2 doubles (re, im).  out_err: host, nsamples doubles,
+ * or NULL: the stated FP64 error of each sample (relative to |x^H y| +
+ * |(Rx)^H z|) -- the contribution of the last refinement correction, or the
+ * final relative residual in MLMC_FP64 mode.  Any nsamples >= 1 is accepted
+ * (split into launches of at most nb). */
+int mlmc_sample_level(void* ctx, int level, uint64_t seed, int64_t first,
+                      int64_t nsamples, double* out, double* out_err);
+
+/* tr(A_L^{-1}) computed at setup by inverting A_L (Remark 4.2). out: 2 doubles. */
+int mlmc_coarse_trace(void* ctx, double* out);
+
+/* n_l, the number of unknowns of level l (1 <= l <= L_s). */
+int mlmc_level_size(void* ctx, int level, int64_t* n);
+
+/* Y = A_l^{-1} B for nrhs <= nb vectors: the solver used by the samples
+ * (precision and tolerance from the options).  b_dev, y_dev: FP64 (complex:
+ * interleaved) RHS-major blocks of nrhs vectors of n_l.  relres: host, nrhs
+ * doubles or NULL, final FP64 relative residuals.  ENOCONV if a column misses
+ * solve_tol within max_refine x max_iter. */
+int mlmc_solve(void* ctx, int level, int nrhs, const double* b_dev,
+               double* y_dev, double* relres);
+
+/* Y = A_l X in FP64 (the FP64 operator of level l). */
+int mlmc_apply(void* ctx, int level, int nrhs, const double* x_dev, double* y_dev);
+
+/* Xc = R_l X = P_l^H X (restriction to level l+1), FP64, 1 <= l < L_s. */
+int mlmc_restrict(void* ctx, int level, int nrhs, const double* x_dev, double* xc_dev);
+
+/* X = P_l Xc (prolongation from level l+1), FP64, 1 <= l < L_s. */
+int mlmc_prolong(void* ctx, int level, int nrhs, const double* xc_dev, double* x_dev);
+
+/* Probe block: vectors k = first..first+nrhs-1 of level l, stream `stream`
+ * (0 level probes, 1 pilot, 3 Hutchinson), written as FP64 (complex:
+ * interleaved) to out_dev [nrhs][n_l]. */
+int mlmc_probes(void* ctx, int level, uint64_t seed, int stream, int64_t first,
+                int nrhs, double* out_dev);
+
+/* Copy the dense FP64 coarsest operator A_{L_s} (or A_L if which == 1) to host
+ * memory, n x n row-major (complex: interleaved).  For inspection and tests. */
+int mlmc_export_coarse(void* ctx, int which, double* out);
+
+/* WILSON2D: copy the aggregation basis of level l (1 <= l < L_s) to host memory
+ * as n_l x n_vec complex values: row i holds the n_vec coefficients of unknown
+ * i in the basis of its aggregate (Example 4.3 aggregation sketch). */
+int mlmc_export_prolongation(void* ctx, int level, double* out);
+
+/* Host-side estimator driver over a caller-supplied sampler (no device use).
+ * sample(user, level, first, count, out): write count samples of level l as
+ * (re, im) pairs; return 0 or a negative status.  pilot(user, count, out):
+ * five (or count) plain Hutchinson samples for tau; may be NULL if opt->tau > 0.
+ * coarse: tr(A_L^{-1}) (re, im).  cost: C_l for l = 1..L-1 (NULL = all 1).
+ * Same control as mlmc_trace. */
+typedef int (*mlmc_sample_fn)(void* user, int level, int64_t first, int64_t count,
+                              double* out);
+typedef int (*mlmc_pilot_fn)(void* user, int64_t count, double* out);
+int mlmc_run_estimator(int levels, mlmc_sample_fn sample, mlmc_pilot_fn pilot,
+                       void* user, const double* coarse, const double* cost,
+                       const mlmc_options* opt, double tol, mlmc_result* out);
+
+/* Device memory hooks (e.g. a framework's caching allocator).  Applies to
+ * contexts created afterwards.  alloc returns NULL on failure.  Pass NULLs to
+ * restore hipMalloc/hipFree. */
+typedef void* (*mlmc_alloc_fn)(size_t bytes, void* user);
+typedef void (*mlmc_free_fn)(void* ptr, void* user);
+int mlmc_set_allocator(mlmc_alloc_fn alloc, mlmc_free_fn free_fn, void* user);
+
+/* Counters of the last mlmc_trace / mlmc_sample_level / mlmc_solve call:
+ * out[0] Krylov iterations (per batch), out[1] refinement steps,
+ * out[2] V-cycles, out[3] batches.  n: entries to copy (<= 4). */
+int mlmc_counters(void* ctx, int64_t* out, int n);
+
+/* Description of the last error on ctx (or of the last failed mlmc_setup
+ * when ctx is NULL).  Valid until the next call on ctx. */
+const char* mlmc_last_error(const void* ctx);
+
+const char* mlmc_status_string(int status);
+
+/* Free everything the context owns.  NULL is ignored. */
+void mlmc_destroy(void* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MLMC_H */

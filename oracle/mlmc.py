@@ -241,3 +241,77 @@ def hutchinson_trace(sampler, eps, seed, nb=128, min_samples=5, tau=None,
         s += list(sampler.hutchinson(seed, N, add))
     m, v = mean_and_var(s)
     return dict(trace=m, rmsd=math.sqrt(v / len(s)), tau=tau, n_samples=len(s))
+
+
+class PoissonDSTSampler(LevelSampler):
+    """Exact samples for the 2D Poisson hierarchy at sizes where sparse LU is slow.
+
+    Uses A_l = 2^{1-l} (diag I - off neighbours) on the N_l = N/2^{l-1} grid --
+    the Galerkin identity of 2x2 orthonormal aggregation (checked against the
+    sparse Galerkin product in the tests) -- and the exact sine-transform solver.
+    """
+
+    def __init__(self, N, levels, diag=4.0, off=1.0):
+        from .hierarchy import aggregation_2d
+        self.N = N
+        self.L = levels
+        self.diag = diag
+        self.off = off
+        self.complex_probe = False
+        self.problem = 0
+        self.sides = [N >> l for l in range(levels)]
+        self.P = [aggregation_2d(self.sides[l]) for l in range(levels - 1)]
+        self.A = None
+
+    def coeffs(self, level):
+        s = 2.0 ** (1 - level)
+        # diag' = diag - 2 off, off' = off/2 per level: exact scaling when diag = 4 off
+        d, c = self.diag, self.off
+        for _ in range(level - 1):
+            d, c = d - 2.0 * c, 0.5 * c
+        return d, c
+
+    def size(self, level):
+        return self.sides[level - 1] ** 2
+
+    def probes(self, level, seed, first, count, stream=philox.STREAM_PROBE):
+        n = self.size(level)
+        return np.stack([philox.probe(n, seed, first + j, level, False, stream)
+                         for j in range(count)], axis=1)
+
+    def _solve(self, level, B):
+        from .operators import poisson2d_solve_dst
+        d, c = self.coeffs(level)
+        return poisson2d_solve_dst(self.sides[level - 1], B, d, c)
+
+    def sample(self, level, seed, first, count):
+        X = self.probes(level, seed, first, count)
+        Y = self._solve(level, X)
+        Xc = self.P[level - 1].T @ X
+        Z = self._solve(level + 1, Xc)
+        return np.array([quad(X[:, j], Y[:, j]) - quad(Xc[:, j], Z[:, j])
+                         for j in range(count)])
+
+    def sample_parts(self, level, seed, first, count):
+        X = self.probes(level, seed, first, count)
+        Y = self._solve(level, X)
+        Xc = self.P[level - 1].T @ X
+        Z = self._solve(level + 1, Xc)
+        return (np.array([quad(X[:, j], Y[:, j]) for j in range(count)]),
+                np.array([quad(Xc[:, j], Z[:, j]) for j in range(count)]))
+
+    def hutchinson(self, seed, first, count, stream=philox.STREAM_HUTCH, level=1):
+        X = self.probes(level, seed, first, count, stream)
+        Y = self._solve(level, X)
+        return np.array([quad(X[:, j], Y[:, j]) for j in range(count)])
+
+    def coarse(self):
+        from .operators import poisson2d_eigenvalues
+        d, c = self.coeffs(self.L)
+        Nl = self.sides[-1]
+        lam = poisson2d_eigenvalues(Nl)         # of 4I - neighbours
+        # d I - c neighbours = c (4I - neighbours) + (d - 4c) I
+        return complex(np.sum(1.0 / (c * lam + (d - 4.0 * c))))
+
+    def cost(self, level):
+        return float(self.size(level) + self.size(level + 1))

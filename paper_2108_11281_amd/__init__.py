@@ -1,0 +1,323 @@
+"""MI355X (gfx950) multilevel Monte-Carlo estimation of tr(A^{-1}).
+
+Thin Python binding of the C ABI in include/mlmc.h.  Every step of the method
+runs in the HIP library libmlmc.so; this module only marshals arguments,
+passes torch's device memory and stream, and converts results.  If the library
+has not been built, importing the binding raises: there is no CPU fallback.
+"""
+import ctypes
+
+import numpy as np
+
+from . import _capi
+from ._capi import (ALLOC_EQUAL, ALLOC_GILES, ALLOC_WEIGHTS, FP32_IR64, FP64,  # noqa: F401
+                    POISSON2D, VARCOEF3D, WILSON2D)
+
+KINDS = {"poisson2d": POISSON2D, "wilson2d": WILSON2D, "varcoef3d": VARCOEF3D}
+PRECISIONS = {"fp64": FP64, "fp32_ir64": FP32_IR64}
+ALLOCS = {"equal": ALLOC_EQUAL, "weights": ALLOC_WEIGHTS, "giles": ALLOC_GILES}
+
+
+class MLMCError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (_status(code), code, msg))
+        self.code = code
+
+
+def lib():
+    return _capi.load()
+
+
+def _status(code):
+    return lib().mlmc_status_string(code).decode()
+
+
+def _check(rc, ctx=None):
+    if rc != 0:
+        msg = lib().mlmc_last_error(ctx)
+        raise MLMCError(rc, msg.decode() if msg else "")
+
+
+def default_options():
+    o = _capi.Options()
+    _check(lib().mlmc_default_options(ctypes.byref(o)))
+    return o
+
+
+def _result_dict(r):
+    L = max(r.levels, 1)
+    nl = L - 1 if L > 1 else 1
+    return dict(
+        trace=complex(r.trace[0], r.trace[1]), rmsd=r.rmsd, tau=r.tau,
+        coarse=complex(r.coarse_trace[0], r.coarse_trace[1]), levels=r.levels,
+        n_samples=[int(r.n_samples[i]) for i in range(nl)],
+        level_mean=[complex(r.level_mean[i][0], r.level_mean[i][1]) for i in range(nl)],
+        level_var=[r.level_var[i] for i in range(nl)],
+        level_cost=[r.level_cost[i] for i in range(nl)],
+        solves=int(r.solves), iterations=int(r.iterations), seconds=r.seconds)
+
+
+# ---------------------------------------------------------------------------
+# torch's caching allocator as the library's device allocator
+# ---------------------------------------------------------------------------
+_alloc_refs = []
+
+
+def use_torch_allocator(enable=True):
+    """Route the library's device allocations through torch's caching allocator."""
+    if not enable:
+        _check(lib().mlmc_set_allocator(_capi.ALLOC_FN(0), _capi.FREE_FN(0), None))
+        return
+    import torch
+
+    def _alloc(nbytes, _user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes))
+        except Exception:  # reported to the library as a failed allocation
+            return None
+
+    def _free(ptr, _user):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    a, f = _capi.ALLOC_FN(_alloc), _capi.FREE_FN(_free)
+    _alloc_refs[:] = [a, f]
+    _check(lib().mlmc_set_allocator(a, f, None))
+
+
+class TraceEstimator:
+    """One operator, its hierarchy and the solvers on the current torch device.
+
+    kind: "poisson2d" | "wilson2d" | "varcoef3d"; field: numpy array of link
+    phases (wilson2d) or face coefficients (varcoef3d).  Options follow
+    mlmc_options (include/mlmc.h); unknown keyword names raise.
+    """
+
+    def __init__(self, kind, n_side, levels_solver, levels_mlmc=None, *, diag=4.0, off=1.0,
+                 mass=0.0, shift=0.0, field=None, block=4, n_vec=8, setup_sweeps=20,
+                 setup_seed=1, stream=None, torch_allocator=True, **options):
+        import torch
+        self._lib = lib()
+        self._ctx = ctypes.c_void_p()
+        if torch_allocator:
+            use_torch_allocator(True)
+        op = _capi.Operator()
+        op.kind = KINDS[kind]
+        op.n_side = int(n_side)
+        op.diag, op.off, op.mass, op.shift = float(diag), float(off), float(mass), float(shift)
+        self._field = None
+        if field is not None:
+            self._field = np.ascontiguousarray(field, dtype=np.float64)
+            op.field = self._field.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        h = _capi.Hierarchy()
+        h.levels_solver = int(levels_solver)
+        h.levels_mlmc = int(levels_mlmc if levels_mlmc is not None else levels_solver)
+        h.block, h.n_vec, h.setup_sweeps = int(block), int(n_vec), int(setup_sweeps)
+        h.setup_seed = int(setup_seed)
+        o = default_options()
+        self._weights = None
+        for k, v in options.items():
+            if k == "precision":
+                v = PRECISIONS[v] if isinstance(v, str) else int(v)
+            elif k == "alloc":
+                v = ALLOCS[v] if isinstance(v, str) else int(v)
+            elif k == "rho_weights":
+                self._weights = np.ascontiguousarray(v, dtype=np.float64)
+                o.rho_weights = self._weights.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+                continue
+            if not hasattr(o, k):
+                raise TypeError("unknown option %r" % k)
+            setattr(o, k, v)
+        self.options = o
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self._stream = stream
+        _check(self._lib.mlmc_setup(ctypes.byref(op), ctypes.byref(h), ctypes.byref(o),
+                                    ctypes.c_void_p(stream.cuda_stream),
+                                    ctypes.byref(self._ctx)), None)
+        self.kind = kind
+        self.is_complex = kind == "wilson2d"
+        self.levels_solver = h.levels_solver
+        self.levels_mlmc = h.levels_mlmc
+        self.nb = o.nb
+
+    # -- lifetime --
+    def close(self):
+        if self._ctx:
+            self._lib.mlmc_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _c(self, rc):
+        _check(rc, self._ctx)
+
+    # -- estimator --
+    def trace(self, tol, seed):
+        r = _capi.Result()
+        self._c(self._lib.mlmc_trace(self._ctx, float(tol), int(seed), ctypes.byref(r)))
+        return _result_dict(r)
+
+    def hutchinson(self, tol, seed):
+        r = _capi.Result()
+        self._c(self._lib.mlmc_hutchinson(self._ctx, float(tol), int(seed), ctypes.byref(r)))
+        return _result_dict(r)
+
+    def sample_level(self, level, seed, first, count, with_error=False):
+        out = np.zeros((count, 2))
+        err = np.zeros(count)
+        self._c(self._lib.mlmc_sample_level(
+            self._ctx, int(level), int(seed), int(first), int(count),
+            out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            err.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        s = out[:, 0] + 1j * out[:, 1]
+        return (s, err) if with_error else s
+
+    def coarse_trace(self):
+        out = np.zeros(2)
+        self._c(self._lib.mlmc_coarse_trace(self._ctx,
+                                            out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return complex(out[0], out[1])
+
+    def level_size(self, level):
+        n = ctypes.c_int64()
+        self._c(self._lib.mlmc_level_size(self._ctx, int(level), ctypes.byref(n)))
+        return n.value
+
+    def counters(self):
+        out = (ctypes.c_int64 * 4)()
+        self._c(self._lib.mlmc_counters(self._ctx, out, 4))
+        return list(out)
+
+    # -- FP64 building blocks on torch device tensors --
+    def _vec(self, level, nrhs, device=None):
+        import torch
+        n = self.level_size(level)
+        cols = 2 * n if self.is_complex else n
+        return torch.empty((nrhs, cols), dtype=torch.float64, device=device or "cuda")
+
+    @staticmethod
+    def _ptr(t):
+        import torch
+        assert t.dtype == torch.float64 and t.is_cuda and t.is_contiguous()
+        return ctypes.c_void_p(t.data_ptr())
+
+    def _sync(self):
+        self._stream.synchronize()
+
+    def solve(self, level, b):
+        """y = A_level^{-1} b for b [nrhs, n] (complex: [nrhs, 2n] interleaved)."""
+        y = self._vec(level, b.shape[0], b.device)
+        rel = np.zeros(b.shape[0])
+        self._c(self._lib.mlmc_solve(self._ctx, int(level), int(b.shape[0]), self._ptr(b),
+                                     self._ptr(y),
+                                     rel.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return y, rel
+
+    def apply(self, level, x):
+        y = self._vec(level, x.shape[0], x.device)
+        self._c(self._lib.mlmc_apply(self._ctx, int(level), int(x.shape[0]), self._ptr(x),
+                                     self._ptr(y)))
+        return y
+
+    def restrict(self, level, x):
+        y = self._vec(level + 1, x.shape[0], x.device)
+        self._c(self._lib.mlmc_restrict(self._ctx, int(level), int(x.shape[0]), self._ptr(x),
+                                        self._ptr(y)))
+        return y
+
+    def prolong(self, level, xc):
+        y = self._vec(level, xc.shape[0], xc.device)
+        self._c(self._lib.mlmc_prolong(self._ctx, int(level), int(xc.shape[0]),
+                                       self._ptr(xc), self._ptr(y)))
+        return y
+
+    def probes(self, level, seed, first, nrhs, stream=0):
+        y = self._vec(level, nrhs)
+        self._c(self._lib.mlmc_probes(self._ctx, int(level), int(seed), int(stream),
+                                      int(first), int(nrhs), self._ptr(y)))
+        return y
+
+    def export_coarse(self, which=0):
+        lvl = self.levels_mlmc if which == 1 else self.levels_solver
+        n = self.level_size(lvl)
+        out = np.zeros((n, 2 * n) if self.is_complex else (n, n))
+        self._c(self._lib.mlmc_export_coarse(self._ctx, int(which),
+                                             out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        if self.is_complex:
+            out = out[:, 0::2] + 1j * out[:, 1::2]
+        return out
+
+    def export_prolongation(self, level, n_vec):
+        n = self.level_size(level)
+        out = np.zeros((n, 2 * n_vec))
+        self._c(self._lib.mlmc_export_prolongation(
+            self._ctx, int(level), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out[:, 0::2] + 1j * out[:, 1::2]
+
+
+def run_estimator(levels, sample, tol, *, pilot=None, coarse=0.0, cost=None, **options):
+    """Host-side estimator over a Python sampler (no device use).
+
+    sample(level, first, count) -> complex array; pilot(count) -> complex array.
+    """
+    L = lib()
+    o = default_options()
+    weights = None
+    for k, v in options.items():
+        if k == "alloc":
+            v = ALLOCS[v] if isinstance(v, str) else int(v)
+        if k == "rho_weights":
+            weights = np.ascontiguousarray(v, dtype=np.float64)
+            o.rho_weights = weights.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            continue
+        if not hasattr(o, k):
+            raise TypeError("unknown option %r" % k)
+        setattr(o, k, v)
+    errors = []
+
+    def _fill(vals, count, out):
+        vals = np.asarray(vals, dtype=np.complex128)
+        assert vals.shape == (count,)
+        for i in range(count):
+            out[2 * i] = vals[i].real
+            out[2 * i + 1] = vals[i].imag
+
+    def _sample(_user, level, first, count, out):
+        try:
+            _fill(sample(level, first, count), count, out)
+            return 0
+        except Exception as e:  # reported through the status code
+            errors.append(e)
+            return -1
+
+    def _pilot(_user, count, out):
+        try:
+            _fill(pilot(count), count, out)
+            return 0
+        except Exception as e:
+            errors.append(e)
+            return -1
+
+    sf = _capi.SAMPLE_FN(_sample)
+    pf = _capi.PILOT_FN(_pilot) if pilot is not None else _capi.PILOT_FN(0)
+    cz = np.array([complex(coarse).real, complex(coarse).imag])
+    cv = None if cost is None else np.ascontiguousarray(cost, dtype=np.float64)
+    r = _capi.Result()
+    rc = L.mlmc_run_estimator(
+        int(levels), sf, pf, None, cz.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+        None if cv is None else cv.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+        ctypes.byref(o), float(tol), ctypes.byref(r))
+    if errors:
+        raise errors[0]
+    _check(rc)
+    return _result_dict(r)

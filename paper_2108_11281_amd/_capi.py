@@ -1,0 +1,126 @@
+"""ctypes declarations of the C ABI in include/mlmc.h (argument marshalling only)."""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmlmc.so")
+
+MLMC_OK = 0
+MLMC_EINVAL = -1
+MLMC_ENOMEM = -2
+MLMC_EDEVICE = -3
+MLMC_ENOCONV = -4
+MLMC_ESTATE = -5
+MLMC_EUNSUPPORTED = -6
+
+POISSON2D = 0
+WILSON2D = 1
+VARCOEF3D = 2
+
+FP64 = 0
+FP32_IR64 = 1
+
+ALLOC_EQUAL = 0
+ALLOC_WEIGHTS = 1
+ALLOC_GILES = 2
+
+MAX_LEVELS = 16
+
+
+class Operator(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("n_side", ctypes.c_int),
+                ("diag", ctypes.c_double), ("off", ctypes.c_double),
+                ("mass", ctypes.c_double), ("shift", ctypes.c_double),
+                ("field", ctypes.POINTER(ctypes.c_double))]
+
+
+class Hierarchy(ctypes.Structure):
+    _fields_ = [("levels_solver", ctypes.c_int), ("levels_mlmc", ctypes.c_int),
+                ("block", ctypes.c_int), ("n_vec", ctypes.c_int),
+                ("setup_sweeps", ctypes.c_int), ("setup_seed", ctypes.c_uint64)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("nb", ctypes.c_int),
+                ("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int),
+                ("omega", ctypes.c_double), ("alloc", ctypes.c_int),
+                ("rho_weights", ctypes.POINTER(ctypes.c_double)),
+                ("solve_tol", ctypes.c_double), ("inner_tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int), ("max_refine", ctypes.c_int),
+                ("krylov_restart", ctypes.c_int), ("min_samples", ctypes.c_int),
+                ("max_samples", ctypes.c_int64), ("tau", ctypes.c_double),
+                ("learned", ctypes.c_int)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("trace", ctypes.c_double * 2), ("rmsd", ctypes.c_double),
+                ("tau", ctypes.c_double), ("coarse_trace", ctypes.c_double * 2),
+                ("levels", ctypes.c_int),
+                ("n_samples", ctypes.c_int64 * MAX_LEVELS),
+                ("level_mean", (ctypes.c_double * 2) * MAX_LEVELS),
+                ("level_var", ctypes.c_double * MAX_LEVELS),
+                ("level_cost", ctypes.c_double * MAX_LEVELS),
+                ("solves", ctypes.c_int64), ("iterations", ctypes.c_int64),
+                ("seconds", ctypes.c_double), ("max_stated_error", ctypes.c_double)]
+
+
+SAMPLE_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int64,
+                             ctypes.c_int64, ctypes.POINTER(ctypes.c_double))
+PILOT_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int64,
+                            ctypes.POINTER(ctypes.c_double))
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+_P = ctypes.c_void_p
+_D = ctypes.POINTER(ctypes.c_double)
+_I64 = ctypes.POINTER(ctypes.c_int64)
+
+# name: (restype, argtypes)
+SIGNATURES = {
+    "mlmc_default_options": (ctypes.c_int, [ctypes.POINTER(Options)]),
+    "mlmc_setup": (ctypes.c_int, [ctypes.POINTER(Operator), ctypes.POINTER(Hierarchy),
+                                  ctypes.POINTER(Options), _P, ctypes.POINTER(_P)]),
+    "mlmc_trace": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_uint64,
+                                  ctypes.POINTER(Result)]),
+    "mlmc_hutchinson": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_uint64,
+                                       ctypes.POINTER(Result)]),
+    "mlmc_sample_level": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_uint64, ctypes.c_int64,
+                                         ctypes.c_int64, _D, _D]),
+    "mlmc_coarse_trace": (ctypes.c_int, [_P, _D]),
+    "mlmc_level_size": (ctypes.c_int, [_P, ctypes.c_int, _I64]),
+    "mlmc_solve": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P, _D]),
+    "mlmc_apply": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P]),
+    "mlmc_restrict": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P]),
+    "mlmc_prolong": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P]),
+    "mlmc_probes": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_uint64, ctypes.c_int,
+                                   ctypes.c_int64, ctypes.c_int, _P]),
+    "mlmc_export_coarse": (ctypes.c_int, [_P, ctypes.c_int, _D]),
+    "mlmc_export_prolongation": (ctypes.c_int, [_P, ctypes.c_int, _D]),
+    "mlmc_run_estimator": (ctypes.c_int, [ctypes.c_int, SAMPLE_FN, PILOT_FN, _P, _D, _D,
+                                          ctypes.POINTER(Options), ctypes.c_double,
+                                          ctypes.POINTER(Result)]),
+    "mlmc_set_allocator": (ctypes.c_int, [ALLOC_FN, FREE_FN, _P]),
+    "mlmc_counters": (ctypes.c_int, [_P, _I64, ctypes.c_int]),
+    "mlmc_last_error": (ctypes.c_char_p, [_P]),
+    "mlmc_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "mlmc_destroy": (None, [_P]),
+}
+
+_lib = None
+
+
+def load(path=LIB_PATH):
+    """Load libmlmc.so; raise if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("libmlmc.so not built at %s: run __graft_entry__.build() or "
+                          "python paper_2108_11281_amd/build.py" % path)
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib

@@ -1,0 +1,243 @@
+// The C ABI (include/mlmc.h): argument checks, exception-to-status mapping.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+#include <string>
+
+#include "context.h"
+
+using mlmc::Context;
+using mlmc::Error;
+
+namespace {
+
+thread_local std::string g_setup_error;
+
+template <typename F>
+int guarded(Context* ctx, F&& f) {
+  try {
+    f();
+    if (ctx) ctx->last_error.clear();
+    return MLMC_OK;
+  } catch (const Error& e) {
+    if (ctx) ctx->last_error = e.what();
+    else g_setup_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    if (ctx) ctx->last_error = "host allocation failed";
+    else g_setup_error = "host allocation failed";
+    return MLMC_ENOMEM;
+  } catch (const std::exception& e) {
+    if (ctx) ctx->last_error = e.what();
+    else g_setup_error = e.what();
+    return MLMC_EINVAL;
+  }
+}
+
+Context* as_ctx(void* p) { return static_cast<Context*>(p); }
+
+}  // namespace
+
+extern "C" {
+
+int mlmc_default_options(mlmc_options* opt) {
+  if (!opt) return MLMC_EINVAL;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->precision = MLMC_FP32_IR64;
+  opt->nb = 128;
+  opt->nu_pre = 1;
+  opt->nu_post = 1;
+  opt->omega = 1.8;
+  opt->alloc = MLMC_ALLOC_EQUAL;
+  opt->rho_weights = nullptr;
+  opt->solve_tol = 1e-10;
+  opt->inner_tol = 1e-5;
+  opt->max_iter = 200;
+  opt->max_refine = 8;
+  opt->krylov_restart = 16;
+  opt->min_samples = 5;
+  opt->max_samples = (int64_t)1 << 22;
+  opt->tau = 0.0;
+  opt->learned = 0;
+  return MLMC_OK;
+}
+
+int mlmc_setup(const mlmc_operator* A, const mlmc_hierarchy* h, const mlmc_options* opt,
+               void* hip_stream, void** out_ctx) {
+  if (!out_ctx) return MLMC_EINVAL;
+  *out_ctx = nullptr;
+  if (!A || !h) {
+    g_setup_error = "null operator or hierarchy";
+    return MLMC_EINVAL;
+  }
+  mlmc_options o;
+  if (opt) o = *opt;
+  else mlmc_default_options(&o);
+  Context* ctx = nullptr;
+  int rc = guarded(nullptr, [&] {
+    ctx = new Context(*A, *h, o, static_cast<hipStream_t>(hip_stream));
+  });
+  if (rc == MLMC_OK) *out_ctx = ctx;
+  return rc;
+}
+
+int mlmc_trace(void* c, double tol, uint64_t seed, mlmc_result* out) {
+  Context* ctx = as_ctx(c);
+  if (!ctx || !out) return MLMC_EINVAL;
+  return guarded(ctx, [&] { ctx->trace(tol, seed, out); });
+}
+
+int mlmc_hutchinson(void* c, double tol, uint64_t seed, mlmc_result* out) {
+  Context* ctx = as_ctx(c);
+  if (!ctx || !out) return MLMC_EINVAL;
+  return guarded(ctx, [&] { ctx->hutchinson(tol, seed, out); });
+}
+
+int mlmc_sample_level(void* c, int level, uint64_t seed, int64_t first, int64_t nsamples,
+                      double* out, double* out_err) {
+  Context* ctx = as_ctx(c);
+  if (!ctx || !out) return MLMC_EINVAL;
+  return guarded(ctx, [&] { ctx->sample_level(level, seed, first, nsamples, out, out_err); });
+}
+
+int mlmc_coarse_trace(void* c, double* out) {
+  Context* ctx = as_ctx(c);
+  if (!ctx || !out) return MLMC_EINVAL;
+  out[0] = ctx->coarse_trace_re();
+  out[1] = ctx->coarse_trace_im();
+  return MLMC_OK;
+}
+
+int mlmc_level_size(void* c, int level, int64_t* n) {
+  Context* ctx = as_ctx(c);
+  if (!ctx || !n) return MLMC_EINVAL;
+  if (level < 1 || level > ctx->levels_solver()) {
+    ctx->last_error = "level out of range";
+    return MLMC_EINVAL;
+  }
+  *n = ctx->level_size(level);
+  return MLMC_OK;
+}
+
+int mlmc_solve(void* c, int level, int nrhs, const double* b_dev, double* y_dev,
+               double* relres) {
+  Context* ctx = as_ctx(c);
+  if (!ctx || !b_dev || !y_dev) return MLMC_EINVAL;
+  return guarded(ctx, [&] { ctx->solve_fp64(level, nrhs, b_dev, y_dev, relres, true); });
+}
+
+int mlmc_apply(void* c, int level, int nrhs, const double* x_dev, double* y_dev) {
+  Context* ctx = as_ctx(c);
+  if (!ctx || !x_dev || !y_dev) return MLMC_EINVAL;
+  return guarded(ctx, [&] { ctx->apply_fp64(level, nrhs, x_dev, y_dev); });
+}
+
+int mlmc_restrict(void* c, int level, int nrhs, const double* x_dev, double* xc_dev) {
+  Context* ctx = as_ctx(c);
+  if (!ctx || !x_dev || !xc_dev) return MLMC_EINVAL;
+  return guarded(ctx, [&] { ctx->restrict_fp64(level, nrhs, x_dev, xc_dev); });
+}
+
+int mlmc_prolong(void* c, int level, int nrhs, const double* xc_dev, double* x_dev) {
+  Context* ctx = as_ctx(c);
+  if (!ctx || !x_dev || !xc_dev) return MLMC_EINVAL;
+  return guarded(ctx, [&] { ctx->prolong_fp64(level, nrhs, xc_dev, x_dev); });
+}
+
+int mlmc_probes(void* c, int level, uint64_t seed, int stream, int64_t first, int nrhs,
+                double* out_dev) {
+  Context* ctx = as_ctx(c);
+  if (!ctx || !out_dev) return MLMC_EINVAL;
+  return guarded(ctx, [&] { ctx->probes_fp64(level, seed, stream, first, nrhs, out_dev); });
+}
+
+int mlmc_export_coarse(void* c, int which, double* out) {
+  Context* ctx = as_ctx(c);
+  if (!ctx || !out) return MLMC_EINVAL;
+  return guarded(ctx, [&] { ctx->export_coarse(which, out); });
+}
+
+int mlmc_export_prolongation(void* c, int level, double* out) {
+  Context* ctx = as_ctx(c);
+  if (!ctx || !out) return MLMC_EINVAL;
+  return guarded(ctx, [&] { ctx->export_prolongation(level, out); });
+}
+
+int mlmc_run_estimator(int levels, mlmc_sample_fn sample, mlmc_pilot_fn pilot, void* user,
+                       const double* coarse, const double* cost, const mlmc_options* opt,
+                       double tol, mlmc_result* out) {
+  if (!sample || !opt || !out || levels < 2 || levels > MLMC_MAX_LEVELS) {
+    g_setup_error = "invalid estimator arguments";
+    return MLMC_EINVAL;
+  }
+  return guarded(nullptr, [&] {
+    MLMC_REQUIRE(opt->nb >= 1, MLMC_EINVAL, "nb must be >= 1");
+    MLMC_REQUIRE(opt->min_samples >= 2, MLMC_EINVAL, "min_samples must be >= 2");
+    MLMC_REQUIRE(opt->max_samples >= opt->min_samples, MLMC_EINVAL,
+                 "max_samples below min_samples");
+    mlmc::SamplerIface smp;
+    smp.sample = [&](int level, int64_t first, int64_t count, mlmc::c64* o) {
+      int rc = sample(user, level, first, count, reinterpret_cast<double*>(o));
+      MLMC_REQUIRE(rc == 0, rc < 0 ? rc : MLMC_EINVAL, "sampler callback failed");
+      for (int64_t k = 0; k < count; ++k)
+        MLMC_REQUIRE(std::isfinite(o[k].re) && std::isfinite(o[k].im), MLMC_ENOCONV,
+                     "sampler returned a non-finite sample on level " +
+                         std::to_string(level));
+    };
+    if (pilot) {
+      smp.pilot = [&](int64_t count, mlmc::c64* o) {
+        int rc = pilot(user, count, reinterpret_cast<double*>(o));
+        MLMC_REQUIRE(rc == 0, rc < 0 ? rc : MLMC_EINVAL, "pilot callback failed");
+      };
+    }
+    std::vector<double> cv(levels - 1, 1.0);
+    if (cost)
+      for (int l = 0; l < levels - 1; ++l) cv[l] = cost[l];
+    mlmc::c64 cz = {coarse ? coarse[0] : 0.0, coarse ? coarse[1] : 0.0};
+    mlmc::run_estimator(levels, smp, cz, cv, *opt, tol, out);
+  });
+}
+
+int mlmc_set_allocator(mlmc_alloc_fn alloc, mlmc_free_fn free_fn, void* user) {
+  if ((alloc == nullptr) != (free_fn == nullptr)) return MLMC_EINVAL;
+  mlmc::alloc_hooks().alloc = alloc;
+  mlmc::alloc_hooks().free_fn = free_fn;
+  mlmc::alloc_hooks().user = user;
+  return MLMC_OK;
+}
+
+int mlmc_counters(void* c, int64_t* out, int n) {
+  Context* ctx = as_ctx(c);
+  if (!ctx || !out || n < 0 || n > 4) return MLMC_EINVAL;
+  for (int i = 0; i < n; ++i) out[i] = ctx->counters[i];
+  return MLMC_OK;
+}
+
+const char* mlmc_last_error(const void* c) {
+  const Context* ctx = static_cast<const Context*>(c);
+  if (!ctx) return g_setup_error.c_str();
+  return ctx->last_error.c_str();
+}
+
+const char* mlmc_status_string(int status) {
+  switch (status) {
+    case MLMC_OK: return "ok";
+    case MLMC_EINVAL: return "invalid argument";
+    case MLMC_ENOMEM: return "out of memory";
+    case MLMC_EDEVICE: return "device error";
+    case MLMC_ENOCONV: return "not converged";
+    case MLMC_ESTATE: return "invalid state";
+    case MLMC_EUNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+void mlmc_destroy(void* c) {
+  try {
+    delete as_ctx(c);
+  } catch (...) {
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,592 @@
+// Hierarchy setup, V-cycle, Krylov solvers with FP64 iterative refinement, and
+// the level-difference samples of the MLMC trace estimator.
+#include "context.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+namespace mlmc {
+
+AllocHooks& alloc_hooks() {
+  static AllocHooks h;
+  return h;
+}
+
+namespace {
+constexpr uint64_t kStreamProbe = 0, kStreamPilot = 1, kStreamHutch = 3;
+}
+
+// ---------------------------------------------------------------------------
+// construction
+// ---------------------------------------------------------------------------
+Context::Context(const mlmc_operator& A, const mlmc_hierarchy& h, const mlmc_options& o,
+                 hipStream_t s)
+    : kind_(A.kind), op_(A), h_(h), opt_(o), s_(s) {
+  hooks_ = alloc_hooks();
+  op_.field = nullptr;
+  Ls_ = h.levels_solver;
+  L_ = h.levels_mlmc;
+  nb_ = o.nb;
+  MLMC_REQUIRE(Ls_ >= 2 && Ls_ <= MLMC_MAX_LEVELS, MLMC_EINVAL,
+               "levels_solver must be in [2, 16]");
+  MLMC_REQUIRE(L_ >= 2 && L_ <= Ls_, MLMC_EINVAL, "levels_mlmc must be in [2, levels_solver]");
+  MLMC_REQUIRE(nb_ >= 1 && nb_ <= 1024, MLMC_EINVAL, "nb must be in [1, 1024]");
+  MLMC_REQUIRE(o.precision == MLMC_FP64 || o.precision == MLMC_FP32_IR64, MLMC_EINVAL,
+               "unknown precision");
+  MLMC_REQUIRE(o.solve_tol > 0 && o.inner_tol > 0, MLMC_EINVAL, "tolerances must be > 0");
+  MLMC_REQUIRE(o.max_iter >= 1 && o.max_refine >= 1, MLMC_EINVAL, "iteration limits < 1");
+  MLMC_REQUIRE(o.nu_pre >= 0 && o.nu_post >= 0, MLMC_EINVAL, "negative sweep count");
+  MLMC_REQUIRE(o.min_samples >= 2, MLMC_EINVAL, "min_samples must be >= 2");
+  MLMC_REQUIRE(o.alloc >= 0 && o.alloc <= 2, MLMC_EINVAL, "unknown allocation rule");
+  try {
+    switch (kind_) {
+      case MLMC_POISSON2D:
+        build_poisson();
+        break;
+      default:
+        throw Error(MLMC_EUNSUPPORTED, "operator kind not supported");
+    }
+  } catch (...) {
+    for (void* p : allocs_) {
+      if (hooks_.free_fn) hooks_.free_fn(p, hooks_.user);
+      else (void)hipFree(p);
+    }
+    allocs_.clear();
+    if (count_host_) (void)hipHostFree(count_host_);
+    if (host_c64_) (void)hipHostFree(host_c64_);
+    count_host_ = nullptr;
+    host_c64_ = nullptr;
+    throw;
+  }
+}
+
+Context::~Context() {
+  (void)hipStreamSynchronize(s_);
+  for (void* p : allocs_) {
+    if (hooks_.free_fn) hooks_.free_fn(p, hooks_.user);
+    else (void)hipFree(p);
+  }
+  if (count_host_) (void)hipHostFree(count_host_);
+  if (host_c64_) (void)hipHostFree(host_c64_);
+}
+
+void* Context::dalloc(size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  void* p = nullptr;
+  if (hooks_.alloc) {
+    p = hooks_.alloc(bytes, hooks_.user);
+    MLMC_REQUIRE(p != nullptr, MLMC_ENOMEM, "device allocation failed");
+  } else {
+    hipError_t e = hipMalloc(&p, bytes);
+    MLMC_REQUIRE(e == hipSuccess, MLMC_ENOMEM,
+                 std::string("hipMalloc failed: ") + hipGetErrorString(e));
+  }
+  allocs_.push_back(p);
+  return p;
+}
+
+template <> Work<float>& Context::work<float>() { return w32_; }
+template <> Work<double>& Context::work<double>() { return w64_; }
+
+template <typename T>
+void Context::alloc_work(Work<T>& w) {
+  const int64_t n1 = lv_[0].n * nb_;
+  w.x = dalloc_n<T>(n1);
+  w.r = dalloc_n<T>(n1);
+  w.z = dalloc_n<T>(n1);
+  w.p = dalloc_n<T>(n1);
+  w.q = dalloc_n<T>(n1);
+  w.vb.assign(Ls_, nullptr);
+  w.vx.assign(Ls_, nullptr);
+  for (int m = 1; m < Ls_; ++m) {
+    w.vb[m] = dalloc_n<T>(lv_[m].n * nb_);
+    w.vx[m] = dalloc_n<T>(lv_[m].n * nb_);
+  }
+}
+
+// Invert A_level densely in FP64 (Gauss-Jordan with partial pivoting on the
+// device).  Returns the row-major inverse and its trace.
+void Context::invert_coarse(int level, double** inv_out, c64* trace_out) {
+  const Level& L = lv_[level - 1];
+  MLMC_REQUIRE(L.n <= 16384, MLMC_EINVAL,
+               "coarsest level too large for a dense inverse (n > 16384)");
+  const int n = (int)L.n;
+  double* aug = dalloc_n<double>(2 * (int64_t)n * n);
+  double* rowbuf = dalloc_n<double>(2 * (int64_t)n);
+  double* colbuf = dalloc_n<double>(n);
+  switch (kind_) {
+    case MLMC_POISSON2D:
+      poisson_dense_build<double>(aug, L.side, L.d, L.c, s_);
+      break;
+    default:
+      throw Error(MLMC_EUNSUPPORTED, "dense build");
+  }
+  dense_set_identity_right<double>(aug, n, s_);
+  dense_invert<double>(aug, n, rowbuf, colbuf, piv_, s_);
+  double* inv = dalloc_n<double>((int64_t)n * n);
+  dense_extract_right<double>(aug, n, inv, s_);
+  dense_trace<double>(inv, n, scal_[kTmp], s_);
+  MLMC_HIP(hipMemcpyAsync(host_c64_, scal_[kTmp], sizeof(c64), hipMemcpyDeviceToHost, s_));
+  MLMC_HIP(hipStreamSynchronize(s_));
+  *trace_out = host_c64_[0];
+  *inv_out = inv;
+}
+
+void Context::build_poisson() {
+  MLMC_REQUIRE(op_.n_side >= 2, MLMC_EINVAL, "n_side must be >= 2");
+  MLMC_REQUIRE(op_.diag > 0 && op_.off >= 0 && op_.diag >= 4 * op_.off, MLMC_EINVAL,
+               "POISSON2D needs diag >= 4*off >= 0 (positive definite)");
+  lv_.resize(Ls_);
+  int side = op_.n_side;
+  double d = op_.diag, c = op_.off;
+  for (int l = 0; l < Ls_; ++l) {
+    if (l > 0) {
+      MLMC_REQUIRE(side % 2 == 0, MLMC_EINVAL,
+                   "grid side not divisible by 2 at level " + std::to_string(l));
+      side /= 2;
+      // Galerkin of the 5-point stencil with orthonormal 2x2 aggregation:
+      // diagonal block sum (4d - 8c)/4, coupling across an edge 2(-c)/4.
+      const double dn = d - 2.0 * c, cn = 0.5 * c;
+      d = dn;
+      c = cn;
+    }
+    Level& L = lv_[l];
+    L.index = l + 1;
+    L.side = side;
+    L.dof = 1;
+    L.n = (int64_t)side * side;
+    L.d = d;
+    L.c = c;
+  }
+  MLMC_REQUIRE(lv_[Ls_ - 1].n <= 16384, MLMC_EINVAL, "coarsest solver level larger than 128^2");
+  const int64_t n1 = lv_[0].n;
+
+  // small device and pinned host buffers
+  // per-column partial sums: enough for one partial per 256-thread block of
+  // the finest level (stencil kernels with fused dots) or kMaxPartials
+  const int64_t per_col = std::max<int64_t>(kMaxPartials, (n1 + kThreads - 1) / kThreads);
+  partials_ = dalloc_n<c64>(per_col * nb_);
+  partials_cap_ = per_col * nb_;
+  c64* sc = dalloc_n<c64>((int64_t)kNumScalars * nb_);
+  for (int i = 0; i < kNumScalars; ++i) scal_[i] = sc + (int64_t)i * nb_;
+  act_outer_ = dalloc_n<int>(nb_);
+  act_inner_ = dalloc_n<int>(nb_);
+  count_dev_ = dalloc_n<int>(4);
+  piv_ = dalloc_n<int>(4);
+  MLMC_HIP(hipHostMalloc((void**)&count_host_, 4 * sizeof(int)));
+  MLMC_HIP(hipHostMalloc((void**)&host_c64_, 8 * (size_t)nb_ * sizeof(c64)));
+
+  // sample-batch buffers (FP64)
+  b1_ = dalloc_n<double>(n1 * nb_);
+  y1_ = dalloc_n<double>(n1 * nb_);
+  b2_ = dalloc_n<double>(lv_[1].n * nb_);
+  y2_ = dalloc_n<double>(lv_[1].n * nb_);
+  r64_ = dalloc_n<double>(n1 * nb_);
+  alloc_work(w64_);
+  if (opt_.precision == MLMC_FP32_IR64) {
+    alloc_work(w32_);
+    r32_ = dalloc_n<float>(n1 * nb_);
+    d32_ = dalloc_n<float>(n1 * nb_);
+  }
+
+  // coarsest inverses (FP64 on the device), the direct trace term (Remark 4.2)
+  c64 tr_s;
+  invert_coarse(Ls_, &ainv_solver_, &tr_s);
+  const int ns = (int)lv_[Ls_ - 1].n;
+  w64_.ainvT = dalloc_n<double>((int64_t)ns * ns);
+  dense_transpose<double>(ainv_solver_, w64_.ainvT, ns, s_);
+  if (opt_.precision == MLMC_FP32_IR64) {
+    w32_.ainvT = dalloc_n<float>((int64_t)ns * ns);
+    vec_convert<float, double>(w64_.ainvT, w32_.ainvT, (int64_t)ns * ns, 1, nullptr, s_);
+  }
+  if (L_ == Ls_) {
+    coarse_trace_ = tr_s;
+  } else {
+    invert_coarse(L_, &ainv_mlmc_, &coarse_trace_);
+  }
+  MLMC_HIP(hipStreamSynchronize(s_));
+  MLMC_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// operator dispatch
+// ---------------------------------------------------------------------------
+template <typename T>
+void Context::op_apply(int l, const T* x, T* y, int nb, const int* act, c64* partials) {
+  const Level& L = lv_[l - 1];
+  poisson_apply<T>(x, y, L.side, L.d, L.c, nb, act, partials, s_);
+}
+
+template <typename Tb, typename Tx, typename Tr>
+void Context::op_residual(int l, const Tb* b, const Tx* x, Tr* r, int nb, const int* act,
+                          c64* partials) {
+  const Level& L = lv_[l - 1];
+  poisson_residual<Tb, Tx, Tr>(b, x, r, L.side, L.d, L.c, nb, act, partials, s_);
+}
+
+template <typename T>
+void Context::op_smooth(int l, const T* b, T* x, int nb, const int* act, bool zero_init,
+                        bool reverse) {
+  const Level& L = lv_[l - 1];
+  poisson_rbgs<T>(b, x, L.side, L.d, L.c, nb, act, zero_init, reverse, s_);
+}
+
+template <typename T>
+void Context::op_res_restrict(int l, const T* b, const T* x, T* rc, int nb, const int* act) {
+  const Level& L = lv_[l - 1];
+  poisson_residual_restrict<T>(b, x, rc, L.side, L.d, L.c, nb, act, s_);
+}
+
+template <typename T>
+void Context::op_prolong(int l, const T* ec, T* x, int nb, const int* act, double beta) {
+  const Level& L = lv_[l - 1];
+  agg2d_prolong<T>(ec, x, L.side, beta == 0.0 ? 1.0 : opt_.omega, beta, nb, act, s_);
+}
+
+template <typename T>
+void Context::op_restrict(int l, const T* x, T* xc, int nb, const int* act) {
+  const Level& L = lv_[l - 1];
+  agg2d_restrict<T>(x, xc, L.side, nb, act, s_);
+}
+
+// ---------------------------------------------------------------------------
+// V-cycle on levels l..L_s: x = M b (x need not be initialised)
+// ---------------------------------------------------------------------------
+template <typename T>
+void Context::vcycle(int l, const T* b, T* x, int nb, const int* act) {
+  Work<T>& w = work<T>();
+  counters[2] += (l == 1) ? 1 : 0;
+  if (l == Ls_) {
+    dense_apply<T>(w.ainvT, b, x, (int)lv_[l - 1].n, nb, act, s_);
+    return;
+  }
+  const int pre = opt_.nu_pre, post = opt_.nu_post;
+  if (pre == 0) vec_zero<T>(x, lv_[l - 1].n, nb, act, s_);
+  for (int i = 0; i < pre; ++i) op_smooth<T>(l, b, x, nb, act, i == 0, false);
+  T* bc = w.vb[l];
+  T* xc = w.vx[l];
+  if (pre == 0)
+    op_restrict<T>(l, b, bc, nb, act);
+  else
+    op_res_restrict<T>(l, b, x, bc, nb, act);
+  vcycle<T>(l + 1, bc, xc, nb, act);
+  op_prolong<T>(l, xc, x, nb, act, 1.0);
+  for (int i = 0; i < post; ++i) op_smooth<T>(l, b, x, nb, act, false, true);
+}
+
+int Context::read_count() {
+  MLMC_HIP(hipMemcpyAsync(count_host_, count_dev_, sizeof(int), hipMemcpyDeviceToHost, s_));
+  MLMC_HIP(hipStreamSynchronize(s_));
+  return count_host_[0];
+}
+
+// ---------------------------------------------------------------------------
+// Preconditioned CG (A Hermitian positive definite), columns in lockstep with
+// per-column scalars on the device.  Convergence: |r| <= tol |b| per column.
+// lastcorr (nullable): per column alpha*rz of the last step, which equals
+// b^H (alpha p) when x starts at 0 -- the last step's contribution to b^H x.
+// Returns the iteration count.
+// ---------------------------------------------------------------------------
+template <typename T>
+int Context::pcg(int l, const T* b, T* x, int nb, int* act, double tol, c64* lastcorr) {
+  Work<T>& w = work<T>();
+  const int64_t n = lv_[l - 1].n;
+  const int nblk = reduce_blocks(n);
+  const int nblk_pts = (int)((n + kThreads - 1) / kThreads);
+  c64 *rr0 = scal_[kRr0], *rz = scal_[kRz], *tmp = scal_[kTmp], *alpha = scal_[kAlpha],
+      *beta = scal_[kBeta];
+  vec_zero<T>(x, n, nb, act, s_);
+  if (l == Ls_) {  // direct solve on the coarsest level
+    dense_apply<T>(w.ainvT, b, x, (int)n, nb, act, s_);
+    if (lastcorr) vec_zero<c64>(lastcorr, 1, nb, nullptr, s_);
+    return 0;
+  }
+  vec_copy<T>(b, w.r, n, nb, act, s_);
+  vec_dot_partials<T>(b, b, n, nb, act, partials_, s_);
+  finish_sums(partials_, nblk, nb, rr0, s_);
+  vcycle<T>(l, w.r, w.z, nb, act);
+  vec_dot_partials<T>(w.r, w.z, n, nb, act, partials_, s_);
+  finish_sums(partials_, nblk, nb, rz, s_);
+  vec_copy<T>(w.z, w.p, n, nb, act, s_);
+  const int check = 2;
+  int it = 0;
+  for (it = 1; it <= opt_.max_iter; ++it) {
+    op_apply<T>(l, w.p, w.q, nb, act, partials_);
+    finish_sums(partials_, nblk_pts, nb, tmp, s_);
+    cg_alpha(rz, tmp, act, alpha, nb, s_);
+    if (lastcorr) cg_lastcorr(alpha, rz, act, lastcorr, nb, s_);
+    cg_update_xr<T>(x, w.r, w.p, w.q, alpha, n, nb, act, partials_, s_);
+    finish_sums(partials_, nblk, nb, tmp, s_);
+    mark_converged(tmp, rr0, tol * tol, act, nb, count_dev_, s_);
+    counters[0] += 1;
+    if (it % check == 0 || it == opt_.max_iter) {
+      if (read_count() == 0) break;
+    }
+    vcycle<T>(l, w.r, w.z, nb, act);
+    vec_dot_partials<T>(w.r, w.z, n, nb, act, partials_, s_);
+    finish_sums(partials_, nblk, nb, tmp, s_);
+    cg_beta(tmp, rz, act, beta, nb, s_);
+    cg_update_p<T>(w.p, w.z, beta, n, nb, act, s_);
+  }
+  return it;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 solve of A_l y = b for nb columns.  err (device, nb): stated error
+// contribution b^H d of the last correction d.  relres_host: final FP64
+// relative residuals (nullable).  converged: all columns met solve_tol.
+// ---------------------------------------------------------------------------
+void Context::solve(int l, const double* b, double* y, int nb, c64* err, double* relres_host,
+                    bool* converged) {
+  const int64_t n = lv_[l - 1].n;
+  const int nblk_pts = (int)((n + kThreads - 1) / kThreads);
+  const int nblk = reduce_blocks(n);
+  c64* bb = scal_[kBb];
+  c64* bd = scal_[kBd];
+  c64* rres = scal_[kRres];
+  vec_dot_partials<double>(b, b, n, nb, nullptr, partials_, s_);
+  finish_sums(partials_, nblk, nb, bb, s_);
+  set_all_active(act_outer_, nb, s_);
+  vec_zero<c64>(err, 1, nb, nullptr, s_);
+  const double tol = opt_.solve_tol;
+  if (l == Ls_) {
+    dense_apply<double>(w64_.ainvT, b, y, (int)n, nb, nullptr, s_);
+  } else if (opt_.precision == MLMC_FP64) {
+    MLMC_HIP(hipMemcpyAsync(act_inner_, act_outer_, sizeof(int) * nb,
+                            hipMemcpyDeviceToDevice, s_));
+    pcg<double>(l, b, y, nb, act_inner_, tol, err);
+    counters[1] += 1;
+  } else {
+    // FP64 iterative refinement around the FP32 solver
+    vec_zero<double>(y, n, nb, nullptr, s_);
+    vec_convert<float, double>(b, r32_, n, nb, nullptr, s_);
+    for (int ir = 0; ir < opt_.max_refine; ++ir) {
+      MLMC_HIP(hipMemcpyAsync(act_inner_, act_outer_, sizeof(int) * nb,
+                              hipMemcpyDeviceToDevice, s_));
+      pcg<float>(l, r32_, d32_, nb, act_inner_, opt_.inner_tol, nullptr);
+      ir_accumulate<double, float>(y, d32_, n, nb, act_outer_, s_);
+      // stated error: b^H d of this correction, kept for the columns refined now
+      vec_convert<double, float>(d32_, r64_, n, nb, act_outer_, s_);
+      vec_dot_partials<double>(b, r64_, n, nb, act_outer_, partials_, s_);
+      finish_sums(partials_, nblk, nb, bd, s_);
+      select_active(err, bd, act_outer_, nb, s_);
+      op_residual<double, double, float>(l, b, y, r32_, nb, act_outer_, partials_);
+      finish_sums(partials_, nblk_pts, nb, rres, s_);
+      mark_converged(rres, bb, tol * tol, act_outer_, nb, count_dev_, s_);
+      counters[1] += 1;
+      const int remaining = read_count();
+      if (remaining == 0) break;
+    }
+  }
+  // final FP64 relative residuals
+  op_residual<double, double, double>(l, b, y, r64_, nb, nullptr, partials_);
+  finish_sums(partials_, nblk_pts, nb, rres, s_);
+  MLMC_HIP(hipMemcpyAsync(host_c64_, rres, sizeof(c64) * nb, hipMemcpyDeviceToHost, s_));
+  MLMC_HIP(hipMemcpyAsync(host_c64_ + nb, bb, sizeof(c64) * nb, hipMemcpyDeviceToHost, s_));
+  MLMC_HIP(hipStreamSynchronize(s_));
+  bool ok = true;
+  for (int k = 0; k < nb; ++k) {
+    const double bn = host_c64_[nb + k].re;
+    const double rel = bn > 0 ? std::sqrt(host_c64_[k].re / bn) : std::sqrt(host_c64_[k].re);
+    if (relres_host) relres_host[k] = rel;
+    if (!(rel <= tol)) ok = false;
+  }
+  if (converged) *converged = ok;
+}
+
+// ---------------------------------------------------------------------------
+// level-difference samples: s = x^H A_l^-1 x - (R x)^H A_{l+1}^-1 (R x)
+// ---------------------------------------------------------------------------
+void Context::samples_batch(int level, uint64_t seed, uint64_t first, int nbatch, c64* out,
+                            double* err_out) {
+  MLMC_REQUIRE(level >= 1 && level < L_, MLMC_EINVAL, "sample level must be in [1, L-1]");
+  MLMC_REQUIRE(nbatch >= 1 && nbatch <= nb_, MLMC_EINVAL, "batch size out of range");
+  const int64_t n1 = lv_[level - 1].n, n2 = lv_[level].n;
+  probes_write<double>(b1_, n1, nbatch, seed, 0, first, (uint64_t)level, kStreamProbe, s_);
+  bool ok1 = true, ok2 = true;
+  c64 *e1 = scal_[kErr1], *e2 = scal_[kErr2], *qa = scal_[kQa], *qb = scal_[kQb];
+  solve(level, b1_, y1_, nbatch, e1, nullptr, &ok1);
+  op_restrict<double>(level, b1_, b2_, nbatch, nullptr);
+  solve(level + 1, b2_, y2_, nbatch, e2, nullptr, &ok2);
+  // x^H y with x regenerated, and (Rx)^H z
+  const int64_t chunk1 = (int64_t)kThreads * 256;  // Rademacher entries per block
+  const int nb1 = (int)((n1 + chunk1 - 1) / chunk1);
+  probe_dot_partials<double>(y1_, n1, nbatch, seed, 0, first, (uint64_t)level, kStreamProbe,
+                             partials_, s_);
+  finish_sums(partials_, nb1, nbatch, qa, s_);
+  vec_dot_partials<double>(b2_, y2_, n2, nbatch, nullptr, partials_, s_);
+  finish_sums(partials_, reduce_blocks(n2), nbatch, qb, s_);
+  // scalars e1, e2, qa, qb are consecutive blocks of nb_ entries
+  MLMC_HIP(hipMemcpyAsync(host_c64_, scal_[kErr1], sizeof(c64) * 4 * nb_,
+                          hipMemcpyDeviceToHost, s_));
+  MLMC_HIP(hipStreamSynchronize(s_));
+  MLMC_HIP(hipGetLastError());
+  const c64 *he1 = host_c64_, *he2 = host_c64_ + nb_, *ha = host_c64_ + 2 * nb_,
+            *hb = host_c64_ + 3 * nb_;
+  for (int k = 0; k < nbatch; ++k) {
+    const c64 a = ha[k], b = hb[k];
+    out[k] = {a.re - b.re, a.im - b.im};
+    if (err_out) {
+      const double den = std::hypot(a.re, a.im) + std::hypot(b.re, b.im);
+      const double num = std::hypot(he1[k].re, he1[k].im) + std::hypot(he2[k].re, he2[k].im);
+      err_out[k] = den > 0 ? num / den : num;
+    }
+  }
+  counters[3] += 1;
+  if (!ok1 || !ok2)
+    throw Error(MLMC_ENOCONV, "solve on level " + std::to_string(ok1 ? level + 1 : level) +
+                                  " missed solve_tol");
+}
+
+void Context::hutch_batch(uint64_t seed, uint64_t stream, uint64_t first, int nbatch,
+                          c64* out) {
+  const int64_t n1 = lv_[0].n;
+  probes_write<double>(b1_, n1, nbatch, seed, 0, first, 1, stream, s_);
+  bool ok = true;
+  solve(1, b1_, y1_, nbatch, scal_[kErr1], nullptr, &ok);
+  const int64_t chunk1 = (int64_t)kThreads * 256;
+  const int nb1 = (int)((n1 + chunk1 - 1) / chunk1);
+  probe_dot_partials<double>(y1_, n1, nbatch, seed, 0, first, 1, stream, partials_, s_);
+  finish_sums(partials_, nb1, nbatch, scal_[kQa], s_);
+  MLMC_HIP(hipMemcpyAsync(host_c64_, scal_[kQa], sizeof(c64) * nbatch, hipMemcpyDeviceToHost,
+                          s_));
+  MLMC_HIP(hipStreamSynchronize(s_));
+  for (int k = 0; k < nbatch; ++k) out[k] = host_c64_[k];
+  counters[3] += 1;
+  if (!ok) throw Error(MLMC_ENOCONV, "solve on level 1 missed solve_tol");
+}
+
+void Context::sample_level(int level, uint64_t seed, int64_t first, int64_t count, double* out,
+                           double* out_err) {
+  MLMC_REQUIRE(level >= 1 && level < L_, MLMC_EINVAL, "sample level must be in [1, L-1]");
+  MLMC_REQUIRE(first >= 0 && count >= 1, MLMC_EINVAL, "bad sample range");
+  std::memset(counters, 0, sizeof(counters));
+  std::vector<c64> buf(nb_);
+  std::vector<double> eb(nb_);
+  for (int64_t j = 0; j < count; j += nb_) {
+    const int nbt = (int)std::min<int64_t>(nb_, count - j);
+    samples_batch(level, seed, (uint64_t)(first + j), nbt, buf.data(), eb.data());
+    for (int k = 0; k < nbt; ++k) {
+      out[2 * (j + k)] = buf[k].re;
+      out[2 * (j + k) + 1] = buf[k].im;
+      if (out_err) out_err[j + k] = eb[k];
+    }
+  }
+}
+
+void Context::trace(double tol, uint64_t seed, mlmc_result* out) {
+  std::memset(counters, 0, sizeof(counters));
+  SamplerIface smp;
+  smp.sample = [&](int level, int64_t first, int64_t count, c64* o) {
+    for (int64_t j = 0; j < count; j += nb_) {
+      const int nbt = (int)std::min<int64_t>(nb_, count - j);
+      samples_batch(level, seed, (uint64_t)(first + j), nbt, o + j, nullptr);
+    }
+  };
+  smp.pilot = [&](int64_t count, c64* o) {
+    for (int64_t j = 0; j < count; j += nb_) {
+      const int nbt = (int)std::min<int64_t>(nb_, count - j);
+      hutch_batch(seed, kStreamPilot, (uint64_t)j, nbt, o + j);
+    }
+  };
+  std::vector<double> cost(L_ - 1);
+  for (int l = 0; l < L_ - 1; ++l) cost[l] = (double)(lv_[l].n + lv_[l + 1].n);
+  run_estimator(L_, smp, coarse_trace_, cost, opt_, tol, out);
+  int64_t solves = 0;
+  for (int l = 0; l < L_ - 1; ++l) solves += 2 * out->n_samples[l];
+  out->solves = solves + (opt_.tau > 0 ? 0 : 5);
+  out->iterations = counters[0];
+}
+
+void Context::hutchinson(double tol, uint64_t seed, mlmc_result* out) {
+  std::memset(counters, 0, sizeof(counters));
+  auto sample = [&](int64_t first, int64_t count, c64* o) {
+    for (int64_t j = 0; j < count; j += nb_) {
+      const int nbt = (int)std::min<int64_t>(nb_, count - j);
+      hutch_batch(seed, kStreamHutch, (uint64_t)(first + j), nbt, o + j);
+    }
+  };
+  auto pilot = [&](int64_t count, c64* o) {
+    for (int64_t j = 0; j < count; j += nb_) {
+      const int nbt = (int)std::min<int64_t>(nb_, count - j);
+      hutch_batch(seed, kStreamPilot, (uint64_t)j, nbt, o + j);
+    }
+  };
+  run_hutchinson(sample, pilot, opt_, tol, out);
+  out->solves = out->n_samples[0] + (opt_.tau > 0 ? 0 : 5);
+  out->iterations = counters[0];
+  out->coarse_trace[0] = coarse_trace_.re;
+  out->coarse_trace[1] = coarse_trace_.im;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 building blocks exposed for tests
+// ---------------------------------------------------------------------------
+void Context::solve_fp64(int level, int nrhs, const double* b, double* y, double* relres,
+                         bool throw_on_noconv) {
+  MLMC_REQUIRE(level >= 1 && level <= Ls_, MLMC_EINVAL, "level out of range");
+  MLMC_REQUIRE(nrhs >= 1 && nrhs <= nb_, MLMC_EINVAL, "nrhs must be in [1, nb]");
+  std::memset(counters, 0, sizeof(counters));
+  bool ok = true;
+  solve(level, b, y, nrhs, scal_[kErr1], relres, &ok);
+  if (!ok && throw_on_noconv) throw Error(MLMC_ENOCONV, "solve missed solve_tol");
+}
+
+void Context::apply_fp64(int level, int nrhs, const double* x, double* y) {
+  MLMC_REQUIRE(level >= 1 && level <= Ls_, MLMC_EINVAL, "level out of range");
+  MLMC_REQUIRE(nrhs >= 1, MLMC_EINVAL, "nrhs must be >= 1");
+  op_apply<double>(level, x, y, nrhs, nullptr, nullptr);
+  MLMC_HIP(hipStreamSynchronize(s_));
+  MLMC_HIP(hipGetLastError());
+}
+
+void Context::restrict_fp64(int level, int nrhs, const double* x, double* xc) {
+  MLMC_REQUIRE(level >= 1 && level < Ls_, MLMC_EINVAL, "level out of range");
+  MLMC_REQUIRE(nrhs >= 1, MLMC_EINVAL, "nrhs must be >= 1");
+  op_restrict<double>(level, x, xc, nrhs, nullptr);
+  MLMC_HIP(hipStreamSynchronize(s_));
+  MLMC_HIP(hipGetLastError());
+}
+
+void Context::prolong_fp64(int level, int nrhs, const double* xc, double* x) {
+  MLMC_REQUIRE(level >= 1 && level < Ls_, MLMC_EINVAL, "level out of range");
+  MLMC_REQUIRE(nrhs >= 1, MLMC_EINVAL, "nrhs must be >= 1");
+  agg2d_prolong<double>(xc, x, lv_[level - 1].side, 1.0, 0.0, nrhs, nullptr, s_);
+  MLMC_HIP(hipStreamSynchronize(s_));
+  MLMC_HIP(hipGetLastError());
+}
+
+void Context::probes_fp64(int level, uint64_t seed, int stream, int64_t first, int nrhs,
+                          double* out) {
+  MLMC_REQUIRE(level >= 1 && level <= Ls_, MLMC_EINVAL, "level out of range");
+  MLMC_REQUIRE(nrhs >= 1 && first >= 0 && stream >= 0, MLMC_EINVAL, "bad probe range");
+  probes_write<double>(out, lv_[level - 1].n, nrhs, seed, 0, (uint64_t)first,
+                       (uint64_t)level, (uint64_t)stream, s_);
+  MLMC_HIP(hipStreamSynchronize(s_));
+  MLMC_HIP(hipGetLastError());
+}
+
+void Context::export_coarse(int which, double* out) {
+  const int level = which == 1 ? L_ : Ls_;
+  const int n = (int)lv_[level - 1].n;
+  double* aug = dalloc_n<double>(2 * (int64_t)n * n);
+  poisson_dense_build<double>(aug, lv_[level - 1].side, lv_[level - 1].d, lv_[level - 1].c,
+                              s_);
+  for (int i = 0; i < n; ++i)
+    MLMC_HIP(hipMemcpyAsync(out + (size_t)i * n, aug + (size_t)i * 2 * n, sizeof(double) * n,
+                            hipMemcpyDeviceToHost, s_));
+  MLMC_HIP(hipStreamSynchronize(s_));
+}
+
+void Context::export_prolongation(int level, double* out) {
+  (void)level;
+  (void)out;
+  throw Error(MLMC_EUNSUPPORTED, "prolongation export is for test-vector aggregation only");
+}
+
+template void Context::vcycle<float>(int, const float*, float*, int, const int*);
+template void Context::vcycle<double>(int, const double*, double*, int, const int*);
+
+}  // namespace mlmc

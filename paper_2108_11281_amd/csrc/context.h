@@ -1,0 +1,155 @@
+// Library context: the hierarchy, work buffers and the solvers.
+#pragma once
+
+#include <functional>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+namespace mlmc {
+
+// Device memory hooks (set through mlmc_set_allocator).
+struct AllocHooks {
+  mlmc_alloc_fn alloc = nullptr;
+  mlmc_free_fn free_fn = nullptr;
+  void* user = nullptr;
+};
+AllocHooks& alloc_hooks();
+
+// One level of the hierarchy (1-based index `index`).
+struct Level {
+  int index = 1;
+  int side = 0;       // grid / lattice side
+  int dof = 1;        // unknowns per site (1 for scalar grids)
+  int64_t n = 0;      // unknowns
+  double d = 0, c = 0;  // POISSON2D stencil: A = d I - c (neighbours)
+};
+
+// Per-precision work buffers (T = float or double for real operators).
+template <typename T>
+struct Work {
+  T *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+  std::vector<T*> vb, vx;   // V-cycle right-hand side / solution per level (0-based)
+  T* ainvT = nullptr;       // transposed inverse of the solver's coarsest operator
+};
+
+struct Estimate;
+
+class Context {
+ public:
+  Context(const mlmc_operator& A, const mlmc_hierarchy& h, const mlmc_options& o,
+          hipStream_t s);
+  ~Context();
+
+  // --- entry points used by the C ABI ---
+  void trace(double tol, uint64_t seed, mlmc_result* out);
+  void hutchinson(double tol, uint64_t seed, mlmc_result* out);
+  void sample_level(int level, uint64_t seed, int64_t first, int64_t count, double* out,
+                    double* out_err);
+  void solve_fp64(int level, int nrhs, const double* b, double* y, double* relres,
+                  bool throw_on_noconv);
+  void apply_fp64(int level, int nrhs, const double* x, double* y);
+  void restrict_fp64(int level, int nrhs, const double* x, double* xc);
+  void prolong_fp64(int level, int nrhs, const double* xc, double* x);
+  void probes_fp64(int level, uint64_t seed, int stream, int64_t first, int nrhs,
+                   double* out);
+  void export_coarse(int which, double* out);
+  void export_prolongation(int level, double* out);
+
+  int levels_mlmc() const { return L_; }
+  int levels_solver() const { return Ls_; }
+  int64_t level_size(int level) const { return lv_.at(level - 1).n; }
+  double coarse_trace_re() const { return coarse_trace_.re; }
+  double coarse_trace_im() const { return coarse_trace_.im; }
+  int64_t counters[4] = {0, 0, 0, 0};
+  std::string last_error;
+  const mlmc_options& options() const { return opt_; }
+
+  // level-difference samples and pilot/Hutchinson samples in batches <= nb
+  void samples_batch(int level, uint64_t seed, uint64_t first, int nbatch, c64* out,
+                     double* err);
+  void hutch_batch(uint64_t seed, uint64_t stream, uint64_t first, int nbatch, c64* out);
+
+ private:
+  void* dalloc(size_t bytes);
+  template <typename T> T* dalloc_n(int64_t count) {
+    return static_cast<T*>(dalloc(sizeof(T) * (size_t)count));
+  }
+  void build_poisson();
+  void invert_coarse(int level, double** inv_out, c64* trace_out);
+  template <typename T> void alloc_work(Work<T>& w);
+
+  // operator pieces on level l (1-based) in precision T
+  template <typename T> void op_apply(int l, const T* x, T* y, int nb, const int* act,
+                                      c64* partials);
+  template <typename T> void op_smooth(int l, const T* b, T* x, int nb, const int* act,
+                                       bool zero_init, bool reverse);
+  template <typename T> void op_res_restrict(int l, const T* b, const T* x, T* rc, int nb,
+                                             const int* act);
+  template <typename T> void op_prolong(int l, const T* ec, T* x, int nb, const int* act,
+                                        double beta);
+  template <typename T> void op_restrict(int l, const T* x, T* xc, int nb, const int* act);
+  template <typename Tb, typename Tx, typename Tr>
+  void op_residual(int l, const Tb* b, const Tx* x, Tr* r, int nb, const int* act,
+                   c64* partials);
+
+  template <typename T> Work<T>& work();
+  template <typename T> void vcycle(int l, const T* b, T* x, int nb, const int* act);
+  // CG on level l in precision T: x = A^-1 b to relative residual tol;
+  // act: per-column flags (in: columns to solve; out: still unconverged)
+  template <typename T> int pcg(int l, const T* b, T* x, int nb, int* act, double tol,
+                                c64* lastcorr);
+  // FP64 solve of level l for nb columns; b, y FP64; err: per-column stated error
+  // contributions (device c64 nb), relres host (nullable)
+  void solve(int l, const double* b, double* y, int nb, c64* err, double* relres_host,
+             bool* converged);
+  int read_count();
+
+  int kind_;
+  mlmc_operator op_;
+  mlmc_hierarchy h_;
+  mlmc_options opt_;
+  hipStream_t s_;
+  int Ls_ = 0, L_ = 0, nb_ = 0;
+  std::vector<Level> lv_;
+  std::vector<void*> allocs_;
+  AllocHooks hooks_;
+
+  Work<float> w32_;
+  Work<double> w64_;
+  double* ainv_mlmc_ = nullptr;   // inverse of A_L (row-major), if L < L_s
+  double* ainv_solver_ = nullptr; // inverse of A_{L_s} (row-major)
+  c64 coarse_trace_ = {0, 0};
+
+  // FP64 buffers of a sample batch
+  double *b1_ = nullptr, *y1_ = nullptr, *b2_ = nullptr, *y2_ = nullptr, *r64_ = nullptr;
+  float* r32_ = nullptr;
+  float* d32_ = nullptr;
+  c64* partials_ = nullptr;
+  int64_t partials_cap_ = 0;
+  // per-column scalar arrays (nb_ entries each); kErr1..kQb are consecutive
+  enum { kRr0, kRz, kTmp, kAlpha, kBeta, kBb, kBd, kRres, kErr1, kErr2, kQa, kQb,
+         kNumScalars };
+  c64* scal_[kNumScalars] = {};
+  int *act_outer_ = nullptr, *act_inner_ = nullptr, *count_dev_ = nullptr;
+  int* count_host_ = nullptr;
+  c64* host_c64_ = nullptr;  // pinned, 8*nb
+  int* piv_ = nullptr;
+};
+
+// ---------------------------------------------------------------------------
+// Estimator driver (host only).  The sampler fills `count` samples of a level.
+// ---------------------------------------------------------------------------
+struct SamplerIface {
+  std::function<void(int level, int64_t first, int64_t count, c64* out)> sample;
+  std::function<void(int64_t count, c64* out)> pilot;
+};
+
+void run_estimator(int L, const SamplerIface& smp, c64 coarse, const std::vector<double>& cost,
+                   const mlmc_options& opt, double tol, mlmc_result* out);
+void run_hutchinson(const std::function<void(int64_t, int64_t, c64*)>& sample,
+                    const std::function<void(int64_t, c64*)>& pilot, const mlmc_options& opt,
+                    double tol, mlmc_result* out);
+
+}  // namespace mlmc

@@ -1,0 +1,125 @@
+// Launchers of the HIP kernels.  All vectors are RHS-major blocks: column k of
+// length n starts at k*n.  `active` (nullable) is a per-column flag array on
+// the device: kernels skip columns whose flag is 0 (converged solves).
+#pragma once
+
+#include "common.h"
+
+namespace mlmc {
+
+constexpr int kThreads = 256;
+constexpr int kMaxPartials = 1024;  // per-column partial sums of a reduction
+
+// ----- vectors ---------------------------------------------------------------
+template <typename T>
+void vec_zero(T* x, int64_t n, int nb, const int* active, hipStream_t s);
+template <typename T>
+void vec_copy(const T* x, T* y, int64_t n, int nb, const int* active, hipStream_t s);
+template <typename To, typename From>
+void vec_convert(const From* x, To* y, int64_t n, int nb, const int* active, hipStream_t s);
+
+// number of partial sums per column for a reduction over n elements
+int reduce_blocks(int64_t n);
+// partials[k*nblk + b] (re, im) = sum over block b of conj(x) y, column k
+template <typename T>
+void vec_dot_partials(const T* x, const T* y, int64_t n, int nb, const int* active,
+                      c64* partials, hipStream_t s);
+// out[k] = fixed-order sum of column k's nblk partials
+void finish_sums(const c64* partials, int nblk, int nb, c64* out, hipStream_t s);
+
+// ----- Krylov scalars (one thread per column) --------------------------------
+// alpha = active ? rz/pq : 0   (Hermitian CG, real rz and pq)
+void cg_alpha(const c64* rz, const c64* pq, const int* active, c64* alpha, int nb,
+              hipStream_t s);
+// beta = rz_new/rz ; rz = rz_new
+void cg_beta(const c64* rz_new, c64* rz, const int* active, c64* beta, int nb,
+             hipStream_t s);
+// active[k] &= (rr[k] > tol2 * ref[k]); count = number still active
+void mark_converged(const c64* rr, const c64* ref, double tol2, int* active, int nb,
+                    int* count, hipStream_t s);
+void count_active(const int* active, int nb, int* count, hipStream_t s);
+void set_all_active(int* active, int nb, hipStream_t s);
+// dst[k] = active[k] ? src[k] : dst[k]
+void select_active(c64* dst, const c64* src, const int* active, int nb, hipStream_t s);
+// lastcorr[k] = alpha[k]*rz[k] for active columns (CG step's share of b^H x)
+void cg_lastcorr(const c64* alpha, const c64* rz, const int* active, c64* lastcorr, int nb,
+                 hipStream_t s);
+
+// x += alpha p ; r -= alpha q ; partials of |r|^2
+template <typename T>
+void cg_update_xr(T* x, T* r, const T* p, const T* q, const c64* alpha, int64_t n,
+                  int nb, const int* active, c64* partials, hipStream_t s);
+// p = z + beta p
+template <typename T>
+void cg_update_p(T* p, const T* z, const c64* beta, int64_t n, int nb,
+                 const int* active, hipStream_t s);
+// y64 += convert(d)
+template <typename T64, typename T32>
+void ir_accumulate(T64* y, const T32* d, int64_t n, int nb, const int* active,
+                   hipStream_t s);
+// y += a[k] * x  (column scalars)
+template <typename T>
+void vec_axpy_cols(T* y, const T* x, const c64* a, int64_t n, int nb,
+                   const int* active, hipStream_t s);
+
+// ----- probes and quadratic forms -------------------------------------------
+template <typename T>
+void probes_write(T* out, int64_t n, int nb, uint64_t seed, uint64_t problem,
+                  uint64_t first_sample, uint64_t level, uint64_t stream,
+                  hipStream_t s);
+// partials of x_k^H y_k with x_k regenerated from the RNG
+template <typename T>
+void probe_dot_partials(const T* y, int64_t n, int nb, uint64_t seed, uint64_t problem,
+                        uint64_t first_sample, uint64_t level, uint64_t stream,
+                        c64* partials, hipStream_t s);
+
+// ----- dense coarsest level -------------------------------------------------
+// in-place Gauss-Jordan inverse with partial pivoting of the n x n matrix held
+// in the left half of aug (n x 2n, row-major); right half receives A^{-1}
+template <typename T>
+void dense_invert(T* aug, int n, T* rowbuf, T* colbuf, int* piv, hipStream_t s);
+template <typename T>
+void dense_extract_right(const T* aug, int n, T* out, hipStream_t s);
+template <typename T>
+void dense_set_identity_right(T* aug, int n, hipStream_t s);
+// trace partial: out = sum_i A[i][i] (single block)
+template <typename T>
+void dense_trace(const T* A, int n, c64* out, hipStream_t s);
+// Z[k][i] = sum_j At[j][i] B[k][j], k < nb: the coarsest solve z_k = A^{-1} b_k
+// with At the transposed inverse
+template <typename T>
+void dense_apply(const T* At, const T* B, T* Z, int n, int nb, const int* active,
+                 hipStream_t s);
+// out[j][i] = in[i][j] (n x n)
+template <typename T>
+void dense_transpose(const T* in, T* out, int n, hipStream_t s);
+
+// ----- 2D Poisson stencil: A = d I - c (grid neighbours), N x N Dirichlet -----
+template <typename T>
+void poisson_dense_build(T* aug, int N, double d, double c, hipStream_t s);
+// y = A x ; optional partials of conj(x)^T y (pass partials = nullptr to skip)
+template <typename T>
+void poisson_apply(const T* x, T* y, int N, double d, double c, int nb,
+                   const int* active, c64* partials, hipStream_t s);
+// r = b - A x (Tr may be lower precision) ; optional partials of |r|^2
+template <typename Tb, typename Tx, typename Tr>
+void poisson_residual(const Tb* b, const Tx* x, Tr* r, int N, double d, double c,
+                      int nb, const int* active, c64* partials, hipStream_t s);
+// one red-black Gauss-Seidel sweep (red then black; reverse: black then red);
+// zero_init: x is taken as 0 on entry
+template <typename T>
+void poisson_rbgs(const T* b, T* x, int N, double d, double c, int nb,
+                  const int* active, bool zero_init, bool reverse, hipStream_t s);
+// rc = R (b - A x), R = P^T, P the orthonormal 2x2 aggregation (entries 1/2)
+template <typename T>
+void poisson_residual_restrict(const T* b, const T* x, T* rc, int N, double d,
+                               double c, int nb, const int* active, hipStream_t s);
+// xc = R x
+template <typename T>
+void agg2d_restrict(const T* x, T* xc, int N, int nb, const int* active, hipStream_t s);
+// x = beta*x + omega * P ec
+template <typename T>
+void agg2d_prolong(const T* ec, T* x, int N, double omega, double beta, int nb,
+                   const int* active, hipStream_t s);
+
+}  // namespace mlmc

@@ -1,0 +1,627 @@
+// Vector, reduction, Krylov-scalar, probe and dense kernels.
+#include "kernels.h"
+
+namespace mlmc {
+
+namespace {
+
+inline dim3 grid_cols(int64_t n, int nb, int per_thread = 1) {
+  int64_t per_block = (int64_t)kThreads * per_thread;
+  return dim3((unsigned)((n + per_block - 1) / per_block), (unsigned)nb);
+}
+
+template <typename T>
+__global__ void k_zero(T* x, int64_t n, const int* active) {
+  const int k = blockIdx.y;
+  if (active && !active[k]) return;
+  int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i < n) x[(int64_t)k * n + i] = zero_of(T());
+}
+
+template <typename To, typename From>
+__global__ void k_convert(const From* x, To* y, int64_t n, const int* active) {
+  const int k = blockIdx.y;
+  if (active && !active[k]) return;
+  int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i < n) y[(int64_t)k * n + i] = convert<To, From>(x[(int64_t)k * n + i]);
+}
+
+// grid (nblk, nb): block b of column k reduces a contiguous chunk
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_dot(const T* x, const T* y, int64_t n,
+                                                  const int* active, c64* partials) {
+  __shared__ double lds[16];
+  const int k = blockIdx.y, nblk = gridDim.x;
+  if (active && !active[k]) return;
+  const int64_t chunk = (n + nblk - 1) / nblk;
+  const int64_t lo = (int64_t)blockIdx.x * chunk;
+  const int64_t hi = lo + chunk < n ? lo + chunk : n;
+  const T* xc = x + (int64_t)k * n;
+  const T* yc = y + (int64_t)k * n;
+  double re = 0.0, im = 0.0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kThreads) cdot_acc(re, im, xc[i], yc[i]);
+  block_sum2<kThreads>(re, im, lds);
+  if (threadIdx.x == 0) partials[(int64_t)k * nblk + blockIdx.x] = {re, im};
+}
+
+__global__ __launch_bounds__(kThreads) void k_finish(const c64* partials, int nblk,
+                                                     c64* out) {
+  __shared__ double lds[16];
+  const int k = blockIdx.x;
+  double re = 0.0, im = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += kThreads) {
+    c64 v = partials[(int64_t)k * nblk + b];
+    re += v.re;
+    im += v.im;
+  }
+  block_sum2<kThreads>(re, im, lds);
+  if (threadIdx.x == 0) out[k] = {re, im};
+}
+
+__global__ void k_cg_alpha(const c64* rz, const c64* pq, const int* active, c64* alpha,
+                           int nb) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nb) return;
+  double a = 0.0;
+  if ((!active || active[k]) && pq[k].re != 0.0 && isfinite(pq[k].re))
+    a = rz[k].re / pq[k].re;
+  alpha[k] = {a, 0.0};
+}
+
+__global__ void k_cg_beta(const c64* rz_new, c64* rz, const int* active, c64* beta,
+                          int nb) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nb) return;
+  double b = 0.0;
+  if ((!active || active[k]) && rz[k].re != 0.0) b = rz_new[k].re / rz[k].re;
+  beta[k] = {b, 0.0};
+  rz[k] = rz_new[k];
+}
+
+__global__ void k_mark(const c64* rr, const c64* ref, double tol2, int* active, int nb,
+                       int* count) {
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  for (int k = threadIdx.x; k < nb; k += blockDim.x) {
+    int a = active[k];
+    if (a && rr[k].re <= tol2 * ref[k].re) a = 0;
+    if (a && !isfinite(rr[k].re)) a = 0;   // reported by the host as non-converged
+    active[k] = a;
+    if (a) atomicAdd(&cnt, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *count = cnt;
+}
+
+__global__ void k_count(const int* active, int nb, int* count) {
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  for (int k = threadIdx.x; k < nb; k += blockDim.x)
+    if (active[k]) atomicAdd(&cnt, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) *count = cnt;
+}
+
+__global__ void k_set_ones(int* a, int nb) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nb) a[k] = 1;
+}
+
+__global__ void k_select(c64* dst, const c64* src, const int* active, int nb) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nb && active[k]) dst[k] = src[k];
+}
+
+__global__ void k_lastcorr(const c64* alpha, const c64* rz, const int* active, c64* lc,
+                           int nb) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nb && (!active || active[k])) lc[k] = {alpha[k].re * rz[k].re, 0.0};
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_cg_xr(T* x, T* r, const T* p, const T* q,
+                                                    const c64* alpha, int64_t n,
+                                                    const int* active, c64* partials) {
+  __shared__ double lds[16];
+  const int k = blockIdx.y, nblk = gridDim.x;
+  if (active && !active[k]) return;
+  const c64 a = alpha[k];
+  const int64_t chunk = (n + nblk - 1) / nblk;
+  const int64_t lo = (int64_t)blockIdx.x * chunk;
+  const int64_t hi = lo + chunk < n ? lo + chunk : n;
+  const int64_t off = (int64_t)k * n;
+  double re = 0.0, im = 0.0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kThreads) {
+    T xi = x[off + i] + scale_by(a.re, a.im, p[off + i]);
+    T ri = r[off + i] - scale_by(a.re, a.im, q[off + i]);
+    x[off + i] = xi;
+    r[off + i] = ri;
+    cdot_acc(re, im, ri, ri);
+  }
+  block_sum2<kThreads>(re, im, lds);
+  if (threadIdx.x == 0) partials[(int64_t)k * nblk + blockIdx.x] = {re, im};
+}
+
+template <typename T>
+__global__ void k_cg_p(T* p, const T* z, const c64* beta, int64_t n, const int* active) {
+  const int k = blockIdx.y;
+  if (active && !active[k]) return;
+  int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  const int64_t j = (int64_t)k * n + i;
+  const c64 b = beta[k];
+  p[j] = z[j] + scale_by(b.re, b.im, p[j]);
+}
+
+template <typename T64, typename T32>
+__global__ void k_ir_acc(T64* y, const T32* d, int64_t n, const int* active) {
+  const int k = blockIdx.y;
+  if (active && !active[k]) return;
+  int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  const int64_t j = (int64_t)k * n + i;
+  y[j] = y[j] + convert<T64, T32>(d[j]);
+}
+
+template <typename T>
+__global__ void k_axpy_cols(T* y, const T* x, const c64* a, int64_t n, const int* active) {
+  const int k = blockIdx.y;
+  if (active && !active[k]) return;
+  int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  const int64_t j = (int64_t)k * n + i;
+  y[j] = y[j] + scale_by(a[k].re, a[k].im, x[j]);
+}
+
+// ---- probes: a block computes 256 Philox blocks into LDS, then expands them.
+constexpr int kProbeWordsPerBlock = kThreads * 4;  // 64-bit words
+
+template <typename T> struct ProbeLayout;
+template <> struct ProbeLayout<double> { static constexpr int bits = 1; };
+template <> struct ProbeLayout<float> { static constexpr int bits = 1; };
+template <> struct ProbeLayout<c64> { static constexpr int bits = 2; };
+template <> struct ProbeLayout<c32> { static constexpr int bits = 2; };
+
+template <typename T>
+__device__ __forceinline__ T probe_from_words(const uint64_t* words, int64_t local);
+
+template <>
+__device__ __forceinline__ double probe_from_words<double>(const uint64_t* w, int64_t l) {
+  return ((w[l >> 6] >> (l & 63)) & 1ull) ? -1.0 : 1.0;
+}
+template <>
+__device__ __forceinline__ float probe_from_words<float>(const uint64_t* w, int64_t l) {
+  return ((w[l >> 6] >> (l & 63)) & 1ull) ? -1.f : 1.f;
+}
+template <>
+__device__ __forceinline__ c64 probe_from_words<c64>(const uint64_t* w, int64_t l) {
+  int f = (int)((w[l >> 5] >> (2 * (l & 31))) & 3ull);
+  c64 r;
+  r.re = (f == 0) ? 1.0 : (f == 2 ? -1.0 : 0.0);
+  r.im = (f == 1) ? 1.0 : (f == 3 ? -1.0 : 0.0);
+  return r;
+}
+template <>
+__device__ __forceinline__ c32 probe_from_words<c32>(const uint64_t* w, int64_t l) {
+  c64 z = probe_from_words<c64>(w, l);
+  return {(float)z.re, (float)z.im};
+}
+
+// entries covered by one thread block: 256 Philox blocks of 256 bits
+template <typename T> constexpr int64_t probe_chunk() {
+  return (int64_t)kThreads * 256 / ProbeLayout<T>::bits;
+}
+
+template <typename T>
+__device__ __forceinline__ void probe_fill_lds(uint64_t* words, int64_t chunk_index,
+                                               const ProbeKey& key) {
+  // Philox block index of this thread: entry e belongs to block e >> (8 - bits + 1)
+  // i.e. 256 (Rademacher) or 128 (Z4) entries per Philox block.
+  const uint64_t blk = (uint64_t)chunk_index * kThreads + threadIdx.x;
+  u64x4 w = philox4x64_10(blk, key.sample, key.level, key.stream, key.seed, key.problem);
+  words[4 * threadIdx.x + 0] = w.v[0];
+  words[4 * threadIdx.x + 1] = w.v[1];
+  words[4 * threadIdx.x + 2] = w.v[2];
+  words[4 * threadIdx.x + 3] = w.v[3];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_probes(T* out, int64_t n, ProbeKey key) {
+  __shared__ uint64_t words[kProbeWordsPerBlock];
+  const int k = blockIdx.y;
+  ProbeKey kk = key;
+  kk.sample = key.sample + k;
+  probe_fill_lds<T>(words, blockIdx.x, kk);
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * probe_chunk<T>();
+  T* o = out + (int64_t)k * n;
+  for (int64_t l = threadIdx.x; l < probe_chunk<T>(); l += kThreads) {
+    int64_t i = base + l;
+    if (i < n) o[i] = probe_from_words<T>(words, l);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_probe_dot(const T* y, int64_t n, ProbeKey key,
+                                                        c64* partials) {
+  __shared__ uint64_t words[kProbeWordsPerBlock];
+  __shared__ double lds[16];
+  const int k = blockIdx.y;
+  ProbeKey kk = key;
+  kk.sample = key.sample + k;
+  probe_fill_lds<T>(words, blockIdx.x, kk);
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * probe_chunk<T>();
+  const T* yc = y + (int64_t)k * n;
+  double re = 0.0, im = 0.0;
+  for (int64_t l = threadIdx.x; l < probe_chunk<T>(); l += kThreads) {
+    int64_t i = base + l;
+    if (i < n) cdot_acc(re, im, probe_from_words<T>(words, l), yc[i]);
+  }
+  block_sum2<kThreads>(re, im, lds);
+  if (threadIdx.x == 0) partials[(int64_t)k * gridDim.x + blockIdx.x] = {re, im};
+}
+
+// ---- dense Gauss-Jordan with partial pivoting on [A | I] (n x 2n) ----------
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_gj_pivot(const T* M, int n, int kcol, int* piv) {
+  __shared__ double bv[kThreads];
+  __shared__ int bi[kThreads];
+  const int64_t ld = 2 * (int64_t)n;
+  double best = -1.0;
+  int besti = kcol;
+  for (int i = kcol + threadIdx.x; i < n; i += kThreads) {
+    double v = abs2_of(M[(int64_t)i * ld + kcol]);
+    if (v > best) {
+      best = v;
+      besti = i;
+    }
+  }
+  bv[threadIdx.x] = best;
+  bi[threadIdx.x] = besti;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      double o = bv[threadIdx.x + s];
+      int oi = bi[threadIdx.x + s];
+      if (o > bv[threadIdx.x] || (o == bv[threadIdx.x] && oi < bi[threadIdx.x])) {
+        bv[threadIdx.x] = o;
+        bi[threadIdx.x] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *piv = bi[0];
+}
+
+template <typename T>
+__global__ void k_gj_swap(T* M, int n, int kcol, const int* piv) {
+  const int p = *piv;
+  if (p == kcol) return;
+  const int64_t ld = 2 * (int64_t)n;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < ld;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    T a = M[(int64_t)kcol * ld + j];
+    M[(int64_t)kcol * ld + j] = M[(int64_t)p * ld + j];
+    M[(int64_t)p * ld + j] = a;
+  }
+}
+
+HD double inv_re(double a) { return 1.0 / a; }
+
+__device__ __forceinline__ double recip(double a) { return 1.0 / a; }
+__device__ __forceinline__ c64 recip(c64 a) {
+  double d = a.re * a.re + a.im * a.im;
+  return {a.re / d, -a.im / d};
+}
+__device__ __forceinline__ float recip(float a) { return 1.f / a; }
+__device__ __forceinline__ c32 recip(c32 a) {
+  float d = a.re * a.re + a.im * a.im;
+  return {a.re / d, -a.im / d};
+}
+
+template <typename T>
+__global__ void k_gj_extract(const T* M, int n, int kcol, T* rowbuf, T* colbuf) {
+  const int64_t ld = 2 * (int64_t)n;
+  const T inv = recip(M[(int64_t)kcol * ld + kcol]);
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < ld;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    rowbuf[j] = inv * M[(int64_t)kcol * ld + j];
+    if (j < n) colbuf[j] = M[j * ld + kcol];
+  }
+}
+
+template <typename T>
+__global__ void k_gj_eliminate(T* M, int n, int kcol, const T* rowbuf, const T* colbuf) {
+  const int64_t ld = 2 * (int64_t)n;
+  const int i = blockIdx.y;
+  const T f = colbuf[i];
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < ld;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    if (i == kcol)
+      M[(int64_t)i * ld + j] = rowbuf[j];
+    else
+      M[(int64_t)i * ld + j] = M[(int64_t)i * ld + j] - f * rowbuf[j];
+  }
+}
+
+template <typename T>
+__global__ void k_set_identity_right(T* M, int n) {
+  const int64_t ld = 2 * (int64_t)n;
+  const int i = blockIdx.y;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    T v = zero_of(T());
+    if (j == i) {
+      c64 one = {1.0, 0.0};
+      v = convert<T, c64>(one);
+    }
+    M[(int64_t)i * ld + n + j] = v;
+  }
+}
+
+template <typename T>
+__global__ void k_extract_right(const T* M, int n, T* out) {
+  const int64_t ld = 2 * (int64_t)n;
+  const int i = blockIdx.y;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+       j += (int64_t)gridDim.x * blockDim.x)
+    out[(int64_t)i * n + j] = M[(int64_t)i * ld + n + j];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_trace(const T* A, int n, c64* out) {
+  __shared__ double lds[16];
+  double re = 0.0, im = 0.0;
+  for (int i = threadIdx.x; i < n; i += kThreads) {
+    c64 one = {1.0, 0.0};
+    T o = convert<T, c64>(one);
+    cdot_acc(re, im, o, A[(int64_t)i * n + i]);
+  }
+  block_sum2<kThreads>(re, im, lds);
+  if (threadIdx.x == 0) *out = {re, im};
+}
+
+// Z[k][i] = sum_j At[j][i] B[k][j] (At = A transposed, so a wave reads 64
+// consecutive i): tile of 64 outputs i x 4 columns k per block; B rows in LDS.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_dense_apply(const T* At, const T* B, T* Z,
+                                                          int n, int nb, const int* active) {
+  constexpr int TK = 64;   // j tile
+  __shared__ T bs[4][TK];
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int kl = threadIdx.x >> 6;          // 0..3
+  const int k = blockIdx.y * 4 + kl;
+  const bool kok = k < nb && (!active || active[k]);
+  T acc = zero_of(T());
+  for (int j0 = 0; j0 < n; j0 += TK) {
+    __syncthreads();
+    {
+      int jj = threadIdx.x & 63;
+      bs[kl][jj] = (k < nb && j0 + jj < n) ? B[(int64_t)k * n + j0 + jj] : zero_of(T());
+    }
+    __syncthreads();
+    if (i < n && kok) {
+      const int jmax = (n - j0) < TK ? (n - j0) : TK;
+      const T* acol = At + (int64_t)j0 * n + i;
+      for (int jj = 0; jj < jmax; ++jj) acc += acol[(int64_t)jj * n] * bs[kl][jj];
+    }
+  }
+  if (i < n && kok) Z[(int64_t)k * n + i] = acc;
+}
+
+}  // namespace
+
+// ============================================================================
+template <typename T>
+void vec_zero(T* x, int64_t n, int nb, const int* active, hipStream_t s) {
+  if (n <= 0 || nb <= 0) return;
+  hipLaunchKernelGGL(k_zero<T>, grid_cols(n, nb), dim3(kThreads), 0, s, x, n, active);
+}
+template <typename T>
+void vec_copy(const T* x, T* y, int64_t n, int nb, const int* active, hipStream_t s) {
+  if (n <= 0 || nb <= 0) return;
+  hipLaunchKernelGGL((k_convert<T, T>), grid_cols(n, nb), dim3(kThreads), 0, s, x, y, n,
+                     active);
+}
+template <typename To, typename From>
+void vec_convert(const From* x, To* y, int64_t n, int nb, const int* active, hipStream_t s) {
+  if (n <= 0 || nb <= 0) return;
+  hipLaunchKernelGGL((k_convert<To, From>), grid_cols(n, nb), dim3(kThreads), 0, s, x, y, n,
+                     active);
+}
+
+int reduce_blocks(int64_t n) {
+  int64_t b = (n + 4 * kThreads - 1) / (4 * kThreads);
+  if (b < 1) b = 1;
+  if (b > kMaxPartials) b = kMaxPartials;
+  return (int)b;
+}
+
+template <typename T>
+void vec_dot_partials(const T* x, const T* y, int64_t n, int nb, const int* active,
+                      c64* partials, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot<T>, dim3(reduce_blocks(n), nb), dim3(kThreads), 0, s, x, y, n,
+                     active, partials);
+}
+
+void finish_sums(const c64* partials, int nblk, int nb, c64* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish, dim3(nb), dim3(kThreads), 0, s, partials, nblk, out);
+}
+
+void cg_alpha(const c64* rz, const c64* pq, const int* active, c64* alpha, int nb,
+              hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_alpha, dim3((nb + 255) / 256), dim3(256), 0, s, rz, pq, active,
+                     alpha, nb);
+}
+void cg_beta(const c64* rz_new, c64* rz, const int* active, c64* beta, int nb,
+             hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_beta, dim3((nb + 255) / 256), dim3(256), 0, s, rz_new, rz, active,
+                     beta, nb);
+}
+void mark_converged(const c64* rr, const c64* ref, double tol2, int* active, int nb,
+                    int* count, hipStream_t s) {
+  hipLaunchKernelGGL(k_mark, dim3(1), dim3(256), 0, s, rr, ref, tol2, active, nb, count);
+}
+void count_active(const int* active, int nb, int* count, hipStream_t s) {
+  hipLaunchKernelGGL(k_count, dim3(1), dim3(256), 0, s, active, nb, count);
+}
+
+void set_all_active(int* active, int nb, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_ones, dim3((nb + 255) / 256), dim3(256), 0, s, active, nb);
+}
+void select_active(c64* dst, const c64* src, const int* active, int nb, hipStream_t s) {
+  hipLaunchKernelGGL(k_select, dim3((nb + 255) / 256), dim3(256), 0, s, dst, src, active, nb);
+}
+void cg_lastcorr(const c64* alpha, const c64* rz, const int* active, c64* lastcorr, int nb,
+                 hipStream_t s) {
+  hipLaunchKernelGGL(k_lastcorr, dim3((nb + 255) / 256), dim3(256), 0, s, alpha, rz, active,
+                     lastcorr, nb);
+}
+
+template <typename T>
+void cg_update_xr(T* x, T* r, const T* p, const T* q, const c64* alpha, int64_t n, int nb,
+                  const int* active, c64* partials, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_xr<T>, dim3(reduce_blocks(n), nb), dim3(kThreads), 0, s, x, r, p,
+                     q, alpha, n, active, partials);
+}
+template <typename T>
+void cg_update_p(T* p, const T* z, const c64* beta, int64_t n, int nb, const int* active,
+                 hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_p<T>, grid_cols(n, nb), dim3(kThreads), 0, s, p, z, beta, n,
+                     active);
+}
+template <typename T64, typename T32>
+void ir_accumulate(T64* y, const T32* d, int64_t n, int nb, const int* active,
+                   hipStream_t s) {
+  hipLaunchKernelGGL((k_ir_acc<T64, T32>), grid_cols(n, nb), dim3(kThreads), 0, s, y, d, n,
+                     active);
+}
+template <typename T>
+void vec_axpy_cols(T* y, const T* x, const c64* a, int64_t n, int nb, const int* active,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy_cols<T>, grid_cols(n, nb), dim3(kThreads), 0, s, y, x, a, n,
+                     active);
+}
+
+template <typename T>
+void probes_write(T* out, int64_t n, int nb, uint64_t seed, uint64_t problem,
+                  uint64_t first_sample, uint64_t level, uint64_t stream, hipStream_t s) {
+  ProbeKey key{seed, problem, first_sample, level, stream};
+  const int64_t chunk = probe_chunk<T>();
+  dim3 grid((unsigned)((n + chunk - 1) / chunk), (unsigned)nb);
+  hipLaunchKernelGGL(k_probes<T>, grid, dim3(kThreads), 0, s, out, n, key);
+}
+
+template <typename T>
+void probe_dot_partials(const T* y, int64_t n, int nb, uint64_t seed, uint64_t problem,
+                        uint64_t first_sample, uint64_t level, uint64_t stream,
+                        c64* partials, hipStream_t s) {
+  ProbeKey key{seed, problem, first_sample, level, stream};
+  const int64_t chunk = probe_chunk<T>();
+  dim3 grid((unsigned)((n + chunk - 1) / chunk), (unsigned)nb);
+  hipLaunchKernelGGL(k_probe_dot<T>, grid, dim3(kThreads), 0, s, y, n, key, partials);
+}
+
+template <typename T>
+void dense_set_identity_right(T* aug, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_identity_right<T>, dim3((n + 255) / 256, n), dim3(256), 0, s, aug,
+                     n);
+}
+
+template <typename T>
+void dense_invert(T* aug, int n, T* rowbuf, T* colbuf, int* piv, hipStream_t s) {
+  const int64_t ld = 2 * (int64_t)n;
+  const unsigned gx = (unsigned)((ld + 255) / 256);
+  for (int kcol = 0; kcol < n; ++kcol) {
+    hipLaunchKernelGGL(k_gj_pivot<T>, dim3(1), dim3(kThreads), 0, s, aug, n, kcol, piv);
+    hipLaunchKernelGGL(k_gj_swap<T>, dim3(gx), dim3(256), 0, s, aug, n, kcol, piv);
+    hipLaunchKernelGGL(k_gj_extract<T>, dim3(gx), dim3(256), 0, s, aug, n, kcol, rowbuf,
+                       colbuf);
+    hipLaunchKernelGGL(k_gj_eliminate<T>, dim3(gx, n), dim3(256), 0, s, aug, n, kcol,
+                       rowbuf, colbuf);
+  }
+}
+
+template <typename T>
+void dense_extract_right(const T* aug, int n, T* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_extract_right<T>, dim3((n + 255) / 256, n), dim3(256), 0, s, aug, n,
+                     out);
+}
+
+template <typename T>
+void dense_trace(const T* A, int n, c64* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_trace<T>, dim3(1), dim3(kThreads), 0, s, A, n, out);
+}
+
+template <typename T>
+void dense_apply(const T* At, const T* B, T* Z, int n, int nb, const int* active,
+                 hipStream_t s) {
+  dim3 grid((unsigned)((n + 63) / 64), (unsigned)((nb + 3) / 4));
+  hipLaunchKernelGGL(k_dense_apply<T>, grid, dim3(kThreads), 0, s, At, B, Z, n, nb, active);
+}
+
+// ---- explicit instantiations ----------------------------------------------
+#define MLMC_INST_T(T)                                                                    \
+  template void vec_zero<T>(T*, int64_t, int, const int*, hipStream_t);                  \
+  template void vec_copy<T>(const T*, T*, int64_t, int, const int*, hipStream_t);        \
+  template void vec_dot_partials<T>(const T*, const T*, int64_t, int, const int*, c64*,  \
+                                    hipStream_t);                                        \
+  template void cg_update_xr<T>(T*, T*, const T*, const T*, const c64*, int64_t, int,    \
+                                const int*, c64*, hipStream_t);                          \
+  template void cg_update_p<T>(T*, const T*, const c64*, int64_t, int, const int*,       \
+                               hipStream_t);                                             \
+  template void vec_axpy_cols<T>(T*, const T*, const c64*, int64_t, int, const int*,     \
+                                 hipStream_t);                                           \
+  template void probes_write<T>(T*, int64_t, int, uint64_t, uint64_t, uint64_t, uint64_t, \
+                                uint64_t, hipStream_t);                                  \
+  template void probe_dot_partials<T>(const T*, int64_t, int, uint64_t, uint64_t,        \
+                                      uint64_t, uint64_t, uint64_t, c64*, hipStream_t);  \
+  template void dense_invert<T>(T*, int, T*, T*, int*, hipStream_t);                     \
+  template void dense_extract_right<T>(const T*, int, T*, hipStream_t);                  \
+  template void dense_set_identity_right<T>(T*, int, hipStream_t);                       \
+  template void dense_trace<T>(const T*, int, c64*, hipStream_t);                        \
+  template void dense_apply<T>(const T*, const T*, T*, int, int, const int*, hipStream_t);
+
+MLMC_INST_T(float)
+MLMC_INST_T(double)
+MLMC_INST_T(c32)
+MLMC_INST_T(c64)
+
+template void vec_convert<float, double>(const double*, float*, int64_t, int, const int*,
+                                         hipStream_t);
+template void vec_convert<double, float>(const float*, double*, int64_t, int, const int*,
+                                         hipStream_t);
+template void vec_convert<c32, c64>(const c64*, c32*, int64_t, int, const int*, hipStream_t);
+template void vec_convert<c64, c32>(const c32*, c64*, int64_t, int, const int*, hipStream_t);
+template void ir_accumulate<double, float>(double*, const float*, int64_t, int, const int*,
+                                           hipStream_t);
+template void ir_accumulate<c64, c32>(c64*, const c32*, int64_t, int, const int*,
+                                      hipStream_t);
+template void ir_accumulate<double, double>(double*, const double*, int64_t, int,
+                                            const int*, hipStream_t);
+template void ir_accumulate<c64, c64>(c64*, const c64*, int64_t, int, const int*,
+                                      hipStream_t);
+
+}  // namespace mlmc
+
+namespace mlmc {
+namespace {
+template <typename T>
+__global__ void k_transpose(const T* in, T* out, int n) {
+  const int i = blockIdx.y;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x)
+    out[(int64_t)j * n + i] = in[(int64_t)i * n + j];
+}
+}  // namespace
+template <typename T>
+void dense_transpose(const T* in, T* out, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_transpose<T>, dim3((n + 255) / 256, n), dim3(256), 0, s, in, out, n);
+}
+template void dense_transpose<float>(const float*, float*, int, hipStream_t);
+template void dense_transpose<double>(const double*, double*, int, hipStream_t);
+template void dense_transpose<c32>(const c32*, c32*, int, hipStream_t);
+template void dense_transpose<c64>(const c64*, c64*, int, hipStream_t);
+}  // namespace mlmc

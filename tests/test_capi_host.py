@@ -1,0 +1,125 @@
+"""CPU-only checks of the C ABI: the library loads, exports every declared
+symbol, and the host estimator driver follows the same rules as the oracle."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2108_11281_amd as m
+from oracle import mlmc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "mlmc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = set(re.findall(r"\b(mlmc_[a-z_]+)\s*\(", src))
+    return sorted(n for n in names if not n.endswith("_fn"))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = m.lib()
+    names = _declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    from paper_2108_11281_amd import _capi
+    assert set(names) == set(_capi.SIGNATURES)
+
+
+def test_struct_sizes_match_header_layout():
+    from paper_2108_11281_amd import _capi
+    # mlmc_result: 2+1+1+2 doubles, int (+pad), 16 int64, 32+16+16 doubles, 2 int64, 2 doubles
+    assert ctypes.sizeof(_capi.Result) == 8 * (6 + 1 + 16 + 32 + 16 + 16 + 2 + 2)
+    assert ctypes.sizeof(_capi.Options) == 96
+
+
+def test_default_options_and_status_strings():
+    o = m.default_options()
+    assert o.nb == 128 and o.min_samples == 5 and o.precision == m.FP32_IR64
+    assert m.lib().mlmc_status_string(-4) == b"not converged"
+
+
+def test_null_arguments_are_rejected():
+    lib = m.lib()
+    assert lib.mlmc_trace(None, 1e-2, 1, None) == -1
+    assert lib.mlmc_setup(None, None, None, None, None) == -1
+
+
+class MockSampler:
+    """Deterministic synthetic samples with known level means and variances."""
+
+    def __init__(self, means, sds, seed=0):
+        self.means, self.sds, self.seed = means, sds, seed
+        self.L = len(means) + 1
+
+    def _draw(self, level, k):
+        rng = np.random.default_rng([self.seed, level, k])
+        return self.means[level - 1] + self.sds[level - 1] * rng.standard_normal()
+
+    def sample(self, level, seed, first, count):
+        return np.array([self._draw(level, first + j) for j in range(count)])
+
+    def hutchinson(self, seed, first, count, stream=1, level=1):
+        rng = np.random.default_rng([self.seed, 99, first])
+        return 1000.0 + 30.0 * rng.standard_normal(count)
+
+    def coarse(self):
+        return 250.0
+
+    def cost(self, level):
+        return 4.0 ** (self.L - level)
+
+
+@pytest.mark.parametrize("alloc", [mlmc.ALLOC_EQUAL, mlmc.ALLOC_GILES, mlmc.ALLOC_WEIGHTS])
+def test_host_driver_matches_oracle_driver(alloc):
+    smp = MockSampler([400.0, 200.0, 100.0], [60.0, 40.0, 25.0])
+    w = [0.5, 0.3, 0.2]
+    ref = mlmc.mlmc_trace(smp, 5e-3, 0, nb=64, alloc=alloc, weights=w)
+    kw = dict(nb=64, alloc=alloc)
+    if alloc == mlmc.ALLOC_WEIGHTS:
+        kw["rho_weights"] = w
+    got = m.run_estimator(4, lambda l, f, c: smp.sample(l, 0, f, c), 5e-3,
+                          pilot=lambda c: smp.hutchinson(0, 0, c), coarse=smp.coarse(),
+                          cost=[smp.cost(l) for l in (1, 2, 3)], **kw)
+    assert got["n_samples"] == ref["n_samples"]
+    assert abs(got["trace"] - ref["trace"]) < 1e-12 * abs(ref["trace"])
+    assert abs(got["rmsd"] - ref["rmsd"]) < 1e-12 * ref["rmsd"]
+    assert abs(got["tau"] - ref["tau"]) < 1e-12 * ref["tau"]
+
+
+def test_host_driver_minimum_samples_and_tau_override():
+    smp = MockSampler([400.0, 200.0], [1e-3, 1e-3])
+    got = m.run_estimator(3, lambda l, f, c: smp.sample(l, 0, f, c), 1e-2, tau=1000.0,
+                          coarse=5.0)
+    assert got["n_samples"] == [5, 5]
+    assert got["tau"] == 1000.0
+
+
+def test_host_driver_reports_sampler_failure():
+    def bad(level, first, count):
+        return np.full(count, np.nan)
+    with pytest.raises(m.MLMCError) as e:
+        m.run_estimator(3, bad, 1e-2, tau=1.0)
+    assert e.value.code == -4
+
+
+def test_host_driver_max_samples_is_enforced():
+    smp = MockSampler([400.0, 200.0], [100.0, 100.0])
+    with pytest.raises(m.MLMCError) as e:
+        m.run_estimator(3, lambda l, f, c: smp.sample(l, 0, f, c), 1e-5, tau=1.0,
+                        max_samples=20, nb=8)
+    assert e.value.code == -4
+
+
+def test_complex_samples_pass_through():
+    def smp(level, first, count):
+        rng = np.random.default_rng([level, first])
+        return (1 + 2j) + rng.standard_normal(count) + 1j * rng.standard_normal(count)
+    got = m.run_estimator(2, smp, 1e-1, tau=10.0, coarse=1 - 1j)
+    ref = mlmc.mean_and_var(np.concatenate([smp(1, 0, 5)]))
+    assert got["n_samples"] == [5]
+    assert abs(got["trace"] - (ref[0] + 1 - 1j)) < 1e-12

@@ -192,3 +192,13 @@ def test_hutchinson_driver(c0_sampler):
     exact = operators.poisson2d_trace_inverse(64)
     r = mlmc.hutchinson_trace(c0_sampler, 2e-2, 1)
     assert abs(r["trace"].real - exact) < 4 * r["rmsd"]
+
+
+def test_dst_sampler_matches_sparse_sampler():
+    A, P = hierarchy.poisson_hierarchy(32, 3)
+    ref = mlmc.LevelSampler(A, P, complex_probe=False)
+    dst = mlmc.PoissonDSTSampler(32, 3)
+    for l in (1, 2):
+        assert np.allclose(dst.sample(l, 3, 5, 4), ref.sample(l, 3, 5, 4), rtol=1e-12, atol=1e-12)
+    assert abs(dst.coarse() - ref.coarse()) < 1e-12 * abs(ref.coarse())
+    assert np.allclose(dst.hutchinson(1, 0, 3), ref.hutchinson(1, 0, 3), rtol=1e-12)
