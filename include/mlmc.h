@@ -104,10 +104,12 @@ typedef struct mlmc_options {
   int alloc;          /* enum mlmc_alloc */
   const double* rho_weights; /* MLMC_ALLOC_WEIGHTS: L-1 weights (host) */
   double solve_tol;   /* per-column FP64 relative residual |b-Ay|/|b| target */
-  double inner_tol;   /* FP32 inner solve: relative residual reduction per
-                         refinement step */
-  int max_iter;       /* Krylov iterations per solve (per refinement step) */
-  int max_refine;     /* refinement steps (MLMC_FP32_IR64) */
+  double inner_tol;   /* MLMC_FP32_IR64: FP32 CG residual reduction after which
+                         the iterate is refined in FP64 (y64 += x32, residual
+                         recomputed in FP64; the search direction is kept) */
+  int max_iter;       /* Krylov iterations per solve (MLMC_FP32_IR64: times
+                         max_refine) */
+  int max_refine;     /* MLMC_FP32_IR64: iteration budget multiplier */
   int krylov_restart; /* FGMRES restart length (complex operators) */
   int min_samples;    /* minimum estimates per level difference (5) */
   int64_t max_samples;/* per-level cap; exceeding it returns MLMC_ENOCONV */
@@ -127,6 +129,7 @@ typedef struct mlmc_result {
   double level_mean[MLMC_MAX_LEVELS][2];
   double level_var[MLMC_MAX_LEVELS];
   double level_cost[MLMC_MAX_LEVELS];   /* cost model C_l */
+  double level_seconds[MLMC_MAX_LEVELS];/* wall time spent on level l's samples */
   int64_t solves;             /* right-hand sides solved, all levels */
   int64_t iterations;         /* Krylov iterations x RHS columns, all solves */
   double seconds;             /* wall time of the call */
@@ -134,7 +137,7 @@ typedef struct mlmc_result {
 } mlmc_result;
 
 /* Fill *opt with defaults: FP32_IR64, nb 128, 1+1 sweeps, omega 1.8, EQUAL,
- * solve_tol 1e-10, inner_tol 1e-5, max_iter 200, max_refine 8, restart 16,
+ * solve_tol 1e-10, inner_tol 1e-2, max_iter 200, max_refine 8, restart 16,
  * min_samples 5, max_samples 2^22, tau 0, learned 0. */
 int mlmc_default_options(mlmc_options* opt);
 
@@ -233,6 +236,26 @@ int mlmc_set_allocator(mlmc_alloc_fn alloc, mlmc_free_fn free_fn, void* user);
  * out[0] Krylov iterations (per batch), out[1] refinement steps,
  * out[2] V-cycles, out[3] batches.  n: entries to copy (<= 4). */
 int mlmc_counters(void* ctx, int64_t* out, int n);
+
+/* Measurement mode.  mask: bit i set = every launch of kernel id i (listed
+ * below) is bracketed by HIP events on the context stream and records its
+ * active columns, so that per-kernel launch counts, durations and algorithmic
+ * bytes can be read back; mask = 0 stops it.  Costs two event records per
+ * timed launch. */
+int mlmc_set_timing(void* ctx, int mask);
+
+/* Kernel ids for mlmc_kernel_stats (algorithmic bytes per unknown and RHS for
+ * element size e): 0 fused red-black Gauss-Seidel sweep (2e from a zero start:
+ * b in, x out; 3e with an input iterate; +0.25e with the folded coarse
+ * correction), 1 fused residual + restriction (2.25e), 2 prolongation +
+ * correction when there is no post-smoothing (2.25e), 3 Krylov direction update
+ * fused with the operator apply and its dot (4e: z, p in; p, q out), 4 CG x/r
+ * update with |r|^2 (6e), 5 unused, 6 unused, 7 FP64 refinement residual
+ * (20 bytes: FP64 b and y in, FP32 r out).  fp64 = 0 selects the FP32/complex64
+ * instantiation, 1 the FP64 one.  out: launches, total milliseconds, total
+ * algorithmic bytes (active columns only). */
+int mlmc_kernel_stats(void* ctx, int kernel, int fp64, double* out);
+int mlmc_reset_kernel_stats(void* ctx);
 
 /* Description of the last error on ctx (or of the last failed mlmc_setup
  * when ctx is NULL).  Valid until the next call on ctx. */

@@ -54,34 +54,40 @@ def _result_dict(r):
         level_mean=[complex(r.level_mean[i][0], r.level_mean[i][1]) for i in range(nl)],
         level_var=[r.level_var[i] for i in range(nl)],
         level_cost=[r.level_cost[i] for i in range(nl)],
+        level_seconds=[r.level_seconds[i] for i in range(nl)],
         solves=int(r.solves), iterations=int(r.iterations), seconds=r.seconds)
 
 
 # ---------------------------------------------------------------------------
 # torch's caching allocator as the library's device allocator
 # ---------------------------------------------------------------------------
-_alloc_refs = []
+_alloc_refs = []   # the ctypes thunks live for the whole process
 
 
 def use_torch_allocator(enable=True):
-    """Route the library's device allocations through torch's caching allocator."""
+    """Route the library's device allocations through torch's caching allocator.
+
+    The callbacks are created once per process and never replaced: contexts
+    keep the function pointers they were created with and call them when they
+    are destroyed.
+    """
     if not enable:
         _check(lib().mlmc_set_allocator(_capi.ALLOC_FN(0), _capi.FREE_FN(0), None))
         return
-    import torch
+    if not _alloc_refs:
+        import torch
 
-    def _alloc(nbytes, _user):
-        try:
-            return torch.cuda.caching_allocator_alloc(int(nbytes))
-        except Exception:  # reported to the library as a failed allocation
-            return None
+        def _alloc(nbytes, _user):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes))
+            except Exception:  # reported to the library as a failed allocation
+                return None
 
-    def _free(ptr, _user):
-        torch.cuda.caching_allocator_delete(ptr)
+        def _free(ptr, _user):
+            torch.cuda.caching_allocator_delete(ptr)
 
-    a, f = _capi.ALLOC_FN(_alloc), _capi.FREE_FN(_free)
-    _alloc_refs[:] = [a, f]
-    _check(lib().mlmc_set_allocator(a, f, None))
+        _alloc_refs[:] = [_capi.ALLOC_FN(_alloc), _capi.FREE_FN(_free)]
+    _check(lib().mlmc_set_allocator(_alloc_refs[0], _alloc_refs[1], None))
 
 
 class TraceEstimator:
@@ -197,6 +203,33 @@ class TraceEstimator:
         out = (ctypes.c_int64 * 4)()
         self._c(self._lib.mlmc_counters(self._ctx, out, 4))
         return list(out)
+
+    # -- measurement --
+    KERNELS = ["rbgs_sweep", "residual_restrict", "prolong_correct", "update_apply", "cg_xr",
+               "unused5", "unused6", "ir_residual"]
+
+    def set_timing(self, kernels=True):
+        """kernels: True (all), False (none) or a list of kernel names to time."""
+        if kernels is True:
+            mask = (1 << len(self.KERNELS)) - 1
+        elif not kernels:
+            mask = 0
+        else:
+            mask = 0
+            for k in kernels:
+                mask |= 1 << self.KERNELS.index(k)
+        self._c(self._lib.mlmc_set_timing(self._ctx, int(mask)))
+
+    def reset_kernel_stats(self):
+        self._c(self._lib.mlmc_reset_kernel_stats(self._ctx))
+
+    def kernel_stats(self, kernel, fp64=False):
+        """(launches, total ms, total algorithmic bytes) of a timed kernel."""
+        kid = self.KERNELS.index(kernel) if isinstance(kernel, str) else int(kernel)
+        out = np.zeros(3)
+        self._c(self._lib.mlmc_kernel_stats(self._ctx, kid, 1 if fp64 else 0,
+                                            out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return int(out[0]), float(out[1]), float(out[2])
 
     # -- FP64 building blocks on torch device tensors --
     def _vec(self, level, nrhs, device=None):

@@ -60,6 +60,7 @@ class Result(ctypes.Structure):
                 ("level_mean", (ctypes.c_double * 2) * MAX_LEVELS),
                 ("level_var", ctypes.c_double * MAX_LEVELS),
                 ("level_cost", ctypes.c_double * MAX_LEVELS),
+                ("level_seconds", ctypes.c_double * MAX_LEVELS),
                 ("solves", ctypes.c_int64), ("iterations", ctypes.c_int64),
                 ("seconds", ctypes.c_double), ("max_stated_error", ctypes.c_double)]
 
@@ -101,6 +102,9 @@ SIGNATURES = {
                                           ctypes.POINTER(Result)]),
     "mlmc_set_allocator": (ctypes.c_int, [ALLOC_FN, FREE_FN, _P]),
     "mlmc_counters": (ctypes.c_int, [_P, _I64, ctypes.c_int]),
+    "mlmc_set_timing": (ctypes.c_int, [_P, ctypes.c_int]),
+    "mlmc_kernel_stats": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _D]),
+    "mlmc_reset_kernel_stats": (ctypes.c_int, [_P]),
     "mlmc_last_error": (ctypes.c_char_p, [_P]),
     "mlmc_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "mlmc_destroy": (None, [_P]),

@@ -52,7 +52,7 @@ int mlmc_default_options(mlmc_options* opt) {
   opt->alloc = MLMC_ALLOC_EQUAL;
   opt->rho_weights = nullptr;
   opt->solve_tol = 1e-10;
-  opt->inner_tol = 1e-5;
+  opt->inner_tol = 1e-2;
   opt->max_iter = 200;
   opt->max_refine = 8;
   opt->krylov_restart = 16;
@@ -212,6 +212,24 @@ int mlmc_counters(void* c, int64_t* out, int n) {
   if (!ctx || !out || n < 0 || n > 4) return MLMC_EINVAL;
   for (int i = 0; i < n; ++i) out[i] = ctx->counters[i];
   return MLMC_OK;
+}
+
+int mlmc_set_timing(void* c, int enable) {
+  Context* ctx = as_ctx(c);
+  if (!ctx) return MLMC_EINVAL;
+  return guarded(ctx, [&] { ctx->set_timing((unsigned)enable); });
+}
+
+int mlmc_kernel_stats(void* c, int kernel, int fp64, double* out) {
+  Context* ctx = as_ctx(c);
+  if (!ctx || !out) return MLMC_EINVAL;
+  return guarded(ctx, [&] { ctx->kernel_stats(kernel, fp64, out); });
+}
+
+int mlmc_reset_kernel_stats(void* c) {
+  Context* ctx = as_ctx(c);
+  if (!ctx) return MLMC_EINVAL;
+  return guarded(ctx, [&] { ctx->reset_kernel_stats(); });
 }
 
 const char* mlmc_last_error(const void* c) {

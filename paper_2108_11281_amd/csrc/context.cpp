@@ -64,6 +64,11 @@ Context::Context(const mlmc_operator& A, const mlmc_hierarchy& h, const mlmc_opt
 
 Context::~Context() {
   (void)hipStreamSynchronize(s_);
+  for (const Pending& p : pending_) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (hipEvent_t e : ev_pool_) (void)hipEventDestroy(e);
   for (void* p : allocs_) {
     if (hooks_.free_fn) hooks_.free_fn(p, hooks_.user);
     else (void)hipFree(p);
@@ -97,12 +102,17 @@ void Context::alloc_work(Work<T>& w) {
   w.r = dalloc_n<T>(n1);
   w.z = dalloc_n<T>(n1);
   w.p = dalloc_n<T>(n1);
+  w.p2 = dalloc_n<T>(n1);
   w.q = dalloc_n<T>(n1);
   w.vb.assign(Ls_, nullptr);
   w.vx.assign(Ls_, nullptr);
-  for (int m = 1; m < Ls_; ++m) {
-    w.vb[m] = dalloc_n<T>(lv_[m].n * nb_);
-    w.vx[m] = dalloc_n<T>(lv_[m].n * nb_);
+  w.vt.assign(Ls_, nullptr);
+  for (int m = 0; m < Ls_; ++m) {
+    if (m > 0) {
+      w.vb[m] = dalloc_n<T>(lv_[m].n * nb_);
+      w.vx[m] = dalloc_n<T>(lv_[m].n * nb_);
+    }
+    if (m < Ls_ - 1) w.vt[m] = dalloc_n<T>(lv_[m].n * nb_);
   }
 }
 
@@ -227,13 +237,6 @@ void Context::op_residual(int l, const Tb* b, const Tx* x, Tr* r, int nb, const 
 }
 
 template <typename T>
-void Context::op_smooth(int l, const T* b, T* x, int nb, const int* act, bool zero_init,
-                        bool reverse) {
-  const Level& L = lv_[l - 1];
-  poisson_rbgs<T>(b, x, L.side, L.d, L.c, nb, act, zero_init, reverse, s_);
-}
-
-template <typename T>
 void Context::op_res_restrict(int l, const T* b, const T* x, T* rc, int nb, const int* act) {
   const Level& L = lv_[l - 1];
   poisson_residual_restrict<T>(b, x, rc, L.side, L.d, L.c, nb, act, s_);
@@ -252,28 +255,176 @@ void Context::op_restrict(int l, const T* x, T* xc, int nb, const int* act) {
 }
 
 // ---------------------------------------------------------------------------
-// V-cycle on levels l..L_s: x = M b (x need not be initialised)
+// V-cycle on levels l..L_s: x = M b.  Pre-smoothing starts from zero; the
+// coarse-grid correction (scaled by omega) is folded into the load of the first
+// post-smoothing sweep.  Sweeps ping-pong between the level's scratch buffer
+// and x.  rz_partials (top level of a Krylov solve only): per-block shares of
+// conj(b)^T x, fused into the last sweep.
 // ---------------------------------------------------------------------------
 template <typename T>
-void Context::vcycle(int l, const T* b, T* x, int nb, const int* act) {
+void Context::vcycle(int l, const T* b, T* x, int nb, const int* act, c64* rz_partials) {
   Work<T>& w = work<T>();
-  counters[2] += (l == 1) ? 1 : 0;
+  if (l == 1) counters[2] += 1;
+  const int64_t n = lv_[l - 1].n;
+  const double en = (double)sizeof(T) * (double)n;
   if (l == Ls_) {
-    dense_apply<T>(w.ainvT, b, x, (int)lv_[l - 1].n, nb, act, s_);
+    dense_apply<T>(w.ainvT, b, x, (int)n, nb, act, s_);
+    if (rz_partials) vec_dot_partials<T>(b, x, n, nb, act, rz_partials, s_);
     return;
   }
+  const Level& L = lv_[l - 1];
+  T* tmp = w.vt[l - 1];
   const int pre = opt_.nu_pre, post = opt_.nu_post;
-  if (pre == 0) vec_zero<T>(x, lv_[l - 1].n, nb, act, s_);
-  for (int i = 0; i < pre; ++i) op_smooth<T>(l, b, x, nb, act, i == 0, false);
+  // pre-smoothing: outputs alternate tmp, x, tmp, ...
+  const T* u = nullptr;  // current iterate (nullptr = 0)
+  for (int i = 0; i < pre; ++i) {
+    T* out = (i % 2 == 0) ? tmp : x;
+    const T* in = u;
+    timed<T>(kTimGs, en * (2.0 + (in ? 1.0 : 0.0)), act, nb, [&] {
+      poisson_rbgs_fused<T>(in, b, out, nullptr, 0.0, L.side, L.d, L.c, nb, act, false,
+                            nullptr, s_);
+    });
+    u = out;
+  }
   T* bc = w.vb[l];
-  T* xc = w.vx[l];
-  if (pre == 0)
+  T* ec = w.vx[l];
+  if (u == nullptr)
     op_restrict<T>(l, b, bc, nb, act);
   else
-    op_res_restrict<T>(l, b, x, bc, nb, act);
-  vcycle<T>(l + 1, bc, xc, nb, act);
-  op_prolong<T>(l, xc, x, nb, act, 1.0);
-  for (int i = 0; i < post; ++i) op_smooth<T>(l, b, x, nb, act, false, true);
+    timed<T>(kTimResRestrict, 2.25 * en, act, nb,
+             [&] { op_res_restrict<T>(l, b, u, bc, nb, act); });
+  vcycle<T>(l + 1, bc, ec, nb, act, nullptr);
+  if (post == 0) {
+    if (u == nullptr) {
+      agg2d_prolong<T>(ec, x, L.side, opt_.omega, 0.0, nb, act, s_);
+    } else {
+      if (u != x) vec_copy<T>(u, x, n, nb, act, s_);
+      agg2d_prolong<T>(ec, x, L.side, opt_.omega, 1.0, nb, act, s_);
+    }
+    if (rz_partials) vec_dot_partials<T>(b, x, n, nb, act, rz_partials, s_);
+    return;
+  }
+  // post-smoothing: the last sweep must land in x
+  for (int i = 0; i < post; ++i) {
+    const int left = post - 1 - i;
+    T* out = (left % 2 == 0) ? x : tmp;
+    if (out == u) out = (out == x) ? tmp : x;  // never sweep in place
+    const T* in = u;
+    const T* corr = (i == 0) ? ec : nullptr;
+    const bool last = (i == post - 1);
+    timed<T>(kTimGs, en * (2.0 + (in ? 1.0 : 0.0) + (corr ? 0.25 : 0.0)), act, nb, [&] {
+      poisson_rbgs_fused<T>(in, b, out, corr, opt_.omega, L.side, L.d, L.c, nb, act, true,
+                            last ? rz_partials : nullptr, s_);
+    });
+    u = out;
+  }
+  if (u != x) {
+    vec_copy<T>(u, x, n, nb, act, s_);
+    if (rz_partials) vec_dot_partials<T>(b, x, n, nb, act, rz_partials, s_);
+  }
+}
+
+// number of per-column partial sums that vcycle(l, ..., rz_partials) writes:
+// the fused sweep's tile count when the last post-sweep lands in x, else the
+// plain dot's block count (replays the buffer choice of vcycle symbolically)
+template <typename T>
+int Context::vcycle_partials(int l, bool* fused) const {
+  const int64_t n = lv_[l - 1].n;
+  *fused = false;
+  if (l == Ls_ || opt_.nu_post == 0) return reduce_blocks(n);
+  enum { kNull, kTmp, kX };
+  int u = kNull;
+  for (int i = 0; i < opt_.nu_pre; ++i) u = (i % 2 == 0) ? kTmp : kX;
+  for (int i = 0; i < opt_.nu_post; ++i) {
+    const int left = opt_.nu_post - 1 - i;
+    int out = (left % 2 == 0) ? kX : kTmp;
+    if (out == u) out = (out == kX) ? kTmp : kX;
+    u = out;
+  }
+  if (u != kX) return reduce_blocks(n);
+  *fused = true;
+  return poisson_gs_tiles<T>(lv_[l - 1].side);
+}
+
+// ---------------------------------------------------------------------------
+// per-kernel timing with HIP events on the context stream (measurement mode):
+// every launch of a timed kernel is bracketed by two events and preceded by a
+// one-block count of its active columns, so the algorithmic bytes of the launch
+// are known without a host synchronisation.
+// ---------------------------------------------------------------------------
+hipEvent_t Context::event() {
+  if (!ev_pool_.empty()) {
+    hipEvent_t e = ev_pool_.back();
+    ev_pool_.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  MLMC_HIP(hipEventCreate(&e));
+  return e;
+}
+
+template <typename T, typename F>
+void Context::timed(int id, double bytes_per_col, const int* act, int nb, F&& launch) {
+  (void)act;
+  if (!timing_ || !(timing_mask_ & (1u << id))) {
+    launch();
+    return;
+  }
+  if (tlog_next_ >= kTimingLog) collect_timing();
+  const int slot = 2 * id + (sizeof(typename Traits<T>::real) == 8 ? 1 : 0);
+  const int idx = tlog_next_++;
+  hipEvent_t a = event(), b = event();
+  MLMC_HIP(hipEventRecord(a, s_));
+  timing_log() = tlog_dev_ + (int64_t)idx * nb_;
+  launch();
+  timing_log() = nullptr;
+  MLMC_HIP(hipEventRecord(b, s_));
+  pending_.push_back({slot, idx, nb, bytes_per_col, a, b});
+}
+
+void Context::set_timing(unsigned mask) {
+  collect_timing();
+  timing_ = mask != 0;
+  timing_mask_ = mask;
+  const bool on = timing_;
+  if (on && !tlog_dev_) tlog_dev_ = dalloc_n<int>((int64_t)kTimingLog * nb_);
+}
+
+void Context::collect_timing() {
+  if (pending_.empty()) return;
+  MLMC_HIP(hipStreamSynchronize(s_));
+  std::vector<int> flags((size_t)tlog_next_ * nb_);
+  if (tlog_next_ > 0)
+    MLMC_HIP(hipMemcpy(flags.data(), tlog_dev_, sizeof(int) * flags.size(),
+                       hipMemcpyDeviceToHost));
+  for (const Pending& p : pending_) {
+    float ms = 0.f;
+    MLMC_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+    TimerStat& t = tstat_[p.slot];
+    int count = 0;
+    for (int k = 0; k < p.nb; ++k) count += flags[(size_t)p.idx * nb_ + k] ? 1 : 0;
+    t.launches += 1;
+    t.ms += ms;
+    t.bytes += p.bytes_per_col * count;
+    ev_pool_.push_back(p.a);
+    ev_pool_.push_back(p.b);
+  }
+  pending_.clear();
+  tlog_next_ = 0;
+}
+
+void Context::kernel_stats(int id, int fp64, double* out) {
+  collect_timing();
+  MLMC_REQUIRE(id >= 0 && id < kNumTimers, MLMC_EINVAL, "unknown kernel id");
+  const TimerStat& t = tstat_[2 * id + (fp64 ? 1 : 0)];
+  out[0] = (double)t.launches;
+  out[1] = t.ms;
+  out[2] = t.bytes;
+}
+
+void Context::reset_kernel_stats() {
+  collect_timing();
+  for (TimerStat& t : tstat_) t = TimerStat();
 }
 
 int Context::read_count() {
@@ -285,6 +436,8 @@ int Context::read_count() {
 // ---------------------------------------------------------------------------
 // Preconditioned CG (A Hermitian positive definite), columns in lockstep with
 // per-column scalars on the device.  Convergence: |r| <= tol |b| per column.
+// Per iteration: [p_new = z + beta p_old ; q = A p_new ; p^T q] fused,
+// [x += alpha p ; r -= alpha q ; |r|^2] fused, [z = M r ; r^T z] fused.
 // lastcorr (nullable): per column alpha*rz of the last step, which equals
 // b^H (alpha p) when x starts at 0 -- the last step's contribution to b^H x.
 // Returns the iteration count.
@@ -292,9 +445,10 @@ int Context::read_count() {
 template <typename T>
 int Context::pcg(int l, const T* b, T* x, int nb, int* act, double tol, c64* lastcorr) {
   Work<T>& w = work<T>();
-  const int64_t n = lv_[l - 1].n;
+  const Level& L = lv_[l - 1];
+  const int64_t n = L.n;
   const int nblk = reduce_blocks(n);
-  const int nblk_pts = (int)((n + kThreads - 1) / kThreads);
+  const int ntiles = poisson_march_tiles(L.side);
   c64 *rr0 = scal_[kRr0], *rz = scal_[kRz], *tmp = scal_[kTmp], *alpha = scal_[kAlpha],
       *beta = scal_[kBeta];
   vec_zero<T>(x, n, nb, act, s_);
@@ -303,34 +457,125 @@ int Context::pcg(int l, const T* b, T* x, int nb, int* act, double tol, c64* las
     if (lastcorr) vec_zero<c64>(lastcorr, 1, nb, nullptr, s_);
     return 0;
   }
+  const double en = (double)sizeof(T) * (double)n;
   vec_copy<T>(b, w.r, n, nb, act, s_);
   vec_dot_partials<T>(b, b, n, nb, act, partials_, s_);
   finish_sums(partials_, nblk, nb, rr0, s_);
-  vcycle<T>(l, w.r, w.z, nb, act);
-  vec_dot_partials<T>(w.r, w.z, n, nb, act, partials_, s_);
-  finish_sums(partials_, nblk, nb, rz, s_);
-  vec_copy<T>(w.z, w.p, n, nb, act, s_);
+  bool fused = false;
+  const int nvp = vcycle_partials<T>(l, &fused);
+  vcycle<T>(l, w.r, w.z, nb, act, partials_);
+  finish_sums(partials_, nvp, nb, rz, s_);
+  vec_zero<c64>(beta, 1, nb, nullptr, s_);
+  T* p_old = w.z;  // first direction: p = z + 0 * z
+  T* p_new = w.p;
   const int check = 2;
   int it = 0;
   for (it = 1; it <= opt_.max_iter; ++it) {
-    op_apply<T>(l, w.p, w.q, nb, act, partials_);
-    finish_sums(partials_, nblk_pts, nb, tmp, s_);
+    timed<T>(kTimApply, 4.0 * en, act, nb, [&] {
+      poisson_update_apply<T>(p_old, w.z, beta, p_new, w.q, L.side, L.d, L.c, nb, act,
+                              partials_, s_);
+    });
+    finish_sums(partials_, ntiles, nb, tmp, s_);
     cg_alpha(rz, tmp, act, alpha, nb, s_);
     if (lastcorr) cg_lastcorr(alpha, rz, act, lastcorr, nb, s_);
-    cg_update_xr<T>(x, w.r, w.p, w.q, alpha, n, nb, act, partials_, s_);
+    timed<T>(kTimCgXr, 6.0 * en, act, nb,
+             [&] { cg_update_xr<T>(x, w.r, p_new, w.q, alpha, n, nb, act, partials_, s_); });
     finish_sums(partials_, nblk, nb, tmp, s_);
     mark_converged(tmp, rr0, tol * tol, act, nb, count_dev_, s_);
     counters[0] += 1;
     if (it % check == 0 || it == opt_.max_iter) {
       if (read_count() == 0) break;
     }
-    vcycle<T>(l, w.r, w.z, nb, act);
-    vec_dot_partials<T>(w.r, w.z, n, nb, act, partials_, s_);
-    finish_sums(partials_, nblk, nb, tmp, s_);
+    vcycle<T>(l, w.r, w.z, nb, act, partials_);
+    finish_sums(partials_, nvp, nb, tmp, s_);
     cg_beta(tmp, rz, act, beta, nb, s_);
-    cg_update_p<T>(w.p, w.z, beta, n, nb, act, s_);
+    // the new direction of this iteration is the old one of the next
+    p_old = p_new;
+    p_new = (p_new == w.p) ? w.p2 : w.p;
   }
   return it;
+}
+
+// ---------------------------------------------------------------------------
+// FP32 preconditioned CG with FP64 iterative refinement by reliable updates:
+// the CG recursion (x32, r32, p, q, z) runs in FP32; whenever a column's
+// recursive residual has dropped by the factor inner_tol since the last
+// refinement (or reaches solve_tol), every active column is refined in FP64:
+// y64 += x32, x32 = 0, r = b - A y64 recomputed in FP64 (and rounded to FP32).
+// The search direction is kept, so the Krylov space is not discarded as in a
+// restarted refinement.  Only the FP64 residual marks a column converged.
+// Stated error of a column (err): the last correction's share |b^H x32| of
+// b^H y scaled by the residual reduction it achieved -- the linear-convergence
+// estimate of what a further correction would add.  On return scal_[kRres]
+// holds the final |b - A y|^2 per column.
+// ---------------------------------------------------------------------------
+void Context::pcg_refined(int l, const double* b, double* y, int nb, double tol, c64* err) {
+  Work<float>& w = w32_;
+  const Level& L = lv_[l - 1];
+  const int64_t n = L.n;
+  const int nblk = reduce_blocks(n);
+  const int ntiles = poisson_march_tiles(L.side);
+  int* act = act_outer_;
+  c64 *bb = scal_[kBb], *bd = scal_[kBd], *rr_upd = scal_[kRres], *rr_new = scal_[kRres2];
+  c64 *rz = scal_[kRz], *tmp = scal_[kTmp], *alpha = scal_[kAlpha], *beta = scal_[kBeta];
+  float* x32 = d32_;
+  float* r = w.r;
+  const double en = 4.0 * (double)n;
+  vec_copy<c64>(bb, rr_upd, 1, nb, nullptr, s_);
+  vec_zero<double>(y, n, nb, nullptr, s_);
+  vec_zero<float>(x32, n, nb, nullptr, s_);
+  vec_convert<float, double>(b, r, n, nb, nullptr, s_);
+  bool fused = false;
+  const int nvp = vcycle_partials<float>(l, &fused);
+  vcycle<float>(l, r, w.z, nb, act, partials_);
+  finish_sums(partials_, nvp, nb, rz, s_);
+  vec_zero<c64>(beta, 1, nb, nullptr, s_);
+  float* p_old = w.z;
+  float* p_new = w.p;
+  const double delta2 = opt_.inner_tol * opt_.inner_tol;
+  const int check = 2;
+  const int max_it = opt_.max_iter * opt_.max_refine;
+  for (int it = 1; it <= max_it; ++it) {
+    timed<float>(kTimApply, 4.0 * en, act, nb, [&] {
+      poisson_update_apply<float>(p_old, w.z, beta, p_new, w.q, L.side, L.d, L.c, nb, act,
+                                  partials_, s_);
+    });
+    finish_sums(partials_, ntiles, nb, tmp, s_);
+    cg_alpha(rz, tmp, act, alpha, nb, s_);
+    timed<float>(kTimCgXr, 6.0 * en, act, nb,
+                 [&] { cg_update_xr<float>(x32, r, p_new, w.q, alpha, n, nb, act, partials_, s_); });
+    finish_sums(partials_, nblk, nb, tmp, s_);
+    counters[0] += 1;
+    if (it % check == 0 || it == max_it) {
+      // a refinement is due when some column's recursive residual has dropped
+      // by inner_tol since its last refinement, or reached the tolerance
+      refine_due(tmp, rr_upd, bb, delta2, tol * tol, act, nb, count_dev_ + 1, s_);
+      MLMC_HIP(hipMemcpyAsync(count_host_ + 1, count_dev_ + 1, sizeof(int),
+                              hipMemcpyDeviceToHost, s_));
+      MLMC_HIP(hipStreamSynchronize(s_));
+      if (count_host_[1] > 0 || it == max_it) {
+        ir_accumulate<double, float>(y, x32, n, nb, act, s_);
+        vec_convert<double, float>(x32, r64_, n, nb, act, s_);
+        vec_dot_partials<double>(b, r64_, n, nb, act, partials_, s_);
+        finish_sums(partials_, nblk, nb, bd, s_);
+        vec_zero<float>(x32, n, nb, act, s_);
+        timed<double>(kTimIrResidual, 20.0 * (double)n, act, nb, [&] {
+          op_residual<double, double, float>(l, b, y, r, nb, act, partials_);
+        });
+        finish_sums(partials_, ntiles, nb, rr_new, s_);
+        ir_stated_error(bd, rr_upd, rr_new, act, err, nb, s_);
+        select_active(rr_upd, rr_new, act, nb, s_);
+        mark_converged(rr_new, bb, tol * tol, act, nb, count_dev_, s_);
+        counters[1] += 1;
+        if (read_count() == 0) break;
+      }
+    }
+    vcycle<float>(l, r, w.z, nb, act, partials_);
+    finish_sums(partials_, nvp, nb, tmp, s_);
+    cg_beta(tmp, rz, act, beta, nb, s_);
+    p_old = p_new;
+    p_new = (p_new == w.p) ? w.p2 : w.p;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -341,11 +586,11 @@ int Context::pcg(int l, const T* b, T* x, int nb, int* act, double tol, c64* las
 void Context::solve(int l, const double* b, double* y, int nb, c64* err, double* relres_host,
                     bool* converged) {
   const int64_t n = lv_[l - 1].n;
-  const int nblk_pts = (int)((n + kThreads - 1) / kThreads);
+  const int nblk_pts = poisson_march_tiles(lv_[l - 1].side);
   const int nblk = reduce_blocks(n);
   c64* bb = scal_[kBb];
   c64* bd = scal_[kBd];
-  c64* rres = scal_[kRres];
+  c64* rres = scal_[kRres];  // also the refinement loop's residual norms
   vec_dot_partials<double>(b, b, n, nb, nullptr, partials_, s_);
   finish_sums(partials_, nblk, nb, bb, s_);
   set_all_active(act_outer_, nb, s_);
@@ -359,30 +604,14 @@ void Context::solve(int l, const double* b, double* y, int nb, c64* err, double*
     pcg<double>(l, b, y, nb, act_inner_, tol, err);
     counters[1] += 1;
   } else {
-    // FP64 iterative refinement around the FP32 solver
-    vec_zero<double>(y, n, nb, nullptr, s_);
-    vec_convert<float, double>(b, r32_, n, nb, nullptr, s_);
-    for (int ir = 0; ir < opt_.max_refine; ++ir) {
-      MLMC_HIP(hipMemcpyAsync(act_inner_, act_outer_, sizeof(int) * nb,
-                              hipMemcpyDeviceToDevice, s_));
-      pcg<float>(l, r32_, d32_, nb, act_inner_, opt_.inner_tol, nullptr);
-      ir_accumulate<double, float>(y, d32_, n, nb, act_outer_, s_);
-      // stated error: b^H d of this correction, kept for the columns refined now
-      vec_convert<double, float>(d32_, r64_, n, nb, act_outer_, s_);
-      vec_dot_partials<double>(b, r64_, n, nb, act_outer_, partials_, s_);
-      finish_sums(partials_, nblk, nb, bd, s_);
-      select_active(err, bd, act_outer_, nb, s_);
-      op_residual<double, double, float>(l, b, y, r32_, nb, act_outer_, partials_);
-      finish_sums(partials_, nblk_pts, nb, rres, s_);
-      mark_converged(rres, bb, tol * tol, act_outer_, nb, count_dev_, s_);
-      counters[1] += 1;
-      const int remaining = read_count();
-      if (remaining == 0) break;
-    }
+    pcg_refined(l, b, y, nb, tol, err);
   }
-  // final FP64 relative residuals
-  op_residual<double, double, double>(l, b, y, r64_, nb, nullptr, partials_);
-  finish_sums(partials_, nblk_pts, nb, rres, s_);
+  // final FP64 relative residuals (the refined solver ends on a true FP64
+  // residual already, kept in rres)
+  if (l == Ls_ || opt_.precision == MLMC_FP64) {
+    op_residual<double, double, double>(l, b, y, r64_, nb, nullptr, partials_);
+    finish_sums(partials_, nblk_pts, nb, rres, s_);
+  }
   MLMC_HIP(hipMemcpyAsync(host_c64_, rres, sizeof(c64) * nb, hipMemcpyDeviceToHost, s_));
   MLMC_HIP(hipMemcpyAsync(host_c64_ + nb, bb, sizeof(c64) * nb, hipMemcpyDeviceToHost, s_));
   MLMC_HIP(hipStreamSynchronize(s_));
@@ -478,12 +707,19 @@ void Context::sample_level(int level, uint64_t seed, int64_t first, int64_t coun
 
 void Context::trace(double tol, uint64_t seed, mlmc_result* out) {
   std::memset(counters, 0, sizeof(counters));
+  double level_s[MLMC_MAX_LEVELS] = {0};
+  auto now = [] {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+  };
   SamplerIface smp;
   smp.sample = [&](int level, int64_t first, int64_t count, c64* o) {
+    const double t0 = now();
     for (int64_t j = 0; j < count; j += nb_) {
       const int nbt = (int)std::min<int64_t>(nb_, count - j);
       samples_batch(level, seed, (uint64_t)(first + j), nbt, o + j, nullptr);
     }
+    level_s[level - 1] += now() - t0;
   };
   smp.pilot = [&](int64_t count, c64* o) {
     for (int64_t j = 0; j < count; j += nb_) {
@@ -495,7 +731,10 @@ void Context::trace(double tol, uint64_t seed, mlmc_result* out) {
   for (int l = 0; l < L_ - 1; ++l) cost[l] = (double)(lv_[l].n + lv_[l + 1].n);
   run_estimator(L_, smp, coarse_trace_, cost, opt_, tol, out);
   int64_t solves = 0;
-  for (int l = 0; l < L_ - 1; ++l) solves += 2 * out->n_samples[l];
+  for (int l = 0; l < L_ - 1; ++l) {
+    solves += 2 * out->n_samples[l];
+    out->level_seconds[l] = level_s[l];
+  }
   out->solves = solves + (opt_.tau > 0 ? 0 : 5);
   out->iterations = counters[0];
 }
@@ -586,7 +825,7 @@ void Context::export_prolongation(int level, double* out) {
   throw Error(MLMC_EUNSUPPORTED, "prolongation export is for test-vector aggregation only");
 }
 
-template void Context::vcycle<float>(int, const float*, float*, int, const int*);
-template void Context::vcycle<double>(int, const double*, double*, int, const int*);
+template void Context::vcycle<float>(int, const float*, float*, int, const int*, c64*);
+template void Context::vcycle<double>(int, const double*, double*, int, const int*, c64*);
 
 }  // namespace mlmc

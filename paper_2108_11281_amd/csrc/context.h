@@ -29,8 +29,9 @@ struct Level {
 // Per-precision work buffers (T = float or double for real operators).
 template <typename T>
 struct Work {
-  T *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
-  std::vector<T*> vb, vx;   // V-cycle right-hand side / solution per level (0-based)
+  T *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *p2 = nullptr, *q = nullptr;
+  // V-cycle right-hand side / solution / sweep scratch per level (0-based)
+  std::vector<T*> vb, vx, vt;
   T* ainvT = nullptr;       // transposed inverse of the solver's coarsest operator
 };
 
@@ -66,6 +67,13 @@ class Context {
   std::string last_error;
   const mlmc_options& options() const { return opt_; }
 
+  // kernel timing (measurement mode)
+  enum { kTimGs, kTimResRestrict, kTimProlong, kTimApply, kTimCgXr, kTimCgP, kTimDot,
+         kTimIrResidual, kNumTimers };
+  void set_timing(unsigned mask);
+  void kernel_stats(int id, int fp64, double* out);
+  void reset_kernel_stats();
+
   // level-difference samples and pilot/Hutchinson samples in batches <= nb
   void samples_batch(int level, uint64_t seed, uint64_t first, int nbatch, c64* out,
                      double* err);
@@ -83,8 +91,6 @@ class Context {
   // operator pieces on level l (1-based) in precision T
   template <typename T> void op_apply(int l, const T* x, T* y, int nb, const int* act,
                                       c64* partials);
-  template <typename T> void op_smooth(int l, const T* b, T* x, int nb, const int* act,
-                                       bool zero_init, bool reverse);
   template <typename T> void op_res_restrict(int l, const T* b, const T* x, T* rc, int nb,
                                              const int* act);
   template <typename T> void op_prolong(int l, const T* ec, T* x, int nb, const int* act,
@@ -95,16 +101,40 @@ class Context {
                    c64* partials);
 
   template <typename T> Work<T>& work();
-  template <typename T> void vcycle(int l, const T* b, T* x, int nb, const int* act);
+  template <typename T> void vcycle(int l, const T* b, T* x, int nb, const int* act,
+                                    c64* rz_partials);
+  template <typename T> int vcycle_partials(int l, bool* fused) const;
   // CG on level l in precision T: x = A^-1 b to relative residual tol;
   // act: per-column flags (in: columns to solve; out: still unconverged)
   template <typename T> int pcg(int l, const T* b, T* x, int nb, int* act, double tol,
                                 c64* lastcorr);
+  void pcg_refined(int l, const double* b, double* y, int nb, double tol, c64* err);
   // FP64 solve of level l for nb columns; b, y FP64; err: per-column stated error
   // contributions (device c64 nb), relres host (nullable)
   void solve(int l, const double* b, double* y, int nb, c64* err, double* relres_host,
              bool* converged);
   int read_count();
+  hipEvent_t event();
+  void collect_timing();
+  template <typename T, typename F>
+  void timed(int id, double bytes_per_col, const int* act, int nb, F&& launch);
+  struct TimerStat {
+    int64_t launches = 0;
+    double ms = 0, bytes = 0;
+  };
+  struct Pending {
+    int slot, idx, nb;
+    double bytes_per_col;
+    hipEvent_t a, b;
+  };
+  static constexpr int kTimingLog = 1 << 16;
+  bool timing_ = false;
+  unsigned timing_mask_ = 0;
+  int* tlog_dev_ = nullptr;
+  int tlog_next_ = 0;
+  std::vector<Pending> pending_;
+  std::vector<hipEvent_t> ev_pool_;
+  TimerStat tstat_[2 * kNumTimers];
 
   int kind_;
   mlmc_operator op_;
@@ -129,7 +159,7 @@ class Context {
   c64* partials_ = nullptr;
   int64_t partials_cap_ = 0;
   // per-column scalar arrays (nb_ entries each); kErr1..kQb are consecutive
-  enum { kRr0, kRz, kTmp, kAlpha, kBeta, kBb, kBd, kRres, kErr1, kErr2, kQa, kQb,
+  enum { kRr0, kRz, kTmp, kAlpha, kBeta, kBb, kBd, kRres, kRres2, kErr1, kErr2, kQa, kQb,
          kNumScalars };
   c64* scal_[kNumScalars] = {};
   int *act_outer_ = nullptr, *act_inner_ = nullptr, *count_dev_ = nullptr;

@@ -10,6 +10,10 @@ namespace mlmc {
 constexpr int kThreads = 256;
 constexpr int kMaxPartials = 1024;  // per-column partial sums of a reduction
 
+// Measurement mode: when non-null, the next timed launch records, for each
+// column k, its active flag at tlog[k] (written by the kernel itself).
+int*& timing_log();
+
 // ----- vectors ---------------------------------------------------------------
 template <typename T>
 void vec_zero(T* x, int64_t n, int nb, const int* active, hipStream_t s);
@@ -39,6 +43,13 @@ void mark_converged(const c64* rr, const c64* ref, double tol2, int* active, int
                     int* count, hipStream_t s);
 void count_active(const int* active, int nb, int* count, hipStream_t s);
 void set_all_active(int* active, int nb, hipStream_t s);
+void set_count(int* count, int value, hipStream_t s);
+// count = number of active columns with rr <= delta2 * rr_upd or rr <= tol2 * bb
+void refine_due(const c64* rr, const c64* rr_upd, const c64* bb, double delta2, double tol2,
+                const int* active, int nb, int* count, hipStream_t s);
+// err[k] = |bd[k]| * sqrt(rr_new[k]/rr_old[k]) for active columns
+void ir_stated_error(const c64* bd, const c64* rr_old, const c64* rr_new, const int* active,
+                     c64* err, int nb, hipStream_t s);
 // dst[k] = active[k] ? src[k] : dst[k]
 void select_active(c64* dst, const c64* src, const int* active, int nb, hipStream_t s);
 // lastcorr[k] = alpha[k]*rz[k] for active columns (CG step's share of b^H x)
@@ -95,21 +106,32 @@ template <typename T>
 void dense_transpose(const T* in, T* out, int n, hipStream_t s);
 
 // ----- 2D Poisson stencil: A = d I - c (grid neighbours), N x N Dirichlet -----
+// partial-sum counts per column of the tiled kernels
+int poisson_march_tiles(int N);   // apply / residual
+template <typename T>
+int poisson_gs_tiles(int N);      // fused Gauss-Seidel sweep
 template <typename T>
 void poisson_dense_build(T* aug, int N, double d, double c, hipStream_t s);
 // y = A x ; optional partials of conj(x)^T y (pass partials = nullptr to skip)
 template <typename T>
 void poisson_apply(const T* x, T* y, int N, double d, double c, int nb,
                    const int* active, c64* partials, hipStream_t s);
+// p_new = z + beta p_old ; q = A p_new ; partials of conj(p_new)^T q
+template <typename T>
+void poisson_update_apply(const T* p_old, const T* z, const c64* beta, T* p_new, T* q, int N,
+                          double d, double c, int nb, const int* active, c64* partials,
+                          hipStream_t s);
 // r = b - A x (Tr may be lower precision) ; optional partials of |r|^2
 template <typename Tb, typename Tx, typename Tr>
 void poisson_residual(const Tb* b, const Tx* x, Tr* r, int N, double d, double c,
                       int nb, const int* active, c64* partials, hipStream_t s);
-// one red-black Gauss-Seidel sweep (red then black; reverse: black then red);
-// zero_init: x is taken as 0 on entry
+// one fused red-black Gauss-Seidel sweep: xout = S(xin + omega/2 P ec ; b),
+// red first (reverse: black first); xin == nullptr means 0, ec == nullptr no
+// correction; partials (nullable): shares of conj(b)^T xout, gs_tiles per column
 template <typename T>
-void poisson_rbgs(const T* b, T* x, int N, double d, double c, int nb,
-                  const int* active, bool zero_init, bool reverse, hipStream_t s);
+void poisson_rbgs_fused(const T* xin, const T* b, T* xout, const T* ec, double omega, int N,
+                        double d, double c, int nb, const int* active, bool reverse,
+                        c64* partials, hipStream_t s);
 // rc = R (b - A x), R = P^T, P the orthonormal 2x2 aggregation (entries 1/2)
 template <typename T>
 void poisson_residual_restrict(const T* b, const T* x, T* rc, int N, double d,

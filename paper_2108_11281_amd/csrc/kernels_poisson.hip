@@ -1,7 +1,13 @@
 // 2D Poisson stencil kernels, matrix-free: A = d I - c (grid neighbours) on an
-// N x N Dirichlet grid, unknown i = y*N + x.  With 2x2 orthonormal aggregation
-// the Galerkin operator of such a stencil is again one (d' = d - 2c, c' = c/2),
-// so every level of the hierarchy runs on these kernels.
+// N x N Dirichlet grid, unknown i = y*N + x, one grid plane per right-hand side.
+// With 2x2 orthonormal aggregation the Galerkin operator of such a stencil is
+// again one (d' = d - 2c, c' = c/2), so every level runs on these kernels.
+//
+// Launch shape: 1D grids of 256-thread blocks over (plane, tile) pairs with an
+// XCD-aware order: the hardware deals consecutive block ids round-robin to the
+// 8 XCDs, so block b is mapped to the logical tile range owned by XCD b % 8 and
+// each XCD sweeps a contiguous run of tiles (neighbouring tiles share halo
+// cache lines in that XCD's L2).
 #include "kernels.h"
 
 namespace mlmc {
@@ -9,171 +15,557 @@ namespace {
 
 template <typename T> using R_t = typename Traits<T>::real;
 
-// neighbour sum with Dirichlet truncation
-template <typename T>
-__device__ __forceinline__ T nbr_sum(const T* u, int x, int y, int N, int64_t i) {
-  T s = zero_of(T());
-  if (x > 0) s += u[i - 1];
-  if (x < N - 1) s += u[i + 1];
-  if (y > 0) s += u[i - N];
-  if (y < N - 1) s += u[i + N];
-  return s;
+constexpr int kXcds = 8;
+
+// logical tile index of this block: a bijection that gives XCD x the
+// contiguous range [x*q + min(x, r), ...) of the `total` tiles
+__device__ __forceinline__ int xcd_tile_index(int total) {
+  const int b = blockIdx.x;
+  const int x = b % kXcds, local = b / kXcds;
+  const int q = total / kXcds, r = total % kXcds;
+  return x * q + (x < r ? x : r) + local;
 }
 
+// ---------------------------------------------------------------------------
+// Fused red-black Gauss-Seidel sweep on a TX x TY tile staged in LDS.
+//   x_out = S(x_in + omega/2 * P e_c ; b)   (one full sweep, first colour
+//   `first`, then the other), Dirichlet zeros outside the grid.
+// The tile is loaded with a 2-cell halo of x and a 1-cell halo of b; the first
+// colour is updated on the tile plus a 1-cell ring (redundantly with the
+// neighbouring tiles), so the second colour sees all its updated neighbours.
+// x_in == nullptr means x_in = 0; ec == nullptr means no coarse correction.
+// With partials, each block also writes its share of conj(b)^T x_out (the
+// r^T z of the Krylov method when b = r and x_out = z).
+// ---------------------------------------------------------------------------
+constexpr int GTX = 128, GTY = 16;
+
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_apply(const T* x, T* y, int N, R_t<T> d,
-                                                    R_t<T> c, const int* active,
-                                                    c64* partials) {
-  __shared__ double lds[16];
-  const int k = blockIdx.y;
-  if (active && !active[k]) return;
+__global__ __launch_bounds__(kThreads) void k_rbgs_tile(const T* __restrict__ xin,
+                                                        const T* __restrict__ b,
+                                                        T* __restrict__ xout,
+                                                        const T* __restrict__ ec,
+                                                        R_t<T> wh, int N, R_t<T> dinv,
+                                                        R_t<T> c, int first, int nbx, int nby,
+                                                        int nb, const int* active,
+                                                        c64* partials, int* tlog) {
+  __shared__ T sx[GTY + 4][GTX + 4];
+  __shared__ T sb[GTY + 2][GTX + 2];
+  __shared__ double red[16];
+  const int t = xcd_tile_index(nbx * nby * nb);
+  const int k = t / (nbx * nby);
+  const int rem = t - k * nbx * nby;
+  const int by = rem / nbx, bx = rem - by * nbx;
+  if (tlog && rem == 0 && threadIdx.x == 0) tlog[k] = active ? active[k] : 1;
+  if (k >= nb || (active && !active[k])) return;
+  const int x0 = bx * GTX, y0 = by * GTY;
   const int64_t n = (int64_t)N * N;
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  const T* xc = x + (int64_t)k * n;
-  double re = 0.0, im = 0.0;
-  if (i < n) {
-    const int yy = (int)(i / N), xx = (int)(i - (int64_t)yy * N);
-    T xi = xc[i];
-    T v = d * xi - c * nbr_sum(xc, xx, yy, N, i);
-    y[(int64_t)k * n + i] = v;
-    cdot_acc(re, im, xi, v);
-  }
-  if (partials) {
-    block_sum2<kThreads>(re, im, lds);
-    if (threadIdx.x == 0) partials[(int64_t)k * gridDim.x + blockIdx.x] = {re, im};
-  }
-}
-
-template <typename Tb, typename Tx, typename Tr>
-__global__ __launch_bounds__(kThreads) void k_residual(const Tb* b, const Tx* x, Tr* r, int N,
-                                                       R_t<Tx> d, R_t<Tx> c,
-                                                       const int* active, c64* partials) {
-  __shared__ double lds[16];
-  const int k = blockIdx.y;
-  if (active && !active[k]) return;
-  const int64_t n = (int64_t)N * N;
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  const Tx* xc = x + (int64_t)k * n;
-  double re = 0.0, im = 0.0;
-  if (i < n) {
-    const int yy = (int)(i / N), xx = (int)(i - (int64_t)yy * N);
-    Tx v = convert<Tx, Tb>(b[(int64_t)k * n + i]) - (d * xc[i] - c * nbr_sum(xc, xx, yy, N, i));
-    r[(int64_t)k * n + i] = convert<Tr, Tx>(v);
-    cdot_acc(re, im, v, v);
-  }
-  if (partials) {
-    block_sum2<kThreads>(re, im, lds);
-    if (threadIdx.x == 0) partials[(int64_t)k * gridDim.x + blockIdx.x] = {re, im};
-  }
-}
-
-// one colour of a red-black Gauss-Seidel sweep, in place
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_gs_colour(const T* b, T* x, int N, R_t<T> dinv,
-                                                        R_t<T> c, int colour, int zero_nbrs,
-                                                        const int* active) {
-  const int k = blockIdx.y;
-  if (active && !active[k]) return;
-  const int64_t n = (int64_t)N * N;
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (i >= n) return;
-  const int yy = (int)(i / N), xx = (int)(i - (int64_t)yy * N);
-  if (((xx + yy) & 1) != colour) return;
-  T* xc = x + (int64_t)k * n;
-  const T bi = b[(int64_t)k * n + i];
-  if (zero_nbrs)
-    xc[i] = dinv * bi;
-  else
-    xc[i] = dinv * (bi + c * nbr_sum(xc, xx, yy, N, i));
-}
-
-// one thread per coarse point: rc = 1/2 sum over the 2x2 block of (b - A x)
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_res_restrict(const T* b, const T* x, T* rc,
-                                                           int N, R_t<T> d, R_t<T> c,
-                                                           const int* active) {
-  const int k = blockIdx.y;
-  if (active && !active[k]) return;
-  const int Nc = N / 2;
-  const int64_t nc = (int64_t)Nc * Nc, n = (int64_t)N * N;
-  const int64_t I = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (I >= nc) return;
-  const int Y = (int)(I / Nc), X = (int)(I - (int64_t)Y * Nc);
-  const T* xc = x + (int64_t)k * n;
+  const int Nc = N >> 1;
+  const T* xc = xin ? xin + (int64_t)k * n : nullptr;
   const T* bc = b + (int64_t)k * n;
-  T acc = zero_of(T());
+  const T* ecc = ec ? ec + (int64_t)k * Nc * Nc : nullptr;
+  const int tid = threadIdx.x;
+
+  // all global loads are issued before the first LDS store, so that each
+  // thread keeps ~20 loads in flight
+  constexpr int NX = (GTY + 4) * (GTX + 4), NB = (GTY + 2) * (GTX + 2);
+  constexpr int LX = (NX + kThreads - 1) / kThreads, LB = (NB + kThreads - 1) / kThreads;
+  T vx[LX], vb[LB];
 #pragma unroll
-  for (int dy = 0; dy < 2; ++dy)
-#pragma unroll
-    for (int dx = 0; dx < 2; ++dx) {
-      const int xx = 2 * X + dx, yy = 2 * Y + dy;
-      const int64_t i = (int64_t)yy * N + xx;
-      acc += bc[i] - (d * xc[i] - c * nbr_sum(xc, xx, yy, N, i));
+  for (int j = 0; j < LX; ++j) {
+    const int idx = tid + j * kThreads;
+    const int r = idx / (GTX + 4), cc = idx - r * (GTX + 4);
+    const int gx = x0 - 2 + cc, gy = y0 - 2 + r;
+    T v = zero_of(T());
+    if (idx < NX && gx >= 0 && gx < N && gy >= 0 && gy < N) {
+      if (xc) v = xc[gy * N + gx];
+      if (ecc) v += wh * ecc[(gy >> 1) * Nc + (gx >> 1)];
     }
-  rc[(int64_t)k * nc + I] = (R_t<T>)0.5 * acc;
+    vx[j] = v;
+  }
+#pragma unroll
+  for (int j = 0; j < LB; ++j) {
+    const int idx = tid + j * kThreads;
+    const int r = idx / (GTX + 2), cc = idx - r * (GTX + 2);
+    const int gx = x0 - 1 + cc, gy = y0 - 1 + r;
+    vb[j] = (idx < NB && gx >= 0 && gx < N && gy >= 0 && gy < N) ? bc[gy * N + gx]
+                                                                  : zero_of(T());
+  }
+#pragma unroll
+  for (int j = 0; j < LX; ++j) {
+    const int idx = tid + j * kThreads;
+    if (idx < NX) (&sx[0][0])[idx] = vx[j];
+  }
+#pragma unroll
+  for (int j = 0; j < LB; ++j) {
+    const int idx = tid + j * kThreads;
+    if (idx < NB) (&sb[0][0])[idx] = vb[j];
+  }
+  __syncthreads();
+  // first colour on the tile and its 1-cell ring
+  for (int idx = tid; idx < (GTY + 2) * (GTX + 2); idx += kThreads) {
+    const int r = idx / (GTX + 2), cc = idx - r * (GTX + 2);
+    const int gx = x0 - 1 + cc, gy = y0 - 1 + r;
+    if (gx >= 0 && gx < N && gy >= 0 && gy < N && ((gx + gy) & 1) == first) {
+      sx[r + 1][cc + 1] =
+          dinv * (sb[r][cc] + c * (sx[r + 1][cc] + sx[r + 1][cc + 2] + sx[r][cc + 1] +
+                                   sx[r + 2][cc + 1]));
+    }
+  }
+  __syncthreads();
+  // second colour on the tile; write the tile
+  double dre = 0.0, dim = 0.0;
+  T* xo = xout + (int64_t)k * n;
+  for (int idx = tid; idx < GTY * GTX; idx += kThreads) {
+    const int r = idx / GTX, cc = idx - r * GTX;
+    const int gx = x0 + cc, gy = y0 + r;
+    if (gx < N && gy < N) {
+      T v;
+      if (((gx + gy) & 1) != first)
+        v = dinv * (sb[r + 1][cc + 1] + c * (sx[r + 2][cc + 1] + sx[r + 2][cc + 3] +
+                                             sx[r + 1][cc + 2] + sx[r + 3][cc + 2]));
+      else
+        v = sx[r + 2][cc + 2];
+      xo[gy * N + gx] = v;
+      if (partials) cdot_acc(dre, dim, sb[r + 1][cc + 1], v);
+    }
+  }
+  if (partials) {
+    block_sum2<kThreads>(dre, dim, red);
+    if (tid == 0) partials[(int64_t)k * (nbx * nby) + rem] = {dre, dim};
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fused red-black Gauss-Seidel sweep, column-marching form (no LDS):
+//   x_out = S(x_in + omega/2 * P e_c ; b)
+// A wave owns 62 consecutive columns (lanes 1..62; lanes 0 and 63 are halo
+// lanes that redo the first colour of the neighbouring columns) and walks a
+// segment of SR rows top to bottom.  At row yy it loads x_in(yy) and b(yy),
+// updates the first colour on row yy-1 (its vertical neighbours yy-2 and yy
+// are in registers, horizontal ones come from the neighbouring lanes) and then
+// the second colour on row yy-2 from the updated first colour of rows
+// yy-3..yy-1.  Every input value is read once and every output written once:
+// 12 bytes per unknown for FP32 (plus 1/4 element for the folded coarse
+// correction and 4 extra rows per segment of SR).
+// ---------------------------------------------------------------------------
+constexpr int SCOLS = 62;       // owned columns per wave
+
+// rows per segment: all loads of a segment are issued before its arithmetic,
+// so the row count is bounded by registers (3 values per row and lane)
+template <typename T> struct GsRows;
+template <> struct GsRows<float> { static constexpr int value = 16; };
+template <> struct GsRows<double> { static constexpr int value = 8; };
+
+// branch-free guarded load: the address is always valid (clamped to the base)
+template <typename T>
+__device__ __forceinline__ T ldz(const T* p, int idx, bool ok) {
+  const T v = p[ok ? idx : 0];
+  return ok ? v : zero_of(T());
+}
+
+// whole-wave lane shifts by one (DPP wave_shr:1 / wave_shl:1): lane i receives
+// lane i-1 (shr) or lane i+1 (shl); the lane without a source keeps its value
+__device__ __forceinline__ float wave_shr1(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x138,
+                                                    0xf, 0xf, false));
+}
+__device__ __forceinline__ float wave_shl1(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x130,
+                                                    0xf, 0xf, false));
+}
+__device__ __forceinline__ double wave_shr1(double v) {
+  const long long u = __double_as_longlong(v);
+  const int lo = (int)(u & 0xffffffffll), hi = (int)(u >> 32);
+  const int l2 = __builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xf, 0xf, false);
+  const int h2 = __builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)h2 << 32) | (unsigned int)l2);
+}
+__device__ __forceinline__ double wave_shl1(double v) {
+  const long long u = __double_as_longlong(v);
+  const int lo = (int)(u & 0xffffffffll), hi = (int)(u >> 32);
+  const int l2 = __builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xf, 0xf, false);
+  const int h2 = __builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)h2 << 32) | (unsigned int)l2);
+}
+
+template <typename T, bool HX, bool HE>
+__global__ __launch_bounds__(kThreads) void k_rbgs_march(const T* __restrict__ xin,
+                                                         const T* __restrict__ b,
+                                                         T* __restrict__ xout,
+                                                         const T* __restrict__ ec, R_t<T> wh,
+                                                         int N, R_t<T> dinv, R_t<T> c,
+                                                         int first, int nb, const int* active,
+                                                         c64* partials, int* tlog) {
+  constexpr int SR = GsRows<T>::value;
+  constexpr int NR = SR + 4;
+  __shared__ double red[16];
+  const int nwx = (N + SCOLS - 1) / SCOLS, nseg = (N + SR - 1) / SR;
+  const int units_per_plane = nwx * nseg;
+  const int blocks_per_plane = (units_per_plane + 3) / 4;
+  const int t = xcd_tile_index(blocks_per_plane * nb);
+  const int k = t / blocks_per_plane;
+  const int bp = t - k * blocks_per_plane;
+  if (tlog && bp == 0 && threadIdx.x == 0) tlog[k] = active ? active[k] : 1;
+  if (k >= nb || (active && !active[k])) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int unit = bp * 4 + w;                // unit = seg * nwx + wx within the plane
+  const bool unit_ok = unit < units_per_plane;
+  const int seg = unit / nwx, wx = unit - seg * nwx;
+  const int x = wx * SCOLS - 1 + lane;
+  const int ys = seg * SR;
+  const int yend = ys + SR < N ? ys + SR : N;
+  const bool col_in = unit_ok && x >= 0 && x < N;
+  const bool owned = col_in && lane >= 1 && lane <= SCOLS;
+  // halo lanes load their outer neighbour column, the others their own column
+  const int xe = (lane == 0) ? x - 1 : (lane == 63 ? x + 1 : x);
+  const bool edge_in = unit_ok && xe >= 0 && xe < N;
+  const int64_t n = (int64_t)N * N;
+  const int Nc = N >> 1;
+  const T* xc = xin + (HX ? (int64_t)k * n : 0);
+  const T* bc = b + (int64_t)k * n;
+  const T* ecc = ec + (HE ? (int64_t)k * Nc * Nc : 0);
+  T* xo = xout + (int64_t)k * n;
+  const T zero = zero_of(T());
+
+  T X[NR], E[NR], B[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int yy = ys - 2 + r;
+    const bool rok = yy >= 0 && yy < N;
+    const bool okc = col_in && rok, oke = edge_in && rok;
+    T xv = zero, ev = zero;
+    if constexpr (HX) {
+      xv = ldz(xc, yy * N + x, okc);
+      ev = ldz(xc, yy * N + xe, oke);
+    }
+    if constexpr (HE) {
+      xv += wh * ldz(ecc, (yy >> 1) * Nc + (x >> 1), okc);
+      ev += wh * ldz(ecc, (yy >> 1) * Nc + (xe >> 1), oke);
+    }
+    X[r] = xv;
+    E[r] = ev;
+    B[r] = ldz(bc, yy * N + x, okc);
+  }
+  // first colour on rows ys-1 .. ys+SR (index r = row - (ys-2))
+  T N1[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) N1[r] = zero;
+#pragma unroll
+  for (int r = 1; r < NR - 1; ++r) {
+    const int y1 = ys - 2 + r;
+    const T sl = wave_shr1(X[r]), sr = wave_shl1(X[r]);
+    const T xl = (lane == 0) ? E[r] : sl;
+    const T xr = (lane == 63) ? E[r] : sr;
+    const bool ok = col_in && y1 >= 0 && y1 < N && ((x + y1) & 1) == first;
+    const T v = dinv * (B[r] + c * (xl + xr + X[r - 1] + X[r + 1]));
+    N1[r] = ok ? v : zero;
+  }
+  // second colour and output on rows ys .. yend-1 (r = 2 .. SR+1)
+  double dre = 0.0, dim = 0.0;
+#pragma unroll
+  for (int r = 2; r < NR - 2; ++r) {
+    const int y2 = ys - 2 + r;
+    const T sl = wave_shr1(N1[r]), sr = wave_shl1(N1[r]);
+    const T v2 = dinv * (B[r] + c * (sl + sr + N1[r - 1] + N1[r + 1]));
+    const T v = (((x + y2) & 1) == first) ? N1[r] : v2;
+    if (owned && y2 < yend) {
+      xo[y2 * N + x] = v;
+      if (partials) cdot_acc(dre, dim, B[r], v);
+    }
+  }
+  if (partials) {
+    block_sum2<kThreads>(dre, dim, red);
+    if (threadIdx.x == 0) partials[(int64_t)k * blocks_per_plane + bp] = {dre, dim};
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Row-marching stencil kernels: a block covers 64 consecutive x (one wave per
+// row group) and 4 x MY rows; each thread walks MY rows keeping the vertical
+// neighbours in registers.  Tile = 64 x (4*MY).
+// ---------------------------------------------------------------------------
+constexpr int MX = 64, MW = 4, MY = 8, MTY = MW * MY;
+
+struct MarchTile {
+  int k, rem, x, ybeg, yend;
+  bool ok;
+};
+
+template <int RY = MY>
+__device__ __forceinline__ MarchTile march_tile(int N, int nb, const int* active) {
+  constexpr int TY = MW * RY;
+  const int nbx = (N + MX - 1) / MX, nby = (N + TY - 1) / TY;
+  const int t = xcd_tile_index(nbx * nby * nb);
+  MarchTile m;
+  m.k = t / (nbx * nby);
+  m.rem = t - m.k * nbx * nby;
+  const int by = m.rem / nbx, bx = m.rem - by * nbx;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  m.x = bx * MX + lane;
+  m.ybeg = by * TY + w * RY;
+  m.yend = m.ybeg + RY < N ? m.ybeg + RY : N;
+  m.ok = m.k < nb && !(active && !active[m.k]);
+  return m;
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_restrict(const T* x, T* xcoarse, int N,
+__device__ __forceinline__ T ld_or0(const T* p, int x, int y, int N) {
+  return (x >= 0 && x < N && y >= 0 && y < N) ? p[y * N + x] : zero_of(T());
+}
+
+// y = A p (+ partials of conj(p)^T y).  With z and beta given, the product is
+// taken of the updated Krylov direction p = z + beta * p_old, recomputed at the
+// neighbours from (z, p_old) and written to p_new (a different buffer, so no
+// block reads a value another block has already replaced).
+template <typename T, bool UPD>
+__global__ __launch_bounds__(kThreads) void k_apply_march(const T* __restrict__ x,
+                                                          const T* __restrict__ z,
+                                                          const c64* beta, T* __restrict__ xnew,
+                                                          T* __restrict__ y, int N, R_t<T> d,
+                                                          R_t<T> c, int nb, const int* active,
+                                                          c64* partials, int* tlog) {
+  __shared__ double red[16];
+  const MarchTile m = march_tile(N, nb, active);
+  if (tlog && m.rem == 0 && threadIdx.x == 0) tlog[m.k] = active ? active[m.k] : 1;
+  if (!m.ok) return;
+  const int64_t n = (int64_t)N * N;
+  const T* xc = x + (int64_t)m.k * n;
+  const T* zc = z + (UPD ? (int64_t)m.k * n : 0);
+  T* xn = xnew + (UPD ? (int64_t)m.k * n : 0);
+  T* yc = y + (int64_t)m.k * n;
+  double dre = 0.0, dim = 0.0;
+  c64 bt = {0.0, 0.0};
+  if (UPD) bt = beta[m.k];
+  const bool col_ok = m.x < N;
+  const int xs = col_ok ? m.x : 0;
+  // loads first (branch-free): the column (rows ybeg-1 .. ybeg+MY) and both
+  // side columns
+  T cz[MY + 2], cx[MY + 2], lz[MY], lx[MY], rz[MY], rx[MY];
+#pragma unroll
+  for (int j = 0; j < MY + 2; ++j) {
+    const int yy = m.ybeg - 1 + j;
+    const bool ok = col_ok && yy >= 0 && yy < N && yy <= m.yend;
+    cx[j] = ldz(xc, yy * N + xs, ok);
+    cz[j] = UPD ? ldz(zc, yy * N + xs, ok) : zero_of(T());
+  }
+#pragma unroll
+  for (int j = 0; j < MY; ++j) {
+    const int yy = m.ybeg + j;
+    const bool ok = col_ok && yy < m.yend;
+    const bool okl = ok && m.x > 0, okr = ok && m.x + 1 < N;
+    lx[j] = ldz(xc, yy * N + xs - 1, okl);
+    rx[j] = ldz(xc, yy * N + xs + 1, okr);
+    lz[j] = UPD ? ldz(zc, yy * N + xs - 1, okl) : zero_of(T());
+    rz[j] = UPD ? ldz(zc, yy * N + xs + 1, okr) : zero_of(T());
+  }
+  auto P = [&](T zz, T xx) -> T { return UPD ? zz + scale_by(bt.re, bt.im, xx) : xx; };
+#pragma unroll
+  for (int j = 0; j < MY; ++j) {
+    const int yy = m.ybeg + j;
+    const T mid = P(cz[j + 1], cx[j + 1]);
+    const T v = d * mid - c * (P(cz[j], cx[j]) + P(cz[j + 2], cx[j + 2]) + P(lz[j], lx[j]) +
+                               P(rz[j], rx[j]));
+    if (col_ok && yy < m.yend) {
+      yc[yy * N + m.x] = v;
+      if (UPD) xn[yy * N + m.x] = mid;
+      cdot_acc(dre, dim, mid, v);
+    }
+  }
+  if (partials) {
+    block_sum2<kThreads>(dre, dim, red);
+    if (threadIdx.x == 0) {
+      const int tiles = ((N + MX - 1) / MX) * ((N + MTY - 1) / MTY);
+      partials[(int64_t)m.k * tiles + m.rem] = {dre, dim};
+    }
+  }
+}
+
+// r = b - A x (any precisions) with optional partials of |r|^2
+template <typename Tb, typename Tx, typename Tr>
+__global__ __launch_bounds__(kThreads) void k_residual_march(const Tb* __restrict__ b,
+                                                             const Tx* __restrict__ x,
+                                                             Tr* __restrict__ r, int N,
+                                                             R_t<Tx> d, R_t<Tx> c, int nb,
+                                                             const int* active,
+                                                             c64* partials, int* tlog) {
+  __shared__ double red[16];
+  const MarchTile m = march_tile(N, nb, active);
+  if (tlog && m.rem == 0 && threadIdx.x == 0) tlog[m.k] = active ? active[m.k] : 1;
+  if (!m.ok) return;
+  const int64_t n = (int64_t)N * N;
+  const Tx* xc = x + (int64_t)m.k * n;
+  const Tb* bc = b + (int64_t)m.k * n;
+  Tr* rc = r + (int64_t)m.k * n;
+  const bool col_ok = m.x < N;
+  const int xs = col_ok ? m.x : 0;
+  Tx cx[MY + 2], lx[MY], rx[MY];
+  Tb bb[MY];
+#pragma unroll
+  for (int j = 0; j < MY + 2; ++j) {
+    const int yy = m.ybeg - 1 + j;
+    cx[j] = ldz(xc, yy * N + xs, col_ok && yy >= 0 && yy < N && yy <= m.yend);
+  }
+#pragma unroll
+  for (int j = 0; j < MY; ++j) {
+    const int yy = m.ybeg + j;
+    const bool ok = col_ok && yy < m.yend;
+    lx[j] = ldz(xc, yy * N + xs - 1, ok && m.x > 0);
+    rx[j] = ldz(xc, yy * N + xs + 1, ok && m.x + 1 < N);
+    bb[j] = ldz(bc, yy * N + xs, ok);
+  }
+  double dre = 0.0, dim = 0.0;
+#pragma unroll
+  for (int j = 0; j < MY; ++j) {
+    const int yy = m.ybeg + j;
+    const Tx ax = d * cx[j + 1] - c * (cx[j] + cx[j + 2] + lx[j] + rx[j]);
+    const Tx v = convert<Tx, Tb>(bb[j]) - ax;
+    if (col_ok && yy < m.yend) {
+      rc[yy * N + m.x] = convert<Tr, Tx>(v);
+      cdot_acc(dre, dim, v, v);
+    }
+  }
+  if (partials) {
+    block_sum2<kThreads>(dre, dim, red);
+    if (threadIdx.x == 0) {
+      const int tiles = ((N + MX - 1) / MX) * ((N + MTY - 1) / MTY);
+      partials[(int64_t)m.k * tiles + m.rem] = {dre, dim};
+    }
+  }
+}
+
+// rc = R (b - A x): one thread per coarse column, RR coarse rows (2*RR fine
+// rows); all loads of a thread are issued before the arithmetic
+constexpr int RR = 4;
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_res_restrict2(const T* __restrict__ b,
+                                                            const T* __restrict__ x,
+                                                            T* __restrict__ rc, int N,
+                                                            R_t<T> d, R_t<T> c, int nb,
+                                                            const int* active, int* tlog) {
+  const int Nc = N >> 1;
+  const MarchTile m = march_tile<RR>(Nc, nb, active);  // coarse-grid tiling
+  if (tlog && m.rem == 0 && threadIdx.x == 0) tlog[m.k] = active ? active[m.k] : 1;
+  if (!m.ok) return;
+  const int64_t n = (int64_t)N * N, nc = (int64_t)Nc * Nc;
+  const T* xc = x + (int64_t)m.k * n;
+  const T* bc = b + (int64_t)m.k * n;
+  T* out = rc + (int64_t)m.k * nc;
+  if (m.x >= Nc) return;
+  const int fx = 2 * m.x;
+  constexpr int FR = 2 * RR + 2;  // fine rows 2*ybeg-1 .. 2*ybeg+2*RR
+  T x0[FR], x1[FR], xl[2 * RR], xr[2 * RR], b0[2 * RR], b1[2 * RR];
+  const int fy0 = 2 * m.ybeg - 1, fyend = 2 * m.yend;  // exclusive
+#pragma unroll
+  for (int j = 0; j < FR; ++j) {
+    const int yy = fy0 + j;
+    const bool ok = yy >= 0 && yy < N && yy <= fyend;
+    x0[j] = ldz(xc, yy * N + fx, ok);
+    x1[j] = ldz(xc, yy * N + fx + 1, ok);
+  }
+#pragma unroll
+  for (int j = 0; j < 2 * RR; ++j) {
+    const int yy = 2 * m.ybeg + j;
+    const bool ok = yy < fyend;
+    xl[j] = ldz(xc, yy * N + fx - 1, ok && fx > 0);
+    xr[j] = ldz(xc, yy * N + fx + 2, ok && fx + 2 < N);
+    b0[j] = ldz(bc, yy * N + fx, ok);
+    b1[j] = ldz(bc, yy * N + fx + 1, ok);
+  }
+#pragma unroll
+  for (int Yl = 0; Yl < RR; ++Yl) {
+    if (m.ybeg + Yl < m.yend) {
+      T acc = zero_of(T());
+#pragma unroll
+      for (int dy = 0; dy < 2; ++dy) {
+        const int j = 2 * Yl + dy;       // index into the 2*RR fine rows
+        const int jc = j + 1;            // index into x0/x1 (offset by the upper row)
+        // fine point (fx, row j): neighbours left xl, right x1, up/down x0
+        acc += b0[j] - (d * x0[jc] - c * (xl[j] + x1[jc] + x0[jc - 1] + x0[jc + 1]));
+        // fine point (fx+1, row j): neighbours left x0, right xr, up/down x1
+        acc += b1[j] - (d * x1[jc] - c * (x0[jc] + xr[j] + x1[jc - 1] + x1[jc + 1]));
+      }
+      out[(m.ybeg + Yl) * Nc + m.x] = (R_t<T>)0.5 * acc;
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_restrict2(const T* __restrict__ x,
+                                                        T* __restrict__ xcoarse, int N, int nb,
+                                                        const int* active) {
+  const int Nc = N >> 1;
+  const MarchTile m = march_tile(Nc, nb, active);
+  if (!m.ok || m.x >= Nc) return;
+  const int64_t n = (int64_t)N * N, nc = (int64_t)Nc * Nc;
+  const T* xc = x + (int64_t)m.k * n;
+  T* out = xcoarse + (int64_t)m.k * nc;
+  for (int Y = m.ybeg; Y < m.yend; ++Y) {
+    const int i0 = (2 * Y) * N + 2 * m.x;
+    out[Y * Nc + m.x] = (R_t<T>)0.5 * (xc[i0] + xc[i0 + 1] + xc[i0 + N] + xc[i0 + N + 1]);
+  }
+}
+
+// x = beta * x + (omega/2) e_c[aggregate]
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_prolong2(const T* __restrict__ ec, T* __restrict__ x,
+                                                       int N, R_t<T> wh, R_t<T> beta, int nb,
                                                        const int* active) {
-  const int k = blockIdx.y;
-  if (active && !active[k]) return;
-  const int Nc = N / 2;
-  const int64_t nc = (int64_t)Nc * Nc, n = (int64_t)N * N;
-  const int64_t I = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (I >= nc) return;
-  const int Y = (int)(I / Nc), X = (int)(I - (int64_t)Y * Nc);
-  const T* xc = x + (int64_t)k * n;
-  const int64_t i0 = (int64_t)(2 * Y) * N + 2 * X;
-  T acc = xc[i0] + xc[i0 + 1] + xc[i0 + N] + xc[i0 + N + 1];
-  xcoarse[(int64_t)k * nc + I] = (R_t<T>)0.5 * acc;
-}
-
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_prolong(const T* ec, T* x, int N, R_t<T> omega_half,
-                                                      R_t<T> beta, const int* active) {
-  const int k = blockIdx.y;
-  if (active && !active[k]) return;
-  const int Nc = N / 2;
-  const int64_t nc = (int64_t)Nc * Nc, n = (int64_t)N * N;
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (i >= n) return;
-  const int yy = (int)(i / N), xx = (int)(i - (int64_t)yy * N);
-  const T e = ec[(int64_t)k * nc + (int64_t)(yy >> 1) * Nc + (xx >> 1)];
-  T* xcol = x + (int64_t)k * n;
-  if (beta == (R_t<T>)0)
-    xcol[i] = omega_half * e;
-  else
-    xcol[i] = beta * xcol[i] + omega_half * e;
+  const MarchTile m = march_tile(N, nb, active);
+  if (!m.ok || m.x >= N) return;
+  const int Nc = N >> 1;
+  const int64_t n = (int64_t)N * N, nc = (int64_t)Nc * Nc;
+  const T* e = ec + (int64_t)m.k * nc;
+  T* xcol = x + (int64_t)m.k * n;
+  for (int yy = m.ybeg; yy < m.yend; ++yy) {
+    const T v = wh * e[(yy >> 1) * Nc + (m.x >> 1)];
+    const int i = yy * N + m.x;
+    xcol[i] = (beta == (R_t<T>)0) ? v : beta * xcol[i] + v;
+  }
 }
 
 template <typename T>
 __global__ void k_dense_build(T* M, int N, R_t<T> d, R_t<T> c) {
-  const int64_t n = (int64_t)N * N, ld = 2 * n;
-  const int64_t i = blockIdx.y;
-  const int yy = (int)(i / N), xx = (int)(i - (int64_t)yy * N);
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
-       j += (int64_t)gridDim.x * blockDim.x) {
-    const int jy = (int)(j / N), jx = (int)(j - (int64_t)jy * N);
+  const int n = N * N;
+  const int64_t ld = 2 * (int64_t)n;
+  const int i = blockIdx.y;
+  const int yy = i / N, xx = i - yy * N;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+    const int jy = j / N, jx = j - jy * N;
     T v = zero_of(T());
     if (j == i)
       v = d;
     else if ((jy == yy && (jx == xx - 1 || jx == xx + 1)) ||
              (jx == xx && (jy == yy - 1 || jy == yy + 1)))
       v = -c;
-    M[i * ld + j] = v;
+    M[(int64_t)i * ld + j] = v;
   }
 }
 
-inline dim3 grid_pts(int64_t n, int nb) {
-  return dim3((unsigned)((n + kThreads - 1) / kThreads), (unsigned)nb);
+inline int march_blocks(int N, int nb, int ry = MY) {
+  const int nbx = (N + MX - 1) / MX, nby = (N + MW * ry - 1) / (MW * ry);
+  return nbx * nby * nb;
 }
 
 }  // namespace
 
+int poisson_march_tiles(int N) { return ((N + MX - 1) / MX) * ((N + MTY - 1) / MTY); }
+// partial sums per column of the fused sweep: blocks of 4 column-marching waves
+// for N >= 64, LDS tiles below
+template <typename T>
+int poisson_gs_tiles(int N) {
+  if (N >= 64) {
+    constexpr int SR = GsRows<T>::value;
+    const int units = ((N + SCOLS - 1) / SCOLS) * ((N + SR - 1) / SR);
+    return (units + 3) / 4;
+  }
+  return ((N + GTX - 1) / GTX) * ((N + GTY - 1) / GTY);
+}
+template int poisson_gs_tiles<float>(int);
+template int poisson_gs_tiles<double>(int);
+
 template <typename T>
 void poisson_dense_build(T* aug, int N, double d, double c, hipStream_t s) {
-  const int64_t n = (int64_t)N * N;
+  const int n = N * N;
   hipLaunchKernelGGL(k_dense_build<T>, dim3((unsigned)((n + 255) / 256), (unsigned)n),
                      dim3(256), 0, s, aug, N, (R_t<T>)d, (R_t<T>)c);
 }
@@ -181,59 +573,92 @@ void poisson_dense_build(T* aug, int N, double d, double c, hipStream_t s) {
 template <typename T>
 void poisson_apply(const T* x, T* y, int N, double d, double c, int nb, const int* active,
                    c64* partials, hipStream_t s) {
-  hipLaunchKernelGGL(k_apply<T>, grid_pts((int64_t)N * N, nb), dim3(kThreads), 0, s, x, y,
-                     N, (R_t<T>)d, (R_t<T>)c, active, partials);
+  hipLaunchKernelGGL((k_apply_march<T, false>), dim3(march_blocks(N, nb)), dim3(kThreads), 0,
+                     s, x, x, (const c64*)nullptr, y, y, N, (R_t<T>)d, (R_t<T>)c, nb, active,
+                     partials, timing_log());
+}
+
+template <typename T>
+void poisson_update_apply(const T* p_old, const T* z, const c64* beta, T* p_new, T* q, int N,
+                          double d, double c, int nb, const int* active, c64* partials,
+                          hipStream_t s) {
+  hipLaunchKernelGGL((k_apply_march<T, true>), dim3(march_blocks(N, nb)), dim3(kThreads), 0, s,
+                     p_old, z, beta, p_new, q, N, (R_t<T>)d, (R_t<T>)c, nb, active, partials, timing_log());
 }
 
 template <typename Tb, typename Tx, typename Tr>
 void poisson_residual(const Tb* b, const Tx* x, Tr* r, int N, double d, double c, int nb,
                       const int* active, c64* partials, hipStream_t s) {
-  hipLaunchKernelGGL((k_residual<Tb, Tx, Tr>), grid_pts((int64_t)N * N, nb), dim3(kThreads),
-                     0, s, b, x, r, N, (R_t<Tx>)d, (R_t<Tx>)c, active, partials);
+  hipLaunchKernelGGL((k_residual_march<Tb, Tx, Tr>), dim3(march_blocks(N, nb)),
+                     dim3(kThreads), 0, s, b, x, r, N, (R_t<Tx>)d, (R_t<Tx>)c, nb, active,
+                     partials, timing_log());
 }
 
 template <typename T>
-void poisson_rbgs(const T* b, T* x, int N, double d, double c, int nb, const int* active,
-                  bool zero_init, bool reverse, hipStream_t s) {
-  const dim3 g = grid_pts((int64_t)N * N, nb);
-  const int first = reverse ? 1 : 0;
-  hipLaunchKernelGGL(k_gs_colour<T>, g, dim3(kThreads), 0, s, b, x, N, (R_t<T>)(1.0 / d),
-                     (R_t<T>)c, first, zero_init ? 1 : 0, active);
-  hipLaunchKernelGGL(k_gs_colour<T>, g, dim3(kThreads), 0, s, b, x, N, (R_t<T>)(1.0 / d),
-                     (R_t<T>)c, 1 - first, 0, active);
+void poisson_rbgs_fused(const T* xin, const T* b, T* xout, const T* ec, double omega, int N,
+                        double d, double c, int nb, const int* active, bool reverse,
+                        c64* partials, hipStream_t s) {
+  if (N >= 64) {
+    const int bpp = poisson_gs_tiles<T>(N);
+    const dim3 g(bpp * nb), blk(kThreads);
+    const R_t<T> wh = (R_t<T>)(0.5 * omega), di = (R_t<T>)(1.0 / d), cc = (R_t<T>)c;
+    const int f = reverse ? 1 : 0;
+    // null pointers are replaced by b (valid, never read) for the templated forms
+    const T* xp = xin ? xin : b;
+    const T* ep = ec ? ec : b;
+    if (xin && ec)
+      hipLaunchKernelGGL((k_rbgs_march<T, true, true>), g, blk, 0, s, xp, b, xout, ep, wh, N, di,
+                         cc, f, nb, active, partials, timing_log());
+    else if (xin)
+      hipLaunchKernelGGL((k_rbgs_march<T, true, false>), g, blk, 0, s, xp, b, xout, ep, wh, N,
+                         di, cc, f, nb, active, partials, timing_log());
+    else if (ec)
+      hipLaunchKernelGGL((k_rbgs_march<T, false, true>), g, blk, 0, s, xp, b, xout, ep, wh, N,
+                         di, cc, f, nb, active, partials, timing_log());
+    else
+      hipLaunchKernelGGL((k_rbgs_march<T, false, false>), g, blk, 0, s, xp, b, xout, ep, wh, N,
+                         di, cc, f, nb, active, partials, timing_log());
+  } else {
+    const int nbx = (N + GTX - 1) / GTX, nby = (N + GTY - 1) / GTY;
+    hipLaunchKernelGGL(k_rbgs_tile<T>, dim3(nbx * nby * nb), dim3(kThreads), 0, s, xin, b,
+                       xout, ec, (R_t<T>)(0.5 * omega), N, (R_t<T>)(1.0 / d), (R_t<T>)c,
+                       reverse ? 1 : 0, nbx, nby, nb, active, partials, timing_log());
+  }
 }
 
 template <typename T>
 void poisson_residual_restrict(const T* b, const T* x, T* rc, int N, double d, double c,
                                int nb, const int* active, hipStream_t s) {
-  const int64_t nc = (int64_t)(N / 2) * (N / 2);
-  hipLaunchKernelGGL(k_res_restrict<T>, grid_pts(nc, nb), dim3(kThreads), 0, s, b, x, rc, N,
-                     (R_t<T>)d, (R_t<T>)c, active);
+  hipLaunchKernelGGL(k_res_restrict2<T>, dim3(march_blocks(N / 2, nb, RR)), dim3(kThreads), 0, s,
+                     b, x, rc, N, (R_t<T>)d, (R_t<T>)c, nb, active, timing_log());
 }
 
 template <typename T>
 void agg2d_restrict(const T* x, T* xc, int N, int nb, const int* active, hipStream_t s) {
-  const int64_t nc = (int64_t)(N / 2) * (N / 2);
-  hipLaunchKernelGGL(k_restrict<T>, grid_pts(nc, nb), dim3(kThreads), 0, s, x, xc, N, active);
+  hipLaunchKernelGGL(k_restrict2<T>, dim3(march_blocks(N / 2, nb)), dim3(kThreads), 0, s, x,
+                     xc, N, nb, active);
 }
 
 template <typename T>
 void agg2d_prolong(const T* ec, T* x, int N, double omega, double beta, int nb,
                    const int* active, hipStream_t s) {
-  hipLaunchKernelGGL(k_prolong<T>, grid_pts((int64_t)N * N, nb), dim3(kThreads), 0, s, ec, x,
-                     N, (R_t<T>)(0.5 * omega), (R_t<T>)beta, active);
+  hipLaunchKernelGGL(k_prolong2<T>, dim3(march_blocks(N, nb)), dim3(kThreads), 0, s, ec, x, N,
+                     (R_t<T>)(0.5 * omega), (R_t<T>)beta, nb, active);
 }
 
-#define MLMC_INST_P(T)                                                                     \
-  template void poisson_dense_build<T>(T*, int, double, double, hipStream_t);             \
-  template void poisson_apply<T>(const T*, T*, int, double, double, int, const int*, c64*, \
-                                 hipStream_t);                                            \
-  template void poisson_rbgs<T>(const T*, T*, int, double, double, int, const int*, bool, \
-                                bool, hipStream_t);                                       \
-  template void poisson_residual_restrict<T>(const T*, const T*, T*, int, double, double, \
-                                             int, const int*, hipStream_t);               \
-  template void agg2d_restrict<T>(const T*, T*, int, int, const int*, hipStream_t);       \
-  template void agg2d_prolong<T>(const T*, T*, int, double, double, int, const int*,      \
+#define MLMC_INST_P(T)                                                                      \
+  template void poisson_dense_build<T>(T*, int, double, double, hipStream_t);              \
+  template void poisson_apply<T>(const T*, T*, int, double, double, int, const int*, c64*,  \
+                                 hipStream_t);                                             \
+  template void poisson_update_apply<T>(const T*, const T*, const c64*, T*, T*, int, double, \
+                                        double, int, const int*, c64*, hipStream_t);       \
+  template void poisson_rbgs_fused<T>(const T*, const T*, T*, const T*, double, int,       \
+                                      double, double, int, const int*, bool, c64*,         \
+                                      hipStream_t);                                        \
+  template void poisson_residual_restrict<T>(const T*, const T*, T*, int, double, double,  \
+                                             int, const int*, hipStream_t);                \
+  template void agg2d_restrict<T>(const T*, T*, int, int, const int*, hipStream_t);        \
+  template void agg2d_prolong<T>(const T*, T*, int, double, double, int, const int*,       \
                                  hipStream_t);
 
 MLMC_INST_P(float)

@@ -1,4 +1,6 @@
 // Vector, reduction, Krylov-scalar, probe and dense kernels.
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace mlmc {
@@ -104,6 +106,31 @@ __global__ void k_count(const int* active, int nb, int* count) {
   if (threadIdx.x == 0) *count = cnt;
 }
 
+__global__ void k_ir_err(const c64* bd, const c64* rr_old, const c64* rr_new,
+                         const int* active, c64* err, int nb) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nb || !active[k]) return;
+  const double mag = sqrt(bd[k].re * bd[k].re + bd[k].im * bd[k].im);
+  const double ratio = rr_old[k].re > 0.0 ? sqrt(rr_new[k].re / rr_old[k].re) : 1.0;
+  err[k] = {mag * ratio, 0.0};
+}
+
+__global__ void k_set_count(int* c, int v) { *c = v; }
+
+__global__ void k_refine_due(const c64* rr, const c64* rr_upd, const c64* bb, double delta2,
+                             double tol2, const int* active, int nb, int* count) {
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  for (int k = threadIdx.x; k < nb; k += blockDim.x) {
+    if (!active[k]) continue;
+    const double v = rr[k].re;
+    if (v <= delta2 * rr_upd[k].re || v <= tol2 * bb[k].re || !isfinite(v)) atomicAdd(&cnt, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *count = cnt;
+}
+
 __global__ void k_set_ones(int* a, int nb) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k < nb) a[k] = 1;
@@ -123,9 +150,11 @@ __global__ void k_lastcorr(const c64* alpha, const c64* rz, const int* active, c
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_cg_xr(T* x, T* r, const T* p, const T* q,
                                                     const c64* alpha, int64_t n,
-                                                    const int* active, c64* partials) {
+                                                    const int* active, c64* partials,
+                                                    int* tlog) {
   __shared__ double lds[16];
   const int k = blockIdx.y, nblk = gridDim.x;
+  if (tlog && blockIdx.x == 0 && threadIdx.x == 0) tlog[k] = active ? active[k] : 1;
   if (active && !active[k]) return;
   const c64 a = alpha[k];
   const int64_t chunk = (n + nblk - 1) / nblk;
@@ -412,6 +441,94 @@ __global__ __launch_bounds__(kThreads) void k_dense_apply(const T* At, const T* 
   if (i < n && kok) Z[(int64_t)k * n + i] = acc;
 }
 
+// ---- coarsest solve as an MFMA GEMM: Z = B At (real types, n % 16 == 0) ----
+// One wave computes a 16 (RHS) x 16 (unknowns) tile of Z with
+// v_mfma_{f32,f64}_16x16x4.  Operand layout of these instructions (one block):
+// A (16x4): lane l holds A[l % 16][l / 16]; B (4x16): lane l holds
+// B[l / 16][l % 16]; D (16x16): lane l, register r holds D[row][l % 16] with
+// row = 4*(l/16) + r for the f32 form and row = 4*r + l/16 for the f64 form.
+// The reduction index is permuted inside each chunk of 16 (lane group g supplies
+// k = 4g + s at step s for both operands), which leaves the sum unchanged and
+// lets each lane load its A values as one vector.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mfma;
+template <> struct Mfma<float> {
+  using acc_t = f32x4;
+  __device__ static acc_t step(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int g, int r) { return 4 * g + r; }
+};
+template <> struct Mfma<double> {
+  using acc_t = f64x4;
+  __device__ static acc_t step(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int g, int r) { return 4 * r + g; }
+};
+
+// A 256-thread block computes one 16 x 16 tile of Z; its four waves split the
+// reduction index (chunk ranges of 16), each keeping UNR chunks of loads in
+// flight, and the four partial tiles are summed in LDS in wave order.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_dense_apply_mfma(const T* __restrict__ At,
+                                                               const T* __restrict__ B,
+                                                               T* __restrict__ Z, int n, int nb,
+                                                               const int* active) {
+  constexpr int UNR = 4;
+  __shared__ T part[4][4][64];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i0 = blockIdx.x * 16;       // unknown tile
+  const int m0 = blockIdx.y * 16;       // RHS tile
+  const int g = lane >> 4, c = lane & 15;
+  const int row = m0 + c;               // RHS whose A-operand this lane supplies
+  const bool row_ok = row < nb;
+  const T* brow = B + (int64_t)(row_ok ? row : 0) * n;
+  const int chunks = n / 16;
+  const int cbeg = wave * chunks / 4, cend = (wave + 1) * chunks / 4;
+  typename Mfma<T>::acc_t acc = {0, 0, 0, 0};
+  int ch = cbeg;
+  for (; ch + UNR <= cend; ch += UNR) {
+    T a[UNR][4], bv[UNR][4];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int j = (ch + u) * 16 + 4 * g + s;
+        a[u][s] = row_ok ? brow[j] : (T)0;
+        bv[u][s] = At[(int64_t)j * n + i0 + c];
+      }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) acc = Mfma<T>::step(a[u][s], bv[u][s], acc);
+  }
+  for (; ch < cend; ++ch) {
+    T a[4], bv[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int j = ch * 16 + 4 * g + s;
+      a[s] = row_ok ? brow[j] : (T)0;
+      bv[s] = At[(int64_t)j * n + i0 + c];
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) acc = Mfma<T>::step(a[s], bv[s], acc);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) part[wave][r][lane] = acc[r];
+  __syncthreads();
+  if (wave == 0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const T v = ((part[0][r][lane] + part[1][r][lane]) + part[2][r][lane]) + part[3][r][lane];
+      const int k = m0 + Mfma<T>::row(g, r);
+      if (k < nb && (!active || active[k])) Z[(int64_t)k * n + i0 + c] = v;
+    }
+  }
+}
+
 }  // namespace
 
 // ============================================================================
@@ -431,6 +548,11 @@ void vec_convert(const From* x, To* y, int64_t n, int nb, const int* active, hip
   if (n <= 0 || nb <= 0) return;
   hipLaunchKernelGGL((k_convert<To, From>), grid_cols(n, nb), dim3(kThreads), 0, s, x, y, n,
                      active);
+}
+
+int*& timing_log() {
+  thread_local int* slot = nullptr;
+  return slot;
 }
 
 int reduce_blocks(int64_t n) {
@@ -469,6 +591,19 @@ void count_active(const int* active, int nb, int* count, hipStream_t s) {
   hipLaunchKernelGGL(k_count, dim3(1), dim3(256), 0, s, active, nb, count);
 }
 
+void ir_stated_error(const c64* bd, const c64* rr_old, const c64* rr_new, const int* active,
+                     c64* err, int nb, hipStream_t s) {
+  hipLaunchKernelGGL(k_ir_err, dim3((nb + 255) / 256), dim3(256), 0, s, bd, rr_old, rr_new,
+                     active, err, nb);
+}
+void refine_due(const c64* rr, const c64* rr_upd, const c64* bb, double delta2, double tol2,
+                const int* active, int nb, int* count, hipStream_t s) {
+  hipLaunchKernelGGL(k_refine_due, dim3(1), dim3(256), 0, s, rr, rr_upd, bb, delta2, tol2,
+                     active, nb, count);
+}
+void set_count(int* count, int value, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, s, count, value);
+}
 void set_all_active(int* active, int nb, hipStream_t s) {
   hipLaunchKernelGGL(k_set_ones, dim3((nb + 255) / 256), dim3(256), 0, s, active, nb);
 }
@@ -485,7 +620,7 @@ template <typename T>
 void cg_update_xr(T* x, T* r, const T* p, const T* q, const c64* alpha, int64_t n, int nb,
                   const int* active, c64* partials, hipStream_t s) {
   hipLaunchKernelGGL(k_cg_xr<T>, dim3(reduce_blocks(n), nb), dim3(kThreads), 0, s, x, r, p,
-                     q, alpha, n, active, partials);
+                     q, alpha, n, active, partials, timing_log());
 }
 template <typename T>
 void cg_update_p(T* p, const T* z, const c64* beta, int64_t n, int nb, const int* active,
@@ -559,6 +694,14 @@ void dense_trace(const T* A, int n, c64* out, hipStream_t s) {
 template <typename T>
 void dense_apply(const T* At, const T* B, T* Z, int n, int nb, const int* active,
                  hipStream_t s) {
+  if constexpr (std::is_same<T, float>::value || std::is_same<T, double>::value) {
+    if (n % 16 == 0) {
+      dim3 grid((unsigned)(n / 16), (unsigned)((nb + 15) / 16));
+      hipLaunchKernelGGL(k_dense_apply_mfma<T>, grid, dim3(kThreads), 0, s, At, B, Z, n, nb,
+                         active);
+      return;
+    }
+  }
   dim3 grid((unsigned)((n + 63) / 64), (unsigned)((nb + 3) / 4));
   hipLaunchKernelGGL(k_dense_apply<T>, grid, dim3(kThreads), 0, s, At, B, Z, n, nb, active);
 }

@@ -32,8 +32,9 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_sizes_match_header_layout():
     from paper_2108_11281_amd import _capi
-    # mlmc_result: 2+1+1+2 doubles, int (+pad), 16 int64, 32+16+16 doubles, 2 int64, 2 doubles
-    assert ctypes.sizeof(_capi.Result) == 8 * (6 + 1 + 16 + 32 + 16 + 16 + 2 + 2)
+    # mlmc_result: 2+1+1+2 doubles, int (+pad), 16 int64, 32+16+16+16 doubles, 2 int64,
+    # 2 doubles
+    assert ctypes.sizeof(_capi.Result) == 8 * (6 + 1 + 16 + 32 + 16 + 16 + 16 + 2 + 2)
     assert ctypes.sizeof(_capi.Options) == 96
 
 
