@@ -12,7 +12,10 @@ BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
 SOURCES = [
     "kernels_vec.hip",
     "kernels_poisson.hip",
+    "kernels_wilson.hip",
+    "kernels_krylov.hip",
     "context.cpp",
+    "context_complex.cpp",
     "estimator.cpp",
     "capi.cpp",
 ]

@@ -43,7 +43,13 @@ Context::Context(const mlmc_operator& A, const mlmc_hierarchy& h, const mlmc_opt
   try {
     switch (kind_) {
       case MLMC_POISSON2D:
+        omega_ = opt_.omega > 0 ? opt_.omega : 1.8;
         build_poisson();
+        break;
+      case MLMC_WILSON2D:
+        complex_ = true;
+        omega_ = opt_.omega > 0 ? opt_.omega : 1.0;
+        build_wilson(A.field);
         break;
       default:
         throw Error(MLMC_EUNSUPPORTED, "operator kind not supported");
@@ -144,6 +150,35 @@ void Context::invert_coarse(int level, double** inv_out, c64* trace_out) {
   *inv_out = inv;
 }
 
+// device/pinned buffers shared by every operator kind: reduction partials,
+// per-column scalars, flags and the FP64 sample-batch vectors (complex: two
+// doubles per unknown)
+void Context::alloc_common() {
+  const int64_t n1 = lv_[0].n;
+  const int64_t elem = complex_ ? 2 : 1;
+  // per-column partial sums: enough for one partial per 256-thread block of
+  // the finest level (stencil kernels with fused dots) or kMaxPartials
+  const int64_t per_col = std::max<int64_t>(kMaxPartials, (n1 + kThreads - 1) / kThreads);
+  // complex operators: the FGMRES multi-dot writes up to 256 partials for each
+  // of the m+1 basis vectors of every column
+  const int64_t cap = std::max<int64_t>(per_col * nb_, complex_ ? 256LL * nb_ * (m_ + 1) : 0);
+  partials_ = dalloc_n<c64>(cap);
+  partials_cap_ = cap;
+  c64* sc = dalloc_n<c64>((int64_t)kNumScalars * nb_);
+  for (int i = 0; i < kNumScalars; ++i) scal_[i] = sc + (int64_t)i * nb_;
+  act_outer_ = dalloc_n<int>(nb_);
+  act_inner_ = dalloc_n<int>(nb_);
+  count_dev_ = dalloc_n<int>(4);
+  piv_ = dalloc_n<int>(4);
+  MLMC_HIP(hipHostMalloc((void**)&count_host_, 4 * sizeof(int)));
+  MLMC_HIP(hipHostMalloc((void**)&host_c64_, 8 * (size_t)nb_ * sizeof(c64)));
+  b1_ = dalloc_n<double>(n1 * nb_ * elem);
+  y1_ = dalloc_n<double>(n1 * nb_ * elem);
+  b2_ = dalloc_n<double>(lv_[1].n * nb_ * elem);
+  y2_ = dalloc_n<double>(lv_[1].n * nb_ * elem);
+  r64_ = dalloc_n<double>(n1 * nb_ * elem);
+}
+
 void Context::build_poisson() {
   MLMC_REQUIRE(op_.n_side >= 2, MLMC_EINVAL, "n_side must be >= 2");
   MLMC_REQUIRE(op_.diag > 0 && op_.off >= 0 && op_.diag >= 4 * op_.off, MLMC_EINVAL,
@@ -172,28 +207,7 @@ void Context::build_poisson() {
   }
   MLMC_REQUIRE(lv_[Ls_ - 1].n <= 16384, MLMC_EINVAL, "coarsest solver level larger than 128^2");
   const int64_t n1 = lv_[0].n;
-
-  // small device and pinned host buffers
-  // per-column partial sums: enough for one partial per 256-thread block of
-  // the finest level (stencil kernels with fused dots) or kMaxPartials
-  const int64_t per_col = std::max<int64_t>(kMaxPartials, (n1 + kThreads - 1) / kThreads);
-  partials_ = dalloc_n<c64>(per_col * nb_);
-  partials_cap_ = per_col * nb_;
-  c64* sc = dalloc_n<c64>((int64_t)kNumScalars * nb_);
-  for (int i = 0; i < kNumScalars; ++i) scal_[i] = sc + (int64_t)i * nb_;
-  act_outer_ = dalloc_n<int>(nb_);
-  act_inner_ = dalloc_n<int>(nb_);
-  count_dev_ = dalloc_n<int>(4);
-  piv_ = dalloc_n<int>(4);
-  MLMC_HIP(hipHostMalloc((void**)&count_host_, 4 * sizeof(int)));
-  MLMC_HIP(hipHostMalloc((void**)&host_c64_, 8 * (size_t)nb_ * sizeof(c64)));
-
-  // sample-batch buffers (FP64)
-  b1_ = dalloc_n<double>(n1 * nb_);
-  y1_ = dalloc_n<double>(n1 * nb_);
-  b2_ = dalloc_n<double>(lv_[1].n * nb_);
-  y2_ = dalloc_n<double>(lv_[1].n * nb_);
-  r64_ = dalloc_n<double>(n1 * nb_);
+  alloc_common();
   alloc_work(w64_);
   if (opt_.precision == MLMC_FP32_IR64) {
     alloc_work(w32_);
@@ -245,7 +259,7 @@ void Context::op_res_restrict(int l, const T* b, const T* x, T* rc, int nb, cons
 template <typename T>
 void Context::op_prolong(int l, const T* ec, T* x, int nb, const int* act, double beta) {
   const Level& L = lv_[l - 1];
-  agg2d_prolong<T>(ec, x, L.side, beta == 0.0 ? 1.0 : opt_.omega, beta, nb, act, s_);
+  agg2d_prolong<T>(ec, x, L.side, beta == 0.0 ? 1.0 : omega_, beta, nb, act, s_);
 }
 
 template <typename T>
@@ -296,10 +310,10 @@ void Context::vcycle(int l, const T* b, T* x, int nb, const int* act, c64* rz_pa
   vcycle<T>(l + 1, bc, ec, nb, act, nullptr);
   if (post == 0) {
     if (u == nullptr) {
-      agg2d_prolong<T>(ec, x, L.side, opt_.omega, 0.0, nb, act, s_);
+      agg2d_prolong<T>(ec, x, L.side, omega_, 0.0, nb, act, s_);
     } else {
       if (u != x) vec_copy<T>(u, x, n, nb, act, s_);
-      agg2d_prolong<T>(ec, x, L.side, opt_.omega, 1.0, nb, act, s_);
+      agg2d_prolong<T>(ec, x, L.side, omega_, 1.0, nb, act, s_);
     }
     if (rz_partials) vec_dot_partials<T>(b, x, n, nb, act, rz_partials, s_);
     return;
@@ -313,7 +327,7 @@ void Context::vcycle(int l, const T* b, T* x, int nb, const int* act, c64* rz_pa
     const T* corr = (i == 0) ? ec : nullptr;
     const bool last = (i == post - 1);
     timed<T>(kTimGs, en * (2.0 + (in ? 1.0 : 0.0) + (corr ? 0.25 : 0.0)), act, nb, [&] {
-      poisson_rbgs_fused<T>(in, b, out, corr, opt_.omega, L.side, L.d, L.c, nb, act, true,
+      poisson_rbgs_fused<T>(in, b, out, corr, omega_, L.side, L.d, L.c, nb, act, true,
                             last ? rz_partials : nullptr, s_);
     });
     u = out;
@@ -586,11 +600,24 @@ void Context::pcg_refined(int l, const double* b, double* y, int nb, double tol,
 void Context::solve(int l, const double* b, double* y, int nb, c64* err, double* relres_host,
                     bool* converged) {
   const int64_t n = lv_[l - 1].n;
-  const int nblk_pts = poisson_march_tiles(lv_[l - 1].side);
+  const int nblk_pts = complex_ ? 0 : poisson_march_tiles(lv_[l - 1].side);
   const int nblk = reduce_blocks(n);
   c64* bb = scal_[kBb];
   c64* bd = scal_[kBd];
   c64* rres = scal_[kRres];  // also the refinement loop's residual norms
+  if (complex_) {
+    solve_complex(l, reinterpret_cast<const c64*>(b), reinterpret_cast<c64*>(y), nb, err);
+    // final FP64 relative residuals
+    cop_residual<c64, c64, c64>(l, reinterpret_cast<const c64*>(b),
+                                reinterpret_cast<const c64*>(y), reinterpret_cast<c64*>(r64_),
+                                nb, nullptr, partials_);
+    finish_sums(partials_, lv_[l - 1].wilson ? wilson_residual_blocks(lv_[l - 1].side)
+                                             : bsr_residual_blocks(lv_[l - 1].side),
+                nb, rres, s_);
+    vec_dot_partials<c64>(reinterpret_cast<const c64*>(b), reinterpret_cast<const c64*>(b), n,
+                          nb, nullptr, partials_, s_);
+    finish_sums(partials_, nblk, nb, bb, s_);
+  } else {
   vec_dot_partials<double>(b, b, n, nb, nullptr, partials_, s_);
   finish_sums(partials_, nblk, nb, bb, s_);
   set_all_active(act_outer_, nb, s_);
@@ -612,6 +639,8 @@ void Context::solve(int l, const double* b, double* y, int nb, c64* err, double*
     op_residual<double, double, double>(l, b, y, r64_, nb, nullptr, partials_);
     finish_sums(partials_, nblk_pts, nb, rres, s_);
   }
+  }
+  const double tol = opt_.solve_tol;
   MLMC_HIP(hipMemcpyAsync(host_c64_, rres, sizeof(c64) * nb, hipMemcpyDeviceToHost, s_));
   MLMC_HIP(hipMemcpyAsync(host_c64_ + nb, bb, sizeof(c64) * nb, hipMemcpyDeviceToHost, s_));
   MLMC_HIP(hipStreamSynchronize(s_));
@@ -626,6 +655,41 @@ void Context::solve(int l, const double* b, double* y, int nb, c64* err, double*
 }
 
 // ---------------------------------------------------------------------------
+// probes (Rademacher for real, Z4 for complex operators), their restriction
+// and quadratic forms, on FP64 buffers (complex: interleaved)
+// ---------------------------------------------------------------------------
+void Context::write_probes(int level, uint64_t seed, uint64_t stream, uint64_t first, int nb,
+                           double* out) {
+  const int64_t n = lv_[level - 1].n;
+  if (complex_)
+    probes_write<c64>(reinterpret_cast<c64*>(out), n, nb, seed, 0, first, (uint64_t)level,
+                      stream, s_);
+  else
+    probes_write<double>(out, n, nb, seed, 0, first, (uint64_t)level, stream, s_);
+}
+
+void Context::restrict64(int level, const double* x, double* xc, int nb) {
+  if (complex_)
+    cop_restrict<c64>(level, reinterpret_cast<const c64*>(x), reinterpret_cast<c64*>(xc), nb,
+                      nullptr);
+  else
+    op_restrict<double>(level, x, xc, nb, nullptr);
+}
+
+void Context::probe_quad(int level, uint64_t seed, uint64_t stream, uint64_t first, int nb,
+                         const double* y, c64* out) {
+  const int64_t n = lv_[level - 1].n;
+  const int64_t chunk = complex_ ? (int64_t)kThreads * 128 : (int64_t)kThreads * 256;
+  const int nblk = (int)((n + chunk - 1) / chunk);
+  if (complex_)
+    probe_dot_partials<c64>(reinterpret_cast<const c64*>(y), n, nb, seed, 0, first,
+                            (uint64_t)level, stream, partials_, s_);
+  else
+    probe_dot_partials<double>(y, n, nb, seed, 0, first, (uint64_t)level, stream, partials_, s_);
+  finish_sums(partials_, nblk, nb, out, s_);
+}
+
+// ---------------------------------------------------------------------------
 // level-difference samples: s = x^H A_l^-1 x - (R x)^H A_{l+1}^-1 (R x)
 // ---------------------------------------------------------------------------
 void Context::samples_batch(int level, uint64_t seed, uint64_t first, int nbatch, c64* out,
@@ -633,19 +697,20 @@ void Context::samples_batch(int level, uint64_t seed, uint64_t first, int nbatch
   MLMC_REQUIRE(level >= 1 && level < L_, MLMC_EINVAL, "sample level must be in [1, L-1]");
   MLMC_REQUIRE(nbatch >= 1 && nbatch <= nb_, MLMC_EINVAL, "batch size out of range");
   const int64_t n1 = lv_[level - 1].n, n2 = lv_[level].n;
-  probes_write<double>(b1_, n1, nbatch, seed, 0, first, (uint64_t)level, kStreamProbe, s_);
+  write_probes(level, seed, kStreamProbe, first, nbatch, b1_);
   bool ok1 = true, ok2 = true;
   c64 *e1 = scal_[kErr1], *e2 = scal_[kErr2], *qa = scal_[kQa], *qb = scal_[kQb];
   solve(level, b1_, y1_, nbatch, e1, nullptr, &ok1);
-  op_restrict<double>(level, b1_, b2_, nbatch, nullptr);
+  restrict64(level, b1_, b2_, nbatch);
   solve(level + 1, b2_, y2_, nbatch, e2, nullptr, &ok2);
   // x^H y with x regenerated, and (Rx)^H z
-  const int64_t chunk1 = (int64_t)kThreads * 256;  // Rademacher entries per block
-  const int nb1 = (int)((n1 + chunk1 - 1) / chunk1);
-  probe_dot_partials<double>(y1_, n1, nbatch, seed, 0, first, (uint64_t)level, kStreamProbe,
-                             partials_, s_);
-  finish_sums(partials_, nb1, nbatch, qa, s_);
-  vec_dot_partials<double>(b2_, y2_, n2, nbatch, nullptr, partials_, s_);
+  probe_quad(level, seed, kStreamProbe, first, nbatch, y1_, qa);
+  if (complex_) {
+    vec_dot_partials<c64>(reinterpret_cast<const c64*>(b2_), reinterpret_cast<const c64*>(y2_),
+                          n2, nbatch, nullptr, partials_, s_);
+  } else {
+    vec_dot_partials<double>(b2_, y2_, n2, nbatch, nullptr, partials_, s_);
+  }
   finish_sums(partials_, reduce_blocks(n2), nbatch, qb, s_);
   // scalars e1, e2, qa, qb are consecutive blocks of nb_ entries
   MLMC_HIP(hipMemcpyAsync(host_c64_, scal_[kErr1], sizeof(c64) * 4 * nb_,
@@ -671,14 +736,10 @@ void Context::samples_batch(int level, uint64_t seed, uint64_t first, int nbatch
 
 void Context::hutch_batch(uint64_t seed, uint64_t stream, uint64_t first, int nbatch,
                           c64* out) {
-  const int64_t n1 = lv_[0].n;
-  probes_write<double>(b1_, n1, nbatch, seed, 0, first, 1, stream, s_);
+  write_probes(1, seed, stream, first, nbatch, b1_);
   bool ok = true;
   solve(1, b1_, y1_, nbatch, scal_[kErr1], nullptr, &ok);
-  const int64_t chunk1 = (int64_t)kThreads * 256;
-  const int nb1 = (int)((n1 + chunk1 - 1) / chunk1);
-  probe_dot_partials<double>(y1_, n1, nbatch, seed, 0, first, 1, stream, partials_, s_);
-  finish_sums(partials_, nb1, nbatch, scal_[kQa], s_);
+  probe_quad(1, seed, stream, first, nbatch, y1_, scal_[kQa]);
   MLMC_HIP(hipMemcpyAsync(host_c64_, scal_[kQa], sizeof(c64) * nbatch, hipMemcpyDeviceToHost,
                           s_));
   MLMC_HIP(hipStreamSynchronize(s_));
@@ -776,7 +837,11 @@ void Context::solve_fp64(int level, int nrhs, const double* b, double* y, double
 void Context::apply_fp64(int level, int nrhs, const double* x, double* y) {
   MLMC_REQUIRE(level >= 1 && level <= Ls_, MLMC_EINVAL, "level out of range");
   MLMC_REQUIRE(nrhs >= 1, MLMC_EINVAL, "nrhs must be >= 1");
-  op_apply<double>(level, x, y, nrhs, nullptr, nullptr);
+  if (complex_)
+    cop_residual<c64, c64, c64>(level, nullptr, reinterpret_cast<const c64*>(x),
+                                reinterpret_cast<c64*>(y), nrhs, nullptr, nullptr);
+  else
+    op_apply<double>(level, x, y, nrhs, nullptr, nullptr);
   MLMC_HIP(hipStreamSynchronize(s_));
   MLMC_HIP(hipGetLastError());
 }
@@ -784,7 +849,7 @@ void Context::apply_fp64(int level, int nrhs, const double* x, double* y) {
 void Context::restrict_fp64(int level, int nrhs, const double* x, double* xc) {
   MLMC_REQUIRE(level >= 1 && level < Ls_, MLMC_EINVAL, "level out of range");
   MLMC_REQUIRE(nrhs >= 1, MLMC_EINVAL, "nrhs must be >= 1");
-  op_restrict<double>(level, x, xc, nrhs, nullptr);
+  restrict64(level, x, xc, nrhs);
   MLMC_HIP(hipStreamSynchronize(s_));
   MLMC_HIP(hipGetLastError());
 }
@@ -792,7 +857,11 @@ void Context::restrict_fp64(int level, int nrhs, const double* x, double* xc) {
 void Context::prolong_fp64(int level, int nrhs, const double* xc, double* x) {
   MLMC_REQUIRE(level >= 1 && level < Ls_, MLMC_EINVAL, "level out of range");
   MLMC_REQUIRE(nrhs >= 1, MLMC_EINVAL, "nrhs must be >= 1");
-  agg2d_prolong<double>(xc, x, lv_[level - 1].side, 1.0, 0.0, nrhs, nullptr, s_);
+  if (complex_)
+    cop_prolong<c64>(level, reinterpret_cast<const c64*>(xc), reinterpret_cast<c64*>(x), nrhs,
+                     nullptr, 1.0, 0.0);
+  else
+    agg2d_prolong<double>(xc, x, lv_[level - 1].side, 1.0, 0.0, nrhs, nullptr, s_);
   MLMC_HIP(hipStreamSynchronize(s_));
   MLMC_HIP(hipGetLastError());
 }
@@ -801,28 +870,36 @@ void Context::probes_fp64(int level, uint64_t seed, int stream, int64_t first, i
                           double* out) {
   MLMC_REQUIRE(level >= 1 && level <= Ls_, MLMC_EINVAL, "level out of range");
   MLMC_REQUIRE(nrhs >= 1 && first >= 0 && stream >= 0, MLMC_EINVAL, "bad probe range");
-  probes_write<double>(out, lv_[level - 1].n, nrhs, seed, 0, (uint64_t)first,
-                       (uint64_t)level, (uint64_t)stream, s_);
+  write_probes(level, seed, (uint64_t)stream, (uint64_t)first, nrhs, out);
   MLMC_HIP(hipStreamSynchronize(s_));
   MLMC_HIP(hipGetLastError());
 }
 
 void Context::export_coarse(int which, double* out) {
   const int level = which == 1 ? L_ : Ls_;
-  const int n = (int)lv_[level - 1].n;
-  double* aug = dalloc_n<double>(2 * (int64_t)n * n);
-  poisson_dense_build<double>(aug, lv_[level - 1].side, lv_[level - 1].d, lv_[level - 1].c,
-                              s_);
+  const Level& L = lv_[level - 1];
+  const int n = (int)L.n;
+  const int elem = complex_ ? 2 : 1;
+  double* aug = dalloc_n<double>(2 * (int64_t)n * n * elem);
+  if (complex_)
+    dense_from_stencil(L.wilson ? nullptr : L.B64, L.U64, op_.mass + 2.0, L.side, L.dof,
+                       reinterpret_cast<c64*>(aug), s_);
+  else
+    poisson_dense_build<double>(aug, L.side, L.d, L.c, s_);
   for (int i = 0; i < n; ++i)
-    MLMC_HIP(hipMemcpyAsync(out + (size_t)i * n, aug + (size_t)i * 2 * n, sizeof(double) * n,
-                            hipMemcpyDeviceToHost, s_));
+    MLMC_HIP(hipMemcpyAsync(out + (size_t)i * n * elem, aug + (size_t)i * 2 * n * elem,
+                            sizeof(double) * n * elem, hipMemcpyDeviceToHost, s_));
   MLMC_HIP(hipStreamSynchronize(s_));
 }
 
 void Context::export_prolongation(int level, double* out) {
-  (void)level;
-  (void)out;
-  throw Error(MLMC_EUNSUPPORTED, "prolongation export is for test-vector aggregation only");
+  MLMC_REQUIRE(complex_, MLMC_EUNSUPPORTED,
+               "prolongation export is for test-vector aggregation only");
+  MLMC_REQUIRE(level >= 1 && level < Ls_, MLMC_EINVAL, "level out of range");
+  const Level& L = lv_[level - 1];
+  MLMC_HIP(hipMemcpyAsync(out, L.q64, sizeof(c64) * (size_t)L.n * lv_[level].dof,
+                          hipMemcpyDeviceToHost, s_));
+  MLMC_HIP(hipStreamSynchronize(s_));
 }
 
 template void Context::vcycle<float>(int, const float*, float*, int, const int*, c64*);

@@ -24,6 +24,28 @@ struct Level {
   int dof = 1;        // unknowns per site (1 for scalar grids)
   int64_t n = 0;      // unknowns
   double d = 0, c = 0;  // POISSON2D stencil: A = d I - c (neighbours)
+  // complex lattice levels: level 1 is the Wilson operator (links U), the
+  // others 5-point block stencils B with inverted diagonal blocks Dinv
+  bool wilson = false;
+  c64* U64 = nullptr;
+  c32* U32 = nullptr;
+  c64 *B64 = nullptr, *Dinv64 = nullptr;
+  c32 *B32 = nullptr, *Dinv32 = nullptr;
+  // aggregation to the next level: row i (fine unknown) holds the coarse
+  // coefficients q[i][0..dof_next-1]; aggregates are blk x blk sites
+  c64* q64 = nullptr;
+  c32* q32 = nullptr;
+  int blk = 0;
+};
+
+// Batched flexible GMRES workspace (precision T)
+template <typename T>
+struct Fgmres {
+  T* V = nullptr;   // (m+1) basis vectors of n1*nb
+  T* Z = nullptr;   // m preconditioned vectors
+  T* r = nullptr;   // right-hand side of the cycle
+  T* d = nullptr;   // correction
+  T* tmp = nullptr;
 };
 
 // Per-precision work buffers (T = float or double for real operators).
@@ -85,6 +107,25 @@ class Context {
     return static_cast<T*>(dalloc(sizeof(T) * (size_t)count));
   }
   void build_poisson();
+  void build_wilson(const double* theta);
+  void alloc_common();
+  // complex operators: op on level l in precision T (c32 / c64)
+  template <typename T> const T* links(int l) const;
+  template <typename T> const T* blocks(int l) const;
+  template <typename T> const T* dinv(int l) const;
+  template <typename T> const T* qmat(int l) const;
+  template <typename Tb, typename T, typename Tr>
+  void cop_residual(int l, const Tb* b, const T* x, Tr* r, int nb, const int* act, c64* partials);
+  template <typename T> void cop_smooth(int l, const T* b, T* x, int nb, const int* act,
+                                        bool zero_init, bool reverse);
+  template <typename T> void cop_restrict(int l, const T* x, T* xc, int nb, const int* act);
+  template <typename T> void cop_prolong(int l, const T* ec, T* x, int nb, const int* act,
+                                         double omega, double beta);
+  template <typename T> void cvcycle(int l, const T* b, T* x, int nb, const int* act);
+  template <typename T> void fgmres_cycle(int l, const T* r, T* d, int nb, int* act,
+                                          double tol);
+  void solve_complex(int l, const c64* b, c64* y, int nb, c64* err);
+  template <typename T> Fgmres<T>& fg();
   void invert_coarse(int level, double** inv_out, c64* trace_out);
   template <typename T> void alloc_work(Work<T>& w);
 
@@ -114,6 +155,11 @@ class Context {
   void solve(int l, const double* b, double* y, int nb, c64* err, double* relres_host,
              bool* converged);
   int read_count();
+  void write_probes(int level, uint64_t seed, uint64_t stream, uint64_t first, int nb,
+                    double* out);
+  void restrict64(int level, const double* x, double* xc, int nb);
+  void probe_quad(int level, uint64_t seed, uint64_t stream, uint64_t first, int nb,
+                  const double* y, c64* out);
   hipEvent_t event();
   void collect_timing();
   template <typename T, typename F>
@@ -148,6 +194,17 @@ class Context {
 
   Work<float> w32_;
   Work<double> w64_;
+  Work<c32> wc32_;
+  Work<c64> wc64_;
+  Fgmres<c32> fg32_;
+  Fgmres<c64> fg64_;
+  bool complex_ = false;
+  int m_ = 16;                    // FGMRES restart length
+  double omega_ = 1.0;            // coarse-correction scaling in use
+  // FGMRES scalars: Hessenberg, rotations, rhs, solution, dims, cycle flags
+  c64 *gH_ = nullptr, *gcs_ = nullptr, *gsn_ = nullptr, *gg_ = nullptr, *gy_ = nullptr;
+  c64* ghcol_ = nullptr;
+  int *gdims_ = nullptr, *gstart_ = nullptr;
   double* ainv_mlmc_ = nullptr;   // inverse of A_L (row-major), if L < L_s
   double* ainv_solver_ = nullptr; // inverse of A_{L_s} (row-major)
   c64 coarse_trace_ = {0, 0};

@@ -1,0 +1,343 @@
+// Complex lattice operators: the Wilson-like 2-spin operator and its
+// test-vector aggregation hierarchy (Example 4.3), a V-cycle with red-black
+// block Gauss-Seidel smoothing, and batched flexible GMRES inside FP64
+// iterative refinement (each restart cycle is one refinement step).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <type_traits>
+
+#include "context.h"
+
+namespace mlmc {
+
+template <> const c32* Context::links<c32>(int l) const { return lv_[l - 1].U32; }
+template <> const c64* Context::links<c64>(int l) const { return lv_[l - 1].U64; }
+template <> const c32* Context::blocks<c32>(int l) const { return lv_[l - 1].B32; }
+template <> const c64* Context::blocks<c64>(int l) const { return lv_[l - 1].B64; }
+template <> const c32* Context::dinv<c32>(int l) const { return lv_[l - 1].Dinv32; }
+template <> const c64* Context::dinv<c64>(int l) const { return lv_[l - 1].Dinv64; }
+template <> const c32* Context::qmat<c32>(int l) const { return lv_[l - 1].q32; }
+template <> const c64* Context::qmat<c64>(int l) const { return lv_[l - 1].q64; }
+template <> Work<c32>& Context::work<c32>() { return wc32_; }
+template <> Work<c64>& Context::work<c64>() { return wc64_; }
+template <> Fgmres<c32>& Context::fg<c32>() { return fg32_; }
+template <> Fgmres<c64>& Context::fg<c64>() { return fg64_; }
+
+// ---------------------------------------------------------------------------
+// setup (Example 4.3 aggregation sketch): on each level, n_vec Z4 start
+// vectors (Philox stream 2, sample j, this level) are smoothed by
+// `setup_sweeps` red-black block Gauss-Seidel sweeps on A v = 0 (FP64), then
+// orthonormalised per aggregate of block x block sites (modified Gram-Schmidt:
+// R with a positive real diagonal); the Galerkin product P^H A P gives the next
+// level's 5-point block stencil.  The coarsest level is inverted densely.
+// ---------------------------------------------------------------------------
+void Context::build_wilson(const double* theta) {
+  const int N = op_.n_side, blk = h_.block, nv = h_.n_vec;
+  MLMC_REQUIRE(theta != nullptr, MLMC_EINVAL, "WILSON2D needs the link phases (field)");
+  MLMC_REQUIRE(N >= 2 && blk >= 2, MLMC_EINVAL, "bad lattice or aggregate size");
+  MLMC_REQUIRE(nv == 2 || nv == 4 || nv == 8 || nv == 12 || nv == 16, MLMC_EUNSUPPORTED,
+               "n_vec must be one of 2, 4, 8, 12, 16");
+  MLMC_REQUIRE(h_.setup_sweeps >= 0, MLMC_EINVAL, "setup_sweeps must be >= 0");
+  MLMC_REQUIRE(opt_.krylov_restart >= 1 && opt_.krylov_restart <= 32, MLMC_EINVAL,
+               "krylov_restart must be in [1, 32]");
+  m_ = opt_.krylov_restart;
+  const double diag = op_.mass + 2.0;
+  lv_.resize(Ls_);
+  int side = N;
+  for (int l = 0; l < Ls_; ++l) {
+    if (l > 0) {
+      MLMC_REQUIRE(side % blk == 0, MLMC_EINVAL,
+                   "lattice side not divisible by the aggregate side at level " +
+                       std::to_string(l));
+      side /= blk;
+    }
+    Level& L = lv_[l];
+    L.index = l + 1;
+    L.side = side;
+    L.dof = l == 0 ? 2 : nv;
+    L.n = (int64_t)side * side * L.dof;
+    L.wilson = (l == 0);
+    L.blk = blk;
+    if (l < Ls_ - 1)
+      MLMC_REQUIRE(side % 2 == 0, MLMC_EINVAL,
+                   "smoothed levels need an even lattice side (red-black colouring)");
+  }
+  MLMC_REQUIRE(lv_[Ls_ - 1].n <= 16384, MLMC_EINVAL, "coarsest level too large (n > 16384)");
+  alloc_common();
+  const int64_t n1 = lv_[0].n;
+
+  // links
+  double* th = dalloc_n<double>(2 * (int64_t)N * N);
+  MLMC_HIP(hipMemcpyAsync(th, theta, sizeof(double) * 2 * N * N, hipMemcpyHostToDevice, s_));
+  lv_[0].U64 = dalloc_n<c64>(2 * (int64_t)N * N);
+  lv_[0].U32 = dalloc_n<c32>(2 * (int64_t)N * N);
+  wilson_links(th, lv_[0].U64, lv_[0].U32, N, s_);
+
+  // hierarchy
+  for (int l = 1; l < Ls_; ++l) {
+    Level& F = lv_[l - 1];
+    Level& C = lv_[l];
+    c64* V = dalloc_n<c64>(F.n * nv);
+    c64* zero = dalloc_n<c64>(F.n * nv);
+    vec_zero<c64>(zero, F.n, nv, nullptr, s_);
+    probes_write<c64>(V, F.n, nv, h_.setup_seed, 0, 0, (uint64_t)l, 2, s_);
+    for (int sw = 0; sw < h_.setup_sweeps; ++sw) {
+      if (F.wilson)
+        wilson_rbgs<c64>(zero, V, F.U64, F.side, diag, nv, nullptr, false, false, s_);
+      else
+        bsr_rbgs<c64>(zero, V, F.B64, F.Dinv64, F.side, F.dof, nv, nullptr, false, false, s_);
+    }
+    F.q64 = dalloc_n<c64>(F.n * nv);
+    F.q32 = dalloc_n<c32>(F.n * nv);
+    agg_orthonormalise(V, F.q64, F.side, F.dof, blk, nv, s_);
+    vec_convert<c32, c64>(F.q64, F.q32, F.n * nv, 1, nullptr, s_);
+    const int64_t nsc = (int64_t)C.side * C.side;
+    C.B64 = dalloc_n<c64>(nsc * 5 * nv * nv);
+    C.B32 = dalloc_n<c32>(nsc * 5 * nv * nv);
+    galerkin_blocks(F.wilson ? nullptr : F.B64, F.U64, diag, F.q64, F.side, F.dof, blk, nv, C.B64,
+                    s_);
+    vec_convert<c32, c64>(C.B64, C.B32, nsc * 5 * nv * nv, 1, nullptr, s_);
+    C.Dinv64 = dalloc_n<c64>(nsc * nv * nv);
+    C.Dinv32 = dalloc_n<c32>(nsc * nv * nv);
+    block_diag_inverse(C.B64, C.Dinv64, C.Dinv32, (int)nsc, nv, s_);
+  }
+
+  // work buffers
+  auto alloc_cwork = [&](auto& w) {
+    using T = std::remove_pointer_t<decltype(w.x)>;
+    w.vb.assign(Ls_, nullptr);
+    w.vx.assign(Ls_, nullptr);
+    w.vt.assign(Ls_, nullptr);
+    for (int m = 0; m < Ls_; ++m) {
+      if (m > 0) {
+        w.vb[m] = dalloc_n<T>(lv_[m].n * nb_);
+        w.vx[m] = dalloc_n<T>(lv_[m].n * nb_);
+      }
+      w.vt[m] = dalloc_n<T>(lv_[m].n * nb_);
+    }
+  };
+  auto alloc_fg = [&](auto& f) {
+    using T = std::remove_pointer_t<decltype(f.V)>;
+    f.V = dalloc_n<T>(n1 * nb_ * (m_ + 1));
+    f.Z = dalloc_n<T>(n1 * nb_ * m_);
+    f.r = dalloc_n<T>(n1 * nb_);
+    f.d = dalloc_n<T>(n1 * nb_);
+  };
+  alloc_cwork(wc64_);
+  alloc_fg(fg64_);
+  if (opt_.precision == MLMC_FP32_IR64) {
+    alloc_cwork(wc32_);
+    alloc_fg(fg32_);
+  }
+  gH_ = dalloc_n<c64>((int64_t)nb_ * (m_ + 1) * m_);
+  gcs_ = dalloc_n<c64>((int64_t)nb_ * m_);
+  gsn_ = dalloc_n<c64>((int64_t)nb_ * m_);
+  gg_ = dalloc_n<c64>((int64_t)nb_ * (m_ + 1));
+  gy_ = dalloc_n<c64>((int64_t)nb_ * m_);
+  ghcol_ = dalloc_n<c64>((int64_t)nb_ * (m_ + 1));
+  gdims_ = dalloc_n<int>(nb_);
+  gstart_ = dalloc_n<int>(nb_);
+
+  // coarsest inverses (complex FP64), direct trace term (Remark 4.2)
+  auto invert = [&](int level, c64** inv_out, c64* tr) {
+    const Level& L = lv_[level - 1];
+    const int n = (int)L.n;
+    c64* aug = dalloc_n<c64>(2 * (int64_t)n * n);
+    c64* rowbuf = dalloc_n<c64>(2 * (int64_t)n);
+    c64* colbuf = dalloc_n<c64>(n);
+    dense_from_stencil(L.wilson ? nullptr : L.B64, L.U64, diag, L.side, L.dof, aug, s_);
+    dense_set_identity_right<c64>(aug, n, s_);
+    dense_invert<c64>(aug, n, rowbuf, colbuf, piv_, s_);
+    c64* inv = dalloc_n<c64>((int64_t)n * n);
+    dense_extract_right<c64>(aug, n, inv, s_);
+    dense_trace<c64>(inv, n, scal_[kTmp], s_);
+    MLMC_HIP(hipMemcpyAsync(host_c64_, scal_[kTmp], sizeof(c64), hipMemcpyDeviceToHost, s_));
+    MLMC_HIP(hipStreamSynchronize(s_));
+    *tr = host_c64_[0];
+    *inv_out = inv;
+  };
+  c64* inv_s = nullptr;
+  c64 tr_s;
+  invert(Ls_, &inv_s, &tr_s);
+  const int ns = (int)lv_[Ls_ - 1].n;
+  wc64_.ainvT = dalloc_n<c64>((int64_t)ns * ns);
+  dense_transpose<c64>(inv_s, wc64_.ainvT, ns, s_);
+  if (opt_.precision == MLMC_FP32_IR64) {
+    wc32_.ainvT = dalloc_n<c32>((int64_t)ns * ns);
+    vec_convert<c32, c64>(wc64_.ainvT, wc32_.ainvT, (int64_t)ns * ns, 1, nullptr, s_);
+  }
+  if (L_ == Ls_) {
+    coarse_trace_ = tr_s;
+  } else {
+    c64* inv_m = nullptr;
+    invert(L_, &inv_m, &coarse_trace_);
+  }
+  MLMC_HIP(hipStreamSynchronize(s_));
+  MLMC_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// operator pieces
+// ---------------------------------------------------------------------------
+template <typename Tb, typename T, typename Tr>
+void Context::cop_residual(int l, const Tb* b, const T* x, Tr* r, int nb, const int* act,
+                           c64* partials) {
+  const Level& L = lv_[l - 1];
+  if (L.wilson)
+    wilson_residual<Tb, T, Tr>(b, x, r, links<T>(l), L.side, op_.mass + 2.0, nb, act, partials,
+                               s_);
+  else
+    bsr_residual<Tb, T, Tr>(b, x, r, blocks<T>(l), L.side, L.dof, nb, act, partials, s_);
+}
+
+template <typename T>
+void Context::cop_smooth(int l, const T* b, T* x, int nb, const int* act, bool zero_init,
+                         bool reverse) {
+  const Level& L = lv_[l - 1];
+  if (L.wilson)
+    wilson_rbgs<T>(b, x, links<T>(l), L.side, op_.mass + 2.0, nb, act, zero_init, reverse, s_);
+  else
+    bsr_rbgs<T>(b, x, blocks<T>(l), dinv<T>(l), L.side, L.dof, nb, act, zero_init, reverse, s_);
+}
+
+template <typename T>
+void Context::cop_restrict(int l, const T* x, T* xc, int nb, const int* act) {
+  const Level& L = lv_[l - 1];
+  agg_restrict<T>(x, xc, qmat<T>(l), L.side, L.dof, L.blk, lv_[l].dof, nb, act, s_);
+}
+
+template <typename T>
+void Context::cop_prolong(int l, const T* ec, T* x, int nb, const int* act, double omega,
+                          double beta) {
+  const Level& L = lv_[l - 1];
+  agg_prolong<T>(ec, x, qmat<T>(l), L.side, L.dof, L.blk, lv_[l].dof, omega, beta, nb, act, s_);
+}
+
+// V-cycle on levels l..L_s: x = M b (pre-smoothing from zero, residual,
+// restriction, recursion, prolongation with omega, post-smoothing in the
+// reverse colour order)
+template <typename T>
+void Context::cvcycle(int l, const T* b, T* x, int nb, const int* act) {
+  Work<T>& w = work<T>();
+  const int64_t n = lv_[l - 1].n;
+  if (l == 1) counters[2] += 1;
+  if (l == Ls_) {
+    dense_apply<T>(w.ainvT, b, x, (int)n, nb, act, s_);
+    return;
+  }
+  const int pre = opt_.nu_pre, post = opt_.nu_post;
+  if (pre == 0) vec_zero<T>(x, n, nb, act, s_);
+  for (int i = 0; i < pre; ++i) cop_smooth<T>(l, b, x, nb, act, i == 0, false);
+  T* res = w.vt[l - 1];
+  cop_residual<T, T, T>(l, b, x, res, nb, act, nullptr);
+  cop_restrict<T>(l, res, w.vb[l], nb, act);
+  cvcycle<T>(l + 1, w.vb[l], w.vx[l], nb, act);
+  cop_prolong<T>(l, w.vx[l], x, nb, act, omega_, 1.0);
+  for (int i = 0; i < post; ++i) cop_smooth<T>(l, b, x, nb, act, false, true);
+}
+
+// ---------------------------------------------------------------------------
+// one cycle of right-preconditioned flexible GMRES(m) for A d = r, columns in
+// lockstep (classical Gram-Schmidt; Givens rotations per column on the
+// device).  act (in/out): columns to solve; a column stops at relative
+// residual estimate tol.  d receives the correction for every column that was
+// active on entry.
+// ---------------------------------------------------------------------------
+template <typename T>
+void Context::fgmres_cycle(int l, const T* r, T* d, int nb, int* act, double tol) {
+  Fgmres<T>& f = fg<T>();
+  const int64_t n = lv_[l - 1].n;
+  const int64_t vs = n * nb;  // stride between basis vectors
+  const int nblk = reduce_blocks(n);
+  c64 *beta2 = scal_[kRr0], *wn2 = scal_[kTmp];
+  MLMC_HIP(hipMemcpyAsync(gstart_, act, sizeof(int) * nb, hipMemcpyDeviceToDevice, s_));
+  vec_dot_partials<T>(r, r, n, nb, act, partials_, s_);
+  finish_sums(partials_, nblk, nb, beta2, s_);
+  vec_scale_inv_norm<T>(f.V, r, beta2, n, nb, act, s_);
+  givens_init(gH_, gcs_, gsn_, gg_, gdims_, beta2, act, m_, nb, s_);
+  for (int j = 0; j < m_; ++j) {
+    T* vj = f.V + j * vs;
+    T* zj = f.Z + j * vs;
+    T* w = f.V + (j + 1) * vs;
+    cvcycle<T>(l, vj, zj, nb, act);
+    cop_residual<T, T, T>(l, (const T*)nullptr, zj, w, nb, act, nullptr);
+    int mb = 0;
+    krylov_mdot<T>(f.V, vs, j + 1, w, n, nb, act, partials_, &mb, s_);
+    finish_sums(partials_, mb, nb * (j + 1), ghcol_, s_);
+    krylov_maxpy<T>(f.V, vs, j + 1, ghcol_, w, n, nb, act, s_);
+    vec_dot_partials<T>(w, w, n, nb, act, partials_, s_);
+    finish_sums(partials_, nblk, nb, wn2, s_);
+    vec_scale_inv_norm<T>(w, w, wn2, n, nb, act, s_);
+    givens_step(gH_, gcs_, gsn_, gg_, gdims_, ghcol_, wn2, beta2, tol, j, m_, act, nb,
+                count_dev_, s_);
+    counters[0] += 1;
+    if (read_count() == 0) break;
+  }
+  givens_solve(gH_, gcs_, gsn_, gg_, gdims_, gy_, gstart_, m_, nb, s_);
+  krylov_combine<T>(f.Z, vs, gy_, m_, gdims_, d, n, nb, gstart_, s_);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 solve of a complex level: refinement loop y += d with d from one
+// FGMRES cycle on the current FP64 residual (in complex64 for
+// MLMC_FP32_IR64, complex128 for MLMC_FP64).  Converged when the FP64
+// residual meets solve_tol.  err: stated error contribution per column (the
+// last correction's |b^H d| scaled by the residual reduction it achieved).
+// ---------------------------------------------------------------------------
+void Context::solve_complex(int l, const c64* b, c64* y, int nb, c64* err) {
+  const Level& L = lv_[l - 1];
+  const int64_t n = L.n;
+  const int nblk = reduce_blocks(n);
+  const int rblk = L.wilson ? wilson_residual_blocks(L.side) : bsr_residual_blocks(L.side);
+  c64 *bb = scal_[kBb], *bd = scal_[kBd], *rr_old = scal_[kRres], *rr_new = scal_[kRres2];
+  const double tol = opt_.solve_tol;
+  vec_dot_partials<c64>(b, b, n, nb, nullptr, partials_, s_);
+  finish_sums(partials_, nblk, nb, bb, s_);
+  set_all_active(act_outer_, nb, s_);
+  vec_zero<c64>(err, 1, nb, nullptr, s_);
+  if (l == Ls_) {
+    dense_apply<c64>(wc64_.ainvT, b, y, (int)n, nb, nullptr, s_);
+    return;
+  }
+  vec_zero<c64>(y, n, nb, nullptr, s_);
+  vec_copy<c64>(bb, rr_old, 1, nb, nullptr, s_);
+  c64* res64 = reinterpret_cast<c64*>(r64_);
+  const bool fp32 = opt_.precision == MLMC_FP32_IR64;
+  const double inner = fp32 ? std::max(opt_.inner_tol, 1e-6) : std::max(opt_.inner_tol, 1e-12);
+  bool have_corr = false;
+  for (int it = 0; it <= opt_.max_refine * 4; ++it) {
+    // FP64 residual of the current iterate
+    if (fp32)
+      cop_residual<c64, c64, c32>(l, b, y, fg32_.r, nb, act_outer_, partials_);
+    else
+      cop_residual<c64, c64, c64>(l, b, y, fg64_.r, nb, act_outer_, partials_);
+    finish_sums(partials_, rblk, nb, rr_new, s_);
+    if (have_corr) ir_stated_error(bd, rr_old, rr_new, act_outer_, err, nb, s_);
+    select_active(rr_old, rr_new, act_outer_, nb, s_);
+    mark_converged(rr_new, bb, tol * tol, act_outer_, nb, count_dev_, s_);
+    counters[1] += 1;
+    if (read_count() == 0) break;
+    MLMC_HIP(hipMemcpyAsync(act_inner_, act_outer_, sizeof(int) * nb, hipMemcpyDeviceToDevice,
+                            s_));
+    if (fp32) {
+      fgmres_cycle<c32>(l, fg32_.r, fg32_.d, nb, act_inner_, inner);
+      ir_accumulate<c64, c32>(y, fg32_.d, n, nb, act_outer_, s_);
+      vec_convert<c64, c32>(fg32_.d, res64, n, nb, act_outer_, s_);
+    } else {
+      fgmres_cycle<c64>(l, fg64_.r, fg64_.d, nb, act_inner_, inner);
+      ir_accumulate<c64, c64>(y, fg64_.d, n, nb, act_outer_, s_);
+      vec_copy<c64>(fg64_.d, res64, n, nb, act_outer_, s_);
+    }
+    vec_dot_partials<c64>(b, res64, n, nb, act_outer_, partials_, s_);
+    finish_sums(partials_, nblk, nb, bd, s_);
+    have_corr = true;
+  }
+}
+
+template void Context::cop_residual<c64, c64, c64>(int, const c64*, const c64*, c64*, int,
+                                                   const int*, c64*);
+template void Context::cop_restrict<c64>(int, const c64*, c64*, int, const int*);
+template void Context::cop_prolong<c64>(int, const c64*, c64*, int, const int*, double, double);
+
+}  // namespace mlmc

@@ -144,4 +144,55 @@ template <typename T>
 void agg2d_prolong(const T* ec, T* x, int N, double omega, double beta, int nb,
                    const int* active, hipStream_t s);
 
+// ----- complex lattice operators (Wilson 2-spin, block stencils, transfers) ---
+int wilson_residual_blocks(int N);
+int bsr_residual_blocks(int Nc);
+// r = b - D x ; b == nullptr: r = D x (partials then of conj(x)^T r)
+template <typename Tb, typename T, typename Tr>
+void wilson_residual(const Tb* b, const T* x, Tr* r, const T* U, int N, double diag, int nb,
+                     const int* active, c64* partials, hipStream_t s);
+template <typename T>
+void wilson_rbgs(const T* b, T* x, const T* U, int N, double diag, int nb, const int* active,
+                 bool zero_init, bool reverse, hipStream_t s);
+template <typename Tb, typename T, typename Tr>
+void bsr_residual(const Tb* b, const T* x, Tr* r, const T* B, int Nc, int dof, int nb,
+                  const int* active, c64* partials, hipStream_t s);
+template <typename T>
+void bsr_rbgs(const T* b, T* x, const T* B, const T* Dinv, int Nc, int dof, int nb,
+              const int* active, bool zero_init, bool reverse, hipStream_t s);
+template <typename T>
+void agg_restrict(const T* x, T* xc, const T* q, int Nf, int dofF, int blk, int dofC, int nb,
+                  const int* active, hipStream_t s);
+template <typename T>
+void agg_prolong(const T* xc, T* x, const T* q, int Nf, int dofF, int blk, int dofC,
+                 double omega, double beta, int nb, const int* active, hipStream_t s);
+void wilson_links(const double* theta, c64* U64, c32* U32, int N, hipStream_t s);
+void agg_orthonormalise(const c64* V, c64* q, int Nf, int dofF, int blk, int nv, hipStream_t s);
+void galerkin_blocks(const c64* Bf, const c64* U, double wdiag, const c64* q, int Nf, int dofF,
+                     int blk, int nv, c64* Bc, hipStream_t s);
+void dense_from_stencil(const c64* Bf, const c64* U, double wdiag, int Nf, int dof, c64* aug,
+                        hipStream_t s);
+void block_diag_inverse(const c64* B, c64* Dinv64, c32* Dinv32, int ns, int dof, hipStream_t s);
+
+// ----- batched flexible GMRES helpers ------------------------------------------
+template <typename T>
+void krylov_mdot(const T* V, int64_t vstride, int nv, const T* w, int64_t n, int nb,
+                 const int* active, c64* partials, int* nblk_out, hipStream_t s);
+template <typename T>
+void krylov_maxpy(const T* V, int64_t vstride, int nv, const c64* h, T* w, int64_t n, int nb,
+                  const int* active, hipStream_t s);
+template <typename T>
+void krylov_combine(const T* Z, int64_t vstride, const c64* y, int ldy, const int* dims, T* d,
+                    int64_t n, int nb, const int* start, hipStream_t s);
+template <typename T>
+void vec_scale_inv_norm(T* dst, const T* src, const c64* nrm2, int64_t n, int nb,
+                        const int* active, hipStream_t s);
+void givens_init(c64* H, c64* cs, c64* sn, c64* g, int* dims, const c64* beta2,
+                 const int* active, int m, int nb, hipStream_t s);
+void givens_step(c64* H, c64* cs, c64* sn, c64* g, int* dims, const c64* h, const c64* wn2,
+                 const c64* beta2, double tol, int j, int m, int* active, int nb, int* count,
+                 hipStream_t s);
+void givens_solve(c64* H, c64* cs, c64* sn, c64* g, int* dims, c64* y, const int* start, int m,
+                  int nb, hipStream_t s);
+
 }  // namespace mlmc

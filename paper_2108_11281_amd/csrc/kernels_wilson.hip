@@ -1,0 +1,665 @@
+// Kernels of the complex lattice operators:
+//  * the Wilson-like 2-spin U(1) operator on an N x N periodic lattice,
+//      D = (m0+2) I - 1/2 sum_mu [(I - s_mu) U_mu(x) d_{x+mu} + (I + s_mu) U_mu(x-mu)^* d_{x-mu}]
+//    with s_1 = [[0,1],[1,0]], s_2 = [[0,i],[-i,0]] (Example 4.3, halved, m0 = m/2),
+//    site s = y*N + x, unknown 2*s + spin;
+//  * coarse operators of test-vector aggregation: 5-point block stencils with
+//    dof x dof complex blocks per site and direction (0 self, 1 +x, 2 -x,
+//    3 +y, 4 -y), site S = Y*Nc + X, unknown S*dof + j;
+//  * the aggregation transfers: P maps a coarse site's dof_c coefficients to
+//    the b x b fine sites of its aggregate through per-unknown rows q[i][j].
+// Vectors are RHS-major blocks (column k of length n at k*n).
+#include "kernels.h"
+
+namespace mlmc {
+namespace {
+
+template <typename T> using R_t = typename Traits<T>::real;
+
+__host__ __device__ __forceinline__ c32 mk(float re, float im) { return {re, im}; }
+__host__ __device__ __forceinline__ c64 mk(double re, double im) { return {re, im}; }
+template <typename T> __device__ __forceinline__ T times_i(T a) { return mk(-a.im, a.re); }
+template <typename T> __device__ __forceinline__ T cmul_conj(T u, T a) {  // conj(u) * a
+  return mk(u.re * a.re + u.im * a.im, u.re * a.im - u.im * a.re);
+}
+
+// hop term H x at site s (the sum in D = (m0+2) I - H/2), 2 spins
+template <typename T>
+__device__ __forceinline__ void wilson_hop(const T* __restrict__ x, const T* __restrict__ U, int N,
+                                           int sx, int sy, T& h0, T& h1) {
+  const int n2 = N * N;
+  const int xp = sx + 1 == N ? 0 : sx + 1, xm = sx == 0 ? N - 1 : sx - 1;
+  const int yp = sy + 1 == N ? 0 : sy + 1, ym = sy == 0 ? N - 1 : sy - 1;
+  const int s = sy * N + sx;
+  // +x: (I - s1) U_0(s) x_{s+x}
+  {
+    const int t = sy * N + xp;
+    const T u = U[s];
+    const T a0 = u * x[2 * t], a1 = u * x[2 * t + 1];
+    h0 = a0 - a1;
+    h1 = a1 - a0;
+  }
+  // -x: (I + s1) conj(U_0(s-x)) x_{s-x}
+  {
+    const int t = sy * N + xm;
+    const T u = U[t];
+    const T a0 = cmul_conj(u, x[2 * t]), a1 = cmul_conj(u, x[2 * t + 1]);
+    h0 += a0 + a1;
+    h1 += a1 + a0;
+  }
+  // +y: (I - s2) U_1(s) x_{s+y};  (I - s2) v = (v0 - i v1, v1 + i v0)
+  {
+    const int t = yp * N + sx;
+    const T u = U[n2 + s];
+    const T a0 = u * x[2 * t], a1 = u * x[2 * t + 1];
+    h0 += a0 - times_i(a1);
+    h1 += a1 + times_i(a0);
+  }
+  // -y: (I + s2) conj(U_1(s-y)) x_{s-y};  (I + s2) v = (v0 + i v1, v1 - i v0)
+  {
+    const int t = ym * N + sx;
+    const T u = U[n2 + t];
+    const T a0 = cmul_conj(u, x[2 * t]), a1 = cmul_conj(u, x[2 * t + 1]);
+    h0 += a0 + times_i(a1);
+    h1 += a1 - times_i(a0);
+  }
+}
+
+// r = b - D x (or y = D x when b == nullptr); one thread per (site, column);
+// optional partials of |r|^2 (or conj(x)^T y)
+template <typename Tb, typename T, typename Tr>
+__global__ __launch_bounds__(kThreads) void k_wilson_residual(const Tb* __restrict__ b,
+                                                              const T* __restrict__ x,
+                                                              Tr* __restrict__ r,
+                                                              const T* __restrict__ U, int N,
+                                                              R_t<T> diag, const int* active,
+                                                              c64* partials) {
+  __shared__ double red[16];
+  const int k = blockIdx.y;
+  if (active && !active[k]) return;
+  const int n2 = N * N;
+  const int s = blockIdx.x * kThreads + threadIdx.x;
+  const int64_t off = (int64_t)k * 2 * n2;
+  double dre = 0.0, dim = 0.0;
+  if (s < n2) {
+    const int sy = s / N, sx = s - sy * N;
+    T h0, h1;
+    wilson_hop(x + off, U, N, sx, sy, h0, h1);
+    const T x0 = x[off + 2 * s], x1 = x[off + 2 * s + 1];
+    const R_t<T> half = (R_t<T>)0.5;
+    T v0 = diag * x0 - half * h0, v1 = diag * x1 - half * h1;
+    if (b) {
+      v0 = convert<T, Tb>(b[off + 2 * s]) - v0;
+      v1 = convert<T, Tb>(b[off + 2 * s + 1]) - v1;
+      cdot_acc(dre, dim, v0, v0);
+      cdot_acc(dre, dim, v1, v1);
+    } else {
+      cdot_acc(dre, dim, x0, v0);
+      cdot_acc(dre, dim, x1, v1);
+    }
+    r[off + 2 * s] = convert<Tr, T>(v0);
+    r[off + 2 * s + 1] = convert<Tr, T>(v1);
+  }
+  if (partials) {
+    block_sum2<kThreads>(dre, dim, red);
+    if (threadIdx.x == 0) partials[(int64_t)k * gridDim.x + blockIdx.x] = {dre, dim};
+  }
+}
+
+// one colour of a red-black site Gauss-Seidel sweep: x_s = (b_s + H x / 2)/diag
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_wilson_gs(const T* __restrict__ b, T* __restrict__ x,
+                                                        const T* __restrict__ U, int N,
+                                                        R_t<T> dinv, int colour, int zero_nbrs,
+                                                        const int* active) {
+  const int k = blockIdx.y;
+  if (active && !active[k]) return;
+  const int n2 = N * N;
+  const int s = blockIdx.x * kThreads + threadIdx.x;
+  if (s >= n2) return;
+  const int sy = s / N, sx = s - sy * N;
+  if (((sx + sy) & 1) != colour) return;
+  const int64_t off = (int64_t)k * 2 * n2;
+  T v0 = b[off + 2 * s], v1 = b[off + 2 * s + 1];
+  if (!zero_nbrs) {
+    T h0, h1;
+    wilson_hop(x + off, U, N, sx, sy, h0, h1);
+    const R_t<T> half = (R_t<T>)0.5;
+    v0 += half * h0;
+    v1 += half * h1;
+  }
+  x[off + 2 * s] = dinv * v0;
+  x[off + 2 * s + 1] = dinv * v1;
+}
+
+// ---- 5-point block stencils (coarse operators) ------------------------------
+__device__ __forceinline__ int nbr_site(int S, int d, int Nc) {
+  const int Y = S / Nc, X = S - Y * Nc;
+  switch (d) {
+    case 1: return Y * Nc + (X + 1 == Nc ? 0 : X + 1);
+    case 2: return Y * Nc + (X == 0 ? Nc - 1 : X - 1);
+    case 3: return (Y + 1 == Nc ? 0 : Y + 1) * Nc + X;
+    case 4: return (Y == 0 ? Nc - 1 : Y - 1) * Nc + X;
+    default: return S;
+  }
+}
+
+// r = b - A x (b == nullptr: r = A x); one thread per (site, column) computing
+// its DOF outputs; blocks [site][5][DOF][DOF]
+template <int DOF, typename Tb, typename T, typename Tr>
+__global__ __launch_bounds__(kThreads) void k_bsr_residual(const Tb* __restrict__ b,
+                                                           const T* __restrict__ x,
+                                                           Tr* __restrict__ r,
+                                                           const T* __restrict__ B, int Nc,
+                                                           const int* active, c64* partials) {
+  __shared__ double red[16];
+  const int k = blockIdx.y;
+  if (active && !active[k]) return;
+  const int ns = Nc * Nc;
+  const int S = blockIdx.x * kThreads + threadIdx.x;
+  const int64_t off = (int64_t)k * DOF * ns;
+  double dre = 0.0, dim = 0.0;
+  if (S < ns) {
+    T acc[DOF];
+#pragma unroll
+    for (int i = 0; i < DOF; ++i) acc[i] = zero_of(T());
+    for (int d = 0; d < 5; ++d) {
+      const int t = nbr_site(S, d, Nc);
+      const T* blk = B + ((int64_t)S * 5 + d) * DOF * DOF;
+      T xv[DOF];
+#pragma unroll
+      for (int j = 0; j < DOF; ++j) xv[j] = x[off + (int64_t)t * DOF + j];
+#pragma unroll
+      for (int i = 0; i < DOF; ++i)
+#pragma unroll
+        for (int j = 0; j < DOF; ++j) acc[i] += blk[i * DOF + j] * xv[j];
+    }
+#pragma unroll
+    for (int i = 0; i < DOF; ++i) {
+      T v = acc[i];
+      if (b) {
+        v = convert<T, Tb>(b[off + (int64_t)S * DOF + i]) - v;
+        cdot_acc(dre, dim, v, v);
+      } else {
+        cdot_acc(dre, dim, x[off + (int64_t)S * DOF + i], v);
+      }
+      r[off + (int64_t)S * DOF + i] = convert<Tr, T>(v);
+    }
+  }
+  if (partials) {
+    block_sum2<kThreads>(dre, dim, red);
+    if (threadIdx.x == 0) partials[(int64_t)k * gridDim.x + blockIdx.x] = {dre, dim};
+  }
+}
+
+// one colour of a red-black block Gauss-Seidel sweep:
+// x_S = Dinv_S (b_S - sum_{d != self} B[S][d] x_nbr)
+template <int DOF, typename T>
+__global__ __launch_bounds__(kThreads) void k_bsr_gs(const T* __restrict__ b, T* __restrict__ x,
+                                                     const T* __restrict__ B,
+                                                     const T* __restrict__ Dinv, int Nc,
+                                                     int colour, int zero_nbrs,
+                                                     const int* active) {
+  const int k = blockIdx.y;
+  if (active && !active[k]) return;
+  const int ns = Nc * Nc;
+  const int S = blockIdx.x * kThreads + threadIdx.x;
+  if (S >= ns) return;
+  const int Y = S / Nc, X = S - Y * Nc;
+  if (((X + Y) & 1) != colour) return;
+  const int64_t off = (int64_t)k * DOF * ns;
+  T rhs[DOF];
+#pragma unroll
+  for (int i = 0; i < DOF; ++i) rhs[i] = b[off + (int64_t)S * DOF + i];
+  if (!zero_nbrs) {
+    for (int d = 1; d < 5; ++d) {
+      const int t = nbr_site(S, d, Nc);
+      const T* blk = B + ((int64_t)S * 5 + d) * DOF * DOF;
+      T xv[DOF];
+#pragma unroll
+      for (int j = 0; j < DOF; ++j) xv[j] = x[off + (int64_t)t * DOF + j];
+#pragma unroll
+      for (int i = 0; i < DOF; ++i)
+#pragma unroll
+        for (int j = 0; j < DOF; ++j) rhs[i] -= blk[i * DOF + j] * xv[j];
+    }
+  }
+  const T* di = Dinv + (int64_t)S * DOF * DOF;
+#pragma unroll
+  for (int i = 0; i < DOF; ++i) {
+    T v = zero_of(T());
+#pragma unroll
+    for (int j = 0; j < DOF; ++j) v += di[i * DOF + j] * rhs[j];
+    x[off + (int64_t)S * DOF + i] = v;
+  }
+}
+
+// ---- aggregation transfers --------------------------------------------------
+// fine lattice Nf x Nf with dofF unknowns per site, aggregates of blk x blk
+// sites, dofC coarse unknowns per coarse site; q[i][j] (i fine unknown).
+
+// xc = P^H x ; one thread per (coarse site, column)
+template <int DOFC, typename T>
+__global__ __launch_bounds__(kThreads) void k_agg_restrict(const T* __restrict__ x,
+                                                           T* __restrict__ xc,
+                                                           const T* __restrict__ q, int Nf,
+                                                           int dofF, int blk,
+                                                           const int* active) {
+  const int k = blockIdx.y;
+  if (active && !active[k]) return;
+  const int Nc = Nf / blk, nsc = Nc * Nc;
+  const int S = blockIdx.x * kThreads + threadIdx.x;
+  if (S >= nsc) return;
+  const int Y = S / Nc, X = S - Y * Nc;
+  const int64_t nf = (int64_t)Nf * Nf * dofF;
+  const T* xk = x + (int64_t)k * nf;
+  T acc[DOFC];
+#pragma unroll
+  for (int j = 0; j < DOFC; ++j) acc[j] = zero_of(T());
+  for (int yy = 0; yy < blk; ++yy)
+    for (int xx = 0; xx < blk; ++xx) {
+      const int s = (Y * blk + yy) * Nf + (X * blk + xx);
+      for (int a = 0; a < dofF; ++a) {
+        const int64_t i = (int64_t)s * dofF + a;
+        const T v = xk[i];
+        const T* qi = q + i * DOFC;
+#pragma unroll
+        for (int j = 0; j < DOFC; ++j) acc[j] += cmul_conj(qi[j], v);
+      }
+    }
+#pragma unroll
+  for (int j = 0; j < DOFC; ++j) xc[(int64_t)k * nsc * DOFC + (int64_t)S * DOFC + j] = acc[j];
+}
+
+// x = beta * x + omega * P xc ; one thread per (fine unknown, column)
+template <int DOFC, typename T>
+__global__ __launch_bounds__(kThreads) void k_agg_prolong(const T* __restrict__ xc, T* __restrict__ x,
+                                                          const T* __restrict__ q, int Nf,
+                                                          int dofF, int blk, R_t<T> omega,
+                                                          R_t<T> beta, const int* active) {
+  const int k = blockIdx.y;
+  if (active && !active[k]) return;
+  const int Nc = Nf / blk;
+  const int64_t nf = (int64_t)Nf * Nf * dofF;
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= nf) return;
+  const int s = (int)(i / dofF);
+  const int sy = s / Nf, sx = s - sy * Nf;
+  const int S = (sy / blk) * Nc + (sx / blk);
+  const T* e = xc + (int64_t)k * Nc * Nc * DOFC + (int64_t)S * DOFC;
+  const T* qi = q + i * DOFC;
+  T v = zero_of(T());
+#pragma unroll
+  for (int j = 0; j < DOFC; ++j) v += qi[j] * e[j];
+  T* xk = x + (int64_t)k * nf;
+  xk[i] = (beta == (R_t<T>)0) ? omega * v : beta * xk[i] + omega * v;
+}
+
+// ---- setup ---------------------------------------------------------------
+__global__ void k_links(const double* theta, c64* U64, c32* U32, int n) {
+  // n = 2 N^2 link phases
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    double s, c;
+    sincos(theta[i], &s, &c);
+    U64[i] = {c, s};
+    U32[i] = {(float)c, (float)s};
+  }
+}
+
+// per-aggregate modified Gram-Schmidt of the nv test vectors restricted to the
+// aggregate (FP64); V: [nv][n] (vector j at j*n), q out: [n][nv]; one block per
+// aggregate, m = blk*blk*dofF rows
+__global__ __launch_bounds__(kThreads) void k_agg_orthonormalise(const c64* __restrict__ V,
+                                                                 c64* __restrict__ q, int Nf,
+                                                                 int dofF, int blk, int nv) {
+  extern __shared__ c64 sv[];  // m * nv
+  __shared__ double red[16];
+  const int Nc = Nf / blk;
+  const int S = blockIdx.x;
+  const int Y = S / Nc, X = S - Y * Nc;
+  const int m = blk * blk * dofF;
+  const int64_t n = (int64_t)Nf * Nf * dofF;
+  auto row_index = [&](int r) -> int64_t {
+    const int site = r / dofF, a = r - site * dofF;
+    const int yy = site / blk, xx = site - yy * blk;
+    return (int64_t)((Y * blk + yy) * Nf + (X * blk + xx)) * dofF + a;
+  };
+  for (int idx = threadIdx.x; idx < m * nv; idx += kThreads) {
+    const int r = idx / nv, j = idx - r * nv;
+    sv[idx] = V[(int64_t)j * n + row_index(r)];
+  }
+  __syncthreads();
+  for (int j = 0; j < nv; ++j) {
+    // remove the components along the previous (already normalised) columns
+    for (int i = 0; i < j; ++i) {
+      double re = 0.0, im = 0.0;
+      for (int r = threadIdx.x; r < m; r += kThreads)
+        cdot_acc(re, im, sv[r * nv + i], sv[r * nv + j]);
+      block_sum2<kThreads>(re, im, red);
+      __shared__ double proj[2];
+      if (threadIdx.x == 0) {
+        proj[0] = re;
+        proj[1] = im;
+      }
+      __syncthreads();
+      const c64 h = {proj[0], proj[1]};
+      for (int r = threadIdx.x; r < m; r += kThreads) sv[r * nv + j] -= h * sv[r * nv + i];
+      __syncthreads();
+    }
+    double re = 0.0, im = 0.0;
+    for (int r = threadIdx.x; r < m; r += kThreads)
+      cdot_acc(re, im, sv[r * nv + j], sv[r * nv + j]);
+    block_sum2<kThreads>(re, im, red);
+    __shared__ double nrm;
+    if (threadIdx.x == 0) nrm = sqrt(re);
+    __syncthreads();
+    const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    for (int r = threadIdx.x; r < m; r += kThreads) sv[r * nv + j] = inv * sv[r * nv + j];
+    __syncthreads();
+  }
+  for (int idx = threadIdx.x; idx < m * nv; idx += kThreads) {
+    const int r = idx / nv, j = idx - r * nv;
+    q[row_index(r) * nv + j] = sv[idx];
+  }
+}
+
+// Galerkin blocks of the coarse operator, labelled by hop direction.
+// Fine operator given as a block stencil (blocks Bf [site][5][dofF][dofF]) or,
+// when Bf == nullptr, as the Wilson operator (links U, diagonal wdiag).
+// One block per (coarse site S, direction d); output Bc[S][d][nv][nv].
+// A fine hop from site s (in S) in direction d lands in the self block of S if
+// the neighbour stays inside the aggregate without wrapping, otherwise in
+// block d (whose coarse neighbour is nbr_site(S, d)).
+__device__ __forceinline__ void fine_hop_target(int sx, int sy, int d, int Nf, int& tx, int& ty) {
+  tx = sx;
+  ty = sy;
+  if (d == 1) tx = sx + 1 == Nf ? 0 : sx + 1;
+  if (d == 2) tx = sx == 0 ? Nf - 1 : sx - 1;
+  if (d == 3) ty = sy + 1 == Nf ? 0 : sy + 1;
+  if (d == 4) ty = sy == 0 ? Nf - 1 : sy - 1;
+}
+
+// fine block (dofF x dofF) coupling site s to its neighbour in direction d
+__device__ __forceinline__ c64 fine_coupling(const c64* Bf, const c64* U, double wdiag, int Nf,
+                                             int dofF, int s, int d, int a, int bcol) {
+  if (Bf) return Bf[((int64_t)s * 5 + d) * dofF * dofF + a * dofF + bcol];
+  // Wilson: dofF = 2
+  const int n2 = Nf * Nf;
+  const int sy = s / Nf, sx = s - sy * Nf;
+  if (d == 0) return {a == bcol ? wdiag : 0.0, 0.0};
+  // -1/2 (I -+ s_mu) u with u the link factor of the hop
+  c64 u;
+  int t;
+  if (d == 1) u = U[s];
+  else if (d == 2) {
+    t = sy * Nf + (sx == 0 ? Nf - 1 : sx - 1);
+    u = {U[t].re, -U[t].im};
+  } else if (d == 3) u = U[n2 + s];
+  else {
+    t = (sy == 0 ? Nf - 1 : sy - 1) * Nf + sx;
+    u = {U[n2 + t].re, -U[n2 + t].im};
+  }
+  // spin matrices: d=1: I - s1 = [[1,-1],[-1,1]]; d=2: I + s1 = [[1,1],[1,1]];
+  // d=3: I - s2 = [[1,-i],[i,1]]; d=4: I + s2 = [[1,i],[-i,1]]
+  c64 m = {0.0, 0.0};
+  if (a == bcol) m = {1.0, 0.0};
+  else if (d == 1) m = {-1.0, 0.0};
+  else if (d == 2) m = {1.0, 0.0};
+  else if (d == 3) m = (a == 0) ? c64{0.0, -1.0} : c64{0.0, 1.0};
+  else m = (a == 0) ? c64{0.0, 1.0} : c64{0.0, -1.0};
+  return -0.5 * (m * u);
+}
+
+__global__ __launch_bounds__(kThreads) void k_galerkin(const c64* __restrict__ Bf,
+                                                       const c64* __restrict__ U, double wdiag,
+                                                       const c64* __restrict__ q, int Nf,
+                                                       int dofF, int blk, int nv,
+                                                       c64* __restrict__ Bc) {
+  const int Nc = Nf / blk;
+  const int S = blockIdx.x, dc = blockIdx.y;
+  const int Y = S / Nc, X = S - Y * Nc;
+  // each thread accumulates some (i, j) entries of the nv x nv output block
+  for (int e = threadIdx.x; e < nv * nv; e += kThreads) {
+    const int i = e / nv, j = e - i * nv;
+    double re = 0.0, im = 0.0;
+    for (int yy = 0; yy < blk; ++yy)
+      for (int xx = 0; xx < blk; ++xx) {
+        const int sx = X * blk + xx, sy = Y * blk + yy;
+        const int s = sy * Nf + sx;
+        for (int d = 0; d < 5; ++d) {
+          int tx, ty;
+          fine_hop_target(sx, sy, d, Nf, tx, ty);
+          // which coarse block receives this hop
+          int target;
+          if (d == 0) target = 0;
+          else {
+            const bool inside = (d == 1 && xx + 1 < blk) || (d == 2 && xx > 0) ||
+                                (d == 3 && yy + 1 < blk) || (d == 4 && yy > 0);
+            target = inside ? 0 : d;
+          }
+          if (target != dc) continue;
+          const int t = ty * Nf + tx;
+          for (int a = 0; a < dofF; ++a) {
+            const c64 qa = q[((int64_t)s * dofF + a) * nv + i];
+            for (int bcol = 0; bcol < dofF; ++bcol) {
+              const c64 f = fine_coupling(Bf, U, wdiag, Nf, dofF, s, d, a, bcol);
+              const c64 qb = q[((int64_t)t * dofF + bcol) * nv + j];
+              const c64 fq = f * qb;
+              // conj(qa) * f * qb
+              re += qa.re * fq.re + qa.im * fq.im;
+              im += qa.re * fq.im - qa.im * fq.re;
+            }
+          }
+        }
+      }
+    Bc[((int64_t)S * 5 + dc) * nv * nv + e] = {re, im};
+  }
+}
+
+// dense n x n (left half of an n x 2n array) from a block stencil or the
+// Wilson operator; one block per row
+__global__ void k_dense_from_stencil(const c64* __restrict__ Bf, const c64* __restrict__ U,
+                                     double wdiag, int Nf, int dof, c64* __restrict__ M) {
+  const int64_t n = (int64_t)Nf * Nf * dof;
+  const int64_t row = blockIdx.x;
+  const int s = (int)(row / dof), a = (int)(row - (int64_t)s * dof);
+  const int sy = s / Nf, sx = s - sy * Nf;
+  c64* mrow = M + row * 2 * n;
+  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) mrow[j] = {0.0, 0.0};
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int d = 0; d < 5; ++d) {
+      int tx, ty;
+      fine_hop_target(sx, sy, d, Nf, tx, ty);
+      const int t = ty * Nf + tx;
+      for (int bcol = 0; bcol < dof; ++bcol) {
+        const c64 f = fine_coupling(Bf, U, wdiag, Nf, dof, s, d, a, bcol);
+        mrow[(int64_t)t * dof + bcol] += f;
+      }
+    }
+  }
+}
+
+// Dinv[S] = (B[S][0])^{-1} by Gauss-Jordan with partial pivoting in registers
+// of one thread per site (dof <= 16, FP64)
+template <int DOF>
+__global__ void k_block_diag_inverse(const c64* __restrict__ B, c64* __restrict__ Dinv64,
+                                     c32* __restrict__ Dinv32, int ns) {
+  const int S = blockIdx.x * blockDim.x + threadIdx.x;
+  if (S >= ns) return;
+  c64 a[DOF][2 * DOF];
+  for (int i = 0; i < DOF; ++i)
+    for (int j = 0; j < DOF; ++j) {
+      a[i][j] = B[((int64_t)S * 5) * DOF * DOF + i * DOF + j];
+      a[i][DOF + j] = {i == j ? 1.0 : 0.0, 0.0};
+    }
+  for (int c = 0; c < DOF; ++c) {
+    int p = c;
+    double best = abs2_of(a[c][c]);
+    for (int i = c + 1; i < DOF; ++i)
+      if (abs2_of(a[i][c]) > best) {
+        best = abs2_of(a[i][c]);
+        p = i;
+      }
+    if (p != c)
+      for (int j = 0; j < 2 * DOF; ++j) {
+        c64 t = a[c][j];
+        a[c][j] = a[p][j];
+        a[p][j] = t;
+      }
+    const double dd = abs2_of(a[c][c]);
+    const c64 inv = {a[c][c].re / dd, -a[c][c].im / dd};
+    for (int j = 0; j < 2 * DOF; ++j) a[c][j] = inv * a[c][j];
+    for (int i = 0; i < DOF; ++i) {
+      if (i == c) continue;
+      const c64 f = a[i][c];
+      for (int j = 0; j < 2 * DOF; ++j) a[i][j] -= f * a[c][j];
+    }
+  }
+  for (int i = 0; i < DOF; ++i)
+    for (int j = 0; j < DOF; ++j) {
+      Dinv64[(int64_t)S * DOF * DOF + i * DOF + j] = a[i][DOF + j];
+      Dinv32[(int64_t)S * DOF * DOF + i * DOF + j] = {(float)a[i][DOF + j].re,
+                                                     (float)a[i][DOF + j].im};
+    }
+}
+
+inline dim3 grid_sites(int64_t sites, int nb) {
+  return dim3((unsigned)((sites + kThreads - 1) / kThreads), (unsigned)nb);
+}
+
+}  // namespace
+
+int wilson_residual_blocks(int N) { return (N * N + kThreads - 1) / kThreads; }
+int bsr_residual_blocks(int Nc) { return (Nc * Nc + kThreads - 1) / kThreads; }
+
+template <typename Tb, typename T, typename Tr>
+void wilson_residual(const Tb* b, const T* x, Tr* r, const T* U, int N, double diag, int nb,
+                     const int* active, c64* partials, hipStream_t s) {
+  hipLaunchKernelGGL((k_wilson_residual<Tb, T, Tr>), grid_sites((int64_t)N * N, nb),
+                     dim3(kThreads), 0, s, b, x, r, U, N, (R_t<T>)diag, active, partials);
+}
+
+template <typename T>
+void wilson_rbgs(const T* b, T* x, const T* U, int N, double diag, int nb, const int* active,
+                 bool zero_init, bool reverse, hipStream_t s) {
+  const dim3 g = grid_sites((int64_t)N * N, nb);
+  const int first = reverse ? 1 : 0;
+  hipLaunchKernelGGL(k_wilson_gs<T>, g, dim3(kThreads), 0, s, b, x, U, N, (R_t<T>)(1.0 / diag),
+                     first, zero_init ? 1 : 0, active);
+  hipLaunchKernelGGL(k_wilson_gs<T>, g, dim3(kThreads), 0, s, b, x, U, N, (R_t<T>)(1.0 / diag),
+                     1 - first, 0, active);
+}
+
+#define BSR_DISPATCH(DOFV, ...)                                                         \
+  switch (DOFV) {                                                                     \
+    case 2: { constexpr int D = 2; __VA_ARGS__; break; }                              \
+    case 4: { constexpr int D = 4; __VA_ARGS__; break; }                              \
+    case 8: { constexpr int D = 8; __VA_ARGS__; break; }                              \
+    case 12: { constexpr int D = 12; __VA_ARGS__; break; }                            \
+    case 16: { constexpr int D = 16; __VA_ARGS__; break; }                            \
+    default: throw Error(MLMC_EUNSUPPORTED, "unsupported number of dofs per site");   \
+  }
+
+template <typename Tb, typename T, typename Tr>
+void bsr_residual(const Tb* b, const T* x, Tr* r, const T* B, int Nc, int dof, int nb,
+                  const int* active, c64* partials, hipStream_t s) {
+  const dim3 g = grid_sites((int64_t)Nc * Nc, nb);
+  BSR_DISPATCH(dof, hipLaunchKernelGGL((k_bsr_residual<D, Tb, T, Tr>), g, dim3(kThreads), 0, s,
+                                        b, x, r, B, Nc, active, partials));
+}
+
+template <typename T>
+void bsr_rbgs(const T* b, T* x, const T* B, const T* Dinv, int Nc, int dof, int nb,
+              const int* active, bool zero_init, bool reverse, hipStream_t s) {
+  const dim3 g = grid_sites((int64_t)Nc * Nc, nb);
+  const int first = reverse ? 1 : 0;
+  BSR_DISPATCH(dof, hipLaunchKernelGGL((k_bsr_gs<D, T>), g, dim3(kThreads), 0, s, b, x, B, Dinv,
+                                        Nc, first, zero_init ? 1 : 0, active));
+  BSR_DISPATCH(dof, hipLaunchKernelGGL((k_bsr_gs<D, T>), g, dim3(kThreads), 0, s, b, x, B, Dinv,
+                                        Nc, 1 - first, 0, active));
+}
+
+template <typename T>
+void agg_restrict(const T* x, T* xc, const T* q, int Nf, int dofF, int blk, int dofC, int nb,
+                  const int* active, hipStream_t s) {
+  const int Nc = Nf / blk;
+  const dim3 g = grid_sites((int64_t)Nc * Nc, nb);
+  BSR_DISPATCH(dofC, hipLaunchKernelGGL((k_agg_restrict<D, T>), g, dim3(kThreads), 0, s, x, xc,
+                                         q, Nf, dofF, blk, active));
+}
+
+template <typename T>
+void agg_prolong(const T* xc, T* x, const T* q, int Nf, int dofF, int blk, int dofC,
+                 double omega, double beta, int nb, const int* active, hipStream_t s) {
+  const dim3 g = grid_sites((int64_t)Nf * Nf * dofF, nb);
+  BSR_DISPATCH(dofC, hipLaunchKernelGGL((k_agg_prolong<D, T>), g, dim3(kThreads), 0, s, xc, x, q,
+                                         Nf, dofF, blk, (R_t<T>)omega, (R_t<T>)beta, active));
+}
+
+void wilson_links(const double* theta, c64* U64, c32* U32, int N, hipStream_t s) {
+  hipLaunchKernelGGL(k_links, dim3(256), dim3(256), 0, s, theta, U64, U32, 2 * N * N);
+}
+
+void agg_orthonormalise(const c64* V, c64* q, int Nf, int dofF, int blk, int nv,
+                        hipStream_t s) {
+  const int Nc = Nf / blk;
+  const size_t lds = sizeof(c64) * (size_t)blk * blk * dofF * nv;
+  MLMC_REQUIRE(lds <= 60 * 1024, MLMC_EUNSUPPORTED,
+               "aggregate too large for the LDS orthonormalisation");
+  hipLaunchKernelGGL(k_agg_orthonormalise, dim3(Nc * Nc), dim3(kThreads), lds, s, V, q, Nf,
+                     dofF, blk, nv);
+}
+
+void galerkin_blocks(const c64* Bf, const c64* U, double wdiag, const c64* q, int Nf, int dofF,
+                     int blk, int nv, c64* Bc, hipStream_t s) {
+  const int Nc = Nf / blk;
+  hipLaunchKernelGGL(k_galerkin, dim3(Nc * Nc, 5), dim3(kThreads), 0, s, Bf, U, wdiag, q, Nf,
+                     dofF, blk, nv, Bc);
+}
+
+void dense_from_stencil(const c64* Bf, const c64* U, double wdiag, int Nf, int dof, c64* aug,
+                        hipStream_t s) {
+  const int64_t n = (int64_t)Nf * Nf * dof;
+  hipLaunchKernelGGL(k_dense_from_stencil, dim3((unsigned)n), dim3(256), 0, s, Bf, U, wdiag, Nf,
+                     dof, aug);
+}
+
+void block_diag_inverse(const c64* B, c64* Dinv64, c32* Dinv32, int ns, int dof,
+                        hipStream_t s) {
+  const dim3 g((ns + 63) / 64), blk(64);
+  BSR_DISPATCH(dof, hipLaunchKernelGGL((k_block_diag_inverse<D>), g, blk, 0, s, B, Dinv64,
+                                        Dinv32, ns));
+}
+
+// ---- explicit instantiations ----------------------------------------------
+template void wilson_residual<c64, c64, c64>(const c64*, const c64*, c64*, const c64*, int,
+                                             double, int, const int*, c64*, hipStream_t);
+template void wilson_residual<c64, c64, c32>(const c64*, const c64*, c32*, const c64*, int,
+                                             double, int, const int*, c64*, hipStream_t);
+template void wilson_residual<c32, c32, c32>(const c32*, const c32*, c32*, const c32*, int,
+                                             double, int, const int*, c64*, hipStream_t);
+template void wilson_rbgs<c32>(const c32*, c32*, const c32*, int, double, int, const int*, bool,
+                               bool, hipStream_t);
+template void wilson_rbgs<c64>(const c64*, c64*, const c64*, int, double, int, const int*, bool,
+                               bool, hipStream_t);
+template void bsr_residual<c64, c64, c64>(const c64*, const c64*, c64*, const c64*, int, int,
+                                          int, const int*, c64*, hipStream_t);
+template void bsr_residual<c64, c64, c32>(const c64*, const c64*, c32*, const c64*, int, int,
+                                          int, const int*, c64*, hipStream_t);
+template void bsr_residual<c32, c32, c32>(const c32*, const c32*, c32*, const c32*, int, int,
+                                          int, const int*, c64*, hipStream_t);
+template void bsr_rbgs<c32>(const c32*, c32*, const c32*, const c32*, int, int, int, const int*,
+                            bool, bool, hipStream_t);
+template void bsr_rbgs<c64>(const c64*, c64*, const c64*, const c64*, int, int, int, const int*,
+                            bool, bool, hipStream_t);
+template void agg_restrict<c32>(const c32*, c32*, const c32*, int, int, int, int, int,
+                                const int*, hipStream_t);
+template void agg_restrict<c64>(const c64*, c64*, const c64*, int, int, int, int, int,
+                                const int*, hipStream_t);
+template void agg_prolong<c32>(const c32*, c32*, const c32*, int, int, int, int, double, double,
+                               int, const int*, hipStream_t);
+template void agg_prolong<c64>(const c64*, c64*, const c64*, int, int, int, int, double, double,
+                               int, const int*, hipStream_t);
+
+}  // namespace mlmc

@@ -1,0 +1,69 @@
+"""Tune m0 of the synthetic Wilson workloads so that the smallest |eigenvalue|
+of D is about 1e-2 (bisection on m0; eigenvalues from shift-invert Arnoldi of
+the CPU oracle's operator).  Writes workloads/wilson_mass.json.
+
+Run:  python workloads/tune_wilson_mass.py 256 512
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import scipy.sparse.linalg as spla
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(HERE))
+
+from oracle.operators import wilson2d  # noqa: E402
+from workloads.generate import gauge_field  # noqa: E402
+
+TARGET = 1e-2
+
+
+def smallest_eig(D):
+    """Eigenvalue of smallest modulus (shift-invert Arnoldi around 0)."""
+    vals = spla.eigs(D.tocsc(), k=4, sigma=0.0, which="LM", return_eigenvectors=False,
+                     tol=1e-8, maxiter=5000)
+    return vals[np.argmin(np.abs(vals))]
+
+
+def tune(N, sigma=0.5, seed=1):
+    """Largest m0 below the free-field value at which the smallest eigenvalue
+    (still in the right half plane) has modulus TARGET: bisection on the sign
+    of Re(lambda_min) - TARGET, starting from the free field (lambda_min = m0)."""
+    theta = gauge_field(N, sigma, seed)
+    hi = TARGET                     # free field would give exactly TARGET
+    lo = None
+    m = hi
+    while lo is None:
+        m -= 0.02
+        lam = smallest_eig(wilson2d(N, theta, m))
+        print("N=%d m0=%.5f lambda_min=%s" % (N, m, lam), flush=True)
+        if lam.real < TARGET:
+            lo = m
+        else:
+            hi = m
+    lam = None
+    for _ in range(40):
+        mid = 0.5 * (lo + hi)
+        lam = smallest_eig(wilson2d(N, theta, mid))
+        print("N=%d m0=%.7f lambda_min=%s" % (N, mid, lam), flush=True)
+        if abs(abs(lam) / TARGET - 1.0) < 0.02 and lam.real > 0:
+            break
+        if lam.real < TARGET:
+            lo = mid
+        else:
+            hi = mid
+    return mid, abs(lam)
+
+
+if __name__ == "__main__":
+    path = os.path.join(HERE, "wilson_mass.json")
+    table = json.load(open(path)) if os.path.exists(path) else {}
+    for arg in sys.argv[1:]:
+        N = int(arg)
+        m0, f = tune(N)
+        table[str(N)] = {"m0": m0, "min_abs_eig": f, "theta_sigma": 0.5, "gauge_seed": 1}
+        with open(path, "w") as fh:
+            json.dump(table, fh, indent=1)
+        print("N=%d m0=%.6f" % (N, m0), flush=True)
