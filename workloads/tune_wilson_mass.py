@@ -21,9 +21,11 @@ TARGET = 1e-2
 
 
 def smallest_eig(D):
-    """Eigenvalue of smallest modulus (shift-invert Arnoldi around 0)."""
-    vals = spla.eigs(D.tocsc(), k=4, sigma=0.0, which="LM", return_eigenvectors=False,
-                     tol=1e-8, maxiter=5000)
+    """Eigenvalue of smallest modulus: Arnoldi on D^-1 (sparse LU, minimum-degree
+    ordering of the symmetric pattern), largest-modulus eigenvalues inverted."""
+    lu = spla.splu(D.tocsc(), permc_spec="MMD_AT_PLUS_A")
+    op = spla.LinearOperator(D.shape, matvec=lu.solve, dtype=np.complex128)
+    vals = 1.0 / spla.eigs(op, k=4, which="LM", return_eigenvectors=False, tol=1e-8, ncv=40)
     return vals[np.argmin(np.abs(vals))]
 
 
@@ -44,7 +46,7 @@ def tune(N, sigma=0.5, seed=1):
         else:
             hi = m
     lam = None
-    for _ in range(40):
+    for _ in range(25):
         mid = 0.5 * (lo + hi)
         lam = smallest_eig(wilson2d(N, theta, mid))
         print("N=%d m0=%.7f lambda_min=%s" % (N, mid, lam), flush=True)
