@@ -27,6 +27,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "time-to-tr(A^-1) at rel err 1e-3 (learned+FP32 vs plain FP64 MLMC); HBM GB/s"
+GS_SOURCE = os.path.join(ROOT, "paper_2108_11281_amd", "csrc", "kernels_poisson.hip")
+GS_TRAFFIC = os.path.join(ROOT, "profiles", "rbgs_sweep_poisson1024_traffic.md")
 
 
 def log(msg):
@@ -65,6 +68,34 @@ def cpu_baseline(n_samples, N, L, budget_s=12.0):
                        % (N, L, sample, list(n_samples)))
 
 
+def source_digest(path):
+    import hashlib
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def stored_traffic():
+    """HBM bytes per launch of the sweep kernel from the committed FETCH_SIZE /
+    WRITE_SIZE counter summary, or None when the kernel source has changed
+    since the counters were taken (the summary records the source digest)."""
+    try:
+        with open(GS_TRAFFIC) as f:
+            text = f.read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if line.startswith("traffic_bytes_per_launch:") or line.startswith("source_digest:"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_digest") != source_digest(GS_SOURCE):
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +109,10 @@ def main():
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the plain FP64 MLMC / Hutchinson comparison runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--timing-stride", type=int, default=8,
+                    help="bracket about one launch in k of the timed kernel with HIP events")
+    ap.add_argument("--copy-check", action="store_true",
+                    help="run one 256 MiB device copy first (calibrates HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -90,6 +125,12 @@ def main():
     from oracle import operators  # closed-form trace for the accuracy report
 
     torch.cuda.set_device(0)
+    if args.copy_check:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     N, L = args.N, args.levels
     log("setup poisson2d N=%d L=%d nb=%d" % (N, L, args.nb))
     t0 = time.perf_counter()
@@ -102,7 +143,7 @@ def main():
         log("warmup %d: %.3fs N_l=%s" % (i, r["seconds"], r["n_samples"]))
     # only the dominant kernel (the fused smoother sweep) is timed inside the
     # timed region; the per-kernel table comes from one extra step afterwards
-    est.set_timing(["rbgs_sweep"])
+    est.set_timing(["rbgs_sweep"], stride=args.timing_stride)
     est.reset_kernel_stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -128,13 +169,14 @@ def main():
     zs = [(r["trace"].real - exact) / r["rmsd"] for r in runs]
 
     # dominant kernel: the fused red-black Gauss-Seidel sweep (largest total time
-    # in the per-kernel table); achieved = algorithmic bytes / time over the
-    # timed steps
+    # in the per-kernel table); achieved = algorithmic bytes / time of the
+    # sampled launches over the timed steps
     name, (launches, ms, nbytes) = "rbgs_sweep", gs
     achieved = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
     roofline = dict(bound="hbm", kernel=name + "<float>", achieved=round(achieved, 1),
                     peak=HBM_PEAK_GBS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
-                    traffic=None, launches=launches,
+                    traffic=stored_traffic(), launches_timed=launches,
+                    timing_stride=args.timing_stride,
                     avg_launch_us=round(1000.0 * ms / max(launches, 1), 2),
                     algorithmic_bytes_per_launch=round(nbytes / max(launches, 1)))
     kernels = {k: dict(launches=v[0], ms=round(v[1], 2),
@@ -167,7 +209,7 @@ def main():
         cpu["value"] = round(cpu["value"], 2)
 
     out = {
-        "metric": "time-to-tr(A^-1) at rel err 1e-3 (FP32 inner + FP64 refinement MLMC)",
+        "metric": METRIC,
         "value": round(ms_per_step / 1000.0, 4),
         "unit": "s",
         "n_gpus": 1,
@@ -179,7 +221,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64ir",
         "data": "synthetic (Rademacher probes from Philox4x64-10 on the device)",
-        "config": {"workload": "poisson2d_1024x1024_L6_agg2x2_nb128_fp32ir64_eps1e-3",
+        "config": {"workload": "poisson2d_%dx%d_L%d_agg2x2_nb%d_fp32ir64_eps%g"
+                               % (N, N, L, args.nb, args.eps),
+                   "variant": "FP32 inner Krylov + V-cycle, FP64 reliable-update refinement "
+                              "(no learned smoother on this operator)",
                    "n": N * N, "levels": L, "nb": args.nb, "eps": args.eps,
                    "alloc": args.alloc, "solve_tol": 1e-10},
         "roofline": roofline,

@@ -237,12 +237,16 @@ int mlmc_set_allocator(mlmc_alloc_fn alloc, mlmc_free_fn free_fn, void* user);
  * out[2] V-cycles, out[3] batches.  n: entries to copy (<= 4). */
 int mlmc_counters(void* ctx, int64_t* out, int n);
 
-/* Measurement mode.  mask: bit i set = every launch of kernel id i (listed
- * below) is bracketed by HIP events on the context stream and records its
+/* Measurement mode.  mask: bit i set = launches of kernel id i (listed
+ * below) are bracketed by HIP events on the context stream and record their
  * active columns, so that per-kernel launch counts, durations and algorithmic
- * bytes can be read back; mask = 0 stops it.  Costs two event records per
- * timed launch. */
-int mlmc_set_timing(void* ctx, int mask);
+ * bytes can be read back; mask = 0 stops it.  stride >= 1: about one launch in
+ * stride of each timed kernel is bracketed (the others run
+ * untouched; which launches is fixed by a hash of the launch index, so the
+ * sample does not alias with the launch pattern of the V-cycle), which bounds
+ * the cost of the two event records per timed launch.
+ * Returns MLMC_EINVAL for stride < 1. */
+int mlmc_set_timing(void* ctx, int mask, int stride);
 
 /* Kernel ids for mlmc_kernel_stats (algorithmic bytes per unknown and RHS for
  * element size e): 0 fused red-black Gauss-Seidel sweep (2e from a zero start:

@@ -113,6 +113,11 @@ class TraceEstimator:
         self._field = None
         if field is not None:
             self._field = np.ascontiguousarray(field, dtype=np.float64)
+            N = int(n_side)
+            want = {"wilson2d": 2 * N * N, "varcoef3d": 3 * N * N * (N + 1)}.get(kind)
+            if want is not None and self._field.size != want:
+                raise ValueError("%s field must hold %d values, got %d"
+                                 % (kind, want, self._field.size))
             op.field = self._field.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         h = _capi.Hierarchy()
         h.levels_solver = int(levels_solver)
@@ -208,8 +213,9 @@ class TraceEstimator:
     KERNELS = ["rbgs_sweep", "residual_restrict", "prolong_correct", "update_apply", "cg_xr",
                "unused5", "unused6", "ir_residual"]
 
-    def set_timing(self, kernels=True):
-        """kernels: True (all), False (none) or a list of kernel names to time."""
+    def set_timing(self, kernels=True, stride=1):
+        """kernels: True (all), False (none) or a list of kernel names to time;
+        stride: time every stride-th launch of each timed kernel."""
         if kernels is True:
             mask = (1 << len(self.KERNELS)) - 1
         elif not kernels:
@@ -218,7 +224,7 @@ class TraceEstimator:
             mask = 0
             for k in kernels:
                 mask |= 1 << self.KERNELS.index(k)
-        self._c(self._lib.mlmc_set_timing(self._ctx, int(mask)))
+        self._c(self._lib.mlmc_set_timing(self._ctx, int(mask), int(stride)))
 
     def reset_kernel_stats(self):
         self._c(self._lib.mlmc_reset_kernel_stats(self._ctx))

@@ -102,7 +102,7 @@ SIGNATURES = {
                                           ctypes.POINTER(Result)]),
     "mlmc_set_allocator": (ctypes.c_int, [ALLOC_FN, FREE_FN, _P]),
     "mlmc_counters": (ctypes.c_int, [_P, _I64, ctypes.c_int]),
-    "mlmc_set_timing": (ctypes.c_int, [_P, ctypes.c_int]),
+    "mlmc_set_timing": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
     "mlmc_kernel_stats": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _D]),
     "mlmc_reset_kernel_stats": (ctypes.c_int, [_P]),
     "mlmc_last_error": (ctypes.c_char_p, [_P]),

@@ -14,6 +14,7 @@ SOURCES = [
     "kernels_poisson.hip",
     "kernels_wilson.hip",
     "kernels_krylov.hip",
+    "kernels_varcoef.hip",
     "context.cpp",
     "context_complex.cpp",
     "estimator.cpp",

@@ -214,10 +214,10 @@ int mlmc_counters(void* c, int64_t* out, int n) {
   return MLMC_OK;
 }
 
-int mlmc_set_timing(void* c, int enable) {
+int mlmc_set_timing(void* c, int mask, int stride) {
   Context* ctx = as_ctx(c);
-  if (!ctx) return MLMC_EINVAL;
-  return guarded(ctx, [&] { ctx->set_timing((unsigned)enable); });
+  if (!ctx || stride < 1) return MLMC_EINVAL;
+  return guarded(ctx, [&] { ctx->set_timing((unsigned)mask, stride); });
 }
 
 int mlmc_kernel_stats(void* c, int kernel, int fp64, double* out) {

@@ -46,6 +46,11 @@ Context::Context(const mlmc_operator& A, const mlmc_hierarchy& h, const mlmc_opt
         omega_ = opt_.omega > 0 ? opt_.omega : 1.8;
         build_poisson();
         break;
+      case MLMC_VARCOEF3D:
+        varcoef_ = true;
+        omega_ = opt_.omega > 0 ? opt_.omega : 1.8;
+        build_varcoef(A.field);
+        break;
       case MLMC_WILSON2D:
         complex_ = true;
         omega_ = opt_.omega > 0 ? opt_.omega : 1.0;
@@ -136,6 +141,9 @@ void Context::invert_coarse(int level, double** inv_out, c64* trace_out) {
     case MLMC_POISSON2D:
       poisson_dense_build<double>(aug, L.side, L.d, L.c, s_);
       break;
+    case MLMC_VARCOEF3D:
+      varcoef_dense(L.kf64, L.dg64, L.side, aug, s_);
+      break;
     default:
       throw Error(MLMC_EUNSUPPORTED, "dense build");
   }
@@ -206,6 +214,58 @@ void Context::build_poisson() {
     L.c = c;
   }
   MLMC_REQUIRE(lv_[Ls_ - 1].n <= 16384, MLMC_EINVAL, "coarsest solver level larger than 128^2");
+  finish_real_build();
+}
+
+// 3D diffusion with face coefficients: every level keeps the 7-point form, the
+// next level's faces being 1/8 of the sum of the four fine faces they cover
+// (orthonormal 2x2x2 aggregation, Galerkin) and the shift carrying over.
+void Context::build_varcoef(const double* k) {
+  MLMC_REQUIRE(k != nullptr, MLMC_EINVAL, "VARCOEF3D needs face coefficients in field");
+  MLMC_REQUIRE(op_.n_side >= 2 && op_.n_side <= 1024, MLMC_EINVAL, "n_side must be in [2, 1024]");
+  MLMC_REQUIRE(std::isfinite(op_.shift) && op_.shift >= 0, MLMC_EINVAL, "shift must be >= 0");
+  const int N = op_.n_side;
+  const int64_t nf = 3LL * N * N * (N + 1);
+  double kmin = INFINITY;
+  for (int64_t t = 0; t < nf; ++t) {
+    MLMC_REQUIRE(std::isfinite(k[t]) && k[t] >= 0, MLMC_EINVAL,
+                 "face coefficients must be finite and >= 0");
+    kmin = std::min(kmin, k[t]);
+  }
+  MLMC_REQUIRE(op_.shift > 0 || kmin > 0, MLMC_EINVAL,
+               "VARCOEF3D needs shift > 0 or positive faces (positive definite)");
+  lv_.resize(Ls_);
+  int side = N;
+  for (int l = 0; l < Ls_; ++l) {
+    if (l > 0) {
+      MLMC_REQUIRE(side % 2 == 0, MLMC_EINVAL,
+                   "grid side not divisible by 2 at level " + std::to_string(l));
+      side /= 2;
+    }
+    Level& L = lv_[l];
+    L.index = l + 1;
+    L.side = side;
+    L.dof = 1;
+    L.n = (int64_t)side * side * side;
+    const int64_t f = 3LL * side * side * (side + 1);
+    L.kf64 = dalloc_n<double>(f);
+    L.kf32 = dalloc_n<float>(f);
+    L.dg64 = dalloc_n<double>(L.n);
+    L.dg32 = dalloc_n<float>(L.n);
+  }
+  MLMC_REQUIRE(lv_[Ls_ - 1].n <= 16384, MLMC_EINVAL, "coarsest solver level larger than 16384");
+  MLMC_HIP(hipMemcpyAsync(lv_[0].kf64, k, sizeof(double) * (size_t)nf, hipMemcpyHostToDevice, s_));
+  for (int l = 0; l < Ls_; ++l) {
+    Level& L = lv_[l];
+    if (l > 0) varcoef_coarsen(lv_[l - 1].kf64, L.kf64, lv_[l - 1].side, s_);
+    varcoef_diag(L.kf64, op_.shift, L.side, L.dg64, L.dg32, L.kf32, s_);
+  }
+  finish_real_build();
+}
+
+// work buffers and coarsest inverses of a real symmetric positive definite
+// operator (POISSON2D, VARCOEF3D)
+void Context::finish_real_build() {
   const int64_t n1 = lv_[0].n;
   alloc_common();
   alloc_work(w64_);
@@ -237,35 +297,114 @@ void Context::build_poisson() {
 // ---------------------------------------------------------------------------
 // operator dispatch
 // ---------------------------------------------------------------------------
+template <> const float* Context::vc_faces<float>(int l) const { return lv_[l - 1].kf32; }
+template <> const double* Context::vc_faces<double>(int l) const { return lv_[l - 1].kf64; }
+template <> const float* Context::vc_diag<float>(int l) const { return lv_[l - 1].dg32; }
+template <> const double* Context::vc_diag<double>(int l) const { return lv_[l - 1].dg64; }
+
+int Context::op_tiles(int l) const {
+  const Level& L = lv_[l - 1];
+  return varcoef_ ? varcoef_blocks(L.side) : poisson_march_tiles(L.side);
+}
+
 template <typename T>
 void Context::op_apply(int l, const T* x, T* y, int nb, const int* act, c64* partials) {
   const Level& L = lv_[l - 1];
-  poisson_apply<T>(x, y, L.side, L.d, L.c, nb, act, partials, s_);
+  if (varcoef_)
+    varcoef_residual<T, T, T>(nullptr, x, y, vc_faces<T>(l), vc_diag<T>(l), L.side, nb, act,
+                              partials, s_);
+  else
+    poisson_apply<T>(x, y, L.side, L.d, L.c, nb, act, partials, s_);
 }
 
 template <typename Tb, typename Tx, typename Tr>
 void Context::op_residual(int l, const Tb* b, const Tx* x, Tr* r, int nb, const int* act,
                           c64* partials) {
   const Level& L = lv_[l - 1];
-  poisson_residual<Tb, Tx, Tr>(b, x, r, L.side, L.d, L.c, nb, act, partials, s_);
+  if (varcoef_)
+    varcoef_residual<Tb, Tx, Tr>(b, x, r, vc_faces<Tx>(l), vc_diag<Tx>(l), L.side, nb, act,
+                                 partials, s_);
+  else
+    poisson_residual<Tb, Tx, Tr>(b, x, r, L.side, L.d, L.c, nb, act, partials, s_);
+}
+
+template <typename T>
+void Context::op_update_apply(int l, const T* p_old, const T* z, const c64* beta, T* p_new,
+                              T* q, int nb, const int* act) {
+  const Level& L = lv_[l - 1];
+  if (varcoef_)
+    varcoef_update_apply<T>(p_old, z, beta, p_new, q, vc_faces<T>(l), vc_diag<T>(l), L.side, nb,
+                            act, partials_, s_);
+  else
+    poisson_update_apply<T>(p_old, z, beta, p_new, q, L.side, L.d, L.c, nb, act, partials_, s_);
 }
 
 template <typename T>
 void Context::op_res_restrict(int l, const T* b, const T* x, T* rc, int nb, const int* act) {
   const Level& L = lv_[l - 1];
-  poisson_residual_restrict<T>(b, x, rc, L.side, L.d, L.c, nb, act, s_);
+  if (varcoef_)
+    varcoef_restrict<T>(b, x, rc, vc_faces<T>(l), vc_diag<T>(l), L.side, true, nb, act, s_);
+  else
+    poisson_residual_restrict<T>(b, x, rc, L.side, L.d, L.c, nb, act, s_);
 }
 
 template <typename T>
 void Context::op_prolong(int l, const T* ec, T* x, int nb, const int* act, double beta) {
   const Level& L = lv_[l - 1];
-  agg2d_prolong<T>(ec, x, L.side, beta == 0.0 ? 1.0 : omega_, beta, nb, act, s_);
+  const double w = beta == 0.0 ? 1.0 : omega_;
+  if (varcoef_)
+    varcoef_prolong<T>(ec, x, L.side, w, beta, nb, act, s_);
+  else
+    agg2d_prolong<T>(ec, x, L.side, w, beta, nb, act, s_);
 }
 
 template <typename T>
 void Context::op_restrict(int l, const T* x, T* xc, int nb, const int* act) {
   const Level& L = lv_[l - 1];
-  agg2d_restrict<T>(x, xc, L.side, nb, act, s_);
+  if (varcoef_)
+    varcoef_restrict<T>(nullptr, x, xc, nullptr, nullptr, L.side, false, nb, act, s_);
+  else
+    agg2d_restrict<T>(x, xc, L.side, nb, act, s_);
+}
+
+// ---------------------------------------------------------------------------
+// V-cycle of the 3D diffusion operator: in-place red-black sweeps (black first
+// after the coarse correction, so the preconditioner is symmetric), fused
+// residual + restriction, prolongation + omega-scaled correction.
+// ---------------------------------------------------------------------------
+template <typename T>
+void Context::vcycle_vc(int l, const T* b, T* x, int nb, const int* act, c64* rz_partials) {
+  Work<T>& w = work<T>();
+  if (l == 1) counters[2] += 1;
+  const int64_t n = lv_[l - 1].n;
+  const double en = (double)sizeof(T) * (double)n;
+  if (l == Ls_) {
+    dense_apply<T>(w.ainvT, b, x, (int)n, nb, act, s_);
+  } else {
+    const Level& L = lv_[l - 1];
+    const T* kf = vc_faces<T>(l);
+    const T* dg = vc_diag<T>(l);
+    const int pre = opt_.nu_pre, post = opt_.nu_post;
+    for (int i = 0; i < pre; ++i)
+      timed<T>(kTimGs, en * ((i == 0 ? 2.0 : 3.0) + 4.0 / (double)nb), act, nb, [&] {
+        varcoef_rbgs<T>(b, x, kf, dg, L.side, nb, act, i == 0, false, s_);
+      });
+    T* bc = w.vb[l];
+    T* ec = w.vx[l];
+    if (pre == 0)
+      op_restrict<T>(l, b, bc, nb, act);
+    else
+      timed<T>(kTimResRestrict, en * (2.0 + 0.125 + 4.0 / (double)nb), act, nb,
+               [&] { op_res_restrict<T>(l, b, x, bc, nb, act); });
+    vcycle_vc<T>(l + 1, bc, ec, nb, act, nullptr);
+    timed<T>(kTimProlong, en * (2.0 + 0.125), act, nb,
+             [&] { varcoef_prolong<T>(ec, x, L.side, omega_, pre == 0 ? 0.0 : 1.0, nb, act, s_); });
+    for (int i = 0; i < post; ++i)
+      timed<T>(kTimGs, en * (3.0 + 4.0 / (double)nb), act, nb, [&] {
+        varcoef_rbgs<T>(b, x, kf, dg, L.side, nb, act, false, true, s_);
+      });
+  }
+  if (rz_partials) vec_dot_partials<T>(b, x, n, nb, act, rz_partials, s_);
 }
 
 // ---------------------------------------------------------------------------
@@ -277,6 +416,10 @@ void Context::op_restrict(int l, const T* x, T* xc, int nb, const int* act) {
 // ---------------------------------------------------------------------------
 template <typename T>
 void Context::vcycle(int l, const T* b, T* x, int nb, const int* act, c64* rz_partials) {
+  if (varcoef_) {
+    vcycle_vc<T>(l, b, x, nb, act, rz_partials);
+    return;
+  }
   Work<T>& w = work<T>();
   if (l == 1) counters[2] += 1;
   const int64_t n = lv_[l - 1].n;
@@ -345,7 +488,7 @@ template <typename T>
 int Context::vcycle_partials(int l, bool* fused) const {
   const int64_t n = lv_[l - 1].n;
   *fused = false;
-  if (l == Ls_ || opt_.nu_post == 0) return reduce_blocks(n);
+  if (varcoef_ || l == Ls_ || opt_.nu_post == 0) return reduce_blocks(n);
   enum { kNull, kTmp, kX };
   int u = kNull;
   for (int i = 0; i < opt_.nu_pre; ++i) u = (i % 2 == 0) ? kTmp : kX;
@@ -366,6 +509,16 @@ int Context::vcycle_partials(int l, bool* fused) const {
 // one-block count of its active columns, so the algorithmic bytes of the launch
 // are known without a host synchronisation.
 // ---------------------------------------------------------------------------
+namespace {
+// splitmix64 finaliser
+uint64_t mix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+}  // namespace
+
 hipEvent_t Context::event() {
   if (!ev_pool_.empty()) {
     hipEvent_t e = ev_pool_.back();
@@ -380,7 +533,11 @@ hipEvent_t Context::event() {
 template <typename T, typename F>
 void Context::timed(int id, double bytes_per_col, const int* act, int nb, F&& launch) {
   (void)act;
-  if (!timing_ || !(timing_mask_ & (1u << id))) {
+  // with stride k, a launch is timed with probability 1/k, chosen by a hash of
+  // its index so that the sample does not alias with the period of the V-cycle
+  if (!timing_ || !(timing_mask_ & (1u << id)) ||
+      (timing_stride_ > 1 && mix64((uint64_t)timing_seen_[id]++ * kNumTimers + id) %
+                                     (uint64_t)timing_stride_ != 0)) {
     launch();
     return;
   }
@@ -388,18 +545,29 @@ void Context::timed(int id, double bytes_per_col, const int* act, int nb, F&& la
   const int slot = 2 * id + (sizeof(typename Traits<T>::real) == 8 ? 1 : 0);
   const int idx = tlog_next_++;
   hipEvent_t a = event(), b = event();
-  MLMC_HIP(hipEventRecord(a, s_));
+  LaunchEvents ev;
+  ev.start = a;
+  ev.stop = b;
   timing_log() = tlog_dev_ + (int64_t)idx * nb_;
+  timing_events() = &ev;
   launch();
+  timing_events() = nullptr;
   timing_log() = nullptr;
-  MLMC_HIP(hipEventRecord(b, s_));
+  MLMC_HIP(hipGetLastError());
+  if (!ev.used) {  // nothing was launched through MLMC_LAUNCH: no sample
+    ev_pool_.push_back(a);
+    ev_pool_.push_back(b);
+    return;
+  }
   pending_.push_back({slot, idx, nb, bytes_per_col, a, b});
 }
 
-void Context::set_timing(unsigned mask) {
+void Context::set_timing(unsigned mask, int stride) {
   collect_timing();
   timing_ = mask != 0;
   timing_mask_ = mask;
+  timing_stride_ = stride;
+  for (int64_t& v : timing_seen_) v = 0;
   const bool on = timing_;
   if (on && !tlog_dev_) tlog_dev_ = dalloc_n<int>((int64_t)kTimingLog * nb_);
 }
@@ -462,7 +630,7 @@ int Context::pcg(int l, const T* b, T* x, int nb, int* act, double tol, c64* las
   const Level& L = lv_[l - 1];
   const int64_t n = L.n;
   const int nblk = reduce_blocks(n);
-  const int ntiles = poisson_march_tiles(L.side);
+  const int ntiles = op_tiles(l);
   c64 *rr0 = scal_[kRr0], *rz = scal_[kRz], *tmp = scal_[kTmp], *alpha = scal_[kAlpha],
       *beta = scal_[kBeta];
   vec_zero<T>(x, n, nb, act, s_);
@@ -485,10 +653,8 @@ int Context::pcg(int l, const T* b, T* x, int nb, int* act, double tol, c64* las
   const int check = 2;
   int it = 0;
   for (it = 1; it <= opt_.max_iter; ++it) {
-    timed<T>(kTimApply, 4.0 * en, act, nb, [&] {
-      poisson_update_apply<T>(p_old, w.z, beta, p_new, w.q, L.side, L.d, L.c, nb, act,
-                              partials_, s_);
-    });
+    timed<T>(kTimApply, 4.0 * en, act, nb,
+             [&] { op_update_apply<T>(l, p_old, w.z, beta, p_new, w.q, nb, act); });
     finish_sums(partials_, ntiles, nb, tmp, s_);
     cg_alpha(rz, tmp, act, alpha, nb, s_);
     if (lastcorr) cg_lastcorr(alpha, rz, act, lastcorr, nb, s_);
@@ -528,7 +694,7 @@ void Context::pcg_refined(int l, const double* b, double* y, int nb, double tol,
   const Level& L = lv_[l - 1];
   const int64_t n = L.n;
   const int nblk = reduce_blocks(n);
-  const int ntiles = poisson_march_tiles(L.side);
+  const int ntiles = op_tiles(l);
   int* act = act_outer_;
   c64 *bb = scal_[kBb], *bd = scal_[kBd], *rr_upd = scal_[kRres], *rr_new = scal_[kRres2];
   c64 *rz = scal_[kRz], *tmp = scal_[kTmp], *alpha = scal_[kAlpha], *beta = scal_[kBeta];
@@ -550,10 +716,8 @@ void Context::pcg_refined(int l, const double* b, double* y, int nb, double tol,
   const int check = 2;
   const int max_it = opt_.max_iter * opt_.max_refine;
   for (int it = 1; it <= max_it; ++it) {
-    timed<float>(kTimApply, 4.0 * en, act, nb, [&] {
-      poisson_update_apply<float>(p_old, w.z, beta, p_new, w.q, L.side, L.d, L.c, nb, act,
-                                  partials_, s_);
-    });
+    timed<float>(kTimApply, 4.0 * en, act, nb,
+                 [&] { op_update_apply<float>(l, p_old, w.z, beta, p_new, w.q, nb, act); });
     finish_sums(partials_, ntiles, nb, tmp, s_);
     cg_alpha(rz, tmp, act, alpha, nb, s_);
     timed<float>(kTimCgXr, 6.0 * en, act, nb,
@@ -600,7 +764,7 @@ void Context::pcg_refined(int l, const double* b, double* y, int nb, double tol,
 void Context::solve(int l, const double* b, double* y, int nb, c64* err, double* relres_host,
                     bool* converged) {
   const int64_t n = lv_[l - 1].n;
-  const int nblk_pts = complex_ ? 0 : poisson_march_tiles(lv_[l - 1].side);
+  const int nblk_pts = complex_ ? 0 : op_tiles(l);
   const int nblk = reduce_blocks(n);
   c64* bb = scal_[kBb];
   c64* bd = scal_[kBd];
@@ -861,7 +1025,7 @@ void Context::prolong_fp64(int level, int nrhs, const double* xc, double* x) {
     cop_prolong<c64>(level, reinterpret_cast<const c64*>(xc), reinterpret_cast<c64*>(x), nrhs,
                      nullptr, 1.0, 0.0);
   else
-    agg2d_prolong<double>(xc, x, lv_[level - 1].side, 1.0, 0.0, nrhs, nullptr, s_);
+    op_prolong<double>(level, xc, x, nrhs, nullptr, 0.0);
   MLMC_HIP(hipStreamSynchronize(s_));
   MLMC_HIP(hipGetLastError());
 }
@@ -884,6 +1048,8 @@ void Context::export_coarse(int which, double* out) {
   if (complex_)
     dense_from_stencil(L.wilson ? nullptr : L.B64, L.U64, op_.mass + 2.0, L.side, L.dof,
                        reinterpret_cast<c64*>(aug), s_);
+  else if (varcoef_)
+    varcoef_dense(L.kf64, L.dg64, L.side, aug, s_);
   else
     poisson_dense_build<double>(aug, L.side, L.d, L.c, s_);
   for (int i = 0; i < n; ++i)

@@ -36,6 +36,10 @@ struct Level {
   c64* q64 = nullptr;
   c32* q32 = nullptr;
   int blk = 0;
+  // VARCOEF3D levels: face coefficients k[3][side][side][side+1] and the
+  // diagonal (shift + six faces), FP64 and FP32 copies
+  double *kf64 = nullptr, *dg64 = nullptr;
+  float *kf32 = nullptr, *dg32 = nullptr;
 };
 
 // Batched flexible GMRES workspace (precision T)
@@ -92,7 +96,7 @@ class Context {
   // kernel timing (measurement mode)
   enum { kTimGs, kTimResRestrict, kTimProlong, kTimApply, kTimCgXr, kTimCgP, kTimDot,
          kTimIrResidual, kNumTimers };
-  void set_timing(unsigned mask);
+  void set_timing(unsigned mask, int stride);
   void kernel_stats(int id, int fp64, double* out);
   void reset_kernel_stats();
 
@@ -107,6 +111,8 @@ class Context {
     return static_cast<T*>(dalloc(sizeof(T) * (size_t)count));
   }
   void build_poisson();
+  void build_varcoef(const double* k);
+  void finish_real_build();
   void build_wilson(const double* theta);
   void alloc_common();
   // complex operators: op on level l in precision T (c32 / c64)
@@ -141,6 +147,14 @@ class Context {
   void op_residual(int l, const Tb* b, const Tx* x, Tr* r, int nb, const int* act,
                    c64* partials);
 
+  template <typename T> const T* vc_faces(int l) const;
+  template <typename T> const T* vc_diag(int l) const;
+  // partial sums per column written by op_residual / op_update_apply
+  int op_tiles(int l) const;
+  template <typename T> void op_update_apply(int l, const T* p_old, const T* z, const c64* beta,
+                                             T* p_new, T* q, int nb, const int* act);
+  template <typename T> void vcycle_vc(int l, const T* b, T* x, int nb, const int* act,
+                                       c64* rz_partials);
   template <typename T> Work<T>& work();
   template <typename T> void vcycle(int l, const T* b, T* x, int nb, const int* act,
                                     c64* rz_partials);
@@ -176,6 +190,8 @@ class Context {
   static constexpr int kTimingLog = 1 << 16;
   bool timing_ = false;
   unsigned timing_mask_ = 0;
+  int timing_stride_ = 1;
+  int64_t timing_seen_[kNumTimers] = {};
   int* tlog_dev_ = nullptr;
   int tlog_next_ = 0;
   std::vector<Pending> pending_;
@@ -199,6 +215,7 @@ class Context {
   Fgmres<c32> fg32_;
   Fgmres<c64> fg64_;
   bool complex_ = false;
+  bool varcoef_ = false;
   int m_ = 16;                    // FGMRES restart length
   double omega_ = 1.0;            // coarse-correction scaling in use
   // FGMRES scalars: Hessenberg, rotations, rhs, solution, dims, cycle flags

@@ -3,6 +3,8 @@
 // the device: kernels skip columns whose flag is 0 (converged solves).
 #pragma once
 
+#include <hip/hip_ext.h>
+
 #include "common.h"
 
 namespace mlmc {
@@ -13,6 +15,28 @@ constexpr int kMaxPartials = 1024;  // per-column partial sums of a reduction
 // Measurement mode: when non-null, the next timed launch records, for each
 // column k, its active flag at tlog[k] (written by the kernel itself).
 int*& timing_log();
+
+// Measurement mode: when non-null, launches made through MLMC_LAUNCH carry
+// these events in the dispatch itself (hipExtLaunchKernel), so the events
+// time the kernel's execution and not the gaps between launches.  The first
+// such launch records `start`; every one records `stop` (the last one wins).
+struct LaunchEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+  bool used = false;
+};
+LaunchEvents*& timing_events();
+
+#define MLMC_LAUNCH(kern, grid, block, shmem, stream, ...)                                   \
+  do {                                                                                       \
+    ::mlmc::LaunchEvents* ev_ = ::mlmc::timing_events();                                     \
+    if (ev_) {                                                                               \
+      hipExtLaunchKernelGGL(kern, grid, block, shmem, stream, ev_->used ? nullptr : ev_->start, \
+                            ev_->stop, 0, __VA_ARGS__);                                      \
+      ev_->used = true;                                                                      \
+    } else {                                                                                 \
+      hipLaunchKernelGGL(kern, grid, block, shmem, stream, __VA_ARGS__);                     \
+    }                                                                                        \
+  } while (0)
 
 // ----- vectors ---------------------------------------------------------------
 template <typename T>
@@ -143,6 +167,45 @@ void agg2d_restrict(const T* x, T* xc, int N, int nb, const int* active, hipStre
 template <typename T>
 void agg2d_prolong(const T* ec, T* x, int N, double omega, double beta, int nb,
                    const int* active, hipStream_t s);
+
+// ----- 3D 7-point variable-coefficient operator, N^3 cells, Dirichlet faces -----
+// k: face coefficients k[3][N][N][N+1] of one level (x-faces [z][y][f], y-faces
+// [z][x][f], z-faces [y][x][f]); diag[i] = shift + the six faces of cell i.
+int varcoef_blocks(int N);  // partial sums per column of residual / update_apply
+// r = b - A x ; b == nullptr: r = A x (partials then of conj(x)^T r)
+template <typename Tb, typename T, typename Tr>
+void varcoef_residual(const Tb* b, const T* x, Tr* r, const typename Traits<T>::real* k,
+                      const typename Traits<T>::real* diag, int N, int nb, const int* active,
+                      c64* partials, hipStream_t s);
+// one in-place red-black Gauss-Seidel sweep (reverse: black first); zero_init:
+// x = 0 on entry (not read)
+template <typename T>
+void varcoef_rbgs(const T* b, T* x, const typename Traits<T>::real* k,
+                  const typename Traits<T>::real* diag, int N, int nb, const int* active,
+                  bool zero_init, bool reverse, hipStream_t s);
+// xc = R (b - A x) when residual, else xc = R x; R the orthonormal 2x2x2
+// aggregation (entries 1/sqrt(8))
+template <typename T>
+void varcoef_restrict(const T* b, const T* x, T* xc, const typename Traits<T>::real* k,
+                      const typename Traits<T>::real* diag, int N, bool residual, int nb,
+                      const int* active, hipStream_t s);
+// x = beta x + omega P ec
+template <typename T>
+void varcoef_prolong(const T* ec, T* x, int N, double omega, double beta, int nb,
+                     const int* active, hipStream_t s);
+// p_new = z + beta p_old ; q = A p_new ; partials of conj(p_new)^T q
+template <typename T>
+void varcoef_update_apply(const T* p_old, const T* z, const c64* beta, T* p_new, T* q,
+                          const typename Traits<T>::real* k,
+                          const typename Traits<T>::real* diag, int N, int nb, const int* active,
+                          c64* partials, hipStream_t s);
+// Galerkin faces of the next level: kc = 1/8 (sum of the 4 fine faces covered)
+void varcoef_coarsen(const double* kf, double* kc, int N, hipStream_t s);
+// diagonal (FP64 and FP32) and FP32 copy of the faces of one level
+void varcoef_diag(const double* k, double shift, int N, double* d64, float* d32, float* k32,
+                  hipStream_t s);
+// left half of aug (n x 2n row-major, n = N^3) = the dense operator
+void varcoef_dense(const double* k, const double* diag, int N, double* aug, hipStream_t s);
 
 // ----- complex lattice operators (Wilson 2-spin, block stencils, transfers) ---
 int wilson_residual_blocks(int N);

@@ -566,14 +566,14 @@ template int poisson_gs_tiles<double>(int);
 template <typename T>
 void poisson_dense_build(T* aug, int N, double d, double c, hipStream_t s) {
   const int n = N * N;
-  hipLaunchKernelGGL(k_dense_build<T>, dim3((unsigned)((n + 255) / 256), (unsigned)n),
+  MLMC_LAUNCH(k_dense_build<T>, dim3((unsigned)((n + 255) / 256), (unsigned)n),
                      dim3(256), 0, s, aug, N, (R_t<T>)d, (R_t<T>)c);
 }
 
 template <typename T>
 void poisson_apply(const T* x, T* y, int N, double d, double c, int nb, const int* active,
                    c64* partials, hipStream_t s) {
-  hipLaunchKernelGGL((k_apply_march<T, false>), dim3(march_blocks(N, nb)), dim3(kThreads), 0,
+  MLMC_LAUNCH((k_apply_march<T, false>), dim3(march_blocks(N, nb)), dim3(kThreads), 0,
                      s, x, x, (const c64*)nullptr, y, y, N, (R_t<T>)d, (R_t<T>)c, nb, active,
                      partials, timing_log());
 }
@@ -582,14 +582,14 @@ template <typename T>
 void poisson_update_apply(const T* p_old, const T* z, const c64* beta, T* p_new, T* q, int N,
                           double d, double c, int nb, const int* active, c64* partials,
                           hipStream_t s) {
-  hipLaunchKernelGGL((k_apply_march<T, true>), dim3(march_blocks(N, nb)), dim3(kThreads), 0, s,
+  MLMC_LAUNCH((k_apply_march<T, true>), dim3(march_blocks(N, nb)), dim3(kThreads), 0, s,
                      p_old, z, beta, p_new, q, N, (R_t<T>)d, (R_t<T>)c, nb, active, partials, timing_log());
 }
 
 template <typename Tb, typename Tx, typename Tr>
 void poisson_residual(const Tb* b, const Tx* x, Tr* r, int N, double d, double c, int nb,
                       const int* active, c64* partials, hipStream_t s) {
-  hipLaunchKernelGGL((k_residual_march<Tb, Tx, Tr>), dim3(march_blocks(N, nb)),
+  MLMC_LAUNCH((k_residual_march<Tb, Tx, Tr>), dim3(march_blocks(N, nb)),
                      dim3(kThreads), 0, s, b, x, r, N, (R_t<Tx>)d, (R_t<Tx>)c, nb, active,
                      partials, timing_log());
 }
@@ -607,20 +607,20 @@ void poisson_rbgs_fused(const T* xin, const T* b, T* xout, const T* ec, double o
     const T* xp = xin ? xin : b;
     const T* ep = ec ? ec : b;
     if (xin && ec)
-      hipLaunchKernelGGL((k_rbgs_march<T, true, true>), g, blk, 0, s, xp, b, xout, ep, wh, N, di,
+      MLMC_LAUNCH((k_rbgs_march<T, true, true>), g, blk, 0, s, xp, b, xout, ep, wh, N, di,
                          cc, f, nb, active, partials, timing_log());
     else if (xin)
-      hipLaunchKernelGGL((k_rbgs_march<T, true, false>), g, blk, 0, s, xp, b, xout, ep, wh, N,
+      MLMC_LAUNCH((k_rbgs_march<T, true, false>), g, blk, 0, s, xp, b, xout, ep, wh, N,
                          di, cc, f, nb, active, partials, timing_log());
     else if (ec)
-      hipLaunchKernelGGL((k_rbgs_march<T, false, true>), g, blk, 0, s, xp, b, xout, ep, wh, N,
+      MLMC_LAUNCH((k_rbgs_march<T, false, true>), g, blk, 0, s, xp, b, xout, ep, wh, N,
                          di, cc, f, nb, active, partials, timing_log());
     else
-      hipLaunchKernelGGL((k_rbgs_march<T, false, false>), g, blk, 0, s, xp, b, xout, ep, wh, N,
+      MLMC_LAUNCH((k_rbgs_march<T, false, false>), g, blk, 0, s, xp, b, xout, ep, wh, N,
                          di, cc, f, nb, active, partials, timing_log());
   } else {
     const int nbx = (N + GTX - 1) / GTX, nby = (N + GTY - 1) / GTY;
-    hipLaunchKernelGGL(k_rbgs_tile<T>, dim3(nbx * nby * nb), dim3(kThreads), 0, s, xin, b,
+    MLMC_LAUNCH(k_rbgs_tile<T>, dim3(nbx * nby * nb), dim3(kThreads), 0, s, xin, b,
                        xout, ec, (R_t<T>)(0.5 * omega), N, (R_t<T>)(1.0 / d), (R_t<T>)c,
                        reverse ? 1 : 0, nbx, nby, nb, active, partials, timing_log());
   }
@@ -629,20 +629,20 @@ void poisson_rbgs_fused(const T* xin, const T* b, T* xout, const T* ec, double o
 template <typename T>
 void poisson_residual_restrict(const T* b, const T* x, T* rc, int N, double d, double c,
                                int nb, const int* active, hipStream_t s) {
-  hipLaunchKernelGGL(k_res_restrict2<T>, dim3(march_blocks(N / 2, nb, RR)), dim3(kThreads), 0, s,
+  MLMC_LAUNCH(k_res_restrict2<T>, dim3(march_blocks(N / 2, nb, RR)), dim3(kThreads), 0, s,
                      b, x, rc, N, (R_t<T>)d, (R_t<T>)c, nb, active, timing_log());
 }
 
 template <typename T>
 void agg2d_restrict(const T* x, T* xc, int N, int nb, const int* active, hipStream_t s) {
-  hipLaunchKernelGGL(k_restrict2<T>, dim3(march_blocks(N / 2, nb)), dim3(kThreads), 0, s, x,
+  MLMC_LAUNCH(k_restrict2<T>, dim3(march_blocks(N / 2, nb)), dim3(kThreads), 0, s, x,
                      xc, N, nb, active);
 }
 
 template <typename T>
 void agg2d_prolong(const T* ec, T* x, int N, double omega, double beta, int nb,
                    const int* active, hipStream_t s) {
-  hipLaunchKernelGGL(k_prolong2<T>, dim3(march_blocks(N, nb)), dim3(kThreads), 0, s, ec, x, N,
+  MLMC_LAUNCH(k_prolong2<T>, dim3(march_blocks(N, nb)), dim3(kThreads), 0, s, ec, x, N,
                      (R_t<T>)(0.5 * omega), (R_t<T>)beta, nb, active);
 }
 

@@ -555,6 +555,11 @@ int*& timing_log() {
   return slot;
 }
 
+LaunchEvents*& timing_events() {
+  thread_local LaunchEvents* slot = nullptr;
+  return slot;
+}
+
 int reduce_blocks(int64_t n) {
   int64_t b = (n + 4 * kThreads - 1) / (4 * kThreads);
   if (b < 1) b = 1;
@@ -619,8 +624,8 @@ void cg_lastcorr(const c64* alpha, const c64* rz, const int* active, c64* lastco
 template <typename T>
 void cg_update_xr(T* x, T* r, const T* p, const T* q, const c64* alpha, int64_t n, int nb,
                   const int* active, c64* partials, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_xr<T>, dim3(reduce_blocks(n), nb), dim3(kThreads), 0, s, x, r, p,
-                     q, alpha, n, active, partials, timing_log());
+  MLMC_LAUNCH(k_cg_xr<T>, dim3(reduce_blocks(n), nb), dim3(kThreads), 0, s, x, r, p, q, alpha,
+              n, active, partials, timing_log());
 }
 template <typename T>
 void cg_update_p(T* p, const T* z, const c64* beta, int64_t n, int nb, const int* active,

@@ -32,6 +32,16 @@ def batch_problem_sizes(count=32, lo=32, hi=128, step=8, seed=7):
     return [int(v) for v in rng.choice(choices, size=count)]
 
 
+def varcoef_levels(N, max_coarse=512):
+    """Hierarchy depth of a 3D diffusion problem: halve the side while it is even
+    and the level still has more than max_coarse cells."""
+    L, side = 1, N
+    while side % 2 == 0 and side ** 3 > max_coarse:
+        side //= 2
+        L += 1
+    return L
+
+
 def wilson_mass(N):
     """m0 for the Wilson workload at lattice side N (tuned on the CPU so that the
     smallest |eigenvalue| is about 1e-2), or None if not tuned yet."""

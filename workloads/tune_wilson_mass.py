@@ -1,6 +1,6 @@
 """Tune m0 of the synthetic Wilson workloads so that the smallest |eigenvalue|
-of D is about 1e-2 (bisection on m0; eigenvalues from shift-invert Arnoldi of
-the CPU oracle's operator).  Writes workloads/wilson_mass.json.
+of D is about 1e-2 (shift steps on m0; eigenvalues from shift-invert Arnoldi
+of the CPU oracle's operator).  Writes workloads/wilson_mass.json.
 
 Run:  python workloads/tune_wilson_mass.py 256 512
 """
@@ -29,34 +29,22 @@ def smallest_eig(D):
     return vals[np.argmin(np.abs(vals))]
 
 
-def tune(N, sigma=0.5, seed=1):
-    """Largest m0 below the free-field value at which the smallest eigenvalue
-    (still in the right half plane) has modulus TARGET: bisection on the sign
-    of Re(lambda_min) - TARGET, starting from the free field (lambda_min = m0)."""
+def tune(N, sigma=0.5, seed=1, max_steps=8):
+    """m0 at which the smallest-modulus eigenvalue of D has modulus TARGET (and a
+    positive real part).  The mass only shifts the spectrum, D(m) = D(m') +
+    (m - m') I, so each step moves m0 by TARGET - Re(lambda_min): exact when the
+    same eigenvalue stays the one nearest to zero, a few steps otherwise.
+    Starts from the free field, where lambda_min = m0."""
     theta = gauge_field(N, sigma, seed)
-    hi = TARGET                     # free field would give exactly TARGET
-    lo = None
-    m = hi
-    while lo is None:
-        m -= 0.02
-        lam = smallest_eig(wilson2d(N, theta, m))
-        print("N=%d m0=%.5f lambda_min=%s" % (N, m, lam), flush=True)
-        if lam.real < TARGET:
-            lo = m
-        else:
-            hi = m
+    m = TARGET
     lam = None
-    for _ in range(25):
-        mid = 0.5 * (lo + hi)
-        lam = smallest_eig(wilson2d(N, theta, mid))
-        print("N=%d m0=%.7f lambda_min=%s" % (N, mid, lam), flush=True)
+    for _ in range(max_steps):
+        lam = smallest_eig(wilson2d(N, theta, m))
+        print("N=%d m0=%.7f lambda_min=%s" % (N, m, lam), flush=True)
         if abs(abs(lam) / TARGET - 1.0) < 0.02 and lam.real > 0:
-            break
-        if lam.real < TARGET:
-            lo = mid
-        else:
-            hi = mid
-    return mid, abs(lam)
+            return m, abs(lam)
+        m += TARGET - lam.real
+    raise RuntimeError("m0 tuning did not settle for N=%d" % N)
 
 
 if __name__ == "__main__":
