@@ -7,4 +7,5 @@ the trace-estimation arithmetic: neither the oracle nor the library is imported
 here, and both receive these arrays as plain inputs.
 """
 from .generate import (gauge_field, varcoef_faces, batch_problem_sizes,  # noqa: F401
-                       WORKLOADS, workload, wilson_mass)
+                       WORKLOADS, workload, wilson_mass, nn_init_weights,  # noqa: F401
+                       varcoef_levels)

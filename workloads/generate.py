@@ -42,6 +42,18 @@ def varcoef_levels(N, max_coarse=512):
     return L
 
 
+def nn_init_weights(seed=1):
+    """Initial weights of the learned smoother (3 layers of 3x3 convolutions,
+    8 -> 16 -> 16 -> 4 channels, flattened W1, W2, W3 with shape [Co, Ci, 3, 3]):
+    He-scaled normal draws (fan-in 9 Ci), the last layer scaled by 0.1."""
+    rng = np.random.default_rng(np.random.SeedSequence([0x6A09E667, 7, seed]))
+    out = []
+    for k, (co, ci) in enumerate(((16, 8), (16, 16), (4, 16))):
+        std = np.sqrt(2.0 / (9 * ci)) * (0.1 if k == 2 else 1.0)
+        out.append(rng.normal(0.0, std, size=(co, ci, 3, 3)).ravel())
+    return np.concatenate(out)
+
+
 def wilson_mass(N):
     """m0 for the Wilson workload at lattice side N (tuned on the CPU so that the
     smallest |eigenvalue| is about 1e-2), or None if not tuned yet."""
