@@ -114,7 +114,9 @@ typedef struct mlmc_options {
   int min_samples;    /* minimum estimates per level difference (5) */
   int64_t max_samples;/* per-level cap; exceeding it returns MLMC_ENOCONV */
   double tau;         /* > 0: use this tau instead of the 5-sample pilot */
-  int learned;        /* 1: learned smoother (WILSON2D), 0: plain */
+  int learned;        /* 1: learned smoother on the finest level (WILSON2D with
+                         MLMC_FP32_IR64, lattice side a multiple of 16); it
+                         takes effect once weights are set or trained.  0: plain */
 } mlmc_options;
 
 #define MLMC_MAX_LEVELS 16
@@ -260,6 +262,71 @@ int mlmc_set_timing(void* ctx, int mask, int stride);
  * algorithmic bytes (active columns only). */
 int mlmc_kernel_stats(void* ctx, int kernel, int fp64, double* out);
 int mlmc_reset_kernel_stats(void* ctx);
+
+/* ---------------------------------------------------------------------------
+ * Learned smoother (WILSON2D).  A 3-layer network of 3x3 periodic convolutions
+ * without bias (8 -> 16 -> 16 -> 4 channels, ReLU after the first two) maps, per
+ * lattice site, the residual scaled by its RMS s over the column (Re/Im of the
+ * two spin components) and cos/sin of the two link phases at the site to a
+ * correction s * (o0 + i o1, o2 + i o3) added to the iterate.  On the finest
+ * level the V-cycle becomes: Gauss-Seidel sweep, network, coarse correction,
+ * network, Gauss-Seidel sweep (two of the four plain sweeps replaced).  The
+ * network runs in BF16 with FP32 accumulation on MFMA.  The FP64 residual of
+ * the refinement loop stays the judge: a solve converges to solve_tol or fails
+ * exactly as without the network, so the estimate is unchanged in
+ * distribution.  If a refinement cycle with the network reduces some column's
+ * FP64 residual norm by less than a factor 2, the rest of that solve uses the
+ * plain smoother (a fallback, counted).
+ *
+ * Weights: MLMC_NN_WEIGHTS FP32 values, W1 [16][8][3][3], W2 [16][16][3][3],
+ * W3 [4][16][3][3] ([out channel][in channel][row offset][column offset],
+ * cross-correlation, offsets -1, 0, +1).
+ * ------------------------------------------------------------------------- */
+#define MLMC_NN_WEIGHTS 4032
+#define MLMC_NN_CROP 22      /* training crop side (output 16 x 16) */
+
+typedef struct mlmc_train_options {
+  int n_batches;        /* plain-multigrid solves used: n_batches * nb */
+  int crops_per_column; /* crops drawn per solved column and state (2 states) */
+  int steps;            /* Adam steps */
+  int batch;            /* crops per step (<= n_batches * nb * 2 * crops_per_column) */
+  double lr;            /* Adam learning rate (betas 0.9, 0.999, eps 1e-8) */
+  uint64_t seed;        /* probes (RNG stream 5) and crop positions */
+} mlmc_train_options;
+
+typedef struct mlmc_train_report {
+  double loss_first;    /* mean squared error of the first step */
+  double loss_last;     /* mean over the last min(10, steps) steps */
+  int64_t solves;       /* plain solves that produced training pairs */
+  int64_t crops;        /* crops in the training set */
+  double gen_seconds;   /* pair generation (solves, states, crops) */
+  double train_seconds; /* Adam steps */
+} mlmc_train_report;
+
+/* Train the network on pairs (r, e) from the method's own plain multigrid
+ * solves: Z4 right-hand sides b (stream 5), y = A^-1 b by the plain solver,
+ * and two states x per solve -- one Gauss-Seidel sweep from zero, and that plus
+ * the coarse-grid correction -- with r = b - A x and e = y - x, both scaled by
+ * the RMS of r, cut into crops of MLMC_NN_CROP^2 sites at positions drawn from
+ * `seed`.  w_init: host MLMC_NN_WEIGHTS initial weights.  The trained weights
+ * stay in ctx.  Errors: MLMC_EUNSUPPORTED for kinds other than WILSON2D or a
+ * lattice side not a multiple of 16; MLMC_EINVAL for bad options. */
+int mlmc_learned_train(void* ctx, const float* w_init, const mlmc_train_options* opt,
+                       mlmc_train_report* out);
+/* Set / read the network weights (host arrays of MLMC_NN_WEIGHTS floats). */
+int mlmc_learned_set_weights(void* ctx, const float* w);
+int mlmc_learned_get_weights(void* ctx, float* w);
+/* out[0] network applications (launches) and out[1] fallbacks to the plain
+ * smoother since setup. */
+int mlmc_learned_stats(void* ctx, int64_t* out);
+/* Building blocks for tests.  mlmc_nn_apply: e = correction of the network for
+ * residuals r (device, nrhs x n_1 complex as interleaved FP64, level 1).
+ * mlmc_nn_loss_grad: mean squared error and its gradient (host, FP32
+ * MLMC_NN_WEIGHTS) over ncrops crops: in device FP32 [ncrops][22][22][8]
+ * (rounded to BF16), target device FP32 [ncrops][16][16][4]. */
+int mlmc_nn_apply(void* ctx, int nrhs, const double* r, double* e);
+int mlmc_nn_loss_grad(void* ctx, int ncrops, const float* in, const float* target, double* loss,
+                      float* grad);
 
 /* Description of the last error on ctx (or of the last failed mlmc_setup
  * when ctx is NULL).  Valid until the next call on ctx. */

@@ -303,6 +303,65 @@ class TraceEstimator:
             self._ctx, int(level), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return out[:, 0::2] + 1j * out[:, 1::2]
 
+    # -- learned smoother (wilson2d) --
+    def learned_train(self, w_init, *, n_batches=8, crops_per_column=4, steps=500, batch=256,
+                      lr=1e-3, seed=1):
+        """Train the network on (residual, error) pairs from the plain solver;
+        returns the training report as a dict."""
+        w = np.ascontiguousarray(w_init, dtype=np.float32)
+        if w.size != _capi.NN_WEIGHTS:
+            raise ValueError("w_init must hold %d weights" % _capi.NN_WEIGHTS)
+        o = _capi.TrainOptions()
+        o.n_batches, o.crops_per_column = int(n_batches), int(crops_per_column)
+        o.steps, o.batch, o.lr, o.seed = int(steps), int(batch), float(lr), int(seed)
+        rep = _capi.TrainReport()
+        self._c(self._lib.mlmc_learned_train(
+            self._ctx, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(o),
+            ctypes.byref(rep)))
+        return {k: getattr(rep, k) for k, _ in _capi.TrainReport._fields_}
+
+    def set_nn_weights(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        if w.size != _capi.NN_WEIGHTS:
+            raise ValueError("weights must hold %d values" % _capi.NN_WEIGHTS)
+        self._c(self._lib.mlmc_learned_set_weights(
+            self._ctx, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+    def get_nn_weights(self):
+        w = np.zeros(_capi.NN_WEIGHTS, dtype=np.float32)
+        self._c(self._lib.mlmc_learned_get_weights(
+            self._ctx, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return w
+
+    def learned_stats(self):
+        """(network applications, fallbacks to the plain smoother) since setup."""
+        out = (ctypes.c_int64 * 2)()
+        self._c(self._lib.mlmc_learned_stats(self._ctx, out))
+        return int(out[0]), int(out[1])
+
+    def nn_apply(self, r):
+        """Correction of the network for residuals r [nrhs, 2 n_1] (interleaved
+        complex FP64 on the device)."""
+        e = self._vec(1, r.shape[0], r.device)
+        self._c(self._lib.mlmc_nn_apply(self._ctx, int(r.shape[0]), self._ptr(r), self._ptr(e)))
+        return e
+
+    def nn_loss_grad(self, inputs, targets):
+        """Mean squared error and weight gradient over crops: inputs [B, 22, 22, 8]
+        and targets [B, 16, 16, 4], FP32 device tensors."""
+        import torch
+        assert inputs.dtype == torch.float32 and targets.dtype == torch.float32
+        assert tuple(inputs.shape[1:]) == (22, 22, 8) and tuple(targets.shape[1:]) == (16, 16, 4)
+        assert inputs.is_cuda and targets.is_cuda
+        assert inputs.is_contiguous() and targets.is_contiguous()
+        loss = ctypes.c_double()
+        grad = np.zeros(_capi.NN_WEIGHTS, dtype=np.float32)
+        self._c(self._lib.mlmc_nn_loss_grad(
+            self._ctx, int(inputs.shape[0]), ctypes.c_void_p(inputs.data_ptr()),
+            ctypes.c_void_p(targets.data_ptr()),
+            ctypes.byref(loss), grad.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return loss.value, grad
+
 
 def run_estimator(levels, sample, tol, *, pilot=None, coarse=0.0, cost=None, **options):
     """Host-side estimator over a Python sampler (no device use).

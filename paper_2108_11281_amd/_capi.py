@@ -65,6 +65,22 @@ class Result(ctypes.Structure):
                 ("seconds", ctypes.c_double), ("max_stated_error", ctypes.c_double)]
 
 
+NN_WEIGHTS = 4032
+NN_CROP = 22
+
+
+class TrainOptions(ctypes.Structure):
+    _fields_ = [("n_batches", ctypes.c_int), ("crops_per_column", ctypes.c_int),
+                ("steps", ctypes.c_int), ("batch", ctypes.c_int), ("lr", ctypes.c_double),
+                ("seed", ctypes.c_uint64)]
+
+
+class TrainReport(ctypes.Structure):
+    _fields_ = [("loss_first", ctypes.c_double), ("loss_last", ctypes.c_double),
+                ("solves", ctypes.c_int64), ("crops", ctypes.c_int64),
+                ("gen_seconds", ctypes.c_double), ("train_seconds", ctypes.c_double)]
+
+
 SAMPLE_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int64,
                              ctypes.c_int64, ctypes.POINTER(ctypes.c_double))
 PILOT_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int64,
@@ -75,6 +91,7 @@ FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 _P = ctypes.c_void_p
 _D = ctypes.POINTER(ctypes.c_double)
 _I64 = ctypes.POINTER(ctypes.c_int64)
+_F = ctypes.POINTER(ctypes.c_float)
 
 # name: (restype, argtypes)
 SIGNATURES = {
@@ -105,6 +122,13 @@ SIGNATURES = {
     "mlmc_set_timing": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
     "mlmc_kernel_stats": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _D]),
     "mlmc_reset_kernel_stats": (ctypes.c_int, [_P]),
+    "mlmc_learned_train": (ctypes.c_int, [_P, _F, ctypes.POINTER(TrainOptions),
+                                          ctypes.POINTER(TrainReport)]),
+    "mlmc_learned_set_weights": (ctypes.c_int, [_P, _F]),
+    "mlmc_learned_get_weights": (ctypes.c_int, [_P, _F]),
+    "mlmc_learned_stats": (ctypes.c_int, [_P, _I64]),
+    "mlmc_nn_apply": (ctypes.c_int, [_P, ctypes.c_int, _P, _P]),
+    "mlmc_nn_loss_grad": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _D, _F]),
     "mlmc_last_error": (ctypes.c_char_p, [_P]),
     "mlmc_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "mlmc_destroy": (None, [_P]),

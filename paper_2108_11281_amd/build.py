@@ -15,8 +15,10 @@ SOURCES = [
     "kernels_wilson.hip",
     "kernels_krylov.hip",
     "kernels_varcoef.hip",
+    "kernels_nn.hip",
     "context.cpp",
     "context_complex.cpp",
+    "context_nn.cpp",
     "estimator.cpp",
     "capi.cpp",
 ]

@@ -207,6 +207,54 @@ int mlmc_set_allocator(mlmc_alloc_fn alloc, mlmc_free_fn free_fn, void* user) {
   return MLMC_OK;
 }
 
+int mlmc_learned_train(void* c, const float* w_init, const mlmc_train_options* opt,
+                       mlmc_train_report* out) {
+  Context* ctx = as_ctx(c);
+  if (!ctx || !w_init || !opt) return MLMC_EINVAL;
+  return guarded(ctx, [&] {
+    for (int i = 0; i < MLMC_NN_WEIGHTS; ++i)
+      MLMC_REQUIRE(std::isfinite(w_init[i]), MLMC_EINVAL, "initial weights must be finite");
+    ctx->nn_train(w_init, *opt, out);
+  });
+}
+
+int mlmc_learned_set_weights(void* c, const float* w) {
+  Context* ctx = as_ctx(c);
+  if (!ctx || !w) return MLMC_EINVAL;
+  return guarded(ctx, [&] {
+    for (int i = 0; i < MLMC_NN_WEIGHTS; ++i)
+      MLMC_REQUIRE(std::isfinite(w[i]), MLMC_EINVAL, "weights must be finite");
+    ctx->nn_set_weights(w);
+  });
+}
+
+int mlmc_learned_get_weights(void* c, float* w) {
+  Context* ctx = as_ctx(c);
+  if (!ctx || !w) return MLMC_EINVAL;
+  return guarded(ctx, [&] { ctx->nn_get_weights(w); });
+}
+
+int mlmc_learned_stats(void* c, int64_t* out) {
+  Context* ctx = as_ctx(c);
+  if (!ctx || !out) return MLMC_EINVAL;
+  out[0] = ctx->nn_stats[0];
+  out[1] = ctx->nn_stats[1];
+  return MLMC_OK;
+}
+
+int mlmc_nn_apply(void* c, int nrhs, const double* r, double* e) {
+  Context* ctx = as_ctx(c);
+  if (!ctx || !r || !e) return MLMC_EINVAL;
+  return guarded(ctx, [&] { ctx->nn_apply_fp64(nrhs, r, e); });
+}
+
+int mlmc_nn_loss_grad(void* c, int ncrops, const float* in, const float* target, double* loss,
+                      float* grad) {
+  Context* ctx = as_ctx(c);
+  if (!ctx || !in || !target || !loss || !grad) return MLMC_EINVAL;
+  return guarded(ctx, [&] { ctx->nn_loss_grad(ncrops, in, target, loss, grad); });
+}
+
 int mlmc_counters(void* c, int64_t* out, int n) {
   Context* ctx = as_ctx(c);
   if (!ctx || !out || n < 0 || n > 4) return MLMC_EINVAL;

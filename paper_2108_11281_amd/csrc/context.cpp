@@ -40,6 +40,10 @@ Context::Context(const mlmc_operator& A, const mlmc_hierarchy& h, const mlmc_opt
   MLMC_REQUIRE(o.nu_pre >= 0 && o.nu_post >= 0, MLMC_EINVAL, "negative sweep count");
   MLMC_REQUIRE(o.min_samples >= 2, MLMC_EINVAL, "min_samples must be >= 2");
   MLMC_REQUIRE(o.alloc >= 0 && o.alloc <= 2, MLMC_EINVAL, "unknown allocation rule");
+  MLMC_REQUIRE(!o.learned || (A.kind == MLMC_WILSON2D && o.precision == MLMC_FP32_IR64 &&
+                              A.n_side % 16 == 0),
+               MLMC_EUNSUPPORTED,
+               "the learned smoother needs WILSON2D, MLMC_FP32_IR64 and a side divisible by 16");
   try {
     switch (kind_) {
       case MLMC_POISSON2D:
@@ -101,6 +105,16 @@ void* Context::dalloc(size_t bytes) {
   }
   allocs_.push_back(p);
   return p;
+}
+
+void Context::dfree(void* p) {
+  if (!p) return;
+  auto it = std::find(allocs_.begin(), allocs_.end(), p);
+  if (it == allocs_.end()) return;
+  MLMC_HIP(hipStreamSynchronize(s_));
+  allocs_.erase(it);
+  if (hooks_.free_fn) hooks_.free_fn(p, hooks_.user);
+  else (void)hipFree(p);
 }
 
 template <> Work<float>& Context::work<float>() { return w32_; }

@@ -83,6 +83,13 @@ class Context {
                    double* out);
   void export_coarse(int which, double* out);
   void export_prolongation(int level, double* out);
+  // learned smoother (WILSON2D)
+  void nn_train(const float* w_init, const mlmc_train_options& o, mlmc_train_report* rep);
+  void nn_set_weights(const float* w);
+  void nn_get_weights(float* w);
+  void nn_apply_fp64(int nrhs, const double* r, double* e);
+  void nn_loss_grad(int ncrops, const float* in, const float* tgt, double* loss, float* grad);
+  int64_t nn_stats[2] = {0, 0};  // network applications, fallbacks
 
   int levels_mlmc() const { return L_; }
   int levels_solver() const { return Ls_; }
@@ -107,6 +114,7 @@ class Context {
 
  private:
   void* dalloc(size_t bytes);
+  void dfree(void* p);  // synchronises the stream, then releases p
   template <typename T> T* dalloc_n(int64_t count) {
     return static_cast<T*>(dalloc(sizeof(T) * (size_t)count));
   }
@@ -114,6 +122,10 @@ class Context {
   void build_varcoef(const double* k);
   void finish_real_build();
   void build_wilson(const double* theta);
+  void nn_alloc();
+  void nn_require() const;
+  // r = b - A_1 x ; x += s * net(r / s)  (finest level, FP32 / complex64)
+  void nn_step(const c32* b, c32* x, int nb, const int* act);
   void alloc_common();
   // complex operators: op on level l in precision T (c32 / c64)
   template <typename T> const T* links(int l) const;
@@ -216,6 +228,13 @@ class Context {
   Fgmres<c64> fg64_;
   bool complex_ = false;
   bool varcoef_ = false;
+  // learned smoother state: FP32 master weights, Adam moments, gradient, BF16
+  // fragments, BF16 link features; nn_use_ is true while a solve runs with it
+  bool nn_ready_ = false, nn_use_ = false;
+  float *nn_w_ = nullptr, *nn_m_ = nullptr, *nn_v_ = nullptr, *nn_g_ = nullptr;
+  void *nn_frag_ = nullptr, *nn_links_ = nullptr;
+  double* theta_dev_ = nullptr;
+  double* nn_loss_ = nullptr;
   int m_ = 16;                    // FGMRES restart length
   double omega_ = 1.0;            // coarse-correction scaling in use
   // FGMRES scalars: Hessenberg, rotations, rhs, solution, dims, cycle flags
@@ -234,9 +253,9 @@ class Context {
   int64_t partials_cap_ = 0;
   // per-column scalar arrays (nb_ entries each); kErr1..kQb are consecutive
   enum { kRr0, kRz, kTmp, kAlpha, kBeta, kBb, kBd, kRres, kRres2, kErr1, kErr2, kQa, kQb,
-         kNumScalars };
+         kNn, kNumScalars };
   c64* scal_[kNumScalars] = {};
-  int *act_outer_ = nullptr, *act_inner_ = nullptr, *count_dev_ = nullptr;
+  int *act_outer_ = nullptr, *act_inner_ = nullptr, *count_dev_ = nullptr;  // count_dev_: 4 ints
   int* count_host_ = nullptr;
   c64* host_c64_ = nullptr;  // pinned, 8*nb
   int* piv_ = nullptr;

@@ -70,6 +70,7 @@ void Context::build_wilson(const double* theta) {
   // links
   double* th = dalloc_n<double>(2 * (int64_t)N * N);
   MLMC_HIP(hipMemcpyAsync(th, theta, sizeof(double) * 2 * N * N, hipMemcpyHostToDevice, s_));
+  theta_dev_ = th;
   lv_[0].U64 = dalloc_n<c64>(2 * (int64_t)N * N);
   lv_[0].U32 = dalloc_n<c32>(2 * (int64_t)N * N);
   wilson_links(th, lv_[0].U64, lv_[0].U32, N, s_);
@@ -226,6 +227,21 @@ void Context::cvcycle(int l, const T* b, T* x, int nb, const int* act) {
     dense_apply<T>(w.ainvT, b, x, (int)n, nb, act, s_);
     return;
   }
+  if constexpr (std::is_same<T, c32>::value) {
+    if (l == 1 && nn_use_) {
+      // learned finest level: sweep, network | coarse correction | network, sweep
+      T* res = w.vt[0];
+      cop_smooth<T>(l, b, x, nb, act, true, false);
+      nn_step(b, x, nb, act);
+      cop_residual<T, T, T>(l, b, x, res, nb, act, nullptr);
+      cop_restrict<T>(l, res, w.vb[1], nb, act);
+      cvcycle<T>(2, w.vb[1], w.vx[1], nb, act);
+      cop_prolong<T>(l, w.vx[1], x, nb, act, omega_, 1.0);
+      nn_step(b, x, nb, act);
+      cop_smooth<T>(l, b, x, nb, act, false, true);
+      return;
+    }
+  }
   const int pre = opt_.nu_pre, post = opt_.nu_post;
   if (pre == 0) vec_zero<T>(x, n, nb, act, s_);
   for (int i = 0; i < pre; ++i) cop_smooth<T>(l, b, x, nb, act, i == 0, false);
@@ -304,6 +320,15 @@ void Context::solve_complex(int l, const c64* b, c64* y, int nb, c64* err) {
   vec_copy<c64>(bb, rr_old, 1, nb, nullptr, s_);
   c64* res64 = reinterpret_cast<c64*>(r64_);
   const bool fp32 = opt_.precision == MLMC_FP32_IR64;
+  // the learned smoother runs on the finest level of FP32 solves; the FP64
+  // residual below stays the judge, and a cycle that reduces some column's
+  // residual norm by less than 2x switches the rest of this solve to the plain
+  // smoother
+  nn_use_ = nn_ready_ && opt_.learned && fp32 && l == 1;
+  struct Reset {
+    bool& f;
+    ~Reset() { f = false; }
+  } reset{nn_use_};
   const double inner = fp32 ? std::max(opt_.inner_tol, 1e-6) : std::max(opt_.inner_tol, 1e-12);
   bool have_corr = false;
   for (int it = 0; it <= opt_.max_refine * 4; ++it) {
@@ -314,10 +339,27 @@ void Context::solve_complex(int l, const c64* b, c64* y, int nb, c64* err) {
       cop_residual<c64, c64, c64>(l, b, y, fg64_.r, nb, act_outer_, partials_);
     finish_sums(partials_, rblk, nb, rr_new, s_);
     if (have_corr) ir_stated_error(bd, rr_old, rr_new, act_outer_, err, nb, s_);
+    const bool guard = nn_use_ && have_corr;
+    if (guard) {
+      // columns that met a 2x norm reduction (or the tolerance) vs. all active
+      refine_due(rr_new, rr_old, bb, 0.25, tol * tol, act_outer_, nb, count_dev_ + 2, s_);
+      count_active(act_outer_, nb, count_dev_ + 3, s_);
+    }
     select_active(rr_old, rr_new, act_outer_, nb, s_);
     mark_converged(rr_new, bb, tol * tol, act_outer_, nb, count_dev_, s_);
     counters[1] += 1;
-    if (read_count() == 0) break;
+    if (guard) {
+      MLMC_HIP(hipMemcpyAsync(count_host_, count_dev_, 4 * sizeof(int), hipMemcpyDeviceToHost,
+                              s_));
+      MLMC_HIP(hipStreamSynchronize(s_));
+      if (count_host_[2] < count_host_[3]) {
+        nn_use_ = false;
+        nn_stats[1] += 1;
+      }
+      if (count_host_[0] == 0) break;
+    } else if (read_count() == 0) {
+      break;
+    }
     MLMC_HIP(hipMemcpyAsync(act_inner_, act_outer_, sizeof(int) * nb, hipMemcpyDeviceToDevice,
                             s_));
     if (fp32) {
@@ -339,5 +381,9 @@ template void Context::cop_residual<c64, c64, c64>(int, const c64*, const c64*, 
                                                    const int*, c64*);
 template void Context::cop_restrict<c64>(int, const c64*, c64*, int, const int*);
 template void Context::cop_prolong<c64>(int, const c64*, c64*, int, const int*, double, double);
+template void Context::cop_residual<c32, c32, c32>(int, const c32*, const c32*, c32*, int,
+                                                   const int*, c64*);
+template void Context::cop_smooth<c64>(int, const c64*, c64*, int, const int*, bool, bool);
+template void Context::cvcycle<c64>(int, const c64*, c64*, int, const int*);
 
 }  // namespace mlmc

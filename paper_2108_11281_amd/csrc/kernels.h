@@ -92,6 +92,9 @@ void cg_update_p(T* p, const T* z, const c64* beta, int64_t n, int nb,
 template <typename T64, typename T32>
 void ir_accumulate(T64* y, const T32* d, int64_t n, int nb, const int* active,
                    hipStream_t s);
+// out = a - b
+template <typename T>
+void vec_sub(const T* a, const T* b, T* out, int64_t n, int nb, hipStream_t s);
 // y += a[k] * x  (column scalars)
 template <typename T>
 void vec_axpy_cols(T* y, const T* x, const c64* a, int64_t n, int nb,
@@ -206,6 +209,34 @@ void varcoef_diag(const double* k, double shift, int N, double* d64, float* d32,
                   hipStream_t s);
 // left half of aug (n x 2n row-major, n = N^3) = the dense operator
 void varcoef_dense(const double* k, const double* diag, int N, double* aug, hipStream_t s);
+
+// ----- learned smoother (2-spin lattice; N a multiple of 16) --------------------
+// weights: 4032 FP32 values, W1 [16][8][3][3], W2 [16][16][3][3], W3 [4][16][3][3]
+int nn_num_weights();
+int nn_frag_count();          // packed BF16 B fragments (16 bytes each)
+int nn_crop_in_elems();       // BF16 per training-crop input (22 * 22 * 8)
+int nn_crop_out_elems();      // FP32 per training-crop target (16 * 16 * 4)
+int nn_crop_side();           // 22
+// link features (cos, sin of theta_mu) in BF16 [site][4]; theta [2][N][N] FP64
+void nn_links(const double* theta, void* links, int N, hipStream_t s);
+// BF16 B fragments of the three layers from the FP32 master weights
+void nn_pack(const float* w, void* frag, hipStream_t s);
+// x += s * net(r / s), s^2 = rr[k].re * inv_n per column (skipped when 0)
+void nn_apply(const c32* r, c32* x, const c64* rr, double inv_n, const void* links,
+              const void* frag, int N, int nb, const int* active, hipStream_t s);
+// forward + backward of ncrops crops (crop order[i], or i when order is null):
+// per-crop gradients, then grad = their fixed-order sum and *loss = the mean
+// squared error
+void nn_train_step(const void* in, const float* tgt, const int* order, int ncrops,
+                   const void* frag, const float* w, float* gpart, double* lpart, float* grad,
+                   double* loss, hipStream_t s);
+// Adam step t (from 1) on the FP32 master weights
+void nn_adam(float* w, float* m, float* v, const float* g, double lr, double b1, double b2,
+             double eps, int t, hipStream_t s);
+// training crops from FP64 residual / error fields (origin: column, y0, x0 per crop)
+void nn_crops(const c64* r, const c64* e, const c64* rr, double inv_n, const void* links,
+              const int* origin, int ncrops, int N, void* in, float* tgt, hipStream_t s);
+void nn_round_inputs(const float* src, void* dst, int64_t count, hipStream_t s);
 
 // ----- complex lattice operators (Wilson 2-spin, block stencils, transfers) ---
 int wilson_residual_blocks(int N);

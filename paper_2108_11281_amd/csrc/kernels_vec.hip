@@ -28,6 +28,15 @@ __global__ void k_convert(const From* x, To* y, int64_t n, const int* active) {
   if (i < n) y[(int64_t)k * n + i] = convert<To, From>(x[(int64_t)k * n + i]);
 }
 
+template <typename T>
+__global__ void k_sub(const T* a, const T* b, T* out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i < n) {
+    const int64_t j = (int64_t)blockIdx.y * n + i;
+    out[j] = a[j] - b[j];
+  }
+}
+
 // grid (nblk, nb): block b of column k reduces a contiguous chunk
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_dot(const T* x, const T* y, int64_t n,
@@ -543,6 +552,11 @@ void vec_copy(const T* x, T* y, int64_t n, int nb, const int* active, hipStream_
   hipLaunchKernelGGL((k_convert<T, T>), grid_cols(n, nb), dim3(kThreads), 0, s, x, y, n,
                      active);
 }
+template <typename T>
+void vec_sub(const T* a, const T* b, T* out, int64_t n, int nb, hipStream_t s) {
+  if (n <= 0 || nb <= 0) return;
+  hipLaunchKernelGGL(k_sub<T>, grid_cols(n, nb), dim3(kThreads), 0, s, a, b, out, n);
+}
 template <typename To, typename From>
 void vec_convert(const From* x, To* y, int64_t n, int nb, const int* active, hipStream_t s) {
   if (n <= 0 || nb <= 0) return;
@@ -715,6 +729,7 @@ void dense_apply(const T* At, const T* B, T* Z, int n, int nb, const int* active
 #define MLMC_INST_T(T)                                                                    \
   template void vec_zero<T>(T*, int64_t, int, const int*, hipStream_t);                  \
   template void vec_copy<T>(const T*, T*, int64_t, int, const int*, hipStream_t);        \
+  template void vec_sub<T>(const T*, const T*, T*, int64_t, int, hipStream_t);           \
   template void vec_dot_partials<T>(const T*, const T*, int64_t, int, const int*, c64*,  \
                                     hipStream_t);                                        \
   template void cg_update_xr<T>(T*, T*, const T*, const T*, const c64*, int64_t, int,    \

@@ -36,6 +36,9 @@ def test_struct_sizes_match_header_layout():
     # 2 doubles
     assert ctypes.sizeof(_capi.Result) == 8 * (6 + 1 + 16 + 32 + 16 + 16 + 16 + 2 + 2)
     assert ctypes.sizeof(_capi.Options) == 96
+    # mlmc_train_options: 4 ints, a double, a uint64; mlmc_train_report: 6 x 8 bytes
+    assert ctypes.sizeof(_capi.TrainOptions) == 32
+    assert ctypes.sizeof(_capi.TrainReport) == 48
 
 
 def test_default_options_and_status_strings():
@@ -48,6 +51,10 @@ def test_null_arguments_are_rejected():
     lib = m.lib()
     assert lib.mlmc_trace(None, 1e-2, 1, None) == -1
     assert lib.mlmc_setup(None, None, None, None, None) == -1
+    assert lib.mlmc_learned_train(None, None, None, None) == -1
+    assert lib.mlmc_learned_set_weights(None, None) == -1
+    assert lib.mlmc_nn_apply(None, 1, None, None) == -1
+    assert lib.mlmc_nn_loss_grad(None, 1, None, None, None, None) == -1
 
 
 class MockSampler:

@@ -1,0 +1,163 @@
+"""GPU checks of the learned smoother: BF16 MFMA inference and gradients against
+the FP64 oracle (oracle/nn.py), training on the method's own solves, the FP64
+residual as the judge (samples unchanged), and the fallback to the plain
+smoother."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import hierarchy, mlmc, nn
+from tests.gpu_util import from_dev, quad_scale, require_gpu, to_dev
+from workloads import gauge_field, nn_init_weights, wilson_mass
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def bf16_round(a):
+    """Round to the nearest BF16 value (ties to even), returned as float32."""
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000).astype(np.uint32)
+    return r.view(np.float32)
+
+
+def rel_l2(a, b):
+    return np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b))
+
+
+def cosine(a, b):
+    a, b = np.ravel(a), np.ravel(b)
+    return float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
+
+
+def _est(N, levels, m0, theta, learned=False, nb=16, **kw):
+    require_gpu()
+    import paper_2108_11281_amd as m
+    kw.setdefault("solve_tol", 1e-12)
+    return m.TraceEstimator("wilson2d", N, levels, levels, mass=m0, field=theta, block=4,
+                            n_vec=8, setup_sweeps=6, setup_seed=1, precision="fp32_ir64",
+                            nb=nb, nu_pre=2, nu_post=2, learned=1 if learned else 0, **kw)
+
+
+def test_bf16_round_helper():
+    x = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, -2.5, 3.0e-3], dtype=np.float32)
+    r = bf16_round(x)
+    assert r[0] == 1.0 and r[1] == 1.0 and r[2] == np.float32(1.0 + 2 ** -6) and r[3] == -2.5
+    assert abs(r[4] - 3.0e-3) <= 3.0e-3 * 2 ** -8
+
+
+def test_inference_matches_oracle():
+    N = 32
+    th = gauge_field(N, seed=2)
+    est = _est(N, 2, 0.1, th, nb=4)
+    w = bf16_round(nn_init_weights(3) * 1.5)
+    est.set_nn_weights(w)
+    rng = np.random.default_rng(5)
+    R = rng.standard_normal((3, 2 * N * N)) + 1j * rng.standard_normal((3, 2 * N * N))
+    E = from_dev(est.nn_apply(to_dev(R)), complex_=True)
+    for k in range(3):
+        ref = nn.correction(R[k], th, N, w.astype(np.float64))
+        assert rel_l2(E[k], ref) <= 2e-2, rel_l2(E[k], ref)
+    # positive homogeneity survives the BF16 path up to rounding
+    E2 = from_dev(est.nn_apply(to_dev(4.0 * R[:1])), complex_=True)
+    assert rel_l2(E2[0], 4.0 * E[0]) <= 1e-6
+
+
+def test_loss_and_gradient_match_oracle():
+    import torch
+    N = 32
+    est = _est(N, 2, 0.1, gauge_field(N, seed=2), nb=4)
+    rng = np.random.default_rng(6)
+    B = 6
+    X = bf16_round(rng.standard_normal((B, 22, 22, 8)))
+    T = rng.standard_normal((B, 16, 16, 4)).astype(np.float32)
+    w = bf16_round(nn_init_weights(4) * 2.0)
+    est.set_nn_weights(w)
+    loss, grad = est.nn_loss_grad(torch.tensor(X, device="cuda"),
+                                  torch.tensor(T, device="cuda"))
+    ref_loss, ref_grad = nn.loss_and_grad(X.transpose(0, 3, 1, 2).astype(np.float64),
+                                          T.transpose(0, 3, 1, 2).astype(np.float64),
+                                          w.astype(np.float64))
+    assert abs(loss - ref_loss) <= 1e-2 * ref_loss, (loss, ref_loss)
+    assert rel_l2(grad, ref_grad) <= 2e-2, rel_l2(grad, ref_grad)
+    assert cosine(grad, ref_grad) >= 0.999
+    # each layer's block separately (the last layer has the fewest terms)
+    for lo, hi in ((0, 1152), (1152, 3456), (3456, 4032)):
+        assert cosine(grad[lo:hi], ref_grad[lo:hi]) >= 0.999, (lo, hi)
+
+
+@pytest.fixture(scope="module")
+def trained():
+    N, levels = 64, 3
+    m0 = wilson_mass(N)
+    th = gauge_field(N, seed=1)
+    est = _est(N, levels, m0, th, learned=True, nb=32)
+    rep = est.learned_train(nn_init_weights(1), n_batches=4, crops_per_column=4, steps=800,
+                            batch=128, lr=2e-3, seed=9)
+    return dict(N=N, levels=levels, m0=m0, th=th, est=est, rep=rep, w=est.get_nn_weights())
+
+
+def test_training_reduces_loss(trained):
+    rep = trained["rep"]
+    assert rep["solves"] == 4 * 32 and rep["crops"] == 4 * 32 * 2 * 4
+    # the error's smooth part is not predictable from a 7 x 7 neighbourhood, so
+    # the loss floor is high; the network still has to learn its local part
+    assert np.isfinite(rep["loss_last"]) and rep["loss_last"] < 0.9 * rep["loss_first"], rep
+
+
+def test_learned_solves_are_judged_and_samples_unchanged(trained):
+    N, levels, m0, th = trained["N"], trained["levels"], trained["m0"], trained["th"]
+    est = trained["est"]
+    plain = _est(N, levels, m0, th, learned=False, nb=32)
+    B = est.probes(1, 21, 0, 16)
+    Y, rel = est.solve(1, B)
+    assert np.all(rel <= 1e-12)
+    it_learned = est.counters()[0]
+    Yp, relp = plain.solve(1, B)
+    it_plain = plain.counters()[0]
+    assert np.all(relp <= 1e-12)
+    y, yp = from_dev(Y, True), from_dev(Yp, True)
+    assert np.max(np.abs(y - yp)) <= 1e-9 * np.max(np.abs(yp))
+    apps, fallbacks = est.learned_stats()
+    assert apps > 0
+    # level-difference samples with the network equal the oracle's exact ones
+    A, P = hierarchy.wilson_hierarchy(N, th, m0, levels, block=4, n_vec=8, sweeps=6, seed=1)
+    orc = mlmc.LevelSampler(A, P, complex_probe=True)
+    s = est.sample_level(1, 7, 0, 8)
+    ref = orc.sample(1, 7, 0, 8)
+    scale = quad_scale(orc.sample_parts(1, 7, 0, 8))
+    assert np.all(np.abs(s - ref) <= 1e-8 * scale)
+    # what the trained network gains (or loses) per solve on this operator
+    out = dict(N=N, m0=m0, fgmres_iterations_plain=int(it_plain),
+               fgmres_iterations_learned=int(it_learned), fallbacks=int(fallbacks),
+               loss_first=trained["rep"]["loss_first"], loss_last=trained["rep"]["loss_last"])
+    print("learned-smoother gain:", json.dumps(out))
+    d = os.path.join(ROOT, "gpurun_out")
+    if os.path.isdir(d):
+        with open(os.path.join(d, "learned_gain.json"), "w") as f:
+            json.dump(out, f)
+
+
+def test_bad_network_falls_back_and_still_converges(trained):
+    N, levels, m0, th = trained["N"], trained["levels"], trained["m0"], trained["th"]
+    est = _est(N, levels, m0, th, learned=True, nb=16)
+    est.set_nn_weights(trained["w"] * 50.0)
+    B = est.probes(1, 3, 0, 16)
+    _, rel = est.solve(1, B)
+    assert np.all(rel <= 1e-12)
+    apps, fallbacks = est.learned_stats()
+    assert apps > 0 and fallbacks >= 1, (apps, fallbacks)
+
+
+def test_learned_option_is_validated():
+    import paper_2108_11281_amd as m
+    require_gpu()
+    with pytest.raises(m.MLMCError):
+        m.TraceEstimator("poisson2d", 64, 3, 3, learned=1)
+    with pytest.raises(m.MLMCError):   # side not a multiple of 16
+        m.TraceEstimator("wilson2d", 40, 2, 2, mass=0.1, field=gauge_field(40), block=4,
+                         n_vec=8, learned=1)
