@@ -1,23 +1,35 @@
 #!/usr/bin/env python3
 """Time-to-tr(A^-1) benchmark of the MI355X multilevel Monte-Carlo trace estimator.
 
-Workload (default): 2D Poisson 5-point operator on a 1024 x 1024 Dirichlet grid
-(n = 1,048,576), 6-level 2x2 aggregation hierarchy (coarsest 32^2 inverted
-densely), 128 Rademacher right-hand sides per launch, FP32 Krylov + V-cycle
-inside FP64 iterative refinement to a 1e-10 relative residual, MLMC to relative
-error 1e-3 with the optimal (Giles) allocation.  One step = one complete
-mlmc_trace call (pilot, all level differences, coarsest term) with a fresh seed;
-all data is generated on the device.
+Workloads (--workload):
+  poisson1024 (default): 2D Poisson 5-point operator on a 1024 x 1024 Dirichlet
+    grid (n = 1,048,576), 6-level 2x2 aggregation hierarchy (coarsest 32^2
+    inverted densely), 128 Rademacher right-hand sides per launch, FP32 Krylov +
+    V-cycle inside FP64 refinement to a 1e-10 relative residual, MLMC to
+    relative error 1e-3 with the optimal (Giles) allocation.  One step = one
+    complete mlmc_trace call (pilot, all level differences, coarsest term) with
+    a fresh seed; all data is generated on the device.
+  wilson256: the Wilson-like 2-spin operator on a 256^2 periodic lattice
+    (U(1) phases ~ N(0, 0.5^2), mass at |lambda_min| ~ 1e-2), 3 levels of 4x4
+    aggregates with 8 test vectors, Z4 probes, complex64 FGMRES inside complex128
+    refinement, MLMC to 1e-3.
+  wilson512: the same operator on 512^2 with 4 solver levels (3 MLMC levels);
+    the learned smoother (trained first, on the method's own plain solves)
+    replaces two of the four finest-level sweeps.  value = learned + FP32 time
+    per trace; the plain FP32 and plain FP64 MLMC times are in `compare`.
+  varcoef_batch: 32 uneven 3D diffusion problems (log-normal faces, sides
+    32..128) sampled concurrently; one step = 64 level-1 samples of every
+    problem (128 solves each); value = aggregate solves/s.
 
 Printed JSON line: the contract fields plus `roofline` (the dominant kernel,
-timed with HIP events on the library's stream during the timed steps),
+timed with HIP events carried in its own dispatches during the timed steps),
 `cpu_baseline` (the FP64 CPU oracle on a bounded sample, extrapolated with the
-GPU run's sample counts), and the plain-FP64 MLMC / FP64 Hutchinson
-comparisons measured outside the timed region.
+GPU run's sample counts; the oracle also supplies the exact trace of the
+Poisson workload for the accuracy report), and comparisons measured outside the
+timed region.
 """
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -27,6 +39,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
 METRIC = "time-to-tr(A^-1) at rel err 1e-3 (learned+FP32 vs plain FP64 MLMC); HBM GB/s"
 GS_SOURCE = os.path.join(ROOT, "paper_2108_11281_amd", "csrc", "kernels_poisson.hip")
 GS_TRAFFIC = os.path.join(ROOT, "profiles", "rbgs_sweep_poisson1024_traffic.md")
@@ -36,10 +49,12 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+# ---------------------------------------------------------------------------
+# CPU oracle leg (the only part of this script that uses oracle/)
+# ---------------------------------------------------------------------------
 def cpu_baseline(n_samples, N, L, budget_s=12.0):
     """FP64 CPU oracle time per trace: per-sample time of each level difference
     on a bounded sample, scaled by the GPU run's per-level sample counts."""
-    import numpy as np  # noqa: F401
     from oracle import mlmc
     orc = mlmc.PoissonDSTSampler(N, L)
     per_level = []
@@ -61,13 +76,45 @@ def cpu_baseline(n_samples, N, L, budget_s=12.0):
     t_c = time.perf_counter() - coarse_t0
     total = sum(n * per_level[l][1] for l, n in enumerate(n_samples)) + 5 * t_h + t_c
     sample = ", ".join("l%d: %d samples" % (l + 1, per_level[l][0]) for l in range(L - 1))
-    return dict(value=total, unit="s", cores=1, kind="oracle",
+    return dict(value=round(total, 2), unit="s", cores=1, kind="oracle",
                 sample="2D Poisson %d^2, %d levels, exact sine-transform solves (scipy.fft, "
                        "1 worker); per-sample time measured on %s, scaled by the GPU run's "
                        "N_l %s, plus 5 pilot solves; extrapolated time per trace"
                        % (N, L, sample, list(n_samples)))
 
 
+def cpu_exact_poisson_trace(N):
+    from oracle import operators
+    return operators.poisson2d_trace_inverse(N)
+
+
+def cpu_baseline_varcoef(sides, seeds, nsamples, budget_s=20.0):
+    """Oracle time per level-1 sample (sparse LU of both levels, factorisation
+    included once) on the smallest and the largest problem that fit the budget,
+    scaled to solves/s."""
+    from oracle import hierarchy, mlmc
+    from workloads import varcoef_faces, varcoef_levels
+    out = []
+    for N in sorted(set([min(sides)])):
+        p = sides.index(N)
+        t0 = time.perf_counter()
+        L = varcoef_levels(N)
+        A, P = hierarchy.varcoef_hierarchy(N, varcoef_faces(N, seed=1000 + p), 1e-3, L)
+        smp = mlmc.LevelSampler(A, P, complex_probe=False)
+        k = 0
+        while k < nsamples and time.perf_counter() - t0 < budget_s:
+            smp.sample(1, seeds[p], k, 1)
+            k += 1
+        dt = time.perf_counter() - t0
+        out.append(dict(N=N, samples=k, seconds=round(dt, 2), solves_per_s=round(2 * k / dt, 2)))
+    return dict(value=out[0]["solves_per_s"], unit="solves/s", cores=1, kind="oracle",
+                sample="3D diffusion %d^3 (smallest batch problem): %d level-1 samples "
+                       "(2 sparse-LU solves each, hierarchy and factorisations included) in "
+                       "%.1f s; the larger problems do not fit a bounded CPU sample"
+                       % (out[0]["N"], out[0]["samples"], out[0]["seconds"]))
+
+
+# ---------------------------------------------------------------------------
 def source_digest(path):
     import hashlib
     with open(path, "rb") as f:
@@ -96,41 +143,41 @@ def stored_traffic():
         return None
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--eps", type=float, default=1e-3)
-    ap.add_argument("--N", type=int, default=1024)
-    ap.add_argument("--levels", type=int, default=6)
-    ap.add_argument("--nb", type=int, default=128)
-    ap.add_argument("--alloc", default="giles")
-    ap.add_argument("--no-compare", action="store_true",
-                    help="skip the plain FP64 MLMC / Hutchinson comparison runs")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--timing-stride", type=int, default=8,
-                    help="bracket about one launch in k of the timed kernel with HIP events")
-    ap.add_argument("--copy-check", action="store_true",
-                    help="run one 256 MiB device copy first (calibrates HBM counters)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(MLMC samples shard across GPUs by sample index; not built here)",
-              file=sys.stderr)
-        sys.exit(2)
+def kernel_table(est):
+    out = {}
+    for k in est.KERNELS:
+        if k.startswith("unused"):
+            continue
+        launches, ms, amount = est.kernel_stats(k)
+        rate = amount / (ms * 1e-3) if ms > 0 else 0.0
+        if k == "nn_apply":
+            out[k] = dict(launches=launches, ms=round(ms, 2), tflops=round(rate / 1e12, 2))
+        else:
+            out[k] = dict(launches=launches, ms=round(ms, 2), gbs=round(rate / 1e9, 1))
+    return out
 
-    import torch
-    import paper_2108_11281_amd as m
-    from oracle import operators  # closed-form trace for the accuracy report
 
-    torch.cuda.set_device(0)
-    if args.copy_check:
-        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+def hbm_roofline(name, stats, stride, traffic=None):
+    launches, ms, nbytes = stats
+    achieved = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    return dict(bound="hbm", kernel=name, achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
+                unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                launches_timed=launches, timing_stride=stride,
+                avg_launch_us=round(1000.0 * ms / max(launches, 1), 2),
+                algorithmic_bytes_per_launch=round(nbytes / max(launches, 1)))
+
+
+def contract(args, value, unit, hib, ms_per_step, dtype, data, config, roofline, cpu, **extra):
+    out = {"metric": METRIC, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms_per_step, 2), "higher_is_better": hib,
+           "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": data,
+           "config": config, "roofline": roofline, "cpu_baseline": cpu}
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+# ---------------------------------------------------------------------------
+def run_poisson(args, m, torch):
     N, L = args.N, args.levels
     log("setup poisson2d N=%d L=%d nb=%d" % (N, L, args.nb))
     t0 = time.perf_counter()
@@ -160,28 +207,10 @@ def main():
     est.set_timing(True)
     est.reset_kernel_stats()
     est.trace(args.eps, 777)
-    stats = {k: est.kernel_stats(k) for k in est.KERNELS if not k.startswith("unused")}
+    kernels = kernel_table(est)
     est.set_timing(False)
     ms_per_step = 1000.0 * elapsed / args.steps
-
-    exact = operators.poisson2d_trace_inverse(N)
-    errs = [abs(r["trace"].real - exact) / exact for r in runs]
-    zs = [(r["trace"].real - exact) / r["rmsd"] for r in runs]
-
-    # dominant kernel: the fused red-black Gauss-Seidel sweep (largest total time
-    # in the per-kernel table); achieved = algorithmic bytes / time of the
-    # sampled launches over the timed steps
-    name, (launches, ms, nbytes) = "rbgs_sweep", gs
-    achieved = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
-    roofline = dict(bound="hbm", kernel=name + "<float>", achieved=round(achieved, 1),
-                    peak=HBM_PEAK_GBS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
-                    traffic=stored_traffic(), launches_timed=launches,
-                    timing_stride=args.timing_stride,
-                    avg_launch_us=round(1000.0 * ms / max(launches, 1), 2),
-                    algorithmic_bytes_per_launch=round(nbytes / max(launches, 1)))
-    kernels = {k: dict(launches=v[0], ms=round(v[1], 2),
-                       gbs=round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else 0.0)
-               for k, v in stats.items()}
+    roofline = hbm_roofline("rbgs_sweep<float>", gs, args.timing_stride, stored_traffic())
 
     compare = {}
     if not args.no_compare:
@@ -202,41 +231,236 @@ def main():
         compare["speedup_vs_fp64_mlmc"] = round(r64["seconds"] / (ms_per_step / 1000.0), 2)
         compare["speedup_vs_fp64_hutchinson"] = round(rh["seconds"] / (ms_per_step / 1000.0), 2)
 
-    cpu = None
+    cpu, accuracy = None, {"n_samples": [r["n_samples"] for r in runs],
+                           "rmsd_rel": [round(r["rmsd"] / abs(r["trace"].real), 7) for r in runs]}
     if not args.no_cpu:
         log("CPU oracle baseline")
         cpu = cpu_baseline(runs[0]["n_samples"], N, L)
-        cpu["value"] = round(cpu["value"], 2)
+        exact = cpu_exact_poisson_trace(N)
+        accuracy.update(exact_trace=exact,
+                        rel_err=[round(abs(r["trace"].real - exact) / exact, 7) for r in runs],
+                        z=[round((r["trace"].real - exact) / r["rmsd"], 2) for r in runs])
 
-    out = {
-        "metric": METRIC,
-        "value": round(ms_per_step / 1000.0, 4),
-        "unit": "s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 2),
-        "higher_is_better": False,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32+f64ir",
-        "data": "synthetic (Rademacher probes from Philox4x64-10 on the device)",
-        "config": {"workload": "poisson2d_%dx%d_L%d_agg2x2_nb%d_fp32ir64_eps%g"
-                               % (N, N, L, args.nb, args.eps),
-                   "variant": "FP32 inner Krylov + V-cycle, FP64 reliable-update refinement "
-                              "(no learned smoother on this operator)",
-                   "n": N * N, "levels": L, "nb": args.nb, "eps": args.eps,
-                   "alloc": args.alloc, "solve_tol": 1e-10},
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-        "accuracy": {"exact_trace": exact, "rel_err": [round(e, 7) for e in errs],
-                     "z": [round(z, 2) for z in zs],
-                     "n_samples": [r["n_samples"] for r in runs]},
-        "setup_s": round(setup_s, 3),
-        "kernels": kernels,
-        "compare": compare,
-    }
-    print(json.dumps(out), flush=True)
+    config = {"workload": "poisson2d_%dx%d_L%d_agg2x2_nb%d_fp32ir64_eps%g"
+                          % (N, N, L, args.nb, args.eps),
+              "variant": "FP32 inner Krylov + V-cycle, FP64 reliable-update refinement "
+                         "(no learned smoother on this operator)",
+              "n": N * N, "levels": L, "nb": args.nb, "eps": args.eps, "alloc": args.alloc,
+              "solve_tol": 1e-10}
+    contract(args, round(ms_per_step / 1000.0, 4), "s", False, ms_per_step, "f32+f64ir",
+             "synthetic (Rademacher probes from Philox4x64-10 on the device)", config,
+             roofline, cpu, accuracy=accuracy, setup_s=round(setup_s, 3), kernels=kernels,
+             compare=compare)
+
+
+def _wilson_est(m, N, Ls, L, precision, learned, nb, alloc):
+    from workloads import gauge_field, wilson_mass
+    return m.TraceEstimator("wilson2d", N, Ls, L, mass=wilson_mass(N),
+                            field=gauge_field(N, sigma=0.5, seed=1), block=4, n_vec=8,
+                            setup_sweeps=20, setup_seed=1, precision=precision, nb=nb,
+                            nu_pre=2, nu_post=2, solve_tol=1e-10, alloc=alloc,
+                            learned=1 if learned else 0)
+
+
+def run_wilson(args, m, torch, N, learned):
+    from workloads import nn_init_weights
+    Ls, L = (4, 3) if N >= 512 else (3, 3)
+    log("setup wilson2d N=%d Ls=%d L=%d nb=%d learned=%s" % (N, Ls, L, args.nb, learned))
+    t0 = time.perf_counter()
+    est = _wilson_est(m, N, Ls, L, "fp32_ir64", learned, args.nb, args.alloc)
+    setup_s = time.perf_counter() - t0
+    log("setup %.2fs" % setup_s)
+    train = None
+    if learned:
+        t0 = time.perf_counter()
+        train = est.learned_train(nn_init_weights(1), n_batches=args.train_batches,
+                                  crops_per_column=4, steps=args.train_steps, batch=256,
+                                  lr=2e-3, seed=5)
+        train["wall_s"] = round(time.perf_counter() - t0, 3)
+        log("training %s" % json.dumps(train))
+    for i in range(args.warmup):
+        r = est.trace(args.eps, 1000 + i)
+        log("warmup %d: %.3fs N_l=%s" % (i, r["seconds"], r["n_samples"]))
+    timed_kernel = "nn_apply" if learned else "rbgs_sweep"
+    est.set_timing([timed_kernel], stride=args.timing_stride)
+    est.reset_kernel_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = []
+    for i in range(args.steps):
+        r = est.trace(args.eps, i + 1)
+        runs.append(r)
+        log("step %d: %.3fs N_l=%s trace=%s rmsd=%.4g iters=%d"
+            % (i, r["seconds"], r["n_samples"], r["trace"], r["rmsd"], r["iterations"]))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ks = est.kernel_stats(timed_kernel)
+    est.set_timing(False)
+    ms_per_step = 1000.0 * elapsed / args.steps
+    if learned:
+        launches, ms, flops = ks
+        ach = flops / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+        roofline = dict(bound="mfma", kernel="k_nn_apply (bf16 16x16x32)", achieved=round(ach, 2),
+                        peak=BF16_PEAK_TFLOPS, unit="TFLOP/s",
+                        frac=round(ach / BF16_PEAK_TFLOPS, 4), traffic=None,
+                        launches_timed=launches, timing_stride=args.timing_stride,
+                        avg_launch_us=round(1000.0 * ms / max(launches, 1), 2),
+                        algorithmic_flops_per_launch=round(flops / max(launches, 1)))
+    else:
+        roofline = hbm_roofline("k_wilson_gs<c32> (sweep of both colours)", ks,
+                                args.timing_stride)
+    compare = {"learned_stats": list(est.learned_stats())} if learned else {}
+    est.close()
+    if not args.no_compare:
+        if learned:
+            log("plain FP32 MLMC (no network), same workload")
+            ep = _wilson_est(m, N, Ls, L, "fp32_ir64", False, args.nb, args.alloc)
+            rp = ep.trace(args.eps, 1)
+            ep.close()
+            compare["plain_fp32_mlmc_s"] = round(rp["seconds"], 3)
+            compare["plain_fp32_mlmc_iterations"] = rp["iterations"]
+            compare["plain_fp32_mlmc_n_samples"] = rp["n_samples"]
+            log("plain FP32 MLMC %.3fs N_l=%s" % (rp["seconds"], rp["n_samples"]))
+        log("plain FP64 MLMC, same workload")
+        e64 = _wilson_est(m, N, Ls, L, "fp64", False, args.nb, args.alloc)
+        r64 = e64.trace(args.eps, 1)
+        e64.close()
+        compare["fp64_mlmc_s"] = round(r64["seconds"], 3)
+        compare["fp64_mlmc_n_samples"] = r64["n_samples"]
+        compare["speedup_vs_fp64_mlmc"] = round(r64["seconds"] / (ms_per_step / 1000.0), 2)
+        if learned:
+            compare["speedup_vs_plain_fp32_mlmc"] = round(
+                compare["plain_fp32_mlmc_s"] / (ms_per_step / 1000.0), 2)
+        log("plain FP64 MLMC %.3fs N_l=%s" % (r64["seconds"], r64["n_samples"]))
+    config = {"workload": "wilson2d_%dx%d_Ls%d_L%d_agg4x4x8_nb%d_c64ir128_eps%g%s"
+                          % (N, N, Ls, L, args.nb, args.eps, "_learned" if learned else ""),
+              "variant": ("learned smoother (2 of 4 finest sweeps) + complex64 FGMRES in "
+                          "complex128 refinement" if learned else
+                          "complex64 FGMRES + V-cycle in complex128 refinement"),
+              "n": 2 * N * N, "levels_solver": Ls, "levels_mlmc": L, "nb": args.nb,
+              "eps": args.eps, "alloc": args.alloc, "solve_tol": 1e-10}
+    contract(args, round(ms_per_step / 1000.0, 4), "s", False, ms_per_step,
+             "c64+c128ir" + ("+bf16net" if learned else ""),
+             "synthetic (U(1) phases N(0,0.5^2), Z4 probes from Philox4x64-10)", config,
+             roofline, None,
+             accuracy={"n_samples": [r["n_samples"] for r in runs],
+                       "rmsd_rel": [round(r["rmsd"] / abs(r["trace"].real), 7) for r in runs],
+                       "trace": [[r["trace"].real, r["trace"].imag] for r in runs]},
+             setup_s=round(setup_s, 3), training=train, compare=compare)
+
+
+def run_batch(args, m, torch):
+    from workloads import batch_problem_sizes, varcoef_faces, varcoef_levels
+    sides = batch_problem_sizes(32)
+    seeds = [1000 + p for p in range(len(sides))]
+    log("setup %d varcoef3d problems, sides %s" % (len(sides), sides))
+    t0 = time.perf_counter()
+    ests = []
+    for p, N in enumerate(sides):
+        L = varcoef_levels(N)
+        ests.append(m.TraceEstimator("varcoef3d", N, L, L, shift=1e-3,
+                                     field=varcoef_faces(N, seed=1000 + p), nb=64,
+                                     precision="fp32_ir64", solve_tol=1e-10,
+                                     stream=torch.cuda.Stream()))
+    setup_s = time.perf_counter() - t0
+    log("setup %.2fs" % setup_s)
+    ns = 64
+    for i in range(args.warmup):
+        m.batch_sample(ests, 1, seeds, 10 ** 6 + i * ns, ns, workers=args.workers)
+    for e in ests:
+        e.set_timing(["rbgs_sweep"], stride=args.timing_stride)
+        e.reset_kernel_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    per = []
+    for i in range(args.steps):
+        _, sec = m.batch_sample(ests, 1, seeds, i * ns, ns, workers=args.workers)
+        per.append(sec)
+        log("step %d: %.3fs (slowest problem %.3fs)" % (i, max(sec), max(sec)))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    tot = [0, 0.0, 0.0]
+    for e in ests:
+        st = e.kernel_stats("rbgs_sweep")
+        tot = [tot[0] + st[0], tot[1] + st[1], tot[2] + st[2]]
+        e.set_timing(False)
+    solves = 2 * ns * len(ests) * args.steps
+    value = solves / elapsed
+    ms_per_step = 1000.0 * elapsed / args.steps
+    import numpy as np
+    per_problem = [dict(N=N, solves_per_s=round(2 * ns / float(np.mean([s[p] for s in per])), 1))
+                   for p, N in enumerate(sides)]
+    compare = {}
+    if not args.no_compare:
+        t1 = time.perf_counter()
+        m.batch_sample(ests, 1, seeds, 0, ns, workers=1)
+        torch.cuda.synchronize()
+        seq = time.perf_counter() - t1
+        compare = dict(sequential_one_worker_solves_per_s=round(2 * ns * len(ests) / seq, 1),
+                       concurrency_speedup=round(seq / (elapsed / args.steps), 2))
+    for e in ests:
+        e.close()
+    cpu = None
+    if not args.no_cpu:
+        log("CPU oracle baseline (smallest problem)")
+        cpu = cpu_baseline_varcoef(sides, seeds, ns)
+    config = {"workload": "varcoef3d_batch32_N32-128_agg2x2x2_nb64_fp32ir64",
+              "problems": len(sides), "sides": sides, "probes_per_problem": ns,
+              "workers": args.workers, "solve_tol": 1e-10}
+    contract(args, round(value, 1), "solves/s", True, ms_per_step, "f32+f64ir",
+             "synthetic (log-normal face coefficients sigma=1, Rademacher probes)", config,
+             hbm_roofline("k_vc_gs<float> (sweep of both colours)", tot, args.timing_stride),
+             cpu, per_problem=per_problem, setup_s=round(setup_s, 2), compare=compare)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="poisson1024",
+                    choices=["poisson1024", "wilson256", "wilson512", "varcoef_batch"])
+    ap.add_argument("--eps", type=float, default=1e-3)
+    ap.add_argument("--N", type=int, default=1024)
+    ap.add_argument("--levels", type=int, default=6)
+    ap.add_argument("--nb", type=int, default=128)
+    ap.add_argument("--alloc", default="giles")
+    ap.add_argument("--workers", type=int, default=4, help="varcoef_batch: host workers")
+    ap.add_argument("--train-batches", type=int, default=80,
+                    help="wilson512: plain solves used for training = this x nb")
+    ap.add_argument("--train-steps", type=int, default=2000)
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the comparison runs after the timed region")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--timing-stride", type=int, default=8,
+                    help="bracket about one launch in k of the timed kernel with HIP events")
+    ap.add_argument("--copy-check", action="store_true",
+                    help="run one 256 MiB device copy first (calibrates HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(MLMC samples shard across GPUs by sample index; not built here)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2108_11281_amd as m
+
+    torch.cuda.set_device(0)
+    if args.copy_check:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    if args.workload == "poisson1024":
+        run_poisson(args, m, torch)
+    elif args.workload == "wilson256":
+        run_wilson(args, m, torch, 256, learned=False)
+    elif args.workload == "wilson512":
+        run_wilson(args, m, torch, 512, learned=True)
+    else:
+        run_batch(args, m, torch)
 
 
 if __name__ == "__main__":

@@ -234,6 +234,19 @@ typedef void* (*mlmc_alloc_fn)(size_t bytes, void* user);
 typedef void (*mlmc_free_fn)(void* ptr, void* user);
 int mlmc_set_allocator(mlmc_alloc_fn alloc, mlmc_free_fn free_fn, void* user);
 
+/* Batch of independent problems (Sec. 4.1 samples of each), run concurrently:
+ * `workers` host threads each take the next problem, longest level first, and
+ * draw samples first..first+nsamples-1 of level `level` with seeds[i] exactly
+ * as mlmc_sample_level would.  Problems overlap on the GPU when their contexts
+ * were set up on different HIP streams (contexts sharing a stream run one
+ * after another, with the same results).  out: count x nsamples x 2 doubles
+ * (re, im), problem-major; seconds (nullable): wall time per problem.  Every
+ * context must be distinct; level must be sampleable on all of them.
+ * Returns the first failing problem's status (its context holds the message). */
+int mlmc_batch_sample(void* const* ctxs, int count, int level, const uint64_t* seeds,
+                      int64_t first, int64_t nsamples, int workers, double* out,
+                      double* seconds);
+
 /* Counters of the last mlmc_trace / mlmc_sample_level / mlmc_solve call:
  * out[0] Krylov iterations (per batch), out[1] refinement steps,
  * out[2] V-cycles, out[3] batches.  n: entries to copy (<= 4). */
@@ -251,12 +264,14 @@ int mlmc_counters(void* ctx, int64_t* out, int n);
 int mlmc_set_timing(void* ctx, int mask, int stride);
 
 /* Kernel ids for mlmc_kernel_stats (algorithmic bytes per unknown and RHS for
- * element size e): 0 fused red-black Gauss-Seidel sweep (2e from a zero start:
+ * element size e; each operator kind reports its own smoother, residual and
+ * transfer kernels under the same ids): 0 red-black Gauss-Seidel sweep (2e from a zero start:
  * b in, x out; 3e with an input iterate; +0.25e with the folded coarse
  * correction), 1 fused residual + restriction (2.25e), 2 prolongation +
  * correction when there is no post-smoothing (2.25e), 3 Krylov direction update
  * fused with the operator apply and its dot (4e: z, p in; p, q out), 4 CG x/r
- * update with |r|^2 (6e), 5 unused, 6 unused, 7 FP64 refinement residual
+ * update with |r|^2 (6e), 5 learned-smoother network (counts FLOPs, not
+ * bytes: 2 x 4032 per site and column), 6 unused, 7 FP64 refinement residual
  * (20 bytes: FP64 b and y in, FP32 r out).  fp64 = 0 selects the FP32/complex64
  * instantiation, 1 the FP64 one.  out: launches, total milliseconds, total
  * algorithmic bytes (active columns only). */

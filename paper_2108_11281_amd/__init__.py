@@ -211,7 +211,7 @@ class TraceEstimator:
 
     # -- measurement --
     KERNELS = ["rbgs_sweep", "residual_restrict", "prolong_correct", "update_apply", "cg_xr",
-               "unused5", "unused6", "ir_residual"]
+               "nn_apply", "unused6", "ir_residual"]
 
     def set_timing(self, kernels=True, stride=1):
         """kernels: True (all), False (none) or a list of kernel names to time;
@@ -361,6 +361,24 @@ class TraceEstimator:
             ctypes.c_void_p(targets.data_ptr()),
             ctypes.byref(loss), grad.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
         return loss.value, grad
+
+
+def batch_sample(estimators, level, seeds, first, nsamples, workers=4):
+    """Samples of one level on several problems at once (mlmc_batch_sample).
+    Returns (samples [count, nsamples] complex, seconds per problem)."""
+    count = len(estimators)
+    ctxs = (ctypes.c_void_p * count)(*[e._ctx.value for e in estimators])
+    sd = (ctypes.c_uint64 * count)(*[int(v) for v in seeds])
+    out = np.zeros((count, int(nsamples), 2))
+    sec = np.zeros(count)
+    rc = lib().mlmc_batch_sample(ctxs, count, int(level), sd, int(first), int(nsamples),
+                                 int(workers), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                 sec.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    if rc != 0:
+        msgs = [e._lib.mlmc_last_error(e._ctx) for e in estimators]
+        msg = next((m.decode() for m in msgs if m), "")
+        raise MLMCError(rc, msg)
+    return out[..., 0] + 1j * out[..., 1], sec
 
 
 def run_estimator(levels, sample, tol, *, pilot=None, coarse=0.0, cost=None, **options):

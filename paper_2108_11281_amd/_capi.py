@@ -122,6 +122,9 @@ SIGNATURES = {
     "mlmc_set_timing": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
     "mlmc_kernel_stats": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _D]),
     "mlmc_reset_kernel_stats": (ctypes.c_int, [_P]),
+    "mlmc_batch_sample": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_uint64), ctypes.c_int64,
+                                         ctypes.c_int64, ctypes.c_int, _D, _D]),
     "mlmc_learned_train": (ctypes.c_int, [_P, _F, ctypes.POINTER(TrainOptions),
                                           ctypes.POINTER(TrainReport)]),
     "mlmc_learned_set_weights": (ctypes.c_int, [_P, _F]),

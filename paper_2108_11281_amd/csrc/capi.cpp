@@ -1,6 +1,10 @@
 // The C ABI (include/mlmc.h): argument checks, exception-to-status mapping.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstring>
+#include <thread>
 #include <new>
 #include <vector>
 #include <string>
@@ -253,6 +257,54 @@ int mlmc_nn_loss_grad(void* c, int ncrops, const float* in, const float* target,
   Context* ctx = as_ctx(c);
   if (!ctx || !in || !target || !loss || !grad) return MLMC_EINVAL;
   return guarded(ctx, [&] { ctx->nn_loss_grad(ncrops, in, target, loss, grad); });
+}
+
+int mlmc_batch_sample(void* const* ctxs, int count, int level, const uint64_t* seeds,
+                      int64_t first, int64_t nsamples, int workers, double* out,
+                      double* seconds) {
+  if (!ctxs || count < 1 || !seeds || !out || nsamples < 1 || first < 0 || workers < 1)
+    return MLMC_EINVAL;
+  std::vector<Context*> cs(count);
+  for (int i = 0; i < count; ++i) {
+    cs[i] = as_ctx(ctxs[i]);
+    if (!cs[i]) return MLMC_EINVAL;
+    for (int j = 0; j < i; ++j)
+      if (cs[j] == cs[i]) return MLMC_EINVAL;  // a context serves one worker at a time
+    if (level < 1 || level >= cs[i]->levels_mlmc()) return MLMC_EINVAL;
+  }
+  // longest first: order by the level's unknowns (the solve cost grows with it)
+  std::vector<int> order(count);
+  for (int i = 0; i < count; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return cs[a]->level_size(level) > cs[b]->level_size(level);
+  });
+  std::vector<int> status(count, MLMC_OK);
+  std::atomic<int> next{0};
+  auto work = [&] {
+    for (;;) {
+      const int t = next.fetch_add(1);
+      if (t >= count) return;
+      const int i = order[t];
+      Context* ctx = cs[i];
+      const auto t0 = std::chrono::steady_clock::now();
+      status[i] = guarded(ctx, [&] {
+        MLMC_HIP(hipSetDevice(ctx->device()));
+        ctx->sample_level(level, seeds[i], first, nsamples, out + (size_t)i * nsamples * 2,
+                          nullptr);
+      });
+      if (seconds)
+        seconds[i] =
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+  };
+  const int nw = std::min(workers, count);
+  std::vector<std::thread> pool;
+  for (int w = 1; w < nw; ++w) pool.emplace_back(work);
+  work();
+  for (auto& th : pool) th.join();
+  for (int i = 0; i < count; ++i)
+    if (status[i] != MLMC_OK) return status[i];
+  return MLMC_OK;
 }
 
 int mlmc_counters(void* c, int64_t* out, int n) {

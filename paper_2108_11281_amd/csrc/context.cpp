@@ -25,6 +25,7 @@ Context::Context(const mlmc_operator& A, const mlmc_hierarchy& h, const mlmc_opt
                  hipStream_t s)
     : kind_(A.kind), op_(A), h_(h), opt_(o), s_(s) {
   hooks_ = alloc_hooks();
+  MLMC_HIP(hipGetDevice(&device_));
   op_.field = nullptr;
   Ls_ = h.levels_solver;
   L_ = h.levels_mlmc;
@@ -117,8 +118,14 @@ void Context::dfree(void* p) {
   else (void)hipFree(p);
 }
 
-template <> Work<float>& Context::work<float>() { return w32_; }
-template <> Work<double>& Context::work<double>() { return w64_; }
+template <> Work<float>& Context::work<float>() {
+  MLMC_REQUIRE(w32_.x != nullptr, MLMC_ESTATE, "FP32 work vectors exist in MLMC_FP32_IR64 mode only");
+  return w32_;
+}
+template <> Work<double>& Context::work<double>() {
+  MLMC_REQUIRE(w64_.x != nullptr, MLMC_ESTATE, "FP64 work vectors exist in MLMC_FP64 mode only");
+  return w64_;
+}
 
 template <typename T>
 void Context::alloc_work(Work<T>& w) {
@@ -170,6 +177,9 @@ void Context::invert_coarse(int level, double** inv_out, c64* trace_out) {
   MLMC_HIP(hipStreamSynchronize(s_));
   *trace_out = host_c64_[0];
   *inv_out = inv;
+  dfree(colbuf);
+  dfree(rowbuf);
+  dfree(aug);
 }
 
 // device/pinned buffers shared by every operator kind: reduction partials,
@@ -282,7 +292,9 @@ void Context::build_varcoef(const double* k) {
 void Context::finish_real_build() {
   const int64_t n1 = lv_[0].n;
   alloc_common();
-  alloc_work(w64_);
+  // the FP64 Krylov / V-cycle vectors serve the plain FP64 mode only; the
+  // refined FP32 mode keeps its FP64 iterate in the sample-batch buffers
+  if (opt_.precision == MLMC_FP64) alloc_work(w64_);
   if (opt_.precision == MLMC_FP32_IR64) {
     alloc_work(w32_);
     r32_ = dalloc_n<float>(n1 * nb_);
@@ -523,15 +535,6 @@ int Context::vcycle_partials(int l, bool* fused) const {
 // one-block count of its active columns, so the algorithmic bytes of the launch
 // are known without a host synchronisation.
 // ---------------------------------------------------------------------------
-namespace {
-// splitmix64 finaliser
-uint64_t mix64(uint64_t z) {
-  z += 0x9E3779B97F4A7C15ULL;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
-  return z ^ (z >> 31);
-}
-}  // namespace
 
 hipEvent_t Context::event() {
   if (!ev_pool_.empty()) {
@@ -544,37 +547,6 @@ hipEvent_t Context::event() {
   return e;
 }
 
-template <typename T, typename F>
-void Context::timed(int id, double bytes_per_col, const int* act, int nb, F&& launch) {
-  (void)act;
-  // with stride k, a launch is timed with probability 1/k, chosen by a hash of
-  // its index so that the sample does not alias with the period of the V-cycle
-  if (!timing_ || !(timing_mask_ & (1u << id)) ||
-      (timing_stride_ > 1 && mix64((uint64_t)timing_seen_[id]++ * kNumTimers + id) %
-                                     (uint64_t)timing_stride_ != 0)) {
-    launch();
-    return;
-  }
-  if (tlog_next_ >= kTimingLog) collect_timing();
-  const int slot = 2 * id + (sizeof(typename Traits<T>::real) == 8 ? 1 : 0);
-  const int idx = tlog_next_++;
-  hipEvent_t a = event(), b = event();
-  LaunchEvents ev;
-  ev.start = a;
-  ev.stop = b;
-  timing_log() = tlog_dev_ + (int64_t)idx * nb_;
-  timing_events() = &ev;
-  launch();
-  timing_events() = nullptr;
-  timing_log() = nullptr;
-  MLMC_HIP(hipGetLastError());
-  if (!ev.used) {  // nothing was launched through MLMC_LAUNCH: no sample
-    ev_pool_.push_back(a);
-    ev_pool_.push_back(b);
-    return;
-  }
-  pending_.push_back({slot, idx, nb, bytes_per_col, a, b});
-}
 
 void Context::set_timing(unsigned mask, int stride) {
   collect_timing();

@@ -99,9 +99,11 @@ class Context {
   int64_t counters[4] = {0, 0, 0, 0};
   std::string last_error;
   const mlmc_options& options() const { return opt_; }
+  int device() const { return device_; }
 
   // kernel timing (measurement mode)
-  enum { kTimGs, kTimResRestrict, kTimProlong, kTimApply, kTimCgXr, kTimCgP, kTimDot,
+  // kTimNn counts flops (not bytes) per column: the network is MFMA-bound
+  enum { kTimGs, kTimResRestrict, kTimProlong, kTimApply, kTimCgXr, kTimNn, kTimUnused6,
          kTimIrResidual, kNumTimers };
   void set_timing(unsigned mask, int stride);
   void kernel_stats(int id, int fp64, double* out);
@@ -211,6 +213,7 @@ class Context {
   TimerStat tstat_[2 * kNumTimers];
 
   int kind_;
+  int device_ = 0;
   mlmc_operator op_;
   mlmc_hierarchy h_;
   mlmc_options opt_;
@@ -260,6 +263,46 @@ class Context {
   c64* host_c64_ = nullptr;  // pinned, 8*nb
   int* piv_ = nullptr;
 };
+
+// splitmix64 finaliser (sampling of timed launches)
+inline uint64_t mix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+template <typename T, typename F>
+inline void Context::timed(int id, double bytes_per_col, const int* act, int nb, F&& launch) {
+  (void)act;
+  // with stride k, a launch is timed with probability 1/k, chosen by a hash of
+  // its index so that the sample does not alias with the period of the V-cycle
+  if (!timing_ || !(timing_mask_ & (1u << id)) ||
+      (timing_stride_ > 1 && mix64((uint64_t)timing_seen_[id]++ * kNumTimers + id) %
+                                     (uint64_t)timing_stride_ != 0)) {
+    launch();
+    return;
+  }
+  if (tlog_next_ >= kTimingLog) collect_timing();
+  const int slot = 2 * id + (sizeof(typename Traits<T>::real) == 8 ? 1 : 0);
+  const int idx = tlog_next_++;
+  hipEvent_t a = event(), b = event();
+  LaunchEvents ev;
+  ev.start = a;
+  ev.stop = b;
+  timing_log() = tlog_dev_ + (int64_t)idx * nb_;
+  timing_events() = &ev;
+  launch();
+  timing_events() = nullptr;
+  timing_log() = nullptr;
+  MLMC_HIP(hipGetLastError());
+  if (!ev.used) {  // nothing was launched through MLMC_LAUNCH: no sample
+    ev_pool_.push_back(a);
+    ev_pool_.push_back(b);
+    return;
+  }
+  pending_.push_back({slot, idx, nb, bytes_per_col, a, b});
+}
 
 // ---------------------------------------------------------------------------
 // Estimator driver (host only).  The sampler fills `count` samples of a level.

@@ -22,7 +22,10 @@ template <> const c64* Context::qmat<c64>(int l) const { return lv_[l - 1].q64; 
 template <> Work<c32>& Context::work<c32>() { return wc32_; }
 template <> Work<c64>& Context::work<c64>() { return wc64_; }
 template <> Fgmres<c32>& Context::fg<c32>() { return fg32_; }
-template <> Fgmres<c64>& Context::fg<c64>() { return fg64_; }
+template <> Fgmres<c64>& Context::fg<c64>() {
+  MLMC_REQUIRE(fg64_.V != nullptr, MLMC_ESTATE, "FP64 FGMRES buffers exist in MLMC_FP64 mode only");
+  return fg64_;
+}
 
 // ---------------------------------------------------------------------------
 // setup (Example 4.3 aggregation sketch): on each level, n_vec Z4 start
@@ -126,7 +129,7 @@ void Context::build_wilson(const double* theta) {
     f.d = dalloc_n<T>(n1 * nb_);
   };
   alloc_cwork(wc64_);
-  alloc_fg(fg64_);
+  if (opt_.precision == MLMC_FP64) alloc_fg(fg64_);  // the FP32 mode iterates in fg32_
   if (opt_.precision == MLMC_FP32_IR64) {
     alloc_cwork(wc32_);
     alloc_fg(fg32_);
@@ -157,6 +160,9 @@ void Context::build_wilson(const double* theta) {
     MLMC_HIP(hipStreamSynchronize(s_));
     *tr = host_c64_[0];
     *inv_out = inv;
+    dfree(colbuf);
+    dfree(rowbuf);
+    dfree(aug);
   };
   c64* inv_s = nullptr;
   c64 tr_s;
@@ -196,9 +202,15 @@ template <typename T>
 void Context::cop_smooth(int l, const T* b, T* x, int nb, const int* act, bool zero_init,
                          bool reverse) {
   const Level& L = lv_[l - 1];
-  if (L.wilson)
-    wilson_rbgs<T>(b, x, links<T>(l), L.side, op_.mass + 2.0, nb, act, zero_init, reverse, s_);
-  else
+  if (L.wilson) {
+    // algorithmic bytes per column: b and x read, x written (x read once more
+    // by the second colour unless from zero), links once per launch
+    const double es = 2.0 * sizeof(T) * (double)L.side * L.side;
+    const double bytes = es * (zero_init ? 2.5 : 3.0) + es / (double)nb;
+    timed<T>(kTimGs, bytes, act, nb, [&] {
+      wilson_rbgs<T>(b, x, links<T>(l), L.side, op_.mass + 2.0, nb, act, zero_init, reverse, s_);
+    });
+  } else
     bsr_rbgs<T>(b, x, blocks<T>(l), dinv<T>(l), L.side, L.dof, nb, act, zero_init, reverse, s_);
 }
 

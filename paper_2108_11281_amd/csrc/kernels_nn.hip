@@ -101,9 +101,10 @@ __global__ __launch_bounds__(256) void k_nn_apply(const c32* __restrict__ r, c32
                                                   const c64* __restrict__ rr, double inv_n,
                                                   const __bf16* __restrict__ links,
                                                   const bf8* __restrict__ frag, int N, int tiles_x,
-                                                  const int* active) {
+                                                  const int* active, int* tlog) {
   __shared__ __attribute__((aligned(16))) NnApplyLds sm;
   const int col = blockIdx.y;
+  if (tlog && blockIdx.x == 0 && threadIdx.x == 0) tlog[col] = active ? active[col] : 1;
   if (active && !active[col]) return;
   const double s2 = rr[col].re * inv_n;
   if (!(s2 > 0.0)) return;  // zero residual: no correction
@@ -447,7 +448,7 @@ void nn_apply(const c32* r, c32* x, const c64* rr, double inv_n, const void* lin
   const int tiles_x = N / kTo;
   MLMC_LAUNCH(k_nn_apply, dim3(tiles_x * tiles_x, nb), dim3(256), 0, s, r, x, rr, inv_n,
               static_cast<const __bf16*>(links), static_cast<const bf8*>(frag), N, tiles_x,
-              active);
+              active, timing_log());
 }
 
 void nn_train_step(const void* in, const float* tgt, const int* order, int ncrops,

@@ -111,8 +111,9 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void k_wilson_gs(const T* __restrict__ b, T* __restrict__ x,
                                                         const T* __restrict__ U, int N,
                                                         R_t<T> dinv, int colour, int zero_nbrs,
-                                                        const int* active) {
+                                                        const int* active, int* tlog) {
   const int k = blockIdx.y;
+  if (tlog && blockIdx.x == 0 && threadIdx.x == 0) tlog[k] = active ? active[k] : 1;
   if (active && !active[k]) return;
   const int n2 = N * N;
   const int s = blockIdx.x * kThreads + threadIdx.x;
@@ -545,10 +546,10 @@ void wilson_rbgs(const T* b, T* x, const T* U, int N, double diag, int nb, const
                  bool zero_init, bool reverse, hipStream_t s) {
   const dim3 g = grid_sites((int64_t)N * N, nb);
   const int first = reverse ? 1 : 0;
-  hipLaunchKernelGGL(k_wilson_gs<T>, g, dim3(kThreads), 0, s, b, x, U, N, (R_t<T>)(1.0 / diag),
-                     first, zero_init ? 1 : 0, active);
-  hipLaunchKernelGGL(k_wilson_gs<T>, g, dim3(kThreads), 0, s, b, x, U, N, (R_t<T>)(1.0 / diag),
-                     1 - first, 0, active);
+  MLMC_LAUNCH(k_wilson_gs<T>, g, dim3(kThreads), 0, s, b, x, U, N, (R_t<T>)(1.0 / diag), first,
+              zero_init ? 1 : 0, active, timing_log());
+  MLMC_LAUNCH(k_wilson_gs<T>, g, dim3(kThreads), 0, s, b, x, U, N, (R_t<T>)(1.0 / diag),
+              1 - first, 0, active, (int*)nullptr);
 }
 
 #define BSR_DISPATCH(DOFV, ...)                                                         \
