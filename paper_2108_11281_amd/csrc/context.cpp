@@ -272,8 +272,10 @@ void Context::build_varcoef(const double* k) {
     L.dof = 1;
     L.n = (int64_t)side * side * side;
     const int64_t f = 3LL * side * side * (side + 1);
+    const int64_t fl = 3 * (L.n + (int64_t)side * side);
     L.kf64 = dalloc_n<double>(f);
-    L.kf32 = dalloc_n<float>(f);
+    L.kl64 = dalloc_n<double>(fl);
+    L.kl32 = dalloc_n<float>(fl);
     L.dg64 = dalloc_n<double>(L.n);
     L.dg32 = dalloc_n<float>(L.n);
   }
@@ -282,9 +284,49 @@ void Context::build_varcoef(const double* k) {
   for (int l = 0; l < Ls_; ++l) {
     Level& L = lv_[l];
     if (l > 0) varcoef_coarsen(lv_[l - 1].kf64, L.kf64, lv_[l - 1].side, s_);
-    varcoef_diag(L.kf64, op_.shift, L.side, L.dg64, L.dg32, L.kf32, s_);
+    varcoef_diag(L.kf64, op_.shift, L.side, L.dg64, L.dg32, L.kl64, L.kl32, s_);
   }
   finish_real_build();
+  tune_varcoef();
+}
+
+// Autotuner of the 3D stencil kernels: per smoothed level, time one full
+// red-black sweep over all nb columns with 1, 2, 4 and 8 right-hand sides per
+// thread (the results are identical; only the load reuse of the couplings and
+// the parallelism differ) and keep the fastest.  Runs once at setup on the
+// library's own work vectors.
+void Context::tune_varcoef() {
+  const bool fp32 = opt_.precision == MLMC_FP32_IR64;
+  hipEvent_t a = event(), b = event();
+  for (int l = 1; l < Ls_; ++l) {
+    Level& L = lv_[l - 1];
+    float best = 1e30f;
+    int best_cols = 4;
+    for (int cols : {1, 2, 4, 8}) {
+      float ms = 0.f;
+      for (int rep = 0; rep < 3; ++rep) {
+        MLMC_HIP(hipEventRecord(a, s_));
+        if (fp32)
+          varcoef_rbgs<float>(w32_.r, w32_.x, L.kl32, L.dg32, L.side, nb_, cols, nullptr,
+                              rep == 0, false, s_);
+        else
+          varcoef_rbgs<double>(w64_.r, w64_.x, L.kl64, L.dg64, L.side, nb_, cols, nullptr,
+                               rep == 0, false, s_);
+        MLMC_HIP(hipEventRecord(b, s_));
+        MLMC_HIP(hipEventSynchronize(b));
+        float t = 0.f;
+        MLMC_HIP(hipEventElapsedTime(&t, a, b));
+        if (rep > 0) ms += t;  // the first run warms caches and code
+      }
+      if (ms < best) {
+        best = ms;
+        best_cols = cols;
+      }
+    }
+    L.cols = best_cols;
+  }
+  ev_pool_.push_back(a);
+  ev_pool_.push_back(b);
 }
 
 // work buffers and coarsest inverses of a real symmetric positive definite
@@ -323,8 +365,8 @@ void Context::finish_real_build() {
 // ---------------------------------------------------------------------------
 // operator dispatch
 // ---------------------------------------------------------------------------
-template <> const float* Context::vc_faces<float>(int l) const { return lv_[l - 1].kf32; }
-template <> const double* Context::vc_faces<double>(int l) const { return lv_[l - 1].kf64; }
+template <> const float* Context::vc_faces<float>(int l) const { return lv_[l - 1].kl32; }
+template <> const double* Context::vc_faces<double>(int l) const { return lv_[l - 1].kl64; }
 template <> const float* Context::vc_diag<float>(int l) const { return lv_[l - 1].dg32; }
 template <> const double* Context::vc_diag<double>(int l) const { return lv_[l - 1].dg64; }
 
@@ -337,8 +379,8 @@ template <typename T>
 void Context::op_apply(int l, const T* x, T* y, int nb, const int* act, c64* partials) {
   const Level& L = lv_[l - 1];
   if (varcoef_)
-    varcoef_residual<T, T, T>(nullptr, x, y, vc_faces<T>(l), vc_diag<T>(l), L.side, nb, act,
-                              partials, s_);
+    varcoef_residual<T, T, T>(nullptr, x, y, vc_faces<T>(l), vc_diag<T>(l), L.side, nb, L.cols,
+                              act, partials, s_);
   else
     poisson_apply<T>(x, y, L.side, L.d, L.c, nb, act, partials, s_);
 }
@@ -348,8 +390,8 @@ void Context::op_residual(int l, const Tb* b, const Tx* x, Tr* r, int nb, const 
                           c64* partials) {
   const Level& L = lv_[l - 1];
   if (varcoef_)
-    varcoef_residual<Tb, Tx, Tr>(b, x, r, vc_faces<Tx>(l), vc_diag<Tx>(l), L.side, nb, act,
-                                 partials, s_);
+    varcoef_residual<Tb, Tx, Tr>(b, x, r, vc_faces<Tx>(l), vc_diag<Tx>(l), L.side, nb, L.cols,
+                                 act, partials, s_);
   else
     poisson_residual<Tb, Tx, Tr>(b, x, r, L.side, L.d, L.c, nb, act, partials, s_);
 }
@@ -360,7 +402,7 @@ void Context::op_update_apply(int l, const T* p_old, const T* z, const c64* beta
   const Level& L = lv_[l - 1];
   if (varcoef_)
     varcoef_update_apply<T>(p_old, z, beta, p_new, q, vc_faces<T>(l), vc_diag<T>(l), L.side, nb,
-                            act, partials_, s_);
+                            L.cols, act, partials_, s_);
   else
     poisson_update_apply<T>(p_old, z, beta, p_new, q, L.side, L.d, L.c, nb, act, partials_, s_);
 }
@@ -369,7 +411,8 @@ template <typename T>
 void Context::op_res_restrict(int l, const T* b, const T* x, T* rc, int nb, const int* act) {
   const Level& L = lv_[l - 1];
   if (varcoef_)
-    varcoef_restrict<T>(b, x, rc, vc_faces<T>(l), vc_diag<T>(l), L.side, true, nb, act, s_);
+    varcoef_restrict<T>(b, x, rc, vc_faces<T>(l), vc_diag<T>(l), L.side, true, nb, L.cols, act,
+                        s_);
   else
     poisson_residual_restrict<T>(b, x, rc, L.side, L.d, L.c, nb, act, s_);
 }
@@ -388,7 +431,7 @@ template <typename T>
 void Context::op_restrict(int l, const T* x, T* xc, int nb, const int* act) {
   const Level& L = lv_[l - 1];
   if (varcoef_)
-    varcoef_restrict<T>(nullptr, x, xc, nullptr, nullptr, L.side, false, nb, act, s_);
+    varcoef_restrict<T>(nullptr, x, xc, nullptr, nullptr, L.side, false, nb, L.cols, act, s_);
   else
     agg2d_restrict<T>(x, xc, L.side, nb, act, s_);
 }
@@ -413,7 +456,7 @@ void Context::vcycle_vc(int l, const T* b, T* x, int nb, const int* act, c64* rz
     const int pre = opt_.nu_pre, post = opt_.nu_post;
     for (int i = 0; i < pre; ++i)
       timed<T>(kTimGs, en * ((i == 0 ? 2.0 : 3.0) + 4.0 / (double)nb), act, nb, [&] {
-        varcoef_rbgs<T>(b, x, kf, dg, L.side, nb, act, i == 0, false, s_);
+        varcoef_rbgs<T>(b, x, kf, dg, L.side, nb, L.cols, act, i == 0, false, s_);
       });
     T* bc = w.vb[l];
     T* ec = w.vx[l];
@@ -427,7 +470,7 @@ void Context::vcycle_vc(int l, const T* b, T* x, int nb, const int* act, c64* rz
              [&] { varcoef_prolong<T>(ec, x, L.side, omega_, pre == 0 ? 0.0 : 1.0, nb, act, s_); });
     for (int i = 0; i < post; ++i)
       timed<T>(kTimGs, en * (3.0 + 4.0 / (double)nb), act, nb, [&] {
-        varcoef_rbgs<T>(b, x, kf, dg, L.side, nb, act, false, true, s_);
+        varcoef_rbgs<T>(b, x, kf, dg, L.side, nb, L.cols, act, false, true, s_);
       });
   }
   if (rz_partials) vec_dot_partials<T>(b, x, n, nb, act, rz_partials, s_);

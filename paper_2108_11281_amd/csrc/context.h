@@ -38,8 +38,9 @@ struct Level {
   int blk = 0;
   // VARCOEF3D levels: face coefficients k[3][side][side][side+1] and the
   // diagonal (shift + six faces), FP64 and FP32 copies
-  double *kf64 = nullptr, *dg64 = nullptr;
-  float *kf32 = nullptr, *dg32 = nullptr;
+  double *kf64 = nullptr, *dg64 = nullptr, *kl64 = nullptr;
+  float *dg32 = nullptr, *kl32 = nullptr;
+  int cols = 4;  // right-hand sides per thread of the stencil kernels (autotuned)
 };
 
 // Batched flexible GMRES workspace (precision T)
@@ -122,6 +123,7 @@ class Context {
   }
   void build_poisson();
   void build_varcoef(const double* k);
+  void tune_varcoef();
   void finish_real_build();
   void build_wilson(const double* theta);
   void nn_alloc();

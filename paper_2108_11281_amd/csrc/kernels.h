@@ -172,25 +172,29 @@ void agg2d_prolong(const T* ec, T* x, int N, double omega, double beta, int nb,
                    const int* active, hipStream_t s);
 
 // ----- 3D 7-point variable-coefficient operator, N^3 cells, Dirichlet faces -----
-// k: face coefficients k[3][N][N][N+1] of one level (x-faces [z][y][f], y-faces
-// [z][x][f], z-faces [y][x][f]); diag[i] = shift + the six faces of cell i.
+// Face coefficients of one level: k[3][N][N][N+1] (x-faces [z][y][f], y-faces
+// [z][x][f], z-faces [y][x][f]); the stencil kernels read the cell-major
+// couplings kl[3][N^3 + N^2] (face below cell i in x, y, z; zero on the
+// boundary; padded) and diag dg[i] = shift + the six faces of cell i.  `cols`
+// (1, 2, 4 or 8): right-hand sides per thread, a tuning choice that does not
+// change results.
 int varcoef_blocks(int N);  // partial sums per column of residual / update_apply
 // r = b - A x ; b == nullptr: r = A x (partials then of conj(x)^T r)
 template <typename Tb, typename T, typename Tr>
-void varcoef_residual(const Tb* b, const T* x, Tr* r, const typename Traits<T>::real* k,
-                      const typename Traits<T>::real* diag, int N, int nb, const int* active,
-                      c64* partials, hipStream_t s);
+void varcoef_residual(const Tb* b, const T* x, Tr* r, const typename Traits<T>::real* kl,
+                      const typename Traits<T>::real* dg, int N, int nb, int cols,
+                      const int* active, c64* partials, hipStream_t s);
 // one in-place red-black Gauss-Seidel sweep (reverse: black first); zero_init:
 // x = 0 on entry (not read)
 template <typename T>
-void varcoef_rbgs(const T* b, T* x, const typename Traits<T>::real* k,
-                  const typename Traits<T>::real* diag, int N, int nb, const int* active,
+void varcoef_rbgs(const T* b, T* x, const typename Traits<T>::real* kl,
+                  const typename Traits<T>::real* dg, int N, int nb, int cols, const int* active,
                   bool zero_init, bool reverse, hipStream_t s);
 // xc = R (b - A x) when residual, else xc = R x; R the orthonormal 2x2x2
 // aggregation (entries 1/sqrt(8))
 template <typename T>
-void varcoef_restrict(const T* b, const T* x, T* xc, const typename Traits<T>::real* k,
-                      const typename Traits<T>::real* diag, int N, bool residual, int nb,
+void varcoef_restrict(const T* b, const T* x, T* xc, const typename Traits<T>::real* kl,
+                      const typename Traits<T>::real* dg, int N, bool residual, int nb, int cols,
                       const int* active, hipStream_t s);
 // x = beta x + omega P ec
 template <typename T>
@@ -199,14 +203,14 @@ void varcoef_prolong(const T* ec, T* x, int N, double omega, double beta, int nb
 // p_new = z + beta p_old ; q = A p_new ; partials of conj(p_new)^T q
 template <typename T>
 void varcoef_update_apply(const T* p_old, const T* z, const c64* beta, T* p_new, T* q,
-                          const typename Traits<T>::real* k,
-                          const typename Traits<T>::real* diag, int N, int nb, const int* active,
-                          c64* partials, hipStream_t s);
+                          const typename Traits<T>::real* kl,
+                          const typename Traits<T>::real* dg, int N, int nb, int cols,
+                          const int* active, c64* partials, hipStream_t s);
 // Galerkin faces of the next level: kc = 1/8 (sum of the 4 fine faces covered)
 void varcoef_coarsen(const double* kf, double* kc, int N, hipStream_t s);
-// diagonal (FP64 and FP32) and FP32 copy of the faces of one level
-void varcoef_diag(const double* k, double shift, int N, double* d64, float* d32, float* k32,
-                  hipStream_t s);
+// diagonal and cell-major couplings (FP64 and FP32) of one level
+void varcoef_diag(const double* k, double shift, int N, double* d64, float* d32, double* kl64,
+                  float* kl32, hipStream_t s);
 // left half of aug (n x 2n row-major, n = N^3) = the dense operator
 void varcoef_dense(const double* k, const double* diag, int N, double* aug, hipStream_t s);
 
