@@ -181,8 +181,9 @@ def run_poisson(args, m, torch):
     N, L = args.N, args.levels
     log("setup poisson2d N=%d L=%d nb=%d" % (N, L, args.nb))
     t0 = time.perf_counter()
+    vc = dict(nu_pre=args.nu, nu_post=args.nu)
     est = m.TraceEstimator("poisson2d", N, L, L, precision="fp32_ir64", nb=args.nb,
-                           solve_tol=1e-10, alloc=args.alloc)
+                           solve_tol=1e-10, alloc=args.alloc, **vc)
     setup_s = time.perf_counter() - t0
     log("setup %.2fs" % setup_s)
     for i in range(args.warmup):
@@ -216,8 +217,21 @@ def run_poisson(args, m, torch):
     if not args.no_compare:
         est.close()
         log("plain FP64 MLMC, same workload")
+        log("FP32 + refinement with HIP-graph replay of the CG iterations (no kernel timing)")
+        eg = m.TraceEstimator("poisson2d", N, L, L, precision="fp32_ir64", nb=args.nb,
+                              solve_tol=1e-10, alloc=args.alloc, graphs=1, **vc)
+        eg.trace(args.eps, 1000)
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        for i in range(args.steps):
+            eg.trace(args.eps, i + 1)
+        torch.cuda.synchronize()
+        compare["graphs_s_per_trace"] = round((time.perf_counter() - tg) / args.steps, 4)
+        eg.set_timing(False)
+        eg.close()
+        log("graphs: %.3fs per trace" % compare["graphs_s_per_trace"])
         e64 = m.TraceEstimator("poisson2d", N, L, L, precision="fp64", nb=args.nb,
-                               solve_tol=1e-10, alloc=args.alloc)
+                               solve_tol=1e-10, alloc=args.alloc, **vc)
         r64 = e64.trace(args.eps, 1)
         compare["fp64_mlmc_s"] = round(r64["seconds"], 3)
         compare["fp64_mlmc_n_samples"] = r64["n_samples"]
@@ -246,7 +260,7 @@ def run_poisson(args, m, torch):
               "variant": "FP32 inner Krylov + V-cycle, FP64 reliable-update refinement "
                          "(no learned smoother on this operator)",
               "n": N * N, "levels": L, "nb": args.nb, "eps": args.eps, "alloc": args.alloc,
-              "solve_tol": 1e-10}
+              "solve_tol": 1e-10, "nu_pre": args.nu, "nu_post": args.nu, "omega": 1.8}
     contract(args, round(ms_per_step / 1000.0, 4), "s", False, ms_per_step, "f32+f64ir",
              "synthetic (Rademacher probes from Philox4x64-10 on the device)", config,
              roofline, cpu, accuracy=accuracy, setup_s=round(setup_s, 3), kernels=kernels,
@@ -425,6 +439,7 @@ def main():
     ap.add_argument("--levels", type=int, default=6)
     ap.add_argument("--nb", type=int, default=128)
     ap.add_argument("--alloc", default="giles")
+    ap.add_argument("--nu", type=int, default=2, help="poisson1024: sweeps before and after")
     ap.add_argument("--workers", type=int, default=4, help="varcoef_batch: host workers")
     ap.add_argument("--train-batches", type=int, default=80,
                     help="wilson512: plain solves used for training = this x nb")

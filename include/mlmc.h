@@ -117,6 +117,12 @@ typedef struct mlmc_options {
   int learned;        /* 1: learned smoother on the finest level (WILSON2D with
                          MLMC_FP32_IR64, lattice side a multiple of 16); it
                          takes effect once weights are set or trained.  0: plain */
+  int graphs;         /* 1: the FP32 refined CG of the real operators replays the
+                         two iterations between refinement checks (V-cycles,
+                         direction update, x/r update, refinement test) from a
+                         HIP graph captured once per (level, batch width);
+                         results are bitwise identical.  Bypassed while
+                         per-kernel timing is on.  0: direct launches */
 } mlmc_options;
 
 #define MLMC_MAX_LEVELS 16
@@ -140,7 +146,7 @@ typedef struct mlmc_result {
 
 /* Fill *opt with defaults: FP32_IR64, nb 128, 1+1 sweeps, omega 1.8, EQUAL,
  * solve_tol 1e-10, inner_tol 1e-2, max_iter 200, max_refine 8, restart 16,
- * min_samples 5, max_samples 2^22, tau 0, learned 0. */
+ * min_samples 5, max_samples 2^22, tau 0, learned 0, graphs 0. */
 int mlmc_default_options(mlmc_options* opt);
 
 /* Build the hierarchy on the device: copies the operator data, forms the

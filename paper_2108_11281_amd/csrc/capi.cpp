@@ -64,6 +64,7 @@ int mlmc_default_options(mlmc_options* opt) {
   opt->max_samples = (int64_t)1 << 22;
   opt->tau = 0.0;
   opt->learned = 0;
+  opt->graphs = 0;
   return MLMC_OK;
 }
 

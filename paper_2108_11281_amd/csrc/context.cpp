@@ -80,6 +80,8 @@ Context::Context(const mlmc_operator& A, const mlmc_hierarchy& h, const mlmc_opt
 
 Context::~Context() {
   (void)hipStreamSynchronize(s_);
+  for (auto& kv : graphs_) (void)hipGraphExecDestroy(kv.second);
+  if (cap_s_) (void)hipStreamDestroy(cap_s_);
   for (const Pending& p : pending_) {
     (void)hipEventDestroy(p.a);
     (void)hipEventDestroy(p.b);
@@ -739,12 +741,12 @@ void Context::pcg_refined(int l, const double* b, double* y, int nb, double tol,
   vcycle<float>(l, r, w.z, nb, act, partials_);
   finish_sums(partials_, nvp, nb, rz, s_);
   vec_zero<c64>(beta, 1, nb, nullptr, s_);
-  float* p_old = w.z;
-  float* p_new = w.p;
   const double delta2 = opt_.inner_tol * opt_.inner_tol;
-  const int check = 2;
   const int max_it = opt_.max_iter * opt_.max_refine;
-  for (int it = 1; it <= max_it; ++it) {
+  float* P1 = w.p;
+  float* P2 = w.p2;
+  // one CG iteration: p_new = z + beta p_old, q = A p_new, alpha, x/r update
+  auto core = [&](float* p_old, float* p_new) {
     timed<float>(kTimApply, 4.0 * en, act, nb,
                  [&] { op_update_apply<float>(l, p_old, w.z, beta, p_new, w.q, nb, act); });
     finish_sums(partials_, ntiles, nb, tmp, s_);
@@ -752,37 +754,118 @@ void Context::pcg_refined(int l, const double* b, double* y, int nb, double tol,
     timed<float>(kTimCgXr, 6.0 * en, act, nb,
                  [&] { cg_update_xr<float>(x32, r, p_new, w.q, alpha, n, nb, act, partials_, s_); });
     finish_sums(partials_, nblk, nb, tmp, s_);
-    counters[0] += 1;
-    if (it % check == 0 || it == max_it) {
-      // a refinement is due when some column's recursive residual has dropped
-      // by inner_tol since its last refinement, or reached the tolerance
-      refine_due(tmp, rr_upd, bb, delta2, tol * tol, act, nb, count_dev_ + 1, s_);
-      MLMC_HIP(hipMemcpyAsync(count_host_ + 1, count_dev_ + 1, sizeof(int),
-                              hipMemcpyDeviceToHost, s_));
-      MLMC_HIP(hipStreamSynchronize(s_));
-      if (count_host_[1] > 0 || it == max_it) {
-        ir_accumulate<double, float>(y, x32, n, nb, act, s_);
-        vec_convert<double, float>(x32, r64_, n, nb, act, s_);
-        vec_dot_partials<double>(b, r64_, n, nb, act, partials_, s_);
-        finish_sums(partials_, nblk, nb, bd, s_);
-        vec_zero<float>(x32, n, nb, act, s_);
-        timed<double>(kTimIrResidual, 20.0 * (double)n, act, nb, [&] {
-          op_residual<double, double, float>(l, b, y, r, nb, act, partials_);
-        });
-        finish_sums(partials_, ntiles, nb, rr_new, s_);
-        ir_stated_error(bd, rr_upd, rr_new, act, err, nb, s_);
-        select_active(rr_upd, rr_new, act, nb, s_);
-        mark_converged(rr_new, bb, tol * tol, act, nb, count_dev_, s_);
-        counters[1] += 1;
-        if (read_count() == 0) break;
-      }
-    }
+  };
+  // preconditioner and the next direction's beta
+  auto tail = [&] {
     vcycle<float>(l, r, w.z, nb, act, partials_);
     finish_sums(partials_, nvp, nb, tmp, s_);
     cg_beta(tmp, rz, act, beta, nb, s_);
-    p_old = p_new;
-    p_new = (p_new == w.p) ? w.p2 : w.p;
+  };
+  // a refinement is due when some column's recursive residual has dropped by
+  // inner_tol since its last refinement, or reached the tolerance
+  auto due = [&] {
+    refine_due(tmp, rr_upd, bb, delta2, tol * tol, act, nb, count_dev_ + 1, s_);
+    MLMC_HIP(hipMemcpyAsync(count_host_ + 1, count_dev_ + 1, sizeof(int), hipMemcpyDeviceToHost,
+                            s_));
+  };
+  // after due(): refine in FP64 if needed; true when every column converged
+  auto refine = [&](bool force) {
+    MLMC_HIP(hipStreamSynchronize(s_));
+    if (count_host_[1] == 0 && !force) return false;
+    ir_accumulate<double, float>(y, x32, n, nb, act, s_);
+    vec_convert<double, float>(x32, r64_, n, nb, act, s_);
+    vec_dot_partials<double>(b, r64_, n, nb, act, partials_, s_);
+    finish_sums(partials_, nblk, nb, bd, s_);
+    vec_zero<float>(x32, n, nb, act, s_);
+    timed<double>(kTimIrResidual, 20.0 * (double)n, act, nb, [&] {
+      op_residual<double, double, float>(l, b, y, r, nb, act, partials_);
+    });
+    finish_sums(partials_, ntiles, nb, rr_new, s_);
+    ir_stated_error(bd, rr_upd, rr_new, act, err, nb, s_);
+    select_active(rr_upd, rr_new, act, nb, s_);
+    mark_converged(rr_new, bb, tol * tol, act, nb, count_dev_, s_);
+    counters[1] += 1;
+    return read_count() == 0;
+  };
+  // iterations 1 and 2 directly (the first direction is z itself), then pairs of
+  // iterations between refinement checks: (p2 -> p), (p -> p2), which repeat
+  // with fixed pointers and can be replayed from a graph
+  int it = 1;
+  core(w.z, P1);
+  counters[0] += 1;
+  if (it == max_it) {
+    due();
+    refine(true);
+    return;
   }
+  tail();
+  core(P1, P2);
+  counters[0] += 1;
+  it = 2;
+  due();
+  if (refine(it == max_it)) return;
+  const bool use_graph = opt_.graphs && !timing_;
+  while (it < max_it) {
+    if (it + 2 <= max_it) {
+      auto pair = [&] {
+        tail();
+        core(P2, P1);
+        tail();
+        core(P1, P2);
+        due();
+      };
+      if (use_graph) {
+        hipGraphExec_t ex = graph_for({l, nb}, pair);
+        MLMC_HIP(hipGraphLaunch(ex, s_));
+        if (l == 1) counters[2] += 2;
+      } else {
+        pair();
+      }
+      counters[0] += 2;
+      it += 2;
+      if (refine(it == max_it)) return;
+    } else {
+      tail();
+      core(P2, P1);
+      counters[0] += 1;
+      it += 1;
+      due();
+      refine(true);
+      return;
+    }
+  }
+}
+
+hipGraphExec_t Context::graph_for(std::pair<int, int> key, const std::function<void()>& body) {
+  auto found = graphs_.find(key);
+  if (found != graphs_.end()) return found->second;
+  // capture on a stream of our own (the caller's stream may be the legacy
+  // default stream, which cannot be captured): the launches of `body` go to s_,
+  // so s_ points at the capture stream while recording
+  if (!cap_s_) MLMC_HIP(hipStreamCreateWithFlags(&cap_s_, hipStreamNonBlocking));
+  int64_t saved[4];
+  std::memcpy(saved, counters, sizeof(saved));
+  hipGraph_t g = nullptr;
+  hipStream_t caller = s_;
+  MLMC_HIP(hipStreamBeginCapture(cap_s_, hipStreamCaptureModeThreadLocal));
+  s_ = cap_s_;
+  try {
+    body();
+  } catch (...) {
+    s_ = caller;
+    (void)hipStreamEndCapture(cap_s_, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  s_ = caller;
+  MLMC_HIP(hipStreamEndCapture(cap_s_, &g));
+  std::memcpy(counters, saved, sizeof(saved));  // capture only recorded the launches
+  hipGraphExec_t ex = nullptr;
+  const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  MLMC_HIP(e);
+  graphs_[key] = ex;
+  return ex;
 }
 
 // ---------------------------------------------------------------------------

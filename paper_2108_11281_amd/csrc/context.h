@@ -2,7 +2,9 @@
 #pragma once
 
 #include <functional>
+#include <map>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "kernels.h"
@@ -180,6 +182,10 @@ class Context {
   template <typename T> int pcg(int l, const T* b, T* x, int nb, int* act, double tol,
                                 c64* lastcorr);
   void pcg_refined(int l, const double* b, double* y, int nb, double tol, c64* err);
+  // HIP graph of `body` captured on the context stream once per key
+  hipGraphExec_t graph_for(std::pair<int, int> key, const std::function<void()>& body);
+  std::map<std::pair<int, int>, hipGraphExec_t> graphs_;
+  hipStream_t cap_s_ = nullptr;  // library-owned stream that graphs are captured on
   // FP64 solve of level l for nb columns; b, y FP64; err: per-column stated error
   // contributions (device c64 nb), relres host (nullable)
   void solve(int l, const double* b, double* y, int nb, c64* err, double* relres_host,
