@@ -321,7 +321,8 @@ def run_wilson(args, m, torch, N, learned):
                         avg_launch_us=round(1000.0 * ms / max(launches, 1), 2),
                         algorithmic_flops_per_launch=round(flops / max(launches, 1)))
     else:
-        roofline = hbm_roofline("k_wilson_gs<c32> (sweep of both colours)", ks,
+        roofline = hbm_roofline("smoother sweeps: k_wilson_gs<c32> (finest) and "
+                                "k_bsr_gs<8, c32> (coarse block stencils)", ks,
                                 args.timing_stride)
     compare = {"learned_stats": list(est.learned_stats())} if learned else {}
     est.close()

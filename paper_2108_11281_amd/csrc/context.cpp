@@ -241,6 +241,57 @@ void Context::build_poisson() {
   }
   MLMC_REQUIRE(lv_[Ls_ - 1].n <= 16384, MLMC_EINVAL, "coarsest solver level larger than 128^2");
   finish_real_build();
+  tune_poisson();
+}
+
+// Autotuner of the fused Poisson sweep: per smoothed level with N >= 64, time
+// the heaviest form (input iterate and folded coarse correction) over all nb
+// columns for each compiled segment length and keep the fastest.  The swept
+// values do not depend on the choice; the fused r^T z partial sums are grouped
+// by segment, so the FP32 recursion can differ in its last bits (the FP64
+// judged solution still meets solve_tol).  Runs once at setup on the library's
+// work vectors.
+void Context::tune_poisson() {
+  hipEvent_t a = event(), b = event();
+  auto tune = [&](auto tag, Level& L, int slot, int l) {
+    using T = decltype(tag);
+    Work<T>& w = work<T>();
+    int opts[3];
+    gs_rows_options<T>(opts);
+    // the default segment length is kept unless another is at least 5% faster,
+    // so that the choice (which sets the grouping of the sweep's fused partial
+    // sums, hence the last bits of the FP32 recursion) does not flap between runs
+    const int dflt = L.gs_rows[slot];
+    float best = 1e30f, t_dflt = 1e30f;
+    int best_rows = dflt;
+    for (int rows : opts) {
+      float ms = 0.f;
+      for (int rep = 0; rep < 3; ++rep) {
+        MLMC_HIP(hipEventRecord(a, s_));
+        poisson_rbgs_fused<T>(w.z, w.r, w.q, w.vb[l], omega_, L.side, L.d, L.c, nb_, nullptr,
+                              true, nullptr, rows, s_);
+        MLMC_HIP(hipEventRecord(b, s_));
+        MLMC_HIP(hipEventSynchronize(b));
+        float t = 0.f;
+        MLMC_HIP(hipEventElapsedTime(&t, a, b));
+        if (rep > 0) ms += t;  // the first run warms caches and code
+      }
+      if (rows == dflt) t_dflt = ms;
+      if (ms < best) {
+        best = ms;
+        best_rows = rows;
+      }
+    }
+    L.gs_rows[slot] = best < 0.95f * t_dflt ? best_rows : dflt;
+  };
+  for (int l = 1; l < Ls_; ++l) {
+    Level& L = lv_[l - 1];
+    if (L.side < 64) continue;
+    if (opt_.precision == MLMC_FP32_IR64) tune(float(), L, 0, l);
+    if (opt_.precision == MLMC_FP64) tune(double(), L, 1, l);
+  }
+  ev_pool_.push_back(a);
+  ev_pool_.push_back(b);
 }
 
 // 3D diffusion with face coefficients: every level keeps the 7-point form, the
@@ -509,8 +560,8 @@ void Context::vcycle(int l, const T* b, T* x, int nb, const int* act, c64* rz_pa
     T* out = (i % 2 == 0) ? tmp : x;
     const T* in = u;
     timed<T>(kTimGs, en * (2.0 + (in ? 1.0 : 0.0)), act, nb, [&] {
-      poisson_rbgs_fused<T>(in, b, out, nullptr, 0.0, L.side, L.d, L.c, nb, act, false,
-                            nullptr, s_);
+      poisson_rbgs_fused<T>(in, b, out, nullptr, 0.0, L.side, L.d, L.c, nb, act, false, nullptr,
+                            gs_rows<T>(l), s_);
     });
     u = out;
   }
@@ -542,7 +593,7 @@ void Context::vcycle(int l, const T* b, T* x, int nb, const int* act, c64* rz_pa
     const bool last = (i == post - 1);
     timed<T>(kTimGs, en * (2.0 + (in ? 1.0 : 0.0) + (corr ? 0.25 : 0.0)), act, nb, [&] {
       poisson_rbgs_fused<T>(in, b, out, corr, omega_, L.side, L.d, L.c, nb, act, true,
-                            last ? rz_partials : nullptr, s_);
+                            last ? rz_partials : nullptr, gs_rows<T>(l), s_);
     });
     u = out;
   }
@@ -571,7 +622,7 @@ int Context::vcycle_partials(int l, bool* fused) const {
   }
   if (u != kX) return reduce_blocks(n);
   *fused = true;
-  return poisson_gs_tiles<T>(lv_[l - 1].side);
+  return poisson_gs_tiles<T>(lv_[l - 1].side, gs_rows<T>(l));
 }
 
 // ---------------------------------------------------------------------------

@@ -43,6 +43,8 @@ struct Level {
   double *kf64 = nullptr, *dg64 = nullptr, *kl64 = nullptr;
   float *dg32 = nullptr, *kl32 = nullptr;
   int cols = 4;  // right-hand sides per thread of the stencil kernels (autotuned)
+  // POISSON2D: rows per segment of the fused sweep, FP32 and FP64 (autotuned)
+  int gs_rows[2] = {16, 8};
 };
 
 // Batched flexible GMRES workspace (precision T)
@@ -62,6 +64,9 @@ struct Work {
   // V-cycle right-hand side / solution / sweep scratch per level (0-based)
   std::vector<T*> vb, vx, vt;
   T* ainvT = nullptr;       // transposed inverse of the solver's coarsest operator
+  // complex operators: its real representation (2n x 2n, transposed) for the
+  // real MFMA product on interleaved vectors
+  typename Traits<T>::real* ainvR = nullptr;
 };
 
 struct Estimate;
@@ -126,6 +131,10 @@ class Context {
   void build_poisson();
   void build_varcoef(const double* k);
   void tune_varcoef();
+  void tune_poisson();
+  template <typename T> int gs_rows(int l) const {
+    return lv_[l - 1].gs_rows[sizeof(typename Traits<T>::real) == 8 ? 1 : 0];
+  }
   void finish_real_build();
   void build_wilson(const double* theta);
   void nn_alloc();
@@ -146,6 +155,7 @@ class Context {
   template <typename T> void cop_prolong(int l, const T* ec, T* x, int nb, const int* act,
                                          double omega, double beta);
   template <typename T> void cvcycle(int l, const T* b, T* x, int nb, const int* act);
+  template <typename T> void coarse_apply(const T* b, T* x, int nb, const int* act);
   template <typename T> void fgmres_cycle(int l, const T* r, T* d, int nb, int* act,
                                           double tol);
   void solve_complex(int l, const c64* b, c64* y, int nb, c64* err);

@@ -174,6 +174,16 @@ void Context::build_wilson(const double* theta) {
     wc32_.ainvT = dalloc_n<c32>((int64_t)ns * ns);
     vec_convert<c32, c64>(wc64_.ainvT, wc32_.ainvT, (int64_t)ns * ns, 1, nullptr, s_);
   }
+  // the coarsest solve as a real MFMA product with the 2n x 2n real
+  // representation (interleaved complex vectors are real vectors of length 2n)
+  if ((2 * ns) % 16 == 0) {
+    wc64_.ainvR = dalloc_n<double>(4 * (int64_t)ns * ns);
+    dense_complex_to_real<c64, double>(wc64_.ainvT, wc64_.ainvR, ns, s_);
+    if (opt_.precision == MLMC_FP32_IR64) {
+      wc32_.ainvR = dalloc_n<float>(4 * (int64_t)ns * ns);
+      dense_complex_to_real<c32, float>(wc32_.ainvT, wc32_.ainvR, ns, s_);
+    }
+  }
   if (L_ == Ls_) {
     coarse_trace_ = tr_s;
   } else {
@@ -210,8 +220,16 @@ void Context::cop_smooth(int l, const T* b, T* x, int nb, const int* act, bool z
     timed<T>(kTimGs, bytes, act, nb, [&] {
       wilson_rbgs<T>(b, x, links<T>(l), L.side, op_.mass + 2.0, nb, act, zero_init, reverse, s_);
     });
-  } else
-    bsr_rbgs<T>(b, x, blocks<T>(l), dinv<T>(l), L.side, L.dof, nb, act, zero_init, reverse, s_);
+  } else {
+    // per column: b and x read, x written (dof complex values per site), the
+    // site's 5 stencil blocks and inverted diagonal block once per launch
+    const double es = (double)sizeof(T) * L.dof * (double)L.side * L.side;
+    const double bytes = es * (zero_init ? 2.5 : 3.0) + 6.0 * L.dof * es / (double)nb;
+    timed<T>(kTimGs, bytes, act, nb, [&] {
+      bsr_rbgs<T>(b, x, blocks<T>(l), dinv<T>(l), L.side, L.dof, nb, act, zero_init, reverse,
+                  s_);
+    });
+  }
 }
 
 template <typename T>
@@ -230,13 +248,26 @@ void Context::cop_prolong(int l, const T* ec, T* x, int nb, const int* act, doub
 // V-cycle on levels l..L_s: x = M b (pre-smoothing from zero, residual,
 // restriction, recursion, prolongation with omega, post-smoothing in the
 // reverse colour order)
+// coarsest solve x = A_{L_s}^{-1} b of the complex hierarchy
+template <typename T>
+void Context::coarse_apply(const T* b, T* x, int nb, const int* act) {
+  using R = typename Traits<T>::real;
+  Work<T>& w = work<T>();
+  const int n = (int)lv_[Ls_ - 1].n;
+  if (w.ainvR)
+    dense_apply<R>(w.ainvR, reinterpret_cast<const R*>(b), reinterpret_cast<R*>(x), 2 * n, nb,
+                   act, s_);
+  else
+    dense_apply<T>(w.ainvT, b, x, n, nb, act, s_);
+}
+
 template <typename T>
 void Context::cvcycle(int l, const T* b, T* x, int nb, const int* act) {
   Work<T>& w = work<T>();
   const int64_t n = lv_[l - 1].n;
   if (l == 1) counters[2] += 1;
   if (l == Ls_) {
-    dense_apply<T>(w.ainvT, b, x, (int)n, nb, act, s_);
+    coarse_apply<T>(b, x, nb, act);
     return;
   }
   if constexpr (std::is_same<T, c32>::value) {
@@ -325,7 +356,7 @@ void Context::solve_complex(int l, const c64* b, c64* y, int nb, c64* err) {
   set_all_active(act_outer_, nb, s_);
   vec_zero<c64>(err, 1, nb, nullptr, s_);
   if (l == Ls_) {
-    dense_apply<c64>(wc64_.ainvT, b, y, (int)n, nb, nullptr, s_);
+    coarse_apply<c64>(b, y, nb, nullptr);
     return;
   }
   vec_zero<c64>(y, n, nb, nullptr, s_);

@@ -128,6 +128,10 @@ void dense_trace(const T* A, int n, c64* out, hipStream_t s);
 template <typename T>
 void dense_apply(const T* At, const T* B, T* Z, int n, int nb, const int* active,
                  hipStream_t s);
+// Mt (2n x 2n, real) = transposed real representation of the complex matrix
+// whose transpose is At, for dense_apply<R> on interleaved (re, im) vectors
+template <typename T, typename R>
+void dense_complex_to_real(const T* At, R* Mt, int n, hipStream_t s);
 // out[j][i] = in[i][j] (n x n)
 template <typename T>
 void dense_transpose(const T* in, T* out, int n, hipStream_t s);
@@ -136,7 +140,10 @@ void dense_transpose(const T* in, T* out, int n, hipStream_t s);
 // partial-sum counts per column of the tiled kernels
 int poisson_march_tiles(int N);   // apply / residual
 template <typename T>
-int poisson_gs_tiles(int N);      // fused Gauss-Seidel sweep
+int poisson_gs_tiles(int N, int rows);  // fused Gauss-Seidel sweep, `rows` per segment
+// the three segment lengths the sweep is compiled for (ascending)
+template <typename T>
+void gs_rows_options(int out[3]);
 template <typename T>
 void poisson_dense_build(T* aug, int N, double d, double c, hipStream_t s);
 // y = A x ; optional partials of conj(x)^T y (pass partials = nullptr to skip)
@@ -154,11 +161,13 @@ void poisson_residual(const Tb* b, const Tx* x, Tr* r, int N, double d, double c
                       int nb, const int* active, c64* partials, hipStream_t s);
 // one fused red-black Gauss-Seidel sweep: xout = S(xin + omega/2 P ec ; b),
 // red first (reverse: black first); xin == nullptr means 0, ec == nullptr no
-// correction; partials (nullable): shares of conj(b)^T xout, gs_tiles per column
+// correction; partials (nullable): shares of conj(b)^T xout, gs_tiles per
+// column; rows: segment length (one of gs_rows_options; a tuning choice that
+// does not change results)
 template <typename T>
 void poisson_rbgs_fused(const T* xin, const T* b, T* xout, const T* ec, double omega, int N,
                         double d, double c, int nb, const int* active, bool reverse,
-                        c64* partials, hipStream_t s);
+                        c64* partials, int rows, hipStream_t s);
 // rc = R (b - A x), R = P^T, P the orthonormal 2x2 aggregation (entries 1/2)
 template <typename T>
 void poisson_residual_restrict(const T* b, const T* x, T* rc, int N, double d,

@@ -150,11 +150,9 @@ __global__ __launch_bounds__(kThreads) void k_rbgs_tile(const T* __restrict__ xi
 // ---------------------------------------------------------------------------
 constexpr int SCOLS = 62;       // owned columns per wave
 
-// rows per segment: all loads of a segment are issued before its arithmetic,
-// so the row count is bounded by registers (3 values per row and lane)
-template <typename T> struct GsRows;
-template <> struct GsRows<float> { static constexpr int value = 16; };
-template <> struct GsRows<double> { static constexpr int value = 8; };
+// rows per segment (SR): all loads of a segment are issued before its
+// arithmetic, so the row count is bounded by registers (4 values per row and
+// lane); chosen per level by the setup-time autotuner among gs_rows_options
 
 // branch-free guarded load: the address is always valid (clamped to the base)
 template <typename T>
@@ -188,7 +186,7 @@ __device__ __forceinline__ double wave_shl1(double v) {
   return __longlong_as_double(((long long)h2 << 32) | (unsigned int)l2);
 }
 
-template <typename T, bool HX, bool HE>
+template <typename T, bool HX, bool HE, int SR>
 __global__ __launch_bounds__(kThreads) void k_rbgs_march(const T* __restrict__ xin,
                                                          const T* __restrict__ b,
                                                          T* __restrict__ xout,
@@ -196,7 +194,6 @@ __global__ __launch_bounds__(kThreads) void k_rbgs_march(const T* __restrict__ x
                                                          int N, R_t<T> dinv, R_t<T> c,
                                                          int first, int nb, const int* active,
                                                          c64* partials, int* tlog) {
-  constexpr int SR = GsRows<T>::value;
   constexpr int NR = SR + 4;
   __shared__ double red[16];
   const int nwx = (N + SCOLS - 1) / SCOLS, nseg = (N + SR - 1) / SR;
@@ -216,9 +213,9 @@ __global__ __launch_bounds__(kThreads) void k_rbgs_march(const T* __restrict__ x
   const int yend = ys + SR < N ? ys + SR : N;
   const bool col_in = unit_ok && x >= 0 && x < N;
   const bool owned = col_in && lane >= 1 && lane <= SCOLS;
-  // halo lanes load their outer neighbour column, the others their own column
+  // the two halo lanes load their outer neighbour column (only they read E)
   const int xe = (lane == 0) ? x - 1 : (lane == 63 ? x + 1 : x);
-  const bool edge_in = unit_ok && xe >= 0 && xe < N;
+  const bool edge_in = unit_ok && (lane == 0 || lane == 63) && xe >= 0 && xe < N;
   const int64_t n = (int64_t)N * N;
   const int Nc = N >> 1;
   const T* xc = xin + (HX ? (int64_t)k * n : 0);
@@ -338,9 +335,11 @@ __global__ __launch_bounds__(kThreads) void k_apply_march(const T* __restrict__ 
   if (UPD) bt = beta[m.k];
   const bool col_ok = m.x < N;
   const int xs = col_ok ? m.x : 0;
-  // loads first (branch-free): the column (rows ybeg-1 .. ybeg+MY) and both
-  // side columns
-  T cz[MY + 2], cx[MY + 2], lz[MY], lx[MY], rz[MY], rx[MY];
+  const int lane = threadIdx.x & 63;  // a wave covers 64 consecutive columns
+  // loads first (branch-free): the column (rows ybeg-1 .. ybeg+MY); the side
+  // columns come from the neighbouring lanes (DPP), except for the two edge
+  // lanes, which load the column beyond the wave
+  T cz[MY + 2], cx[MY + 2], ez[MY], ex[MY];
 #pragma unroll
   for (int j = 0; j < MY + 2; ++j) {
     const int yy = m.ybeg - 1 + j;
@@ -348,23 +347,25 @@ __global__ __launch_bounds__(kThreads) void k_apply_march(const T* __restrict__ 
     cx[j] = ldz(xc, yy * N + xs, ok);
     cz[j] = UPD ? ldz(zc, yy * N + xs, ok) : zero_of(T());
   }
+  const int xe = lane == 0 ? m.x - 1 : m.x + 1;  // edge lanes' outer column
+  const bool edge = (lane == 0 || lane == 63) && xe >= 0 && xe < N;
 #pragma unroll
   for (int j = 0; j < MY; ++j) {
     const int yy = m.ybeg + j;
-    const bool ok = col_ok && yy < m.yend;
-    const bool okl = ok && m.x > 0, okr = ok && m.x + 1 < N;
-    lx[j] = ldz(xc, yy * N + xs - 1, okl);
-    rx[j] = ldz(xc, yy * N + xs + 1, okr);
-    lz[j] = UPD ? ldz(zc, yy * N + xs - 1, okl) : zero_of(T());
-    rz[j] = UPD ? ldz(zc, yy * N + xs + 1, okr) : zero_of(T());
+    const bool ok = edge && yy < m.yend;
+    ex[j] = ldz(xc, yy * N + xe, ok);
+    ez[j] = UPD ? ldz(zc, yy * N + xe, ok) : zero_of(T());
   }
   auto P = [&](T zz, T xx) -> T { return UPD ? zz + scale_by(bt.re, bt.im, xx) : xx; };
 #pragma unroll
   for (int j = 0; j < MY; ++j) {
     const int yy = m.ybeg + j;
     const T mid = P(cz[j + 1], cx[j + 1]);
-    const T v = d * mid - c * (P(cz[j], cx[j]) + P(cz[j + 2], cx[j + 2]) + P(lz[j], lx[j]) +
-                               P(rz[j], rx[j]));
+    const T pe = P(ez[j], ex[j]);
+    const T sl = wave_shr1(mid), sr = wave_shl1(mid);
+    const T left = lane == 0 ? pe : sl;
+    const T right = lane == 63 ? pe : sr;
+    const T v = d * mid - c * (P(cz[j], cx[j]) + P(cz[j + 2], cx[j + 2]) + left + right);
     if (col_ok && yy < m.yend) {
       yc[yy * N + m.x] = v;
       if (UPD) xn[yy * N + m.x] = mid;
@@ -450,42 +451,49 @@ __global__ __launch_bounds__(kThreads) void k_res_restrict2(const T* __restrict_
   const T* xc = x + (int64_t)m.k * n;
   const T* bc = b + (int64_t)m.k * n;
   T* out = rc + (int64_t)m.k * nc;
-  if (m.x >= Nc) return;
-  const int fx = 2 * m.x;
+  // lanes of a wave are 64 consecutive coarse columns (128 fine columns); the
+  // fine neighbours left of 2x and right of 2x+1 come from the neighbouring
+  // lanes (DPP), the two edge lanes load the column beyond the wave.  No early
+  // exit: every lane takes part in the lane shifts.
+  const int lane = threadIdx.x & 63;
+  const bool col_ok = m.x < Nc;
+  const int fx = 2 * (col_ok ? m.x : 0);
   constexpr int FR = 2 * RR + 2;  // fine rows 2*ybeg-1 .. 2*ybeg+2*RR
-  T x0[FR], x1[FR], xl[2 * RR], xr[2 * RR], b0[2 * RR], b1[2 * RR];
+  T x0[FR], x1[FR], xe[2 * RR], b0[2 * RR], b1[2 * RR];
   const int fy0 = 2 * m.ybeg - 1, fyend = 2 * m.yend;  // exclusive
 #pragma unroll
   for (int j = 0; j < FR; ++j) {
     const int yy = fy0 + j;
-    const bool ok = yy >= 0 && yy < N && yy <= fyend;
+    const bool ok = col_ok && yy >= 0 && yy < N && yy <= fyend;
     x0[j] = ldz(xc, yy * N + fx, ok);
     x1[j] = ldz(xc, yy * N + fx + 1, ok);
   }
+  const int fe = lane == 0 ? fx - 1 : fx + 2;  // edge lanes' outer fine column
+  const bool edge = col_ok && (lane == 0 || lane == 63) && fe >= 0 && fe < N;
 #pragma unroll
   for (int j = 0; j < 2 * RR; ++j) {
     const int yy = 2 * m.ybeg + j;
-    const bool ok = yy < fyend;
-    xl[j] = ldz(xc, yy * N + fx - 1, ok && fx > 0);
-    xr[j] = ldz(xc, yy * N + fx + 2, ok && fx + 2 < N);
+    const bool ok = col_ok && yy < fyend;
+    xe[j] = ldz(xc, yy * N + fe, ok && edge);
     b0[j] = ldz(bc, yy * N + fx, ok);
     b1[j] = ldz(bc, yy * N + fx + 1, ok);
   }
 #pragma unroll
   for (int Yl = 0; Yl < RR; ++Yl) {
-    if (m.ybeg + Yl < m.yend) {
-      T acc = zero_of(T());
+    T acc = zero_of(T());
 #pragma unroll
-      for (int dy = 0; dy < 2; ++dy) {
-        const int j = 2 * Yl + dy;       // index into the 2*RR fine rows
-        const int jc = j + 1;            // index into x0/x1 (offset by the upper row)
-        // fine point (fx, row j): neighbours left xl, right x1, up/down x0
-        acc += b0[j] - (d * x0[jc] - c * (xl[j] + x1[jc] + x0[jc - 1] + x0[jc + 1]));
-        // fine point (fx+1, row j): neighbours left x0, right xr, up/down x1
-        acc += b1[j] - (d * x1[jc] - c * (x0[jc] + xr[j] + x1[jc - 1] + x1[jc + 1]));
-      }
-      out[(m.ybeg + Yl) * Nc + m.x] = (R_t<T>)0.5 * acc;
+    for (int dy = 0; dy < 2; ++dy) {
+      const int j = 2 * Yl + dy;       // index into the 2*RR fine rows
+      const int jc = j + 1;            // index into x0/x1 (offset by the upper row)
+      const T sl = wave_shr1(x1[jc]), sr = wave_shl1(x0[jc]);
+      const T xl = lane == 0 ? xe[j] : sl;    // fine column 2x-1
+      const T xr = lane == 63 ? xe[j] : sr;   // fine column 2x+2
+      // fine point (fx, row j): neighbours left xl, right x1, up/down x0
+      acc += b0[j] - (d * x0[jc] - c * (xl + x1[jc] + x0[jc - 1] + x0[jc + 1]));
+      // fine point (fx+1, row j): neighbours left x0, right xr, up/down x1
+      acc += b1[j] - (d * x1[jc] - c * (x0[jc] + xr + x1[jc - 1] + x1[jc + 1]));
     }
+    if (col_ok && m.ybeg + Yl < m.yend) out[(m.ybeg + Yl) * Nc + m.x] = (R_t<T>)0.5 * acc;
   }
 }
 
@@ -552,16 +560,18 @@ int poisson_march_tiles(int N) { return ((N + MX - 1) / MX) * ((N + MTY - 1) / M
 // partial sums per column of the fused sweep: blocks of 4 column-marching waves
 // for N >= 64, LDS tiles below
 template <typename T>
-int poisson_gs_tiles(int N) {
+int poisson_gs_tiles(int N, int rows) {
   if (N >= 64) {
-    constexpr int SR = GsRows<T>::value;
-    const int units = ((N + SCOLS - 1) / SCOLS) * ((N + SR - 1) / SR);
+    const int units = ((N + SCOLS - 1) / SCOLS) * ((N + rows - 1) / rows);
     return (units + 3) / 4;
   }
   return ((N + GTX - 1) / GTX) * ((N + GTY - 1) / GTY);
 }
-template int poisson_gs_tiles<float>(int);
-template int poisson_gs_tiles<double>(int);
+template int poisson_gs_tiles<float>(int, int);
+template int poisson_gs_tiles<double>(int, int);
+
+template <> void gs_rows_options<float>(int out[3]) { out[0] = 8; out[1] = 16; out[2] = 32; }
+template <> void gs_rows_options<double>(int out[3]) { out[0] = 4; out[1] = 8; out[2] = 16; }
 
 template <typename T>
 void poisson_dense_build(T* aug, int N, double d, double c, hipStream_t s) {
@@ -594,30 +604,49 @@ void poisson_residual(const Tb* b, const Tx* x, Tr* r, int N, double d, double c
                      partials, timing_log());
 }
 
+template <typename T, int SR>
+static void rbgs_march_launch(const T* xin, const T* b, T* xout, const T* ec, double omega, int N,
+                              double d, double c, int nb, const int* active, bool reverse,
+                              c64* partials, hipStream_t s) {
+  const int bpp = poisson_gs_tiles<T>(N, SR);
+  const dim3 g(bpp * nb), blk(kThreads);
+  const R_t<T> wh = (R_t<T>)(0.5 * omega), di = (R_t<T>)(1.0 / d), cc = (R_t<T>)c;
+  const int f = reverse ? 1 : 0;
+  // null pointers are replaced by b (valid, never read) for the templated forms
+  const T* xp = xin ? xin : b;
+  const T* ep = ec ? ec : b;
+  if (xin && ec)
+    MLMC_LAUNCH((k_rbgs_march<T, true, true, SR>), g, blk, 0, s, xp, b, xout, ep, wh, N, di, cc,
+                f, nb, active, partials, timing_log());
+  else if (xin)
+    MLMC_LAUNCH((k_rbgs_march<T, true, false, SR>), g, blk, 0, s, xp, b, xout, ep, wh, N, di, cc,
+                f, nb, active, partials, timing_log());
+  else if (ec)
+    MLMC_LAUNCH((k_rbgs_march<T, false, true, SR>), g, blk, 0, s, xp, b, xout, ep, wh, N, di, cc,
+                f, nb, active, partials, timing_log());
+  else
+    MLMC_LAUNCH((k_rbgs_march<T, false, false, SR>), g, blk, 0, s, xp, b, xout, ep, wh, N, di,
+                cc, f, nb, active, partials, timing_log());
+}
+
 template <typename T>
 void poisson_rbgs_fused(const T* xin, const T* b, T* xout, const T* ec, double omega, int N,
                         double d, double c, int nb, const int* active, bool reverse,
-                        c64* partials, hipStream_t s) {
+                        c64* partials, int rows, hipStream_t s) {
   if (N >= 64) {
-    const int bpp = poisson_gs_tiles<T>(N);
-    const dim3 g(bpp * nb), blk(kThreads);
-    const R_t<T> wh = (R_t<T>)(0.5 * omega), di = (R_t<T>)(1.0 / d), cc = (R_t<T>)c;
-    const int f = reverse ? 1 : 0;
-    // null pointers are replaced by b (valid, never read) for the templated forms
-    const T* xp = xin ? xin : b;
-    const T* ep = ec ? ec : b;
-    if (xin && ec)
-      MLMC_LAUNCH((k_rbgs_march<T, true, true>), g, blk, 0, s, xp, b, xout, ep, wh, N, di,
-                         cc, f, nb, active, partials, timing_log());
-    else if (xin)
-      MLMC_LAUNCH((k_rbgs_march<T, true, false>), g, blk, 0, s, xp, b, xout, ep, wh, N,
-                         di, cc, f, nb, active, partials, timing_log());
-    else if (ec)
-      MLMC_LAUNCH((k_rbgs_march<T, false, true>), g, blk, 0, s, xp, b, xout, ep, wh, N,
-                         di, cc, f, nb, active, partials, timing_log());
+    int opts[3];
+    gs_rows_options<T>(opts);
+    if (rows == opts[0])
+      rbgs_march_launch<T, (sizeof(T) == 4 ? 8 : 4)>(xin, b, xout, ec, omega, N, d, c, nb, active,
+                                                     reverse, partials, s);
+    else if (rows == opts[1])
+      rbgs_march_launch<T, (sizeof(T) == 4 ? 16 : 8)>(xin, b, xout, ec, omega, N, d, c, nb,
+                                                      active, reverse, partials, s);
+    else if (rows == opts[2])
+      rbgs_march_launch<T, (sizeof(T) == 4 ? 32 : 16)>(xin, b, xout, ec, omega, N, d, c, nb,
+                                                       active, reverse, partials, s);
     else
-      MLMC_LAUNCH((k_rbgs_march<T, false, false>), g, blk, 0, s, xp, b, xout, ep, wh, N,
-                         di, cc, f, nb, active, partials, timing_log());
+      throw Error(MLMC_EINVAL, "unsupported rows per Gauss-Seidel segment");
   } else {
     const int nbx = (N + GTX - 1) / GTX, nby = (N + GTY - 1) / GTY;
     MLMC_LAUNCH(k_rbgs_tile<T>, dim3(nbx * nby * nb), dim3(kThreads), 0, s, xin, b,
@@ -653,7 +682,7 @@ void agg2d_prolong(const T* ec, T* x, int N, double omega, double beta, int nb,
   template void poisson_update_apply<T>(const T*, const T*, const c64*, T*, T*, int, double, \
                                         double, int, const int*, c64*, hipStream_t);       \
   template void poisson_rbgs_fused<T>(const T*, const T*, T*, const T*, double, int,       \
-                                      double, double, int, const int*, bool, c64*,         \
+                                      double, double, int, const int*, bool, c64*, int,    \
                                       hipStream_t);                                        \
   template void poisson_residual_restrict<T>(const T*, const T*, T*, int, double, double,  \
                                              int, const int*, hipStream_t);                \

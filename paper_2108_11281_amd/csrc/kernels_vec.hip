@@ -783,6 +783,30 @@ template <typename T>
 void dense_transpose(const T* in, T* out, int n, hipStream_t s) {
   hipLaunchKernelGGL(k_transpose<T>, dim3((n + 255) / 256, n), dim3(256), 0, s, in, out, n);
 }
+// real representation of a complex matrix for the real MFMA product: with
+// A_ij = At[j][i] (complex, transposed), M (2n x 2n) acts on interleaved
+// (re, im) vectors -- M[2i+a][2j+c] = Re A_ij if a == c, -Im A_ij for (0, 1),
+// Im A_ij for (1, 0) -- and is written transposed: Mt[j'][i'] = M[i'][j']
+template <typename T, typename R>
+__global__ void k_complex_to_real(const T* __restrict__ At, R* __restrict__ Mt, int n) {
+  const int n2 = 2 * n;
+  const int ip = blockIdx.x * blockDim.x + threadIdx.x;  // i'
+  const int jp = blockIdx.y;                             // j'
+  if (ip >= n2) return;
+  const int i = ip >> 1, a = ip & 1, j = jp >> 1, c = jp & 1;
+  const T v = At[(int64_t)j * n + i];
+  const R m = (a == c) ? v.re : (a == 0 ? -v.im : v.im);
+  Mt[(int64_t)jp * n2 + ip] = m;
+}
+
+template <typename T, typename R>
+void dense_complex_to_real(const T* At, R* Mt, int n, hipStream_t s) {
+  hipLaunchKernelGGL((k_complex_to_real<T, R>), dim3((2 * n + 255) / 256, 2 * n), dim3(256), 0,
+                     s, At, Mt, n);
+}
+template void dense_complex_to_real<c32, float>(const c32*, float*, int, hipStream_t);
+template void dense_complex_to_real<c64, double>(const c64*, double*, int, hipStream_t);
+
 template void dense_transpose<float>(const float*, float*, int, hipStream_t);
 template void dense_transpose<double>(const double*, double*, int, hipStream_t);
 template void dense_transpose<c32>(const c32*, c32*, int, hipStream_t);

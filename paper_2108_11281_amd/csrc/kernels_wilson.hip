@@ -200,8 +200,9 @@ __global__ __launch_bounds__(kThreads) void k_bsr_gs(const T* __restrict__ b, T*
                                                      const T* __restrict__ B,
                                                      const T* __restrict__ Dinv, int Nc,
                                                      int colour, int zero_nbrs,
-                                                     const int* active) {
+                                                     const int* active, int* tlog) {
   const int k = blockIdx.y;
+  if (tlog && blockIdx.x == 0 && threadIdx.x == 0) tlog[k] = active ? active[k] : 1;
   if (active && !active[k]) return;
   const int ns = Nc * Nc;
   const int S = blockIdx.x * kThreads + threadIdx.x;
@@ -575,10 +576,10 @@ void bsr_rbgs(const T* b, T* x, const T* B, const T* Dinv, int Nc, int dof, int 
               const int* active, bool zero_init, bool reverse, hipStream_t s) {
   const dim3 g = grid_sites((int64_t)Nc * Nc, nb);
   const int first = reverse ? 1 : 0;
-  BSR_DISPATCH(dof, hipLaunchKernelGGL((k_bsr_gs<D, T>), g, dim3(kThreads), 0, s, b, x, B, Dinv,
-                                        Nc, first, zero_init ? 1 : 0, active));
-  BSR_DISPATCH(dof, hipLaunchKernelGGL((k_bsr_gs<D, T>), g, dim3(kThreads), 0, s, b, x, B, Dinv,
-                                        Nc, 1 - first, 0, active));
+  BSR_DISPATCH(dof, MLMC_LAUNCH((k_bsr_gs<D, T>), g, dim3(kThreads), 0, s, b, x, B, Dinv, Nc,
+                                 first, zero_init ? 1 : 0, active, timing_log()));
+  BSR_DISPATCH(dof, MLMC_LAUNCH((k_bsr_gs<D, T>), g, dim3(kThreads), 0, s, b, x, B, Dinv, Nc,
+                                 1 - first, 0, active, (int*)nullptr));
 }
 
 template <typename T>
