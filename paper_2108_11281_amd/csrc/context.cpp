@@ -361,10 +361,10 @@ void Context::tune_varcoef() {
         MLMC_HIP(hipEventRecord(a, s_));
         if (fp32)
           varcoef_rbgs<float>(w32_.r, w32_.x, L.kl32, L.dg32, L.side, nb_, cols, nullptr,
-                              rep == 0, false, s_);
+                              rep == 0, false, nullptr, 0.0, s_);
         else
           varcoef_rbgs<double>(w64_.r, w64_.x, L.kl64, L.dg64, L.side, nb_, cols, nullptr,
-                               rep == 0, false, s_);
+                               rep == 0, false, nullptr, 0.0, s_);
         MLMC_HIP(hipEventRecord(b, s_));
         MLMC_HIP(hipEventSynchronize(b));
         float t = 0.f;
@@ -509,7 +509,7 @@ void Context::vcycle_vc(int l, const T* b, T* x, int nb, const int* act, c64* rz
     const int pre = opt_.nu_pre, post = opt_.nu_post;
     for (int i = 0; i < pre; ++i)
       timed<T>(kTimGs, en * ((i == 0 ? 2.0 : 3.0) + 4.0 / (double)nb), act, nb, [&] {
-        varcoef_rbgs<T>(b, x, kf, dg, L.side, nb, L.cols, act, i == 0, false, s_);
+        varcoef_rbgs<T>(b, x, kf, dg, L.side, nb, L.cols, act, i == 0, false, nullptr, 0.0, s_);
       });
     T* bc = w.vb[l];
     T* ec = w.vx[l];
@@ -519,12 +519,19 @@ void Context::vcycle_vc(int l, const T* b, T* x, int nb, const int* act, c64* rz
       timed<T>(kTimResRestrict, en * (2.0 + 0.125 + 4.0 / (double)nb), act, nb,
                [&] { op_res_restrict<T>(l, b, x, bc, nb, act); });
     vcycle_vc<T>(l + 1, bc, ec, nb, act, nullptr);
-    timed<T>(kTimProlong, en * (2.0 + 0.125), act, nb,
-             [&] { varcoef_prolong<T>(ec, x, L.side, omega_, pre == 0 ? 0.0 : 1.0, nb, act, s_); });
-    for (int i = 0; i < post; ++i)
-      timed<T>(kTimGs, en * (3.0 + 4.0 / (double)nb), act, nb, [&] {
-        varcoef_rbgs<T>(b, x, kf, dg, L.side, nb, L.cols, act, false, true, s_);
+    if (post == 0 || pre == 0) {
+      timed<T>(kTimProlong, en * (2.0 + 0.125), act, nb, [&] {
+        varcoef_prolong<T>(ec, x, L.side, omega_, pre == 0 ? 0.0 : 1.0, nb, act, s_);
       });
+    }
+    for (int i = 0; i < post; ++i) {
+      // the first post-sweep reads the corrected iterate x + omega P ec on the fly
+      const bool fold = (i == 0 && pre > 0);
+      timed<T>(kTimGs, en * (3.0 + (fold ? 0.125 : 0.0) + 4.0 / (double)nb), act, nb, [&] {
+        varcoef_rbgs<T>(b, x, kf, dg, L.side, nb, L.cols, act, false, true, fold ? ec : nullptr,
+                        omega_, s_);
+      });
+    }
   }
   if (rz_partials) vec_dot_partials<T>(b, x, n, nb, act, rz_partials, s_);
 }

@@ -194,11 +194,13 @@ void varcoef_residual(const Tb* b, const T* x, Tr* r, const typename Traits<T>::
                       const typename Traits<T>::real* dg, int N, int nb, int cols,
                       const int* active, c64* partials, hipStream_t s);
 // one in-place red-black Gauss-Seidel sweep (reverse: black first); zero_init:
-// x = 0 on entry (not read)
+// x = 0 on entry (not read); ec (nullable): x + omega P ec is swept instead of
+// x (the coarse-grid correction folded into the sweep; the result is written
+// to x)
 template <typename T>
 void varcoef_rbgs(const T* b, T* x, const typename Traits<T>::real* kl,
                   const typename Traits<T>::real* dg, int N, int nb, int cols, const int* active,
-                  bool zero_init, bool reverse, hipStream_t s);
+                  bool zero_init, bool reverse, const T* ec, double omega, hipStream_t s);
 // xc = R (b - A x) when residual, else xc = R x; R the orthonormal 2x2x2
 // aggregation (entries 1/sqrt(8))
 template <typename T>

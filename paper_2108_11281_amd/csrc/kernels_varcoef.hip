@@ -128,34 +128,62 @@ __global__ __launch_bounds__(kThreads) void k_vc_residual(const Tb* __restrict__
 }
 
 // one colour of a red-black Gauss-Seidel sweep, in place; a thread per cell of
-// that colour (cell x = 2j + ((colour + y + z) & 1) of row (y, z))
+// that colour (cell x = 2j + ((colour + y + z) & 1) of row (y, z)).  With ec
+// (first colour after the coarse solve), the neighbours are read as
+// x + wscaled * ec(aggregate): the prolongation and correction of the other
+// colour's cells folded into the sweep (this colour's own cells are
+// overwritten, so their correction is never needed).
 template <typename T, int COLS>
 __global__ __launch_bounds__(kThreads) void k_vc_gs(const T* __restrict__ b, T* __restrict__ x,
                                                     const R_t<T>* __restrict__ kl,
                                                     const R_t<T>* __restrict__ dg, int N,
                                                     int colour, int zero_nbrs, int nb,
-                                                    const int* active, int* tlog) {
+                                                    const int* active, const T* __restrict__ ec,
+                                                    R_t<T> wscaled, int* tlog) {
   const int col0 = blockIdx.y * COLS;
   if (tlog && blockIdx.x == 0 && threadIdx.x < COLS && col0 + (int)threadIdx.x < nb)
     tlog[col0 + threadIdx.x] = active ? active[col0 + threadIdx.x] : 1;
   const int half = N >> 1;
   const int64_t n = (int64_t)N * N * N;
-  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (t >= n / 2) return;
-  const int64_t row = t / half;
-  const int j = (int)(t - row * half);
-  const int y = (int)(row % N), z = (int)(row / N);
+  // 32-bit index arithmetic (N^3 < 2^31 for every supported side)
+  const int t = blockIdx.x * kThreads + threadIdx.x;
+  if (t >= (int)(n / 2)) return;
+  const int row = t / half;
+  const int j = t - row * half;
+  const int z = row / N, y = row - z * N;
   const int xx = 2 * j + ((colour + y + z) & 1);
-  const int64_t i = row * N + xx;
+  const int64_t i = (int64_t)row * N + xx;
   Couplings<R_t<T>> c = couplings(kl, dg, i, N);
   const R_t<T> inv_d = (R_t<T>)1 / c.d;
+  // aggregates of the six neighbours (coordinates clamped; their coupling is
+  // zero wherever the clamp acts)
+  const int Nc = N >> 1;
+  auto agg = [&](int ax, int ay, int az) { return ((az >> 1) * Nc + (ay >> 1)) * Nc + (ax >> 1); };
+  int ga[6] = {0, 0, 0, 0, 0, 0};
+  if (ec) {
+    ga[0] = agg(xx > 0 ? xx - 1 : 0, y, z);
+    ga[1] = agg(xx + 1 < N ? xx + 1 : N - 1, y, z);
+    ga[2] = agg(xx, y > 0 ? y - 1 : 0, z);
+    ga[3] = agg(xx, y + 1 < N ? y + 1 : N - 1, z);
+    ga[4] = agg(xx, y, z > 0 ? z - 1 : 0);
+    ga[5] = agg(xx, y, z + 1 < N ? z + 1 : N - 1);
+  }
 #pragma unroll
   for (int q = 0; q < COLS; ++q) {
     const int col = col0 + q;
     if (!col_on(active, col, nb)) continue;
     const int64_t off = (int64_t)col * n;
     T v = b[off + i];
-    if (!zero_nbrs) v += nbr_sum(x + off, c);
+    if (ec) {
+      const T* u = x + off;
+      const T* e = ec + (int64_t)col * Nc * Nc * Nc;
+      v += term(c.cx0, u[c.im1] + wscaled * e[ga[0]]) + term(c.cx1, u[c.ip1] + wscaled * e[ga[1]]) +
+           term(c.cy0, u[c.imN] + wscaled * e[ga[2]]) + term(c.cy1, u[c.ipN] + wscaled * e[ga[3]]) +
+           term(c.cz0, u[c.imNN] + wscaled * e[ga[4]]) +
+           term(c.cz1, u[c.ipNN] + wscaled * e[ga[5]]);
+    } else if (!zero_nbrs) {
+      v += nbr_sum(x + off, c);
+    }
     x[off + i] = inv_d * v;
   }
 }
@@ -174,18 +202,18 @@ __global__ __launch_bounds__(kThreads) void k_vc_restrict(const T* __restrict__ 
     tlog[col0 + threadIdx.x] = active ? active[col0 + threadIdx.x] : 1;
   const int Nc = N / 2;
   const int64_t nc = (int64_t)Nc * Nc * Nc, n = (int64_t)N * N * N;
-  const int64_t I = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (I >= nc) return;
-  const int64_t Z = I / ((int64_t)Nc * Nc);
-  const int64_t rem = I - Z * Nc * Nc;
-  const int Y = (int)(rem / Nc), X = (int)(rem - (int64_t)Y * Nc);
+  const int I = blockIdx.x * kThreads + threadIdx.x;
+  if (I >= (int)nc) return;
+  const int Z = I / (Nc * Nc);
+  const int rem = I - Z * Nc * Nc;
+  const int Y = rem / Nc, X = rem - Y * Nc;
   T acc[COLS];
 #pragma unroll
   for (int q = 0; q < COLS; ++q) acc[q] = zero_of(T());
   for (int dz = 0; dz < 2; ++dz)
     for (int dy = 0; dy < 2; ++dy)
       for (int dx = 0; dx < 2; ++dx) {
-        const int64_t i = ((2 * Z + dz) * N + (2 * Y + dy)) * (int64_t)N + (2 * X + dx);
+        const int64_t i = ((int64_t)(2 * Z + dz) * N + (2 * Y + dy)) * N + (2 * X + dx);
         if (residual) {
           Couplings<R_t<T>> c = couplings(kl, dg, i, N);
 #pragma unroll
@@ -222,11 +250,11 @@ __global__ __launch_bounds__(kThreads) void k_vc_prolong(const T* __restrict__ e
   if (active && !active[col]) return;
   const int Nc = N / 2;
   const int64_t n = (int64_t)N * N * N;
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (i >= n) return;
-  const int64_t z = i / ((int64_t)N * N);
-  const int64_t rem = i - z * N * N;
-  const int y = (int)(rem / N), xx = (int)(rem - (int64_t)y * N);
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= (int)n) return;
+  const int z = i / (N * N);
+  const int rem = i - z * N * N;
+  const int y = rem / N, xx = rem - y * N;
   const T e = ec[(int64_t)col * Nc * Nc * Nc + ((z >> 1) * Nc + (y >> 1)) * Nc + (xx >> 1)];
   T* xk = x + (int64_t)col * n;
   xk[i] = (beta == (R_t<T>)0) ? wscaled * e : beta * xk[i] + wscaled * e;
@@ -367,15 +395,17 @@ void varcoef_residual(const Tb* b, const T* x, Tr* r, const typename Traits<T>::
 template <typename T>
 void varcoef_rbgs(const T* b, T* x, const typename Traits<T>::real* kl,
                   const typename Traits<T>::real* dg, int N, int nb, int cols, const int* active,
-                  bool zero_init, bool reverse, hipStream_t s) {
+                  bool zero_init, bool reverse, const T* ec, double omega, hipStream_t s) {
+  using R = typename Traits<T>::real;
   const int64_t half = (int64_t)N * N * N / 2;
   const dim3 g((unsigned)((half + kThreads - 1) / kThreads), (unsigned)((nb + cols - 1) / cols));
   const int first = reverse ? 1 : 0;
+  const R ws = (R)(omega * 0.35355339059327373);  // omega / sqrt(8)
   VC_COLS_DISPATCH(cols, {
     MLMC_LAUNCH((k_vc_gs<T, C>), g, dim3(kThreads), 0, s, b, x, kl, dg, N, first,
-                zero_init ? 1 : 0, nb, active, timing_log());
+                zero_init ? 1 : 0, nb, active, ec, ws, timing_log());
     MLMC_LAUNCH((k_vc_gs<T, C>), g, dim3(kThreads), 0, s, b, x, kl, dg, N, 1 - first, 0, nb,
-                active, (int*)nullptr);
+                active, (const T*)nullptr, (R)0, (int*)nullptr);
   });
 }
 
@@ -425,7 +455,7 @@ void varcoef_dense(const double* k, const double* diag, int N, double* aug, hipS
 
 #define VC_INST(T)                                                                          \
   template void varcoef_rbgs<T>(const T*, T*, const T*, const T*, int, int, int, const int*,  \
-                                bool, bool, hipStream_t);                                    \
+                                bool, bool, const T*, double, hipStream_t);                  \
   template void varcoef_restrict<T>(const T*, const T*, T*, const T*, const T*, int, bool,    \
                                     int, int, const int*, hipStream_t);                      \
   template void varcoef_prolong<T>(const T*, T*, int, double, double, int, const int*,        \
