@@ -258,15 +258,15 @@ void Context::tune_poisson() {
     Work<T>& w = work<T>();
     int opts[3];
     gs_rows_options<T>(opts);
-    // the default segment length is kept unless another is at least 5% faster,
+    // the default segment length is kept unless another is at least 10% faster,
     // so that the choice (which sets the grouping of the sweep's fused partial
     // sums, hence the last bits of the FP32 recursion) does not flap between runs
     const int dflt = L.gs_rows[slot];
     float best = 1e30f, t_dflt = 1e30f;
     int best_rows = dflt;
     for (int rows : opts) {
-      float ms = 0.f;
-      for (int rep = 0; rep < 3; ++rep) {
+      float ms = 1e30f;  // best of 5 after a warm-up run (robust to noise)
+      for (int rep = 0; rep < 6; ++rep) {
         MLMC_HIP(hipEventRecord(a, s_));
         poisson_rbgs_fused<T>(w.z, w.r, w.q, w.vb[l], omega_, L.side, L.d, L.c, nb_, nullptr,
                               true, nullptr, rows, s_);
@@ -274,7 +274,7 @@ void Context::tune_poisson() {
         MLMC_HIP(hipEventSynchronize(b));
         float t = 0.f;
         MLMC_HIP(hipEventElapsedTime(&t, a, b));
-        if (rep > 0) ms += t;  // the first run warms caches and code
+        if (rep > 0) ms = std::min(ms, t);
       }
       if (rows == dflt) t_dflt = ms;
       if (ms < best) {
@@ -282,7 +282,7 @@ void Context::tune_poisson() {
         best_rows = rows;
       }
     }
-    L.gs_rows[slot] = best < 0.95f * t_dflt ? best_rows : dflt;
+    L.gs_rows[slot] = best < 0.90f * t_dflt ? best_rows : dflt;
   };
   for (int l = 1; l < Ls_; ++l) {
     Level& L = lv_[l - 1];
