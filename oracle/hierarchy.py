@@ -85,6 +85,40 @@ def site_coloring(N):
     return (x + y) % 2
 
 
+def site_coloring_3d(N):
+    """Red (0) / black (1) colour of each cell of an N^3 grid: (x+y+z) mod 2,
+    cell index (z*N + y)*N + x."""
+    z, rest = np.divmod(np.arange(N ** 3), N * N)
+    y, x = np.divmod(rest, N)
+    return (x + y + z) % 2
+
+
+def coloured_gs_sweep(A, v, colour, b, order=(0, 1)):
+    """One block Gauss-Seidel sweep over two colour classes, in `order`.
+
+    For each class m in turn the unknowns of m are solved exactly with the
+    others held: v_m <- A_mm^{-1} (b_m - A_{m,rest} v_rest).  With a red-black
+    colouring of a nearest-neighbour operator A_mm is (block) diagonal.
+    """
+    A = A.tocsr()
+    for c in order:
+        m = colour == c
+        Amm = A[m][:, m]
+        rhs = b[m] - A[m][:, ~m] @ v[~m]
+        v = v.copy()
+        v[m] = sp.linalg.spsolve(Amm.tocsc(), rhs)
+    return v
+
+
+def rbgs_sweeps(A, b, x, colour, sweeps, reverse=False):
+    """`sweeps` red-black sweeps from x; reverse: colour 1 first (the
+    post-smoothing order that keeps a V-cycle symmetric)."""
+    order = (1, 0) if reverse else (0, 1)
+    for _ in range(sweeps):
+        x = coloured_gs_sweep(A, x, colour, b, order)
+    return x
+
+
 def block_rbgs_sweep(A, v, N, dof, b=None):
     """One red-black block Gauss-Seidel sweep for A v = b (b = 0 by default).
 
@@ -94,15 +128,7 @@ def block_rbgs_sweep(A, v, N, dof, b=None):
     n = A.shape[0]
     if b is None:
         b = np.zeros(n, dtype=A.dtype)
-    colour = np.repeat(site_coloring(N), dof)
-    A = A.tocsr()
-    for c in (0, 1):
-        m = colour == c
-        Amm = A[m][:, m]       # block diagonal (a site has no same-colour neighbour)
-        rhs = b[m] - A[m][:, ~m] @ v[~m]
-        v = v.copy()
-        v[m] = sp.linalg.spsolve(Amm.tocsc(), rhs)
-    return v
+    return coloured_gs_sweep(A, v, np.repeat(site_coloring(N), dof), b)
 
 
 def orthonormal_basis(V):

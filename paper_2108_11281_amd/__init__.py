@@ -268,6 +268,15 @@ class TraceEstimator:
                                      self._ptr(y)))
         return y
 
+    def smooth(self, level, b, x, sweeps, reverse=False):
+        """`sweeps` red-black Gauss-Seidel sweeps of A_level x = b, in the working
+        precision with the V-cycle's own kernels; returns the new x (x is not
+        changed).  reverse: second colour first, as in post-smoothing."""
+        y = x.clone()
+        self._c(self._lib.mlmc_smooth(self._ctx, int(level), int(b.shape[0]), int(sweeps),
+                                      1 if reverse else 0, self._ptr(b), self._ptr(y)))
+        return y
+
     def restrict(self, level, x):
         y = self._vec(level + 1, x.shape[0], x.device)
         self._c(self._lib.mlmc_restrict(self._ctx, int(level), int(x.shape[0]), self._ptr(x),

@@ -108,6 +108,8 @@ SIGNATURES = {
     "mlmc_level_size": (ctypes.c_int, [_P, ctypes.c_int, _I64]),
     "mlmc_solve": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P, _D]),
     "mlmc_apply": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P]),
+    "mlmc_smooth": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                   _P, _P]),
     "mlmc_restrict": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P]),
     "mlmc_prolong": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P]),
     "mlmc_probes": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_uint64, ctypes.c_int,

@@ -245,8 +245,9 @@ void Context::build_poisson() {
 }
 
 // Autotuner of the fused Poisson sweep: per smoothed level with N >= 64, time
-// the heaviest form (input iterate and folded coarse correction) over all nb
-// columns for each compiled segment length and keep the fastest.  The swept
+// the heaviest form (input iterate, folded coarse correction, as many fused
+// sweeps as the post-smoother's first pass) over all nb columns for each
+// compiled segment length and keep the fastest.  The swept
 // values do not depend on the choice; the fused r^T z partial sums are grouped
 // by segment, so the FP32 recursion can differ in its last bits (the FP64
 // judged solution still meets solve_tol).  Runs once at setup on the library's
@@ -258,6 +259,8 @@ void Context::tune_poisson() {
     Work<T>& w = work<T>();
     int opts[3];
     gs_rows_options<T>(opts);
+    // the pass the post-smoother starts with (the heaviest form)
+    const int sw = std::min(sweeps_per_pass(l), std::max(1, opt_.nu_post));
     // the default segment length is kept unless another is at least 10% faster,
     // so that the choice (which sets the grouping of the sweep's fused partial
     // sums, hence the last bits of the FP32 recursion) does not flap between runs
@@ -269,7 +272,7 @@ void Context::tune_poisson() {
       for (int rep = 0; rep < 6; ++rep) {
         MLMC_HIP(hipEventRecord(a, s_));
         poisson_rbgs_fused<T>(w.z, w.r, w.q, w.vb[l], omega_, L.side, L.d, L.c, nb_, nullptr,
-                              true, nullptr, rows, s_);
+                              true, nullptr, rows, sw, s_);
         MLMC_HIP(hipEventRecord(b, s_));
         MLMC_HIP(hipEventSynchronize(b));
         float t = 0.f;
@@ -561,16 +564,20 @@ void Context::vcycle(int l, const T* b, T* x, int nb, const int* act, c64* rz_pa
   const Level& L = lv_[l - 1];
   T* tmp = w.vt[l - 1];
   const int pre = opt_.nu_pre, post = opt_.nu_post;
-  // pre-smoothing: outputs alternate tmp, x, tmp, ...
+  const int per = sweeps_per_pass(l);
+  const int rows = gs_rows<T>(l);
+  // pre-smoothing in passes of up to `per` sweeps: outputs alternate tmp, x, tmp, ...
   const T* u = nullptr;  // current iterate (nullptr = 0)
-  for (int i = 0; i < pre; ++i) {
-    T* out = (i % 2 == 0) ? tmp : x;
+  for (int i = 0, pass = 0; i < pre; ++pass) {
+    const int sw = std::min(per, pre - i);
+    T* out = (pass % 2 == 0) ? tmp : x;
     const T* in = u;
     timed<T>(kTimGs, en * (2.0 + (in ? 1.0 : 0.0)), act, nb, [&] {
       poisson_rbgs_fused<T>(in, b, out, nullptr, 0.0, L.side, L.d, L.c, nb, act, false, nullptr,
-                            gs_rows<T>(l), s_);
+                            rows, sw, s_);
     });
     u = out;
+    i += sw;
   }
   T* bc = w.vb[l];
   T* ec = w.vx[l];
@@ -590,19 +597,22 @@ void Context::vcycle(int l, const T* b, T* x, int nb, const int* act, c64* rz_pa
     if (rz_partials) vec_dot_partials<T>(b, x, n, nb, act, rz_partials, s_);
     return;
   }
-  // post-smoothing: the last sweep must land in x
-  for (int i = 0; i < post; ++i) {
-    const int left = post - 1 - i;
+  // post-smoothing in passes of up to `per` sweeps; the last pass must land in x
+  const int passes = (post + per - 1) / per;
+  for (int i = 0, pass = 0; i < post; ++pass) {
+    const int sw = std::min(per, post - i);
+    const int left = passes - 1 - pass;
     T* out = (left % 2 == 0) ? x : tmp;
     if (out == u) out = (out == x) ? tmp : x;  // never sweep in place
     const T* in = u;
-    const T* corr = (i == 0) ? ec : nullptr;
-    const bool last = (i == post - 1);
+    const T* corr = (pass == 0) ? ec : nullptr;
+    const bool last = (pass == passes - 1);
     timed<T>(kTimGs, en * (2.0 + (in ? 1.0 : 0.0) + (corr ? 0.25 : 0.0)), act, nb, [&] {
       poisson_rbgs_fused<T>(in, b, out, corr, omega_, L.side, L.d, L.c, nb, act, true,
-                            last ? rz_partials : nullptr, gs_rows<T>(l), s_);
+                            last ? rz_partials : nullptr, rows, sw, s_);
     });
     u = out;
+    i += sw;
   }
   if (u != x) {
     vec_copy<T>(u, x, n, nb, act, s_);
@@ -619,17 +629,28 @@ int Context::vcycle_partials(int l, bool* fused) const {
   *fused = false;
   if (varcoef_ || l == Ls_ || opt_.nu_post == 0) return reduce_blocks(n);
   enum { kNull, kTmp, kX };
+  const int per = sweeps_per_pass(l);
   int u = kNull;
-  for (int i = 0; i < opt_.nu_pre; ++i) u = (i % 2 == 0) ? kTmp : kX;
-  for (int i = 0; i < opt_.nu_post; ++i) {
-    const int left = opt_.nu_post - 1 - i;
+  for (int i = 0, pass = 0; i < opt_.nu_pre; ++pass) {
+    u = (pass % 2 == 0) ? kTmp : kX;
+    i += std::min(per, opt_.nu_pre - i);
+  }
+  const int passes = (opt_.nu_post + per - 1) / per;
+  int last_sw = 1;
+  for (int i = 0, pass = 0; i < opt_.nu_post; ++pass) {
+    const int left = passes - 1 - pass;
     int out = (left % 2 == 0) ? kX : kTmp;
     if (out == u) out = (out == kX) ? kTmp : kX;
     u = out;
+    last_sw = std::min(per, opt_.nu_post - i);
+    i += last_sw;
   }
   if (u != kX) return reduce_blocks(n);
   *fused = true;
-  return poisson_gs_tiles<T>(lv_[l - 1].side, gs_rows<T>(l));
+  const int tiles = poisson_gs_tiles<T>(lv_[l - 1].side, gs_rows<T>(l), last_sw);
+  MLMC_REQUIRE((int64_t)tiles * nb_ <= partials_cap_, MLMC_EINVAL,
+               "fused sweep partial sums exceed the partials buffer");
+  return tiles;
 }
 
 // ---------------------------------------------------------------------------
@@ -1178,6 +1199,64 @@ void Context::apply_fp64(int level, int nrhs, const double* x, double* y) {
     op_apply<double>(level, x, y, nrhs, nullptr, nullptr);
   MLMC_HIP(hipStreamSynchronize(s_));
   MLMC_HIP(hipGetLastError());
+}
+
+// x <- `sweeps` red-black Gauss-Seidel sweeps of A_level x = b in the working
+// precision, with the V-cycle's own kernels (passes of fused sweeps on the 2D
+// Poisson levels); reverse: second colour first, as in post-smoothing
+void Context::smooth_fp64(int level, int nrhs, int sweeps, bool reverse, const double* b,
+                          double* x) {
+  MLMC_REQUIRE(level >= 1 && level < Ls_, MLMC_EINVAL, "level out of range (no smoother on L_s)");
+  MLMC_REQUIRE(nrhs >= 1 && nrhs <= nb_, MLMC_EINVAL, "nrhs must be in [1, nb]");
+  MLMC_REQUIRE(sweeps >= 0, MLMC_EINVAL, "sweeps must be >= 0");
+  const int64_t n = lv_[level - 1].n;
+  const int64_t m = n * nrhs * (complex_ ? 2 : 1);
+  auto run = [&](auto tag) {
+    using T = decltype(tag);
+    T* bt = dalloc_n<T>(m);
+    T* xa = dalloc_n<T>(m);
+    T* xb = dalloc_n<T>(m);
+    if constexpr (std::is_same<T, double>::value) {
+      vec_copy<double>(b, bt, m, 1, nullptr, s_);
+      vec_copy<double>(x, xa, m, 1, nullptr, s_);
+    } else {
+      vec_convert<T, double>(b, bt, m, 1, nullptr, s_);
+      vec_convert<T, double>(x, xa, m, 1, nullptr, s_);
+    }
+    const Level& L = lv_[level - 1];
+    if (complex_) {
+      using C = typename std::conditional<sizeof(T) == 4, c32, c64>::type;
+      for (int i = 0; i < sweeps; ++i)
+        cop_smooth<C>(level, reinterpret_cast<const C*>(bt), reinterpret_cast<C*>(xa), nrhs,
+                      nullptr, false, reverse);
+    } else if (varcoef_) {
+      for (int i = 0; i < sweeps; ++i)
+        varcoef_rbgs<T>(bt, xa, vc_faces<T>(level), vc_diag<T>(level), L.side, nrhs, L.cols,
+                        nullptr, false, reverse, nullptr, 0.0, s_);
+    } else {
+      const int per = sweeps_per_pass(level);
+      for (int i = 0; i < sweeps;) {
+        const int sw = std::min(per, sweeps - i);
+        poisson_rbgs_fused<T>(xa, bt, xb, nullptr, 0.0, L.side, L.d, L.c, nrhs, nullptr, reverse,
+                              nullptr, gs_rows<T>(level), sw, s_);
+        std::swap(xa, xb);
+        i += sw;
+      }
+    }
+    if constexpr (std::is_same<T, double>::value)
+      vec_copy<double>(xa, x, m, 1, nullptr, s_);
+    else
+      vec_convert<double, T>(xa, x, m, 1, nullptr, s_);
+    MLMC_HIP(hipStreamSynchronize(s_));
+    MLMC_HIP(hipGetLastError());
+    dfree(bt);
+    dfree(xa);
+    dfree(xb);
+  };
+  if (opt_.precision == MLMC_FP64)
+    run(double());
+  else
+    run(float());
 }
 
 void Context::restrict_fp64(int level, int nrhs, const double* x, double* xc) {

@@ -85,6 +85,7 @@ class Context {
   void solve_fp64(int level, int nrhs, const double* b, double* y, double* relres,
                   bool throw_on_noconv);
   void apply_fp64(int level, int nrhs, const double* x, double* y);
+  void smooth_fp64(int level, int nrhs, int sweeps, bool reverse, const double* b, double* x);
   void restrict_fp64(int level, int nrhs, const double* x, double* xc);
   void prolong_fp64(int level, int nrhs, const double* xc, double* x);
   void probes_fp64(int level, uint64_t seed, int stream, int64_t first, int nrhs,
@@ -132,6 +133,8 @@ class Context {
   void build_varcoef(const double* k);
   void tune_varcoef();
   void tune_poisson();
+  // red-black sweeps fused into one pass of the Poisson smoother on level l
+  int sweeps_per_pass(int l) const { return lv_[l - 1].side >= 64 ? 2 : 1; }
   template <typename T> int gs_rows(int l) const {
     return lv_[l - 1].gs_rows[sizeof(typename Traits<T>::real) == 8 ? 1 : 0];
   }

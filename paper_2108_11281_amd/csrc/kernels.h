@@ -139,8 +139,9 @@ void dense_transpose(const T* in, T* out, int n, hipStream_t s);
 // ----- 2D Poisson stencil: A = d I - c (grid neighbours), N x N Dirichlet -----
 // partial-sum counts per column of the tiled kernels
 int poisson_march_tiles(int N);   // apply / residual
+// fused Gauss-Seidel pass of `sweeps` (1 or 2) sweeps, `rows` per segment
 template <typename T>
-int poisson_gs_tiles(int N, int rows);  // fused Gauss-Seidel sweep, `rows` per segment
+int poisson_gs_tiles(int N, int rows, int sweeps);
 // the three segment lengths the sweep is compiled for (ascending)
 template <typename T>
 void gs_rows_options(int out[3]);
@@ -159,15 +160,17 @@ void poisson_update_apply(const T* p_old, const T* z, const c64* beta, T* p_new,
 template <typename Tb, typename Tx, typename Tr>
 void poisson_residual(const Tb* b, const Tx* x, Tr* r, int N, double d, double c,
                       int nb, const int* active, c64* partials, hipStream_t s);
-// one fused red-black Gauss-Seidel sweep: xout = S(xin + omega/2 P ec ; b),
-// red first (reverse: black first); xin == nullptr means 0, ec == nullptr no
-// correction; partials (nullable): shares of conj(b)^T xout, gs_tiles per
-// column; rows: segment length (one of gs_rows_options; a tuning choice that
-// does not change results)
+// one pass of `sweeps` (1 or 2; 2 needs N >= 64) red-black Gauss-Seidel sweeps,
+// fused: xout = S^sweeps(xin + omega/2 P ec ; b), red first (reverse: black
+// first) in every sweep; xin == nullptr means 0, ec == nullptr no correction;
+// partials (nullable): shares of conj(b)^T xout, gs_tiles per column; rows:
+// segment length (one of gs_rows_options; a tuning choice that does not change
+// the swept values).  Two sweeps in one pass equal two one-sweep passes bit for
+// bit.
 template <typename T>
 void poisson_rbgs_fused(const T* xin, const T* b, T* xout, const T* ec, double omega, int N,
                         double d, double c, int nb, const int* active, bool reverse,
-                        c64* partials, int rows, hipStream_t s);
+                        c64* partials, int rows, int sweeps, hipStream_t s);
 // rc = R (b - A x), R = P^T, P the orthonormal 2x2 aggregation (entries 1/2)
 template <typename T>
 void poisson_residual_restrict(const T* b, const T* x, T* rc, int N, double d,

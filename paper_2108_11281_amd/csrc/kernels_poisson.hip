@@ -277,6 +277,139 @@ __global__ __launch_bounds__(kThreads) void k_rbgs_march(const T* __restrict__ x
 }
 
 // ---------------------------------------------------------------------------
+// Two fused red-black sweeps (the march above blocked in time):
+//   x_out = S(S(x_in + omega/2 * P e_c ; b) ; b)
+// Each lane holds two adjacent columns (an even and an odd one), so in every
+// row exactly one of its two cells has the colour being updated: a colour stage
+// costs one update and one DPP lane shift per lane and row, and the loads are
+// 2-element vectors.  The four colour stages (first, second, first, second)
+// update the register rows in place (a colour's neighbours all have the other
+// colour).  Each stage is valid one column and one row further in than the one
+// before, so a wave owns lanes 2..61 (120 columns) and a segment of SR output
+// rows loads SR + 8 rows.  HBM traffic is that of one sweep (x_in and b in,
+// x_out out); every updated value is formed by the same operations, in the
+// same order, as in two launches of the one-sweep kernel, so the results agree
+// bit for bit.  Needs N even (every smoothed level has a coarser one).
+// ---------------------------------------------------------------------------
+constexpr int SCOLS2 = 120;  // owned columns per wave, two fused sweeps
+
+template <typename T>
+struct alignas(2 * sizeof(T)) Pair {
+  T e0, e1;
+};
+
+template <typename T, bool HX, bool HE, int SR, int F>
+__global__ __launch_bounds__(kThreads) void k_rbgs2_march(const T* __restrict__ xin,
+                                                          const T* __restrict__ b,
+                                                          T* __restrict__ xout,
+                                                          const T* __restrict__ ec, R_t<T> wh,
+                                                          int N, R_t<T> dinv, R_t<T> c, int nb,
+                                                          const int* active, c64* partials,
+                                                          int* tlog) {
+  constexpr int NR = SR + 8;
+  __shared__ double red[16];
+  const int nwx = (N + SCOLS2 - 1) / SCOLS2, nseg = (N + SR - 1) / SR;
+  const int units_per_plane = nwx * nseg;
+  const int blocks_per_plane = (units_per_plane + 3) / 4;
+  const int t = xcd_tile_index(blocks_per_plane * nb);
+  const int k = t / blocks_per_plane;
+  const int bp = t - k * blocks_per_plane;
+  if (tlog && bp == 0 && threadIdx.x == 0) tlog[k] = active ? active[k] : 1;
+  if (k >= nb || (active && !active[k])) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int unit = bp * 4 + w;                // unit = seg * nwx + wx within the plane
+  const bool unit_ok = unit < units_per_plane;
+  const int seg = unit / nwx, wx = unit - seg * nwx;
+  const int x = wx * SCOLS2 - 4 + 2 * lane;   // even column of the lane's pair
+  const int ys = seg * SR;                    // even, so row parity = parity of r below
+  const int yend = ys + SR < N ? ys + SR : N;
+  const bool col_in = unit_ok && x >= 0 && x < N;
+  const bool owned = col_in && lane >= 2 && lane <= 61;
+  const int64_t n = (int64_t)N * N;
+  const int Nc = N >> 1;
+  const Pair<T>* xc = reinterpret_cast<const Pair<T>*>(xin + (HX ? (int64_t)k * n : 0));
+  const Pair<T>* bc = reinterpret_cast<const Pair<T>*>(b + (int64_t)k * n);
+  const T* ecc = ec + (HE ? (int64_t)k * Nc * Nc : 0);
+  Pair<T>* xo = reinterpret_cast<Pair<T>*>(xout + (int64_t)k * n);
+  const T zero = zero_of(T());
+  const int half = N >> 1;                    // pairs per row
+  const int px = x >> 1;
+
+  // rows ys-4 .. ys+SR+3 (index r = row - (ys-4)); b is read on rows 1..NR-2
+  T S0[NR], S1[NR], B0[NR], B1[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int yy = ys - 4 + r;
+    const bool ok = col_in && yy >= 0 && yy < N;
+    T v0 = zero, v1 = zero;
+    if constexpr (HX) {
+      const Pair<T> p = xc[ok ? yy * half + px : 0];
+      v0 = ok ? p.e0 : zero;
+      v1 = ok ? p.e1 : zero;
+    }
+    if constexpr (HE) {
+      // both columns of the pair lie in one 2x2 aggregate
+      const T e = ldz(ecc, (yy >> 1) * Nc + px, ok);
+      v0 += wh * e;
+      v1 += wh * e;
+    }
+    S0[r] = v0;
+    S1[r] = v1;
+    if (r >= 1 && r <= NR - 2) {
+      const Pair<T> q = bc[ok ? yy * half + px : 0];
+      B0[r] = ok ? q.e0 : zero;
+      B1[r] = ok ? q.e1 : zero;
+    } else {
+      B0[r] = zero;
+      B1[r] = zero;
+    }
+  }
+  auto in_grid = [&](int r) {
+    const int yy = ys - 4 + r;
+    return col_in && yy >= 0 && yy < N;
+  };
+  // one colour stage on rows lo..NR-1-lo: in row r the lane's cell of colour
+  // C is its even column when (C + r) is even, else its odd column
+  auto stage = [&](auto colour, int lo) {
+    constexpr int C = decltype(colour)::value;
+#pragma unroll
+    for (int r = lo; r < NR - lo; ++r) {
+      if (((C + r) & 1) == 0) {
+        const T xl = wave_shr1(S1[r]), xr = S1[r];
+        const T v = dinv * (B0[r] + c * (xl + xr + S0[r - 1] + S0[r + 1]));
+        S0[r] = in_grid(r) ? v : zero;
+      } else {
+        const T xl = S0[r], xr = wave_shl1(S0[r]);
+        const T v = dinv * (B1[r] + c * (xl + xr + S1[r - 1] + S1[r + 1]));
+        S1[r] = in_grid(r) ? v : zero;
+      }
+    }
+  };
+  using First = std::integral_constant<int, F>;
+  using Second = std::integral_constant<int, 1 - F>;
+  stage(First(), 1);    // valid columns 1..126 of the wave's 128
+  stage(Second(), 2);   // 2..125
+  stage(First(), 3);    // 3..124
+  stage(Second(), 4);   // 4..123: lanes 2..61
+  double dre = 0.0, dim = 0.0;
+#pragma unroll
+  for (int r = 4; r < NR - 4; ++r) {
+    const int y2 = ys - 4 + r;
+    if (owned && y2 < yend) {
+      xo[y2 * half + px] = Pair<T>{S0[r], S1[r]};
+      if (partials) {
+        cdot_acc(dre, dim, B0[r], S0[r]);
+        cdot_acc(dre, dim, B1[r], S1[r]);
+      }
+    }
+  }
+  if (partials) {
+    block_sum2<kThreads>(dre, dim, red);
+    if (threadIdx.x == 0) partials[(int64_t)k * blocks_per_plane + bp] = {dre, dim};
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Row-marching stencil kernels: a block covers 64 consecutive x (one wave per
 // row group) and 4 x MY rows; each thread walks MY rows keeping the vertical
 // neighbours in registers.  Tile = 64 x (4*MY).
@@ -560,15 +693,16 @@ int poisson_march_tiles(int N) { return ((N + MX - 1) / MX) * ((N + MTY - 1) / M
 // partial sums per column of the fused sweep: blocks of 4 column-marching waves
 // for N >= 64, LDS tiles below
 template <typename T>
-int poisson_gs_tiles(int N, int rows) {
+int poisson_gs_tiles(int N, int rows, int sweeps) {
   if (N >= 64) {
-    const int units = ((N + SCOLS - 1) / SCOLS) * ((N + rows - 1) / rows);
+    const int cols = sweeps == 2 ? SCOLS2 : SCOLS;
+    const int units = ((N + cols - 1) / cols) * ((N + rows - 1) / rows);
     return (units + 3) / 4;
   }
   return ((N + GTX - 1) / GTX) * ((N + GTY - 1) / GTY);
 }
-template int poisson_gs_tiles<float>(int, int);
-template int poisson_gs_tiles<double>(int, int);
+template int poisson_gs_tiles<float>(int, int, int);
+template int poisson_gs_tiles<double>(int, int, int);
 
 template <> void gs_rows_options<float>(int out[3]) { out[0] = 8; out[1] = 16; out[2] = 32; }
 template <> void gs_rows_options<double>(int out[3]) { out[0] = 4; out[1] = 8; out[2] = 16; }
@@ -604,50 +738,75 @@ void poisson_residual(const Tb* b, const Tx* x, Tr* r, int N, double d, double c
                      partials, timing_log());
 }
 
-template <typename T, int SR>
+template <typename T, int SR, int NSW>
 static void rbgs_march_launch(const T* xin, const T* b, T* xout, const T* ec, double omega, int N,
                               double d, double c, int nb, const int* active, bool reverse,
                               c64* partials, hipStream_t s) {
-  const int bpp = poisson_gs_tiles<T>(N, SR);
+  const int bpp = poisson_gs_tiles<T>(N, SR, NSW);
   const dim3 g(bpp * nb), blk(kThreads);
   const R_t<T> wh = (R_t<T>)(0.5 * omega), di = (R_t<T>)(1.0 / d), cc = (R_t<T>)c;
   const int f = reverse ? 1 : 0;
   // null pointers are replaced by b (valid, never read) for the templated forms
   const T* xp = xin ? xin : b;
   const T* ep = ec ? ec : b;
+#define MLMC_RBGS_LAUNCH(HX, HE)                                                            \
+  do {                                                                                      \
+    if constexpr (NSW == 2) {                                                               \
+      if (f)                                                                                \
+        MLMC_LAUNCH((k_rbgs2_march<T, HX, HE, SR, 1>), g, blk, 0, s, xp, b, xout, ep, wh, N, \
+                    di, cc, nb, active, partials, timing_log());                            \
+      else                                                                                  \
+        MLMC_LAUNCH((k_rbgs2_march<T, HX, HE, SR, 0>), g, blk, 0, s, xp, b, xout, ep, wh, N, \
+                    di, cc, nb, active, partials, timing_log());                            \
+    } else                                                                                  \
+      MLMC_LAUNCH((k_rbgs_march<T, HX, HE, SR>), g, blk, 0, s, xp, b, xout, ep, wh, N, di,   \
+                  cc, f, nb, active, partials, timing_log());                               \
+  } while (0)
   if (xin && ec)
-    MLMC_LAUNCH((k_rbgs_march<T, true, true, SR>), g, blk, 0, s, xp, b, xout, ep, wh, N, di, cc,
-                f, nb, active, partials, timing_log());
+    MLMC_RBGS_LAUNCH(true, true);
   else if (xin)
-    MLMC_LAUNCH((k_rbgs_march<T, true, false, SR>), g, blk, 0, s, xp, b, xout, ep, wh, N, di, cc,
-                f, nb, active, partials, timing_log());
+    MLMC_RBGS_LAUNCH(true, false);
   else if (ec)
-    MLMC_LAUNCH((k_rbgs_march<T, false, true, SR>), g, blk, 0, s, xp, b, xout, ep, wh, N, di, cc,
-                f, nb, active, partials, timing_log());
+    MLMC_RBGS_LAUNCH(false, true);
   else
-    MLMC_LAUNCH((k_rbgs_march<T, false, false, SR>), g, blk, 0, s, xp, b, xout, ep, wh, N, di,
-                cc, f, nb, active, partials, timing_log());
+    MLMC_RBGS_LAUNCH(false, false);
+#undef MLMC_RBGS_LAUNCH
+}
+
+template <typename T, int NSW>
+static void rbgs_march_rows(const T* xin, const T* b, T* xout, const T* ec, double omega, int N,
+                            double d, double c, int nb, const int* active, bool reverse,
+                            c64* partials, int rows, hipStream_t s) {
+  int opts[3];
+  gs_rows_options<T>(opts);
+  if (rows == opts[0])
+    rbgs_march_launch<T, (sizeof(T) == 4 ? 8 : 4), NSW>(xin, b, xout, ec, omega, N, d, c, nb,
+                                                        active, reverse, partials, s);
+  else if (rows == opts[1])
+    rbgs_march_launch<T, (sizeof(T) == 4 ? 16 : 8), NSW>(xin, b, xout, ec, omega, N, d, c, nb,
+                                                         active, reverse, partials, s);
+  else if (rows == opts[2])
+    rbgs_march_launch<T, (sizeof(T) == 4 ? 32 : 16), NSW>(xin, b, xout, ec, omega, N, d, c, nb,
+                                                          active, reverse, partials, s);
+  else
+    throw Error(MLMC_EINVAL, "unsupported rows per Gauss-Seidel segment");
 }
 
 template <typename T>
 void poisson_rbgs_fused(const T* xin, const T* b, T* xout, const T* ec, double omega, int N,
                         double d, double c, int nb, const int* active, bool reverse,
-                        c64* partials, int rows, hipStream_t s) {
+                        c64* partials, int rows, int sweeps, hipStream_t s) {
+  if (sweeps != 1 && sweeps != 2) throw Error(MLMC_EINVAL, "a fused pass holds 1 or 2 sweeps");
   if (N >= 64) {
-    int opts[3];
-    gs_rows_options<T>(opts);
-    if (rows == opts[0])
-      rbgs_march_launch<T, (sizeof(T) == 4 ? 8 : 4)>(xin, b, xout, ec, omega, N, d, c, nb, active,
-                                                     reverse, partials, s);
-    else if (rows == opts[1])
-      rbgs_march_launch<T, (sizeof(T) == 4 ? 16 : 8)>(xin, b, xout, ec, omega, N, d, c, nb,
-                                                      active, reverse, partials, s);
-    else if (rows == opts[2])
-      rbgs_march_launch<T, (sizeof(T) == 4 ? 32 : 16)>(xin, b, xout, ec, omega, N, d, c, nb,
-                                                       active, reverse, partials, s);
+    if (sweeps == 2 && (N & 1)) throw Error(MLMC_EINVAL, "two fused sweeps need an even side");
+    if (sweeps == 2)
+      rbgs_march_rows<T, 2>(xin, b, xout, ec, omega, N, d, c, nb, active, reverse, partials, rows,
+                            s);
     else
-      throw Error(MLMC_EINVAL, "unsupported rows per Gauss-Seidel segment");
+      rbgs_march_rows<T, 1>(xin, b, xout, ec, omega, N, d, c, nb, active, reverse, partials, rows,
+                            s);
   } else {
+    if (sweeps != 1) throw Error(MLMC_EINVAL, "two fused sweeps need a side of at least 64");
     const int nbx = (N + GTX - 1) / GTX, nby = (N + GTY - 1) / GTY;
     MLMC_LAUNCH(k_rbgs_tile<T>, dim3(nbx * nby * nb), dim3(kThreads), 0, s, xin, b,
                        xout, ec, (R_t<T>)(0.5 * omega), N, (R_t<T>)(1.0 / d), (R_t<T>)c,
@@ -683,7 +842,7 @@ void agg2d_prolong(const T* ec, T* x, int N, double omega, double beta, int nb,
                                         double, int, const int*, c64*, hipStream_t);       \
   template void poisson_rbgs_fused<T>(const T*, const T*, T*, const T*, double, int,       \
                                       double, double, int, const int*, bool, c64*, int,    \
-                                      hipStream_t);                                        \
+                                      int, hipStream_t);                                   \
   template void poisson_residual_restrict<T>(const T*, const T*, T*, int, double, double,  \
                                              int, const int*, hipStream_t);                \
   template void agg2d_restrict<T>(const T*, T*, int, int, const int*, hipStream_t);        \

@@ -1,0 +1,114 @@
+"""GPU parity of the smoother kernels (the V-cycle's red-black Gauss-Seidel
+sweeps, called through mlmc_smooth) against the oracle's coloured sweep, and
+the two-sweep fused pass of the 2D Poisson levels against two one-sweep passes,
+bit for bit."""
+import numpy as np
+import pytest
+
+from oracle import hierarchy
+from tests.gpu_util import from_dev, require_gpu, to_dev
+from workloads import gauge_field, varcoef_faces
+
+pytestmark = pytest.mark.gpu
+
+NRHS = 5
+# FP32 sweeps against the FP64 oracle: inputs rounded to FP32 and a few
+# roundings per update; the sweep is a contraction, so the error stays at a
+# few FP32 ulps of the largest value
+TOL = {"fp64": 1e-13, "fp32_ir64": 1e-5}
+
+
+def _check(est, A, colour, level, precision, complex_=False, sweeps=(1, 2, 3), tol=None):
+    tol = TOL[precision] if tol is None else max(tol, TOL[precision])
+    rng = np.random.default_rng(level)
+    n = A.shape[0]
+    B = rng.standard_normal((NRHS, n))
+    X = rng.standard_normal((NRHS, n))
+    if complex_:
+        B = B + 1j * rng.standard_normal((NRHS, n))
+        X = X + 1j * rng.standard_normal((NRHS, n))
+    for sw in sweeps:
+        for reverse in (False, True):
+            got = from_dev(est.smooth(level, to_dev(B), to_dev(X), sw, reverse), complex_)
+            for k in range(NRHS):
+                ref = hierarchy.rbgs_sweeps(A, B[k], X[k], colour, sw, reverse)
+                err = np.max(np.abs(got[k] - ref))
+                assert err <= tol * np.max(np.abs(ref)), (level, sw, reverse, k, err)
+
+
+def _poisson(N, L, precision):
+    require_gpu()
+    import paper_2108_11281_amd as m
+    return m.TraceEstimator("poisson2d", N, L, L, nb=8, precision=precision)
+
+
+# sides 200 -> 100 -> 50 -> 25: the register-march kernels on 200 and 100
+# (ragged last wave of columns and last row segment), the LDS tile kernel on 50;
+# 128 -> 64 -> 32: power-of-two edges, the march kernel's smallest side (64)
+@pytest.mark.parametrize("precision", ["fp32_ir64", "fp64"])
+@pytest.mark.parametrize("N,L", [(200, 4), (128, 3)])
+def test_poisson_sweeps_match_oracle(N, L, precision):
+    est = _poisson(N, L, precision)
+    A, _ = hierarchy.poisson_hierarchy(N, L)
+    for level in range(1, L):
+        side = N >> (level - 1)
+        _check(est, A[level - 1], hierarchy.site_coloring(side), level, precision)
+
+
+@pytest.mark.parametrize("precision", ["fp32_ir64", "fp64"])
+def test_fused_two_sweep_pass_equals_two_passes_bitwise(precision):
+    est = _poisson(200, 3, precision)
+    rng = np.random.default_rng(7)
+    for level in (1, 2):
+        n = est.level_size(level)
+        B = to_dev(rng.standard_normal((NRHS, n)))
+        X = to_dev(rng.standard_normal((NRHS, n)))
+        for reverse in (False, True):
+            one = X
+            for sw in range(1, 4):
+                one = est.smooth(level, B, one, 1, reverse)
+                fused = est.smooth(level, B, X, sw, reverse)
+                assert np.array_equal(from_dev(fused), from_dev(one)), (level, sw, reverse)
+
+
+@pytest.mark.parametrize("precision", ["fp32_ir64", "fp64"])
+def test_wilson_and_block_sweeps_match_oracle(precision):
+    require_gpu()
+    import paper_2108_11281_amd as m
+    N, L, m0 = 32, 3, 0.1
+    th = gauge_field(N, seed=2)
+    est = m.TraceEstimator("wilson2d", N, L, L, mass=m0, field=th, block=4, n_vec=8,
+                           setup_sweeps=6, setup_seed=1, precision=precision, nb=8)
+    A, _ = hierarchy.wilson_hierarchy(N, th, m0, L, block=4, n_vec=8, sweeps=6, seed=1)
+    # level 1: 2 spins per site; level 2: 8 coarse unknowns per 4 x 4 aggregate
+    _check(est, A[0], np.repeat(hierarchy.site_coloring(N), 2), 1, precision, True, (1, 2))
+    # (the oracle's own test-vector basis agrees with the library's to ~1e-12,
+    # so the coarse operator, and the sweep through it, to about 1e-9)
+    _check(est, A[1], np.repeat(hierarchy.site_coloring(N // 4), 8), 2, precision, True, (1, 2),
+           tol=1e-9)
+
+
+@pytest.mark.parametrize("precision", ["fp32_ir64", "fp64"])
+def test_varcoef_sweeps_match_oracle(precision):
+    require_gpu()
+    import paper_2108_11281_amd as m
+    N, L = 20, 3
+    faces = varcoef_faces(N, seed=1000)
+    est = m.TraceEstimator("varcoef3d", N, L, L, shift=1e-3, field=faces, nb=8,
+                           precision=precision)
+    A, _ = hierarchy.varcoef_hierarchy(N, faces, 1e-3, L)
+    for level in (1, 2):
+        _check(est, A[level - 1], hierarchy.site_coloring_3d(N >> (level - 1)), level, precision,
+               sweeps=(1, 2))
+
+
+def test_smooth_rejects_bad_arguments():
+    est = _poisson(64, 3, "fp32_ir64")
+    import paper_2108_11281_amd as m
+    import torch
+    B = torch.zeros((2, est.level_size(3)), dtype=torch.float64, device="cuda")
+    with pytest.raises(m.MLMCError):   # no smoother on the coarsest level
+        est.smooth(3, B, B, 1)
+    B = torch.zeros((2, est.level_size(1)), dtype=torch.float64, device="cuda")
+    with pytest.raises(m.MLMCError):
+        est.smooth(1, B, B, -1)

@@ -166,3 +166,35 @@ def test_block_rbgs_sweep_fixed_point():
     x = rng.standard_normal(D.shape[0]) + 1j * rng.standard_normal(D.shape[0])
     b = D @ x
     assert np.allclose(hierarchy.block_rbgs_sweep(D, x, N, 2, b), x, atol=1e-13)
+
+
+def test_red_black_sweep_is_permuted_lexicographic_gauss_seidel():
+    # with the unknowns ordered colour 0 first, a red-black sweep of a 5-point
+    # (or 7-point) operator is the point Gauss-Seidel splitting
+    # (D + L) x_new = b - U x of the permuted matrix
+    import scipy.sparse.linalg as spla
+    from oracle import operators
+    rng = np.random.default_rng(3)
+    cases = [(operators.poisson2d(7), hierarchy.site_coloring(7)),
+             (operators.varcoef3d(4, np.exp(rng.standard_normal((3, 4, 4, 5))), 1e-3),
+              hierarchy.site_coloring_3d(4))]
+    for A, colour in cases:
+        A = A.tocsr()
+        n = A.shape[0]
+        b, x = rng.standard_normal(n), rng.standard_normal(n)
+        for reverse in (False, True):
+            first = 1 if reverse else 0
+            perm = np.concatenate([np.flatnonzero(colour == first),
+                                   np.flatnonzero(colour != first)])
+            Ap = A[perm][:, perm]
+            rhs = b[perm] - sp.triu(Ap, 1) @ x[perm]
+            xp = spla.spsolve_triangular(sp.tril(Ap).tocsr(), rhs, lower=True)
+            ref = np.empty(n)
+            ref[perm] = xp
+            got = hierarchy.rbgs_sweeps(A, b, x, colour, 1, reverse=reverse)
+            assert np.allclose(got, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    # repeated sweeps converge to the solution of the SPD system
+    A, colour = cases[0]
+    b = rng.standard_normal(A.shape[0])
+    x = hierarchy.rbgs_sweeps(A, b, np.zeros_like(b), colour, 200)
+    assert np.linalg.norm(A @ x - b) <= 1e-10 * np.linalg.norm(b)
