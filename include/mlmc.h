@@ -203,13 +203,15 @@ int mlmc_apply(void* ctx, int level, int nrhs, const double* x_dev, double* y_de
  * smoother, Section 4 multigrid setting; sites coloured by the parity of the sum
  * of their coordinates, first colour (even) first, reverse != 0: odd first, as
  * in post-smoothing), run in the working precision by the V-cycle's own kernels
- * (2D Poisson levels: passes of up to two fused sweeps).  b_dev, x_dev: FP64
- * (complex: interleaved) RHS-major blocks of nrhs <= nb vectors of n_l; x_dev is
- * read and overwritten.  1 <= l < L_s; sweeps >= 0.  The library allocates and
- * frees three working-precision blocks of nrhs x n_l during the call.  For
- * tests and inspection. */
+ * (2D Poisson levels: passes of up to two fused sweeps).  With rc_dev non-NULL
+ * (reverse == 0 only) also Rc = R_l (B - A_l X) of the final X, as the last
+ * pre-smoothing pass of the V-cycle writes it (fused into that pass where the
+ * V-cycle fuses it).  b_dev, x_dev: FP64 (complex: interleaved) RHS-major blocks
+ * of nrhs <= nb vectors of n_l, x_dev read and overwritten; rc_dev: nrhs
+ * vectors of n_{l+1}.  1 <= l < L_s; sweeps >= 0.  The library allocates and
+ * frees working-precision copies during the call.  For tests and inspection. */
 int mlmc_smooth(void* ctx, int level, int nrhs, int sweeps, int reverse, const double* b_dev,
-                double* x_dev);
+                double* x_dev, double* rc_dev);
 
 /* Xc = R_l X = P_l^H X (restriction to level l+1), FP64, 1 <= l < L_s. */
 int mlmc_restrict(void* ctx, int level, int nrhs, const double* x_dev, double* xc_dev);

@@ -268,14 +268,18 @@ class TraceEstimator:
                                      self._ptr(y)))
         return y
 
-    def smooth(self, level, b, x, sweeps, reverse=False):
+    def smooth(self, level, b, x, sweeps, reverse=False, restrict=False):
         """`sweeps` red-black Gauss-Seidel sweeps of A_level x = b, in the working
         precision with the V-cycle's own kernels; returns the new x (x is not
-        changed).  reverse: second colour first, as in post-smoothing."""
+        changed), and with restrict=True also R (b - A x) of it, as the V-cycle's
+        last pre-smoothing pass forms it.  reverse: second colour first, as in
+        post-smoothing."""
         y = x.clone()
+        rc = self._vec(level + 1, b.shape[0], b.device) if restrict else None
         self._c(self._lib.mlmc_smooth(self._ctx, int(level), int(b.shape[0]), int(sweeps),
-                                      1 if reverse else 0, self._ptr(b), self._ptr(y)))
-        return y
+                                      1 if reverse else 0, self._ptr(b), self._ptr(y),
+                                      self._ptr(rc) if restrict else None))
+        return (y, rc) if restrict else y
 
     def restrict(self, level, x):
         y = self._vec(level + 1, x.shape[0], x.device)

@@ -109,7 +109,7 @@ SIGNATURES = {
     "mlmc_solve": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P, _D]),
     "mlmc_apply": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P]),
     "mlmc_smooth": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                   _P, _P]),
+                                   _P, _P, _P]),
     "mlmc_restrict": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P]),
     "mlmc_prolong": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P]),
     "mlmc_probes": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_uint64, ctypes.c_int,

@@ -139,11 +139,12 @@ int mlmc_apply(void* c, int level, int nrhs, const double* x_dev, double* y_dev)
 }
 
 int mlmc_smooth(void* c, int level, int nrhs, int sweeps, int reverse, const double* b_dev,
-                double* x_dev) {
+                double* x_dev, double* rc_dev) {
   Context* ctx = as_ctx(c);
   if (!ctx || !b_dev || !x_dev) return MLMC_EINVAL;
-  return guarded(ctx,
-                 [&] { ctx->smooth_fp64(level, nrhs, sweeps, reverse != 0, b_dev, x_dev); });
+  return guarded(ctx, [&] {
+    ctx->smooth_fp64(level, nrhs, sweeps, reverse != 0, b_dev, x_dev, rc_dev);
+  });
 }
 
 int mlmc_restrict(void* c, int level, int nrhs, const double* x_dev, double* xc_dev) {

@@ -566,24 +566,33 @@ void Context::vcycle(int l, const T* b, T* x, int nb, const int* act, c64* rz_pa
   const int pre = opt_.nu_pre, post = opt_.nu_post;
   const int per = sweeps_per_pass(l);
   const int rows = gs_rows<T>(l);
-  // pre-smoothing in passes of up to `per` sweeps: outputs alternate tmp, x, tmp, ...
+  T* bc = w.vb[l];
+  T* ec = w.vx[l];
+  // pre-smoothing in passes of up to `per` sweeps: outputs alternate tmp, x, tmp,
+  // ...; a last pass of two fused sweeps also writes the restricted residual
   const T* u = nullptr;  // current iterate (nullptr = 0)
+  bool restricted = false;
   for (int i = 0, pass = 0; i < pre; ++pass) {
     const int sw = std::min(per, pre - i);
     T* out = (pass % 2 == 0) ? tmp : x;
     const T* in = u;
-    timed<T>(kTimGs, en * (2.0 + (in ? 1.0 : 0.0)), act, nb, [&] {
-      poisson_rbgs_fused<T>(in, b, out, nullptr, 0.0, L.side, L.d, L.c, nb, act, false, nullptr,
-                            rows, sw, s_);
-    });
+    if (sw == 2 && i + sw == pre) {
+      timed<T>(kTimGs, en * (2.25 + (in ? 1.0 : 0.0)), act, nb, [&] {
+        poisson_rbgs_restrict<T>(in, b, out, bc, L.side, L.d, L.c, nb, act, rows, s_);
+      });
+      restricted = true;
+    } else {
+      timed<T>(kTimGs, en * (2.0 + (in ? 1.0 : 0.0)), act, nb, [&] {
+        poisson_rbgs_fused<T>(in, b, out, nullptr, 0.0, L.side, L.d, L.c, nb, act, false,
+                              nullptr, rows, sw, s_);
+      });
+    }
     u = out;
     i += sw;
   }
-  T* bc = w.vb[l];
-  T* ec = w.vx[l];
   if (u == nullptr)
     op_restrict<T>(l, b, bc, nb, act);
-  else
+  else if (!restricted)
     timed<T>(kTimResRestrict, 2.25 * en, act, nb,
              [&] { op_res_restrict<T>(l, b, u, bc, nb, act); });
   vcycle<T>(l + 1, bc, ec, nb, act, nullptr);
@@ -1203,27 +1212,41 @@ void Context::apply_fp64(int level, int nrhs, const double* x, double* y) {
 
 // x <- `sweeps` red-black Gauss-Seidel sweeps of A_level x = b in the working
 // precision, with the V-cycle's own kernels (passes of fused sweeps on the 2D
-// Poisson levels); reverse: second colour first, as in post-smoothing
+// Poisson levels); reverse: second colour first, as in post-smoothing.  rc
+// (nullable): R (b - A x) of the final x, as the V-cycle's last pre-pass forms it
 void Context::smooth_fp64(int level, int nrhs, int sweeps, bool reverse, const double* b,
-                          double* x) {
+                          double* x, double* rc) {
   MLMC_REQUIRE(level >= 1 && level < Ls_, MLMC_EINVAL, "level out of range (no smoother on L_s)");
   MLMC_REQUIRE(nrhs >= 1 && nrhs <= nb_, MLMC_EINVAL, "nrhs must be in [1, nb]");
   MLMC_REQUIRE(sweeps >= 0, MLMC_EINVAL, "sweeps must be >= 0");
+  MLMC_REQUIRE(!(rc && reverse), MLMC_EINVAL, "the restricted residual follows a forward pass");
   const int64_t n = lv_[level - 1].n;
-  const int64_t m = n * nrhs * (complex_ ? 2 : 1);
+  const int64_t elem = complex_ ? 2 : 1;
+  const int64_t m = n * nrhs * elem, mc = lv_[level].n * nrhs * elem;
+  auto to_t = [&](auto* dst, const double* src, int64_t cnt) {
+    using T = typename std::remove_pointer<decltype(dst)>::type;
+    if constexpr (std::is_same<T, double>::value)
+      vec_copy<double>(src, dst, cnt, 1, nullptr, s_);
+    else
+      vec_convert<T, double>(src, dst, cnt, 1, nullptr, s_);
+  };
+  auto from_t = [&](const auto* src, double* dst, int64_t cnt) {
+    using T = typename std::remove_const<typename std::remove_pointer<decltype(src)>::type>::type;
+    if constexpr (std::is_same<T, double>::value)
+      vec_copy<double>(src, dst, cnt, 1, nullptr, s_);
+    else
+      vec_convert<double, T>(src, dst, cnt, 1, nullptr, s_);
+  };
   auto run = [&](auto tag) {
     using T = decltype(tag);
     T* bt = dalloc_n<T>(m);
     T* xa = dalloc_n<T>(m);
     T* xb = dalloc_n<T>(m);
-    if constexpr (std::is_same<T, double>::value) {
-      vec_copy<double>(b, bt, m, 1, nullptr, s_);
-      vec_copy<double>(x, xa, m, 1, nullptr, s_);
-    } else {
-      vec_convert<T, double>(b, bt, m, 1, nullptr, s_);
-      vec_convert<T, double>(x, xa, m, 1, nullptr, s_);
-    }
+    T* rct = rc ? dalloc_n<T>(mc) : nullptr;
+    to_t(bt, b, m);
+    to_t(xa, x, m);
     const Level& L = lv_[level - 1];
+    bool restricted = false;
     if (complex_) {
       using C = typename std::conditional<sizeof(T) == 4, c32, c64>::type;
       for (int i = 0; i < sweeps; ++i)
@@ -1237,21 +1260,38 @@ void Context::smooth_fp64(int level, int nrhs, int sweeps, bool reverse, const d
       const int per = sweeps_per_pass(level);
       for (int i = 0; i < sweeps;) {
         const int sw = std::min(per, sweeps - i);
-        poisson_rbgs_fused<T>(xa, bt, xb, nullptr, 0.0, L.side, L.d, L.c, nrhs, nullptr, reverse,
-                              nullptr, gs_rows<T>(level), sw, s_);
+        if (rct && sw == 2 && i + sw == sweeps) {
+          poisson_rbgs_restrict<T>(xa, bt, xb, rct, L.side, L.d, L.c, nrhs, nullptr,
+                                   gs_rows<T>(level), s_);
+          restricted = true;
+        } else {
+          poisson_rbgs_fused<T>(xa, bt, xb, nullptr, 0.0, L.side, L.d, L.c, nrhs, nullptr,
+                                reverse, nullptr, gs_rows<T>(level), sw, s_);
+        }
         std::swap(xa, xb);
         i += sw;
       }
     }
-    if constexpr (std::is_same<T, double>::value)
-      vec_copy<double>(xa, x, m, 1, nullptr, s_);
-    else
-      vec_convert<double, T>(xa, x, m, 1, nullptr, s_);
+    if (rct && !restricted) {
+      if (complex_) {
+        using C = typename std::conditional<sizeof(T) == 4, c32, c64>::type;
+        cop_residual<C, C, C>(level, reinterpret_cast<const C*>(bt),
+                              reinterpret_cast<const C*>(xa), reinterpret_cast<C*>(xb), nrhs,
+                              nullptr, nullptr);
+        cop_restrict<C>(level, reinterpret_cast<const C*>(xb), reinterpret_cast<C*>(rct), nrhs,
+                        nullptr);
+      } else {
+        op_res_restrict<T>(level, bt, xa, rct, nrhs, nullptr);
+      }
+    }
+    from_t(xa, x, m);
+    if (rct) from_t(rct, rc, mc);
     MLMC_HIP(hipStreamSynchronize(s_));
     MLMC_HIP(hipGetLastError());
     dfree(bt);
     dfree(xa);
     dfree(xb);
+    if (rct) dfree(rct);
   };
   if (opt_.precision == MLMC_FP64)
     run(double());

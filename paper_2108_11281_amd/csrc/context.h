@@ -85,7 +85,8 @@ class Context {
   void solve_fp64(int level, int nrhs, const double* b, double* y, double* relres,
                   bool throw_on_noconv);
   void apply_fp64(int level, int nrhs, const double* x, double* y);
-  void smooth_fp64(int level, int nrhs, int sweeps, bool reverse, const double* b, double* x);
+  void smooth_fp64(int level, int nrhs, int sweeps, bool reverse, const double* b, double* x,
+                   double* rc);
   void restrict_fp64(int level, int nrhs, const double* x, double* xc);
   void prolong_fp64(int level, int nrhs, const double* xc, double* x);
   void probes_fp64(int level, uint64_t seed, int stream, int64_t first, int nrhs,

@@ -423,6 +423,7 @@ void Context::solve_complex(int l, const c64* b, c64* y, int nb, c64* err) {
 template void Context::cop_residual<c64, c64, c64>(int, const c64*, const c64*, c64*, int,
                                                    const int*, c64*);
 template void Context::cop_restrict<c64>(int, const c64*, c64*, int, const int*);
+template void Context::cop_restrict<c32>(int, const c32*, c32*, int, const int*);
 template void Context::cop_prolong<c64>(int, const c64*, c64*, int, const int*, double, double);
 template void Context::cop_residual<c32, c32, c32>(int, const c32*, const c32*, c32*, int,
                                                    const int*, c64*);

@@ -171,6 +171,11 @@ template <typename T>
 void poisson_rbgs_fused(const T* xin, const T* b, T* xout, const T* ec, double omega, int N,
                         double d, double c, int nb, const int* active, bool reverse,
                         c64* partials, int rows, int sweeps, hipStream_t s);
+// last pre-smoothing pass: xout = S^2(xin ; b) (two fused sweeps, red first;
+// xin == nullptr means 0) and rc = R (b - A xout) in the same pass; N even, >= 64
+template <typename T>
+void poisson_rbgs_restrict(const T* xin, const T* b, T* xout, T* rc, int N, double d, double c,
+                           int nb, const int* active, int rows, hipStream_t s);
 // rc = R (b - A x), R = P^T, P the orthonormal 2x2 aggregation (entries 1/2)
 template <typename T>
 void poisson_residual_restrict(const T* b, const T* x, T* rc, int N, double d,

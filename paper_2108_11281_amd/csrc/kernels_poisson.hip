@@ -291,24 +291,34 @@ __global__ __launch_bounds__(kThreads) void k_rbgs_march(const T* __restrict__ x
 // same order, as in two launches of the one-sweep kernel, so the results agree
 // bit for bit.  Needs N even (every smoothed level has a coarser one).
 // ---------------------------------------------------------------------------
-constexpr int SCOLS2 = 120;  // owned columns per wave, two fused sweeps
+// RS (the last pre-smoothing pass): the pass also writes the restricted
+// residual rc = R (b - A x_out) of 2x2 aggregates (a lane's column pair is one
+// aggregate column); the residual needs x_out one column and one row beyond
+// the owned cells, so a wave then owns lanes 3..60 and loads SR + 10 rows.
+template <bool RS> constexpr int rbgs2_first_lane() { return RS ? 3 : 2; }
+template <bool RS> constexpr int rbgs2_cols() { return 2 * (64 - 2 * rbgs2_first_lane<RS>()); }
+constexpr int SCOLS2 = rbgs2_cols<false>();  // 120 owned columns per wave
 
 template <typename T>
 struct alignas(2 * sizeof(T)) Pair {
   T e0, e1;
 };
 
-template <typename T, bool HX, bool HE, int SR, int F>
+template <typename T, bool HX, bool HE, int SR, int F, bool RS>
 __global__ __launch_bounds__(kThreads) void k_rbgs2_march(const T* __restrict__ xin,
                                                           const T* __restrict__ b,
                                                           T* __restrict__ xout,
                                                           const T* __restrict__ ec, R_t<T> wh,
-                                                          int N, R_t<T> dinv, R_t<T> c, int nb,
-                                                          const int* active, c64* partials,
+                                                          int N, R_t<T> dinv, R_t<T> d, R_t<T> c,
+                                                          int nb, const int* active,
+                                                          c64* partials, T* __restrict__ rc,
                                                           int* tlog) {
-  constexpr int NR = SR + 8;
+  constexpr int HALO = RS ? 5 : 4;            // rows loaded above and below a segment
+  constexpr int NR = SR + 2 * HALO;
+  constexpr int LO = rbgs2_first_lane<RS>(), HI = 63 - LO;
+  constexpr int COLS = rbgs2_cols<RS>();
   __shared__ double red[16];
-  const int nwx = (N + SCOLS2 - 1) / SCOLS2, nseg = (N + SR - 1) / SR;
+  const int nwx = (N + COLS - 1) / COLS, nseg = (N + SR - 1) / SR;
   const int units_per_plane = nwx * nseg;
   const int blocks_per_plane = (units_per_plane + 3) / 4;
   const int t = xcd_tile_index(blocks_per_plane * nb);
@@ -320,11 +330,11 @@ __global__ __launch_bounds__(kThreads) void k_rbgs2_march(const T* __restrict__ 
   const int unit = bp * 4 + w;                // unit = seg * nwx + wx within the plane
   const bool unit_ok = unit < units_per_plane;
   const int seg = unit / nwx, wx = unit - seg * nwx;
-  const int x = wx * SCOLS2 - 4 + 2 * lane;   // even column of the lane's pair
-  const int ys = seg * SR;                    // even, so row parity = parity of r below
+  const int x = wx * COLS - 2 * LO + 2 * lane;  // even column of the lane's pair
+  const int ys = seg * SR;                    // even: row ys-HALO+r has the parity of r+HALO
   const int yend = ys + SR < N ? ys + SR : N;
   const bool col_in = unit_ok && x >= 0 && x < N;
-  const bool owned = col_in && lane >= 2 && lane <= 61;
+  const bool owned = col_in && lane >= LO && lane <= HI;
   const int64_t n = (int64_t)N * N;
   const int Nc = N >> 1;
   const Pair<T>* xc = reinterpret_cast<const Pair<T>*>(xin + (HX ? (int64_t)k * n : 0));
@@ -335,11 +345,11 @@ __global__ __launch_bounds__(kThreads) void k_rbgs2_march(const T* __restrict__ 
   const int half = N >> 1;                    // pairs per row
   const int px = x >> 1;
 
-  // rows ys-4 .. ys+SR+3 (index r = row - (ys-4)); b is read on rows 1..NR-2
+  // rows ys-HALO .. ys+SR+HALO-1 (index r = row - (ys-HALO)); b on rows 1..NR-2
   T S0[NR], S1[NR], B0[NR], B1[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
-    const int yy = ys - 4 + r;
+    const int yy = ys - HALO + r;
     const bool ok = col_in && yy >= 0 && yy < N;
     T v0 = zero, v1 = zero;
     if constexpr (HX) {
@@ -365,16 +375,16 @@ __global__ __launch_bounds__(kThreads) void k_rbgs2_march(const T* __restrict__ 
     }
   }
   auto in_grid = [&](int r) {
-    const int yy = ys - 4 + r;
+    const int yy = ys - HALO + r;
     return col_in && yy >= 0 && yy < N;
   };
   // one colour stage on rows lo..NR-1-lo: in row r the lane's cell of colour
-  // C is its even column when (C + r) is even, else its odd column
+  // C is its even column when C + r + HALO is even, else its odd column
   auto stage = [&](auto colour, int lo) {
     constexpr int C = decltype(colour)::value;
 #pragma unroll
     for (int r = lo; r < NR - lo; ++r) {
-      if (((C + r) & 1) == 0) {
+      if (((C + r + HALO) & 1) == 0) {
         const T xl = wave_shr1(S1[r]), xr = S1[r];
         const T v = dinv * (B0[r] + c * (xl + xr + S0[r - 1] + S0[r + 1]));
         S0[r] = in_grid(r) ? v : zero;
@@ -387,20 +397,38 @@ __global__ __launch_bounds__(kThreads) void k_rbgs2_march(const T* __restrict__ 
   };
   using First = std::integral_constant<int, F>;
   using Second = std::integral_constant<int, 1 - F>;
-  stage(First(), 1);    // valid columns 1..126 of the wave's 128
+  stage(First(), 1);    // valid on columns 1..126 of the wave's 128
   stage(Second(), 2);   // 2..125
   stage(First(), 3);    // 3..124
-  stage(Second(), 4);   // 4..123: lanes 2..61
+  stage(Second(), 4);   // 4..123 (lanes 2..61)
   double dre = 0.0, dim = 0.0;
 #pragma unroll
-  for (int r = 4; r < NR - 4; ++r) {
-    const int y2 = ys - 4 + r;
+  for (int r = HALO; r < NR - HALO; ++r) {
+    const int y2 = ys - HALO + r;
     if (owned && y2 < yend) {
       xo[y2 * half + px] = Pair<T>{S0[r], S1[r]};
       if (partials) {
         cdot_acc(dre, dim, B0[r], S0[r]);
         cdot_acc(dre, dim, B1[r], S1[r]);
       }
+    }
+  }
+  if constexpr (RS) {
+    // rc(px, Y) = 1/2 sum over the aggregate's 4 cells of (b - A x_out), in the
+    // order of the stand-alone residual-restriction kernel
+    T* rcc = rc + (int64_t)k * Nc * Nc;
+#pragma unroll
+    for (int r = HALO; r < NR - HALO; r += 2) {
+      T acc = zero;
+#pragma unroll
+      for (int dy = 0; dy < 2; ++dy) {
+        const int j = r + dy;
+        const T xl = wave_shr1(S1[j]), xr = wave_shl1(S0[j]);
+        acc += B0[j] - (d * S0[j] - c * (xl + S1[j] + S0[j - 1] + S0[j + 1]));
+        acc += B1[j] - (d * S1[j] - c * (S0[j] + xr + S1[j - 1] + S1[j + 1]));
+      }
+      const int y2 = ys - HALO + r;
+      if (owned && y2 < yend) rcc[(y2 >> 1) * Nc + px] = (R_t<T>)0.5 * acc;
     }
   }
   if (partials) {
@@ -741,23 +769,39 @@ void poisson_residual(const Tb* b, const Tx* x, Tr* r, int N, double d, double c
 template <typename T, int SR, int NSW>
 static void rbgs_march_launch(const T* xin, const T* b, T* xout, const T* ec, double omega, int N,
                               double d, double c, int nb, const int* active, bool reverse,
-                              c64* partials, hipStream_t s) {
-  const int bpp = poisson_gs_tiles<T>(N, SR, NSW);
-  const dim3 g(bpp * nb), blk(kThreads);
+                              c64* partials, T* rc, hipStream_t s) {
   const R_t<T> wh = (R_t<T>)(0.5 * omega), di = (R_t<T>)(1.0 / d), cc = (R_t<T>)c;
+  const R_t<T> dd = (R_t<T>)d;
   const int f = reverse ? 1 : 0;
   // null pointers are replaced by b (valid, never read) for the templated forms
   const T* xp = xin ? xin : b;
   const T* ep = ec ? ec : b;
+  const dim3 blk(kThreads);
+  if constexpr (NSW == 2) {
+    if (rc) {
+      // last pre-smoothing pass: forward colour order, no coarse correction
+      if (ec || reverse) throw Error(MLMC_EINVAL, "restricted residual only on a pre-pass");
+      const int nwx = (N + rbgs2_cols<true>() - 1) / rbgs2_cols<true>();
+      const dim3 g(((nwx * ((N + SR - 1) / SR) + 3) / 4) * nb);
+      if (xin)
+        MLMC_LAUNCH((k_rbgs2_march<T, true, false, SR, 0, true>), g, blk, 0, s, xp, b, xout, ep,
+                    wh, N, di, dd, cc, nb, active, partials, rc, timing_log());
+      else
+        MLMC_LAUNCH((k_rbgs2_march<T, false, false, SR, 0, true>), g, blk, 0, s, xp, b, xout, ep,
+                    wh, N, di, dd, cc, nb, active, partials, rc, timing_log());
+      return;
+    }
+  }
+  const dim3 g(poisson_gs_tiles<T>(N, SR, NSW) * nb);
 #define MLMC_RBGS_LAUNCH(HX, HE)                                                            \
   do {                                                                                      \
     if constexpr (NSW == 2) {                                                               \
       if (f)                                                                                \
-        MLMC_LAUNCH((k_rbgs2_march<T, HX, HE, SR, 1>), g, blk, 0, s, xp, b, xout, ep, wh, N, \
-                    di, cc, nb, active, partials, timing_log());                            \
+        MLMC_LAUNCH((k_rbgs2_march<T, HX, HE, SR, 1, false>), g, blk, 0, s, xp, b, xout, ep, \
+                    wh, N, di, dd, cc, nb, active, partials, (T*)nullptr, timing_log());    \
       else                                                                                  \
-        MLMC_LAUNCH((k_rbgs2_march<T, HX, HE, SR, 0>), g, blk, 0, s, xp, b, xout, ep, wh, N, \
-                    di, cc, nb, active, partials, timing_log());                            \
+        MLMC_LAUNCH((k_rbgs2_march<T, HX, HE, SR, 0, false>), g, blk, 0, s, xp, b, xout, ep, \
+                    wh, N, di, dd, cc, nb, active, partials, (T*)nullptr, timing_log());    \
     } else                                                                                  \
       MLMC_LAUNCH((k_rbgs_march<T, HX, HE, SR>), g, blk, 0, s, xp, b, xout, ep, wh, N, di,   \
                   cc, f, nb, active, partials, timing_log());                               \
@@ -776,18 +820,18 @@ static void rbgs_march_launch(const T* xin, const T* b, T* xout, const T* ec, do
 template <typename T, int NSW>
 static void rbgs_march_rows(const T* xin, const T* b, T* xout, const T* ec, double omega, int N,
                             double d, double c, int nb, const int* active, bool reverse,
-                            c64* partials, int rows, hipStream_t s) {
+                            c64* partials, T* rc, int rows, hipStream_t s) {
   int opts[3];
   gs_rows_options<T>(opts);
   if (rows == opts[0])
     rbgs_march_launch<T, (sizeof(T) == 4 ? 8 : 4), NSW>(xin, b, xout, ec, omega, N, d, c, nb,
-                                                        active, reverse, partials, s);
+                                                        active, reverse, partials, rc, s);
   else if (rows == opts[1])
     rbgs_march_launch<T, (sizeof(T) == 4 ? 16 : 8), NSW>(xin, b, xout, ec, omega, N, d, c, nb,
-                                                         active, reverse, partials, s);
+                                                         active, reverse, partials, rc, s);
   else if (rows == opts[2])
     rbgs_march_launch<T, (sizeof(T) == 4 ? 32 : 16), NSW>(xin, b, xout, ec, omega, N, d, c, nb,
-                                                          active, reverse, partials, s);
+                                                          active, reverse, partials, rc, s);
   else
     throw Error(MLMC_EINVAL, "unsupported rows per Gauss-Seidel segment");
 }
@@ -800,11 +844,11 @@ void poisson_rbgs_fused(const T* xin, const T* b, T* xout, const T* ec, double o
   if (N >= 64) {
     if (sweeps == 2 && (N & 1)) throw Error(MLMC_EINVAL, "two fused sweeps need an even side");
     if (sweeps == 2)
-      rbgs_march_rows<T, 2>(xin, b, xout, ec, omega, N, d, c, nb, active, reverse, partials, rows,
-                            s);
+      rbgs_march_rows<T, 2>(xin, b, xout, ec, omega, N, d, c, nb, active, reverse, partials,
+                            (T*)nullptr, rows, s);
     else
-      rbgs_march_rows<T, 1>(xin, b, xout, ec, omega, N, d, c, nb, active, reverse, partials, rows,
-                            s);
+      rbgs_march_rows<T, 1>(xin, b, xout, ec, omega, N, d, c, nb, active, reverse, partials,
+                            (T*)nullptr, rows, s);
   } else {
     if (sweeps != 1) throw Error(MLMC_EINVAL, "two fused sweeps need a side of at least 64");
     const int nbx = (N + GTX - 1) / GTX, nby = (N + GTY - 1) / GTY;
@@ -812,6 +856,14 @@ void poisson_rbgs_fused(const T* xin, const T* b, T* xout, const T* ec, double o
                        xout, ec, (R_t<T>)(0.5 * omega), N, (R_t<T>)(1.0 / d), (R_t<T>)c,
                        reverse ? 1 : 0, nbx, nby, nb, active, partials, timing_log());
   }
+}
+
+template <typename T>
+void poisson_rbgs_restrict(const T* xin, const T* b, T* xout, T* rc, int N, double d, double c,
+                           int nb, const int* active, int rows, hipStream_t s) {
+  if (N < 64 || (N & 1)) throw Error(MLMC_EINVAL, "fused pre-pass needs an even side >= 64");
+  rbgs_march_rows<T, 2>(xin, b, xout, (const T*)nullptr, 0.0, N, d, c, nb, active, false,
+                        (c64*)nullptr, rc, rows, s);
 }
 
 template <typename T>
@@ -843,6 +895,8 @@ void agg2d_prolong(const T* ec, T* x, int N, double omega, double beta, int nb,
   template void poisson_rbgs_fused<T>(const T*, const T*, T*, const T*, double, int,       \
                                       double, double, int, const int*, bool, c64*, int,    \
                                       int, hipStream_t);                                   \
+  template void poisson_rbgs_restrict<T>(const T*, const T*, T*, T*, int, double, double,  \
+                                         int, const int*, int, hipStream_t);               \
   template void poisson_residual_restrict<T>(const T*, const T*, T*, int, double, double,  \
                                              int, const int*, hipStream_t);                \
   template void agg2d_restrict<T>(const T*, T*, int, int, const int*, hipStream_t);        \

@@ -56,7 +56,7 @@ def test_null_arguments_are_rejected():
     assert lib.mlmc_nn_apply(None, 1, None, None) == -1
     assert lib.mlmc_nn_loss_grad(None, 1, None, None, None, None) == -1
     assert lib.mlmc_batch_sample(None, 0, 1, None, 0, 1, 1, None, None) == -1
-    assert lib.mlmc_smooth(None, 1, 1, 2, 0, None, None) == -1
+    assert lib.mlmc_smooth(None, 1, 1, 2, 0, None, None, None) == -1
 
 
 class MockSampler:

@@ -72,6 +72,34 @@ def test_fused_two_sweep_pass_equals_two_passes_bitwise(precision):
 
 
 @pytest.mark.parametrize("precision", ["fp32_ir64", "fp64"])
+def test_pre_pass_restricted_residual(precision):
+    # the V-cycle's last pre-smoothing pass writes R (b - A x) with the swept x;
+    # two fused sweeps do it in one pass, one sweep with the stand-alone kernel
+    est = _poisson(200, 3, precision)
+    A, P = hierarchy.poisson_hierarchy(200, 3)
+    rng = np.random.default_rng(11)
+    for level in (1, 2):
+        n = est.level_size(level)
+        Bh = rng.standard_normal((NRHS, n))
+        B, X = to_dev(Bh), to_dev(rng.standard_normal((NRHS, n)))
+        for sw in (1, 2, 3):
+            xr, rc = est.smooth(level, B, X, sw, restrict=True)
+            assert np.array_equal(from_dev(xr), from_dev(est.smooth(level, B, X, sw)))
+            x, r = from_dev(xr), from_dev(rc)
+            Al, Pl = A[level - 1], P[level - 1]
+            for k in range(NRHS):
+                ref = Pl.T @ (Bh[k] - Al @ x[k])
+                bound = np.max(Pl.T @ (np.abs(Bh[k]) + abs(Al) @ np.abs(x[k])))
+                assert np.max(np.abs(r[k] - ref)) <= TOL[precision] * bound, (level, sw, k)
+        # the fused pass and the stand-alone kernel form the same values
+        x1 = est.smooth(level, B, X, 1)
+        xa, rca = est.smooth(level, B, x1, 1, restrict=True)
+        xb, rcb = est.smooth(level, B, X, 2, restrict=True)
+        assert np.array_equal(from_dev(xa), from_dev(xb))
+        assert np.array_equal(from_dev(rca), from_dev(rcb)), level
+
+
+@pytest.mark.parametrize("precision", ["fp32_ir64", "fp64"])
 def test_wilson_and_block_sweeps_match_oracle(precision):
     require_gpu()
     import paper_2108_11281_amd as m
@@ -112,3 +140,5 @@ def test_smooth_rejects_bad_arguments():
     B = torch.zeros((2, est.level_size(1)), dtype=torch.float64, device="cuda")
     with pytest.raises(m.MLMCError):
         est.smooth(1, B, B, -1)
+    with pytest.raises(m.MLMCError):   # the restricted residual follows a forward pass
+        est.smooth(1, B, B, 2, reverse=True, restrict=True)
