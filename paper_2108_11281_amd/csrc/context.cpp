@@ -573,7 +573,8 @@ void Context::vcycle(int l, const T* b, T* x, int nb, const int* act, c64* rz_pa
   const T* u = nullptr;  // current iterate (nullptr = 0)
   bool restricted = false;
   for (int i = 0, pass = 0; i < pre; ++pass) {
-    const int sw = std::min(per, pre - i);
+    // an odd remainder goes first, so the last pass is a full one
+    const int sw = (pre - i) % per ? (pre - i) % per : per;
     T* out = (pass % 2 == 0) ? tmp : x;
     const T* in = u;
     if (sw == 2 && i + sw == pre) {
@@ -640,10 +641,7 @@ int Context::vcycle_partials(int l, bool* fused) const {
   enum { kNull, kTmp, kX };
   const int per = sweeps_per_pass(l);
   int u = kNull;
-  for (int i = 0, pass = 0; i < opt_.nu_pre; ++pass) {
-    u = (pass % 2 == 0) ? kTmp : kX;
-    i += std::min(per, opt_.nu_pre - i);
-  }
+  for (int pass = 0; pass < (opt_.nu_pre + per - 1) / per; ++pass) u = (pass % 2 == 0) ? kTmp : kX;
   const int passes = (opt_.nu_post + per - 1) / per;
   int last_sw = 1;
   for (int i = 0, pass = 0; i < opt_.nu_post; ++pass) {
