@@ -134,6 +134,11 @@ __global__ __launch_bounds__(kThreads) void k_wilson_gs(const T* __restrict__ b,
 }
 
 // ---- 5-point block stencils (coarse operators) ------------------------------
+// Lanes along right-hand sides: a wave serves one site at a time for 64
+// consecutive columns.  The site, hence every stencil block, inverted
+// diagonal block and aggregate basis row it reads, is uniform over the wave
+// (read through the scalar data cache, shared by the 64 columns); each lane
+// reads its own column's DOF contiguous values of a site.
 __device__ __forceinline__ int nbr_site(int S, int d, int Nc) {
   const int Y = S / Nc, X = S - Y * Nc;
   switch (d) {
@@ -145,135 +150,172 @@ __device__ __forceinline__ int nbr_site(int S, int d, int Nc) {
   }
 }
 
-// r = b - A x (b == nullptr: r = A x); one thread per (site, column) computing
-// its DOF outputs; blocks [site][5][DOF][DOF]
-template <int DOF, typename Tb, typename T, typename Tr>
+// the wave's index within the grid (uniform: every lane computes the same)
+__device__ __forceinline__ int wave_index() {
+  return __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6)));
+}
+
+// acc -= B x (DOF x DOF block, row-major) or acc += B x
+template <int DOF, typename T>
+__device__ __forceinline__ void block_mac(T* acc, const T* __restrict__ blk, const T* xv,
+                                          bool subtract) {
+#pragma unroll
+  for (int i = 0; i < DOF; ++i) {
+    T v = zero_of(T());
+#pragma unroll
+    for (int j = 0; j < DOF; ++j) v += blk[i * DOF + j] * xv[j];
+    acc[i] = subtract ? acc[i] - v : acc[i] + v;
+  }
+}
+
+// r = b - A x (b == nullptr: r = A x); blocks [site][5][DOF][DOF].  A wave
+// serves sites wave*spw .. wave*spw+spw-1; with partials, each lane writes its
+// column's share of |r|^2 (or conj(x)^T r) over those sites at
+// partials[column * waves + wave].
+template <int DOF, typename Tb, typename T, typename Tr, bool PART>
 __global__ __launch_bounds__(kThreads) void k_bsr_residual(const Tb* __restrict__ b,
                                                            const T* __restrict__ x,
                                                            Tr* __restrict__ r,
                                                            const T* __restrict__ B, int Nc,
-                                                           const int* active, c64* partials) {
-  __shared__ double red[16];
-  const int k = blockIdx.y;
-  if (active && !active[k]) return;
+                                                           int spw, int nb, const int* active,
+                                                           c64* partials) {
+  const int lane = threadIdx.x & 63;
+  const int wave = wave_index();
+  const int k = blockIdx.y * 64 + lane;
   const int ns = Nc * Nc;
-  const int S = blockIdx.x * kThreads + threadIdx.x;
-  const int64_t off = (int64_t)k * DOF * ns;
+  if (!PART) spw = 1;
+  const int waves = (ns + spw - 1) / spw;
+  if (wave >= waves) return;
+  const bool on = k < nb && (!active || active[k]);
+  const int64_t off = (int64_t)(on ? k : 0) * ns * DOF;
   double dre = 0.0, dim = 0.0;
-  if (S < ns) {
+  for (int q = 0; q < spw; ++q) {
+    const int S = wave * spw + q;
+    if (S >= ns) break;
+    if (!on) continue;
     T acc[DOF];
 #pragma unroll
     for (int i = 0; i < DOF; ++i) acc[i] = zero_of(T());
+#pragma unroll
     for (int d = 0; d < 5; ++d) {
       const int t = nbr_site(S, d, Nc);
-      const T* blk = B + ((int64_t)S * 5 + d) * DOF * DOF;
       T xv[DOF];
 #pragma unroll
       for (int j = 0; j < DOF; ++j) xv[j] = x[off + (int64_t)t * DOF + j];
-#pragma unroll
-      for (int i = 0; i < DOF; ++i)
-#pragma unroll
-        for (int j = 0; j < DOF; ++j) acc[i] += blk[i * DOF + j] * xv[j];
+      block_mac<DOF>(acc, B + ((int64_t)S * 5 + d) * DOF * DOF, xv, false);
     }
 #pragma unroll
     for (int i = 0; i < DOF; ++i) {
       T v = acc[i];
       if (b) {
         v = convert<T, Tb>(b[off + (int64_t)S * DOF + i]) - v;
-        cdot_acc(dre, dim, v, v);
-      } else {
+        if (PART) cdot_acc(dre, dim, v, v);
+      } else if (PART) {
         cdot_acc(dre, dim, x[off + (int64_t)S * DOF + i], v);
       }
       r[off + (int64_t)S * DOF + i] = convert<Tr, T>(v);
     }
   }
-  if (partials) {
-    block_sum2<kThreads>(dre, dim, red);
-    if (threadIdx.x == 0) partials[(int64_t)k * gridDim.x + blockIdx.x] = {dre, dim};
-  }
+  if (PART && k < nb) partials[(int64_t)k * waves + wave] = {dre, dim};
 }
 
-// one colour of a red-black block Gauss-Seidel sweep:
-// x_S = Dinv_S (b_S - sum_{d != self} B[S][d] x_nbr)
+// one colour of a red-black block Gauss-Seidel sweep, in place:
+// x_S = Dinv_S (b_S - sum_{d != self} B[S][d] x_nbr); a wave per site of the
+// colour (Nc even: the j-th site of colour c in row Y is X = 2j + ((c+Y) & 1))
 template <int DOF, typename T>
 __global__ __launch_bounds__(kThreads) void k_bsr_gs(const T* __restrict__ b, T* __restrict__ x,
                                                      const T* __restrict__ B,
                                                      const T* __restrict__ Dinv, int Nc,
-                                                     int colour, int zero_nbrs,
+                                                     int colour, int zero_nbrs, int nb,
                                                      const int* active, int* tlog) {
-  const int k = blockIdx.y;
-  if (tlog && blockIdx.x == 0 && threadIdx.x == 0) tlog[k] = active ? active[k] : 1;
-  if (active && !active[k]) return;
-  const int ns = Nc * Nc;
-  const int S = blockIdx.x * kThreads + threadIdx.x;
-  if (S >= ns) return;
-  const int Y = S / Nc, X = S - Y * Nc;
-  if (((X + Y) & 1) != colour) return;
-  const int64_t off = (int64_t)k * DOF * ns;
+  const int lane = threadIdx.x & 63;
+  const int k = blockIdx.y * 64 + lane;
+  if (tlog && blockIdx.x == 0 && threadIdx.x < 64 && k < nb) tlog[k] = active ? active[k] : 1;
+  const int t = wave_index();
+  const int hc = Nc >> 1;
+  if (t >= Nc * hc) return;
+  if (k >= nb || (active && !active[k])) return;
+  const int Y = t / hc, j = t - Y * hc;
+  const int S = Y * Nc + 2 * j + ((colour + Y) & 1);
+  const int64_t off = (int64_t)k * Nc * Nc * DOF;
   T rhs[DOF];
 #pragma unroll
   for (int i = 0; i < DOF; ++i) rhs[i] = b[off + (int64_t)S * DOF + i];
   if (!zero_nbrs) {
+#pragma unroll
     for (int d = 1; d < 5; ++d) {
-      const int t = nbr_site(S, d, Nc);
-      const T* blk = B + ((int64_t)S * 5 + d) * DOF * DOF;
+      const int tn = nbr_site(S, d, Nc);
       T xv[DOF];
 #pragma unroll
-      for (int j = 0; j < DOF; ++j) xv[j] = x[off + (int64_t)t * DOF + j];
-#pragma unroll
-      for (int i = 0; i < DOF; ++i)
-#pragma unroll
-        for (int j = 0; j < DOF; ++j) rhs[i] -= blk[i * DOF + j] * xv[j];
+      for (int jj = 0; jj < DOF; ++jj) xv[jj] = x[off + (int64_t)tn * DOF + jj];
+      block_mac<DOF>(rhs, B + ((int64_t)S * 5 + d) * DOF * DOF, xv, true);
     }
   }
-  const T* di = Dinv + (int64_t)S * DOF * DOF;
+  T out[DOF];
 #pragma unroll
-  for (int i = 0; i < DOF; ++i) {
-    T v = zero_of(T());
+  for (int i = 0; i < DOF; ++i) out[i] = zero_of(T());
+  block_mac<DOF>(out, Dinv + (int64_t)S * DOF * DOF, rhs, false);
 #pragma unroll
-    for (int j = 0; j < DOF; ++j) v += di[i * DOF + j] * rhs[j];
-    x[off + (int64_t)S * DOF + i] = v;
-  }
+  for (int i = 0; i < DOF; ++i) x[off + (int64_t)S * DOF + i] = out[i];
 }
 
 // ---- aggregation transfers --------------------------------------------------
 // fine lattice Nf x Nf with dofF unknowns per site, aggregates of blk x blk
-// sites, dofC coarse unknowns per coarse site; q[i][j] (i fine unknown).
+// sites, DOFC coarse unknowns per coarse site; q[i][j] (i fine unknown).
 
-// xc = P^H x ; one thread per (coarse site, column)
+// xc = P^H x: a workgroup per (coarse site, 64 columns); its waves take the
+// aggregate's rows in turn (the rows of q are uniform over a wave, each lane
+// walks its column's blk*dofF contiguous fine values of a row), and the
+// waves' shares are added in a fixed order through LDS
 template <int DOFC, typename T>
 __global__ __launch_bounds__(kThreads) void k_agg_restrict(const T* __restrict__ x,
                                                            T* __restrict__ xc,
                                                            const T* __restrict__ q, int Nf,
-                                                           int dofF, int blk,
+                                                           int dofF, int blk, int nb,
                                                            const int* active) {
-  const int k = blockIdx.y;
-  if (active && !active[k]) return;
+  constexpr int W = kThreads / 64;
+  __shared__ T part[W - 1][DOFC][64];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int k = blockIdx.y * 64 + lane;
   const int Nc = Nf / blk, nsc = Nc * Nc;
-  const int S = blockIdx.x * kThreads + threadIdx.x;
-  if (S >= nsc) return;
+  const int S = blockIdx.x;
+  const bool on = k < nb && (!active || active[k]);
   const int Y = S / Nc, X = S - Y * Nc;
   const int64_t nf = (int64_t)Nf * Nf * dofF;
-  const T* xk = x + (int64_t)k * nf;
+  const T* xk = x + (int64_t)(on ? k : 0) * nf;
+  const int wr = blk * dofF;  // contiguous fine unknowns per aggregate row
   T acc[DOFC];
 #pragma unroll
   for (int j = 0; j < DOFC; ++j) acc[j] = zero_of(T());
-  for (int yy = 0; yy < blk; ++yy)
-    for (int xx = 0; xx < blk; ++xx) {
-      const int s = (Y * blk + yy) * Nf + (X * blk + xx);
-      for (int a = 0; a < dofF; ++a) {
-        const int64_t i = (int64_t)s * dofF + a;
-        const T v = xk[i];
-        const T* qi = q + i * DOFC;
+  if (on) {
+    for (int yy = w; yy < blk; yy += W) {
+      const int64_t i0 = ((int64_t)(Y * blk + yy) * Nf + X * blk) * dofF;
+      for (int a = 0; a < wr; ++a) {
+        const T v = xk[i0 + a];
+        const T* qi = q + (i0 + a) * DOFC;
 #pragma unroll
         for (int j = 0; j < DOFC; ++j) acc[j] += cmul_conj(qi[j], v);
       }
     }
+  }
+  if (w > 0) {
 #pragma unroll
-  for (int j = 0; j < DOFC; ++j) xc[(int64_t)k * nsc * DOFC + (int64_t)S * DOFC + j] = acc[j];
+    for (int j = 0; j < DOFC; ++j) part[w - 1][j][lane] = acc[j];
+  }
+  __syncthreads();
+  if (w == 0 && on) {
+#pragma unroll
+    for (int v = 0; v < W - 1; ++v)
+#pragma unroll
+      for (int j = 0; j < DOFC; ++j) acc[j] += part[v][j][lane];
+#pragma unroll
+    for (int j = 0; j < DOFC; ++j) xc[(int64_t)k * nsc * DOFC + (int64_t)S * DOFC + j] = acc[j];
+  }
 }
 
-// x = beta * x + omega * P xc ; one thread per (fine unknown, column)
+// x = beta * x + omega * P xc ; one thread per (fine unknown, column): loads
+// of x and of the rows of q are coalesced along the fine unknowns
 template <int DOFC, typename T>
 __global__ __launch_bounds__(kThreads) void k_agg_prolong(const T* __restrict__ xc, T* __restrict__ x,
                                                           const T* __restrict__ q, int Nf,
@@ -530,10 +572,23 @@ inline dim3 grid_sites(int64_t sites, int nb) {
   return dim3((unsigned)((sites + kThreads - 1) / kThreads), (unsigned)nb);
 }
 
+// a wave per item, 64 columns per wave: blocks of kThreads/64 waves
+inline dim3 grid_waves(int64_t items, int nb) {
+  constexpr int wpb = kThreads / 64;
+  return dim3((unsigned)((items + wpb - 1) / wpb), (unsigned)((nb + 63) / 64));
+}
+
+// sites per wave of the block-stencil residual: enough that at most
+// kMaxPartials waves (partial sums per column) cover the level
+inline int bsr_spw(int Nc) { return (Nc * Nc + kMaxPartials - 1) / kMaxPartials; }
+
 }  // namespace
 
 int wilson_residual_blocks(int N) { return (N * N + kThreads - 1) / kThreads; }
-int bsr_residual_blocks(int Nc) { return (Nc * Nc + kThreads - 1) / kThreads; }
+int bsr_residual_blocks(int Nc) {
+  const int spw = bsr_spw(Nc);
+  return (Nc * Nc + spw - 1) / spw;
+}
 
 template <typename Tb, typename T, typename Tr>
 void wilson_residual(const Tb* b, const T* x, Tr* r, const T* U, int N, double diag, int nb,
@@ -566,29 +621,39 @@ void wilson_rbgs(const T* b, T* x, const T* U, int N, double diag, int nb, const
 template <typename Tb, typename T, typename Tr>
 void bsr_residual(const Tb* b, const T* x, Tr* r, const T* B, int Nc, int dof, int nb,
                   const int* active, c64* partials, hipStream_t s) {
-  const dim3 g = grid_sites((int64_t)Nc * Nc, nb);
-  BSR_DISPATCH(dof, hipLaunchKernelGGL((k_bsr_residual<D, Tb, T, Tr>), g, dim3(kThreads), 0, s,
-                                        b, x, r, B, Nc, active, partials));
+  // without partial sums, one site per wave (most parallel); with them, the
+  // site count per wave that bsr_residual_blocks reports
+  const int spw = partials ? bsr_spw(Nc) : 1;
+  const dim3 g = grid_waves(((int64_t)Nc * Nc + spw - 1) / spw, nb);
+  if (partials) {
+    BSR_DISPATCH(dof, hipLaunchKernelGGL((k_bsr_residual<D, Tb, T, Tr, true>), g, dim3(kThreads),
+                                          0, s, b, x, r, B, Nc, spw, nb, active, partials));
+  } else {
+    BSR_DISPATCH(dof, hipLaunchKernelGGL((k_bsr_residual<D, Tb, T, Tr, false>), g,
+                                          dim3(kThreads), 0, s, b, x, r, B, Nc, spw, nb, active,
+                                          partials));
+  }
 }
 
 template <typename T>
 void bsr_rbgs(const T* b, T* x, const T* B, const T* Dinv, int Nc, int dof, int nb,
               const int* active, bool zero_init, bool reverse, hipStream_t s) {
-  const dim3 g = grid_sites((int64_t)Nc * Nc, nb);
+  if (Nc & 1) throw Error(MLMC_EINVAL, "red-black block sweep needs an even lattice side");
+  const dim3 g = grid_waves((int64_t)Nc * Nc / 2, nb);
   const int first = reverse ? 1 : 0;
   BSR_DISPATCH(dof, MLMC_LAUNCH((k_bsr_gs<D, T>), g, dim3(kThreads), 0, s, b, x, B, Dinv, Nc,
-                                 first, zero_init ? 1 : 0, active, timing_log()));
+                                 first, zero_init ? 1 : 0, nb, active, timing_log()));
   BSR_DISPATCH(dof, MLMC_LAUNCH((k_bsr_gs<D, T>), g, dim3(kThreads), 0, s, b, x, B, Dinv, Nc,
-                                 1 - first, 0, active, (int*)nullptr));
+                                 1 - first, 0, nb, active, (int*)nullptr));
 }
 
 template <typename T>
 void agg_restrict(const T* x, T* xc, const T* q, int Nf, int dofF, int blk, int dofC, int nb,
                   const int* active, hipStream_t s) {
   const int Nc = Nf / blk;
-  const dim3 g = grid_sites((int64_t)Nc * Nc, nb);
+  const dim3 g((unsigned)(Nc * Nc), (unsigned)((nb + 63) / 64));
   BSR_DISPATCH(dofC, hipLaunchKernelGGL((k_agg_restrict<D, T>), g, dim3(kThreads), 0, s, x, xc,
-                                         q, Nf, dofF, blk, active));
+                                         q, Nf, dofF, blk, nb, active));
 }
 
 template <typename T>
