@@ -424,7 +424,8 @@ def run_batch(args, m, torch):
               "workers": args.workers, "solve_tol": 1e-10}
     contract(args, round(value, 1), "solves/s", True, ms_per_step, "f32+f64ir",
              "synthetic (log-normal face coefficients sigma=1, Rademacher probes)", config,
-             hbm_roofline("k_vc_gs<float> (sweep of both colours)", tot, args.timing_stride),
+             hbm_roofline("3D red-black sweep: k_vc_march<float> (both colours, one pass)", tot,
+                          args.timing_stride),
              cpu, per_problem=per_problem, setup_s=round(setup_s, 2), compare=compare)
 
 

@@ -349,8 +349,10 @@ void Context::build_varcoef(const double* k) {
 // Autotuner of the 3D stencil kernels: per smoothed level, time one full
 // red-black sweep over all nb columns with 1, 2, 4 and 8 right-hand sides per
 // thread (the results are identical; only the load reuse of the couplings and
-// the parallelism differ) and keep the fastest.  Runs once at setup on the
-// library's own work vectors.
+// the parallelism differ) and keep the fastest; on even sides up to 128 the
+// sweeps run as the fused out-of-place pass instead, whose columns per wave
+// (1 or 2) are tuned the same way.
+// Runs once at setup on the library's own work vectors.
 void Context::tune_varcoef() {
   const bool fp32 = opt_.precision == MLMC_FP32_IR64;
   hipEvent_t a = event(), b = event();
@@ -380,6 +382,34 @@ void Context::tune_varcoef() {
       }
     }
     L.cols = best_cols;
+    // the fused out-of-place sweep (even sides up to 128) replaces the in-place
+    // pair of colour launches; tune its columns per wave
+    L.mcols = 0;
+    if (varcoef_march_ok(L.side)) {
+      float mbest = 1e30f;
+      for (int cols : {1, 2}) {
+        float ms = 0.f;
+        for (int rep = 0; rep < 3; ++rep) {
+          MLMC_HIP(hipEventRecord(a, s_));
+          if (fp32)
+            varcoef_rbgs_march<float>(rep == 0 ? nullptr : w32_.x, w32_.r, w32_.z, nullptr, 0.0,
+                                      L.kl32, L.dg32, L.side, nb_, cols, nullptr, false, s_);
+          else
+            varcoef_rbgs_march<double>(rep == 0 ? nullptr : w64_.x, w64_.r, w64_.z, nullptr,
+                                       0.0, L.kl64, L.dg64, L.side, nb_, cols, nullptr, false,
+                                       s_);
+          MLMC_HIP(hipEventRecord(b, s_));
+          MLMC_HIP(hipEventSynchronize(b));
+          float t = 0.f;
+          MLMC_HIP(hipEventElapsedTime(&t, a, b));
+          if (rep > 0) ms += t;
+        }
+        if (ms < mbest) {
+          mbest = ms;
+          L.mcols = cols;
+        }
+      }
+    }
   }
   ev_pool_.push_back(a);
   ev_pool_.push_back(b);
@@ -505,6 +535,52 @@ void Context::vcycle_vc(int l, const T* b, T* x, int nb, const int* act, c64* rz
   const double en = (double)sizeof(T) * (double)n;
   if (l == Ls_) {
     dense_apply<T>(w.ainvT, b, x, (int)n, nb, act, s_);
+  } else if (lv_[l - 1].mcols > 0) {
+    // fused out-of-place sweeps, ping-ponging between the level's scratch
+    // buffer and x; the coarse correction is folded into the first post-sweep
+    const Level& L = lv_[l - 1];
+    const T* kf = vc_faces<T>(l);
+    const T* dg = vc_diag<T>(l);
+    const int pre = opt_.nu_pre, post = opt_.nu_post;
+    T* tmp = w.vt[l - 1];
+    const T* u = nullptr;  // current iterate (nullptr = 0)
+    for (int i = 0; i < pre; ++i) {
+      T* out = (i % 2 == 0) ? tmp : x;
+      const T* in = u;
+      timed<T>(kTimGs, en * ((in ? 3.0 : 2.0) + 4.0 / (double)nb), act, nb, [&] {
+        varcoef_rbgs_march<T>(in, b, out, nullptr, 0.0, kf, dg, L.side, nb, L.mcols, act, false,
+                              s_);
+      });
+      u = out;
+    }
+    T* bc = w.vb[l];
+    T* ec = w.vx[l];
+    if (u == nullptr)
+      op_restrict<T>(l, b, bc, nb, act);
+    else
+      timed<T>(kTimResRestrict, en * (2.0 + 0.125 + 4.0 / (double)nb), act, nb,
+               [&] { op_res_restrict<T>(l, b, u, bc, nb, act); });
+    vcycle_vc<T>(l + 1, bc, ec, nb, act, nullptr);
+    if (post == 0) {
+      if (u != nullptr && u != x) vec_copy<T>(u, x, n, nb, act, s_);
+      timed<T>(kTimProlong, en * (2.0 + 0.125), act, nb, [&] {
+        varcoef_prolong<T>(ec, x, L.side, omega_, u == nullptr ? 0.0 : 1.0, nb, act, s_);
+      });
+    }
+    for (int i = 0; i < post; ++i) {
+      const int left = post - 1 - i;
+      T* out = (left % 2 == 0) ? x : tmp;
+      if (out == u) out = (out == x) ? tmp : x;  // never sweep in place
+      const T* in = u;
+      const T* corr = (i == 0) ? ec : nullptr;
+      timed<T>(kTimGs,
+               en * ((in ? 3.0 : 2.0) + (corr ? 0.125 : 0.0) + 4.0 / (double)nb), act, nb, [&] {
+                 varcoef_rbgs_march<T>(in, b, out, corr, omega_, kf, dg, L.side, nb, L.mcols,
+                                       act, true, s_);
+               });
+      u = out;
+    }
+    if (post > 0 && u != x) vec_copy<T>(u, x, n, nb, act, s_);
   } else {
     const Level& L = lv_[l - 1];
     const T* kf = vc_faces<T>(l);
@@ -1251,9 +1327,16 @@ void Context::smooth_fp64(int level, int nrhs, int sweeps, bool reverse, const d
         cop_smooth<C>(level, reinterpret_cast<const C*>(bt), reinterpret_cast<C*>(xa), nrhs,
                       nullptr, false, reverse);
     } else if (varcoef_) {
-      for (int i = 0; i < sweeps; ++i)
-        varcoef_rbgs<T>(bt, xa, vc_faces<T>(level), vc_diag<T>(level), L.side, nrhs, L.cols,
-                        nullptr, false, reverse, nullptr, 0.0, s_);
+      for (int i = 0; i < sweeps; ++i) {
+        if (L.mcols > 0) {
+          varcoef_rbgs_march<T>(xa, bt, xb, nullptr, 0.0, vc_faces<T>(level), vc_diag<T>(level),
+                                L.side, nrhs, L.mcols, nullptr, reverse, s_);
+          std::swap(xa, xb);
+        } else {
+          varcoef_rbgs<T>(bt, xa, vc_faces<T>(level), vc_diag<T>(level), L.side, nrhs, L.cols,
+                          nullptr, false, reverse, nullptr, 0.0, s_);
+        }
+      }
     } else {
       const int per = sweeps_per_pass(level);
       for (int i = 0; i < sweeps;) {

@@ -43,6 +43,7 @@ struct Level {
   double *kf64 = nullptr, *dg64 = nullptr, *kl64 = nullptr;
   float *dg32 = nullptr, *kl32 = nullptr;
   int cols = 4;  // right-hand sides per thread of the stencil kernels (autotuned)
+  int mcols = 0;  // right-hand sides per wave of the fused 3D sweep (0: in-place sweeps)
   // POISSON2D: rows per segment of the fused sweep, FP32 and FP64 (autotuned)
   int gs_rows[2] = {16, 8};
 };

@@ -209,6 +209,16 @@ template <typename T>
 void varcoef_rbgs(const T* b, T* x, const typename Traits<T>::real* kl,
                   const typename Traits<T>::real* dg, int N, int nb, int cols, const int* active,
                   bool zero_init, bool reverse, const T* ec, double omega, hipStream_t s);
+// one red-black sweep fused into one out-of-place pass (both colours; reverse:
+// black first): xout = S(xin + omega/sqrt(8) P ec ; b); xin == nullptr means 0,
+// ec nullable; `cols` in {1, 2, 4}: right-hand sides per lane.  For even sides
+// up to 128 (varcoef_march_ok).
+bool varcoef_march_ok(int N);
+template <typename T>
+void varcoef_rbgs_march(const T* xin, const T* b, T* xout, const T* ec, double omega,
+                        const typename Traits<T>::real* kl, const typename Traits<T>::real* dg,
+                        int N, int nb, int cols, const int* active, bool reverse,
+                        hipStream_t s);
 // xc = R (b - A x) when residual, else xc = R x; R the orthonormal 2x2x2
 // aggregation (entries 1/sqrt(8))
 template <typename T>

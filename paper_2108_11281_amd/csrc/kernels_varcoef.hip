@@ -8,6 +8,7 @@
 // 1/sqrt(8)) the Galerkin operator is again of this form: a coarse face is 1/8
 // of the sum of the four fine faces it covers and the shift is kept.
 #include "kernels.h"
+#include "lanes.h"
 
 namespace mlmc {
 namespace {
@@ -370,6 +371,259 @@ inline dim3 grid_cells(int64_t n, int nb) {
   return dim3((unsigned)((n + kThreads - 1) / kThreads), (unsigned)nb);
 }
 
+// ---------------------------------------------------------------------------
+// One fused red-black sweep, out of place, marching along z:
+//   x_out = S(x_in + ws * P ec ; b)      (ws = omega / sqrt(8); F = first colour)
+// A workgroup of 8 waves owns TY = 8 RPW - 2 consecutive rows y0 .. y0+TY-1
+// of COLS right-hand sides and walks a segment of SZ planes.  It holds the
+// rows y0-1 .. y0+TY as lane pairs (x = 2*pl, 2*pl+1), RPW rows per wave of
+// 64/RPW lanes each (2*64/RPW >= N, so a row needs no x halo; a wave's rows
+// have one parity), with five planes of each row in registers.  At step p a
+// wave loads plane p+2, updates the first colour on plane p and the second
+// colour on plane p-1, and writes plane p-1 (owned rows).  In a row both
+// updates of a step hit the same element of the pair, and the y-neighbours each
+// needs are one value per lane of the rows above and below: the rows swap them
+// through LDS (double-buffered, one barrier per step); the two outermost rows
+// also load the row beyond them.  Cells outside the grid read as zero, so no
+// coupling ever multiplies a value that was not written.
+// ---------------------------------------------------------------------------
+// couplings of a row pair on one plane; d0, d1 hold 1 / diagonal
+template <typename R>
+struct PlaneK {
+  R kx0, kx1, kyl0, kyl1, kyu0, kyu1, kz0, kz1, d0, d1;
+};
+
+constexpr int kMarchWaves = 8;
+
+template <typename T, int COLS, int RPW, bool HX, bool HE, int F>
+__global__ __launch_bounds__(kMarchWaves * 64) void k_vc_march(
+    const T* __restrict__ xin, const T* __restrict__ b, T* __restrict__ xout,
+    const T* __restrict__ ec, R_t<T> ws, const R_t<T>* __restrict__ kl,
+    const R_t<T>* __restrict__ dg, int N, int SZ, int nb, const int* active, int* tlog) {
+  using R = R_t<T>;
+  constexpr int RW = kMarchWaves * RPW;  // rows held, incl. one halo row each side
+  constexpr int TY = RW - 2;             // rows owned
+  constexpr int LPR = 64 / RPW;          // lanes (pairs) per row
+  __shared__ T xa[2][RW][COLS][LPR];  // a row's second-colour cell at plane p (x_in)
+  __shared__ T xb[2][RW][COLS][LPR];  // a row's first-colour cell at plane p-1 (updated)
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int col0 = blockIdx.y * COLS;
+  if (tlog && blockIdx.x == 0 && blockIdx.z == 0 && threadIdx.x < COLS &&
+      col0 + (int)threadIdx.x < nb)
+    tlog[col0 + threadIdx.x] = active ? active[col0 + threadIdx.x] : 1;
+  bool con[COLS];
+  bool any = false;
+#pragma unroll
+  for (int c = 0; c < COLS; ++c) {
+    con[c] = col_on(active, col0 + c, nb);
+    any = any || con[c];
+  }
+  if (!any) return;  // uniform over the workgroup
+  const int seg = lane / LPR, pl = lane - seg * LPR;
+  // row slot: wave w holds slots of parity w & 1 (so e below is wave-uniform)
+  const int r = (w & 1) + 2 * (seg + RPW * (w >> 1));
+  const int y = blockIdx.x * TY - 1 + r;
+  // a row of the wave's parity (uniform; y has this parity in every lane)
+  const int ybase = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * TY - 1 + (w & 1)));
+  const int x0 = 2 * pl;
+  const bool xok = x0 < N;
+  const bool row_in = y >= 0 && y < N;
+  const bool cell_ok = row_in && xok;
+  const bool edge = (r == 0) || (r == RW - 1);
+  const int ye = (r == 0) ? y - 1 : y + 1;  // the outermost rows' outer neighbour row
+  const bool eok = edge && ye >= 0 && ye < N && xok;
+  const bool inner = r >= 1 && r <= TY;
+  const bool owner = inner && row_in;
+  const int NN = N * N;
+  const int64_t n = (int64_t)NN * N, stride = n + NN;
+  const int Nc = N >> 1;
+  const T zero = zero_of(T());
+
+  // column base pointers (inactive columns point at column 0 and are never stored)
+  const T* xc[COLS];
+  const T* bc[COLS];
+  const T* ecc[COLS];
+  T* xo[COLS];
+#pragma unroll
+  for (int c = 0; c < COLS; ++c) {
+    const int64_t col = con[c] ? col0 + c : 0;
+    xc[c] = xin + (HX ? col * n : 0);
+    bc[c] = b + col * n;
+    ecc[c] = ec + (HE ? col * (int64_t)Nc * Nc * Nc : 0);
+    xo[c] = xout + col * n;
+  }
+  auto ld2 = [&](const T* base, int64_t i, bool ok, T& v0, T& v1) {
+    v0 = ok ? base[i] : zero;
+    v1 = ok ? base[i + 1] : zero;
+  };
+  auto ldk2 = [&](const R* base, int64_t i, bool ok, R& v0, R& v1) {
+    v0 = ok ? base[i] : (R)0;
+    v1 = ok ? base[i + 1] : (R)0;
+  };
+  // x_in of row yy, plane z (with the folded correction)
+  auto load_x = [&](int c, int yy, int z, bool ok, T& v0, T& v1) {
+    v0 = zero;
+    v1 = zero;
+    const int64_t i = ((int64_t)z * N + yy) * N + x0;
+    if constexpr (HX) ld2(xc[c], i, ok, v0, v1);
+    if constexpr (HE) {
+      const T e = ok ? ecc[c][((int64_t)(z >> 1) * Nc + (yy >> 1)) * Nc + (x0 >> 1)] : zero;
+      v0 += ws * e;
+      v1 += ws * e;
+    }
+  };
+  auto load_k = [&](int z, bool ok, PlaneK<R>& k) {
+    const int64_t i = ((int64_t)z * N + y) * N + x0;
+    ldk2(kl, i, ok, k.kx0, k.kx1);
+    ldk2(kl + stride, i, ok, k.kyl0, k.kyl1);
+    ldk2(kl + stride, i + N, ok, k.kyu0, k.kyu1);
+    ldk2(kl + 2 * stride, i, ok, k.kz0, k.kz1);
+    ldk2(dg, i, ok, k.d0, k.d1);
+    // reciprocals of the diagonal, shared by the columns (1 outside the grid)
+    k.d0 = ok ? (R)1 / k.d0 : (R)1;
+    k.d1 = ok ? (R)1 / k.d1 : (R)1;
+  };
+
+  // planes p+2 (m, loads in flight), p+1 (n), p (c), p-1 (p), p-2 (q) of the
+  // wave's row, per column
+  T Xm0[COLS], Xm1[COLS], Xn0[COLS], Xn1[COLS], Xc0[COLS], Xc1[COLS], Xp0[COLS], Xp1[COLS],
+      Xq0[COLS], Xq1[COLS];
+  // edge waves: outer row, planes p+2, p+1, p
+  T Em0[COLS], Em1[COLS], En0[COLS], En1[COLS], Ec0[COLS], Ec1[COLS];
+  T Bm0[COLS], Bm1[COLS], Bn0[COLS], Bn1[COLS], Bc0[COLS], Bc1[COLS], Bp0[COLS], Bp1[COLS];
+  PlaneK<R> Km, Kn, Kc, Kp;
+#pragma unroll
+  for (int c = 0; c < COLS; ++c) {
+    Xn0[c] = Xn1[c] = Xc0[c] = Xc1[c] = Xp0[c] = Xp1[c] = Xq0[c] = Xq1[c] = zero;
+    En0[c] = En1[c] = Ec0[c] = Ec1[c] = zero;
+    Bn0[c] = Bn1[c] = Bc0[c] = Bc1[c] = Bp0[c] = Bp1[c] = zero;
+  }
+  Kn = PlaneK<R>{};
+  Kc = PlaneK<R>{};
+  Kp = PlaneK<R>{};
+  auto load_plane = [&](int z) {
+    const bool zok = z < N;
+#pragma unroll
+    for (int c = 0; c < COLS; ++c) {
+      load_x(c, y, z, cell_ok && zok, Xm0[c], Xm1[c]);
+      if (edge) load_x(c, ye, z, eok && zok, Em0[c], Em1[c]);
+      else Em0[c] = Em1[c] = zero;
+      const int64_t i = ((int64_t)z * N + y) * N + x0;
+      ld2(bc[c], i, cell_ok && zok, Bm0[c], Bm1[c]);
+    }
+    load_k(z, cell_ok && zok, Km);
+  };
+  auto shift = [&]() {
+#pragma unroll
+    for (int c = 0; c < COLS; ++c) {
+      Xq0[c] = Xp0[c]; Xq1[c] = Xp1[c];
+      Xp0[c] = Xc0[c]; Xp1[c] = Xc1[c];
+      Xc0[c] = Xn0[c]; Xc1[c] = Xn1[c];
+      Xn0[c] = Xm0[c]; Xn1[c] = Xm1[c];
+      Ec0[c] = En0[c]; Ec1[c] = En1[c];
+      En0[c] = Em0[c]; En1[c] = Em1[c];
+      Bp0[c] = Bc0[c]; Bp1[c] = Bc1[c];
+      Bc0[c] = Bn0[c]; Bc1[c] = Bn1[c];
+      Bn0[c] = Bm0[c]; Bn1[c] = Bm1[c];
+    }
+    Kp = Kc;
+    Kc = Kn;
+    Kn = Km;
+  };
+  // this workgroup's planes zs .. ze-1 (segments of SZ): the march starts one
+  // plane early (first colour only there) and reads one plane more below it
+  const int zs = blockIdx.z * SZ;
+  const int ze = zs + SZ < N ? zs + SZ : N;
+  const int p0 = zs > 0 ? zs - 1 : 0;
+  const int pe = ze < N ? ze : N;
+  // prologue: planes p0-1 (zero below the grid), p0 and p0+1 into the c, n and
+  // m slots, so that the first shift of the loop sees p0-1, p0, p0+1
+  if (p0 >= 1) {
+    load_plane(p0 - 1);
+    shift();
+  }
+  load_plane(p0);
+  shift();
+  load_plane(p0 + 1);
+  for (int p = p0; p <= pe; ++p) {
+    // shift planes: p+1 moves into the "next" slot; plane p+2 is loaded a step
+    // ahead of its first use
+    shift();
+    load_plane(p + 2);  // zeros beyond the last plane
+    // element of the pair updated in this step (first colour on plane p,
+    // second colour on plane p-1): e = (F + y + p) & 1, uniform per wave
+    const int e = (F + ybase + p) & 1;
+    const int buf = p & 1;
+    // publish: this row's second-colour cell of plane p (x_in, element 1-e) and
+    // first-colour cell of plane p-1 (updated last step, element 1-e)
+#pragma unroll
+    for (int c = 0; c < COLS; ++c) {
+      xa[buf][r][c][pl] = e ? Xc0[c] : Xc1[c];
+      xb[buf][r][c][pl] = e ? Xp0[c] : Xp1[c];
+    }
+    __syncthreads();
+    // first colour on plane p, element e (all rows of the workgroup)
+    if (p < N) {
+#pragma unroll
+      for (int c = 0; c < COLS; ++c) {
+        const T alo = xa[buf][r > 0 ? r - 1 : 0][c][pl];
+        const T ahi = xa[buf][r < RW - 1 ? r + 1 : RW - 1][c][pl];
+        const T ev = e ? Ec1[c] : Ec0[c];
+        const T ylo = r > 0 ? alo : ev;
+        const T yhi = r < RW - 1 ? ahi : ev;
+        T v;
+        if (e == 0) {
+          const T sh = wave_shr1(Xc1[c]);
+          const T l = pl > 0 ? sh : zero;
+          v = Bc0[c] + Kc.kx0 * l + Kc.kx1 * Xc1[c] + Kc.kyl0 * ylo + Kc.kyu0 * yhi +
+              Kc.kz0 * Xp0[c] + Kn.kz0 * Xn0[c];
+          Xc0[c] = cell_ok ? Kc.d0 * v : zero;
+        } else {
+          const T sh = wave_shl1(Xc0[c]);
+          const R shk = wave_shl1(Kc.kx0);
+          const T rr = x0 + 2 < N ? sh : zero;
+          const R kr = x0 + 2 < N ? shk : (R)0;
+          v = Bc1[c] + Kc.kx1 * Xc0[c] + kr * rr + Kc.kyl1 * ylo + Kc.kyu1 * yhi +
+              Kc.kz1 * Xp1[c] + Kn.kz1 * Xn1[c];
+          Xc1[c] = cell_ok ? Kc.d1 * v : zero;
+        }
+      }
+    }
+    // second colour on plane p-1, element e (rows y0 .. y0+TY-1), and output
+    if (p - 1 >= zs) {
+      const int z = p - 1;
+#pragma unroll
+      for (int c = 0; c < COLS; ++c) {
+        const T ylo = xb[buf][r > 0 ? r - 1 : 0][c][pl];
+        const T yhi = xb[buf][r < RW - 1 ? r + 1 : RW - 1][c][pl];
+        {
+          if (e == 0) {
+            const T sh = wave_shr1(Xp1[c]);
+            const T l = pl > 0 ? sh : zero;
+            const T v = Bp0[c] + Kp.kx0 * l + Kp.kx1 * Xp1[c] + Kp.kyl0 * ylo + Kp.kyu0 * yhi +
+                        Kp.kz0 * Xq0[c] + Kc.kz0 * Xc0[c];
+            if (inner) Xp0[c] = cell_ok ? Kp.d0 * v : zero;
+          } else {
+            const T sh = wave_shl1(Xp0[c]);
+            const R shk = wave_shl1(Kp.kx0);
+            const T rr = x0 + 2 < N ? sh : zero;
+            const R kr = x0 + 2 < N ? shk : (R)0;
+            const T v = Bp1[c] + Kp.kx1 * Xp0[c] + kr * rr + Kp.kyl1 * ylo + Kp.kyu1 * yhi +
+                        Kp.kz1 * Xq1[c] + Kc.kz1 * Xc1[c];
+            if (inner) Xp1[c] = cell_ok ? Kp.d1 * v : zero;
+          }
+          if (owner && xok && con[c]) {
+            const int64_t i = ((int64_t)z * N + y) * N + x0;
+            xo[c][i] = Xp0[c];
+            xo[c][i + 1] = Xp1[c];
+          }
+        }
+      }
+    }
+  }
+}
+
 }  // namespace
 
 int varcoef_blocks(int N) { return (N * N * N + kThreads - 1) / kThreads; }
@@ -407,6 +661,62 @@ void varcoef_rbgs(const T* b, T* x, const typename Traits<T>::real* kl,
     MLMC_LAUNCH((k_vc_gs<T, C>), g, dim3(kThreads), 0, s, b, x, kl, dg, N, 1 - first, 0, nb,
                 active, (const T*)nullptr, (R)0, (int*)nullptr);
   });
+}
+
+template <typename T, int RPW>
+static void vc_march_launch(const T* xin, const T* b, T* xout, const T* ec, double omega,
+                            const typename Traits<T>::real* kl,
+                            const typename Traits<T>::real* dg, int N, int nb, int cols,
+                            const int* active, bool reverse, hipStream_t s) {
+  using R = typename Traits<T>::real;
+  constexpr int TY = kMarchWaves * RPW - 2;
+  const R ws = (R)(omega * 0.35355339059327373);  // omega / sqrt(8)
+  const T* xp = xin ? xin : b;  // placeholders (never read) for the templated forms
+  const T* ep = ec ? ec : b;
+  const dim3 blk(kMarchWaves * 64);
+  const int first = reverse ? 1 : 0;
+  // z segments of SZ planes: more workgroups in flight than one march per
+  // column of rows, at the price of 3 extra planes read per segment
+  const int SZ = N >= 32 ? 16 : N;
+#define VC_MARCH(HX, HE)                                                                      \
+  VC_COLS_DISPATCH(cols, {                                                                    \
+    const dim3 g((unsigned)((N + TY - 1) / TY), (unsigned)((nb + C - 1) / C),                 \
+                 (unsigned)((N + SZ - 1) / SZ));                                              \
+    if (first)                                                                                \
+      MLMC_LAUNCH((k_vc_march<T, C, RPW, HX, HE, 1>), g, blk, 0, s, xp, b, xout, ep, ws, kl,   \
+                  dg, N, SZ, nb, active, timing_log());                                       \
+    else                                                                                      \
+      MLMC_LAUNCH((k_vc_march<T, C, RPW, HX, HE, 0>), g, blk, 0, s, xp, b, xout, ep, ws, kl,   \
+                  dg, N, SZ, nb, active, timing_log());                                       \
+  })
+  if (xin && ec) {
+    VC_MARCH(true, true);
+  } else if (xin) {
+    VC_MARCH(true, false);
+  } else if (ec) {
+    VC_MARCH(false, true);
+  } else {
+    VC_MARCH(false, false);
+  }
+#undef VC_MARCH
+}
+
+bool varcoef_march_ok(int N) { return N <= 128 && N % 2 == 0; }
+
+template <typename T>
+void varcoef_rbgs_march(const T* xin, const T* b, T* xout, const T* ec, double omega,
+                        const typename Traits<T>::real* kl, const typename Traits<T>::real* dg,
+                        int N, int nb, int cols, const int* active, bool reverse,
+                        hipStream_t s) {
+  if (!varcoef_march_ok(N)) throw Error(MLMC_EINVAL, "fused 3D sweep needs an even side <= 128");
+  if (cols == 8) throw Error(MLMC_EINVAL, "fused 3D sweep takes 1, 2 or 4 columns per wave");
+  // rows per wave: as many as fit 64 lane pairs (a row of N needs N/2 lanes)
+  if (N <= 32)
+    vc_march_launch<T, 4>(xin, b, xout, ec, omega, kl, dg, N, nb, cols, active, reverse, s);
+  else if (N <= 64)
+    vc_march_launch<T, 2>(xin, b, xout, ec, omega, kl, dg, N, nb, cols, active, reverse, s);
+  else
+    vc_march_launch<T, 1>(xin, b, xout, ec, omega, kl, dg, N, nb, cols, active, reverse, s);
 }
 
 template <typename T>
@@ -456,6 +766,9 @@ void varcoef_dense(const double* k, const double* diag, int N, double* aug, hipS
 #define VC_INST(T)                                                                          \
   template void varcoef_rbgs<T>(const T*, T*, const T*, const T*, int, int, int, const int*,  \
                                 bool, bool, const T*, double, hipStream_t);                  \
+  template void varcoef_rbgs_march<T>(const T*, const T*, T*, const T*, double, const T*,    \
+                                      const T*, int, int, int, const int*, bool,             \
+                                      hipStream_t);                                          \
   template void varcoef_restrict<T>(const T*, const T*, T*, const T*, const T*, int, bool,    \
                                     int, int, const int*, hipStream_t);                      \
   template void varcoef_prolong<T>(const T*, T*, int, double, double, int, const int*,        \

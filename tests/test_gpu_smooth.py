@@ -116,11 +116,14 @@ def test_wilson_and_block_sweeps_match_oracle(precision):
            tol=1e-9)
 
 
+# N = 20: the fused 3D sweep marches all planes (20, 10); N = 40: z segments of
+# 16 planes (the last ragged) and 5 tiles of 8 rows on level 1
 @pytest.mark.parametrize("precision", ["fp32_ir64", "fp64"])
-def test_varcoef_sweeps_match_oracle(precision):
+@pytest.mark.parametrize("N", [20, 40])
+def test_varcoef_sweeps_match_oracle(precision, N):
     require_gpu()
     import paper_2108_11281_amd as m
-    N, L = 20, 3
+    L = 3
     faces = varcoef_faces(N, seed=1000)
     est = m.TraceEstimator("varcoef3d", N, L, L, shift=1e-3, field=faces, nb=8,
                            precision=precision)
