@@ -5,7 +5,10 @@ runs in the HIP library libmlmc.so; this module only marshals arguments,
 passes torch's device memory and stream, and converts results.  If the library
 has not been built, importing the binding raises: there is no CPU fallback.
 """
+import atexit
 import ctypes
+import sys
+import weakref
 
 import numpy as np
 
@@ -90,6 +93,17 @@ def use_torch_allocator(enable=True):
     _check(lib().mlmc_set_allocator(_alloc_refs[0], _alloc_refs[1], None))
 
 
+_live = weakref.WeakSet()  # open estimators, closed at interpreter exit
+_exit_hook = []
+
+
+def _close_live():
+    # runs while the interpreter, torch and the allocator thunks are intact, so
+    # a context freeing its device memory through the thunks is still safe
+    for est in list(_live):
+        est.close()
+
+
 class TraceEstimator:
     """One operator, its hierarchy and the solvers on the current torch device.
 
@@ -145,6 +159,12 @@ class TraceEstimator:
         _check(self._lib.mlmc_setup(ctypes.byref(op), ctypes.byref(h), ctypes.byref(o),
                                     ctypes.c_void_p(stream.cuda_stream),
                                     ctypes.byref(self._ctx)), None)
+        if not _exit_hook:
+            # registered after torch is imported, so it runs before torch's own
+            # exit handlers
+            atexit.register(_close_live)
+            _exit_hook.append(True)
+        _live.add(self)
         self.kind = kind
         self.is_complex = kind == "wilson2d"
         self.levels_solver = h.levels_solver
@@ -158,6 +178,10 @@ class TraceEstimator:
             self._ctx = ctypes.c_void_p()
 
     def __del__(self):
+        # during interpreter shutdown the allocator callbacks may already be
+        # gone; the exit handler has closed every estimator by then
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

@@ -43,6 +43,7 @@ struct Level {
   double *kf64 = nullptr, *dg64 = nullptr, *kl64 = nullptr;
   float *dg32 = nullptr, *kl32 = nullptr;
   int cols = 4;  // right-hand sides per thread of the stencil kernels (autotuned)
+  int bsr_form[2] = {0, 0};  // block-stencil kernel form, complex64 / complex128 (autotuned)
   int mcols = 0;  // right-hand sides per wave of the fused 3D sweep (0: in-place sweeps)
   // POISSON2D: rows per segment of the fused sweep, FP32 and FP64 (autotuned)
   int gs_rows[2] = {16, 8};
@@ -134,7 +135,14 @@ class Context {
   void build_poisson();
   void build_varcoef(const double* k);
   void tune_varcoef();
+  void tune_bsr();
   void tune_poisson();
+  // block-stencil kernel form for a call over nb columns: the tuned form, but
+  // the thread-per-site form for narrow batches (a wave-uniform wave serves 64
+  // columns, so fewer than 32 would leave most of its lanes idle)
+  template <typename T> int bsr_form(const Level& L, int nb) const {
+    return nb >= 32 ? L.bsr_form[sizeof(T) == sizeof(c64) ? 1 : 0] : 0;
+  }
   // red-black sweeps fused into one pass of the Poisson smoother on level l
   int sweeps_per_pass(int l) const { return lv_[l - 1].side >= 64 ? 2 : 1; }
   template <typename T> int gs_rows(int l) const {

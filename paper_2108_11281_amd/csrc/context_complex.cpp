@@ -90,7 +90,7 @@ void Context::build_wilson(const double* theta) {
       if (F.wilson)
         wilson_rbgs<c64>(zero, V, F.U64, F.side, diag, nv, nullptr, false, false, s_);
       else
-        bsr_rbgs<c64>(zero, V, F.B64, F.Dinv64, F.side, F.dof, nv, nullptr, false, false, s_);
+        bsr_rbgs<c64>(zero, V, F.B64, F.Dinv64, F.side, F.dof, nv, nullptr, false, false, 0, s_);
     }
     F.q64 = dalloc_n<c64>(F.n * nv);
     F.q32 = dalloc_n<c32>(F.n * nv);
@@ -192,6 +192,41 @@ void Context::build_wilson(const double* theta) {
   }
   MLMC_HIP(hipStreamSynchronize(s_));
   MLMC_HIP(hipGetLastError());
+  tune_bsr();
+}
+
+// Autotuner of the block-stencil kernels: per smoothed block level and per
+// precision the V-cycle runs (complex64 in the refined mode, complex128 in the
+// plain FP64 mode), time one red-black sweep over all nb columns in both
+// kernel forms (best of 3 after a warm-up) and keep the faster.  The two forms
+// agree up to rounding; runs once at setup on the level's work vectors.
+void Context::tune_bsr() {
+  hipEvent_t a = event(), b = event();
+  auto time_form = [&](auto tag, Level& L, int l, int form) {
+    using T = decltype(tag);
+    Work<T>& w = work<T>();
+    float best = 1e30f;
+    for (int rep = 0; rep < 4; ++rep) {
+      MLMC_HIP(hipEventRecord(a, s_));
+      bsr_rbgs<T>(w.vb[l - 1], w.vx[l - 1], blocks<T>(l), dinv<T>(l), L.side, L.dof, nb_,
+                  nullptr, rep == 0, false, form, s_);
+      MLMC_HIP(hipEventRecord(b, s_));
+      MLMC_HIP(hipEventSynchronize(b));
+      float t = 0.f;
+      MLMC_HIP(hipEventElapsedTime(&t, a, b));
+      if (rep > 0) best = std::min(best, t);
+    }
+    return best;
+  };
+  for (int l = 2; l < Ls_; ++l) {
+    Level& L = lv_[l - 1];
+    if (opt_.precision == MLMC_FP32_IR64)
+      L.bsr_form[0] = time_form(c32(), L, l, 1) < time_form(c32(), L, l, 0) ? 1 : 0;
+    else
+      L.bsr_form[1] = time_form(c64(), L, l, 1) < time_form(c64(), L, l, 0) ? 1 : 0;
+  }
+  ev_pool_.push_back(a);
+  ev_pool_.push_back(b);
 }
 
 // ---------------------------------------------------------------------------
@@ -205,7 +240,8 @@ void Context::cop_residual(int l, const Tb* b, const T* x, Tr* r, int nb, const 
     wilson_residual<Tb, T, Tr>(b, x, r, links<T>(l), L.side, op_.mass + 2.0, nb, act, partials,
                                s_);
   else
-    bsr_residual<Tb, T, Tr>(b, x, r, blocks<T>(l), L.side, L.dof, nb, act, partials, s_);
+    bsr_residual<Tb, T, Tr>(b, x, r, blocks<T>(l), L.side, L.dof, nb, act, partials,
+                            bsr_form<T>(L, nb), s_);
 }
 
 template <typename T>
@@ -227,7 +263,7 @@ void Context::cop_smooth(int l, const T* b, T* x, int nb, const int* act, bool z
     const double bytes = es * (zero_init ? 2.5 : 3.0) + 6.0 * L.dof * es / (double)nb;
     timed<T>(kTimGs, bytes, act, nb, [&] {
       bsr_rbgs<T>(b, x, blocks<T>(l), dinv<T>(l), L.side, L.dof, nb, act, zero_init, reverse,
-                  s_);
+                  bsr_form<T>(L, nb), s_);
     });
   }
 }

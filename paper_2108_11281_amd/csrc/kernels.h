@@ -281,12 +281,15 @@ void wilson_residual(const Tb* b, const T* x, Tr* r, const T* U, int N, double d
 template <typename T>
 void wilson_rbgs(const T* b, T* x, const T* U, int N, double diag, int nb, const int* active,
                  bool zero_init, bool reverse, hipStream_t s);
+// block stencils: form 0 = a thread per (site, column), 1 = a wave per site
+// and 64 columns with the site's blocks read wave-uniformly (a tuning choice;
+// results agree up to rounding); partial sums always come from form 0
 template <typename Tb, typename T, typename Tr>
 void bsr_residual(const Tb* b, const T* x, Tr* r, const T* B, int Nc, int dof, int nb,
-                  const int* active, c64* partials, hipStream_t s);
+                  const int* active, c64* partials, int form, hipStream_t s);
 template <typename T>
 void bsr_rbgs(const T* b, T* x, const T* B, const T* Dinv, int Nc, int dof, int nb,
-              const int* active, bool zero_init, bool reverse, hipStream_t s);
+              const int* active, bool zero_init, bool reverse, int form, hipStream_t s);
 template <typename T>
 void agg_restrict(const T* x, T* xc, const T* q, int Nf, int dofF, int blk, int dofC, int nb,
                   const int* active, hipStream_t s);

@@ -168,55 +168,39 @@ __device__ __forceinline__ void block_mac(T* acc, const T* __restrict__ blk, con
   }
 }
 
-// r = b - A x (b == nullptr: r = A x); blocks [site][5][DOF][DOF].  A wave
-// serves sites wave*spw .. wave*spw+spw-1; with partials, each lane writes its
-// column's share of |r|^2 (or conj(x)^T r) over those sites at
-// partials[column * waves + wave].
-template <int DOF, typename Tb, typename T, typename Tr, bool PART>
+// r = b - A x (b == nullptr: r = A x); blocks [site][5][DOF][DOF]; a wave per
+// site and 64 columns
+template <int DOF, typename Tb, typename T, typename Tr>
 __global__ __launch_bounds__(kThreads) void k_bsr_residual(const Tb* __restrict__ b,
                                                            const T* __restrict__ x,
                                                            Tr* __restrict__ r,
                                                            const T* __restrict__ B, int Nc,
-                                                           int spw, int nb, const int* active,
-                                                           c64* partials) {
+                                                           int nb, const int* active) {
   const int lane = threadIdx.x & 63;
-  const int wave = wave_index();
+  const int S = wave_index();
   const int k = blockIdx.y * 64 + lane;
   const int ns = Nc * Nc;
-  if (!PART) spw = 1;
-  const int waves = (ns + spw - 1) / spw;
-  if (wave >= waves) return;
-  const bool on = k < nb && (!active || active[k]);
-  const int64_t off = (int64_t)(on ? k : 0) * ns * DOF;
-  double dre = 0.0, dim = 0.0;
-  for (int q = 0; q < spw; ++q) {
-    const int S = wave * spw + q;
-    if (S >= ns) break;
-    if (!on) continue;
-    T acc[DOF];
+  if (S >= ns) return;
+  if (k >= nb || (active && !active[k])) return;
+  const int64_t off = (int64_t)k * ns * DOF;
+  T acc[DOF];
 #pragma unroll
-    for (int i = 0; i < DOF; ++i) acc[i] = zero_of(T());
+  for (int i = 0; i < DOF; ++i) acc[i] = zero_of(T());
+  // one neighbour's values live at a time
+#pragma unroll 1
+  for (int d = 0; d < 5; ++d) {
+    const int t = nbr_site(S, d, Nc);
+    T xv[DOF];
 #pragma unroll
-    for (int d = 0; d < 5; ++d) {
-      const int t = nbr_site(S, d, Nc);
-      T xv[DOF];
-#pragma unroll
-      for (int j = 0; j < DOF; ++j) xv[j] = x[off + (int64_t)t * DOF + j];
-      block_mac<DOF>(acc, B + ((int64_t)S * 5 + d) * DOF * DOF, xv, false);
-    }
-#pragma unroll
-    for (int i = 0; i < DOF; ++i) {
-      T v = acc[i];
-      if (b) {
-        v = convert<T, Tb>(b[off + (int64_t)S * DOF + i]) - v;
-        if (PART) cdot_acc(dre, dim, v, v);
-      } else if (PART) {
-        cdot_acc(dre, dim, x[off + (int64_t)S * DOF + i], v);
-      }
-      r[off + (int64_t)S * DOF + i] = convert<Tr, T>(v);
-    }
+    for (int j = 0; j < DOF; ++j) xv[j] = x[off + (int64_t)t * DOF + j];
+    block_mac<DOF>(acc, B + ((int64_t)S * 5 + d) * DOF * DOF, xv, false);
   }
-  if (PART && k < nb) partials[(int64_t)k * waves + wave] = {dre, dim};
+#pragma unroll
+  for (int i = 0; i < DOF; ++i) {
+    T v = acc[i];
+    if (b) v = convert<T, Tb>(b[off + (int64_t)S * DOF + i]) - v;
+    r[off + (int64_t)S * DOF + i] = convert<Tr, T>(v);
+  }
 }
 
 // one colour of a red-black block Gauss-Seidel sweep, in place:
@@ -257,6 +241,102 @@ __global__ __launch_bounds__(kThreads) void k_bsr_gs(const T* __restrict__ b, T*
   block_mac<DOF>(out, Dinv + (int64_t)S * DOF * DOF, rhs, false);
 #pragma unroll
   for (int i = 0; i < DOF; ++i) x[off + (int64_t)S * DOF + i] = out[i];
+}
+
+// Thread-per-site forms: a thread serves one (site, column) and reads the
+// site's blocks itself.  Which of the two forms is faster depends on the
+// precision and the lattice (with complex128 blocks on large lattices the
+// wave-uniform form waits on its scalar loads); the setup-time autotuner
+// chooses per level.
+// r = b - A x (b == nullptr: r = A x); one thread per (site, column) computing
+// its DOF outputs; partial sums per column and block of kThreads sites
+template <int DOF, typename Tb, typename T, typename Tr>
+__global__ __launch_bounds__(kThreads) void k_bsr_residual_sites(const Tb* __restrict__ b,
+                                                           const T* __restrict__ x,
+                                                           Tr* __restrict__ r,
+                                                           const T* __restrict__ B, int Nc,
+                                                           const int* active, c64* partials) {
+  __shared__ double red[16];
+  const int k = blockIdx.y;
+  if (active && !active[k]) return;
+  const int ns = Nc * Nc;
+  const int S = blockIdx.x * kThreads + threadIdx.x;
+  const int64_t off = (int64_t)k * DOF * ns;
+  double dre = 0.0, dim = 0.0;
+  if (S < ns) {
+    T acc[DOF];
+#pragma unroll
+    for (int i = 0; i < DOF; ++i) acc[i] = zero_of(T());
+    for (int d = 0; d < 5; ++d) {
+      const int t = nbr_site(S, d, Nc);
+      const T* blk = B + ((int64_t)S * 5 + d) * DOF * DOF;
+      T xv[DOF];
+#pragma unroll
+      for (int j = 0; j < DOF; ++j) xv[j] = x[off + (int64_t)t * DOF + j];
+#pragma unroll
+      for (int i = 0; i < DOF; ++i)
+#pragma unroll
+        for (int j = 0; j < DOF; ++j) acc[i] += blk[i * DOF + j] * xv[j];
+    }
+#pragma unroll
+    for (int i = 0; i < DOF; ++i) {
+      T v = acc[i];
+      if (b) {
+        v = convert<T, Tb>(b[off + (int64_t)S * DOF + i]) - v;
+        cdot_acc(dre, dim, v, v);
+      } else {
+        cdot_acc(dre, dim, x[off + (int64_t)S * DOF + i], v);
+      }
+      r[off + (int64_t)S * DOF + i] = convert<Tr, T>(v);
+    }
+  }
+  if (partials) {
+    block_sum2<kThreads>(dre, dim, red);
+    if (threadIdx.x == 0) partials[(int64_t)k * gridDim.x + blockIdx.x] = {dre, dim};
+  }
+}
+
+// one colour of a red-black block Gauss-Seidel sweep:
+// x_S = Dinv_S (b_S - sum_{d != self} B[S][d] x_nbr)
+template <int DOF, typename T>
+__global__ __launch_bounds__(kThreads) void k_bsr_gs_sites(const T* __restrict__ b, T* __restrict__ x,
+                                                     const T* __restrict__ B,
+                                                     const T* __restrict__ Dinv, int Nc,
+                                                     int colour, int zero_nbrs,
+                                                     const int* active, int* tlog) {
+  const int k = blockIdx.y;
+  if (tlog && blockIdx.x == 0 && threadIdx.x == 0) tlog[k] = active ? active[k] : 1;
+  if (active && !active[k]) return;
+  const int ns = Nc * Nc;
+  const int S = blockIdx.x * kThreads + threadIdx.x;
+  if (S >= ns) return;
+  const int Y = S / Nc, X = S - Y * Nc;
+  if (((X + Y) & 1) != colour) return;
+  const int64_t off = (int64_t)k * DOF * ns;
+  T rhs[DOF];
+#pragma unroll
+  for (int i = 0; i < DOF; ++i) rhs[i] = b[off + (int64_t)S * DOF + i];
+  if (!zero_nbrs) {
+    for (int d = 1; d < 5; ++d) {
+      const int t = nbr_site(S, d, Nc);
+      const T* blk = B + ((int64_t)S * 5 + d) * DOF * DOF;
+      T xv[DOF];
+#pragma unroll
+      for (int j = 0; j < DOF; ++j) xv[j] = x[off + (int64_t)t * DOF + j];
+#pragma unroll
+      for (int i = 0; i < DOF; ++i)
+#pragma unroll
+        for (int j = 0; j < DOF; ++j) rhs[i] -= blk[i * DOF + j] * xv[j];
+    }
+  }
+  const T* di = Dinv + (int64_t)S * DOF * DOF;
+#pragma unroll
+  for (int i = 0; i < DOF; ++i) {
+    T v = zero_of(T());
+#pragma unroll
+    for (int j = 0; j < DOF; ++j) v += di[i * DOF + j] * rhs[j];
+    x[off + (int64_t)S * DOF + i] = v;
+  }
 }
 
 // ---- aggregation transfers --------------------------------------------------
@@ -578,17 +658,10 @@ inline dim3 grid_waves(int64_t items, int nb) {
   return dim3((unsigned)((items + wpb - 1) / wpb), (unsigned)((nb + 63) / 64));
 }
 
-// sites per wave of the block-stencil residual: enough that at most
-// kMaxPartials waves (partial sums per column) cover the level
-inline int bsr_spw(int Nc) { return (Nc * Nc + kMaxPartials - 1) / kMaxPartials; }
-
 }  // namespace
 
 int wilson_residual_blocks(int N) { return (N * N + kThreads - 1) / kThreads; }
-int bsr_residual_blocks(int Nc) {
-  const int spw = bsr_spw(Nc);
-  return (Nc * Nc + spw - 1) / spw;
-}
+int bsr_residual_blocks(int Nc) { return (Nc * Nc + kThreads - 1) / kThreads; }
 
 template <typename Tb, typename T, typename Tr>
 void wilson_residual(const Tb* b, const T* x, Tr* r, const T* U, int N, double diag, int nb,
@@ -620,31 +693,37 @@ void wilson_rbgs(const T* b, T* x, const T* U, int N, double diag, int nb, const
 
 template <typename Tb, typename T, typename Tr>
 void bsr_residual(const Tb* b, const T* x, Tr* r, const T* B, int Nc, int dof, int nb,
-                  const int* active, c64* partials, hipStream_t s) {
-  // without partial sums, one site per wave (most parallel); with them, the
-  // site count per wave that bsr_residual_blocks reports
-  const int spw = partials ? bsr_spw(Nc) : 1;
-  const dim3 g = grid_waves(((int64_t)Nc * Nc + spw - 1) / spw, nb);
-  if (partials) {
-    BSR_DISPATCH(dof, hipLaunchKernelGGL((k_bsr_residual<D, Tb, T, Tr, true>), g, dim3(kThreads),
-                                          0, s, b, x, r, B, Nc, spw, nb, active, partials));
+                  const int* active, c64* partials, int form, hipStream_t s) {
+  // partial sums (the outer residual) come from the thread-per-site form
+  if (form == 1 && !partials) {
+    const dim3 g = grid_waves((int64_t)Nc * Nc, nb);
+    BSR_DISPATCH(dof, hipLaunchKernelGGL((k_bsr_residual<D, Tb, T, Tr>), g, dim3(kThreads), 0, s,
+                                          b, x, r, B, Nc, nb, active));
   } else {
-    BSR_DISPATCH(dof, hipLaunchKernelGGL((k_bsr_residual<D, Tb, T, Tr, false>), g,
-                                          dim3(kThreads), 0, s, b, x, r, B, Nc, spw, nb, active,
-                                          partials));
+    const dim3 g = grid_sites((int64_t)Nc * Nc, nb);
+    BSR_DISPATCH(dof, hipLaunchKernelGGL((k_bsr_residual_sites<D, Tb, T, Tr>), g, dim3(kThreads),
+                                          0, s, b, x, r, B, Nc, active, partials));
   }
 }
 
 template <typename T>
 void bsr_rbgs(const T* b, T* x, const T* B, const T* Dinv, int Nc, int dof, int nb,
-              const int* active, bool zero_init, bool reverse, hipStream_t s) {
+              const int* active, bool zero_init, bool reverse, int form, hipStream_t s) {
   if (Nc & 1) throw Error(MLMC_EINVAL, "red-black block sweep needs an even lattice side");
-  const dim3 g = grid_waves((int64_t)Nc * Nc / 2, nb);
   const int first = reverse ? 1 : 0;
-  BSR_DISPATCH(dof, MLMC_LAUNCH((k_bsr_gs<D, T>), g, dim3(kThreads), 0, s, b, x, B, Dinv, Nc,
-                                 first, zero_init ? 1 : 0, nb, active, timing_log()));
-  BSR_DISPATCH(dof, MLMC_LAUNCH((k_bsr_gs<D, T>), g, dim3(kThreads), 0, s, b, x, B, Dinv, Nc,
-                                 1 - first, 0, nb, active, (int*)nullptr));
+  if (form == 1) {
+    const dim3 g = grid_waves((int64_t)Nc * Nc / 2, nb);
+    BSR_DISPATCH(dof, MLMC_LAUNCH((k_bsr_gs<D, T>), g, dim3(kThreads), 0, s, b, x, B, Dinv, Nc,
+                                   first, zero_init ? 1 : 0, nb, active, timing_log()));
+    BSR_DISPATCH(dof, MLMC_LAUNCH((k_bsr_gs<D, T>), g, dim3(kThreads), 0, s, b, x, B, Dinv, Nc,
+                                   1 - first, 0, nb, active, (int*)nullptr));
+  } else {
+    const dim3 g = grid_sites((int64_t)Nc * Nc, nb);
+    BSR_DISPATCH(dof, MLMC_LAUNCH((k_bsr_gs_sites<D, T>), g, dim3(kThreads), 0, s, b, x, B, Dinv,
+                                   Nc, first, zero_init ? 1 : 0, active, timing_log()));
+    BSR_DISPATCH(dof, MLMC_LAUNCH((k_bsr_gs_sites<D, T>), g, dim3(kThreads), 0, s, b, x, B, Dinv,
+                                   Nc, 1 - first, 0, active, (int*)nullptr));
+  }
 }
 
 template <typename T>
@@ -711,15 +790,15 @@ template void wilson_rbgs<c32>(const c32*, c32*, const c32*, int, double, int, c
 template void wilson_rbgs<c64>(const c64*, c64*, const c64*, int, double, int, const int*, bool,
                                bool, hipStream_t);
 template void bsr_residual<c64, c64, c64>(const c64*, const c64*, c64*, const c64*, int, int,
-                                          int, const int*, c64*, hipStream_t);
+                                          int, const int*, c64*, int, hipStream_t);
 template void bsr_residual<c64, c64, c32>(const c64*, const c64*, c32*, const c64*, int, int,
-                                          int, const int*, c64*, hipStream_t);
+                                          int, const int*, c64*, int, hipStream_t);
 template void bsr_residual<c32, c32, c32>(const c32*, const c32*, c32*, const c32*, int, int,
-                                          int, const int*, c64*, hipStream_t);
+                                          int, const int*, c64*, int, hipStream_t);
 template void bsr_rbgs<c32>(const c32*, c32*, const c32*, const c32*, int, int, int, const int*,
-                            bool, bool, hipStream_t);
+                            bool, bool, int, hipStream_t);
 template void bsr_rbgs<c64>(const c64*, c64*, const c64*, const c64*, int, int, int, const int*,
-                            bool, bool, hipStream_t);
+                            bool, bool, int, hipStream_t);
 template void agg_restrict<c32>(const c32*, c32*, const c32*, int, int, int, int, int,
                                 const int*, hipStream_t);
 template void agg_restrict<c64>(const c64*, c64*, const c64*, int, int, int, int, int,

@@ -133,3 +133,15 @@ def test_invalid_setup_is_rejected():
         m.TraceEstimator("poisson2d", 30, 4, 4)   # 30 -> 15 -> not divisible
     with pytest.raises(m.MLMCError):
         m.TraceEstimator("poisson2d", 64, 3, 4)   # L > L_s
+
+
+def test_exit_handler_closes_live_estimators():
+    # estimators still open at interpreter exit are closed by an exit handler
+    # (while the allocator callbacks are intact), not by __del__ during
+    # finalization
+    import paper_2108_11281_amd as m
+    est = _est(64, 3)
+    assert est in m._live and est._ctx
+    m._close_live()
+    assert not est._ctx
+    est.close()  # idempotent
