@@ -78,8 +78,9 @@ def cpu_baseline(n_samples, N, L, budget_s=12.0):
     sample = ", ".join("l%d: %d samples" % (l + 1, per_level[l][0]) for l in range(L - 1))
     return dict(value=round(total, 2), unit="s", cores=1, kind="oracle",
                 sample="2D Poisson %d^2, %d levels, exact sine-transform solves (scipy.fft, "
-                       "1 worker); per-sample time measured on %s, scaled by the GPU run's "
-                       "N_l %s, plus 5 pilot solves; extrapolated time per trace"
+                       "1 worker); per-sample time measured on %s, scaled by the mean N_l %s "
+                       "of the GPU run's timed steps, plus 5 pilot solves; extrapolated time "
+                       "per trace"
                        % (N, L, sample, list(n_samples)))
 
 
@@ -167,6 +168,18 @@ def hbm_roofline(name, stats, stride, traffic=None):
                 algorithmic_bytes_per_launch=round(nbytes / max(launches, 1)))
 
 
+def timed_traces(est, args, torch, method="trace"):
+    """Seconds per trace of `est` over the timed steps' own seeds (1..steps),
+    after one warm-up trace; returns (mean seconds, per-seed sample counts)."""
+    run = getattr(est, method)
+    run(args.eps, 1000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ns = [run(args.eps, i + 1)["n_samples"] for i in range(args.steps)]
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / args.steps, ns
+
+
 def contract(args, value, unit, hib, ms_per_step, dtype, data, config, roofline, cpu, **extra):
     out = {"metric": METRIC, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms_per_step, 2), "higher_is_better": hib,
@@ -232,24 +245,27 @@ def run_poisson(args, m, torch):
         log("graphs: %.3fs per trace" % compare["graphs_s_per_trace"])
         e64 = m.TraceEstimator("poisson2d", N, L, L, precision="fp64", nb=args.nb,
                                solve_tol=1e-10, alloc=args.alloc, **vc)
-        r64 = e64.trace(args.eps, 1)
-        compare["fp64_mlmc_s"] = round(r64["seconds"], 3)
-        compare["fp64_mlmc_n_samples"] = r64["n_samples"]
-        log("plain FP64 MLMC %.3fs N_l=%s" % (r64["seconds"], r64["n_samples"]))
+        t64, n64 = timed_traces(e64, args, torch)
+        compare["fp64_mlmc_s"] = round(t64, 3)
+        compare["fp64_mlmc_n_samples"] = n64
+        log("plain FP64 MLMC %.3fs per trace, N_l=%s" % (t64, n64))
         log("plain FP64 Hutchinson, same accuracy")
-        rh = e64.hutchinson(args.eps, 1)
-        compare["fp64_hutchinson_s"] = round(rh["seconds"], 3)
-        compare["fp64_hutchinson_n_samples"] = rh["n_samples"][0]
-        log("plain FP64 Hutchinson %.3fs N=%d" % (rh["seconds"], rh["n_samples"][0]))
+        th, nh = timed_traces(e64, args, torch, "hutchinson")
+        compare["fp64_hutchinson_s"] = round(th, 3)
+        compare["fp64_hutchinson_n_samples"] = [n[0] for n in nh]
+        log("plain FP64 Hutchinson %.3fs per trace, N=%s" % (th, [n[0] for n in nh]))
         e64.close()
-        compare["speedup_vs_fp64_mlmc"] = round(r64["seconds"] / (ms_per_step / 1000.0), 2)
-        compare["speedup_vs_fp64_hutchinson"] = round(rh["seconds"] / (ms_per_step / 1000.0), 2)
+        compare["speedup_vs_fp64_mlmc"] = round(t64 / (ms_per_step / 1000.0), 2)
+        compare["speedup_vs_fp64_hutchinson"] = round(th / (ms_per_step / 1000.0), 2)
 
     cpu, accuracy = None, {"n_samples": [r["n_samples"] for r in runs],
                            "rmsd_rel": [round(r["rmsd"] / abs(r["trace"].real), 7) for r in runs]}
     if not args.no_cpu:
         log("CPU oracle baseline")
-        cpu = cpu_baseline(runs[0]["n_samples"], N, L)
+        # the oracle's time for the mean sample counts of the timed steps
+        mean_n = [int(round(sum(r["n_samples"][j] for r in runs) / len(runs)))
+                  for j in range(len(runs[0]["n_samples"]))]
+        cpu = cpu_baseline(mean_n, N, L)
         exact = cpu_exact_poisson_trace(N)
         accuracy.update(exact_trace=exact,
                         rel_err=[round(abs(r["trace"].real - exact) / exact, 7) for r in runs],
@@ -330,23 +346,22 @@ def run_wilson(args, m, torch, N, learned):
         if learned:
             log("plain FP32 MLMC (no network), same workload")
             ep = _wilson_est(m, N, Ls, L, "fp32_ir64", False, args.nb, args.alloc)
-            rp = ep.trace(args.eps, 1)
+            tp, npl = timed_traces(ep, args, torch)
             ep.close()
-            compare["plain_fp32_mlmc_s"] = round(rp["seconds"], 3)
-            compare["plain_fp32_mlmc_iterations"] = rp["iterations"]
-            compare["plain_fp32_mlmc_n_samples"] = rp["n_samples"]
-            log("plain FP32 MLMC %.3fs N_l=%s" % (rp["seconds"], rp["n_samples"]))
+            compare["plain_fp32_mlmc_s"] = round(tp, 3)
+            compare["plain_fp32_mlmc_n_samples"] = npl
+            log("plain FP32 MLMC %.3fs per trace, N_l=%s" % (tp, npl))
         log("plain FP64 MLMC, same workload")
         e64 = _wilson_est(m, N, Ls, L, "fp64", False, args.nb, args.alloc)
-        r64 = e64.trace(args.eps, 1)
+        t64, n64 = timed_traces(e64, args, torch)
         e64.close()
-        compare["fp64_mlmc_s"] = round(r64["seconds"], 3)
-        compare["fp64_mlmc_n_samples"] = r64["n_samples"]
-        compare["speedup_vs_fp64_mlmc"] = round(r64["seconds"] / (ms_per_step / 1000.0), 2)
+        compare["fp64_mlmc_s"] = round(t64, 3)
+        compare["fp64_mlmc_n_samples"] = n64
+        compare["speedup_vs_fp64_mlmc"] = round(t64 / (ms_per_step / 1000.0), 2)
         if learned:
             compare["speedup_vs_plain_fp32_mlmc"] = round(
                 compare["plain_fp32_mlmc_s"] / (ms_per_step / 1000.0), 2)
-        log("plain FP64 MLMC %.3fs N_l=%s" % (r64["seconds"], r64["n_samples"]))
+        log("plain FP64 MLMC %.3fs per trace, N_l=%s" % (t64, n64))
     config = {"workload": "wilson2d_%dx%d_Ls%d_L%d_agg4x4x8_nb%d_c64ir128_eps%g%s"
                           % (N, N, Ls, L, args.nb, args.eps, "_learned" if learned else ""),
               "variant": ("learned smoother (2 of 4 finest sweeps) + complex64 FGMRES in "
