@@ -371,6 +371,80 @@ inline dim3 grid_cells(int64_t n, int nb) {
   return dim3((unsigned)((n + kThreads - 1) / kThreads), (unsigned)nb);
 }
 
+// rc = R (b - A x) (2x2x2 aggregates, 1/sqrt(8)), the aggregate read as four
+// rows of two cells: a thread per coarse cell (lanes along coarse x, so each
+// row is a 2-element load contiguous over the wave), COLS right-hand sides
+// sharing the couplings; neighbours outside the grid read as zero
+template <typename T, int COLS>
+__global__ __launch_bounds__(kThreads) void k_vc_res_restrict(const T* __restrict__ b,
+                                                              const T* __restrict__ x,
+                                                              T* __restrict__ rc,
+                                                              const R_t<T>* __restrict__ kl,
+                                                              const R_t<T>* __restrict__ dg,
+                                                              int N, int nb, const int* active,
+                                                              int* tlog) {
+  using R = R_t<T>;
+  const int col0 = blockIdx.y * COLS;
+  if (tlog && blockIdx.x == 0 && threadIdx.x < COLS && col0 + (int)threadIdx.x < nb)
+    tlog[col0 + threadIdx.x] = active ? active[col0 + threadIdx.x] : 1;
+  const int Nc = N >> 1;
+  const int nc = Nc * Nc * Nc;
+  const int I = blockIdx.x * kThreads + threadIdx.x;
+  if (I >= nc) return;
+  const int Z = I / (Nc * Nc);
+  const int rem = I - Z * Nc * Nc;
+  const int Y = rem / Nc, X = rem - Y * Nc;
+  const int x0 = 2 * X;
+  const int NN = N * N;
+  const int64_t n = (int64_t)NN * N, stride = n + NN;
+  const T zero = zero_of(T());
+  T acc[COLS];
+#pragma unroll
+  for (int q = 0; q < COLS; ++q) acc[q] = zero;
+#pragma unroll
+  for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy) {
+      const int y = 2 * Y + dy, z = 2 * Z + dz;
+      const int64_t i = ((int64_t)z * N + y) * N + x0;
+      // couplings of the pair (faces below each cell and the ones above, which
+      // are the faces below the next cells; zero on the boundary, padded)
+      const R kx0 = kl[i], kx1 = kl[i + 1], kx2 = kl[i + 2];
+      const R ky0 = kl[stride + i], ky1 = kl[stride + i + 1];
+      const R kyu0 = kl[stride + i + N], kyu1 = kl[stride + i + N + 1];
+      const R kz0 = kl[2 * stride + i], kz1 = kl[2 * stride + i + 1];
+      const R kzu0 = kl[2 * stride + i + NN], kzu1 = kl[2 * stride + i + NN + 1];
+      const R d0 = dg[i], d1 = dg[i + 1];
+      const bool xl_in = x0 > 0, xr_in = x0 + 2 < N;
+      const bool yl_in = y > 0, yu_in = y + 1 < N, zl_in = z > 0, zu_in = z + 1 < N;
+#pragma unroll
+      for (int q = 0; q < COLS; ++q) {
+        const int col = col0 + q;
+        if (!col_on(active, col, nb)) continue;  // uniform over the block
+        const T* xc = x + (int64_t)col * n;
+        const T* bc = b + (int64_t)col * n;
+        const T c0 = xc[i], c1 = xc[i + 1];
+        const T xl = xl_in ? xc[i - 1] : zero, xr = xr_in ? xc[i + 2] : zero;
+        const T yl0 = yl_in ? xc[i - N] : zero, yl1 = yl_in ? xc[i - N + 1] : zero;
+        const T yu0 = yu_in ? xc[i + N] : zero, yu1 = yu_in ? xc[i + N + 1] : zero;
+        const T zl0 = zl_in ? xc[i - NN] : zero, zl1 = zl_in ? xc[i - NN + 1] : zero;
+        const T zu0 = zu_in ? xc[i + NN] : zero, zu1 = zu_in ? xc[i + NN + 1] : zero;
+        const T r0 = bc[i] - (d0 * c0 - (kx0 * xl + kx1 * c1 + ky0 * yl0 + kyu0 * yu0 +
+                                          kz0 * zl0 + kzu0 * zu0));
+        const T r1 = bc[i + 1] - (d1 * c1 - (kx1 * c0 + kx2 * xr + ky1 * yl1 + kyu1 * yu1 +
+                                              kz1 * zl1 + kzu1 * zu1));
+        acc[q] += r0;
+        acc[q] += r1;
+      }
+    }
+#pragma unroll
+  for (int q = 0; q < COLS; ++q) {
+    const int col = col0 + q;
+    if (!col_on(active, col, nb)) continue;
+    rc[(int64_t)col * nc + I] = (R)0.35355339059327373 * acc[q];  // 1/sqrt(8)
+  }
+}
+
 // ---------------------------------------------------------------------------
 // One fused red-black sweep, out of place, marching along z:
 //   x_out = S(x_in + ws * P ec ; b)      (ws = omega / sqrt(8); F = first colour)
@@ -725,8 +799,13 @@ void varcoef_restrict(const T* b, const T* x, T* xc, const typename Traits<T>::r
                       const int* active, hipStream_t s) {
   const int64_t nc = (int64_t)(N / 2) * (N / 2) * (N / 2);
   const dim3 g((unsigned)((nc + kThreads - 1) / kThreads), (unsigned)((nb + cols - 1) / cols));
-  VC_COLS_DISPATCH(cols, MLMC_LAUNCH((k_vc_restrict<T, C>), g, dim3(kThreads), 0, s, b, x, xc,
-                                     kl, dg, N, residual ? 1 : 0, nb, active, timing_log()));
+  if (residual) {
+    VC_COLS_DISPATCH(cols, MLMC_LAUNCH((k_vc_res_restrict<T, C>), g, dim3(kThreads), 0, s, b, x,
+                                       xc, kl, dg, N, nb, active, timing_log()));
+  } else {
+    VC_COLS_DISPATCH(cols, MLMC_LAUNCH((k_vc_restrict<T, C>), g, dim3(kThreads), 0, s, b, x, xc,
+                                       kl, dg, N, 0, nb, active, timing_log()));
+  }
 }
 
 template <typename T>

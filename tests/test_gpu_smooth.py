@@ -127,10 +127,22 @@ def test_varcoef_sweeps_match_oracle(precision, N):
     faces = varcoef_faces(N, seed=1000)
     est = m.TraceEstimator("varcoef3d", N, L, L, shift=1e-3, field=faces, nb=8,
                            precision=precision)
-    A, _ = hierarchy.varcoef_hierarchy(N, faces, 1e-3, L)
+    A, P = hierarchy.varcoef_hierarchy(N, faces, 1e-3, L)
+    rng = np.random.default_rng(12)
     for level in (1, 2):
         _check(est, A[level - 1], hierarchy.site_coloring_3d(N >> (level - 1)), level, precision,
                sweeps=(1, 2))
+        # the V-cycle's residual restriction R (b - A x) of the swept x
+        n = est.level_size(level)
+        Bh = rng.standard_normal((NRHS, n))
+        xr, rc = est.smooth(level, to_dev(Bh), to_dev(rng.standard_normal((NRHS, n))), 2,
+                            restrict=True)
+        x, r = from_dev(xr), from_dev(rc)
+        Al, Pl = A[level - 1], P[level - 1]
+        for k in range(NRHS):
+            ref = Pl.T @ (Bh[k] - Al @ x[k])
+            bound = np.max(abs(Pl.T) @ (np.abs(Bh[k]) + abs(Al) @ np.abs(x[k])))
+            assert np.max(np.abs(r[k] - ref)) <= TOL[precision] * bound, (level, k)
 
 
 def test_smooth_rejects_bad_arguments():
@@ -145,3 +157,26 @@ def test_smooth_rejects_bad_arguments():
         est.smooth(1, B, B, -1)
     with pytest.raises(m.MLMCError):   # the restricted residual follows a forward pass
         est.smooth(1, B, B, 2, reverse=True, restrict=True)
+
+
+def test_varcoef_in_place_sweep_above_side_128():
+    # sides above 128 keep the in-place pair of colour launches (the fused 3D
+    # pass holds a row of at most 128 cells in one wave)
+    require_gpu()
+    import paper_2108_11281_amd as m
+    from oracle import operators
+    N = 136
+    faces = varcoef_faces(N, seed=1000)
+    est = m.TraceEstimator("varcoef3d", N, 4, 4, shift=1e-3, field=faces, nb=4,
+                           precision="fp32_ir64")
+    A = operators.varcoef3d(N, faces, 1e-3).tocsr()
+    colour = hierarchy.site_coloring_3d(N)
+    rng = np.random.default_rng(4)
+    B = rng.standard_normal((2, A.shape[0]))
+    X = rng.standard_normal((2, A.shape[0]))
+    for reverse in (False, True):
+        got = from_dev(est.smooth(1, to_dev(B), to_dev(X), 1, reverse))
+        for k in range(2):
+            ref = hierarchy.rbgs_sweeps(A, B[k], X[k], colour, 1, reverse)
+            err = np.max(np.abs(got[k] - ref))
+            assert err <= TOL["fp32_ir64"] * np.max(np.abs(ref)), (reverse, k, err)
