@@ -106,7 +106,9 @@ typedef struct mlmc_options {
   double solve_tol;   /* per-column FP64 relative residual |b-Ay|/|b| target */
   double inner_tol;   /* MLMC_FP32_IR64: FP32 CG residual reduction after which
                          the iterate is refined in FP64 (y64 += x32, residual
-                         recomputed in FP64; the search direction is kept) */
+                         recomputed in FP64; the search direction is kept);
+                         for the complex operators the FGMRES cycle's residual
+                         reduction.  0 = automatic: 1e-3 (real), 1e-2 (complex) */
   int max_iter;       /* Krylov iterations per solve (MLMC_FP32_IR64: times
                          max_refine) */
   int max_refine;     /* MLMC_FP32_IR64: iteration budget multiplier */
@@ -145,7 +147,7 @@ typedef struct mlmc_result {
 } mlmc_result;
 
 /* Fill *opt with defaults: FP32_IR64, nb 128, 1+1 sweeps, omega 1.8, EQUAL,
- * solve_tol 1e-10, inner_tol 1e-2, max_iter 200, max_refine 8, restart 16,
+ * solve_tol 1e-10, inner_tol 0 (automatic), max_iter 200, max_refine 8, restart 16,
  * min_samples 5, max_samples 2^22, tau 0, learned 0, graphs 0. */
 int mlmc_default_options(mlmc_options* opt);
 

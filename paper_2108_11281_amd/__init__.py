@@ -177,10 +177,11 @@ class TraceEstimator:
             self._lib.mlmc_destroy(self._ctx)
             self._ctx = ctypes.c_void_p()
 
-    def __del__(self):
-        # during interpreter shutdown the allocator callbacks may already be
-        # gone; the exit handler has closed every estimator by then
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # during interpreter shutdown the allocator callbacks (and this module's
+        # globals) may already be gone; the exit handler has closed every
+        # estimator by then
+        if _finalizing():
             return
         try:
             self.close()

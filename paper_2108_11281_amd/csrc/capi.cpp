@@ -56,7 +56,7 @@ int mlmc_default_options(mlmc_options* opt) {
   opt->alloc = MLMC_ALLOC_EQUAL;
   opt->rho_weights = nullptr;
   opt->solve_tol = 1e-10;
-  opt->inner_tol = 1e-2;
+  opt->inner_tol = 0.0;  // automatic per operator kind
   opt->max_iter = 200;
   opt->max_refine = 8;
   opt->krylov_restart = 16;

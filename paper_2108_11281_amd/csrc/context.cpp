@@ -36,7 +36,11 @@ Context::Context(const mlmc_operator& A, const mlmc_hierarchy& h, const mlmc_opt
   MLMC_REQUIRE(nb_ >= 1 && nb_ <= 1024, MLMC_EINVAL, "nb must be in [1, 1024]");
   MLMC_REQUIRE(o.precision == MLMC_FP64 || o.precision == MLMC_FP32_IR64, MLMC_EINVAL,
                "unknown precision");
-  MLMC_REQUIRE(o.solve_tol > 0 && o.inner_tol > 0, MLMC_EINVAL, "tolerances must be > 0");
+  MLMC_REQUIRE(o.solve_tol > 0 && o.inner_tol >= 0, MLMC_EINVAL,
+               "solve_tol must be > 0 and inner_tol >= 0");
+  // inner_tol 0: the measured best per solver -- 1e-3 for the refined CG of the
+  // real operators, 1e-2 for the complex FGMRES restart cycles
+  if (opt_.inner_tol == 0.0) opt_.inner_tol = A.kind == MLMC_WILSON2D ? 1e-2 : 1e-3;
   MLMC_REQUIRE(o.max_iter >= 1 && o.max_refine >= 1, MLMC_EINVAL, "iteration limits < 1");
   MLMC_REQUIRE(o.nu_pre >= 0 && o.nu_post >= 0, MLMC_EINVAL, "negative sweep count");
   MLMC_REQUIRE(o.min_samples >= 2, MLMC_EINVAL, "min_samples must be >= 2");

@@ -44,6 +44,7 @@ def test_struct_sizes_match_header_layout():
 def test_default_options_and_status_strings():
     o = m.default_options()
     assert o.nb == 128 and o.min_samples == 5 and o.precision == m.FP32_IR64
+    assert o.inner_tol == 0.0 and o.solve_tol == 1e-10  # 0: chosen per operator kind
     assert m.lib().mlmc_status_string(-4) == b"not converged"
 
 
