@@ -9,6 +9,8 @@ hierarchy here is:
 * 2D: 2x2 blocks of grid points form an aggregate; P has entry 1/2 in each of
   the four rows of an aggregate (orthonormal piecewise constants).
 * 3D: 2x2x2 blocks, entries 1/sqrt(8).
+* General sparse operators: greedy aggregates of the matrix graph, entries
+  1/sqrt(|J|) (see the section at the end of this file).
 * Wilson: b x b blocks of lattice sites form an aggregate; P restricted to one
   aggregate is an orthonormal basis of the span of n_vec near-null test
   vectors restricted to that aggregate (Example 4.3, the aggregation sketch:
@@ -94,11 +96,12 @@ def site_coloring_3d(N):
 
 
 def coloured_gs_sweep(A, v, colour, b, order=(0, 1)):
-    """One block Gauss-Seidel sweep over two colour classes, in `order`.
+    """One block Gauss-Seidel sweep over the colour classes listed in `order`.
 
     For each class m in turn the unknowns of m are solved exactly with the
     others held: v_m <- A_mm^{-1} (b_m - A_{m,rest} v_rest).  With a red-black
-    colouring of a nearest-neighbour operator A_mm is (block) diagonal.
+    colouring of a nearest-neighbour operator (or any proper colouring of the
+    matrix graph) A_mm is (block) diagonal.
     """
     A = A.tocsr()
     for c in order:
@@ -189,4 +192,110 @@ def wilson_hierarchy(N, theta, m0, levels, block=4, n_vec=8, sweeps=20, seed=1):
         A.append(galerkin(A[-1], Pl))
         n_side //= block
         dof = n_vec
+    return A, P
+
+
+# ---------------------------------------------------------------------------
+# General sparse operators: aggregation and colouring on the matrix graph
+# ---------------------------------------------------------------------------
+#
+# Sec. 4.1 takes the hierarchy as given: aggregates of unknowns and, on each,
+# the coarse basis.  For an operator given only as a sparse matrix (the
+# gauge-Laplacian and graph examples of Sec. 5 leave this to an algebraic
+# multigrid package), the aggregates here come from plain two-pass greedy
+# aggregation on the graph of A (j is a neighbour of i when i != j and
+# a_ij != 0), visiting unknowns in index order, and P holds the orthonormal
+# piecewise constants 1/sqrt(|J|) of each aggregate J.  The smoother's colour
+# classes come from first-fit greedy colouring of the same graph in index
+# order.  Plain Python loops: for the small cases of the tests.
+
+def matrix_graph(A):
+    """Neighbour lists [(j, |a_ij|), ...] of every row, in column order."""
+    A = sp.csr_matrix(A)
+    out = []
+    for i in range(A.shape[0]):
+        lo, hi = A.indptr[i], A.indptr[i + 1]
+        out.append([(int(j), abs(v)) for j, v in zip(A.indices[lo:hi], A.data[lo:hi])
+                    if j != i and v != 0])
+    return out
+
+
+def greedy_aggregation(A, return_seeds=False):
+    """Aggregate number of every unknown (numbered in order of creation).
+
+    Pass 1: an unknown whose neighbours are all still unassigned founds an
+    aggregate with them.  Pass 2: every unknown left over joins the pass-1
+    aggregate of its neighbour with the largest |a_ij| (the smallest j among
+    equal ones); after pass 1 each such unknown has a neighbour in a pass-1
+    aggregate, since otherwise it would have founded one.  return_seeds: also
+    the founding unknown of every aggregate.
+    """
+    nbrs = matrix_graph(A)
+    n = len(nbrs)
+    agg = [-1] * n
+    seeds = []
+    for i in range(n):
+        if agg[i] < 0 and all(agg[j] < 0 for j, _ in nbrs[i]):
+            agg[i] = len(seeds)
+            for j, _ in nbrs[i]:
+                agg[j] = len(seeds)
+            seeds.append(i)
+    first = list(agg)
+    for i in range(n):
+        if agg[i] < 0:
+            best = None
+            for j, w in nbrs[i]:
+                if first[j] >= 0 and (best is None or w > best[0]):
+                    best = (w, j)
+            agg[i] = first[best[1]]
+    agg = np.array(agg, dtype=np.int64)
+    return (agg, np.array(seeds, dtype=np.int64)) if return_seeds else agg
+
+
+def aggregate_prolongation(agg):
+    """P with entry 1/sqrt(|J|) in row i, column J = agg[i] (orthonormal columns)."""
+    agg = np.asarray(agg)
+    n, nc = len(agg), int(agg.max()) + 1
+    size = np.bincount(agg, minlength=nc)
+    assert np.all(size > 0), "aggregate numbers must be 0..nc-1 without gaps"
+    return sp.csr_matrix((1.0 / np.sqrt(size[agg]), (np.arange(n), agg)), shape=(n, nc))
+
+
+def first_fit_coloring(A):
+    """Colour of every unknown: the smallest colour not taken by a neighbour
+    with a smaller index (unknowns visited in index order)."""
+    nbrs = matrix_graph(A)
+    colour = [0] * len(nbrs)
+    for i, nb in enumerate(nbrs):
+        used = {colour[j] for j, _ in nb if j < i}
+        c = 0
+        while c in used:
+            c += 1
+        colour[i] = c
+    return np.array(colour, dtype=np.int64)
+
+
+def multicolour_gs_sweeps(A, b, x, colour, sweeps, reverse=False):
+    """`sweeps` Gauss-Seidel sweeps over the colour classes 0, 1, ... (reverse:
+    from the last class down, the post-smoothing order)."""
+    C = int(np.max(colour)) + 1
+    order = tuple(range(C - 1, -1, -1)) if reverse else tuple(range(C))
+    for _ in range(sweeps):
+        x = coloured_gs_sweep(A, x, colour, b, order)
+    return x
+
+
+def csr_hierarchy(A, levels, aggs=None):
+    """A_1..A_levels, P_1..P_{levels-1} of a sparse operator: greedy aggregation
+    on every level, or the given aggregate maps aggs[l] (level l+1 unknown ->
+    aggregate), orthonormal piecewise-constant P, Galerkin coarse operators."""
+    A = [sp.csr_matrix(A, dtype=np.float64)]
+    A[0].eliminate_zeros()
+    P = []
+    for l in range(levels - 1):
+        agg = greedy_aggregation(A[-1]) if aggs is None else np.asarray(aggs[l])
+        P.append(aggregate_prolongation(agg))
+        Ac = galerkin(A[-1], P[-1])
+        Ac.eliminate_zeros()
+        A.append(Ac)
     return A, P

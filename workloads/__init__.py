@@ -2,10 +2,10 @@
 CPU oracle.
 
 This module generates operator data only (gauge-link phases, diffusion face
-coefficients, problem sizes) and the workload parameter sets.  It holds none of
-the trace-estimation arithmetic: neither the oracle nor the library is imported
-here, and both receive these arrays as plain inputs.
+coefficients, graph matrices, problem sizes) and the workload parameter sets.
+It holds none of the trace-estimation arithmetic: neither the oracle nor the
+library is imported here, and both receive these arrays as plain inputs.
 """
 from .generate import (gauge_field, varcoef_faces, batch_problem_sizes,  # noqa: F401
                        WORKLOADS, workload, wilson_mass, nn_init_weights,  # noqa: F401
-                       varcoef_levels)
+                       varcoef_levels, graph_laplacian)

@@ -54,6 +54,34 @@ def nn_init_weights(seed=1):
     return np.concatenate(out)
 
 
+def graph_laplacian(n, degree=8.0, shift=1e-2, seed=1):
+    """Shifted Laplacian L + shift*I of a random geometric graph, as CSR.
+
+    n points uniform in the unit square, an edge (weight 1) between every two
+    points closer than r = sqrt(degree / (pi n)), so the mean degree is about
+    `degree` away from the boundary.  The points are numbered cell by cell
+    (cells of side r, row-major, points in a cell by x) so that neighbours have
+    nearby indices.  Returns a scipy.sparse CSR matrix with sorted indices.
+    """
+    import scipy.sparse as sp
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(np.random.SeedSequence([0x6A09E667, 8, seed, n]))
+    pts = rng.random((n, 2))
+    r = float(np.sqrt(degree / (np.pi * n)))
+    cells = np.floor(pts / r).astype(np.int64)
+    order = np.lexsort((pts[:, 0], cells[:, 0], cells[:, 1]))
+    pts = pts[order]
+    pairs = cKDTree(pts).query_pairs(r, output_type="ndarray")
+    i, j = pairs[:, 0], pairs[:, 1]
+    W = sp.coo_matrix((np.ones(2 * len(i)), (np.concatenate([i, j]), np.concatenate([j, i]))),
+                      shape=(n, n)).tocsr()
+    deg = np.asarray(W.sum(axis=1)).ravel()
+    A = (sp.diags(deg + shift) - W).tocsr()
+    A.sum_duplicates()
+    A.sort_indices()
+    return A
+
+
 def wilson_mass(N):
     """m0 for the Wilson workload at lattice side N (tuned on the CPU so that the
     smallest |eigenvalue| is about 1e-2), or None if not tuned yet."""
@@ -86,6 +114,9 @@ WORKLOADS = {
         kind="wilson2d", N=512, levels_mlmc=3, levels_solver=4, nb=128,
         precision="fp32_ir64", eps=1e-3, solve_tol=1e-10, block=4, n_vec=8,
         setup_sweeps=20, theta_sigma=0.5, gauge_seed=1, learned=True),
+    "graph1m_fp32ir": dict(
+        kind="csr", n=1 << 20, degree=8.0, shift=1e-2, graph_seed=1, levels_mlmc=4,
+        levels_solver=4, nb=128, precision="fp32_ir64", eps=1e-3, solve_tol=1e-10),
 }
 
 
