@@ -55,8 +55,16 @@ enum mlmc_kind {
   MLMC_WILSON2D = 1,   /* (m0+2) I - 1/2 sum_mu [(I - s_mu) U_mu(x) d_{x+mu}
                           + (I + s_mu) U_mu(x-mu)^* d_{x-mu}], 2 spins, N x N
                           periodic (Example 4.3 halved, m0 = m/2) */
-  MLMC_VARCOEF3D = 2   /* 7-point diffusion with face coefficients, N^3,
+  MLMC_VARCOEF3D = 2,  /* 7-point diffusion with face coefficients, N^3,
                           Dirichlet faces, plus shift*I */
+  MLMC_CSR = 3         /* a real symmetric positive definite matrix given in
+                          compressed sparse row form (the algebraic operators
+                          of Sec. 5, whose hierarchy an algebraic multigrid
+                          method supplies): aggregates of the matrix graph
+                          (given per level, or built by greedy aggregation),
+                          orthonormal piecewise-constant P (entries 1/sqrt|J|),
+                          Galerkin coarse operators (Sec. 4.1), multicolour
+                          Gauss-Seidel smoothing over a first-fit colouring */
 };
 
 enum mlmc_precision {
@@ -83,6 +91,17 @@ typedef struct mlmc_operator {
                          VARCOEF3D: face coefficients k[3][N][N][N+1]
                          (x-faces [z][y][f], y-faces [z][x][f], z-faces [y][x][f],
                           face f between cells f-1 and f); unused for POISSON2D */
+  /* CSR: A (n x n) as row offsets row_ptr[0..n] (row_ptr[0] = 0), column
+     indices col_idx[row_ptr[i]..row_ptr[i+1]-1] in [0, n) and their values.
+     Columns may come in any order; repeated entries are summed; entries equal
+     to zero are dropped.  Every row needs a positive diagonal entry; the
+     matrix must be symmetric (pattern and values, to 1e-12 relative) and
+     positive definite (not checked: a solve that fails to converge returns
+     MLMC_ENOCONV).  n < 2^31, nnz < 2^31.  Unused by the other kinds. */
+  int64_t n;
+  const int64_t* row_ptr;
+  const int32_t* col_idx;
+  const double* vals;
 } mlmc_operator;
 
 /* Hierarchy description (Sec. 4.1; solver levels may exceed MLMC levels, Sec. 5). */
@@ -93,6 +112,16 @@ typedef struct mlmc_hierarchy {
   int n_vec;          /* WILSON2D: test vectors = coarse dofs per site (8) */
   int setup_sweeps;   /* WILSON2D: smoothing sweeps on A v = 0 per test vector */
   uint64_t setup_seed;/* WILSON2D: seed of the test-vector start vectors */
+  /* CSR: NULL, or levels_solver - 1 host arrays: agg[l][i] = aggregate (the
+     coarse unknown of level l+2) of unknown i of level l+1.  Aggregate numbers
+     must cover 0..n_{l+2}-1 without gaps.  NULL builds every level by greedy
+     aggregation of the matrix graph (j is a neighbour of i when a_ij != 0):
+     pass 1 visits the unknowns in index order, and one whose neighbours are
+     all unassigned founds an aggregate with them; pass 2 puts every unknown
+     left over into the pass-1 aggregate of its neighbour with the largest
+     |a_ij| (the smallest j among equal ones).  Aggregates are numbered in
+     order of creation. */
+  const int32_t* const* agg;
 } mlmc_hierarchy;
 
 typedef struct mlmc_options {
@@ -235,6 +264,16 @@ int mlmc_export_coarse(void* ctx, int which, double* out);
  * as n_l x n_vec complex values: row i holds the n_vec coefficients of unknown
  * i in the basis of its aggregate (Example 4.3 aggregation sketch). */
 int mlmc_export_prolongation(void* ctx, int level, double* out);
+
+/* MLMC_CSR: level `level` (1..L_s) of the hierarchy as the library holds it
+ * (Sec. 4.1: A_{l+1} = P_l^T A_l P_l).  *nnz receives its entry count; row_ptr
+ * (n_l + 1), col_idx and vals (nnz each) the matrix in canonical form (columns
+ * ascending, no repeated or zero entries); agg (n_l, levels below L_s) the
+ * aggregate of every unknown; colour (n_l) its first-fit colour class, the
+ * Gauss-Seidel order.  Host arrays, each may be NULL (not written).  Other
+ * kinds: MLMC_EUNSUPPORTED. */
+int mlmc_export_csr(void* ctx, int level, int64_t* nnz, int64_t* row_ptr, int32_t* col_idx,
+                    double* vals, int32_t* agg, int32_t* colour);
 
 /* Host-side estimator driver over a caller-supplied sampler (no device use).
  * sample(user, level, first, count, out): write count samples of level l as

@@ -211,7 +211,7 @@ def wilson_hierarchy(N, theta, m0, levels, block=4, n_vec=8, sweeps=20, seed=1):
 
 def matrix_graph(A):
     """Neighbour lists [(j, |a_ij|), ...] of every row, in column order."""
-    A = sp.csr_matrix(A)
+    A = sp.csr_matrix(A).sorted_indices()
     out = []
     for i in range(A.shape[0]):
         lo, hi = A.indptr[i], A.indptr[i + 1]
@@ -289,13 +289,15 @@ def csr_hierarchy(A, levels, aggs=None):
     """A_1..A_levels, P_1..P_{levels-1} of a sparse operator: greedy aggregation
     on every level, or the given aggregate maps aggs[l] (level l+1 unknown ->
     aggregate), orthonormal piecewise-constant P, Galerkin coarse operators."""
-    A = [sp.csr_matrix(A, dtype=np.float64)]
-    A[0].eliminate_zeros()
+    def canonical(M):     # storage order only: columns ascending, no zeros
+        M = sp.csr_matrix(M, dtype=np.float64)
+        M.sum_duplicates()
+        M.eliminate_zeros()
+        return M.sorted_indices()
+    A = [canonical(A)]
     P = []
     for l in range(levels - 1):
         agg = greedy_aggregation(A[-1]) if aggs is None else np.asarray(aggs[l])
         P.append(aggregate_prolongation(agg))
-        Ac = galerkin(A[-1], P[-1])
-        Ac.eliminate_zeros()
-        A.append(Ac)
+        A.append(canonical(galerkin(A[-1], P[-1])))
     return A, P

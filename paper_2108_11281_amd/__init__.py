@@ -13,10 +13,10 @@ import weakref
 import numpy as np
 
 from . import _capi
-from ._capi import (ALLOC_EQUAL, ALLOC_GILES, ALLOC_WEIGHTS, FP32_IR64, FP64,  # noqa: F401
-                    POISSON2D, VARCOEF3D, WILSON2D)
+from ._capi import (ALLOC_EQUAL, ALLOC_GILES, ALLOC_WEIGHTS, CSR, FP32_IR64,  # noqa: F401
+                    FP64, POISSON2D, VARCOEF3D, WILSON2D)
 
-KINDS = {"poisson2d": POISSON2D, "wilson2d": WILSON2D, "varcoef3d": VARCOEF3D}
+KINDS = {"poisson2d": POISSON2D, "wilson2d": WILSON2D, "varcoef3d": VARCOEF3D, "csr": CSR}
 PRECISIONS = {"fp64": FP64, "fp32_ir64": FP32_IR64}
 ALLOCS = {"equal": ALLOC_EQUAL, "weights": ALLOC_WEIGHTS, "giles": ALLOC_GILES}
 
@@ -107,14 +107,18 @@ def _close_live():
 class TraceEstimator:
     """One operator, its hierarchy and the solvers on the current torch device.
 
-    kind: "poisson2d" | "wilson2d" | "varcoef3d"; field: numpy array of link
-    phases (wilson2d) or face coefficients (varcoef3d).  Options follow
-    mlmc_options (include/mlmc.h); unknown keyword names raise.
+    kind: "poisson2d" | "wilson2d" | "varcoef3d" | "csr"; field: numpy array of
+    link phases (wilson2d) or face coefficients (varcoef3d); matrix: the csr
+    kind's matrix (anything with indptr, indices and data after .tocsr(), e.g.
+    a scipy.sparse matrix; n_side is ignored); agg: optional aggregate maps of
+    the csr kind, one integer array per level below the coarsest (None: greedy
+    aggregation in the library).  Options follow mlmc_options
+    (include/mlmc.h); unknown keyword names raise.
     """
 
     def __init__(self, kind, n_side, levels_solver, levels_mlmc=None, *, diag=4.0, off=1.0,
-                 mass=0.0, shift=0.0, field=None, block=4, n_vec=8, setup_sweeps=20,
-                 setup_seed=1, stream=None, torch_allocator=True, **options):
+                 mass=0.0, shift=0.0, field=None, matrix=None, agg=None, block=4, n_vec=8,
+                 setup_sweeps=20, setup_seed=1, stream=None, torch_allocator=True, **options):
         import torch
         self._lib = lib()
         self._ctx = ctypes.c_void_p()
@@ -133,11 +137,27 @@ class TraceEstimator:
                 raise ValueError("%s field must hold %d values, got %d"
                                  % (kind, want, self._field.size))
             op.field = self._field.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        if matrix is not None:
+            m = matrix.tocsr() if hasattr(matrix, "tocsr") else matrix
+            self._csr = (np.ascontiguousarray(m.indptr, dtype=np.int64),
+                         np.ascontiguousarray(m.indices, dtype=np.int32),
+                         np.ascontiguousarray(m.data, dtype=np.float64))
+            op.n = len(self._csr[0]) - 1
+            op.row_ptr = self._csr[0].ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+            op.col_idx = self._csr[1].ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+            op.vals = self._csr[2].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         h = _capi.Hierarchy()
         h.levels_solver = int(levels_solver)
         h.levels_mlmc = int(levels_mlmc if levels_mlmc is not None else levels_solver)
         h.block, h.n_vec, h.setup_sweeps = int(block), int(n_vec), int(setup_sweeps)
         h.setup_seed = int(setup_seed)
+        if agg is not None:
+            self._agg = [np.ascontiguousarray(a, dtype=np.int32) for a in agg]
+            if len(self._agg) != h.levels_solver - 1:
+                raise ValueError("agg needs levels_solver - 1 maps, got %d" % len(self._agg))
+            self._agg_ptrs = (ctypes.POINTER(ctypes.c_int32) * len(self._agg))(
+                *[a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) for a in self._agg])
+            h.agg = ctypes.cast(self._agg_ptrs, ctypes.POINTER(ctypes.POINTER(ctypes.c_int32)))
         o = default_options()
         self._weights = None
         for k, v in options.items():
@@ -323,6 +343,27 @@ class TraceEstimator:
         self._c(self._lib.mlmc_probes(self._ctx, int(level), int(seed), int(stream),
                                       int(first), int(nrhs), self._ptr(y)))
         return y
+
+    def export_csr(self, level):
+        """Level `level` of a csr hierarchy: (scipy CSR matrix A_level, aggregate
+        map or None on the coarsest level, colour classes)."""
+        import scipy.sparse as sp
+        n = self.level_size(level)
+        nnz = ctypes.c_int64()
+        self._c(self._lib.mlmc_export_csr(self._ctx, int(level), ctypes.byref(nnz), None, None,
+                                          None, None, None))
+        rp = np.zeros(n + 1, dtype=np.int64)
+        ci = np.zeros(nnz.value, dtype=np.int32)
+        v = np.zeros(nnz.value)
+        col = np.zeros(n, dtype=np.int32)
+        agg = np.zeros(n, dtype=np.int32) if level < self.levels_solver else None
+        i32 = ctypes.POINTER(ctypes.c_int32)
+        self._c(self._lib.mlmc_export_csr(
+            self._ctx, int(level), ctypes.byref(nnz),
+            rp.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), ci.ctypes.data_as(i32),
+            v.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            agg.ctypes.data_as(i32) if agg is not None else None, col.ctypes.data_as(i32)))
+        return sp.csr_matrix((v, ci, rp), shape=(n, n)), agg, col
 
     def export_coarse(self, which=0):
         lvl = self.levels_mlmc if which == 1 else self.levels_solver

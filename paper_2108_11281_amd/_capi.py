@@ -16,6 +16,7 @@ MLMC_EUNSUPPORTED = -6
 POISSON2D = 0
 WILSON2D = 1
 VARCOEF3D = 2
+CSR = 3
 
 FP64 = 0
 FP32_IR64 = 1
@@ -31,13 +32,17 @@ class Operator(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("n_side", ctypes.c_int),
                 ("diag", ctypes.c_double), ("off", ctypes.c_double),
                 ("mass", ctypes.c_double), ("shift", ctypes.c_double),
-                ("field", ctypes.POINTER(ctypes.c_double))]
+                ("field", ctypes.POINTER(ctypes.c_double)),
+                ("n", ctypes.c_int64), ("row_ptr", ctypes.POINTER(ctypes.c_int64)),
+                ("col_idx", ctypes.POINTER(ctypes.c_int32)),
+                ("vals", ctypes.POINTER(ctypes.c_double))]
 
 
 class Hierarchy(ctypes.Structure):
     _fields_ = [("levels_solver", ctypes.c_int), ("levels_mlmc", ctypes.c_int),
                 ("block", ctypes.c_int), ("n_vec", ctypes.c_int),
-                ("setup_sweeps", ctypes.c_int), ("setup_seed", ctypes.c_uint64)]
+                ("setup_sweeps", ctypes.c_int), ("setup_seed", ctypes.c_uint64),
+                ("agg", ctypes.POINTER(ctypes.POINTER(ctypes.c_int32)))]
 
 
 class Options(ctypes.Structure):
@@ -92,6 +97,7 @@ _P = ctypes.c_void_p
 _D = ctypes.POINTER(ctypes.c_double)
 _I64 = ctypes.POINTER(ctypes.c_int64)
 _F = ctypes.POINTER(ctypes.c_float)
+_I32 = ctypes.POINTER(ctypes.c_int32)
 
 # name: (restype, argtypes)
 SIGNATURES = {
@@ -116,6 +122,7 @@ SIGNATURES = {
                                    ctypes.c_int64, ctypes.c_int, _P]),
     "mlmc_export_coarse": (ctypes.c_int, [_P, ctypes.c_int, _D]),
     "mlmc_export_prolongation": (ctypes.c_int, [_P, ctypes.c_int, _D]),
+    "mlmc_export_csr": (ctypes.c_int, [_P, ctypes.c_int, _I64, _I64, _I32, _D, _I32, _I32]),
     "mlmc_run_estimator": (ctypes.c_int, [ctypes.c_int, SAMPLE_FN, PILOT_FN, _P, _D, _D,
                                           ctypes.POINTER(Options), ctypes.c_double,
                                           ctypes.POINTER(Result)]),

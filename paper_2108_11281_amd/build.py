@@ -16,9 +16,11 @@ SOURCES = [
     "kernels_krylov.hip",
     "kernels_varcoef.hip",
     "kernels_nn.hip",
+    "kernels_csr.hip",
     "context.cpp",
     "context_complex.cpp",
     "context_nn.cpp",
+    "context_csr.cpp",
     "estimator.cpp",
     "capi.cpp",
 ]

@@ -178,6 +178,13 @@ int mlmc_export_prolongation(void* c, int level, double* out) {
   return guarded(ctx, [&] { ctx->export_prolongation(level, out); });
 }
 
+int mlmc_export_csr(void* c, int level, int64_t* nnz, int64_t* row_ptr, int32_t* col_idx,
+                    double* vals, int32_t* agg, int32_t* colour) {
+  Context* ctx = as_ctx(c);
+  if (!ctx || !nnz) return MLMC_EINVAL;
+  return guarded(ctx, [&] { ctx->export_csr(level, nnz, row_ptr, col_idx, vals, agg, colour); });
+}
+
 int mlmc_run_estimator(int levels, mlmc_sample_fn sample, mlmc_pilot_fn pilot, void* user,
                        const double* coarse, const double* cost, const mlmc_options* opt,
                        double tol, mlmc_result* out) {

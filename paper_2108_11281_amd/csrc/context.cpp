@@ -26,7 +26,11 @@ Context::Context(const mlmc_operator& A, const mlmc_hierarchy& h, const mlmc_opt
     : kind_(A.kind), op_(A), h_(h), opt_(o), s_(s) {
   hooks_ = alloc_hooks();
   MLMC_HIP(hipGetDevice(&device_));
-  op_.field = nullptr;
+  op_.field = nullptr;  // caller memory is not kept
+  op_.row_ptr = nullptr;
+  op_.col_idx = nullptr;
+  op_.vals = nullptr;
+  h_.agg = nullptr;
   Ls_ = h.levels_solver;
   L_ = h.levels_mlmc;
   nb_ = o.nb;
@@ -59,6 +63,11 @@ Context::Context(const mlmc_operator& A, const mlmc_hierarchy& h, const mlmc_opt
         varcoef_ = true;
         omega_ = opt_.omega > 0 ? opt_.omega : 1.8;
         build_varcoef(A.field);
+        break;
+      case MLMC_CSR:
+        csr_ = true;
+        omega_ = opt_.omega > 0 ? opt_.omega : 1.8;
+        build_csr(A, h.agg);
         break;
       case MLMC_WILSON2D:
         complex_ = true;
@@ -170,6 +179,9 @@ void Context::invert_coarse(int level, double** inv_out, c64* trace_out) {
       break;
     case MLMC_VARCOEF3D:
       varcoef_dense(L.kf64, L.dg64, L.side, aug, s_);
+      break;
+    case MLMC_CSR:
+      csr_dense(L.A64, aug, s_);
       break;
     default:
       throw Error(MLMC_EUNSUPPORTED, "dense build");
@@ -462,13 +474,16 @@ template <> const double* Context::vc_diag<double>(int l) const { return lv_[l -
 
 int Context::op_tiles(int l) const {
   const Level& L = lv_[l - 1];
+  if (csr_) return csr_blocks((int)L.n);
   return varcoef_ ? varcoef_blocks(L.side) : poisson_march_tiles(L.side);
 }
 
 template <typename T>
 void Context::op_apply(int l, const T* x, T* y, int nb, const int* act, c64* partials) {
   const Level& L = lv_[l - 1];
-  if (varcoef_)
+  if (csr_)
+    csr_residual<T, T, T>(nullptr, x, y, csr_mat<T>(l), nb, L.cols, act, partials, s_);
+  else if (varcoef_)
     varcoef_residual<T, T, T>(nullptr, x, y, vc_faces<T>(l), vc_diag<T>(l), L.side, nb, L.cols,
                               act, partials, s_);
   else
@@ -479,7 +494,9 @@ template <typename Tb, typename Tx, typename Tr>
 void Context::op_residual(int l, const Tb* b, const Tx* x, Tr* r, int nb, const int* act,
                           c64* partials) {
   const Level& L = lv_[l - 1];
-  if (varcoef_)
+  if (csr_)
+    csr_residual<Tb, Tx, Tr>(b, x, r, csr_mat<Tx>(l), nb, L.cols, act, partials, s_);
+  else if (varcoef_)
     varcoef_residual<Tb, Tx, Tr>(b, x, r, vc_faces<Tx>(l), vc_diag<Tx>(l), L.side, nb, L.cols,
                                  act, partials, s_);
   else
@@ -490,7 +507,9 @@ template <typename T>
 void Context::op_update_apply(int l, const T* p_old, const T* z, const c64* beta, T* p_new,
                               T* q, int nb, const int* act) {
   const Level& L = lv_[l - 1];
-  if (varcoef_)
+  if (csr_)
+    csr_update_apply<T>(p_old, z, beta, p_new, q, csr_mat<T>(l), nb, L.cols, act, partials_, s_);
+  else if (varcoef_)
     varcoef_update_apply<T>(p_old, z, beta, p_new, q, vc_faces<T>(l), vc_diag<T>(l), L.side, nb,
                             L.cols, act, partials_, s_);
   else
@@ -500,7 +519,9 @@ void Context::op_update_apply(int l, const T* p_old, const T* z, const c64* beta
 template <typename T>
 void Context::op_res_restrict(int l, const T* b, const T* x, T* rc, int nb, const int* act) {
   const Level& L = lv_[l - 1];
-  if (varcoef_)
+  if (csr_)
+    csr_restrict<T>(b, x, rc, csr_mat<T>(l), csr_agg<T>(l), true, nb, L.cols, act, s_);
+  else if (varcoef_)
     varcoef_restrict<T>(b, x, rc, vc_faces<T>(l), vc_diag<T>(l), L.side, true, nb, L.cols, act,
                         s_);
   else
@@ -511,7 +532,9 @@ template <typename T>
 void Context::op_prolong(int l, const T* ec, T* x, int nb, const int* act, double beta) {
   const Level& L = lv_[l - 1];
   const double w = beta == 0.0 ? 1.0 : omega_;
-  if (varcoef_)
+  if (csr_)
+    csr_prolong<T>(ec, x, csr_agg<T>(l), (int)L.n, w, beta, nb, act, s_);
+  else if (varcoef_)
     varcoef_prolong<T>(ec, x, L.side, w, beta, nb, act, s_);
   else
     agg2d_prolong<T>(ec, x, L.side, w, beta, nb, act, s_);
@@ -520,7 +543,9 @@ void Context::op_prolong(int l, const T* ec, T* x, int nb, const int* act, doubl
 template <typename T>
 void Context::op_restrict(int l, const T* x, T* xc, int nb, const int* act) {
   const Level& L = lv_[l - 1];
-  if (varcoef_)
+  if (csr_)
+    csr_restrict<T>(nullptr, x, xc, csr_mat<T>(l), csr_agg<T>(l), false, nb, L.cols, act, s_);
+  else if (varcoef_)
     varcoef_restrict<T>(nullptr, x, xc, nullptr, nullptr, L.side, false, nb, L.cols, act, s_);
   else
     agg2d_restrict<T>(x, xc, L.side, nb, act, s_);
@@ -632,6 +657,10 @@ void Context::vcycle(int l, const T* b, T* x, int nb, const int* act, c64* rz_pa
     vcycle_vc<T>(l, b, x, nb, act, rz_partials);
     return;
   }
+  if (csr_) {
+    vcycle_csr<T>(l, b, x, nb, act, rz_partials);
+    return;
+  }
   Work<T>& w = work<T>();
   if (l == 1) counters[2] += 1;
   const int64_t n = lv_[l - 1].n;
@@ -717,7 +746,7 @@ template <typename T>
 int Context::vcycle_partials(int l, bool* fused) const {
   const int64_t n = lv_[l - 1].n;
   *fused = false;
-  if (varcoef_ || l == Ls_ || opt_.nu_post == 0) return reduce_blocks(n);
+  if (varcoef_ || csr_ || l == Ls_ || opt_.nu_post == 0) return reduce_blocks(n);
   enum { kNull, kTmp, kX };
   const int per = sweeps_per_pass(l);
   int u = kNull;
@@ -1330,6 +1359,9 @@ void Context::smooth_fp64(int level, int nrhs, int sweeps, bool reverse, const d
       for (int i = 0; i < sweeps; ++i)
         cop_smooth<C>(level, reinterpret_cast<const C*>(bt), reinterpret_cast<C*>(xa), nrhs,
                       nullptr, false, reverse);
+    } else if (csr_) {
+      for (int i = 0; i < sweeps; ++i)
+        csr_gs_sweep<T>(bt, xa, csr_sweep<T>(level), (int)n, nrhs, L.cols, nullptr, reverse, s_);
     } else if (varcoef_) {
       for (int i = 0; i < sweeps; ++i) {
         if (L.mcols > 0) {
@@ -1424,6 +1456,8 @@ void Context::export_coarse(int which, double* out) {
                        reinterpret_cast<c64*>(aug), s_);
   else if (varcoef_)
     varcoef_dense(L.kf64, L.dg64, L.side, aug, s_);
+  else if (csr_)
+    csr_dense(L.A64, aug, s_);
   else
     poisson_dense_build<double>(aug, L.side, L.d, L.c, s_);
   for (int i = 0; i < n; ++i)

@@ -47,6 +47,18 @@ struct Level {
   int mcols = 0;  // right-hand sides per wave of the fused 3D sweep (0: in-place sweeps)
   // POISSON2D: rows per segment of the fused sweep, FP32 and FP64 (autotuned)
   int gs_rows[2] = {16, 8};
+  // CSR levels: the matrix by rows, the colour-sorted off-diagonal part for the
+  // sweep and the aggregation to the next level, with FP32 and FP64 values
+  // (device); host copies of the matrix, aggregate map and colours for export
+  CsrMat<float> A32;
+  CsrMat<double> A64;
+  CsrSweep<float> S32;
+  CsrSweep<double> S64;
+  CsrAgg<float> G32;
+  CsrAgg<double> G64;
+  std::vector<int64_t> h_rp;
+  std::vector<int> h_ci, h_agg, h_colour;
+  std::vector<double> h_v;
 };
 
 // Batched flexible GMRES workspace (precision T)
@@ -95,6 +107,8 @@ class Context {
                    double* out);
   void export_coarse(int which, double* out);
   void export_prolongation(int level, double* out);
+  void export_csr(int level, int64_t* nnz, int64_t* row_ptr, int32_t* col_idx, double* vals,
+                  int32_t* agg, int32_t* colour);
   // learned smoother (WILSON2D)
   void nn_train(const float* w_init, const mlmc_train_options& o, mlmc_train_report* rep);
   void nn_set_weights(const float* w);
@@ -134,6 +148,14 @@ class Context {
   }
   void build_poisson();
   void build_varcoef(const double* k);
+  void build_csr(const mlmc_operator& A, const int32_t* const* aggs);
+  void csr_upload(Level& L, bool last);
+  void tune_csr();
+  template <typename T> const CsrMat<T>& csr_mat(int l) const;
+  template <typename T> const CsrSweep<T>& csr_sweep(int l) const;
+  template <typename T> const CsrAgg<T>& csr_agg(int l) const;
+  template <typename T> void vcycle_csr(int l, const T* b, T* x, int nb, const int* act,
+                                        c64* rz_partials);
   void tune_varcoef();
   void tune_bsr();
   void tune_poisson();
@@ -262,6 +284,7 @@ class Context {
   Fgmres<c64> fg64_;
   bool complex_ = false;
   bool varcoef_ = false;
+  bool csr_ = false;
   // learned smoother state: FP32 master weights, Adam moments, gradient, BF16
   // fragments, BF16 link features; nn_use_ is true while a solve runs with it
   bool nn_ready_ = false, nn_use_ = false;

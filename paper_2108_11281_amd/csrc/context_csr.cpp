@@ -1,0 +1,427 @@
+// Operators given as a sparse matrix (MLMC_CSR): hierarchy construction on the
+// host (canonical rows, symmetry check, greedy aggregation of the matrix graph,
+// first-fit colouring, Galerkin products with orthonormal piecewise-constant
+// aggregation, Sec. 4.1), upload of every level, the autotuner of the sweep
+// and the V-cycle.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "context.h"
+
+namespace mlmc {
+namespace {
+
+struct HostCsr {
+  int n = 0;
+  std::vector<int64_t> rp;
+  std::vector<int> ci;
+  std::vector<double> v;
+};
+
+// rows sorted by column, repeated entries summed, zero entries dropped
+HostCsr canonical(int64_t n, const int64_t* rp, const int32_t* ci, const double* v) {
+  MLMC_REQUIRE(n >= 1 && n < (int64_t)1 << 31, MLMC_EINVAL, "CSR needs 1 <= n < 2^31");
+  MLMC_REQUIRE(rp != nullptr && ci != nullptr && v != nullptr, MLMC_EINVAL,
+               "CSR needs row_ptr, col_idx and vals");
+  MLMC_REQUIRE(rp[0] == 0, MLMC_EINVAL, "row_ptr[0] must be 0");
+  for (int64_t i = 0; i < n; ++i)
+    MLMC_REQUIRE(rp[i + 1] >= rp[i], MLMC_EINVAL, "row_ptr must be non-decreasing");
+  MLMC_REQUIRE(rp[n] < (int64_t)1 << 31, MLMC_EINVAL, "CSR needs nnz < 2^31");
+  HostCsr A;
+  A.n = (int)n;
+  A.rp.assign(n + 1, 0);
+  A.ci.reserve(rp[n]);
+  A.v.reserve(rp[n]);
+  std::vector<std::pair<int, double>> row;
+  for (int64_t i = 0; i < n; ++i) {
+    row.clear();
+    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+      MLMC_REQUIRE(ci[e] >= 0 && ci[e] < n, MLMC_EINVAL, "column index out of range");
+      MLMC_REQUIRE(std::isfinite(v[e]), MLMC_EINVAL, "CSR values must be finite");
+      row.push_back({ci[e], v[e]});
+    }
+    std::stable_sort(row.begin(), row.end(),
+                     [](const std::pair<int, double>& a, const std::pair<int, double>& b) {
+                       return a.first < b.first;
+                     });
+    for (size_t k = 0; k < row.size();) {
+      const int j = row[k].first;
+      double sum = 0.0;
+      for (; k < row.size() && row[k].first == j; ++k) sum += row[k].second;
+      if (sum != 0.0) {
+        A.ci.push_back(j);
+        A.v.push_back(sum);
+      }
+    }
+    A.rp[i + 1] = (int64_t)A.ci.size();
+  }
+  return A;
+}
+
+// value of entry (i, j), or 0 (rows sorted)
+double entry(const HostCsr& A, int i, int j) {
+  const int* lo = A.ci.data() + A.rp[i];
+  const int* hi = A.ci.data() + A.rp[i + 1];
+  const int* p = std::lower_bound(lo, hi, j);
+  return (p != hi && *p == j) ? A.v[p - A.ci.data()] : 0.0;
+}
+
+void check_spd_shape(const HostCsr& A, int level) {
+  const std::string at = " (level " + std::to_string(level) + ")";
+  for (int i = 0; i < A.n; ++i) {
+    MLMC_REQUIRE(entry(A, i, i) > 0, MLMC_EINVAL, "every row needs a positive diagonal" + at);
+    for (int64_t e = A.rp[i]; e < A.rp[i + 1]; ++e) {
+      const int j = A.ci[e];
+      const double a = A.v[e], b = entry(A, j, i);
+      MLMC_REQUIRE(std::fabs(a - b) <= 1e-12 * std::max(std::fabs(a), std::fabs(b)), MLMC_EINVAL,
+                   "the matrix must be symmetric" + at);
+    }
+  }
+}
+
+// Greedy aggregation of the matrix graph: pass 1 visits unknowns in index
+// order and one whose neighbours are all unassigned founds an aggregate with
+// them; pass 2 puts every unknown left over into the pass-1 aggregate of its
+// neighbour with the largest |a_ij| (the smallest j among equal ones; the
+// columns are ascending, so the first maximum wins).
+std::vector<int> greedy_aggregates(const HostCsr& A, int* nc_out) {
+  std::vector<int> agg(A.n, -1);
+  int nc = 0;
+  for (int i = 0; i < A.n; ++i) {
+    if (agg[i] >= 0) continue;
+    bool free = true;
+    for (int64_t e = A.rp[i]; e < A.rp[i + 1] && free; ++e)
+      if (A.ci[e] != i && agg[A.ci[e]] >= 0) free = false;
+    if (!free) continue;
+    agg[i] = nc;
+    for (int64_t e = A.rp[i]; e < A.rp[i + 1]; ++e) agg[A.ci[e]] = nc;
+    ++nc;
+  }
+  const std::vector<int> first = agg;
+  for (int i = 0; i < A.n; ++i) {
+    if (agg[i] >= 0) continue;
+    double best = -1.0;
+    int to = -1;
+    for (int64_t e = A.rp[i]; e < A.rp[i + 1]; ++e) {
+      const int j = A.ci[e];
+      if (j == i || first[j] < 0) continue;
+      if (std::fabs(A.v[e]) > best) {
+        best = std::fabs(A.v[e]);
+        to = first[j];
+      }
+    }
+    MLMC_REQUIRE(to >= 0, MLMC_EINVAL, "greedy aggregation left an unknown unassigned");
+    agg[i] = to;
+  }
+  *nc_out = nc;
+  return agg;
+}
+
+// first-fit colouring in index order: the smallest colour that no neighbour
+// with a smaller index holds
+std::vector<int> first_fit_colours(const HostCsr& A) {
+  std::vector<int> colour(A.n, 0);
+  std::vector<int> mark;
+  for (int i = 0; i < A.n; ++i) {
+    for (int64_t e = A.rp[i]; e < A.rp[i + 1]; ++e) {
+      const int j = A.ci[e];
+      if (j >= i) continue;
+      const int c = colour[j];
+      if ((int)mark.size() <= c) mark.resize(c + 1, -1);
+      mark[c] = i;
+    }
+    int c = 0;
+    while (c < (int)mark.size() && mark[c] == i) ++c;
+    colour[i] = c;
+  }
+  return colour;
+}
+
+// A_c = P^T A P with P(i, J) = 1/sqrt|J| for J = agg[i]
+HostCsr galerkin(const HostCsr& A, const std::vector<int>& agg, int nc) {
+  std::vector<int> size(nc, 0);
+  for (int i = 0; i < A.n; ++i) ++size[agg[i]];
+  std::vector<int> aptr(nc + 1, 0), arows(A.n);
+  for (int J = 0; J < nc; ++J) aptr[J + 1] = aptr[J] + size[J];
+  {
+    std::vector<int> fill(aptr.begin(), aptr.end() - 1);
+    for (int i = 0; i < A.n; ++i) arows[fill[agg[i]]++] = i;
+  }
+  HostCsr C;
+  C.n = nc;
+  C.rp.assign(nc + 1, 0);
+  std::vector<double> acc(nc, 0.0);
+  std::vector<int> seen(nc, -1), touched;
+  for (int I = 0; I < nc; ++I) {
+    touched.clear();
+    for (int m = aptr[I]; m < aptr[I + 1]; ++m) {
+      const int i = arows[m];
+      for (int64_t e = A.rp[i]; e < A.rp[i + 1]; ++e) {
+        const int J = agg[A.ci[e]];
+        if (seen[J] != I) {
+          seen[J] = I;
+          acc[J] = 0.0;
+          touched.push_back(J);
+        }
+        acc[J] += A.v[e];
+      }
+    }
+    std::sort(touched.begin(), touched.end());
+    for (int J : touched) {
+      const double val = acc[J] / std::sqrt((double)size[I] * (double)size[J]);
+      if (val != 0.0) {
+        C.ci.push_back(J);
+        C.v.push_back(val);
+      }
+    }
+    C.rp[I + 1] = (int64_t)C.ci.size();
+  }
+  return C;
+}
+
+}  // namespace
+
+template <> const CsrMat<float>& Context::csr_mat<float>(int l) const { return lv_[l - 1].A32; }
+template <> const CsrMat<double>& Context::csr_mat<double>(int l) const { return lv_[l - 1].A64; }
+template <> const CsrSweep<float>& Context::csr_sweep<float>(int l) const {
+  return lv_[l - 1].S32;
+}
+template <> const CsrSweep<double>& Context::csr_sweep<double>(int l) const {
+  return lv_[l - 1].S64;
+}
+template <> const CsrAgg<float>& Context::csr_agg<float>(int l) const { return lv_[l - 1].G32; }
+template <> const CsrAgg<double>& Context::csr_agg<double>(int l) const { return lv_[l - 1].G64; }
+
+// device copies of level L's matrix, colour-sorted sweep arrays and (unless it
+// is the coarsest level) its aggregation, from the host copies in L
+void Context::csr_upload(Level& L, bool last) {
+  const int n = (int)L.n;
+  auto up = [&](const auto& h) {
+    using V = typename std::decay<decltype(h)>::type::value_type;
+    V* d = dalloc_n<V>(std::max<int64_t>((int64_t)h.size(), 1));
+    if (!h.empty()) {  // h may be a temporary: wait for the copy
+      MLMC_HIP(hipMemcpyAsync(d, h.data(), sizeof(V) * h.size(), hipMemcpyHostToDevice, s_));
+      MLMC_HIP(hipStreamSynchronize(s_));
+    }
+    return d;
+  };
+  auto to_f32 = [](const std::vector<double>& a) {
+    return std::vector<float>(a.begin(), a.end());
+  };
+  // the matrix by rows
+  std::vector<int> rp32(L.h_rp.begin(), L.h_rp.end());
+  const int* rp = up(rp32);
+  const int* ci = up(L.h_ci);
+  L.A64 = {n, rp, ci, up(L.h_v)};
+  L.A32 = {n, rp, ci, up(to_f32(L.h_v))};
+  // the off-diagonal part with rows grouped by colour (ascending rows within a
+  // class) and the inverted diagonal per position
+  const int ncol = n ? *std::max_element(L.h_colour.begin(), L.h_colour.end()) + 1 : 0;
+  std::vector<int> coff(ncol + 1, 0), crow(n);
+  for (int i = 0; i < n; ++i) ++coff[L.h_colour[i] + 1];
+  for (int c = 0; c < ncol; ++c) coff[c + 1] += coff[c];
+  {
+    std::vector<int> fill(coff.begin(), coff.end() - 1);
+    for (int i = 0; i < n; ++i) crow[fill[L.h_colour[i]]++] = i;
+  }
+  std::vector<int> cp(n + 1, 0), cci;
+  std::vector<double> cv, cdi(n);
+  for (int k = 0; k < n; ++k) {
+    const int i = crow[k];
+    for (int64_t e = L.h_rp[i]; e < L.h_rp[i + 1]; ++e) {
+      if (L.h_ci[e] == i) {
+        cdi[k] = 1.0 / L.h_v[e];
+      } else {
+        cci.push_back(L.h_ci[e]);
+        cv.push_back(L.h_v[e]);
+      }
+    }
+    cp[k + 1] = (int)cci.size();
+  }
+  const int* dcrow = up(crow);
+  const int* dcp = up(cp);
+  const int* dcci = up(cci);
+  L.S64.crow = L.S32.crow = dcrow;
+  L.S64.cp = L.S32.cp = dcp;
+  L.S64.cci = L.S32.cci = dcci;
+  L.S64.cv = up(cv);
+  L.S64.cdi = up(cdi);
+  L.S32.cv = up(to_f32(cv));
+  L.S32.cdi = up(to_f32(cdi));
+  L.S64.coff = L.S32.coff = coff;
+  if (last) return;
+  // aggregation: member lists (ascending) and the scales 1/sqrt|J|
+  const int nc = *std::max_element(L.h_agg.begin(), L.h_agg.end()) + 1;
+  std::vector<int> aptr(nc + 1, 0), arows(n);
+  for (int i = 0; i < n; ++i) ++aptr[L.h_agg[i] + 1];
+  for (int J = 0; J < nc; ++J) aptr[J + 1] += aptr[J];
+  {
+    std::vector<int> fill(aptr.begin(), aptr.end() - 1);
+    for (int i = 0; i < n; ++i) arows[fill[L.h_agg[i]]++] = i;
+  }
+  std::vector<double> cs(nc), fs(n);
+  for (int J = 0; J < nc; ++J) cs[J] = 1.0 / std::sqrt((double)(aptr[J + 1] - aptr[J]));
+  for (int i = 0; i < n; ++i) fs[i] = cs[L.h_agg[i]];
+  const int* dagg = up(L.h_agg);
+  const int* daptr = up(aptr);
+  const int* darows = up(arows);
+  L.G64 = {nc, dagg, daptr, darows, up(fs), up(cs)};
+  L.G32 = {nc, dagg, daptr, darows, up(to_f32(fs)), up(to_f32(cs))};
+}
+
+void Context::build_csr(const mlmc_operator& A, const int32_t* const* aggs) {
+  lv_.resize(Ls_);
+  HostCsr cur = canonical(A.n, A.row_ptr, A.col_idx, A.vals);
+  for (int l = 0; l < Ls_; ++l) {
+    check_spd_shape(cur, l + 1);
+    Level& L = lv_[l];
+    L.index = l + 1;
+    L.side = 0;
+    L.dof = 1;
+    L.n = cur.n;
+    L.h_colour = first_fit_colours(cur);
+    if (l + 1 < Ls_) {
+      int nc = 0;
+      if (aggs) {
+        MLMC_REQUIRE(aggs[l] != nullptr, MLMC_EINVAL, "agg[" + std::to_string(l) + "] is null");
+        L.h_agg.assign(aggs[l], aggs[l] + cur.n);
+        int mx = -1;
+        for (int a : L.h_agg) {
+          MLMC_REQUIRE(a >= 0 && a < cur.n, MLMC_EINVAL, "aggregate number out of range");
+          mx = std::max(mx, a);
+        }
+        nc = mx + 1;
+        std::vector<char> used(nc, 0);
+        for (int a : L.h_agg) used[a] = 1;
+        MLMC_REQUIRE(std::all_of(used.begin(), used.end(), [](char u) { return u != 0; }),
+                     MLMC_EINVAL, "aggregate numbers must cover 0..nc-1 without gaps");
+      } else {
+        L.h_agg = greedy_aggregates(cur, &nc);
+      }
+      HostCsr next = galerkin(cur, L.h_agg, nc);
+      L.h_rp = std::move(cur.rp);
+      L.h_ci = std::move(cur.ci);
+      L.h_v = std::move(cur.v);
+      cur = std::move(next);
+    } else {
+      L.h_rp = std::move(cur.rp);
+      L.h_ci = std::move(cur.ci);
+      L.h_v = std::move(cur.v);
+    }
+  }
+  MLMC_REQUIRE(lv_[Ls_ - 1].n <= 16384, MLMC_EINVAL,
+               "coarsest solver level larger than 16384 unknowns (add levels)");
+  for (int l = 0; l < Ls_; ++l) csr_upload(lv_[l], l + 1 == Ls_);
+  MLMC_HIP(hipStreamSynchronize(s_));
+  finish_real_build();
+  tune_csr();
+}
+
+// Autotuner of the CSR kernels: per smoothed level, time one Gauss-Seidel
+// sweep over all nb columns with 1, 2, 4 and 8 right-hand sides per thread (the
+// results are identical; only the reuse of the row's indices and values and
+// the parallelism differ) and keep the fastest for every CSR kernel of that
+// level.  Runs once at setup on the library's own work vectors.
+void Context::tune_csr() {
+  const bool fp32 = opt_.precision == MLMC_FP32_IR64;
+  hipEvent_t a = event(), b = event();
+  for (int l = 1; l < Ls_; ++l) {
+    Level& L = lv_[l - 1];
+    float best = 1e30f;
+    int best_cols = 4;
+    for (int cols : {1, 2, 4, 8}) {
+      float ms = 0.f;
+      for (int rep = 0; rep < 3; ++rep) {
+        MLMC_HIP(hipEventRecord(a, s_));
+        if (fp32)
+          csr_gs_sweep<float>(w32_.r, w32_.x, L.S32, (int)L.n, nb_, cols, nullptr, false, s_);
+        else
+          csr_gs_sweep<double>(w64_.r, w64_.x, L.S64, (int)L.n, nb_, cols, nullptr, false, s_);
+        MLMC_HIP(hipEventRecord(b, s_));
+        MLMC_HIP(hipEventSynchronize(b));
+        float t = 0.f;
+        MLMC_HIP(hipEventElapsedTime(&t, a, b));
+        if (rep > 0) ms += t;  // the first run warms caches and code
+      }
+      if (ms < best) {
+        best = ms;
+        best_cols = cols;
+      }
+    }
+    L.cols = best_cols;
+  }
+  ev_pool_.push_back(a);
+  ev_pool_.push_back(b);
+}
+
+// V-cycle of a CSR level: in-place multicolour Gauss-Seidel sweeps (classes in
+// ascending order before the coarse correction, descending after it, so the
+// preconditioner is symmetric), residual + restriction, prolongation +
+// omega-scaled correction.
+template <typename T>
+void Context::vcycle_csr(int l, const T* b, T* x, int nb, const int* act, c64* rz_partials) {
+  Work<T>& w = work<T>();
+  if (l == 1) counters[2] += 1;
+  const Level& L = lv_[l - 1];
+  const int64_t n = L.n;
+  const double en = (double)sizeof(T) * (double)n;
+  if (l == Ls_) {
+    dense_apply<T>(w.ainvT, b, x, (int)n, nb, act, s_);
+  } else {
+    const CsrMat<T>& A = csr_mat<T>(l);
+    const CsrSweep<T>& S = csr_sweep<T>(l);
+    const CsrAgg<T>& G = csr_agg<T>(l);
+    const int64_t nnz = L.h_rp[n];
+    // matrix bytes of a sweep (off-diagonal entries, row ids, offsets, inverted
+    // diagonal) and of a residual (all entries, offsets), shared by the columns
+    const double sweep_mat = (double)(nnz - n) * (4.0 + sizeof(T)) + (double)n * (8.0 + sizeof(T));
+    const double res_mat = (double)nnz * (4.0 + sizeof(T)) + 4.0 * (double)n;
+    const double enc = (double)sizeof(T) * (double)G.nc;
+    const int pre = opt_.nu_pre, post = opt_.nu_post;
+    if (pre > 0) vec_zero<T>(x, n, nb, act, s_);
+    for (int i = 0; i < pre; ++i)
+      timed<T>(kTimGs, 3.0 * en + sweep_mat / nb, act, nb,
+               [&] { csr_gs_sweep<T>(b, x, S, (int)n, nb, L.cols, act, false, s_); });
+    T* bc = w.vb[l];
+    T* ec = w.vx[l];
+    if (pre == 0)
+      csr_restrict<T>(nullptr, b, bc, A, G, false, nb, L.cols, act, s_);
+    else
+      timed<T>(kTimResRestrict, 2.0 * en + enc + res_mat / nb, act, nb,
+               [&] { csr_restrict<T>(b, x, bc, A, G, true, nb, L.cols, act, s_); });
+    vcycle_csr<T>(l + 1, bc, ec, nb, act, nullptr);
+    timed<T>(kTimProlong, (pre == 0 ? 1.0 : 2.0) * en + enc, act, nb, [&] {
+      csr_prolong<T>(ec, x, G, (int)n, omega_, pre == 0 ? 0.0 : 1.0, nb, act, s_);
+    });
+    for (int i = 0; i < post; ++i)
+      timed<T>(kTimGs, 3.0 * en + sweep_mat / nb, act, nb,
+               [&] { csr_gs_sweep<T>(b, x, S, (int)n, nb, L.cols, act, true, s_); });
+  }
+  if (rz_partials) vec_dot_partials<T>(b, x, n, nb, act, rz_partials, s_);
+}
+
+template void Context::vcycle_csr<float>(int, const float*, float*, int, const int*, c64*);
+template void Context::vcycle_csr<double>(int, const double*, double*, int, const int*, c64*);
+
+// the matrix of a level in canonical CSR form (nnz always; every array
+// nullable), its aggregate map (levels below L_s) and its colours
+void Context::export_csr(int level, int64_t* nnz, int64_t* row_ptr, int32_t* col_idx,
+                         double* vals, int32_t* agg, int32_t* colour) {
+  MLMC_REQUIRE(csr_, MLMC_EUNSUPPORTED, "export_csr is for CSR operators");
+  MLMC_REQUIRE(level >= 1 && level <= Ls_, MLMC_EINVAL, "level out of range");
+  MLMC_REQUIRE(nnz != nullptr, MLMC_EINVAL, "nnz must not be null");
+  const Level& L = lv_[level - 1];
+  *nnz = L.h_rp.back();
+  if (row_ptr) std::copy(L.h_rp.begin(), L.h_rp.end(), row_ptr);
+  if (col_idx) std::copy(L.h_ci.begin(), L.h_ci.end(), col_idx);
+  if (vals) std::copy(L.h_v.begin(), L.h_v.end(), vals);
+  if (agg) {
+    MLMC_REQUIRE(level < Ls_, MLMC_EINVAL, "the coarsest level has no aggregates");
+    std::copy(L.h_agg.begin(), L.h_agg.end(), agg);
+  }
+  if (colour) std::copy(L.h_colour.begin(), L.h_colour.end(), colour);
+}
+
+}  // namespace mlmc

@@ -5,6 +5,8 @@
 
 #include <hip/hip_ext.h>
 
+#include <vector>
+
 #include "common.h"
 
 namespace mlmc {
@@ -324,5 +326,57 @@ void givens_step(c64* H, c64* cs, c64* sn, c64* g, int* dims, const c64* h, cons
                  hipStream_t s);
 void givens_solve(c64* H, c64* cs, c64* sn, c64* g, int* dims, c64* y, const int* start, int m,
                   int nb, hipStream_t s);
+
+// ----- general sparse (CSR) operators -----------------------------------------
+// A by rows, diagonal included (device arrays; values in precision T)
+template <typename T>
+struct CsrMat {
+  int n = 0;
+  const int* rp = nullptr;  // n + 1 row offsets
+  const int* ci = nullptr;  // column of each entry
+  const T* v = nullptr;     // value of each entry
+};
+// the off-diagonal part with rows grouped by colour class: positions
+// coff[c]..coff[c+1]-1 hold class c (host offsets), crow[k] is the row at
+// position k, its entries cci/cv[cp[k]..cp[k+1]-1], cdi[k] = 1 / a_ii
+template <typename T>
+struct CsrSweep {
+  const int *crow = nullptr, *cp = nullptr, *cci = nullptr;
+  const T *cv = nullptr, *cdi = nullptr;
+  std::vector<int> coff;
+};
+// aggregation to the next level: agg[i] = aggregate of unknown i; the members
+// of J are arows[aptr[J]..aptr[J+1]-1] (ascending); fs[i] = cs[agg[i]] = 1/sqrt|J|
+template <typename T>
+struct CsrAgg {
+  int nc = 0;
+  const int *agg = nullptr, *aptr = nullptr, *arows = nullptr;
+  const T *fs = nullptr, *cs = nullptr;
+};
+int csr_blocks(int n);  // partial sums per column of csr_residual / csr_update_apply
+// r = b - A x (r = A x when b is null); partials as the stencil residuals
+template <typename Tb, typename T, typename Tr>
+void csr_residual(const Tb* b, const T* x, Tr* r, const CsrMat<T>& A, int nb, int cols,
+                  const int* active, c64* partials, hipStream_t s);
+// p_new = z + beta p_old, q = A p_new, partials of p_new^T q
+template <typename T>
+void csr_update_apply(const T* p_old, const T* z, const c64* beta, T* p_new, T* q,
+                      const CsrMat<T>& A, int nb, int cols, const int* active, c64* partials,
+                      hipStream_t s);
+// one Gauss-Seidel sweep in place over the colour classes (reverse: last class
+// first); one launch per class
+template <typename T>
+void csr_gs_sweep(const T* b, T* x, const CsrSweep<T>& S, int n, int nb, int cols,
+                  const int* active, bool reverse, hipStream_t s);
+// xc = R (b - A x) (residual) or R x, R = P^T
+template <typename T>
+void csr_restrict(const T* b, const T* x, T* xc, const CsrMat<T>& A, const CsrAgg<T>& G,
+                  bool residual, int nb, int cols, const int* active, hipStream_t s);
+// x = beta x + omega P ec
+template <typename T>
+void csr_prolong(const T* ec, T* x, const CsrAgg<T>& G, int n, double omega, double beta, int nb,
+                 const int* active, hipStream_t s);
+// left half of the n x 2n augmented matrix [A | .] (rows of width 2n)
+void csr_dense(const CsrMat<double>& A, double* aug, hipStream_t s);
 
 }  // namespace mlmc

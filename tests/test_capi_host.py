@@ -39,6 +39,10 @@ def test_struct_sizes_match_header_layout():
     # mlmc_train_options: 4 ints, a double, a uint64; mlmc_train_report: 6 x 8 bytes
     assert ctypes.sizeof(_capi.TrainOptions) == 32
     assert ctypes.sizeof(_capi.TrainReport) == 48
+    # mlmc_operator: 2 ints, 4 doubles, a pointer, an int64, 3 pointers;
+    # mlmc_hierarchy: 5 ints (+pad), a uint64, a pointer
+    assert ctypes.sizeof(_capi.Operator) == 8 + 32 + 8 + 8 + 24
+    assert ctypes.sizeof(_capi.Hierarchy) == 24 + 8 + 8
 
 
 def test_default_options_and_status_strings():
@@ -58,6 +62,7 @@ def test_null_arguments_are_rejected():
     assert lib.mlmc_nn_loss_grad(None, 1, None, None, None, None) == -1
     assert lib.mlmc_batch_sample(None, 0, 1, None, 0, 1, 1, None, None) == -1
     assert lib.mlmc_smooth(None, 1, 1, 2, 0, None, None, None) == -1
+    assert lib.mlmc_export_csr(None, 1, None, None, None, None, None, None) == -1
 
 
 class MockSampler:

@@ -1,0 +1,216 @@
+"""GPU parity of the path for operators given as sparse matrices (the csr kind)
+against the oracle's hierarchy (greedy aggregation, first-fit colouring,
+Galerkin products; Sec. 4.1) and its exact level-difference samples
+(Remark 4.3)."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import hierarchy, mlmc, operators
+from tests.gpu_util import from_dev, quad_scale, require_gpu, to_dev
+from workloads import graph_laplacian
+
+pytestmark = pytest.mark.gpu
+
+NRHS = 5
+TOL = {"fp64": 1e-13, "fp32_ir64": 1e-5}
+
+
+def _graph(n=3000, isolated=3, seed=1):
+    # a random geometric graph Laplacian (+ shift) with a few isolated unknowns
+    # appended (singleton aggregates, rows holding only a diagonal)
+    A = graph_laplacian(n, degree=8.0, shift=1e-2, seed=seed)
+    if isolated:
+        A = sp.block_diag([A, sp.diags(np.linspace(0.5, 1.5, isolated))]).tocsr()
+    return A
+
+
+def _est(A, L, agg=None, **kw):
+    require_gpu()
+    import paper_2108_11281_amd as m
+    kw.setdefault("nb", 8)
+    kw.setdefault("solve_tol", 1e-12)
+    return m.TraceEstimator("csr", 0, L, L, matrix=A, agg=agg, **kw)
+
+
+_ORACLES = {}
+
+
+def _oracle(key, A, L, agg=None):
+    if key not in _ORACLES:
+        Al, P = hierarchy.csr_hierarchy(A, L, agg)
+        _ORACLES[key] = mlmc.LevelSampler(Al, P, complex_probe=False)
+    return _ORACLES[key]
+
+
+def test_hierarchy_equals_oracle():
+    A, L = _graph(), 3
+    est = _est(A, L)
+    orc = _oracle("g3000", A, L)
+    for l in range(1, L + 1):
+        Al, agg, col = est.export_csr(l)
+        ref = orc.A[l - 1]
+        assert Al.shape == ref.shape
+        # same pattern (integer data: bit-exact), values to rounding
+        assert np.array_equal(Al.indptr, ref.indptr) and np.array_equal(Al.indices, ref.indices)
+        assert np.max(np.abs(Al.data - ref.data)) <= 1e-14 * np.max(np.abs(ref.data))
+        assert np.array_equal(col, hierarchy.first_fit_coloring(ref)), l
+        if l < L:
+            assert np.array_equal(agg, orc.P[l - 1].indices), l
+        else:
+            assert agg is None
+    # the coarsest operator as the dense solve holds it, and the direct term
+    ref = orc.A[-1].toarray()
+    assert np.max(np.abs(est.export_coarse(0) - ref)) <= 1e-14 * np.max(np.abs(ref))
+    assert abs(est.coarse_trace() - orc.coarse()) <= 1e-11 * abs(orc.coarse())
+
+
+def test_apply_restrict_prolong():
+    A, L = _graph(), 3
+    est = _est(A, L)
+    orc = _oracle("g3000", A, L)
+    rng = np.random.default_rng(1)
+    for l in range(1, L + 1):
+        Al = orc.A[l - 1]
+        X = rng.standard_normal((NRHS, Al.shape[0]))
+        Y = from_dev(est.apply(l, to_dev(X)))
+        ref = (Al @ X.T).T
+        assert np.max(np.abs(Y - ref)) <= 1e-13 * np.max(np.abs(ref)), l
+        if l < L:
+            P = orc.P[l - 1]
+            Xc = from_dev(est.restrict(l, to_dev(X)))
+            assert np.max(np.abs(Xc - (P.T @ X.T).T)) <= 1e-14 * np.max(np.abs(X)) * 16
+            E = rng.standard_normal((3, P.shape[1]))
+            Xf = from_dev(est.prolong(l, to_dev(E)))
+            assert np.max(np.abs(Xf - (P @ E.T).T)) <= 1e-15 * np.max(np.abs(E))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir64"])
+def test_sweeps_and_restricted_residual(precision):
+    A, L = _graph(), 3
+    est = _est(A, L, precision=precision)
+    orc = _oracle("g3000", A, L)
+    rng = np.random.default_rng(3)
+    for l in (1, 2):
+        Al, Pl = orc.A[l - 1], orc.P[l - 1]
+        col = hierarchy.first_fit_coloring(Al)
+        B = rng.standard_normal((NRHS, Al.shape[0]))
+        X = rng.standard_normal((NRHS, Al.shape[0]))
+        for sw in (1, 2):
+            for rev in (False, True):
+                got = from_dev(est.smooth(l, to_dev(B), to_dev(X), sw, rev))
+                for k in range(NRHS):
+                    ref = hierarchy.multicolour_gs_sweeps(Al, B[k], X[k], col, sw, rev)
+                    err = np.max(np.abs(got[k] - ref))
+                    assert err <= TOL[precision] * np.max(np.abs(ref)), (l, sw, rev, k, err)
+        xr, rc = est.smooth(l, to_dev(B), to_dev(X), 2, restrict=True)
+        x, r = from_dev(xr), from_dev(rc)
+        for k in range(NRHS):
+            ref = Pl.T @ (B[k] - Al @ x[k])
+            bound = np.max(abs(Pl.T) @ (np.abs(B[k]) + abs(Al) @ np.abs(x[k])))
+            assert np.max(np.abs(r[k] - ref)) <= TOL[precision] * bound, (l, k)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir64"])
+def test_solve_matches_exact(precision):
+    A, L = _graph(), 3
+    est = _est(A, L, precision=precision)
+    orc = _oracle("g3000", A, L)
+    rng = np.random.default_rng(2)
+    for l in (1, 2, 3):
+        B = rng.standard_normal((7, est.level_size(l)))
+        Y, rel = est.solve(l, to_dev(B))
+        assert np.all(rel <= 1e-12), (l, rel)
+        ref = orc.solver(l).solve(B.T).T
+        assert np.max(np.abs(from_dev(Y) - ref)) <= 1e-8 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir64"])
+def test_samples_match_oracle(precision):
+    A, L = _graph(), 3
+    est = _est(A, L, precision=precision, nb=16)
+    orc = _oracle("g3000", A, L)
+    for level, first, count in [(1, 0, 19), (2, 40, 5)]:
+        s, err = est.sample_level(level, 11, first, count, with_error=True)
+        ref = orc.sample(level, 11, first, count)
+        scale = quad_scale(orc.sample_parts(level, 11, first, count))
+        assert np.all(np.abs(s - ref) <= 1e-8 * scale), np.max(np.abs(s - ref) / scale)
+        assert np.all(err <= 1e-8)
+
+
+def test_mlmc_trace_matches_oracle_driver():
+    A, L = _graph(), 3
+    est = _est(A, L, precision="fp32_ir64", nb=32, alloc="giles")
+    orc = _oracle("g3000", A, L)
+    got = est.trace(2e-2, 3)
+    ref = mlmc.mlmc_trace(orc, 2e-2, 3, nb=32, alloc=mlmc.ALLOC_GILES)
+    assert got["n_samples"] == ref["n_samples"]
+    assert abs(got["trace"] - ref["trace"]) <= 1e-8 * abs(ref["trace"])
+    exact = np.trace(np.linalg.inv(A.toarray()))
+    assert abs(got["trace"].real - exact) <= 4 * got["rmsd"]
+
+
+def test_given_aggregates_reproduce_the_poisson_kind():
+    # the 2D Poisson matrix with the 2x2 aggregate maps: the same hierarchy as
+    # the matrix-free kind, so the same samples for the same seed
+    N, L = 32, 3
+    _, P = hierarchy.poisson_hierarchy(N, L)
+    maps = [p.indices for p in P]
+    A = operators.poisson2d(N)
+    est = _est(A, L, agg=maps, precision="fp64", nb=8)
+    for l in (1, 2):
+        Al, agg, col = est.export_csr(l)
+        assert np.array_equal(agg, maps[l - 1])
+        assert np.array_equal(col, hierarchy.site_coloring(N >> (l - 1)))
+    import paper_2108_11281_amd as m
+    ref = m.TraceEstimator("poisson2d", N, L, L, nb=8, precision="fp64", solve_tol=1e-12)
+    orc = _oracle("poisson32", A, L, maps)
+    for level in (1, 2):
+        s = est.sample_level(level, 5, 0, 8)
+        t = ref.sample_level(level, 5, 0, 8)
+        scale = quad_scale(orc.sample_parts(level, 5, 0, 8))
+        assert np.all(np.abs(s - t) <= 1e-8 * scale)
+        assert np.all(np.abs(s - orc.sample(level, 5, 0, 8)) <= 1e-8 * scale)
+
+
+def test_unsorted_repeated_and_zero_entries_are_canonicalised():
+    A = _graph(600, isolated=0, seed=4)
+    coo = A.tocoo()
+    rng = np.random.default_rng(5)
+    # split every entry in two halves, add explicit zeros, shuffle each row
+    rows = np.concatenate([coo.row, coo.row, coo.row[:50]])
+    cols = np.concatenate([coo.col, coo.col, coo.col[:50]])
+    vals = np.concatenate([0.5 * coo.data, 0.5 * coo.data, np.zeros(50)])
+    perm = rng.permutation(len(rows))
+    order = np.argsort(rows[perm], kind="stable")
+    rows, cols, vals = rows[perm][order], cols[perm][order], vals[perm][order]
+    indptr = np.concatenate([[0], np.cumsum(np.bincount(rows, minlength=A.shape[0]))])
+
+    class Raw:      # an already-CSR triple, handed over as is
+        pass
+    raw = Raw()
+    raw.indptr, raw.indices, raw.data = indptr, cols, vals
+    est = _est(raw, 2)
+    Al, _, _ = est.export_csr(1)
+    assert np.array_equal(Al.indptr, A.indptr) and np.array_equal(Al.indices, A.indices)
+    assert np.max(np.abs(Al.data - A.data)) <= 1e-15 * np.max(np.abs(A.data))
+
+
+def test_invalid_setup_is_rejected():
+    import paper_2108_11281_amd as m
+    A = _graph(400, isolated=0, seed=6).tolil()
+    bad = A.copy()
+    bad[3, 7] = -5.0        # not symmetric
+    with pytest.raises(m.MLMCError):
+        _est(bad.tocsr(), 2)
+    bad = A.copy()
+    bad[5, 5] = 0.0         # no diagonal in row 5
+    with pytest.raises(m.MLMCError):
+        _est(bad.tocsr(), 2)
+    agg = hierarchy.greedy_aggregation(A.tocsr())
+    gap = agg.copy()
+    gap[gap == 1] = 0       # aggregate 1 missing
+    with pytest.raises(m.MLMCError):
+        _est(A.tocsr(), 2, agg=[gap])
+    with pytest.raises(m.MLMCError):    # 20000 unknowns cannot be the coarsest level
+        _est(graph_laplacian(20000), 1 + 1, agg=[np.arange(20000)])
