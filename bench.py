@@ -20,6 +20,11 @@ Workloads (--workload):
   varcoef_batch: 32 uneven 3D diffusion problems (log-normal faces, sides
     32..128) sampled concurrently; one step = 64 level-1 samples of every
     problem (128 solves each); value = aggregate solves/s.
+  graph1m: a general sparse operator (the csr kind): the shifted Laplacian
+    L + 0.01 I of a random geometric graph with 2^20 vertices and mean degree
+    about 8, 4-level greedy aggregation hierarchy built by the library,
+    multicolour Gauss-Seidel V-cycle inside FP32 CG with FP64 refinement, MLMC
+    to relative error 1e-3.
 
 Printed JSON line: the contract fields plus `roofline` (the dominant kernel,
 timed with HIP events carried in its own dispatches during the timed steps),
@@ -444,13 +449,88 @@ def run_batch(args, m, torch):
              cpu, per_problem=per_problem, setup_s=round(setup_s, 2), compare=compare)
 
 
+def run_graph(args, m, torch):
+    from workloads import graph_laplacian, workload
+    w = workload("graph1m_fp32ir")
+    n, Ls, L = w["n"], w["levels_solver"], w["levels_mlmc"]
+    log("generate graph n=%d degree=%g shift=%g" % (n, w["degree"], w["shift"]))
+    A = graph_laplacian(n, degree=w["degree"], shift=w["shift"], seed=w["graph_seed"])
+    vc = dict(nu_pre=args.nu, nu_post=args.nu)
+    if args.omega > 0:
+        vc["omega"] = args.omega
+
+    def make(precision):
+        return m.TraceEstimator("csr", 0, Ls, L, matrix=A, precision=precision, nb=args.nb,
+                                solve_tol=w["solve_tol"], alloc=args.alloc, **vc)
+    t0 = time.perf_counter()
+    est = make("fp32_ir64")
+    setup_s = time.perf_counter() - t0
+    sizes = [est.level_size(l) for l in range(1, Ls + 1)]
+    log("setup %.2fs, level sizes %s" % (setup_s, sizes))
+    for i in range(args.warmup):
+        r = est.trace(args.eps, 1000 + i)
+        log("warmup %d: %.3fs N_l=%s iters=%d" % (i, r["seconds"], r["n_samples"],
+                                                  r["iterations"]))
+    est.set_timing(["rbgs_sweep"], stride=args.timing_stride)
+    est.reset_kernel_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = []
+    for i in range(args.steps):
+        r = est.trace(args.eps, i + 1)
+        runs.append(r)
+        log("step %d: %.3fs N_l=%s trace=%.6f rmsd=%.3f iters=%d"
+            % (i, r["seconds"], r["n_samples"], r["trace"].real, r["rmsd"], r["iterations"]))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    gs = est.kernel_stats("rbgs_sweep")
+    est.set_timing(True)
+    est.reset_kernel_stats()
+    est.trace(args.eps, 777)
+    kernels = kernel_table(est)
+    est.set_timing(False)
+    est.close()
+    ms_per_step = 1000.0 * elapsed / args.steps
+    compare = {}
+    if not args.no_compare:
+        log("plain FP64 MLMC, same workload")
+        e64 = make("fp64")
+        t64, n64 = timed_traces(e64, args, torch)
+        compare.update(fp64_mlmc_s=round(t64, 3), fp64_mlmc_n_samples=n64,
+                       speedup_vs_fp64_mlmc=round(t64 / (ms_per_step / 1000.0), 2))
+        log("plain FP64 MLMC %.3fs per trace, N_l=%s" % (t64, n64))
+        th, nh = timed_traces(e64, args, torch, "hutchinson")
+        compare.update(fp64_hutchinson_s=round(th, 3),
+                       fp64_hutchinson_n_samples=[v[0] for v in nh],
+                       speedup_vs_fp64_hutchinson=round(th / (ms_per_step / 1000.0), 2))
+        log("plain FP64 Hutchinson %.3fs per trace, N=%s" % (th, [v[0] for v in nh]))
+        e64.close()
+    config = {"workload": "graph_laplacian_rgg_n%d_deg%g_shift%g_L%d_greedyagg_nb%d_fp32ir64_eps%g"
+                          % (n, w["degree"], w["shift"], L, args.nb, args.eps),
+              "variant": "general CSR operator: FP32 CG + multicolour Gauss-Seidel V-cycle, "
+                         "FP64 reliable-update refinement",
+              "n": n, "nnz": int(A.nnz), "level_sizes": sizes, "levels": L, "nb": args.nb,
+              "eps": args.eps, "alloc": args.alloc, "solve_tol": w["solve_tol"],
+              "nu_pre": args.nu, "nu_post": args.nu,
+              "omega": args.omega if args.omega > 0 else 1.8}
+    contract(args, round(ms_per_step / 1000.0, 4), "s", False, ms_per_step, "f32+f64ir",
+             "synthetic (random geometric graph Laplacian + shift, Rademacher probes)", config,
+             hbm_roofline("multicolour Gauss-Seidel sweep: k_csr_gs<float> (all colour classes)",
+                          gs, args.timing_stride),
+             None, accuracy={"n_samples": [r["n_samples"] for r in runs],
+                             "rmsd_rel": [round(r["rmsd"] / abs(r["trace"].real), 7)
+                                          for r in runs]},
+             setup_s=round(setup_s, 3), kernels=kernels, compare=compare)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="poisson1024",
-                    choices=["poisson1024", "wilson256", "wilson512", "varcoef_batch"])
+                    choices=["poisson1024", "wilson256", "wilson512", "varcoef_batch",
+                             "graph1m"])
     ap.add_argument("--eps", type=float, default=1e-3)
     ap.add_argument("--N", type=int, default=1024)
     ap.add_argument("--levels", type=int, default=6)
@@ -458,6 +538,8 @@ def main():
     ap.add_argument("--alloc", default="giles")
     ap.add_argument("--nu", type=int, default=2, help="poisson1024: sweeps before and after")
     ap.add_argument("--workers", type=int, default=4, help="varcoef_batch: host workers")
+    ap.add_argument("--omega", type=float, default=0.0,
+                    help="graph1m: coarse-correction scaling (0 = the library default)")
     ap.add_argument("--train-batches", type=int, default=80,
                     help="wilson512: plain solves used for training = this x nb")
     ap.add_argument("--train-steps", type=int, default=2000)
@@ -491,6 +573,8 @@ def main():
         run_wilson(args, m, torch, 256, learned=False)
     elif args.workload == "wilson512":
         run_wilson(args, m, torch, 512, learned=True)
+    elif args.workload == "graph1m":
+        run_graph(args, m, torch)
     else:
         run_batch(args, m, torch)
 

@@ -66,7 +66,7 @@ Context::Context(const mlmc_operator& A, const mlmc_hierarchy& h, const mlmc_opt
         break;
       case MLMC_CSR:
         csr_ = true;
-        omega_ = opt_.omega > 0 ? opt_.omega : 1.8;
+        omega_ = opt_.omega > 0 ? opt_.omega : 1.0;
         build_csr(A, h.agg);
         break;
       case MLMC_WILSON2D:
@@ -448,12 +448,25 @@ void Context::finish_real_build() {
   // coarsest inverses (FP64 on the device), the direct trace term (Remark 4.2)
   c64 tr_s;
   invert_coarse(Ls_, &ainv_solver_, &tr_s);
+  // the transposed inverse, zero-padded to a multiple of 16 so that the MFMA
+  // tile kernel applies it for any coarsest size
   const int ns = (int)lv_[Ls_ - 1].n;
-  w64_.ainvT = dalloc_n<double>((int64_t)ns * ns);
-  dense_transpose<double>(ainv_solver_, w64_.ainvT, ns, s_);
+  const int ld = (ns + 15) / 16 * 16;
+  w64_.ainvT = dalloc_n<double>((int64_t)ld * ld);
+  w64_.ld = w32_.ld = ld;
+  if (ld == ns) {
+    dense_transpose<double>(ainv_solver_, w64_.ainvT, ns, s_);
+  } else {
+    double* t = dalloc_n<double>((int64_t)ns * ns);
+    dense_transpose<double>(ainv_solver_, t, ns, s_);
+    vec_zero<double>(w64_.ainvT, (int64_t)ld * ld, 1, nullptr, s_);
+    MLMC_HIP(hipMemcpy2DAsync(w64_.ainvT, sizeof(double) * ld, t, sizeof(double) * ns,
+                              sizeof(double) * ns, ns, hipMemcpyDeviceToDevice, s_));
+    dfree(t);
+  }
   if (opt_.precision == MLMC_FP32_IR64) {
-    w32_.ainvT = dalloc_n<float>((int64_t)ns * ns);
-    vec_convert<float, double>(w64_.ainvT, w32_.ainvT, (int64_t)ns * ns, 1, nullptr, s_);
+    w32_.ainvT = dalloc_n<float>((int64_t)ld * ld);
+    vec_convert<float, double>(w64_.ainvT, w32_.ainvT, (int64_t)ld * ld, 1, nullptr, s_);
   }
   if (L_ == Ls_) {
     coarse_trace_ = tr_s;
@@ -520,7 +533,8 @@ template <typename T>
 void Context::op_res_restrict(int l, const T* b, const T* x, T* rc, int nb, const int* act) {
   const Level& L = lv_[l - 1];
   if (csr_)
-    csr_restrict<T>(b, x, rc, csr_mat<T>(l), csr_agg<T>(l), true, nb, L.cols, act, s_);
+    csr_restrict<T>(b, x, rc, work<T>().vt[l - 1], csr_mat<T>(l), csr_agg<T>(l), nb, L.cols, act,
+                    s_);
   else if (varcoef_)
     varcoef_restrict<T>(b, x, rc, vc_faces<T>(l), vc_diag<T>(l), L.side, true, nb, L.cols, act,
                         s_);
@@ -544,7 +558,7 @@ template <typename T>
 void Context::op_restrict(int l, const T* x, T* xc, int nb, const int* act) {
   const Level& L = lv_[l - 1];
   if (csr_)
-    csr_restrict<T>(nullptr, x, xc, csr_mat<T>(l), csr_agg<T>(l), false, nb, L.cols, act, s_);
+    csr_restrict<T>(nullptr, x, xc, nullptr, csr_mat<T>(l), csr_agg<T>(l), nb, L.cols, act, s_);
   else if (varcoef_)
     varcoef_restrict<T>(nullptr, x, xc, nullptr, nullptr, L.side, false, nb, L.cols, act, s_);
   else
@@ -563,7 +577,7 @@ void Context::vcycle_vc(int l, const T* b, T* x, int nb, const int* act, c64* rz
   const int64_t n = lv_[l - 1].n;
   const double en = (double)sizeof(T) * (double)n;
   if (l == Ls_) {
-    dense_apply<T>(w.ainvT, b, x, (int)n, nb, act, s_);
+    dense_apply<T>(w.ainvT, b, x, (int)n, nb, act, s_, w.ld);
   } else if (lv_[l - 1].mcols > 0) {
     // fused out-of-place sweeps, ping-ponging between the level's scratch
     // buffer and x; the coarse correction is folded into the first post-sweep
@@ -666,7 +680,7 @@ void Context::vcycle(int l, const T* b, T* x, int nb, const int* act, c64* rz_pa
   const int64_t n = lv_[l - 1].n;
   const double en = (double)sizeof(T) * (double)n;
   if (l == Ls_) {
-    dense_apply<T>(w.ainvT, b, x, (int)n, nb, act, s_);
+    dense_apply<T>(w.ainvT, b, x, (int)n, nb, act, s_, w.ld);
     if (rz_partials) vec_dot_partials<T>(b, x, n, nb, act, rz_partials, s_);
     return;
   }
@@ -861,7 +875,7 @@ int Context::pcg(int l, const T* b, T* x, int nb, int* act, double tol, c64* las
       *beta = scal_[kBeta];
   vec_zero<T>(x, n, nb, act, s_);
   if (l == Ls_) {  // direct solve on the coarsest level
-    dense_apply<T>(w.ainvT, b, x, (int)n, nb, act, s_);
+    dense_apply<T>(w.ainvT, b, x, (int)n, nb, act, s_, w.ld);
     if (lastcorr) vec_zero<c64>(lastcorr, 1, nb, nullptr, s_);
     return 0;
   }
@@ -1095,7 +1109,7 @@ void Context::solve(int l, const double* b, double* y, int nb, c64* err, double*
   vec_zero<c64>(err, 1, nb, nullptr, s_);
   const double tol = opt_.solve_tol;
   if (l == Ls_) {
-    dense_apply<double>(w64_.ainvT, b, y, (int)n, nb, nullptr, s_);
+    dense_apply<double>(w64_.ainvT, b, y, (int)n, nb, nullptr, s_, w64_.ld);
   } else if (opt_.precision == MLMC_FP64) {
     MLMC_HIP(hipMemcpyAsync(act_inner_, act_outer_, sizeof(int) * nb,
                             hipMemcpyDeviceToDevice, s_));

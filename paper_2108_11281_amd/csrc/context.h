@@ -78,6 +78,7 @@ struct Work {
   // V-cycle right-hand side / solution / sweep scratch per level (0-based)
   std::vector<T*> vb, vx, vt;
   T* ainvT = nullptr;       // transposed inverse of the solver's coarsest operator
+  int ld = 0;               // its leading dimension (n rounded up to 16, zero padded)
   // complex operators: its real representation (2n x 2n, transposed) for the
   // real MFMA product on interleaved vectors
   typename Traits<T>::real* ainvR = nullptr;

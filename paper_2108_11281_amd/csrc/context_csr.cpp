@@ -210,47 +210,93 @@ void Context::csr_upload(Level& L, bool last) {
   auto to_f32 = [](const std::vector<double>& a) {
     return std::vector<float>(a.begin(), a.end());
   };
-  // the matrix by rows
+  // SELL-64 copy of rows rows[0..m-1] (row -1: an empty padding position):
+  // slice offsets, column indices and values; with skip_diag the diagonal is
+  // left out.  Padding entries hold value 0 and the row itself as column (0
+  // for padding positions), so they add nothing and read in bounds.
+  auto sell = [&](const std::vector<int>& rows, bool skip_diag, std::vector<int>& sptr,
+                  std::vector<int>& sci, std::vector<double>& sv) {
+    const int m = (int)rows.size();
+    const int ns = (m + 63) / 64;
+    sptr.assign(ns + 1, 0);
+    for (int sl = 0; sl < ns; ++sl) {
+      int w = 0;
+      for (int l = 0; l < 64 && sl * 64 + l < m; ++l) {
+        const int i = rows[sl * 64 + l];
+        if (i < 0) continue;
+        const int len = (int)(L.h_rp[i + 1] - L.h_rp[i]) - (skip_diag ? 1 : 0);
+        w = std::max(w, len);
+      }
+      MLMC_REQUIRE((int64_t)sptr[sl] + 64LL * w < (int64_t)1 << 31, MLMC_EINVAL,
+                   "sliced matrix copy exceeds 2^31 entries");
+      sptr[sl + 1] = sptr[sl] + 64 * w;
+    }
+    sci.assign(sptr[ns], 0);
+    sv.assign(sptr[ns], 0.0);
+    for (int sl = 0; sl < ns; ++sl) {
+      const int w = (sptr[sl + 1] - sptr[sl]) / 64;
+      for (int l = 0; l < 64; ++l) {
+        const int pos = sl * 64 + l;
+        const int i = pos < m ? rows[pos] : -1;
+        int e = 0;
+        if (i >= 0) {
+          for (int64_t q = L.h_rp[i]; q < L.h_rp[i + 1]; ++q) {
+            if (skip_diag && L.h_ci[q] == i) continue;
+            sci[sptr[sl] + e * 64 + l] = L.h_ci[q];
+            sv[sptr[sl] + e * 64 + l] = L.h_v[q];
+            ++e;
+          }
+        }
+        for (; e < w; ++e) sci[sptr[sl] + e * 64 + l] = i >= 0 ? i : 0;
+      }
+    }
+  };
+  // the matrix by rows: plain CSR (dense build) and its SELL-64 copy
   std::vector<int> rp32(L.h_rp.begin(), L.h_rp.end());
   const int* rp = up(rp32);
   const int* ci = up(L.h_ci);
-  L.A64 = {n, rp, ci, up(L.h_v)};
-  L.A32 = {n, rp, ci, up(to_f32(L.h_v))};
-  // the off-diagonal part with rows grouped by colour (ascending rows within a
-  // class) and the inverted diagonal per position
+  std::vector<int> all(n), sptr, sci;
+  std::vector<double> sv;
+  std::iota(all.begin(), all.end(), 0);
+  sell(all, false, sptr, sci, sv);
+  const int* dsptr = up(sptr);
+  const int* dsci = up(sci);
+  L.A64 = {n, rp, ci, up(L.h_v), dsptr, dsci, up(sv)};
+  L.A32 = {n, rp, ci, up(to_f32(L.h_v)), dsptr, dsci, up(to_f32(sv))};
+  // the off-diagonal part by colour class (ascending rows within a class), each
+  // class padded to whole slices, and the inverted diagonal per position
   const int ncol = n ? *std::max_element(L.h_colour.begin(), L.h_colour.end()) + 1 : 0;
-  std::vector<int> coff(ncol + 1, 0), crow(n);
-  for (int i = 0; i < n; ++i) ++coff[L.h_colour[i] + 1];
-  for (int c = 0; c < ncol; ++c) coff[c + 1] += coff[c];
+  std::vector<int> cnt(ncol, 0);
+  for (int i = 0; i < n; ++i) ++cnt[L.h_colour[i]];
+  std::vector<int> soff(ncol + 1, 0);
+  for (int c = 0; c < ncol; ++c) soff[c + 1] = soff[c] + (cnt[c] + 63) / 64;
+  std::vector<int> srow(64 * (size_t)soff[ncol], -1);
   {
-    std::vector<int> fill(coff.begin(), coff.end() - 1);
-    for (int i = 0; i < n; ++i) crow[fill[L.h_colour[i]]++] = i;
+    std::vector<int> fill(ncol);
+    for (int c = 0; c < ncol; ++c) fill[c] = 64 * soff[c];
+    for (int i = 0; i < n; ++i) srow[fill[L.h_colour[i]]++] = i;
   }
-  std::vector<int> cp(n + 1, 0), cci;
-  std::vector<double> cv, cdi(n);
-  for (int k = 0; k < n; ++k) {
-    const int i = crow[k];
-    for (int64_t e = L.h_rp[i]; e < L.h_rp[i + 1]; ++e) {
-      if (L.h_ci[e] == i) {
-        cdi[k] = 1.0 / L.h_v[e];
-      } else {
-        cci.push_back(L.h_ci[e]);
-        cv.push_back(L.h_v[e]);
-      }
+  std::vector<double> sdi(srow.size(), 0.0);
+  for (size_t k = 0; k < srow.size(); ++k)
+    if (srow[k] >= 0) {
+      const int i = srow[k];
+      for (int64_t q = L.h_rp[i]; q < L.h_rp[i + 1]; ++q)
+        if (L.h_ci[q] == i) sdi[k] = 1.0 / L.h_v[q];
     }
-    cp[k + 1] = (int)cci.size();
-  }
-  const int* dcrow = up(crow);
-  const int* dcp = up(cp);
-  const int* dcci = up(cci);
-  L.S64.crow = L.S32.crow = dcrow;
-  L.S64.cp = L.S32.cp = dcp;
-  L.S64.cci = L.S32.cci = dcci;
-  L.S64.cv = up(cv);
-  L.S64.cdi = up(cdi);
-  L.S32.cv = up(to_f32(cv));
-  L.S32.cdi = up(to_f32(cdi));
-  L.S64.coff = L.S32.coff = coff;
+  std::vector<int> gptr, gci;
+  std::vector<double> gv;
+  sell(srow, true, gptr, gci, gv);
+  const int* dsrow = up(srow);
+  const int* dgptr = up(gptr);
+  const int* dgci = up(gci);
+  L.S64.srow = L.S32.srow = dsrow;
+  L.S64.sptr = L.S32.sptr = dgptr;
+  L.S64.sci = L.S32.sci = dgci;
+  L.S64.sv = up(gv);
+  L.S64.sdi = up(sdi);
+  L.S32.sv = up(to_f32(gv));
+  L.S32.sdi = up(to_f32(sdi));
+  L.S64.soff = L.S32.soff = soff;
   if (last) return;
   // aggregation: member lists (ascending) and the scales 1/sqrt|J|
   const int nc = *std::max_element(L.h_agg.begin(), L.h_agg.end()) + 1;
@@ -368,7 +414,7 @@ void Context::vcycle_csr(int l, const T* b, T* x, int nb, const int* act, c64* r
   const int64_t n = L.n;
   const double en = (double)sizeof(T) * (double)n;
   if (l == Ls_) {
-    dense_apply<T>(w.ainvT, b, x, (int)n, nb, act, s_);
+    dense_apply<T>(w.ainvT, b, x, (int)n, nb, act, s_, w.ld);
   } else {
     const CsrMat<T>& A = csr_mat<T>(l);
     const CsrSweep<T>& S = csr_sweep<T>(l);
@@ -387,10 +433,10 @@ void Context::vcycle_csr(int l, const T* b, T* x, int nb, const int* act, c64* r
     T* bc = w.vb[l];
     T* ec = w.vx[l];
     if (pre == 0)
-      csr_restrict<T>(nullptr, b, bc, A, G, false, nb, L.cols, act, s_);
-    else
+      csr_restrict<T>(nullptr, b, bc, nullptr, A, G, nb, L.cols, act, s_);
+    else  // the residual passes through the level's scratch vector
       timed<T>(kTimResRestrict, 2.0 * en + enc + res_mat / nb, act, nb,
-               [&] { csr_restrict<T>(b, x, bc, A, G, true, nb, L.cols, act, s_); });
+               [&] { csr_restrict<T>(b, x, bc, w.vt[l - 1], A, G, nb, L.cols, act, s_); });
     vcycle_csr<T>(l + 1, bc, ec, nb, act, nullptr);
     timed<T>(kTimProlong, (pre == 0 ? 1.0 : 2.0) * en + enc, act, nb, [&] {
       csr_prolong<T>(ec, x, G, (int)n, omega_, pre == 0 ? 0.0 : 1.0, nb, act, s_);

@@ -126,10 +126,11 @@ void dense_set_identity_right(T* aug, int n, hipStream_t s);
 template <typename T>
 void dense_trace(const T* A, int n, c64* out, hipStream_t s);
 // Z[k][i] = sum_j At[j][i] B[k][j], k < nb: the coarsest solve z_k = A^{-1} b_k
-// with At the transposed inverse
+// with At the transposed inverse.  ld (0: n): leading dimension of At; with ld a
+// multiple of 16 (At zero-padded to ld x ld) the MFMA tile kernel runs for any n
 template <typename T>
 void dense_apply(const T* At, const T* B, T* Z, int n, int nb, const int* active,
-                 hipStream_t s);
+                 hipStream_t s, int ld = 0);
 // Mt (2n x 2n, real) = transposed real representation of the complex matrix
 // whose transpose is At, for dense_apply<R> on interleaved (re, im) vectors
 template <typename T, typename R>
@@ -328,22 +329,34 @@ void givens_solve(c64* H, c64* cs, c64* sn, c64* g, int* dims, c64* y, const int
                   int nb, hipStream_t s);
 
 // ----- general sparse (CSR) operators -----------------------------------------
-// A by rows, diagonal included (device arrays; values in precision T)
+// The kernels read sliced ELLPACK copies (SELL-64): slice s holds 64
+// consecutive rows (or colour-class positions) and w_s = (sptr[s+1] -
+// sptr[s]) / 64 entries per row, entry e of lane l at sptr[s] + 64 e + l, so
+// the column indices and values of a wave's rows load coalesced and every lane
+// runs the same trip count.  Entries keep the row's column order; rows shorter
+// than w_s are padded with value 0 and their own row as column.
+//
+// A by rows, diagonal included (device arrays; values in precision T); rp/ci/v
+// are the plain CSR arrays (dense build of the coarsest level)
 template <typename T>
 struct CsrMat {
   int n = 0;
-  const int* rp = nullptr;  // n + 1 row offsets
-  const int* ci = nullptr;  // column of each entry
-  const T* v = nullptr;     // value of each entry
+  const int* rp = nullptr;    // n + 1 row offsets
+  const int* ci = nullptr;    // column of each entry
+  const T* v = nullptr;       // value of each entry
+  const int* sptr = nullptr;  // SELL-64 slice offsets (ceil(n/64) + 1)
+  const int* sci = nullptr;
+  const T* sv = nullptr;
 };
-// the off-diagonal part with rows grouped by colour class: positions
-// coff[c]..coff[c+1]-1 hold class c (host offsets), crow[k] is the row at
-// position k, its entries cci/cv[cp[k]..cp[k+1]-1], cdi[k] = 1 / a_ii
+// the off-diagonal part with rows grouped by colour class, in SELL-64 slices
+// that never straddle two classes: class c owns slices soff[c]..soff[c+1]-1
+// (host offsets); position k = 64 s + l holds row srow[k] (-1: padding) with
+// sdi[k] = 1 / a_ii
 template <typename T>
 struct CsrSweep {
-  const int *crow = nullptr, *cp = nullptr, *cci = nullptr;
-  const T *cv = nullptr, *cdi = nullptr;
-  std::vector<int> coff;
+  const int *srow = nullptr, *sptr = nullptr, *sci = nullptr;
+  const T *sv = nullptr, *sdi = nullptr;
+  std::vector<int> soff;
 };
 // aggregation to the next level: agg[i] = aggregate of unknown i; the members
 // of J are arows[aptr[J]..aptr[J+1]-1] (ascending); fs[i] = cs[agg[i]] = 1/sqrt|J|
@@ -368,10 +381,11 @@ void csr_update_apply(const T* p_old, const T* z, const c64* beta, T* p_new, T* 
 template <typename T>
 void csr_gs_sweep(const T* b, T* x, const CsrSweep<T>& S, int n, int nb, int cols,
                   const int* active, bool reverse, hipStream_t s);
-// xc = R (b - A x) (residual) or R x, R = P^T
+// xc = R (b - A x) (b non-null; the residual goes through rtmp, n x nb) or
+// xc = R x (b null), R = P^T
 template <typename T>
-void csr_restrict(const T* b, const T* x, T* xc, const CsrMat<T>& A, const CsrAgg<T>& G,
-                  bool residual, int nb, int cols, const int* active, hipStream_t s);
+void csr_restrict(const T* b, const T* x, T* xc, T* rtmp, const CsrMat<T>& A,
+                  const CsrAgg<T>& G, int nb, int cols, const int* active, hipStream_t s);
 // x = beta x + omega P ec
 template <typename T>
 void csr_prolong(const T* ec, T* x, const CsrAgg<T>& G, int n, double omega, double beta, int nb,

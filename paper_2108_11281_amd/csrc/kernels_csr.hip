@@ -1,12 +1,15 @@
 // General sparse operators given in compressed sparse row form: residual and
 // product, the CG direction update fused with the product, one colour class of
 // a multicolour Gauss-Seidel sweep, and the aggregation transfers (orthonormal
-// piecewise constants, Sec. 4.1).  Vectors are RHS-major blocks.  A thread
-// takes one row (or one aggregate) and COLS right-hand sides, so each column
-// index and value of the row is loaded once for COLS columns; the lanes of a
-// wave take consecutive rows, whose gathers from x stay close in memory when
-// neighbouring unknowns carry nearby indices.  Row sums run in the stored
-// column order.  Indices are 32-bit (n, nnz < 2^31); column offsets 64-bit.
+// piecewise constants, Sec. 4.1).  Vectors are RHS-major blocks.  The matrix
+// is read from sliced ELLPACK copies (SELL-64, described with CsrMat): a wave
+// takes the 64 rows of one slice, so each load of column indices and values is
+// one coalesced 256-byte access and all lanes run the same trip count.  A
+// thread takes one row (or one aggregate) and COLS right-hand sides, so each
+// index and value is loaded once for COLS columns; the gathers from x stay
+// close in memory when neighbouring unknowns carry nearby indices.  Row sums
+// run in the stored column order.  Indices are 32-bit (n, nnz < 2^31); column
+// offsets 64-bit.
 #include "kernels.h"
 
 namespace mlmc {
@@ -16,12 +19,49 @@ __device__ __forceinline__ bool col_on(const int* active, int col, int nb) {
   return col < nb && (!active || active[col]);
 }
 
-// r = b - A x (or r = A x when b is null); partials: per column and block of
-// |r|^2 (or x^T A x)
+// Row sum over one SELL-64 slice: acc[q] += sum_e v_e x_q[j_e] for the entries
+// of this lane's row, in stored order.  Indices and values of four entries are
+// loaded before their gathers, so several gathers of a lane are in flight.
+template <typename T, int COLS>
+__device__ __forceinline__ void sell_row_sum(const int* __restrict__ sci,
+                                             const T* __restrict__ sv, int base, int w,
+                                             const T* __restrict__ x, int64_t n, int col0,
+                                             const bool* on, T* acc) {
+  int e = 0;
+  for (; e + 4 <= w; e += 4) {
+    int j[4];
+    T a[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      j[u] = sci[base + (e + u) * 64];
+      a[u] = sv[base + (e + u) * 64];
+    }
+#pragma unroll
+    for (int q = 0; q < COLS; ++q) {
+      if (!on[q]) continue;
+      const T* xq = x + (int64_t)(col0 + q) * n;
+      T g[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) g[u] = xq[j[u]];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[q] += a[u] * g[u];
+    }
+  }
+  for (; e < w; ++e) {
+    const int j = sci[base + e * 64];
+    const T a = sv[base + e * 64];
+#pragma unroll
+    for (int q = 0; q < COLS; ++q)
+      if (on[q]) acc[q] += a * x[(int64_t)(col0 + q) * n + j];
+  }
+}
+
+// r = b - A x (or r = A x when b is null); partials (nullable): per column and
+// block of |r|^2 (or x^T A x).  Block = 4 slices = 256 consecutive rows.
 template <typename Tb, typename T, typename Tr, int COLS>
 __global__ __launch_bounds__(kThreads) void k_csr_residual(
     const Tb* __restrict__ b, const T* __restrict__ x, Tr* __restrict__ r,
-    const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ v, int n,
+    const int* __restrict__ sptr, const int* __restrict__ sci, const T* __restrict__ sv, int n,
     int nb, const int* active, c64* partials, int* tlog) {
   __shared__ double red[16];
   const int col0 = blockIdx.y * COLS;
@@ -37,14 +77,9 @@ __global__ __launch_bounds__(kThreads) void k_csr_residual(
     acc[q] = T(0);
   }
   if (in) {
-    const int e1 = rp[i + 1];
-    for (int e = rp[i]; e < e1; ++e) {
-      const int j = ci[e];
-      const T a = v[e];
-#pragma unroll
-      for (int q = 0; q < COLS; ++q)
-        if (on[q]) acc[q] += a * x[(int64_t)(col0 + q) * n + j];
-    }
+    const int sl = i >> 6;
+    const int base = sptr[sl] + (i & 63);
+    sell_row_sum<T, COLS>(sci, sv, base, (sptr[sl + 1] - sptr[sl]) >> 6, x, n, col0, on, acc);
   }
 #pragma unroll
   for (int q = 0; q < COLS; ++q) {
@@ -74,8 +109,8 @@ __global__ __launch_bounds__(kThreads) void k_csr_residual(
 template <typename T, int COLS>
 __global__ __launch_bounds__(kThreads) void k_csr_update_apply(
     const T* __restrict__ p_old, const T* __restrict__ z, const c64* __restrict__ beta,
-    T* __restrict__ p_new, T* __restrict__ qv, const int* __restrict__ rp,
-    const int* __restrict__ ci, const T* __restrict__ v, int n, int nb, const int* active,
+    T* __restrict__ p_new, T* __restrict__ qv, const int* __restrict__ sptr,
+    const int* __restrict__ sci, const T* __restrict__ sv, int n, int nb, const int* active,
     c64* partials, int* tlog) {
   __shared__ double red[16];
   const int col0 = blockIdx.y * COLS;
@@ -92,10 +127,12 @@ __global__ __launch_bounds__(kThreads) void k_csr_update_apply(
     acc[q] = T(0);
   }
   if (in) {
-    const int e1 = rp[i + 1];
-    for (int e = rp[i]; e < e1; ++e) {
-      const int j = ci[e];
-      const T a = v[e];
+    const int sl = i >> 6;
+    const int base = sptr[sl] + (i & 63);
+    const int w = (sptr[sl + 1] - sptr[sl]) >> 6;
+    for (int e = 0; e < w; ++e) {
+      const int j = sci[base + e * 64];
+      const T a = sv[base + e * 64];
 #pragma unroll
       for (int q = 0; q < COLS; ++q) {
         if (!on[q]) continue;
@@ -120,51 +157,45 @@ __global__ __launch_bounds__(kThreads) void k_csr_update_apply(
   }
 }
 
-// one colour class of a Gauss-Seidel sweep, in place: for the sorted positions
-// k0..k0+cnt-1 (rows crow[k] of one class, an independent set of the matrix
-// graph) x_i = (b_i - sum_{j != i} a_ij x_j) / a_ii; the off-diagonal entries
-// of position k are cci/cv[cp[k]..cp[k+1]-1], cdi[k] = 1 / a_ii
+// one colour class of a Gauss-Seidel sweep, in place: the class owns slices
+// s0..s1-1; position k = 64 s + l holds row i = srow[k] (an independent set of
+// the matrix graph; -1 pads the last slice) and x_i = (b_i - sum_{j != i}
+// a_ij x_j) / a_ii with the off-diagonal entries of the slice
 template <typename T, int COLS>
 __global__ __launch_bounds__(kThreads) void k_csr_gs(
-    const T* __restrict__ b, T* __restrict__ x, const int* __restrict__ crow,
-    const int* __restrict__ cp, const int* __restrict__ cci, const T* __restrict__ cv,
-    const T* __restrict__ cdi, int k0, int cnt, int n, int nb, const int* active, int* tlog) {
+    const T* __restrict__ b, T* __restrict__ x, const int* __restrict__ srow,
+    const int* __restrict__ sptr, const int* __restrict__ sci, const T* __restrict__ sv,
+    const T* __restrict__ sdi, int s0, int s1, int n, int nb, const int* active, int* tlog) {
   const int col0 = blockIdx.y * COLS;
   if (tlog && blockIdx.x == 0 && threadIdx.x < COLS && col0 + (int)threadIdx.x < nb)
     tlog[col0 + threadIdx.x] = active ? active[col0 + threadIdx.x] : 1;
-  const int t = blockIdx.x * kThreads + threadIdx.x;
-  if (t >= cnt) return;
-  const int k = k0 + t;
-  const int i = crow[k];
+  const int sl = s0 + blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  if (sl >= s1) return;
+  const int k = sl * 64 + (threadIdx.x & 63);
+  const int i = srow[k];
+  if (i < 0) return;
   bool on[COLS];
-  T acc[COLS];
+  T acc[COLS], sum[COLS];
 #pragma unroll
   for (int q = 0; q < COLS; ++q) {
     on[q] = col_on(active, col0 + q, nb);
     acc[q] = on[q] ? b[(int64_t)(col0 + q) * n + i] : T(0);
+    sum[q] = T(0);
   }
-  const int e1 = cp[k + 1];
-  for (int e = cp[k]; e < e1; ++e) {
-    const int j = cci[e];
-    const T a = cv[e];
-#pragma unroll
-    for (int q = 0; q < COLS; ++q)
-      if (on[q]) acc[q] -= a * x[(int64_t)(col0 + q) * n + j];
-  }
-  const T d = cdi[k];
+  sell_row_sum<T, COLS>(sci, sv, sptr[sl] + (threadIdx.x & 63), (sptr[sl + 1] - sptr[sl]) >> 6,
+                        x, n, col0, on, sum);
+  const T d = sdi[k];
 #pragma unroll
   for (int q = 0; q < COLS; ++q)
-    if (on[q]) x[(int64_t)(col0 + q) * n + i] = acc[q] * d;
+    if (on[q]) x[(int64_t)(col0 + q) * n + i] = (acc[q] - sum[q]) * d;
 }
 
-// rc_J = s_J sum_{i in J} (b - A x)_i when residual, else s_J sum_{i in J} x_i;
-// a thread per aggregate J, whose members are arows[aptr[J]..aptr[J+1]-1]
+// rc_J = s_J sum_{i in J} r_i, a thread per aggregate J, members in ascending order
 template <typename T, int COLS>
-__global__ __launch_bounds__(kThreads) void k_csr_restrict(
-    const T* __restrict__ b, const T* __restrict__ x, T* __restrict__ rc,
-    const int* __restrict__ aptr, const int* __restrict__ arows, const T* __restrict__ cs,
-    const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ v, int n,
-    int nc, int residual, int nb, const int* active, int* tlog) {
+__global__ __launch_bounds__(kThreads) void k_csr_agg_sum(
+    const T* __restrict__ r, T* __restrict__ rc, const int* __restrict__ aptr,
+    const int* __restrict__ arows, const T* __restrict__ cs, int n, int nc, int nb,
+    const int* active, int* tlog) {
   const int col0 = blockIdx.y * COLS;
   if (tlog && blockIdx.x == 0 && threadIdx.x < COLS && col0 + (int)threadIdx.x < nb)
     tlog[col0 + threadIdx.x] = active ? active[col0 + threadIdx.x] : 1;
@@ -180,26 +211,9 @@ __global__ __launch_bounds__(kThreads) void k_csr_restrict(
   const int m1 = aptr[J + 1];
   for (int m = aptr[J]; m < m1; ++m) {
     const int i = arows[m];
-    if (residual) {
-      T s[COLS];
 #pragma unroll
-      for (int q = 0; q < COLS; ++q) s[q] = T(0);
-      const int e1 = rp[i + 1];
-      for (int e = rp[i]; e < e1; ++e) {
-        const int j = ci[e];
-        const T a = v[e];
-#pragma unroll
-        for (int q = 0; q < COLS; ++q)
-          if (on[q]) s[q] += a * x[(int64_t)(col0 + q) * n + j];
-      }
-#pragma unroll
-      for (int q = 0; q < COLS; ++q)
-        if (on[q]) acc[q] += b[(int64_t)(col0 + q) * n + i] - s[q];
-    } else {
-#pragma unroll
-      for (int q = 0; q < COLS; ++q)
-        if (on[q]) acc[q] += x[(int64_t)(col0 + q) * n + i];
-    }
+    for (int q = 0; q < COLS; ++q)
+      if (on[q]) acc[q] += r[(int64_t)(col0 + q) * n + i];
   }
   const T sj = cs[J];
 #pragma unroll
@@ -256,8 +270,8 @@ void csr_residual(const Tb* b, const T* x, Tr* r, const CsrMat<T>& A, int nb, in
                   const int* active, c64* partials, hipStream_t s) {
   if (A.n == 0) return;
   CSR_COLS_DISPATCH(cols, MLMC_LAUNCH((k_csr_residual<Tb, T, Tr, C>), csr_grid(A.n, nb, C),
-                                      dim3(kThreads), 0, s, b, x, r, A.rp, A.ci, A.v, A.n, nb,
-                                      active, partials, timing_log()));
+                                      dim3(kThreads), 0, s, b, x, r, A.sptr, A.sci, A.sv, A.n,
+                                      nb, active, partials, timing_log()));
 }
 
 template <typename T>
@@ -266,32 +280,38 @@ void csr_update_apply(const T* p_old, const T* z, const c64* beta, T* p_new, T* 
                       hipStream_t s) {
   if (A.n == 0) return;
   CSR_COLS_DISPATCH(cols, MLMC_LAUNCH((k_csr_update_apply<T, C>), csr_grid(A.n, nb, C),
-                                      dim3(kThreads), 0, s, p_old, z, beta, p_new, q, A.rp, A.ci,
-                                      A.v, A.n, nb, active, partials, timing_log()));
+                                      dim3(kThreads), 0, s, p_old, z, beta, p_new, q, A.sptr,
+                                      A.sci, A.sv, A.n, nb, active, partials, timing_log()));
 }
 
 template <typename T>
 void csr_gs_sweep(const T* b, T* x, const CsrSweep<T>& S, int n, int nb, int cols,
                   const int* active, bool reverse, hipStream_t s) {
-  const int classes = (int)S.coff.size() - 1;
+  const int classes = (int)S.soff.size() - 1;
   for (int t = 0; t < classes; ++t) {
     const int c = reverse ? classes - 1 - t : t;
-    const int k0 = S.coff[c], cnt = S.coff[c + 1] - S.coff[c];
-    if (cnt == 0) continue;
-    CSR_COLS_DISPATCH(cols, MLMC_LAUNCH((k_csr_gs<T, C>), csr_grid(cnt, nb, C), dim3(kThreads), 0,
-                                        s, b, x, S.crow, S.cp, S.cci, S.cv, S.cdi, k0, cnt, n, nb,
-                                        active, timing_log()));
+    const int s0 = S.soff[c], s1 = S.soff[c + 1];
+    if (s1 == s0) continue;
+    const int per = kThreads / 64;  // slices per block
+    const dim3 g((unsigned)((s1 - s0 + per - 1) / per), (unsigned)((nb + cols - 1) / cols));
+    CSR_COLS_DISPATCH(cols, MLMC_LAUNCH((k_csr_gs<T, C>), g, dim3(kThreads), 0, s, b, x, S.srow,
+                                        S.sptr, S.sci, S.sv, S.sdi, s0, s1, n, nb, active,
+                                        timing_log()));
   }
 }
 
 template <typename T>
-void csr_restrict(const T* b, const T* x, T* xc, const CsrMat<T>& A, const CsrAgg<T>& G,
-                  bool residual, int nb, int cols, const int* active, hipStream_t s) {
+void csr_restrict(const T* b, const T* x, T* xc, T* rtmp, const CsrMat<T>& A,
+                  const CsrAgg<T>& G, int nb, int cols, const int* active, hipStream_t s) {
   if (G.nc == 0) return;
-  CSR_COLS_DISPATCH(cols, MLMC_LAUNCH((k_csr_restrict<T, C>), csr_grid(G.nc, nb, C),
-                                      dim3(kThreads), 0, s, b, x, xc, G.aptr, G.arows, G.cs, A.rp,
-                                      A.ci, A.v, A.n, G.nc, residual ? 1 : 0, nb, active,
-                                      timing_log()));
+  const T* src = x;
+  if (b) {
+    csr_residual<T, T, T>(b, x, rtmp, A, nb, cols, active, nullptr, s);
+    src = rtmp;
+  }
+  CSR_COLS_DISPATCH(cols, MLMC_LAUNCH((k_csr_agg_sum<T, C>), csr_grid(G.nc, nb, C),
+                                      dim3(kThreads), 0, s, src, xc, G.aptr, G.arows, G.cs, A.n,
+                                      G.nc, nb, active, timing_log()));
 }
 
 template <typename T>
@@ -313,8 +333,8 @@ void csr_dense(const CsrMat<double>& A, double* aug, hipStream_t s) {
                                     int, int, const int*, c64*, hipStream_t);                 \
   template void csr_gs_sweep<T>(const T*, T*, const CsrSweep<T>&, int, int, int, const int*,   \
                                 bool, hipStream_t);                                           \
-  template void csr_restrict<T>(const T*, const T*, T*, const CsrMat<T>&, const CsrAgg<T>&,    \
-                                bool, int, int, const int*, hipStream_t);                     \
+  template void csr_restrict<T>(const T*, const T*, T*, T*, const CsrMat<T>&,                  \
+                                const CsrAgg<T>&, int, int, const int*, hipStream_t);         \
   template void csr_prolong<T>(const T*, T*, const CsrAgg<T>&, int, double, double, int,       \
                                const int*, hipStream_t);
 CSR_INST(float)

@@ -480,12 +480,15 @@ template <> struct Mfma<double> {
 
 // A 256-thread block computes one 16 x 16 tile of Z; its four waves split the
 // reduction index (chunk ranges of 16), each keeping UNR chunks of loads in
-// flight, and the four partial tiles are summed in LDS in wave order.
+// flight, and the four partial tiles are summed in LDS in wave order.  At has
+// leading dimension ld (a multiple of 16; rows and columns n..ld-1 are zero);
+// B and Z columns have length n, so the tail of the last tile reads zeros and
+// writes nothing.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_dense_apply_mfma(const T* __restrict__ At,
                                                                const T* __restrict__ B,
-                                                               T* __restrict__ Z, int n, int nb,
-                                                               const int* active) {
+                                                               T* __restrict__ Z, int n, int ld,
+                                                               int nb, const int* active) {
   constexpr int UNR = 4;
   __shared__ T part[4][4][64];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -495,7 +498,7 @@ __global__ __launch_bounds__(kThreads) void k_dense_apply_mfma(const T* __restri
   const int row = m0 + c;               // RHS whose A-operand this lane supplies
   const bool row_ok = row < nb;
   const T* brow = B + (int64_t)(row_ok ? row : 0) * n;
-  const int chunks = n / 16;
+  const int chunks = ld / 16;
   const int cbeg = wave * chunks / 4, cend = (wave + 1) * chunks / 4;
   typename Mfma<T>::acc_t acc = {0, 0, 0, 0};
   int ch = cbeg;
@@ -506,8 +509,8 @@ __global__ __launch_bounds__(kThreads) void k_dense_apply_mfma(const T* __restri
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int j = (ch + u) * 16 + 4 * g + s;
-        a[u][s] = row_ok ? brow[j] : (T)0;
-        bv[u][s] = At[(int64_t)j * n + i0 + c];
+        a[u][s] = (row_ok && j < n) ? brow[j] : (T)0;
+        bv[u][s] = At[(int64_t)j * ld + i0 + c];
       }
 #pragma unroll
     for (int u = 0; u < UNR; ++u)
@@ -519,8 +522,8 @@ __global__ __launch_bounds__(kThreads) void k_dense_apply_mfma(const T* __restri
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int j = ch * 16 + 4 * g + s;
-      a[s] = row_ok ? brow[j] : (T)0;
-      bv[s] = At[(int64_t)j * n + i0 + c];
+      a[s] = (row_ok && j < n) ? brow[j] : (T)0;
+      bv[s] = At[(int64_t)j * ld + i0 + c];
     }
 #pragma unroll
     for (int s = 0; s < 4; ++s) acc = Mfma<T>::step(a[s], bv[s], acc);
@@ -533,7 +536,7 @@ __global__ __launch_bounds__(kThreads) void k_dense_apply_mfma(const T* __restri
     for (int r = 0; r < 4; ++r) {
       const T v = ((part[0][r][lane] + part[1][r][lane]) + part[2][r][lane]) + part[3][r][lane];
       const int k = m0 + Mfma<T>::row(g, r);
-      if (k < nb && (!active || active[k])) Z[(int64_t)k * n + i0 + c] = v;
+      if (k < nb && (!active || active[k]) && i0 + c < n) Z[(int64_t)k * n + i0 + c] = v;
     }
   }
 }
@@ -712,15 +715,17 @@ void dense_trace(const T* A, int n, c64* out, hipStream_t s) {
 
 template <typename T>
 void dense_apply(const T* At, const T* B, T* Z, int n, int nb, const int* active,
-                 hipStream_t s) {
+                 hipStream_t s, int ld) {
+  if (ld == 0) ld = n;
   if constexpr (std::is_same<T, float>::value || std::is_same<T, double>::value) {
-    if (n % 16 == 0) {
-      dim3 grid((unsigned)(n / 16), (unsigned)((nb + 15) / 16));
-      hipLaunchKernelGGL(k_dense_apply_mfma<T>, grid, dim3(kThreads), 0, s, At, B, Z, n, nb,
+    if (ld % 16 == 0) {
+      dim3 grid((unsigned)(ld / 16), (unsigned)((nb + 15) / 16));
+      hipLaunchKernelGGL(k_dense_apply_mfma<T>, grid, dim3(kThreads), 0, s, At, B, Z, n, ld, nb,
                          active);
       return;
     }
   }
+  if (ld != n) throw Error(MLMC_EINVAL, "dense_apply: padded inverse needs ld % 16 == 0");
   dim3 grid((unsigned)((n + 63) / 64), (unsigned)((nb + 3) / 4));
   hipLaunchKernelGGL(k_dense_apply<T>, grid, dim3(kThreads), 0, s, At, B, Z, n, nb, active);
 }
@@ -746,7 +751,7 @@ void dense_apply(const T* At, const T* B, T* Z, int n, int nb, const int* active
   template void dense_extract_right<T>(const T*, int, T*, hipStream_t);                  \
   template void dense_set_identity_right<T>(T*, int, hipStream_t);                       \
   template void dense_trace<T>(const T*, int, c64*, hipStream_t);                        \
-  template void dense_apply<T>(const T*, const T*, T*, int, int, const int*, hipStream_t);
+  template void dense_apply<T>(const T*, const T*, T*, int, int, const int*, hipStream_t, int);
 
 MLMC_INST_T(float)
 MLMC_INST_T(double)
