@@ -479,8 +479,9 @@ def run_graph(args, m, torch):
     for i in range(args.steps):
         r = est.trace(args.eps, i + 1)
         runs.append(r)
-        log("step %d: %.3fs N_l=%s trace=%.6f rmsd=%.3f iters=%d"
-            % (i, r["seconds"], r["n_samples"], r["trace"].real, r["rmsd"], r["iterations"]))
+        log("step %d: %.3fs N_l=%s trace=%.6f rmsd=%.3f iters=%d level_s=%s"
+            % (i, r["seconds"], r["n_samples"], r["trace"].real, r["rmsd"], r["iterations"],
+               [round(v, 3) for v in r["level_seconds"]]))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     gs = est.kernel_stats("rbgs_sweep")

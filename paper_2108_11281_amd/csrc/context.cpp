@@ -495,7 +495,7 @@ template <typename T>
 void Context::op_apply(int l, const T* x, T* y, int nb, const int* act, c64* partials) {
   const Level& L = lv_[l - 1];
   if (csr_)
-    csr_residual<T, T, T>(nullptr, x, y, csr_mat<T>(l), nb, L.cols, act, partials, s_);
+    csr_residual<T, T, T>(nullptr, x, y, csr_mat<T>(l), nb, csr_cols(L, nb), act, partials, s_);
   else if (varcoef_)
     varcoef_residual<T, T, T>(nullptr, x, y, vc_faces<T>(l), vc_diag<T>(l), L.side, nb, L.cols,
                               act, partials, s_);
@@ -508,7 +508,7 @@ void Context::op_residual(int l, const Tb* b, const Tx* x, Tr* r, int nb, const 
                           c64* partials) {
   const Level& L = lv_[l - 1];
   if (csr_)
-    csr_residual<Tb, Tx, Tr>(b, x, r, csr_mat<Tx>(l), nb, L.cols, act, partials, s_);
+    csr_residual<Tb, Tx, Tr>(b, x, r, csr_mat<Tx>(l), nb, csr_cols(L, nb), act, partials, s_);
   else if (varcoef_)
     varcoef_residual<Tb, Tx, Tr>(b, x, r, vc_faces<Tx>(l), vc_diag<Tx>(l), L.side, nb, L.cols,
                                  act, partials, s_);
@@ -521,7 +521,8 @@ void Context::op_update_apply(int l, const T* p_old, const T* z, const c64* beta
                               T* q, int nb, const int* act) {
   const Level& L = lv_[l - 1];
   if (csr_)
-    csr_update_apply<T>(p_old, z, beta, p_new, q, csr_mat<T>(l), nb, L.cols, act, partials_, s_);
+    csr_update_apply<T>(p_old, z, beta, p_new, q, csr_mat<T>(l), nb, csr_cols(L, nb), act,
+                        partials_, s_);
   else if (varcoef_)
     varcoef_update_apply<T>(p_old, z, beta, p_new, q, vc_faces<T>(l), vc_diag<T>(l), L.side, nb,
                             L.cols, act, partials_, s_);
@@ -533,8 +534,8 @@ template <typename T>
 void Context::op_res_restrict(int l, const T* b, const T* x, T* rc, int nb, const int* act) {
   const Level& L = lv_[l - 1];
   if (csr_)
-    csr_restrict<T>(b, x, rc, work<T>().vt[l - 1], csr_mat<T>(l), csr_agg<T>(l), nb, L.cols, act,
-                    s_);
+    csr_restrict<T>(b, x, rc, work<T>().vt[l - 1], csr_mat<T>(l), csr_agg<T>(l), nb,
+                    csr_cols(L, nb), act, s_);
   else if (varcoef_)
     varcoef_restrict<T>(b, x, rc, vc_faces<T>(l), vc_diag<T>(l), L.side, true, nb, L.cols, act,
                         s_);
@@ -558,7 +559,8 @@ template <typename T>
 void Context::op_restrict(int l, const T* x, T* xc, int nb, const int* act) {
   const Level& L = lv_[l - 1];
   if (csr_)
-    csr_restrict<T>(nullptr, x, xc, nullptr, csr_mat<T>(l), csr_agg<T>(l), nb, L.cols, act, s_);
+    csr_restrict<T>(nullptr, x, xc, nullptr, csr_mat<T>(l), csr_agg<T>(l), nb, csr_cols(L, nb),
+                    act, s_);
   else if (varcoef_)
     varcoef_restrict<T>(nullptr, x, xc, nullptr, nullptr, L.side, false, nb, L.cols, act, s_);
   else
@@ -1375,7 +1377,8 @@ void Context::smooth_fp64(int level, int nrhs, int sweeps, bool reverse, const d
                       nullptr, false, reverse);
     } else if (csr_) {
       for (int i = 0; i < sweeps; ++i)
-        csr_gs_sweep<T>(bt, xa, csr_sweep<T>(level), (int)n, nrhs, L.cols, nullptr, reverse, s_);
+        csr_gs_sweep<T>(bt, xa, csr_sweep<T>(level), (int)n, nrhs, csr_cols(L, nrhs), nullptr,
+                        reverse, s_);
     } else if (varcoef_) {
       for (int i = 0; i < sweeps; ++i) {
         if (L.mcols > 0) {

@@ -43,6 +43,7 @@ struct Level {
   double *kf64 = nullptr, *dg64 = nullptr, *kl64 = nullptr;
   float *dg32 = nullptr, *kl32 = nullptr;
   int cols = 4;  // right-hand sides per thread of the stencil kernels (autotuned)
+  int cols_narrow = 4;  // CSR kernels: the same for launches of at most 16 columns
   int bsr_form[2] = {0, 0};  // block-stencil kernel form, complex64 / complex128 (autotuned)
   int mcols = 0;  // right-hand sides per wave of the fused 3D sweep (0: in-place sweeps)
   // POISSON2D: rows per segment of the fused sweep, FP32 and FP64 (autotuned)
@@ -166,6 +167,10 @@ class Context {
   template <typename T> int bsr_form(const Level& L, int nb) const {
     return nb >= 32 ? L.bsr_form[sizeof(T) == sizeof(c64) ? 1 : 0] : 0;
   }
+  // right-hand sides per thread of the CSR kernels on level L for nb columns
+  // (narrow batches, such as the pilot and the first samples of a level, have
+  // their own tuned value)
+  int csr_cols(const Level& L, int nb) const { return nb <= 16 ? L.cols_narrow : L.cols; }
   // red-black sweeps fused into one pass of the Poisson smoother on level l
   int sweeps_per_pass(int l) const { return lv_[l - 1].side >= 64 ? 2 : 1; }
   template <typename T> int gs_rows(int l) const {

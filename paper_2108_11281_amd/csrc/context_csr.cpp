@@ -366,37 +366,42 @@ void Context::build_csr(const mlmc_operator& A, const int32_t* const* aggs) {
 }
 
 // Autotuner of the CSR kernels: per smoothed level, time one Gauss-Seidel
-// sweep over all nb columns with 1, 2, 4 and 8 right-hand sides per thread (the
-// results are identical; only the reuse of the row's indices and values and
-// the parallelism differ) and keep the fastest for every CSR kernel of that
-// level.  Runs once at setup on the library's own work vectors.
+// sweep with 1, 2, 4 and 8 right-hand sides per thread (the results are
+// identical; only the reuse of the row's indices and values and the
+// parallelism differ), once over all nb columns and once over a narrow batch
+// of 16, and keep the fastest of each for every CSR kernel of that level.
+// Runs once at setup on the library's own work vectors.
 void Context::tune_csr() {
   const bool fp32 = opt_.precision == MLMC_FP32_IR64;
   hipEvent_t a = event(), b = event();
   for (int l = 1; l < Ls_; ++l) {
     Level& L = lv_[l - 1];
-    float best = 1e30f;
-    int best_cols = 4;
-    for (int cols : {1, 2, 4, 8}) {
-      float ms = 0.f;
-      for (int rep = 0; rep < 3; ++rep) {
-        MLMC_HIP(hipEventRecord(a, s_));
-        if (fp32)
-          csr_gs_sweep<float>(w32_.r, w32_.x, L.S32, (int)L.n, nb_, cols, nullptr, false, s_);
-        else
-          csr_gs_sweep<double>(w64_.r, w64_.x, L.S64, (int)L.n, nb_, cols, nullptr, false, s_);
-        MLMC_HIP(hipEventRecord(b, s_));
-        MLMC_HIP(hipEventSynchronize(b));
-        float t = 0.f;
-        MLMC_HIP(hipEventElapsedTime(&t, a, b));
-        if (rep > 0) ms += t;  // the first run warms caches and code
+    for (int narrow = 0; narrow < 2; ++narrow) {
+      const int ncols = narrow ? std::min(nb_, 16) : nb_;
+      float best = 1e30f;
+      int best_cols = 4;
+      for (int cols : {1, 2, 4, 8}) {
+        float ms = 0.f;
+        for (int rep = 0; rep < 3; ++rep) {
+          MLMC_HIP(hipEventRecord(a, s_));
+          if (fp32)
+            csr_gs_sweep<float>(w32_.r, w32_.x, L.S32, (int)L.n, ncols, cols, nullptr, false, s_);
+          else
+            csr_gs_sweep<double>(w64_.r, w64_.x, L.S64, (int)L.n, ncols, cols, nullptr, false,
+                                 s_);
+          MLMC_HIP(hipEventRecord(b, s_));
+          MLMC_HIP(hipEventSynchronize(b));
+          float t = 0.f;
+          MLMC_HIP(hipEventElapsedTime(&t, a, b));
+          if (rep > 0) ms += t;  // the first run warms caches and code
+        }
+        if (ms < best) {
+          best = ms;
+          best_cols = cols;
+        }
       }
-      if (ms < best) {
-        best = ms;
-        best_cols = cols;
-      }
+      (narrow ? L.cols_narrow : L.cols) = best_cols;
     }
-    L.cols = best_cols;
   }
   ev_pool_.push_back(a);
   ev_pool_.push_back(b);
@@ -426,24 +431,25 @@ void Context::vcycle_csr(int l, const T* b, T* x, int nb, const int* act, c64* r
     const double res_mat = (double)nnz * (4.0 + sizeof(T)) + 4.0 * (double)n;
     const double enc = (double)sizeof(T) * (double)G.nc;
     const int pre = opt_.nu_pre, post = opt_.nu_post;
+    const int cols = csr_cols(L, nb);
     if (pre > 0) vec_zero<T>(x, n, nb, act, s_);
     for (int i = 0; i < pre; ++i)
       timed<T>(kTimGs, 3.0 * en + sweep_mat / nb, act, nb,
-               [&] { csr_gs_sweep<T>(b, x, S, (int)n, nb, L.cols, act, false, s_); });
+               [&] { csr_gs_sweep<T>(b, x, S, (int)n, nb, cols, act, false, s_); });
     T* bc = w.vb[l];
     T* ec = w.vx[l];
     if (pre == 0)
-      csr_restrict<T>(nullptr, b, bc, nullptr, A, G, nb, L.cols, act, s_);
+      csr_restrict<T>(nullptr, b, bc, nullptr, A, G, nb, cols, act, s_);
     else  // the residual passes through the level's scratch vector
       timed<T>(kTimResRestrict, 2.0 * en + enc + res_mat / nb, act, nb,
-               [&] { csr_restrict<T>(b, x, bc, w.vt[l - 1], A, G, nb, L.cols, act, s_); });
+               [&] { csr_restrict<T>(b, x, bc, w.vt[l - 1], A, G, nb, cols, act, s_); });
     vcycle_csr<T>(l + 1, bc, ec, nb, act, nullptr);
     timed<T>(kTimProlong, (pre == 0 ? 1.0 : 2.0) * en + enc, act, nb, [&] {
       csr_prolong<T>(ec, x, G, (int)n, omega_, pre == 0 ? 0.0 : 1.0, nb, act, s_);
     });
     for (int i = 0; i < post; ++i)
       timed<T>(kTimGs, 3.0 * en + sweep_mat / nb, act, nb,
-               [&] { csr_gs_sweep<T>(b, x, S, (int)n, nb, L.cols, act, true, s_); });
+               [&] { csr_gs_sweep<T>(b, x, S, (int)n, nb, cols, act, true, s_); });
   }
   if (rz_partials) vec_dot_partials<T>(b, x, n, nb, act, rz_partials, s_);
 }

@@ -19,41 +19,45 @@ __device__ __forceinline__ bool col_on(const int* active, int col, int nb) {
   return col < nb && (!active || active[col]);
 }
 
-// Row sum over one SELL-64 slice: acc[q] += sum_e v_e x_q[j_e] for the entries
-// of this lane's row, in stored order.  Indices and values of four entries are
-// loaded before their gathers, so several gathers of a lane are in flight.
+// U entries of a SELL-64 row: indices and values first, then the gathers of
+// every column, so U gathers per column are in flight; sums in entry order
+template <typename T, int COLS, int U>
+__device__ __forceinline__ void sell_chunk(const int* __restrict__ sci, const T* __restrict__ sv,
+                                           int at, const T* __restrict__ x, int64_t n, int col0,
+                                           const bool* on, T* acc) {
+  int j[U];
+  T a[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    j[u] = sci[at + u * 64];
+    a[u] = sv[at + u * 64];
+  }
+#pragma unroll
+  for (int q = 0; q < COLS; ++q) {
+    if (!on[q]) continue;
+    const T* xq = x + (int64_t)(col0 + q) * n;
+    T g[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) g[u] = xq[j[u]];
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc[q] += a[u] * g[u];
+  }
+}
+
+// Row sum over one SELL-64 slice: acc[q] += sum_e v_e x_q[j_e] for the w
+// entries of this lane's row, in stored order, in chunks of 8, 4 and 1
 template <typename T, int COLS>
 __device__ __forceinline__ void sell_row_sum(const int* __restrict__ sci,
                                              const T* __restrict__ sv, int base, int w,
                                              const T* __restrict__ x, int64_t n, int col0,
                                              const bool* on, T* acc) {
   int e = 0;
-  for (; e + 4 <= w; e += 4) {
-    int j[4];
-    T a[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      j[u] = sci[base + (e + u) * 64];
-      a[u] = sv[base + (e + u) * 64];
-    }
-#pragma unroll
-    for (int q = 0; q < COLS; ++q) {
-      if (!on[q]) continue;
-      const T* xq = x + (int64_t)(col0 + q) * n;
-      T g[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) g[u] = xq[j[u]];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) acc[q] += a[u] * g[u];
-    }
+  for (; e + 8 <= w; e += 8) sell_chunk<T, COLS, 8>(sci, sv, base + e * 64, x, n, col0, on, acc);
+  if (e + 4 <= w) {
+    sell_chunk<T, COLS, 4>(sci, sv, base + e * 64, x, n, col0, on, acc);
+    e += 4;
   }
-  for (; e < w; ++e) {
-    const int j = sci[base + e * 64];
-    const T a = sv[base + e * 64];
-#pragma unroll
-    for (int q = 0; q < COLS; ++q)
-      if (on[q]) acc[q] += a * x[(int64_t)(col0 + q) * n + j];
-  }
+  for (; e < w; ++e) sell_chunk<T, COLS, 1>(sci, sv, base + e * 64, x, n, col0, on, acc);
 }
 
 // r = b - A x (or r = A x when b is null); partials (nullable): per column and
@@ -130,14 +134,30 @@ __global__ __launch_bounds__(kThreads) void k_csr_update_apply(
     const int sl = i >> 6;
     const int base = sptr[sl] + (i & 63);
     const int w = (sptr[sl + 1] - sptr[sl]) >> 6;
-    for (int e = 0; e < w; ++e) {
-      const int j = sci[base + e * 64];
-      const T a = sv[base + e * 64];
+    // chunks of 4 entries: indices and values first, then 8 gathers per column
+    int e = 0;
+    for (; e < w; e += 4) {
+      const int m = w - e < 4 ? w - e : 4;
+      int j[4];
+      T a[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        j[u] = u < m ? sci[base + (e + u) * 64] : i;
+        a[u] = u < m ? sv[base + (e + u) * 64] : T(0);
+      }
 #pragma unroll
       for (int q = 0; q < COLS; ++q) {
         if (!on[q]) continue;
         const int64_t off = (int64_t)(col0 + q) * n;
-        acc[q] += a * (z[off + j] + bt[q] * p_old[off + j]);
+        T zz[4], pp[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          zz[u] = z[off + j[u]];
+          pp[u] = p_old[off + j[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (u < m) acc[q] += a[u] * (zz[u] + bt[q] * pp[u]);
       }
     }
   }

@@ -214,3 +214,23 @@ def test_invalid_setup_is_rejected():
         _est(A.tocsr(), 2, agg=[gap])
     with pytest.raises(m.MLMCError):    # 20000 unknowns cannot be the coarsest level
         _est(graph_laplacian(20000), 1 + 1, agg=[np.arange(20000)])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir64"])
+def test_sweep_with_large_and_small_classes(precision):
+    # 20000 unknowns: colour classes from 4332 rows (68 slices of 64) down to 2
+    # rows (one padded slice), thirteen launches per sweep
+    A = _graph(20000, isolated=0, seed=7)
+    est = _est(A, 2, precision=precision, nb=4)
+    col = hierarchy.first_fit_coloring(A)
+    sizes = np.bincount(col)
+    assert sizes.max() > 1024 and sizes.min() <= 1024
+    rng = np.random.default_rng(8)
+    B = rng.standard_normal((3, A.shape[0]))
+    X = rng.standard_normal((3, A.shape[0]))
+    for rev in (False, True):
+        got = from_dev(est.smooth(1, to_dev(B), to_dev(X), 1, rev))
+        for k in range(3):
+            ref = hierarchy.multicolour_gs_sweeps(A, B[k], X[k], col, 1, rev)
+            err = np.max(np.abs(got[k] - ref))
+            assert err <= TOL[precision] * np.max(np.abs(ref)), (rev, k, err)
