@@ -234,3 +234,46 @@ def test_sweep_with_large_and_small_classes(precision):
             ref = hierarchy.multicolour_gs_sweeps(A, B[k], X[k], col, 1, rev)
             err = np.max(np.abs(got[k] - ref))
             assert err <= TOL[precision] * np.max(np.abs(ref)), (rev, k, err)
+
+
+def test_full_size_graph_workload():
+    """The benchmark's graph (2^20 vertices) in its launch configuration (128
+    columns, 4 levels): the library's Galerkin products against sparse
+    products of its own exported levels and aggregate maps, products on
+    sampled rows against the input matrix, and FP64 residuals of level-1 solves
+    (the sparse-direct oracle cannot factor this graph inside a test)."""
+    from workloads import workload
+    w = workload("graph1m_fp32ir")
+    A = graph_laplacian(w["n"], degree=w["degree"], shift=w["shift"], seed=w["graph_seed"])
+    est = _est(A, w["levels_solver"], precision="fp32_ir64", nb=w["nb"], solve_tol=1e-10)
+    prev, prev_agg = None, None
+    for l in range(1, w["levels_solver"] + 1):
+        Al, agg, col = est.export_csr(l)
+        if l == 1:
+            assert np.array_equal(Al.indptr, A.indptr) and np.array_equal(Al.indices, A.indices)
+            assert np.array_equal(Al.data, A.data)
+        else:
+            ref = hierarchy.galerkin(prev, hierarchy.aggregate_prolongation(prev_agg))
+            ref.sum_duplicates()
+            ref.eliminate_zeros()
+            ref = ref.sorted_indices()
+            assert np.array_equal(Al.indptr, ref.indptr) and np.array_equal(Al.indices, ref.indices)
+            assert np.max(np.abs(Al.data - ref.data)) <= 1e-13 * np.max(np.abs(ref.data)), l
+        # a proper colouring of the level's graph
+        C = Al.tocoo()
+        off = C.row != C.col
+        assert np.all(col[C.row[off]] != col[C.col[off]]), l
+        prev, prev_agg = Al, agg
+    rng = np.random.default_rng(9)
+    rows = rng.choice(A.shape[0], 2000, replace=False)
+    X = rng.standard_normal((4, A.shape[0]))
+    Y = from_dev(est.apply(1, to_dev(X)))
+    ref = (A[rows] @ X.T).T
+    assert np.max(np.abs(Y[:, rows] - ref)) <= 1e-13 * np.max(np.abs(ref))
+    import torch
+    B = est.probes(1, 3, 0, 128)
+    Yd, rel = est.solve(1, B)
+    assert np.all(rel <= 1e-10), np.max(rel)
+    R = B - est.apply(1, Yd)
+    rr = torch.linalg.vector_norm(R, dim=1) / torch.linalg.vector_norm(B, dim=1)
+    assert float(rr.max()) <= 2e-10
