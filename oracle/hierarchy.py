@@ -142,14 +142,22 @@ def orthonormal_basis(V):
     return Q * np.conj(phase)[None, :]
 
 
-def testvector_aggregation(A, N, dof, block, n_vec, sweeps, seed, level):
+def testvector_aggregation(A, N, dof, block, n_vec, sweeps, seed, level, spin_split=False):
     """Aggregation P for a lattice operator with `dof` unknowns per site.
 
     Test vectors: n_vec Z4 start vectors (stream 2, sample j, this level), then
     `sweeps` red-black block Gauss-Seidel sweeps on A v = 0.  Aggregates are
     block x block site squares; within each, the n_vec restricted vectors are
     orthonormalised (QR with positive diagonal).  Coarse site S = Y*Nc + X,
-    coarse unknown S*n_vec + j.
+    coarse unknown S*nc + c.
+
+    spin_split (the spin-structure-preserving aggregation of Example 4.3):
+    within each aggregate the test vectors are restricted separately to the
+    unknowns of each spin (a site's first dof/2 unknowns carry spin 0, the rest
+    spin 1; on the fine lattice the two spin components) and each part is
+    orthonormalised on its own, so each aggregate gets nc = 2 n_vec coarse
+    unknowns, the first n_vec on spin 0 and the rest on spin 1, and P maps
+    spin to spin.  Otherwise nc = n_vec.
     """
     n = A.shape[0]
     assert n == N * N * dof and N % block == 0
@@ -160,39 +168,51 @@ def testvector_aggregation(A, N, dof, block, n_vec, sweeps, seed, level):
             v = block_rbgs_sweep(A, v, N, dof)
         V[:, j] = v
     Nc = N // block
+    nc = 2 * n_vec if spin_split else n_vec
+    half = dof // 2
     rows, cols, vals = [], [], []
     for Y in range(Nc):
         for X in range(Nc):
             S = Y * Nc + X
-            idx = []
+            parts = [[] for _ in range(2 if spin_split else 1)]
             for yy in range(block):
                 for xx in range(block):
                     s = (Y * block + yy) * N + (X * block + xx)
-                    idx += [s * dof + a for a in range(dof)]
-            Q = orthonormal_basis(V[idx, :])
-            for r, i in enumerate(idx):
-                for j in range(n_vec):
-                    rows.append(i)
-                    cols.append(S * n_vec + j)
-                    vals.append(Q[r, j])
-    P = sp.csr_matrix((np.array(vals), (rows, cols)), shape=(n, Nc * Nc * n_vec))
+                    for a in range(dof):
+                        parts[a // half if spin_split else 0].append(s * dof + a)
+            for p, idx in enumerate(parts):
+                Q = orthonormal_basis(V[idx, :])
+                for r, i in enumerate(idx):
+                    for j in range(n_vec):
+                        rows.append(i)
+                        cols.append(S * nc + p * n_vec + j)
+                        vals.append(Q[r, j])
+    P = sp.csr_matrix((np.array(vals), (rows, cols)), shape=(n, Nc * Nc * nc))
     return P, V
 
 
-def wilson_hierarchy(N, theta, m0, levels, block=4, n_vec=8, sweeps=20, seed=1):
-    """A_1..A_levels, P_1..P_{levels-1} for the Wilson operator (Example 4.3)."""
+def wilson_hierarchy(N, theta, m0, levels, block=4, n_vec=8, sweeps=20, seed=1,
+                     spin_split=False):
+    """A_1..A_levels, P_1..P_{levels-1} for the Wilson operator (Example 4.3);
+    spin_split: spin-structure-preserving aggregation on every level."""
     from .operators import wilson2d
     A = [wilson2d(N, theta, m0)]
     P = []
     n_side, dof = N, 2
     for lvl in range(1, levels):
         Pl, _ = testvector_aggregation(A[-1], n_side, dof, block, n_vec, sweeps,
-                                       seed, lvl)
+                                       seed, lvl, spin_split)
         P.append(Pl)
         A.append(galerkin(A[-1], Pl))
         n_side //= block
-        dof = n_vec
+        dof = 2 * n_vec if spin_split else n_vec
     return A, P
+
+
+def spin_sign(n_sites, dof):
+    """J on a lattice level: +1 on a site's first dof/2 unknowns (spin 0), -1 on
+    the rest; on the fine lattice (dof 2) the gamma5 of Example 4.3."""
+    return sp.diags(np.tile(np.repeat([1.0, -1.0], dof // 2), n_sites))
 
 
 # ---------------------------------------------------------------------------

@@ -198,3 +198,34 @@ def test_red_black_sweep_is_permuted_lexicographic_gauss_seidel():
     b = rng.standard_normal(A.shape[0])
     x = hierarchy.rbgs_sweeps(A, b, np.zeros_like(b), colour, 200)
     assert np.linalg.norm(A @ x - b) <= 1e-10 * np.linalg.norm(b)
+
+
+def test_spin_preserving_aggregation_keeps_the_spin_symmetry():
+    """Example 4.3: J S = S^* J on the fine lattice; with the test vectors split
+    by spin (2 n_vec coarse unknowns per aggregate) the coarse operators keep
+    J_c A_c = A_c^* J_c, so their eigenvalues pair up as (lambda, conj(lambda))
+    and tr(A_c^-1) is real; without the split they do not."""
+    N, nv = 8, 2
+    th = gauge_field(N, seed=4)
+    A, P = hierarchy.wilson_hierarchy(N, th, 0.1, levels=3, block=2, n_vec=nv, sweeps=6,
+                                      seed=1, spin_split=True)
+    sides, dofs = [N, N // 2, N // 4], [2, 2 * nv, 2 * nv]
+    for l in range(3):
+        J = hierarchy.spin_sign(sides[l] ** 2, dofs[l])
+        D = A[l]
+        assert abs(J @ D @ J - D.conj().T).max() <= 1e-13 * abs(D).max(), l
+        if l < 2:
+            Jc = hierarchy.spin_sign(sides[l + 1] ** 2, dofs[l + 1])
+            assert abs(J @ P[l] - P[l] @ Jc).max() == 0       # P maps spin to spin
+            Pd = P[l].toarray()
+            assert np.allclose(Pd.conj().T @ Pd, np.eye(Pd.shape[1]), atol=1e-13)
+    tr = np.trace(np.linalg.inv(A[2].toarray()))
+    assert abs(tr.imag) <= 1e-10 * abs(tr)
+    ev = np.linalg.eigvals(A[1].toarray())
+    gap = np.abs(ev.conj()[:, None] - ev[None, :]).min(axis=1)   # conj(lambda) is one too
+    assert gap.max() <= 1e-9 * np.abs(ev).max()
+    # the plain aggregation with the same number of coarse unknowns breaks it
+    A2, _ = hierarchy.wilson_hierarchy(N, th, 0.1, levels=2, block=2, n_vec=2 * nv, sweeps=6,
+                                       seed=1)
+    J = hierarchy.spin_sign((N // 2) ** 2, 2 * nv)
+    assert abs(J @ A2[1] @ J - A2[1].conj().T).max() > 1e-3 * abs(A2[1]).max()
