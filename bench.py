@@ -288,13 +288,13 @@ def run_poisson(args, m, torch):
              compare=compare)
 
 
-def _wilson_est(m, N, Ls, L, precision, learned, nb, alloc):
+def _wilson_est(m, N, Ls, L, precision, learned, nb, alloc, n_vec=8, spin_split=False):
     from workloads import gauge_field, wilson_mass
     return m.TraceEstimator("wilson2d", N, Ls, L, mass=wilson_mass(N),
-                            field=gauge_field(N, sigma=0.5, seed=1), block=4, n_vec=8,
-                            setup_sweeps=20, setup_seed=1, precision=precision, nb=nb,
-                            nu_pre=2, nu_post=2, solve_tol=1e-10, alloc=alloc,
-                            learned=1 if learned else 0)
+                            field=gauge_field(N, sigma=0.5, seed=1), block=4, n_vec=n_vec,
+                            spin_split=spin_split, setup_sweeps=20, setup_seed=1,
+                            precision=precision, nb=nb, nu_pre=2, nu_post=2, solve_tol=1e-10,
+                            alloc=alloc, learned=1 if learned else 0)
 
 
 def run_wilson(args, m, torch, N, learned):
@@ -302,7 +302,8 @@ def run_wilson(args, m, torch, N, learned):
     Ls, L = (4, 3) if N >= 512 else (3, 3)
     log("setup wilson2d N=%d Ls=%d L=%d nb=%d learned=%s" % (N, Ls, L, args.nb, learned))
     t0 = time.perf_counter()
-    est = _wilson_est(m, N, Ls, L, "fp32_ir64", learned, args.nb, args.alloc)
+    nv = args.n_vec if args.n_vec > 0 else (4 if args.spin_split else 8)
+    est = _wilson_est(m, N, Ls, L, "fp32_ir64", learned, args.nb, args.alloc, nv, args.spin_split)
     setup_s = time.perf_counter() - t0
     log("setup %.2fs" % setup_s)
     train = None
@@ -350,14 +351,15 @@ def run_wilson(args, m, torch, N, learned):
     if not args.no_compare:
         if learned:
             log("plain FP32 MLMC (no network), same workload")
-            ep = _wilson_est(m, N, Ls, L, "fp32_ir64", False, args.nb, args.alloc)
+            ep = _wilson_est(m, N, Ls, L, "fp32_ir64", False, args.nb, args.alloc, nv,
+                             args.spin_split)
             tp, npl = timed_traces(ep, args, torch)
             ep.close()
             compare["plain_fp32_mlmc_s"] = round(tp, 3)
             compare["plain_fp32_mlmc_n_samples"] = npl
             log("plain FP32 MLMC %.3fs per trace, N_l=%s" % (tp, npl))
         log("plain FP64 MLMC, same workload")
-        e64 = _wilson_est(m, N, Ls, L, "fp64", False, args.nb, args.alloc)
+        e64 = _wilson_est(m, N, Ls, L, "fp64", False, args.nb, args.alloc, nv, args.spin_split)
         t64, n64 = timed_traces(e64, args, torch)
         e64.close()
         compare["fp64_mlmc_s"] = round(t64, 3)
@@ -367,8 +369,11 @@ def run_wilson(args, m, torch, N, learned):
             compare["speedup_vs_plain_fp32_mlmc"] = round(
                 compare["plain_fp32_mlmc_s"] / (ms_per_step / 1000.0), 2)
         log("plain FP64 MLMC %.3fs per trace, N_l=%s" % (t64, n64))
-    config = {"workload": "wilson2d_%dx%d_Ls%d_L%d_agg4x4x8_nb%d_c64ir128_eps%g%s"
-                          % (N, N, Ls, L, args.nb, args.eps, "_learned" if learned else ""),
+    dof = 2 * nv if args.spin_split else nv
+    config = {"workload": "wilson2d_%dx%d_Ls%d_L%d_agg4x4x%d%s_nb%d_c64ir128_eps%g%s"
+                          % (N, N, Ls, L, dof, "spin" if args.spin_split else "", args.nb,
+                             args.eps, "_learned" if learned else ""),
+              "n_vec": nv, "spin_split": bool(args.spin_split),
               "variant": ("learned smoother (2 of 4 finest sweeps) + complex64 FGMRES in "
                           "complex128 refinement" if learned else
                           "complex64 FGMRES + V-cycle in complex128 refinement"),
@@ -539,6 +544,10 @@ def main():
     ap.add_argument("--alloc", default="giles")
     ap.add_argument("--nu", type=int, default=2, help="poisson1024: sweeps before and after")
     ap.add_argument("--workers", type=int, default=4, help="varcoef_batch: host workers")
+    ap.add_argument("--spin-split", action="store_true",
+                    help="wilson*: spin-structure-preserving aggregation (Example 4.3)")
+    ap.add_argument("--n-vec", type=int, default=0,
+                    help="wilson*: test vectors per aggregate (0: 8, or 4 with --spin-split)")
     ap.add_argument("--omega", type=float, default=0.0,
                     help="graph1m: coarse-correction scaling (0 = the library default)")
     ap.add_argument("--train-batches", type=int, default=80,

@@ -109,7 +109,8 @@ typedef struct mlmc_hierarchy {
   int levels_solver;  /* L_s: levels of the multigrid solver (>= 2) */
   int levels_mlmc;    /* L <= L_s: levels of the trace decomposition (>= 2) */
   int block;          /* WILSON2D: aggregate side in sites (4) */
-  int n_vec;          /* WILSON2D: test vectors = coarse dofs per site (8) */
+  int n_vec;          /* WILSON2D: test vectors per aggregate (8); coarse dofs per
+                         site = n_vec, or 2 n_vec with spin_split */
   int setup_sweeps;   /* WILSON2D: smoothing sweeps on A v = 0 per test vector */
   uint64_t setup_seed;/* WILSON2D: seed of the test-vector start vectors */
   /* CSR: NULL, or levels_solver - 1 host arrays: agg[l][i] = aggregate (the
@@ -122,6 +123,13 @@ typedef struct mlmc_hierarchy {
      |a_ij| (the smallest j among equal ones).  Aggregates are numbered in
      order of creation. */
   const int32_t* const* agg;
+  /* WILSON2D: 1 = spin-structure-preserving aggregation (Example 4.3): on every
+     level the test vectors are restricted separately to the unknowns of each
+     spin (a site's first dof/2 unknowns carry spin 0) and orthonormalised per
+     spin, so an aggregate has 2 n_vec coarse unknowns (the first n_vec on spin
+     0) and every coarse operator keeps J A = A^* J.  2 n_vec must be one of
+     the supported site sizes (2, 4, 8, 12, 16).  0 = n_vec coarse unknowns. */
+  int spin_split;
 } mlmc_hierarchy;
 
 typedef struct mlmc_options {

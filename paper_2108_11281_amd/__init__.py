@@ -112,13 +112,15 @@ class TraceEstimator:
     kind's matrix (anything with indptr, indices and data after .tocsr(), e.g.
     a scipy.sparse matrix; n_side is ignored); agg: optional aggregate maps of
     the csr kind, one integer array per level below the coarsest (None: greedy
-    aggregation in the library).  Options follow mlmc_options
+    aggregation in the library); spin_split: the spin-structure-preserving
+    aggregation of the wilson2d kind.  Options follow mlmc_options
     (include/mlmc.h); unknown keyword names raise.
     """
 
     def __init__(self, kind, n_side, levels_solver, levels_mlmc=None, *, diag=4.0, off=1.0,
                  mass=0.0, shift=0.0, field=None, matrix=None, agg=None, block=4, n_vec=8,
-                 setup_sweeps=20, setup_seed=1, stream=None, torch_allocator=True, **options):
+                 setup_sweeps=20, setup_seed=1, spin_split=False, stream=None,
+                 torch_allocator=True, **options):
         import torch
         self._lib = lib()
         self._ctx = ctypes.c_void_p()
@@ -151,6 +153,7 @@ class TraceEstimator:
         h.levels_mlmc = int(levels_mlmc if levels_mlmc is not None else levels_solver)
         h.block, h.n_vec, h.setup_sweeps = int(block), int(n_vec), int(setup_sweeps)
         h.setup_seed = int(setup_seed)
+        h.spin_split = 1 if spin_split else 0
         if agg is not None:
             self._agg = [np.ascontiguousarray(a, dtype=np.int32) for a in agg]
             if len(self._agg) != h.levels_solver - 1:

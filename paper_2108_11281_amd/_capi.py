@@ -42,7 +42,8 @@ class Hierarchy(ctypes.Structure):
     _fields_ = [("levels_solver", ctypes.c_int), ("levels_mlmc", ctypes.c_int),
                 ("block", ctypes.c_int), ("n_vec", ctypes.c_int),
                 ("setup_sweeps", ctypes.c_int), ("setup_seed", ctypes.c_uint64),
-                ("agg", ctypes.POINTER(ctypes.POINTER(ctypes.c_int32)))]
+                ("agg", ctypes.POINTER(ctypes.POINTER(ctypes.c_int32))),
+                ("spin_split", ctypes.c_int)]
 
 
 class Options(ctypes.Structure):

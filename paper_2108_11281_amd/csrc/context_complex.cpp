@@ -37,10 +37,15 @@ template <> Fgmres<c64>& Context::fg<c64>() {
 // ---------------------------------------------------------------------------
 void Context::build_wilson(const double* theta) {
   const int N = op_.n_side, blk = h_.block, nv = h_.n_vec;
+  // coarse unknowns per site: the test vectors, doubled by the spin split
+  const bool split = h_.spin_split != 0;
+  const int nc = split ? 2 * nv : nv;
   MLMC_REQUIRE(theta != nullptr, MLMC_EINVAL, "WILSON2D needs the link phases (field)");
   MLMC_REQUIRE(N >= 2 && blk >= 2, MLMC_EINVAL, "bad lattice or aggregate size");
-  MLMC_REQUIRE(nv == 2 || nv == 4 || nv == 8 || nv == 12 || nv == 16, MLMC_EUNSUPPORTED,
-               "n_vec must be one of 2, 4, 8, 12, 16");
+  MLMC_REQUIRE(nv >= 1 && (nc == 2 || nc == 4 || nc == 8 || nc == 12 || nc == 16),
+               MLMC_EUNSUPPORTED,
+               "coarse unknowns per site (n_vec, doubled by spin_split) must be one of 2, 4, 8, "
+               "12, 16");
   MLMC_REQUIRE(h_.setup_sweeps >= 0, MLMC_EINVAL, "setup_sweeps must be >= 0");
   MLMC_REQUIRE(opt_.krylov_restart >= 1 && opt_.krylov_restart <= 32, MLMC_EINVAL,
                "krylov_restart must be in [1, 32]");
@@ -58,7 +63,7 @@ void Context::build_wilson(const double* theta) {
     Level& L = lv_[l];
     L.index = l + 1;
     L.side = side;
-    L.dof = l == 0 ? 2 : nv;
+    L.dof = l == 0 ? 2 : nc;
     L.n = (int64_t)side * side * L.dof;
     L.wilson = (l == 0);
     L.blk = blk;
@@ -92,19 +97,19 @@ void Context::build_wilson(const double* theta) {
       else
         bsr_rbgs<c64>(zero, V, F.B64, F.Dinv64, F.side, F.dof, nv, nullptr, false, false, 0, s_);
     }
-    F.q64 = dalloc_n<c64>(F.n * nv);
-    F.q32 = dalloc_n<c32>(F.n * nv);
-    agg_orthonormalise(V, F.q64, F.side, F.dof, blk, nv, s_);
-    vec_convert<c32, c64>(F.q64, F.q32, F.n * nv, 1, nullptr, s_);
+    F.q64 = dalloc_n<c64>(F.n * nc);
+    F.q32 = dalloc_n<c32>(F.n * nc);
+    agg_orthonormalise(V, F.q64, F.side, F.dof, blk, nv, split, s_);
+    vec_convert<c32, c64>(F.q64, F.q32, F.n * nc, 1, nullptr, s_);
     const int64_t nsc = (int64_t)C.side * C.side;
-    C.B64 = dalloc_n<c64>(nsc * 5 * nv * nv);
-    C.B32 = dalloc_n<c32>(nsc * 5 * nv * nv);
-    galerkin_blocks(F.wilson ? nullptr : F.B64, F.U64, diag, F.q64, F.side, F.dof, blk, nv, C.B64,
+    C.B64 = dalloc_n<c64>(nsc * 5 * nc * nc);
+    C.B32 = dalloc_n<c32>(nsc * 5 * nc * nc);
+    galerkin_blocks(F.wilson ? nullptr : F.B64, F.U64, diag, F.q64, F.side, F.dof, blk, nc, C.B64,
                     s_);
-    vec_convert<c32, c64>(C.B64, C.B32, nsc * 5 * nv * nv, 1, nullptr, s_);
-    C.Dinv64 = dalloc_n<c64>(nsc * nv * nv);
-    C.Dinv32 = dalloc_n<c32>(nsc * nv * nv);
-    block_diag_inverse(C.B64, C.Dinv64, C.Dinv32, (int)nsc, nv, s_);
+    vec_convert<c32, c64>(C.B64, C.B32, nsc * 5 * nc * nc, 1, nullptr, s_);
+    C.Dinv64 = dalloc_n<c64>(nsc * nc * nc);
+    C.Dinv32 = dalloc_n<c32>(nsc * nc * nc);
+    block_diag_inverse(C.B64, C.Dinv64, C.Dinv32, (int)nsc, nc, s_);
   }
 
   // work buffers

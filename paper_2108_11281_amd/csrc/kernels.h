@@ -300,7 +300,8 @@ template <typename T>
 void agg_prolong(const T* xc, T* x, const T* q, int Nf, int dofF, int blk, int dofC,
                  double omega, double beta, int nb, const int* active, hipStream_t s);
 void wilson_links(const double* theta, c64* U64, c32* U32, int N, hipStream_t s);
-void agg_orthonormalise(const c64* V, c64* q, int Nf, int dofF, int blk, int nv, hipStream_t s);
+void agg_orthonormalise(const c64* V, c64* q, int Nf, int dofF, int blk, int nv, bool split,
+                        hipStream_t s);
 void galerkin_blocks(const c64* Bf, const c64* U, double wdiag, const c64* q, int Nf, int dofF,
                      int blk, int nv, c64* Bc, hipStream_t s);
 void dense_from_stencil(const c64* Bf, const c64* U, double wdiag, int Nf, int dof, c64* aug,

@@ -431,59 +431,73 @@ __global__ void k_links(const double* theta, c64* U64, c32* U32, int n) {
 }
 
 // per-aggregate modified Gram-Schmidt of the nv test vectors restricted to the
-// aggregate (FP64); V: [nv][n] (vector j at j*n), q out: [n][nv]; one block per
-// aggregate, m = blk*blk*dofF rows
+// aggregate (FP64); V: [nv][n] (vector j at j*n), q out: [n][nq]; one block per
+// aggregate, m = blk*blk*dofF rows.  split: the rows of each spin (a site's
+// first dofF/2 unknowns carry spin 0) are orthonormalised on their own (the two
+// row sets are disjoint, so both run in place in the same LDS copy); row r of
+// spin p gets its basis in columns p*nv..p*nv+nv-1 and zeros in the others
+// (nq = 2 nv); otherwise nq = nv.
 __global__ __launch_bounds__(kThreads) void k_agg_orthonormalise(const c64* __restrict__ V,
                                                                  c64* __restrict__ q, int Nf,
-                                                                 int dofF, int blk, int nv) {
+                                                                 int dofF, int blk, int nv,
+                                                                 int split) {
   extern __shared__ c64 sv[];  // m * nv
   __shared__ double red[16];
   const int Nc = Nf / blk;
   const int S = blockIdx.x;
   const int Y = S / Nc, X = S - Y * Nc;
   const int m = blk * blk * dofF;
+  const int half = dofF / 2;
   const int64_t n = (int64_t)Nf * Nf * dofF;
   auto row_index = [&](int r) -> int64_t {
     const int site = r / dofF, a = r - site * dofF;
     const int yy = site / blk, xx = site - yy * blk;
     return (int64_t)((Y * blk + yy) * Nf + (X * blk + xx)) * dofF + a;
   };
+  // spin of row r (0 for every row without the split)
+  auto spin = [&](int r) { return split ? (r % dofF) / half : 0; };
   for (int idx = threadIdx.x; idx < m * nv; idx += kThreads) {
     const int r = idx / nv, j = idx - r * nv;
     sv[idx] = V[(int64_t)j * n + row_index(r)];
   }
   __syncthreads();
-  for (int j = 0; j < nv; ++j) {
-    // remove the components along the previous (already normalised) columns
-    for (int i = 0; i < j; ++i) {
+  for (int p = 0; p < (split ? 2 : 1); ++p) {
+    for (int j = 0; j < nv; ++j) {
+      // remove the components along the previous (already normalised) columns
+      for (int i = 0; i < j; ++i) {
+        double re = 0.0, im = 0.0;
+        for (int r = threadIdx.x; r < m; r += kThreads)
+          if (spin(r) == p) cdot_acc(re, im, sv[r * nv + i], sv[r * nv + j]);
+        block_sum2<kThreads>(re, im, red);
+        __shared__ double proj[2];
+        if (threadIdx.x == 0) {
+          proj[0] = re;
+          proj[1] = im;
+        }
+        __syncthreads();
+        const c64 h = {proj[0], proj[1]};
+        for (int r = threadIdx.x; r < m; r += kThreads)
+          if (spin(r) == p) sv[r * nv + j] -= h * sv[r * nv + i];
+        __syncthreads();
+      }
       double re = 0.0, im = 0.0;
       for (int r = threadIdx.x; r < m; r += kThreads)
-        cdot_acc(re, im, sv[r * nv + i], sv[r * nv + j]);
+        if (spin(r) == p) cdot_acc(re, im, sv[r * nv + j], sv[r * nv + j]);
       block_sum2<kThreads>(re, im, red);
-      __shared__ double proj[2];
-      if (threadIdx.x == 0) {
-        proj[0] = re;
-        proj[1] = im;
-      }
+      __shared__ double nrm;
+      if (threadIdx.x == 0) nrm = sqrt(re);
       __syncthreads();
-      const c64 h = {proj[0], proj[1]};
-      for (int r = threadIdx.x; r < m; r += kThreads) sv[r * nv + j] -= h * sv[r * nv + i];
+      const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+      for (int r = threadIdx.x; r < m; r += kThreads)
+        if (spin(r) == p) sv[r * nv + j] = inv * sv[r * nv + j];
       __syncthreads();
     }
-    double re = 0.0, im = 0.0;
-    for (int r = threadIdx.x; r < m; r += kThreads)
-      cdot_acc(re, im, sv[r * nv + j], sv[r * nv + j]);
-    block_sum2<kThreads>(re, im, red);
-    __shared__ double nrm;
-    if (threadIdx.x == 0) nrm = sqrt(re);
-    __syncthreads();
-    const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-    for (int r = threadIdx.x; r < m; r += kThreads) sv[r * nv + j] = inv * sv[r * nv + j];
-    __syncthreads();
   }
-  for (int idx = threadIdx.x; idx < m * nv; idx += kThreads) {
-    const int r = idx / nv, j = idx - r * nv;
-    q[row_index(r) * nv + j] = sv[idx];
+  const int nq = split ? 2 * nv : nv;
+  for (int idx = threadIdx.x; idx < m * nq; idx += kThreads) {
+    const int r = idx / nq, c = idx - r * nq;
+    const int p = c / nv, j = c - p * nv;  // p = 0 without the split
+    q[row_index(r) * nq + c] = (spin(r) == p) ? sv[r * nv + j] : c64{0.0, 0.0};
   }
 }
 
@@ -747,14 +761,15 @@ void wilson_links(const double* theta, c64* U64, c32* U32, int N, hipStream_t s)
   hipLaunchKernelGGL(k_links, dim3(256), dim3(256), 0, s, theta, U64, U32, 2 * N * N);
 }
 
-void agg_orthonormalise(const c64* V, c64* q, int Nf, int dofF, int blk, int nv,
+void agg_orthonormalise(const c64* V, c64* q, int Nf, int dofF, int blk, int nv, bool split,
                         hipStream_t s) {
   const int Nc = Nf / blk;
   const size_t lds = sizeof(c64) * (size_t)blk * blk * dofF * nv;
   MLMC_REQUIRE(lds <= 60 * 1024, MLMC_EUNSUPPORTED,
                "aggregate too large for the LDS orthonormalisation");
+  MLMC_REQUIRE(!split || dofF % 2 == 0, MLMC_EINVAL, "the spin split needs an even site size");
   hipLaunchKernelGGL(k_agg_orthonormalise, dim3(Nc * Nc), dim3(kThreads), lds, s, V, q, Nf,
-                     dofF, blk, nv);
+                     dofF, blk, nv, split ? 1 : 0);
 }
 
 void galerkin_blocks(const c64* Bf, const c64* U, double wdiag, const c64* q, int Nf, int dofF,
