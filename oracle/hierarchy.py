@@ -321,3 +321,45 @@ def csr_hierarchy(A, levels, aggs=None):
         P.append(aggregate_prolongation(agg))
         A.append(canonical(galerkin(A[-1], P[-1])))
     return A, P
+
+
+# ---------------------------------------------------------------------------
+# Example 4.1: bilinear interpolation (non-orthonormal P, R = P^T)
+# ---------------------------------------------------------------------------
+
+def linear_interpolation_1d(Nf):
+    """p in R^{Nf x Nc}, Nc = floor(Nf/2): coarse point I sits at fine point
+    2I+1; fine point 2I+1 takes it with weight 1, fine points 2I and 2I+2 with
+    weight 1/2 (Dirichlet: the boundary values are zero)."""
+    Nc = Nf // 2
+    p = sp.lil_matrix((Nf, Nc))
+    for I in range(Nc):
+        p[2 * I + 1, I] = 1.0
+        p[2 * I, I] = 0.5
+        if 2 * I + 2 < Nf:
+            p[2 * I + 2, I] = 0.5
+    return p.tocsr()
+
+
+def bilinear_interpolation(Nf):
+    """Standard bilinear interpolation from the Nc x Nc to the Nf x Nf grid
+    (Example 4.1), unknowns numbered iy*N + ix: the tensor product of the 1D
+    linear interpolations, so fine points take weights 1, 1/2 and 1/4."""
+    p = linear_interpolation_1d(Nf)
+    return sp.kron(p, p).tocsr()
+
+
+def laplace_bilinear_hierarchy(N, levels):
+    """Example 4.1's hierarchy: A_1 the 5-point Laplacian (diagonal 4), P_l the
+    bilinear interpolation, R_l = P_l^T, A_{l+1} = R_l A_l P_l; N_{l+1} = floor(N_l/2)."""
+    from .operators import poisson2d
+    A = [poisson2d(N)]
+    P = []
+    n = N
+    for _ in range(levels - 1):
+        P.append(bilinear_interpolation(n))
+        Ac = galerkin(A[-1], P[-1])
+        Ac.eliminate_zeros()
+        A.append(Ac.sorted_indices())
+        n //= 2
+    return A, P

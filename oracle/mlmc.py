@@ -135,6 +135,59 @@ class LevelSampler:
         return float(self.A[level - 1].shape[0] + self.A[level].shape[0])
 
 
+class GeneralLevelSampler(LevelSampler):
+    """Exact level-difference samples of the general decomposition of Sec. 4.1
+    for any P_l (R_l = P_l^H): with a probe x on the finest level,
+        s = x^H Phat_l A_l^{-1} Rhat_l x - x^H Phat_{l+1} A_{l+1}^{-1} Rhat_{l+1} x,
+    Rhat_l = R_{l-1} ... R_1, Phat_l = P_1 ... P_{l-1}; the coarsest term is
+    tr(A_L^{-1} Rhat_L Phat_L) (Remark 4.2, trace of a product commutes).  Both
+    quadratic forms are taken as written: the solution is prolongated back to
+    the finest level and multiplied with x there."""
+
+    def probes(self, level, seed, first, count, stream=philox.STREAM_PROBE):
+        n = self.A[0].shape[0]
+        return np.stack([philox.probe(n, seed, first + j, level, self.complex_probe,
+                                      stream, self.problem)
+                         for j in range(count)], axis=1)
+
+    def restrict_to(self, level, X):
+        for l in range(level - 1):
+            X = self.P[l].conj().T @ X
+        return X
+
+    def prolong_from(self, level, Y):
+        for l in range(level - 2, -1, -1):
+            Y = self.P[l] @ Y
+        return Y
+
+    def parts_for(self, level, X):
+        """(x^H Phat_l A_l^-1 Rhat_l x, x^H Phat_{l+1} A_{l+1}^-1 Rhat_{l+1} x) for
+        the columns x of X."""
+        parts = []
+        for lv in (level, level + 1):
+            Y = self.prolong_from(lv, self.solver(lv).solve(self.restrict_to(lv, X)))
+            parts.append(np.array([quad(X[:, j], Y[:, j]) for j in range(X.shape[1])]))
+        return parts[0], parts[1]
+
+    def sample_parts(self, level, seed, first, count):
+        return self.parts_for(level, self.probes(level, seed, first, count))
+
+    def sample(self, level, seed, first, count):
+        assert 1 <= level < self.L
+        a, b = self.sample_parts(level, seed, first, count)
+        return a - b
+
+    def coarse(self):
+        L = self.L
+        Rh = sp.identity(self.A[0].shape[0], format="csr")
+        Ph = Rh
+        for l in range(L - 1):
+            Rh = self.P[l].conj().T @ Rh
+            Ph = Ph @ self.P[l]
+        M = (Rh @ Ph).toarray()
+        return complex(np.trace(np.linalg.inv(sp.csr_matrix(self.A[-1]).toarray()) @ M))
+
+
 def mean_and_var(s):
     """Mean and Bessel-corrected variance E|s - mean|^2 (convention of Sec. 3)."""
     s = np.asarray(s, dtype=np.complex128)
