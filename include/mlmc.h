@@ -104,6 +104,15 @@ typedef struct mlmc_operator {
   const double* vals;
 } mlmc_operator;
 
+/* A sparse matrix in compressed sparse row form (host memory): row_ptr[0..rows],
+ * column indices in [0, cols) and values per entry. */
+typedef struct mlmc_csr {
+  int64_t rows, cols;
+  const int64_t* row_ptr;
+  const int32_t* col_idx;
+  const double* vals;
+} mlmc_csr;
+
 /* Hierarchy description (Sec. 4.1; solver levels may exceed MLMC levels, Sec. 5). */
 typedef struct mlmc_hierarchy {
   int levels_solver;  /* L_s: levels of the multigrid solver (>= 2) */
@@ -130,6 +139,15 @@ typedef struct mlmc_hierarchy {
      0) and every coarse operator keeps J A = A^* J.  2 n_vec must be one of
      the supported site sizes (2, 4, 8, 12, 16).  0 = n_vec coarse unknowns. */
   int spin_split;
+  /* CSR: NULL, or levels_solver - 1 prolongations P_l (n_l x n_{l+1}, any
+     sparse real matrices with full column rank, e.g. the bilinear
+     interpolation of Example 4.1), copied at setup.  Then R_l = P_l^T,
+     A_{l+1} = R_l A_l P_l, and the estimator uses the general decomposition of
+     Sec. 4.1: the level-l sample is x^T Phat_l A_l^{-1} Rhat_l x -
+     x^T Phat_{l+1} A_{l+1}^{-1} Rhat_{l+1} x with a probe x on the finest level
+     (keyed by (seed, l, k) like every probe), and the coarsest term is
+     tr(A_L^{-1} Rhat_L Phat_L) (Remark 4.2).  Excludes agg. */
+  const mlmc_csr* P;
 } mlmc_hierarchy;
 
 typedef struct mlmc_options {

@@ -112,14 +112,16 @@ class TraceEstimator:
     kind's matrix (anything with indptr, indices and data after .tocsr(), e.g.
     a scipy.sparse matrix; n_side is ignored); agg: optional aggregate maps of
     the csr kind, one integer array per level below the coarsest (None: greedy
-    aggregation in the library); spin_split: the spin-structure-preserving
+    aggregation in the library); prolongations: the csr kind's P_l (scipy sparse,
+    n_l x n_{l+1}; R_l = P_l^T, general decomposition with finest-level
+    probes); spin_split: the spin-structure-preserving
     aggregation of the wilson2d kind.  Options follow mlmc_options
     (include/mlmc.h); unknown keyword names raise.
     """
 
     def __init__(self, kind, n_side, levels_solver, levels_mlmc=None, *, diag=4.0, off=1.0,
-                 mass=0.0, shift=0.0, field=None, matrix=None, agg=None, block=4, n_vec=8,
-                 setup_sweeps=20, setup_seed=1, spin_split=False, stream=None,
+                 mass=0.0, shift=0.0, field=None, matrix=None, agg=None, prolongations=None,
+                 block=4, n_vec=8, setup_sweeps=20, setup_seed=1, spin_split=False, stream=None,
                  torch_allocator=True, **options):
         import torch
         self._lib = lib()
@@ -161,6 +163,24 @@ class TraceEstimator:
             self._agg_ptrs = (ctypes.POINTER(ctypes.c_int32) * len(self._agg))(
                 *[a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) for a in self._agg])
             h.agg = ctypes.cast(self._agg_ptrs, ctypes.POINTER(ctypes.POINTER(ctypes.c_int32)))
+        if prolongations is not None:
+            if len(prolongations) != h.levels_solver - 1:
+                raise ValueError("prolongations needs levels_solver - 1 matrices, got %d"
+                                 % len(prolongations))
+            self._P = []
+            self._P_c = (_capi.Csr * len(prolongations))()
+            for k, Pm in enumerate(prolongations):
+                Pm = Pm.tocsr()
+                arrs = (np.ascontiguousarray(Pm.indptr, dtype=np.int64),
+                        np.ascontiguousarray(Pm.indices, dtype=np.int32),
+                        np.ascontiguousarray(Pm.data, dtype=np.float64))
+                self._P.append(arrs)
+                c = self._P_c[k]
+                c.rows, c.cols = Pm.shape
+                c.row_ptr = arrs[0].ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+                c.col_idx = arrs[1].ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+                c.vals = arrs[2].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            h.P = ctypes.cast(self._P_c, ctypes.POINTER(_capi.Csr))
         o = default_options()
         self._weights = None
         for k, v in options.items():
@@ -189,6 +209,7 @@ class TraceEstimator:
             _exit_hook.append(True)
         _live.add(self)
         self.kind = kind
+        self.general = prolongations is not None  # general decomposition (given P)
         self.is_complex = kind == "wilson2d"
         self.levels_solver = h.levels_solver
         self.levels_mlmc = h.levels_mlmc
@@ -349,7 +370,8 @@ class TraceEstimator:
 
     def export_csr(self, level):
         """Level `level` of a csr hierarchy: (scipy CSR matrix A_level, aggregate
-        map or None on the coarsest level, colour classes)."""
+        map, or None on the coarsest level and with given prolongations, colour
+        classes)."""
         import scipy.sparse as sp
         n = self.level_size(level)
         nnz = ctypes.c_int64()
@@ -359,7 +381,8 @@ class TraceEstimator:
         ci = np.zeros(nnz.value, dtype=np.int32)
         v = np.zeros(nnz.value)
         col = np.zeros(n, dtype=np.int32)
-        agg = np.zeros(n, dtype=np.int32) if level < self.levels_solver else None
+        agg = (np.zeros(n, dtype=np.int32)
+               if level < self.levels_solver and not self.general else None)
         i32 = ctypes.POINTER(ctypes.c_int32)
         self._c(self._lib.mlmc_export_csr(
             self._ctx, int(level), ctypes.byref(nnz),

@@ -38,12 +38,20 @@ class Operator(ctypes.Structure):
                 ("vals", ctypes.POINTER(ctypes.c_double))]
 
 
+class Csr(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_int64), ("cols", ctypes.c_int64),
+                ("row_ptr", ctypes.POINTER(ctypes.c_int64)),
+                ("col_idx", ctypes.POINTER(ctypes.c_int32)),
+                ("vals", ctypes.POINTER(ctypes.c_double))]
+
+
 class Hierarchy(ctypes.Structure):
     _fields_ = [("levels_solver", ctypes.c_int), ("levels_mlmc", ctypes.c_int),
                 ("block", ctypes.c_int), ("n_vec", ctypes.c_int),
                 ("setup_sweeps", ctypes.c_int), ("setup_seed", ctypes.c_uint64),
                 ("agg", ctypes.POINTER(ctypes.POINTER(ctypes.c_int32))),
-                ("spin_split", ctypes.c_int)]
+                ("spin_split", ctypes.c_int),
+                ("P", ctypes.POINTER(Csr))]
 
 
 class Options(ctypes.Structure):

@@ -14,10 +14,6 @@ AllocHooks& alloc_hooks() {
   return h;
 }
 
-namespace {
-constexpr uint64_t kStreamProbe = 0, kStreamPilot = 1, kStreamHutch = 3;
-}
-
 // ---------------------------------------------------------------------------
 // construction
 // ---------------------------------------------------------------------------
@@ -31,6 +27,7 @@ Context::Context(const mlmc_operator& A, const mlmc_hierarchy& h, const mlmc_opt
   op_.col_idx = nullptr;
   op_.vals = nullptr;
   h_.agg = nullptr;
+  h_.P = nullptr;
   Ls_ = h.levels_solver;
   L_ = h.levels_mlmc;
   nb_ = o.nb;
@@ -67,7 +64,7 @@ Context::Context(const mlmc_operator& A, const mlmc_hierarchy& h, const mlmc_opt
       case MLMC_CSR:
         csr_ = true;
         omega_ = opt_.omega > 0 ? opt_.omega : 1.0;
-        build_csr(A, h.agg);
+        build_csr(A, h.agg, h.P);
         break;
       case MLMC_WILSON2D:
         complex_ = true;
@@ -533,9 +530,14 @@ void Context::op_update_apply(int l, const T* p_old, const T* z, const c64* beta
 template <typename T>
 void Context::op_res_restrict(int l, const T* b, const T* x, T* rc, int nb, const int* act) {
   const Level& L = lv_[l - 1];
-  if (csr_)
+  if (csr_ && general_) {
+    T* r = work<T>().vt[l - 1];
+    csr_residual<T, T, T>(b, x, r, csr_mat<T>(l), nb, csr_cols(L, nb), act, nullptr, s_);
+    csr_spmm<T>(r, rc, csr_R<T>(l), 1.0, 0.0, nb, csr_cols(L, nb), act, s_);
+  } else if (csr_) {
     csr_restrict<T>(b, x, rc, work<T>().vt[l - 1], csr_mat<T>(l), csr_agg<T>(l), nb,
                     csr_cols(L, nb), act, s_);
+  }
   else if (varcoef_)
     varcoef_restrict<T>(b, x, rc, vc_faces<T>(l), vc_diag<T>(l), L.side, true, nb, L.cols, act,
                         s_);
@@ -547,7 +549,9 @@ template <typename T>
 void Context::op_prolong(int l, const T* ec, T* x, int nb, const int* act, double beta) {
   const Level& L = lv_[l - 1];
   const double w = beta == 0.0 ? 1.0 : omega_;
-  if (csr_)
+  if (csr_ && general_)
+    csr_spmm<T>(ec, x, csr_P<T>(l), w, beta, nb, csr_cols(L, nb), act, s_);
+  else if (csr_)
     csr_prolong<T>(ec, x, csr_agg<T>(l), (int)L.n, w, beta, nb, act, s_);
   else if (varcoef_)
     varcoef_prolong<T>(ec, x, L.side, w, beta, nb, act, s_);
@@ -558,7 +562,9 @@ void Context::op_prolong(int l, const T* ec, T* x, int nb, const int* act, doubl
 template <typename T>
 void Context::op_restrict(int l, const T* x, T* xc, int nb, const int* act) {
   const Level& L = lv_[l - 1];
-  if (csr_)
+  if (csr_ && general_)
+    csr_spmm<T>(x, xc, csr_R<T>(l), 1.0, 0.0, nb, csr_cols(L, nb), act, s_);
+  else if (csr_)
     csr_restrict<T>(nullptr, x, xc, nullptr, csr_mat<T>(l), csr_agg<T>(l), nb, csr_cols(L, nb),
                     act, s_);
   else if (varcoef_)
@@ -1183,6 +1189,10 @@ void Context::samples_batch(int level, uint64_t seed, uint64_t first, int nbatch
                             double* err_out) {
   MLMC_REQUIRE(level >= 1 && level < L_, MLMC_EINVAL, "sample level must be in [1, L-1]");
   MLMC_REQUIRE(nbatch >= 1 && nbatch <= nb_, MLMC_EINVAL, "batch size out of range");
+  if (general_) {
+    samples_batch_general(level, seed, first, nbatch, out, err_out);
+    return;
+  }
   const int64_t n1 = lv_[level - 1].n, n2 = lv_[level].n;
   write_probes(level, seed, kStreamProbe, first, nbatch, b1_);
   bool ok1 = true, ok2 = true;
@@ -1199,7 +1209,14 @@ void Context::samples_batch(int level, uint64_t seed, uint64_t first, int nbatch
     vec_dot_partials<double>(b2_, y2_, n2, nbatch, nullptr, partials_, s_);
   }
   finish_sums(partials_, reduce_blocks(n2), nbatch, qb, s_);
-  // scalars e1, e2, qa, qb are consecutive blocks of nb_ entries
+  finish_samples(level, nbatch, ok1, ok2, out, err_out);
+}
+
+// copy the batch's scalars (stated errors e1, e2 and quadratic forms qa, qb,
+// consecutive blocks of nb_ entries) to the host, form s = qa - qb and the
+// relative stated errors; throw if a solve missed solve_tol
+void Context::finish_samples(int level, int nbatch, bool ok1, bool ok2, c64* out,
+                             double* err_out) {
   MLMC_HIP(hipMemcpyAsync(host_c64_, scal_[kErr1], sizeof(c64) * 4 * nb_,
                           hipMemcpyDeviceToHost, s_));
   MLMC_HIP(hipStreamSynchronize(s_));

@@ -11,6 +11,9 @@
 
 namespace mlmc {
 
+// counter-RNG streams of the probes: level samples, pilot, plain Hutchinson
+constexpr uint64_t kStreamProbe = 0, kStreamPilot = 1, kStreamHutch = 3;
+
 // Device memory hooks (set through mlmc_set_allocator).
 struct AllocHooks {
   mlmc_alloc_fn alloc = nullptr;
@@ -60,6 +63,14 @@ struct Level {
   std::vector<int64_t> h_rp;
   std::vector<int> h_ci, h_agg, h_colour;
   std::vector<double> h_v;
+  // CSR levels with given prolongations: P (n x pcols) and R = P^T, device
+  // copies in both precisions, and P's host copy
+  CsrMat<float> P32, R32;
+  CsrMat<double> P64, R64;
+  int pcols = 0;
+  std::vector<int64_t> hp_rp;
+  std::vector<int> hp_ci;
+  std::vector<double> hp_v;
 };
 
 // Batched flexible GMRES workspace (precision T)
@@ -150,12 +161,18 @@ class Context {
   }
   void build_poisson();
   void build_varcoef(const double* k);
-  void build_csr(const mlmc_operator& A, const int32_t* const* aggs);
+  void build_csr(const mlmc_operator& A, const int32_t* const* aggs, const mlmc_csr* P);
+  void csr_general_coarse_trace();
+  void samples_batch_general(int level, uint64_t seed, uint64_t first, int nbatch, c64* out,
+                             double* err);
+  void finish_samples(int level, int nbatch, bool ok1, bool ok2, c64* out, double* err);
   void csr_upload(Level& L, bool last);
   void tune_csr();
   template <typename T> const CsrMat<T>& csr_mat(int l) const;
   template <typename T> const CsrSweep<T>& csr_sweep(int l) const;
   template <typename T> const CsrAgg<T>& csr_agg(int l) const;
+  template <typename T> const CsrMat<T>& csr_P(int l) const;  // given prolongation
+  template <typename T> const CsrMat<T>& csr_R(int l) const;  // its transpose
   template <typename T> void vcycle_csr(int l, const T* b, T* x, int nb, const int* act,
                                         c64* rz_partials);
   void tune_varcoef();
@@ -291,6 +308,10 @@ class Context {
   bool complex_ = false;
   bool varcoef_ = false;
   bool csr_ = false;
+  // CSR with given prolongations: the general decomposition of Sec. 4.1
+  // (finest-level probes restricted level by level through gA_/gB_)
+  bool general_ = false;
+  double *gA_ = nullptr, *gB_ = nullptr;
   // learned smoother state: FP32 master weights, Adam moments, gradient, BF16
   // fragments, BF16 link features; nn_use_ is true while a solve runs with it
   bool nn_ready_ = false, nn_use_ = false;

@@ -14,15 +14,21 @@ namespace mlmc {
 namespace {
 
 struct HostCsr {
-  int n = 0;
+  int n = 0;     // rows
+  int cols = 0;  // columns
   std::vector<int64_t> rp;
   std::vector<int> ci;
   std::vector<double> v;
 };
 
-// rows sorted by column, repeated entries summed, zero entries dropped
-HostCsr canonical(int64_t n, const int64_t* rp, const int32_t* ci, const double* v) {
+// rows sorted by column, repeated entries summed, zero entries dropped; n rows,
+// ncols columns (ncols 0: square)
+HostCsr canonical(int64_t n, const int64_t* rp, const int32_t* ci, const double* v,
+                  int64_t ncols = 0) {
+  if (ncols == 0) ncols = n;
   MLMC_REQUIRE(n >= 1 && n < (int64_t)1 << 31, MLMC_EINVAL, "CSR needs 1 <= n < 2^31");
+  MLMC_REQUIRE(ncols >= 1 && ncols < (int64_t)1 << 31, MLMC_EINVAL,
+               "CSR needs 1 <= cols < 2^31");
   MLMC_REQUIRE(rp != nullptr && ci != nullptr && v != nullptr, MLMC_EINVAL,
                "CSR needs row_ptr, col_idx and vals");
   MLMC_REQUIRE(rp[0] == 0, MLMC_EINVAL, "row_ptr[0] must be 0");
@@ -31,6 +37,7 @@ HostCsr canonical(int64_t n, const int64_t* rp, const int32_t* ci, const double*
   MLMC_REQUIRE(rp[n] < (int64_t)1 << 31, MLMC_EINVAL, "CSR needs nnz < 2^31");
   HostCsr A;
   A.n = (int)n;
+  A.cols = (int)ncols;
   A.rp.assign(n + 1, 0);
   A.ci.reserve(rp[n]);
   A.v.reserve(rp[n]);
@@ -38,7 +45,7 @@ HostCsr canonical(int64_t n, const int64_t* rp, const int32_t* ci, const double*
   for (int64_t i = 0; i < n; ++i) {
     row.clear();
     for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
-      MLMC_REQUIRE(ci[e] >= 0 && ci[e] < n, MLMC_EINVAL, "column index out of range");
+      MLMC_REQUIRE(ci[e] >= 0 && ci[e] < ncols, MLMC_EINVAL, "column index out of range");
       MLMC_REQUIRE(std::isfinite(v[e]), MLMC_EINVAL, "CSR values must be finite");
       row.push_back({ci[e], v[e]});
     }
@@ -151,6 +158,7 @@ HostCsr galerkin(const HostCsr& A, const std::vector<int>& agg, int nc) {
   }
   HostCsr C;
   C.n = nc;
+  C.cols = nc;
   C.rp.assign(nc + 1, 0);
   std::vector<double> acc(nc, 0.0);
   std::vector<int> seen(nc, -1), touched;
@@ -181,6 +189,106 @@ HostCsr galerkin(const HostCsr& A, const std::vector<int>& agg, int nc) {
   return C;
 }
 
+// X^T (cols x rows), rows of the result in ascending column order
+HostCsr transpose(const HostCsr& X) {
+  HostCsr T;
+  T.n = X.cols;
+  T.cols = X.n;
+  T.rp.assign(T.n + 1, 0);
+  for (int c : X.ci) ++T.rp[c + 1];
+  for (int i = 0; i < T.n; ++i) T.rp[i + 1] += T.rp[i];
+  T.ci.resize(X.ci.size());
+  T.v.resize(X.v.size());
+  std::vector<int64_t> fill(T.rp.begin(), T.rp.end() - 1);
+  for (int i = 0; i < X.n; ++i)
+    for (int64_t e = X.rp[i]; e < X.rp[i + 1]; ++e) {
+      const int64_t d = fill[X.ci[e]]++;
+      T.ci[d] = i;
+      T.v[d] = X.v[e];
+    }
+  return T;
+}
+
+// X Y (X.n x Y.cols), rows with ascending columns, exact zeros dropped
+HostCsr spgemm(const HostCsr& X, const HostCsr& Y) {
+  MLMC_REQUIRE(X.cols == Y.n, MLMC_EINVAL, "sparse product: inner dimensions differ");
+  HostCsr C;
+  C.n = X.n;
+  C.cols = Y.cols;
+  C.rp.assign(C.n + 1, 0);
+  std::vector<double> acc(Y.cols, 0.0);
+  std::vector<int> seen(Y.cols, -1), touched;
+  for (int i = 0; i < X.n; ++i) {
+    touched.clear();
+    for (int64_t e = X.rp[i]; e < X.rp[i + 1]; ++e) {
+      const int k = X.ci[e];
+      const double a = X.v[e];
+      for (int64_t f = Y.rp[k]; f < Y.rp[k + 1]; ++f) {
+        const int j = Y.ci[f];
+        if (seen[j] != i) {
+          seen[j] = i;
+          acc[j] = 0.0;
+          touched.push_back(j);
+        }
+        acc[j] += a * Y.v[f];
+      }
+    }
+    std::sort(touched.begin(), touched.end());
+    for (int j : touched)
+      if (acc[j] != 0.0) {
+        C.ci.push_back(j);
+        C.v.push_back(acc[j]);
+      }
+    C.rp[i + 1] = (int64_t)C.ci.size();
+  }
+  return C;
+}
+
+// SELL-64 copy (see CsrMat) of the rows `rows` of (rp, ci, v) (row -1: an
+// empty padding position): slice offsets, column indices and values; with
+// skip_diag the diagonal entry of each row is left out.  Padding entries hold
+// value 0 and, for square matrices (own_pad), the row itself as column,
+// otherwise column 0, so they add nothing and read in bounds.
+void sell_build(const std::vector<int64_t>& rp, const std::vector<int>& ci,
+                const std::vector<double>& v, const std::vector<int>& rows, bool skip_diag,
+                bool own_pad, std::vector<int>& sptr, std::vector<int>& sci,
+                std::vector<double>& sv) {
+  const int m = (int)rows.size();
+  const int ns = (m + 63) / 64;
+  sptr.assign(ns + 1, 0);
+  for (int sl = 0; sl < ns; ++sl) {
+    int w = 0;
+    for (int l = 0; l < 64 && sl * 64 + l < m; ++l) {
+      const int i = rows[sl * 64 + l];
+      if (i < 0) continue;
+      const int len = (int)(rp[i + 1] - rp[i]) - (skip_diag ? 1 : 0);
+      w = std::max(w, len);
+    }
+    MLMC_REQUIRE((int64_t)sptr[sl] + 64LL * w < (int64_t)1 << 31, MLMC_EINVAL,
+                 "sliced matrix copy exceeds 2^31 entries");
+    sptr[sl + 1] = sptr[sl] + 64 * w;
+  }
+  sci.assign(sptr[ns], 0);
+  sv.assign(sptr[ns], 0.0);
+  for (int sl = 0; sl < ns; ++sl) {
+    const int w = (sptr[sl + 1] - sptr[sl]) / 64;
+    for (int l = 0; l < 64; ++l) {
+      const int pos = sl * 64 + l;
+      const int i = pos < m ? rows[pos] : -1;
+      int e = 0;
+      if (i >= 0) {
+        for (int64_t q = rp[i]; q < rp[i + 1]; ++q) {
+          if (skip_diag && ci[q] == i) continue;
+          sci[sptr[sl] + e * 64 + l] = ci[q];
+          sv[sptr[sl] + e * 64 + l] = v[q];
+          ++e;
+        }
+      }
+      for (; e < w; ++e) sci[sptr[sl] + e * 64 + l] = (own_pad && i >= 0) ? i : 0;
+    }
+  }
+}
+
 }  // namespace
 
 template <> const CsrMat<float>& Context::csr_mat<float>(int l) const { return lv_[l - 1].A32; }
@@ -191,6 +299,10 @@ template <> const CsrSweep<float>& Context::csr_sweep<float>(int l) const {
 template <> const CsrSweep<double>& Context::csr_sweep<double>(int l) const {
   return lv_[l - 1].S64;
 }
+template <> const CsrMat<float>& Context::csr_P<float>(int l) const { return lv_[l - 1].P32; }
+template <> const CsrMat<double>& Context::csr_P<double>(int l) const { return lv_[l - 1].P64; }
+template <> const CsrMat<float>& Context::csr_R<float>(int l) const { return lv_[l - 1].R32; }
+template <> const CsrMat<double>& Context::csr_R<double>(int l) const { return lv_[l - 1].R64; }
 template <> const CsrAgg<float>& Context::csr_agg<float>(int l) const { return lv_[l - 1].G32; }
 template <> const CsrAgg<double>& Context::csr_agg<double>(int l) const { return lv_[l - 1].G64; }
 
@@ -210,46 +322,9 @@ void Context::csr_upload(Level& L, bool last) {
   auto to_f32 = [](const std::vector<double>& a) {
     return std::vector<float>(a.begin(), a.end());
   };
-  // SELL-64 copy of rows rows[0..m-1] (row -1: an empty padding position):
-  // slice offsets, column indices and values; with skip_diag the diagonal is
-  // left out.  Padding entries hold value 0 and the row itself as column (0
-  // for padding positions), so they add nothing and read in bounds.
   auto sell = [&](const std::vector<int>& rows, bool skip_diag, std::vector<int>& sptr,
                   std::vector<int>& sci, std::vector<double>& sv) {
-    const int m = (int)rows.size();
-    const int ns = (m + 63) / 64;
-    sptr.assign(ns + 1, 0);
-    for (int sl = 0; sl < ns; ++sl) {
-      int w = 0;
-      for (int l = 0; l < 64 && sl * 64 + l < m; ++l) {
-        const int i = rows[sl * 64 + l];
-        if (i < 0) continue;
-        const int len = (int)(L.h_rp[i + 1] - L.h_rp[i]) - (skip_diag ? 1 : 0);
-        w = std::max(w, len);
-      }
-      MLMC_REQUIRE((int64_t)sptr[sl] + 64LL * w < (int64_t)1 << 31, MLMC_EINVAL,
-                   "sliced matrix copy exceeds 2^31 entries");
-      sptr[sl + 1] = sptr[sl] + 64 * w;
-    }
-    sci.assign(sptr[ns], 0);
-    sv.assign(sptr[ns], 0.0);
-    for (int sl = 0; sl < ns; ++sl) {
-      const int w = (sptr[sl + 1] - sptr[sl]) / 64;
-      for (int l = 0; l < 64; ++l) {
-        const int pos = sl * 64 + l;
-        const int i = pos < m ? rows[pos] : -1;
-        int e = 0;
-        if (i >= 0) {
-          for (int64_t q = L.h_rp[i]; q < L.h_rp[i + 1]; ++q) {
-            if (skip_diag && L.h_ci[q] == i) continue;
-            sci[sptr[sl] + e * 64 + l] = L.h_ci[q];
-            sv[sptr[sl] + e * 64 + l] = L.h_v[q];
-            ++e;
-          }
-        }
-        for (; e < w; ++e) sci[sptr[sl] + e * 64 + l] = i >= 0 ? i : 0;
-      }
-    }
+    sell_build(L.h_rp, L.h_ci, L.h_v, rows, skip_diag, true, sptr, sci, sv);
   };
   // the matrix by rows: plain CSR (dense build) and its SELL-64 copy
   std::vector<int> rp32(L.h_rp.begin(), L.h_rp.end());
@@ -261,8 +336,8 @@ void Context::csr_upload(Level& L, bool last) {
   sell(all, false, sptr, sci, sv);
   const int* dsptr = up(sptr);
   const int* dsci = up(sci);
-  L.A64 = {n, rp, ci, up(L.h_v), dsptr, dsci, up(sv)};
-  L.A32 = {n, rp, ci, up(to_f32(L.h_v)), dsptr, dsci, up(to_f32(sv))};
+  L.A64 = {n, n, rp, ci, up(L.h_v), dsptr, dsci, up(sv)};
+  L.A32 = {n, n, rp, ci, up(to_f32(L.h_v)), dsptr, dsci, up(to_f32(sv))};
   // the off-diagonal part by colour class (ascending rows within a class), each
   // class padded to whole slices, and the inverted diagonal per position
   const int ncol = n ? *std::max_element(L.h_colour.begin(), L.h_colour.end()) + 1 : 0;
@@ -298,6 +373,29 @@ void Context::csr_upload(Level& L, bool last) {
   L.S32.sdi = up(to_f32(sdi));
   L.S64.soff = L.S32.soff = soff;
   if (last) return;
+  if (general_) {
+    // given prolongation P (n x pcols) and R = P^T, SELL-64 copies of both
+    HostCsr Ph;
+    Ph.n = n;
+    Ph.cols = L.pcols;
+    Ph.rp = L.hp_rp;
+    Ph.ci = L.hp_ci;
+    Ph.v = L.hp_v;
+    const HostCsr Rh = transpose(Ph);
+    auto put = [&](const HostCsr& M, CsrMat<float>& m32, CsrMat<double>& m64) {
+      std::vector<int> rows(M.n), sp, sc;
+      std::vector<double> sw;
+      std::iota(rows.begin(), rows.end(), 0);
+      sell_build(M.rp, M.ci, M.v, rows, false, false, sp, sc, sw);
+      const int* dsp = up(sp);
+      const int* dsc = up(sc);
+      m64 = {M.n, M.cols, nullptr, nullptr, nullptr, dsp, dsc, up(sw)};
+      m32 = {M.n, M.cols, nullptr, nullptr, nullptr, dsp, dsc, up(to_f32(sw))};
+    };
+    put(Ph, L.P32, L.P64);
+    put(Rh, L.R32, L.R64);
+    return;
+  }
   // aggregation: member lists (ascending) and the scales 1/sqrt|J|
   const int nc = *std::max_element(L.h_agg.begin(), L.h_agg.end()) + 1;
   std::vector<int> aptr(nc + 1, 0), arows(n);
@@ -317,7 +415,9 @@ void Context::csr_upload(Level& L, bool last) {
   L.G32 = {nc, dagg, daptr, darows, up(to_f32(fs)), up(to_f32(cs))};
 }
 
-void Context::build_csr(const mlmc_operator& A, const int32_t* const* aggs) {
+void Context::build_csr(const mlmc_operator& A, const int32_t* const* aggs, const mlmc_csr* P) {
+  MLMC_REQUIRE(!(aggs && P), MLMC_EINVAL, "give aggregate maps or prolongations, not both");
+  general_ = P != nullptr;
   lv_.resize(Ls_);
   HostCsr cur = canonical(A.n, A.row_ptr, A.col_idx, A.vals);
   for (int l = 0; l < Ls_; ++l) {
@@ -328,7 +428,24 @@ void Context::build_csr(const mlmc_operator& A, const int32_t* const* aggs) {
     L.dof = 1;
     L.n = cur.n;
     L.h_colour = first_fit_colours(cur);
-    if (l + 1 < Ls_) {
+    if (l + 1 < Ls_ && P) {
+      // given prolongation: A_{l+1} = P^T A_l P (Sec. 4.1, R = P^T)
+      const mlmc_csr& Pl = P[l];
+      MLMC_REQUIRE(Pl.rows == cur.n, MLMC_EINVAL,
+                   "P[" + std::to_string(l) + "] must have n_l rows");
+      MLMC_REQUIRE(Pl.cols >= 1 && Pl.cols <= Pl.rows, MLMC_EINVAL,
+                   "P[" + std::to_string(l) + "] needs 1 <= cols <= rows");
+      HostCsr Ph = canonical(Pl.rows, Pl.row_ptr, Pl.col_idx, Pl.vals, Pl.cols);
+      HostCsr next = spgemm(transpose(Ph), spgemm(cur, Ph));
+      L.pcols = Ph.cols;
+      L.hp_rp = std::move(Ph.rp);
+      L.hp_ci = std::move(Ph.ci);
+      L.hp_v = std::move(Ph.v);
+      L.h_rp = std::move(cur.rp);
+      L.h_ci = std::move(cur.ci);
+      L.h_v = std::move(cur.v);
+      cur = std::move(next);
+    } else if (l + 1 < Ls_) {
       int nc = 0;
       if (aggs) {
         MLMC_REQUIRE(aggs[l] != nullptr, MLMC_EINVAL, "agg[" + std::to_string(l) + "] is null");
@@ -362,7 +479,73 @@ void Context::build_csr(const mlmc_operator& A, const int32_t* const* aggs) {
   for (int l = 0; l < Ls_; ++l) csr_upload(lv_[l], l + 1 == Ls_);
   MLMC_HIP(hipStreamSynchronize(s_));
   finish_real_build();
+  if (general_) {
+    gA_ = dalloc_n<double>(lv_[1].n * nb_);
+    gB_ = dalloc_n<double>(lv_[1].n * nb_);
+    csr_general_coarse_trace();
+  }
   tune_csr();
+}
+
+// Coarsest term of the general decomposition (Remark 4.2): tr(A_L^{-1} M) with
+// M = Rhat_L Phat_L, formed level by level as M_{l+1} = P_l^T M_l P_l from
+// M_2 = P_1^T P_1 (sparse, on the host); the FP64 inverse of A_L comes from
+// the device.
+void Context::csr_general_coarse_trace() {
+  auto hp = [&](int l) {  // P_l as a host matrix (l 1-based)
+    HostCsr Ph;
+    Ph.n = (int)lv_[l - 1].n;
+    Ph.cols = lv_[l - 1].pcols;
+    Ph.rp = lv_[l - 1].hp_rp;
+    Ph.ci = lv_[l - 1].hp_ci;
+    Ph.v = lv_[l - 1].hp_v;
+    return Ph;
+  };
+  HostCsr P1 = hp(1);
+  HostCsr M = spgemm(transpose(P1), P1);
+  for (int l = 2; l < L_; ++l) {
+    HostCsr Pl = hp(l);
+    M = spgemm(transpose(Pl), spgemm(M, Pl));
+  }
+  const int nL = (int)lv_[L_ - 1].n;
+  MLMC_REQUIRE(M.n == nL && M.cols == nL, MLMC_EINVAL, "coarsest product has the wrong shape");
+  std::vector<double> inv((size_t)nL * nL);
+  const double* dinv = (L_ == Ls_) ? ainv_solver_ : ainv_mlmc_;
+  MLMC_HIP(hipMemcpyAsync(inv.data(), dinv, sizeof(double) * inv.size(), hipMemcpyDeviceToHost,
+                          s_));
+  MLMC_HIP(hipStreamSynchronize(s_));
+  // tr(A^{-1} M) = sum_{i,j} inv[i][j] M[j][i], over M's entries
+  double tr = 0.0;
+  for (int j = 0; j < nL; ++j)
+    for (int64_t e = M.rp[j]; e < M.rp[j + 1]; ++e) tr += inv[(size_t)M.ci[e] * nL + j] * M.v[e];
+  coarse_trace_ = {tr, 0.0};
+}
+
+// Level-l samples of the general decomposition: x on the finest level (probe
+// stream keyed by level l), b_l = Rhat_l x by l-1 restrictions (FP64), y =
+// A_l^{-1} b_l and z = A_{l+1}^{-1} R_l b_l; with R = P^T the two quadratic forms
+// x^T Phat y and x^T Phat_{l+1} z are b_l^T y and b_{l+1}^T z.
+void Context::samples_batch_general(int level, uint64_t seed, uint64_t first, int nbatch,
+                                    c64* out, double* err_out) {
+  const int64_t n1 = lv_[0].n;
+  probes_write<double>(b1_, n1, nbatch, seed, 0, first, (uint64_t)level, kStreamProbe, s_);
+  double* bl = b1_;
+  for (int l = 1; l < level; ++l) {
+    double* nxt = (bl == gA_) ? gB_ : gA_;
+    op_restrict<double>(l, bl, nxt, nbatch, nullptr);
+    bl = nxt;
+  }
+  bool ok1 = true, ok2 = true;
+  c64 *e1 = scal_[kErr1], *e2 = scal_[kErr2], *qa = scal_[kQa], *qb = scal_[kQb];
+  solve(level, bl, y1_, nbatch, e1, nullptr, &ok1);
+  op_restrict<double>(level, bl, b2_, nbatch, nullptr);
+  solve(level + 1, b2_, y2_, nbatch, e2, nullptr, &ok2);
+  const int64_t nl = lv_[level - 1].n, nl1 = lv_[level].n;
+  vec_dot_partials<double>(bl, y1_, nl, nbatch, nullptr, partials_, s_);
+  finish_sums(partials_, reduce_blocks(nl), nbatch, qa, s_);
+  vec_dot_partials<double>(b2_, y2_, nl1, nbatch, nullptr, partials_, s_);
+  finish_sums(partials_, reduce_blocks(nl1), nbatch, qb, s_);
+  finish_samples(level, nbatch, ok1, ok2, out, err_out);
 }
 
 // Autotuner of the CSR kernels: per smoothed level, time one Gauss-Seidel
@@ -429,7 +612,7 @@ void Context::vcycle_csr(int l, const T* b, T* x, int nb, const int* act, c64* r
     // diagonal) and of a residual (all entries, offsets), shared by the columns
     const double sweep_mat = (double)(nnz - n) * (4.0 + sizeof(T)) + (double)n * (8.0 + sizeof(T));
     const double res_mat = (double)nnz * (4.0 + sizeof(T)) + 4.0 * (double)n;
-    const double enc = (double)sizeof(T) * (double)G.nc;
+    const double enc = (double)sizeof(T) * (double)lv_[l].n;
     const int pre = opt_.nu_pre, post = opt_.nu_post;
     const int cols = csr_cols(L, nb);
     if (pre > 0) vec_zero<T>(x, n, nb, act, s_);
@@ -438,15 +621,32 @@ void Context::vcycle_csr(int l, const T* b, T* x, int nb, const int* act, c64* r
                [&] { csr_gs_sweep<T>(b, x, S, (int)n, nb, cols, act, false, s_); });
     T* bc = w.vb[l];
     T* ec = w.vx[l];
-    if (pre == 0)
-      csr_restrict<T>(nullptr, b, bc, nullptr, A, G, nb, cols, act, s_);
-    else  // the residual passes through the level's scratch vector
-      timed<T>(kTimResRestrict, 2.0 * en + enc + res_mat / nb, act, nb,
-               [&] { csr_restrict<T>(b, x, bc, w.vt[l - 1], A, G, nb, cols, act, s_); });
-    vcycle_csr<T>(l + 1, bc, ec, nb, act, nullptr);
-    timed<T>(kTimProlong, (pre == 0 ? 1.0 : 2.0) * en + enc, act, nb, [&] {
-      csr_prolong<T>(ec, x, G, (int)n, omega_, pre == 0 ? 0.0 : 1.0, nb, act, s_);
-    });
+    if (general_) {  // given P and R = P^T
+      const CsrMat<T>& Pm = csr_P<T>(l);
+      const CsrMat<T>& Rm = csr_R<T>(l);
+      if (pre == 0) {
+        csr_spmm<T>(b, bc, Rm, 1.0, 0.0, nb, cols, act, s_);
+      } else {
+        timed<T>(kTimResRestrict, 2.0 * en + enc + res_mat / nb, act, nb, [&] {
+          csr_residual<T, T, T>(b, x, w.vt[l - 1], A, nb, cols, act, nullptr, s_);
+          csr_spmm<T>(w.vt[l - 1], bc, Rm, 1.0, 0.0, nb, cols, act, s_);
+        });
+      }
+      vcycle_csr<T>(l + 1, bc, ec, nb, act, nullptr);
+      timed<T>(kTimProlong, (pre == 0 ? 1.0 : 2.0) * en + enc, act, nb, [&] {
+        csr_spmm<T>(ec, x, Pm, omega_, pre == 0 ? 0.0 : 1.0, nb, cols, act, s_);
+      });
+    } else {
+      if (pre == 0)
+        csr_restrict<T>(nullptr, b, bc, nullptr, A, G, nb, cols, act, s_);
+      else  // the residual passes through the level's scratch vector
+        timed<T>(kTimResRestrict, 2.0 * en + enc + res_mat / nb, act, nb,
+                 [&] { csr_restrict<T>(b, x, bc, w.vt[l - 1], A, G, nb, cols, act, s_); });
+      vcycle_csr<T>(l + 1, bc, ec, nb, act, nullptr);
+      timed<T>(kTimProlong, (pre == 0 ? 1.0 : 2.0) * en + enc, act, nb, [&] {
+        csr_prolong<T>(ec, x, G, (int)n, omega_, pre == 0 ? 0.0 : 1.0, nb, act, s_);
+      });
+    }
     for (int i = 0; i < post; ++i)
       timed<T>(kTimGs, 3.0 * en + sweep_mat / nb, act, nb,
                [&] { csr_gs_sweep<T>(b, x, S, (int)n, nb, cols, act, true, s_); });
@@ -471,6 +671,7 @@ void Context::export_csr(int level, int64_t* nnz, int64_t* row_ptr, int32_t* col
   if (vals) std::copy(L.h_v.begin(), L.h_v.end(), vals);
   if (agg) {
     MLMC_REQUIRE(level < Ls_, MLMC_EINVAL, "the coarsest level has no aggregates");
+    MLMC_REQUIRE(!general_, MLMC_EINVAL, "a hierarchy with given prolongations has no aggregates");
     std::copy(L.h_agg.begin(), L.h_agg.end(), agg);
   }
   if (colour) std::copy(L.h_colour.begin(), L.h_colour.end(), colour);

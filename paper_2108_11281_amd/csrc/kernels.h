@@ -341,7 +341,8 @@ void givens_solve(c64* H, c64* cs, c64* sn, c64* g, int* dims, c64* y, const int
 // are the plain CSR arrays (dense build of the coarsest level)
 template <typename T>
 struct CsrMat {
-  int n = 0;
+  int n = 0;                  // rows
+  int ncol = 0;               // columns (the length of the vectors it multiplies)
   const int* rp = nullptr;    // n + 1 row offsets
   const int* ci = nullptr;    // column of each entry
   const T* v = nullptr;       // value of each entry
@@ -393,5 +394,11 @@ void csr_prolong(const T* ec, T* x, const CsrAgg<T>& G, int n, double omega, dou
                  const int* active, hipStream_t s);
 // left half of the n x 2n augmented matrix [A | .] (rows of width 2n)
 void csr_dense(const CsrMat<double>& A, double* aug, hipStream_t s);
+// y = beta y + w M x for a rectangular M (M.n x M.ncol; y has M.n, x M.ncol
+// entries per column; beta = 0: y is not read): the general prolongation
+// (M = P) and restriction (M = R = P^T) between CSR levels
+template <typename T>
+void csr_spmm(const T* x, T* y, const CsrMat<T>& M, double w, double beta, int nb, int cols,
+              const int* active, hipStream_t s);
 
 }  // namespace mlmc

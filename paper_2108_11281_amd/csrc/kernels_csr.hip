@@ -210,6 +210,35 @@ __global__ __launch_bounds__(kThreads) void k_csr_gs(
     if (on[q]) x[(int64_t)(col0 + q) * n + i] = (acc[q] - sum[q]) * d;
 }
 
+// y = beta y + w M x, M rectangular (m rows, x of length nx per column)
+template <typename T, int COLS>
+__global__ __launch_bounds__(kThreads) void k_csr_spmm(
+    const T* __restrict__ x, T* __restrict__ y, const int* __restrict__ sptr,
+    const int* __restrict__ sci, const T* __restrict__ sv, int m, int nx, T w, T beta, int nb,
+    const int* active, int* tlog) {
+  const int col0 = blockIdx.y * COLS;
+  if (tlog && blockIdx.x == 0 && threadIdx.x < COLS && col0 + (int)threadIdx.x < nb)
+    tlog[col0 + threadIdx.x] = active ? active[col0 + threadIdx.x] : 1;
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= m) return;
+  bool on[COLS];
+  T acc[COLS];
+#pragma unroll
+  for (int q = 0; q < COLS; ++q) {
+    on[q] = col_on(active, col0 + q, nb);
+    acc[q] = T(0);
+  }
+  const int sl = i >> 6;
+  sell_row_sum<T, COLS>(sci, sv, sptr[sl] + (i & 63), (sptr[sl + 1] - sptr[sl]) >> 6, x, nx,
+                        col0, on, acc);
+#pragma unroll
+  for (int q = 0; q < COLS; ++q) {
+    if (!on[q]) continue;
+    T* yq = y + (int64_t)(col0 + q) * m + i;
+    *yq = (beta == T(0)) ? w * acc[q] : beta * *yq + w * acc[q];
+  }
+}
+
 // rc_J = s_J sum_{i in J} r_i, a thread per aggregate J, members in ascending order
 template <typename T, int COLS>
 __global__ __launch_bounds__(kThreads) void k_csr_agg_sum(
@@ -343,12 +372,23 @@ void csr_prolong(const T* ec, T* x, const CsrAgg<T>& G, int n, double omega, dou
               timing_log());
 }
 
+template <typename T>
+void csr_spmm(const T* x, T* y, const CsrMat<T>& M, double w, double beta, int nb, int cols,
+              const int* active, hipStream_t s) {
+  if (M.n == 0) return;
+  CSR_COLS_DISPATCH(cols, MLMC_LAUNCH((k_csr_spmm<T, C>), csr_grid(M.n, nb, C), dim3(kThreads), 0,
+                                      s, x, y, M.sptr, M.sci, M.sv, M.n, M.ncol, (T)w, (T)beta, nb,
+                                      active, timing_log()));
+}
+
 void csr_dense(const CsrMat<double>& A, double* aug, hipStream_t s) {
   if (A.n == 0) return;
   MLMC_LAUNCH(k_csr_dense, dim3((unsigned)A.n), dim3(kThreads), 0, s, A.rp, A.ci, A.v, A.n, aug);
 }
 
 #define CSR_INST(T)                                                                           \
+  template void csr_spmm<T>(const T*, T*, const CsrMat<T>&, double, double, int, int,          \
+                            const int*, hipStream_t);                                         \
   template void csr_update_apply<T>(const T*, const T*, const c64*, T*, T*, const CsrMat<T>&,  \
                                     int, int, const int*, c64*, hipStream_t);                 \
   template void csr_gs_sweep<T>(const T*, T*, const CsrSweep<T>&, int, int, int, const int*,   \

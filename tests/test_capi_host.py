@@ -40,9 +40,11 @@ def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(_capi.TrainOptions) == 32
     assert ctypes.sizeof(_capi.TrainReport) == 48
     # mlmc_operator: 2 ints, 4 doubles, a pointer, an int64, 3 pointers;
-    # mlmc_hierarchy: 5 ints (+pad), a uint64, a pointer, an int (+pad)
+    # mlmc_hierarchy: 5 ints (+pad), a uint64, a pointer, an int (+pad), a pointer;
+    # mlmc_csr: 2 int64, 3 pointers
     assert ctypes.sizeof(_capi.Operator) == 8 + 32 + 8 + 8 + 24
-    assert ctypes.sizeof(_capi.Hierarchy) == 24 + 8 + 8 + 8
+    assert ctypes.sizeof(_capi.Hierarchy) == 24 + 8 + 8 + 8 + 8
+    assert ctypes.sizeof(_capi.Csr) == 16 + 24
 
 
 def test_default_options_and_status_strings():
