@@ -25,6 +25,10 @@ Workloads (--workload):
     about 8, 4-level greedy aggregation hierarchy built by the library,
     multicolour Gauss-Seidel V-cycle inside FP32 CG with FP64 refinement, MLMC
     to relative error 1e-3.
+  laplace_bilinear: Example 4.1's own hierarchy at N = 1023 (bilinear
+    interpolation, R = P^T, Galerkin 9-point coarse operators) through the csr
+    kind with the general decomposition (finest-level probes), 7 MLMC levels
+    (coarsest 15^2) and 8 solver levels (coarsest 7^2).
 
 Printed JSON line: the contract fields plus `roofline` (the dominant kernel,
 timed with HIP events carried in its own dispatches during the timed steps),
@@ -201,7 +205,7 @@ def run_poisson(args, m, torch):
     t0 = time.perf_counter()
     vc = dict(nu_pre=args.nu, nu_post=args.nu)
     est = m.TraceEstimator("poisson2d", N, L, L, precision="fp32_ir64", nb=args.nb,
-                           solve_tol=1e-10, alloc=args.alloc, **vc)
+                           solve_tol=1e-10, alloc=args.alloc, narrow_fp64=args.narrow_fp64, **vc)
     setup_s = time.perf_counter() - t0
     log("setup %.2fs" % setup_s)
     for i in range(args.warmup):
@@ -237,7 +241,8 @@ def run_poisson(args, m, torch):
         log("plain FP64 MLMC, same workload")
         log("FP32 + refinement with HIP-graph replay of the CG iterations (no kernel timing)")
         eg = m.TraceEstimator("poisson2d", N, L, L, precision="fp32_ir64", nb=args.nb,
-                              solve_tol=1e-10, alloc=args.alloc, graphs=1, **vc)
+                              solve_tol=1e-10, alloc=args.alloc, graphs=1,
+                              narrow_fp64=args.narrow_fp64, **vc)
         eg.trace(args.eps, 1000)
         torch.cuda.synchronize()
         tg = time.perf_counter()
@@ -281,7 +286,8 @@ def run_poisson(args, m, torch):
               "variant": "FP32 inner Krylov + V-cycle, FP64 reliable-update refinement "
                          "(no learned smoother on this operator)",
               "n": N * N, "levels": L, "nb": args.nb, "eps": args.eps, "alloc": args.alloc,
-              "solve_tol": 1e-10, "nu_pre": args.nu, "nu_post": args.nu, "omega": 1.8}
+              "solve_tol": 1e-10, "nu_pre": args.nu, "nu_post": args.nu, "omega": 1.8,
+              "narrow_fp64": args.narrow_fp64}
     contract(args, round(ms_per_step / 1000.0, 4), "s", False, ms_per_step, "f32+f64ir",
              "synthetic (Rademacher probes from Philox4x64-10 on the device)", config,
              roofline, cpu, accuracy=accuracy, setup_s=round(setup_s, 3), kernels=kernels,
@@ -466,7 +472,8 @@ def run_graph(args, m, torch):
 
     def make(precision):
         return m.TraceEstimator("csr", 0, Ls, L, matrix=A, precision=precision, nb=args.nb,
-                                solve_tol=w["solve_tol"], alloc=args.alloc, **vc)
+                                solve_tol=w["solve_tol"], alloc=args.alloc,
+                                narrow_fp64=args.narrow_fp64 if precision != "fp64" else 0, **vc)
     t0 = time.perf_counter()
     est = make("fp32_ir64")
     setup_s = time.perf_counter() - t0
@@ -517,8 +524,8 @@ def run_graph(args, m, torch):
                          "FP64 reliable-update refinement",
               "n": n, "nnz": int(A.nnz), "level_sizes": sizes, "levels": L, "nb": args.nb,
               "eps": args.eps, "alloc": args.alloc, "solve_tol": w["solve_tol"],
-              "nu_pre": args.nu, "nu_post": args.nu,
-              "omega": args.omega if args.omega > 0 else 1.8}
+              "nu_pre": args.nu, "nu_post": args.nu, "narrow_fp64": args.narrow_fp64,
+              "omega": args.omega if args.omega > 0 else 1.0}
     contract(args, round(ms_per_step / 1000.0, 4), "s", False, ms_per_step, "f32+f64ir",
              "synthetic (random geometric graph Laplacian + shift, Rademacher probes)", config,
              hbm_roofline("multicolour Gauss-Seidel sweep: k_csr_gs<float> (all colour classes)",
@@ -529,6 +536,88 @@ def run_graph(args, m, torch):
              setup_s=round(setup_s, 3), kernels=kernels, compare=compare)
 
 
+def run_laplace_bilinear(args, m, torch):
+    """Example 4.1's setup at N = 1023: the 5-point Laplacian, bilinear
+    interpolation, Galerkin coarse operators, the general decomposition with
+    finest-level probes, MLMC levels down to 15^2, solver levels down to 7^2."""
+    from workloads import bilinear_prolongations, laplace_matrix, workload
+    w = workload("laplace1023_bilinear_fp32ir")
+    N, Ls, L = w["N"], w["levels_solver"], w["levels_mlmc"]
+    A = laplace_matrix(N)
+    P = bilinear_prolongations(N, Ls)
+    vc = dict(nu_pre=args.nu, nu_post=args.nu)
+    if args.omega > 0:
+        vc["omega"] = args.omega
+
+    def make(precision):
+        return m.TraceEstimator("csr", 0, Ls, L, matrix=A, prolongations=P, precision=precision,
+                                nb=args.nb, solve_tol=w["solve_tol"], alloc=args.alloc,
+                                narrow_fp64=args.narrow_fp64 if precision != "fp64" else 0, **vc)
+    t0 = time.perf_counter()
+    est = make("fp32_ir64")
+    setup_s = time.perf_counter() - t0
+    sizes = [est.level_size(l) for l in range(1, Ls + 1)]
+    log("setup %.2fs, level sizes %s" % (setup_s, sizes))
+    for i in range(args.warmup):
+        r = est.trace(args.eps, 1000 + i)
+        log("warmup %d: %.3fs N_l=%s iters=%d" % (i, r["seconds"], r["n_samples"],
+                                                  r["iterations"]))
+    est.set_timing(["rbgs_sweep"], stride=args.timing_stride)
+    est.reset_kernel_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = []
+    for i in range(args.steps):
+        r = est.trace(args.eps, i + 1)
+        runs.append(r)
+        log("step %d: %.3fs N_l=%s trace=%.6f rmsd=%.3f iters=%d level_s=%s"
+            % (i, r["seconds"], r["n_samples"], r["trace"].real, r["rmsd"], r["iterations"],
+               [round(v, 3) for v in r["level_seconds"]]))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    gs = est.kernel_stats("rbgs_sweep")
+    est.set_timing(True)
+    est.reset_kernel_stats()
+    est.trace(args.eps, 777)
+    kernels = kernel_table(est)
+    est.set_timing(False)
+    est.close()
+    ms_per_step = 1000.0 * elapsed / args.steps
+    compare = {}
+    if not args.no_compare:
+        log("plain FP64 MLMC, same workload")
+        e64 = make("fp64")
+        t64, n64 = timed_traces(e64, args, torch)
+        compare.update(fp64_mlmc_s=round(t64, 3), fp64_mlmc_n_samples=n64,
+                       speedup_vs_fp64_mlmc=round(t64 / (ms_per_step / 1000.0), 2))
+        log("plain FP64 MLMC %.3fs per trace, N_l=%s" % (t64, n64))
+        # (plain Hutchinson at this accuracy needs thousands of finest-level
+        # solves per trace; the aggregation workload reports that comparison)
+        e64.close()
+    accuracy = {"n_samples": [r["n_samples"] for r in runs],
+                "rmsd_rel": [round(r["rmsd"] / abs(r["trace"].real), 7) for r in runs]}
+    if not args.no_cpu:
+        exact = cpu_exact_poisson_trace(N)
+        accuracy.update(exact_trace=exact,
+                        rel_err=[round(abs(r["trace"].real - exact) / exact, 7) for r in runs],
+                        z=[round((r["trace"].real - exact) / r["rmsd"], 2) for r in runs])
+    config = {"workload": "laplace2d_%dx%d_bilinear_Ls%d_L%d_general_nb%d_fp32ir64_eps%g"
+                          % (N, N, Ls, L, args.nb, args.eps),
+              "variant": "Example 4.1 hierarchy (bilinear interpolation, R = P^T, Galerkin), "
+                         "general decomposition with finest-level probes; FP32 CG + "
+                         "multicolour Gauss-Seidel V-cycle, FP64 reliable-update refinement",
+              "n": N * N, "level_sizes": sizes, "levels_mlmc": L, "levels_solver": Ls,
+              "nb": args.nb, "eps": args.eps, "alloc": args.alloc, "solve_tol": w["solve_tol"],
+              "nu_pre": args.nu, "nu_post": args.nu, "narrow_fp64": args.narrow_fp64,
+              "omega": args.omega if args.omega > 0 else 1.0}
+    contract(args, round(ms_per_step / 1000.0, 4), "s", False, ms_per_step, "f32+f64ir",
+             "synthetic (Example 4.1 Laplacian, Rademacher probes)", config,
+             hbm_roofline("multicolour Gauss-Seidel sweep: k_csr_gs<float> (all colour classes)",
+                          gs, args.timing_stride),
+             None, accuracy=accuracy, setup_s=round(setup_s, 3), kernels=kernels,
+             compare=compare)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -536,7 +625,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="poisson1024",
                     choices=["poisson1024", "wilson256", "wilson512", "varcoef_batch",
-                             "graph1m"])
+                             "graph1m", "laplace_bilinear"])
     ap.add_argument("--eps", type=float, default=1e-3)
     ap.add_argument("--N", type=int, default=1024)
     ap.add_argument("--levels", type=int, default=6)
@@ -548,6 +637,9 @@ def main():
                     help="wilson*: spin-structure-preserving aggregation (Example 4.3)")
     ap.add_argument("--n-vec", type=int, default=0,
                     help="wilson*: test vectors per aggregate (0: 8, or 4 with --spin-split)")
+    ap.add_argument("--narrow-fp64", type=int, default=0,
+                    help="real operators: batches of at most this many columns solved in "
+                         "plain FP64 inside the FP32 + refinement run")
     ap.add_argument("--omega", type=float, default=0.0,
                     help="graph1m: coarse-correction scaling (0 = the library default)")
     ap.add_argument("--train-batches", type=int, default=80,
@@ -585,6 +677,8 @@ def main():
         run_wilson(args, m, torch, 512, learned=True)
     elif args.workload == "graph1m":
         run_graph(args, m, torch)
+    elif args.workload == "laplace_bilinear":
+        run_laplace_bilinear(args, m, torch)
     else:
         run_batch(args, m, torch)
 

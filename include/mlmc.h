@@ -180,6 +180,12 @@ typedef struct mlmc_options {
                          HIP graph captured once per (level, batch width);
                          results are bitwise identical.  Bypassed while
                          per-kernel timing is on.  0: direct launches */
+  int narrow_fp64;    /* MLMC_FP32_IR64, real operators: solves of batches of at
+                         most this many columns run in plain FP64 CG (for a few
+                         columns the refinement's extra launches cost more than
+                         the FP32 bandwidth saves); FP64 work vectors of this
+                         width are allocated.  0: every batch in FP32 + FP64
+                         refinement */
 } mlmc_options;
 
 #define MLMC_MAX_LEVELS 16
@@ -203,7 +209,7 @@ typedef struct mlmc_result {
 
 /* Fill *opt with defaults: FP32_IR64, nb 128, 1+1 sweeps, omega 1.8, EQUAL,
  * solve_tol 1e-10, inner_tol 0 (automatic), max_iter 200, max_refine 8, restart 16,
- * min_samples 5, max_samples 2^22, tau 0, learned 0, graphs 0. */
+ * min_samples 5, max_samples 2^22, tau 0, learned 0, graphs 0, narrow_fp64 0. */
 int mlmc_default_options(mlmc_options* opt);
 
 /* Build the hierarchy on the device: copies the operator data, forms the

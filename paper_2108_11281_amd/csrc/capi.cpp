@@ -65,6 +65,7 @@ int mlmc_default_options(mlmc_options* opt) {
   opt->tau = 0.0;
   opt->learned = 0;
   opt->graphs = 0;
+  opt->narrow_fp64 = 0;
   return MLMC_OK;
 }
 

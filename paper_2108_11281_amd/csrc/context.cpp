@@ -139,9 +139,11 @@ template <> Work<double>& Context::work<double>() {
   return w64_;
 }
 
+// work vectors for batches of up to `width` columns (0: nb)
 template <typename T>
-void Context::alloc_work(Work<T>& w) {
-  const int64_t n1 = lv_[0].n * nb_;
+void Context::alloc_work(Work<T>& w, int width) {
+  const int cols = width > 0 ? std::min(width, nb_) : nb_;
+  const int64_t n1 = lv_[0].n * cols;
   w.x = dalloc_n<T>(n1);
   w.r = dalloc_n<T>(n1);
   w.z = dalloc_n<T>(n1);
@@ -153,10 +155,10 @@ void Context::alloc_work(Work<T>& w) {
   w.vt.assign(Ls_, nullptr);
   for (int m = 0; m < Ls_; ++m) {
     if (m > 0) {
-      w.vb[m] = dalloc_n<T>(lv_[m].n * nb_);
-      w.vx[m] = dalloc_n<T>(lv_[m].n * nb_);
+      w.vb[m] = dalloc_n<T>(lv_[m].n * cols);
+      w.vx[m] = dalloc_n<T>(lv_[m].n * cols);
     }
-    if (m < Ls_ - 1) w.vt[m] = dalloc_n<T>(lv_[m].n * nb_);
+    if (m < Ls_ - 1) w.vt[m] = dalloc_n<T>(lv_[m].n * cols);
   }
 }
 
@@ -436,6 +438,9 @@ void Context::finish_real_build() {
   // the FP64 Krylov / V-cycle vectors serve the plain FP64 mode only; the
   // refined FP32 mode keeps its FP64 iterate in the sample-batch buffers
   if (opt_.precision == MLMC_FP64) alloc_work(w64_);
+  MLMC_REQUIRE(opt_.narrow_fp64 >= 0, MLMC_EINVAL, "narrow_fp64 must be >= 0");
+  if (opt_.precision == MLMC_FP32_IR64 && opt_.narrow_fp64 > 0)
+    alloc_work(w64_, opt_.narrow_fp64);
   if (opt_.precision == MLMC_FP32_IR64) {
     alloc_work(w32_);
     r32_ = dalloc_n<float>(n1 * nb_);
@@ -1118,7 +1123,7 @@ void Context::solve(int l, const double* b, double* y, int nb, c64* err, double*
   const double tol = opt_.solve_tol;
   if (l == Ls_) {
     dense_apply<double>(w64_.ainvT, b, y, (int)n, nb, nullptr, s_, w64_.ld);
-  } else if (opt_.precision == MLMC_FP64) {
+  } else if (opt_.precision == MLMC_FP64 || fp64_batch(nb)) {
     MLMC_HIP(hipMemcpyAsync(act_inner_, act_outer_, sizeof(int) * nb,
                             hipMemcpyDeviceToDevice, s_));
     pcg<double>(l, b, y, nb, act_inner_, tol, err);
@@ -1128,7 +1133,7 @@ void Context::solve(int l, const double* b, double* y, int nb, c64* err, double*
   }
   // final FP64 relative residuals (the refined solver ends on a true FP64
   // residual already, kept in rres)
-  if (l == Ls_ || opt_.precision == MLMC_FP64) {
+  if (l == Ls_ || opt_.precision == MLMC_FP64 || fp64_batch(nb)) {
     op_residual<double, double, double>(l, b, y, r64_, nb, nullptr, partials_);
     finish_sums(partials_, nblk_pts, nb, rres, s_);
   }

@@ -219,7 +219,11 @@ class Context {
   void solve_complex(int l, const c64* b, c64* y, int nb, c64* err);
   template <typename T> Fgmres<T>& fg();
   void invert_coarse(int level, double** inv_out, c64* trace_out);
-  template <typename T> void alloc_work(Work<T>& w);
+  template <typename T> void alloc_work(Work<T>& w, int width = 0);
+  // batches solved in plain FP64 although the mode is MLMC_FP32_IR64
+  bool fp64_batch(int nb) const {
+    return opt_.precision == MLMC_FP32_IR64 && !complex_ && nb <= opt_.narrow_fp64;
+  }
 
   // operator pieces on level l (1-based) in precision T
   template <typename T> void op_apply(int l, const T* x, T* y, int nb, const int* act,

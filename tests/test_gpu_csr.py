@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 import scipy.sparse as sp
 
-from oracle import hierarchy, mlmc, operators
+from oracle import hierarchy, mlmc
 from tests.gpu_util import from_dev, quad_scale, require_gpu, to_dev
 from workloads import graph_laplacian
 
@@ -154,9 +154,14 @@ def test_given_aggregates_reproduce_the_poisson_kind():
     # the 2D Poisson matrix with the 2x2 aggregate maps: the same hierarchy as
     # the matrix-free kind, so the same samples for the same seed
     N, L = 32, 3
+    maps = []
+    for side in (N, N // 2):      # 2 x 2 blocks of grid points, numbered row by row
+        iy, ix = np.divmod(np.arange(side * side), side)
+        maps.append((iy // 2) * (side // 2) + ix // 2)
     _, P = hierarchy.poisson_hierarchy(N, L)
-    maps = [p.indices for p in P]
-    A = operators.poisson2d(N)
+    assert all(np.array_equal(m_, p.indices) for m_, p in zip(maps, P))
+    from workloads import laplace_matrix
+    A = laplace_matrix(N)
     est = _est(A, L, agg=maps, precision="fp64", nb=8)
     for l in (1, 2):
         Al, agg, col = est.export_csr(l)

@@ -7,6 +7,7 @@ import pytest
 
 from oracle import hierarchy, mlmc, operators
 from tests.gpu_util import from_dev, quad_scale, require_gpu, to_dev
+from workloads import bilinear_prolongations, laplace_matrix
 
 pytestmark = pytest.mark.gpu
 
@@ -16,10 +17,12 @@ N, LS = 63, 4          # 63^2 -> 31^2 -> 15^2 -> 7^2
 def _est(L, **kw):
     require_gpu()
     import paper_2108_11281_amd as m
-    A, P = hierarchy.laplace_bilinear_hierarchy(N, LS)
     kw.setdefault("nb", 16)
     kw.setdefault("solve_tol", 1e-12)
-    return m.TraceEstimator("csr", 0, LS, L, matrix=A[0], prolongations=P, **kw)
+    # the library's inputs come from the workload generators; the oracle builds
+    # its own hierarchy, so the comparison also checks the two against each other
+    return m.TraceEstimator("csr", 0, LS, L, matrix=laplace_matrix(N),
+                            prolongations=bilinear_prolongations(N, LS), **kw)
 
 
 _ORC = {}
@@ -109,11 +112,25 @@ def test_trace_matches_oracle_driver_and_closed_form():
 def test_prolongations_are_validated():
     require_gpu()
     import paper_2108_11281_amd as m
-    A, P = hierarchy.laplace_bilinear_hierarchy(N, LS)
+    A, P = laplace_matrix(N), bilinear_prolongations(N, LS)
     with pytest.raises(m.MLMCError):          # P_2 given where P_1 belongs
-        m.TraceEstimator("csr", 0, 2, 2, matrix=A[0], prolongations=[P[1]])
+        m.TraceEstimator("csr", 0, 2, 2, matrix=A, prolongations=[P[1]])
     with pytest.raises(ValueError):           # one matrix per level below the coarsest
-        m.TraceEstimator("csr", 0, LS, LS, matrix=A[0], prolongations=P[:1])
+        m.TraceEstimator("csr", 0, LS, LS, matrix=A, prolongations=P[:1])
     with pytest.raises(m.MLMCError):          # aggregates and prolongations together
-        m.TraceEstimator("csr", 0, 2, 2, matrix=A[0], prolongations=P[:1],
+        m.TraceEstimator("csr", 0, 2, 2, matrix=A, prolongations=P[:1],
                          agg=[np.zeros(N * N, dtype=np.int32)])
+
+
+def test_narrow_batches_in_fp64():
+    # FP32 + refinement with batches of up to 8 columns solved in plain FP64:
+    # a batch of 5 takes the FP64 path, a batch of 12 the FP32 one; both give the
+    # oracle's samples
+    est = _est(3, precision="fp32_ir64", nb=16, narrow_fp64=8)
+    orc = _oracle(3)
+    for count in (5, 12):
+        s, err = est.sample_level(1, 21, 0, count, with_error=True)
+        ref = orc.sample(1, 21, 0, count)
+        scale = quad_scale(orc.sample_parts(1, 21, 0, count))
+        assert np.all(np.abs(s - ref) <= 1e-8 * scale), (count, np.max(np.abs(s - ref) / scale))
+        assert np.all(err <= 1e-8)

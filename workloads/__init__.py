@@ -8,4 +8,5 @@ library is imported here, and both receive these arrays as plain inputs.
 """
 from .generate import (gauge_field, varcoef_faces, batch_problem_sizes,  # noqa: F401
                        WORKLOADS, workload, wilson_mass, nn_init_weights,  # noqa: F401
-                       varcoef_levels, graph_laplacian)
+                       varcoef_levels, graph_laplacian,  # noqa: F401
+                       laplace_matrix, bilinear_prolongations)

@@ -82,6 +82,40 @@ def graph_laplacian(n, degree=8.0, shift=1e-2, seed=1):
     return A
 
 
+def laplace_matrix(N):
+    """The 2D 5-point Laplacian of Example 4.1 (diagonal 4, neighbours -1,
+    Dirichlet), N^2 x N^2, unknown iy*N + ix, as a scipy CSR matrix."""
+    import scipy.sparse as sp
+    e = np.ones(N)
+    T = sp.diags([-e[:-1], 2 * e, -e[:-1]], [-1, 0, 1])
+    I = sp.identity(N)
+    A = (sp.kron(T, I) + sp.kron(I, T)).tocsr()
+    A.sort_indices()
+    return A
+
+
+def bilinear_prolongations(N, levels):
+    """The levels-1 interpolation matrices of Example 4.1's hierarchy: grid sides
+    N_{l+1} = floor(N_l / 2), coarse point I at fine point 2I+1, fine points
+    weighted 1, 1/2, 1/4 (tensor product of 1D linear interpolation, Dirichlet
+    boundary), unknowns iy*N + ix; scipy CSR matrices N_l^2 x N_{l+1}^2."""
+    import scipy.sparse as sp
+    out, n = [], N
+    for _ in range(levels - 1):
+        nc = n // 2
+        rows, cols, vals = [], [], []
+        for I in range(nc):
+            for f, w in ((2 * I, 0.5), (2 * I + 1, 1.0), (2 * I + 2, 0.5)):
+                if f < n:
+                    rows.append(f)
+                    cols.append(I)
+                    vals.append(w)
+        p = sp.csr_matrix((vals, (rows, cols)), shape=(n, nc))
+        out.append(sp.kron(p, p).tocsr())
+        n = nc
+    return out
+
+
 def wilson_mass(N):
     """m0 for the Wilson workload at lattice side N (tuned on the CPU so that the
     smallest |eigenvalue| is about 1e-2), or None if not tuned yet."""
@@ -114,6 +148,9 @@ WORKLOADS = {
         kind="wilson2d", N=512, levels_mlmc=3, levels_solver=4, nb=128,
         precision="fp32_ir64", eps=1e-3, solve_tol=1e-10, block=4, n_vec=8,
         setup_sweeps=20, theta_sigma=0.5, gauge_seed=1, learned=True),
+    "laplace1023_bilinear_fp32ir": dict(
+        kind="csr", N=1023, levels_mlmc=7, levels_solver=8, nb=128, precision="fp32_ir64",
+        eps=1e-3, solve_tol=1e-10),
     "graph1m_fp32ir": dict(
         kind="csr", n=1 << 20, degree=8.0, shift=1e-2, graph_seed=1, levels_mlmc=4,
         levels_solver=4, nb=128, precision="fp32_ir64", eps=1e-3, solve_tol=1e-10),
