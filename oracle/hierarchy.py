@@ -209,6 +209,23 @@ def wilson_hierarchy(N, theta, m0, levels, block=4, n_vec=8, sweeps=20, seed=1,
     return A, P
 
 
+def gauge_hierarchy(N, theta, mass, levels, block=4, n_vec=4, sweeps=20, seed=1):
+    """A_1..A_levels, P_1..P_{levels-1} for the gauge Laplacian (Example 4.2):
+    test-vector aggregation as for the Wilson operator, one unknown per fine
+    site (the example's adaptive smoothed aggregation is not reproduced)."""
+    from .operators import gauge_laplacian
+    A = [gauge_laplacian(N, theta, mass)]
+    P = []
+    n_side, dof = N, 1
+    for lvl in range(1, levels):
+        Pl, _ = testvector_aggregation(A[-1], n_side, dof, block, n_vec, sweeps, seed, lvl)
+        P.append(Pl)
+        A.append(galerkin(A[-1], Pl))
+        n_side //= block
+        dof = n_vec
+    return A, P
+
+
 def spin_sign(n_sites, dof):
     """J on a lattice level: +1 on a site's first dof/2 unknowns (spin 0), -1 on
     the rest; on the fine lattice (dof 2) the gamma5 of Example 4.3."""

@@ -13,6 +13,12 @@ Test infrastructure (see the package docstring).
   on an N x N periodic lattice.  Site s = y*N + x, unknown 2*s + spin.
   U_mu(x) = exp(i theta[mu, y, x]); mu = 0 is the x direction (the paper's
   Theta, paired with sigma_1), mu = 1 the y direction (Phi, sigma_2).
+* Gauge Laplacian, Example 4.2: one unknown per site of an N x N periodic
+  lattice, row s = (x, y):
+      (4 + m) u_s - U_0(s) u_{s+x} - U_1(s) u_{s+y}
+                  - conj(U_0(s-x)) u_{s-x} - conj(U_1(s-y)) u_{s-y},
+  U_mu(s) = exp(i theta[mu, y, x]) (the example's Theta for mu = 0, Phi for
+  mu = 1); Hermitian, positive definite for m > 0 or non-trivial phases.
 * 3D 7-point variable-coefficient diffusion with Dirichlet faces:
       A = sum_interior faces k_f (e_i - e_j)(e_i - e_j)^T
         + sum_boundary faces k_f e_i e_i^T + shift * I,
@@ -98,6 +104,43 @@ def wilson2d(N, theta, m0):
                 put(s, yb * N + xb, -0.5 * ub * bwd[mu])
     n = 2 * N * N
     return sp.csr_matrix((np.array(vals), (rows, cols)), shape=(n, n))
+
+
+def gauge_laplacian(N, theta, mass=0.0):
+    """Gauge Laplacian of Example 4.2 (see module doc); theta [2, N, N]."""
+    theta = np.asarray(theta, dtype=np.float64)
+    assert theta.shape == (2, N, N)
+    rows, cols, vals = [], [], []
+    for y in range(N):
+        for x in range(N):
+            s = y * N + x
+            rows.append(s)
+            cols.append(s)
+            vals.append(4.0 + mass)
+            for mu, t in ((0, y * N + (x + 1) % N), (1, ((y + 1) % N) * N + x)):
+                u = np.exp(1j * theta[mu, y, x])
+                rows += [s, t]          # the forward hop and its Hermitian partner
+                cols += [t, s]
+                vals += [-u, -np.conj(u)]
+    return sp.csr_matrix((np.array(vals), (rows, cols)), shape=(N * N, N * N))
+
+
+def gauge_transform(N, theta, phi):
+    """Link phases after the gauge transformation u_s -> exp(i phi_s) u_s:
+    theta_mu(s) + phi(s) - phi(s + mu); the operator becomes D A D^* with
+    D = diag(exp(i phi)), so its spectrum and tr(A^-1) are unchanged."""
+    theta = np.array(theta, dtype=np.float64)
+    phi = np.asarray(phi, dtype=np.float64).reshape(N, N)
+    theta[0] += phi - np.roll(phi, -1, axis=1)
+    theta[1] += phi - np.roll(phi, -1, axis=0)
+    return theta
+
+
+def gauge_laplacian_free_trace(N, mass):
+    """tr(A^-1) of the gauge Laplacian with all phases zero: the periodic
+    Laplacian plus m, eigenvalues m + 4 - 2 cos(2 pi k/N) - 2 cos(2 pi l/N)."""
+    c = 2.0 - 2.0 * np.cos(2.0 * np.pi * np.arange(N) / N)
+    return float(np.sum(1.0 / (mass + c[:, None] + c[None, :])))
 
 
 def gamma5(n_sites):
