@@ -57,7 +57,7 @@ enum mlmc_kind {
                           periodic (Example 4.3 halved, m0 = m/2) */
   MLMC_VARCOEF3D = 2,  /* 7-point diffusion with face coefficients, N^3,
                           Dirichlet faces, plus shift*I */
-  MLMC_CSR = 3         /* a real symmetric positive definite matrix given in
+  MLMC_CSR = 3,        /* a real symmetric positive definite matrix given in
                           compressed sparse row form (the algebraic operators
                           of Sec. 5, whose hierarchy an algebraic multigrid
                           method supplies): aggregates of the matrix graph
@@ -65,6 +65,11 @@ enum mlmc_kind {
                           orthonormal piecewise-constant P (entries 1/sqrt|J|),
                           Galerkin coarse operators (Sec. 4.1), multicolour
                           Gauss-Seidel smoothing over a first-fit colouring */
+  MLMC_GAUGE2D = 4     /* gauge Laplacian (Example 4.2): (4 + m) I minus the
+                          U(1)-linked nearest neighbours, one unknown per site,
+                          N x N periodic; Hermitian; field = link phases
+                          theta[2][N][N] as for WILSON2D, mass = m; hierarchy by
+                          test-vector aggregation as for WILSON2D */
 };
 
 enum mlmc_precision {
@@ -85,9 +90,9 @@ typedef struct mlmc_operator {
   int kind;           /* enum mlmc_kind */
   int n_side;         /* grid / lattice side N (all directions) */
   double diag, off;   /* POISSON2D coefficients (Example 4.1: 4, 1) */
-  double mass;        /* WILSON2D: m0 */
+  double mass;        /* WILSON2D: m0; GAUGE2D: m */
   double shift;       /* VARCOEF3D: shift (>= 0) */
-  const double* field;/* WILSON2D: link phases theta[2][N][N] (mu, y, x);
+  const double* field;/* WILSON2D, GAUGE2D: link phases theta[2][N][N] (mu, y, x);
                          VARCOEF3D: face coefficients k[3][N][N][N+1]
                          (x-faces [z][y][f], y-faces [z][x][f], z-faces [y][x][f],
                           face f between cells f-1 and f); unused for POISSON2D */

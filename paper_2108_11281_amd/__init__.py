@@ -14,9 +14,10 @@ import numpy as np
 
 from . import _capi
 from ._capi import (ALLOC_EQUAL, ALLOC_GILES, ALLOC_WEIGHTS, CSR, FP32_IR64,  # noqa: F401
-                    FP64, POISSON2D, VARCOEF3D, WILSON2D)
+                    FP64, GAUGE2D, POISSON2D, VARCOEF3D, WILSON2D)
 
-KINDS = {"poisson2d": POISSON2D, "wilson2d": WILSON2D, "varcoef3d": VARCOEF3D, "csr": CSR}
+KINDS = {"poisson2d": POISSON2D, "wilson2d": WILSON2D, "varcoef3d": VARCOEF3D, "csr": CSR,
+         "gauge2d": GAUGE2D}
 PRECISIONS = {"fp64": FP64, "fp32_ir64": FP32_IR64}
 ALLOCS = {"equal": ALLOC_EQUAL, "weights": ALLOC_WEIGHTS, "giles": ALLOC_GILES}
 
@@ -107,8 +108,9 @@ def _close_live():
 class TraceEstimator:
     """One operator, its hierarchy and the solvers on the current torch device.
 
-    kind: "poisson2d" | "wilson2d" | "varcoef3d" | "csr"; field: numpy array of
-    link phases (wilson2d) or face coefficients (varcoef3d); matrix: the csr
+    kind: "poisson2d" | "wilson2d" | "gauge2d" | "varcoef3d" | "csr"; field:
+    numpy array of link phases (wilson2d, gauge2d) or face coefficients
+    (varcoef3d); matrix: the csr
     kind's matrix (anything with indptr, indices and data after .tocsr(), e.g.
     a scipy.sparse matrix; n_side is ignored); agg: optional aggregate maps of
     the csr kind, one integer array per level below the coarsest (None: greedy
@@ -136,7 +138,8 @@ class TraceEstimator:
         if field is not None:
             self._field = np.ascontiguousarray(field, dtype=np.float64)
             N = int(n_side)
-            want = {"wilson2d": 2 * N * N, "varcoef3d": 3 * N * N * (N + 1)}.get(kind)
+            want = {"wilson2d": 2 * N * N, "gauge2d": 2 * N * N,
+                    "varcoef3d": 3 * N * N * (N + 1)}.get(kind)
             if want is not None and self._field.size != want:
                 raise ValueError("%s field must hold %d values, got %d"
                                  % (kind, want, self._field.size))
@@ -210,7 +213,7 @@ class TraceEstimator:
         _live.add(self)
         self.kind = kind
         self.general = prolongations is not None  # general decomposition (given P)
-        self.is_complex = kind == "wilson2d"
+        self.is_complex = kind in ("wilson2d", "gauge2d")
         self.levels_solver = h.levels_solver
         self.levels_mlmc = h.levels_mlmc
         self.nb = o.nb

@@ -17,6 +17,7 @@ POISSON2D = 0
 WILSON2D = 1
 VARCOEF3D = 2
 CSR = 3
+GAUGE2D = 4
 
 FP64 = 0
 FP32_IR64 = 1

@@ -41,7 +41,8 @@ Context::Context(const mlmc_operator& A, const mlmc_hierarchy& h, const mlmc_opt
                "solve_tol must be > 0 and inner_tol >= 0");
   // inner_tol 0: the measured best per solver -- 1e-3 for the refined CG of the
   // real operators, 1e-2 for the complex FGMRES restart cycles
-  if (opt_.inner_tol == 0.0) opt_.inner_tol = A.kind == MLMC_WILSON2D ? 1e-2 : 1e-3;
+  if (opt_.inner_tol == 0.0)
+    opt_.inner_tol = (A.kind == MLMC_WILSON2D || A.kind == MLMC_GAUGE2D) ? 1e-2 : 1e-3;
   MLMC_REQUIRE(o.max_iter >= 1 && o.max_refine >= 1, MLMC_EINVAL, "iteration limits < 1");
   MLMC_REQUIRE(o.nu_pre >= 0 && o.nu_post >= 0, MLMC_EINVAL, "negative sweep count");
   MLMC_REQUIRE(o.min_samples >= 2, MLMC_EINVAL, "min_samples must be >= 2");
@@ -67,6 +68,7 @@ Context::Context(const mlmc_operator& A, const mlmc_hierarchy& h, const mlmc_opt
         build_csr(A, h.agg, h.P);
         break;
       case MLMC_WILSON2D:
+      case MLMC_GAUGE2D:
         complex_ = true;
         omega_ = opt_.omega > 0 ? opt_.omega : 1.0;
         build_wilson(A.field);

@@ -37,10 +37,12 @@ template <> Fgmres<c64>& Context::fg<c64>() {
 // ---------------------------------------------------------------------------
 void Context::build_wilson(const double* theta) {
   const int N = op_.n_side, blk = h_.block, nv = h_.n_vec;
+  // GAUGE2D: the finest level is a 1 x 1 block stencil of the gauge Laplacian
+  const bool gauge = kind_ == MLMC_GAUGE2D;
   // coarse unknowns per site: the test vectors, doubled by the spin split
   const bool split = h_.spin_split != 0;
   const int nc = split ? 2 * nv : nv;
-  MLMC_REQUIRE(theta != nullptr, MLMC_EINVAL, "WILSON2D needs the link phases (field)");
+  MLMC_REQUIRE(theta != nullptr, MLMC_EINVAL, "WILSON2D and GAUGE2D need the link phases (field)");
   MLMC_REQUIRE(N >= 2 && blk >= 2, MLMC_EINVAL, "bad lattice or aggregate size");
   MLMC_REQUIRE(nv >= 1 && (nc == 2 || nc == 4 || nc == 8 || nc == 12 || nc == 16),
                MLMC_EUNSUPPORTED,
@@ -63,9 +65,9 @@ void Context::build_wilson(const double* theta) {
     Level& L = lv_[l];
     L.index = l + 1;
     L.side = side;
-    L.dof = l == 0 ? 2 : nc;
+    L.dof = l == 0 ? (gauge ? 1 : 2) : nc;
     L.n = (int64_t)side * side * L.dof;
-    L.wilson = (l == 0);
+    L.wilson = (l == 0) && !gauge;
     L.blk = blk;
     if (l < Ls_ - 1)
       MLMC_REQUIRE(side % 2 == 0, MLMC_EINVAL,
@@ -82,6 +84,17 @@ void Context::build_wilson(const double* theta) {
   lv_[0].U64 = dalloc_n<c64>(2 * (int64_t)N * N);
   lv_[0].U32 = dalloc_n<c32>(2 * (int64_t)N * N);
   wilson_links(th, lv_[0].U64, lv_[0].U32, N, s_);
+  if (gauge) {
+    Level& F = lv_[0];
+    const int64_t ns = (int64_t)N * N;
+    F.B64 = dalloc_n<c64>(ns * 5);
+    F.B32 = dalloc_n<c32>(ns * 5);
+    F.Dinv64 = dalloc_n<c64>(ns);
+    F.Dinv32 = dalloc_n<c32>(ns);
+    gauge_blocks(F.U64, N, 4.0 + op_.mass, F.B64, s_);
+    vec_convert<c32, c64>(F.B64, F.B32, ns * 5, 1, nullptr, s_);
+    block_diag_inverse(F.B64, F.Dinv64, F.Dinv32, (int)ns, 1, s_);
+  }
 
   // hierarchy
   for (int l = 1; l < Ls_; ++l) {

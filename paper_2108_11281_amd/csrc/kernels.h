@@ -300,6 +300,8 @@ template <typename T>
 void agg_prolong(const T* xc, T* x, const T* q, int Nf, int dofF, int blk, int dofC,
                  double omega, double beta, int nb, const int* active, hipStream_t s);
 void wilson_links(const double* theta, c64* U64, c32* U32, int N, hipStream_t s);
+// gauge Laplacian (4 + m) I - linked neighbours as 1 x 1 blocks B[site][5]
+void gauge_blocks(const c64* U, int N, double diag, c64* B, hipStream_t s);
 void agg_orthonormalise(const c64* V, c64* q, int Nf, int dofF, int blk, int nv, bool split,
                         hipStream_t s);
 void galerkin_blocks(const c64* Bf, const c64* U, double wdiag, const c64* q, int Nf, int dofF,

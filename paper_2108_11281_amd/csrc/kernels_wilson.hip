@@ -501,6 +501,25 @@ __global__ __launch_bounds__(kThreads) void k_agg_orthonormalise(const c64* __re
   }
 }
 
+// gauge Laplacian (Example 4.2) as a 1 x 1 block stencil: B[s][0] = diag,
+// B[s][1] = -U_0(s) (+x), B[s][2] = -conj(U_0(s-x)), B[s][3] = -U_1(s) (+y),
+// B[s][4] = -conj(U_1(s-y)); U [2][N][N] (mu, y, x); a thread per site
+__global__ __launch_bounds__(kThreads) void k_gauge_blocks(const c64* __restrict__ U, int N,
+                                                           double diag, c64* __restrict__ B) {
+  const int s = blockIdx.x * kThreads + threadIdx.x;
+  if (s >= N * N) return;
+  const int n2 = N * N;
+  const int sy = s / N, sx = s - sy * N;
+  const int tx = sy * N + (sx == 0 ? N - 1 : sx - 1);
+  const int ty = (sy == 0 ? N - 1 : sy - 1) * N + sx;
+  c64* b = B + (int64_t)s * 5;
+  b[0] = {diag, 0.0};
+  b[1] = {-U[s].re, -U[s].im};
+  b[2] = {-U[tx].re, U[tx].im};
+  b[3] = {-U[n2 + s].re, -U[n2 + s].im};
+  b[4] = {-U[n2 + ty].re, U[n2 + ty].im};
+}
+
 // Galerkin blocks of the coarse operator, labelled by hop direction.
 // Fine operator given as a block stencil (blocks Bf [site][5][dofF][dofF]) or,
 // when Bf == nullptr, as the Wilson operator (links U, diagonal wdiag).
@@ -697,6 +716,7 @@ void wilson_rbgs(const T* b, T* x, const T* U, int N, double diag, int nb, const
 
 #define BSR_DISPATCH(DOFV, ...)                                                         \
   switch (DOFV) {                                                                     \
+    case 1: { constexpr int D = 1; __VA_ARGS__; break; }                              \
     case 2: { constexpr int D = 2; __VA_ARGS__; break; }                              \
     case 4: { constexpr int D = 4; __VA_ARGS__; break; }                              \
     case 8: { constexpr int D = 8; __VA_ARGS__; break; }                              \
@@ -755,6 +775,11 @@ void agg_prolong(const T* xc, T* x, const T* q, int Nf, int dofF, int blk, int d
   const dim3 g = grid_sites((int64_t)Nf * Nf * dofF, nb);
   BSR_DISPATCH(dofC, hipLaunchKernelGGL((k_agg_prolong<D, T>), g, dim3(kThreads), 0, s, xc, x, q,
                                          Nf, dofF, blk, (R_t<T>)omega, (R_t<T>)beta, active));
+}
+
+void gauge_blocks(const c64* U, int N, double diag, c64* B, hipStream_t s) {
+  hipLaunchKernelGGL(k_gauge_blocks, dim3((N * N + kThreads - 1) / kThreads), dim3(kThreads), 0,
+                     s, U, N, diag, B);
 }
 
 void wilson_links(const double* theta, c64* U64, c32* U32, int N, hipStream_t s) {
