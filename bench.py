@@ -29,6 +29,9 @@ Workloads (--workload):
     interpolation, R = P^T, Galerkin 9-point coarse operators) through the csr
     kind with the general decomposition (finest-level probes), 7 MLMC levels
     (coarsest 15^2) and 8 solver levels (coarsest 7^2).
+  gauge256: the gauge Laplacian of Example 4.2 on a 256^2 periodic lattice
+    (U(1) phases N(0, 0.3^2)), 4 levels of 4x4 test-vector aggregation, Z4
+    probes, complex64 FGMRES inside complex128 refinement, MLMC to 1e-3.
 
 Printed JSON line: the contract fields plus `roofline` (the dominant kernel,
 timed with HIP events carried in its own dispatches during the timed steps),
@@ -618,6 +621,71 @@ def run_laplace_bilinear(args, m, torch):
              compare=compare)
 
 
+def run_gauge(args, m, torch):
+    """Gauge Laplacian of Example 4.2 at 256^2 (U(1) phases N(0, 0.3^2), m = 0),
+    test-vector aggregation (4 x 4 aggregates, n_vec test vectors), 4 levels."""
+    from workloads import gauge_field, workload
+    w = workload("gauge256_c64ir")
+    N, Ls, L = w["N"], w["levels_solver"], w["levels_mlmc"]
+    nv = args.n_vec if args.n_vec > 0 else w["n_vec"]
+    th = gauge_field(N, sigma=w["theta_sigma"], seed=w["gauge_seed"])
+
+    def make(precision):
+        return m.TraceEstimator("gauge2d", N, Ls, L, mass=w["mass"], field=th, block=4,
+                                n_vec=nv, setup_sweeps=w["setup_sweeps"], setup_seed=1,
+                                precision=precision, nb=args.nb, nu_pre=args.nu,
+                                nu_post=args.nu, solve_tol=w["solve_tol"], alloc=args.alloc)
+    t0 = time.perf_counter()
+    est = make("fp32_ir64")
+    setup_s = time.perf_counter() - t0
+    sizes = [est.level_size(l) for l in range(1, Ls + 1)]
+    log("setup %.2fs, level sizes %s" % (setup_s, sizes))
+    for i in range(args.warmup):
+        r = est.trace(args.eps, 1000 + i)
+        log("warmup %d: %.3fs N_l=%s" % (i, r["seconds"], r["n_samples"]))
+    est.set_timing(["rbgs_sweep"], stride=args.timing_stride)
+    est.reset_kernel_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = []
+    for i in range(args.steps):
+        r = est.trace(args.eps, i + 1)
+        runs.append(r)
+        log("step %d: %.3fs N_l=%s trace=%s rmsd=%.4g iters=%d"
+            % (i, r["seconds"], r["n_samples"], r["trace"], r["rmsd"], r["iterations"]))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ks = est.kernel_stats("rbgs_sweep")
+    est.set_timing(False)
+    est.close()
+    ms_per_step = 1000.0 * elapsed / args.steps
+    compare = {}
+    if not args.no_compare:
+        log("plain FP64 MLMC, same workload")
+        e64 = make("fp64")
+        t64, n64 = timed_traces(e64, args, torch)
+        e64.close()
+        compare.update(fp64_mlmc_s=round(t64, 3), fp64_mlmc_n_samples=n64,
+                       speedup_vs_fp64_mlmc=round(t64 / (ms_per_step / 1000.0), 2))
+        log("plain FP64 MLMC %.3fs per trace, N_l=%s" % (t64, n64))
+    config = {"workload": "gauge_laplacian2d_%dx%d_Ls%d_L%d_agg4x4x%d_nb%d_c64ir128_eps%g"
+                          % (N, N, Ls, L, nv, args.nb, args.eps),
+              "variant": "complex64 FGMRES + block Gauss-Seidel V-cycle in complex128 "
+                         "refinement; test-vector aggregation",
+              "n": N * N, "level_sizes": sizes, "levels_solver": Ls, "levels_mlmc": L,
+              "n_vec": nv, "nb": args.nb, "eps": args.eps, "alloc": args.alloc,
+              "solve_tol": w["solve_tol"], "nu_pre": args.nu, "nu_post": args.nu}
+    contract(args, round(ms_per_step / 1000.0, 4), "s", False, ms_per_step, "c64+c128ir",
+             "synthetic (U(1) phases N(0,0.3^2), Z4 probes from Philox4x64-10)", config,
+             hbm_roofline("smoother sweeps: k_bsr_gs<1, c32> (finest, 1 x 1 blocks) and "
+                          "k_bsr_gs<n_vec, c32> (coarse block stencils)", ks, args.timing_stride),
+             None, accuracy={"n_samples": [r["n_samples"] for r in runs],
+                             "rmsd_rel": [round(r["rmsd"] / abs(r["trace"].real), 7)
+                                          for r in runs],
+                             "trace": [[r["trace"].real, r["trace"].imag] for r in runs]},
+             setup_s=round(setup_s, 3), compare=compare)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -625,7 +693,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="poisson1024",
                     choices=["poisson1024", "wilson256", "wilson512", "varcoef_batch",
-                             "graph1m", "laplace_bilinear"])
+                             "graph1m", "laplace_bilinear", "gauge256"])
     ap.add_argument("--eps", type=float, default=1e-3)
     ap.add_argument("--N", type=int, default=1024)
     ap.add_argument("--levels", type=int, default=6)
@@ -679,6 +747,8 @@ def main():
         run_graph(args, m, torch)
     elif args.workload == "laplace_bilinear":
         run_laplace_bilinear(args, m, torch)
+    elif args.workload == "gauge256":
+        run_gauge(args, m, torch)
     else:
         run_batch(args, m, torch)
 

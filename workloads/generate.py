@@ -151,6 +151,10 @@ WORKLOADS = {
     "laplace1023_bilinear_fp32ir": dict(
         kind="csr", N=1023, levels_mlmc=7, levels_solver=8, nb=128, precision="fp32_ir64",
         eps=1e-3, solve_tol=1e-10),
+    "gauge256_c64ir": dict(
+        kind="gauge2d", N=256, levels_mlmc=4, levels_solver=4, nb=128, precision="fp32_ir64",
+        eps=1e-3, solve_tol=1e-10, n_vec=4, setup_sweeps=20, theta_sigma=0.3, gauge_seed=1,
+        mass=0.0),
     "graph1m_fp32ir": dict(
         kind="csr", n=1 << 20, degree=8.0, shift=1e-2, graph_seed=1, levels_mlmc=4,
         levels_solver=4, nb=128, precision="fp32_ir64", eps=1e-3, solve_tol=1e-10),
