@@ -996,11 +996,9 @@ void Context::pcg_refined(int l, const double* b, double* y, int nb, double tol,
   auto refine = [&](bool force) {
     MLMC_HIP(hipStreamSynchronize(s_));
     if (count_host_[1] == 0 && !force) return false;
-    ir_accumulate<double, float>(y, x32, n, nb, act, s_);
-    vec_convert<double, float>(x32, r64_, n, nb, act, s_);
-    vec_dot_partials<double>(b, r64_, n, nb, act, partials_, s_);
+    // y += x32, bd = b^T x32, x32 = 0 in one pass
+    ir_fold(y, x32, b, n, nb, act, partials_, s_);
     finish_sums(partials_, nblk, nb, bd, s_);
-    vec_zero<float>(x32, n, nb, act, s_);
     timed<double>(kTimIrResidual, 20.0 * (double)n, act, nb, [&] {
       op_residual<double, double, float>(l, b, y, r, nb, act, partials_);
     });

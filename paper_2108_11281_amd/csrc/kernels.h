@@ -90,6 +90,10 @@ void cg_update_xr(T* x, T* r, const T* p, const T* q, const c64* alpha, int64_t 
 template <typename T>
 void cg_update_p(T* p, const T* z, const c64* beta, int64_t n, int nb,
                  const int* active, hipStream_t s);
+// refinement fold in one pass: y += d, partials of b^T d (reduce_blocks(n)
+// blocks per column, as vec_dot_partials(b, d)), d = 0
+void ir_fold(double* y, float* d, const double* b, int64_t n, int nb, const int* active,
+             c64* partials, hipStream_t s);
 // y64 += convert(d)
 template <typename T64, typename T32>
 void ir_accumulate(T64* y, const T32* d, int64_t n, int nb, const int* active,

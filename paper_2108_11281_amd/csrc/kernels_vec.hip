@@ -203,6 +203,30 @@ __global__ void k_ir_acc(T64* y, const T32* d, int64_t n, const int* active) {
   y[j] = y[j] + convert<T64, T32>(d[j]);
 }
 
+// The FP64 refinement's fold of the FP32 correction, one pass: y += d,
+// partials of b^T d (the stated-error share, same blocks and order as k_dot),
+// d = 0.  Per column k; blocks as in k_dot.
+__global__ __launch_bounds__(kThreads) void k_ir_fold(double* y, float* d, const double* b,
+                                                      int64_t n, const int* active,
+                                                      c64* partials) {
+  __shared__ double lds[16];
+  const int k = blockIdx.y, nblk = gridDim.x;
+  if (active && !active[k]) return;
+  const int64_t chunk = (n + nblk - 1) / nblk;
+  const int64_t lo = (int64_t)blockIdx.x * chunk;
+  const int64_t hi = lo + chunk < n ? lo + chunk : n;
+  const int64_t off = (int64_t)k * n;
+  double re = 0.0, im = 0.0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kThreads) {
+    const double di = (double)d[off + i];
+    y[off + i] = y[off + i] + di;
+    cdot_acc(re, im, b[off + i], di);
+    d[off + i] = 0.0f;
+  }
+  block_sum2<kThreads>(re, im, lds);
+  if (threadIdx.x == 0) partials[(int64_t)k * nblk + blockIdx.x] = {re, im};
+}
+
 template <typename T>
 __global__ void k_axpy_cols(T* y, const T* x, const c64* a, int64_t n, const int* active) {
   const int k = blockIdx.y;
@@ -649,6 +673,12 @@ void cg_update_p(T* p, const T* z, const c64* beta, int64_t n, int nb, const int
                  hipStream_t s) {
   hipLaunchKernelGGL(k_cg_p<T>, grid_cols(n, nb), dim3(kThreads), 0, s, p, z, beta, n,
                      active);
+}
+void ir_fold(double* y, float* d, const double* b, int64_t n, int nb, const int* active,
+             c64* partials, hipStream_t s) {
+  if (n <= 0 || nb <= 0) return;
+  hipLaunchKernelGGL(k_ir_fold, dim3(reduce_blocks(n), nb), dim3(kThreads), 0, s, y, d, b, n,
+                     active, partials);
 }
 template <typename T64, typename T32>
 void ir_accumulate(T64* y, const T32* d, int64_t n, int nb, const int* active,
