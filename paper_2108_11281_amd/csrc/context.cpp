@@ -1004,6 +1004,10 @@ void Context::pcg_refined(int l, const double* b, double* y, int nb, double tol,
     });
     finish_sums(partials_, ntiles, nb, rr_new, s_);
     ir_stated_error(bd, rr_upd, rr_new, act, err, nb, s_);
+    // the kept direction stays only while the recursion's residual (tmp, from
+    // the last x/r update) still describes the true one; when the recursion has
+    // run far below FP32 accuracy (a nearly exact preconditioner) restart it
+    cg_restart_on_drift(rr_new, tmp, rz, act, 100.0, nb, s_);
     select_active(rr_upd, rr_new, act, nb, s_);
     mark_converged(rr_new, bb, tol * tol, act, nb, count_dev_, s_);
     counters[1] += 1;

@@ -56,6 +56,10 @@ void vec_dot_partials(const T* x, const T* y, int64_t n, int nb, const int* acti
                       c64* partials, hipStream_t s);
 // out[k] = fixed-order sum of column k's nblk partials
 void finish_sums(const c64* partials, int nblk, int nb, c64* out, hipStream_t s);
+// refined CG: rz = 0 (so the next beta is 0) for active columns whose FP64
+// residual after a refinement exceeds factor x the recursion's own residual
+void cg_restart_on_drift(const c64* rr_new, const c64* rr_rec, c64* rz, const int* active,
+                         double factor, int nb, hipStream_t s);
 
 // ----- Krylov scalars (one thread per column) --------------------------------
 // alpha = active ? rz/pq : 0   (Hermitian CG, real rz and pq)

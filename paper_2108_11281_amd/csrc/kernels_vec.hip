@@ -124,6 +124,16 @@ __global__ void k_ir_err(const c64* bd, const c64* rr_old, const c64* rr_new,
   err[k] = {mag * ratio, 0.0};
 }
 
+// after a refinement: where the new FP64 residual exceeds the FP32 recursion's
+// own residual by more than `factor` (in squared norm), the kept direction no
+// longer fits the new residual; zeroing rz makes the next beta 0 (a restart)
+__global__ void k_cg_restart(const c64* rr_new, const c64* rr_rec, c64* rz, const int* active,
+                             double factor, int nb) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nb || !active[k]) return;
+  if (!(rr_new[k].re <= factor * rr_rec[k].re)) rz[k] = {0.0, 0.0};
+}
+
 __global__ void k_set_count(int* c, int v) { *c = v; }
 
 __global__ void k_refine_due(const c64* rr, const c64* rr_upd, const c64* bb, double delta2,
@@ -637,6 +647,11 @@ void count_active(const int* active, int nb, int* count, hipStream_t s) {
   hipLaunchKernelGGL(k_count, dim3(1), dim3(256), 0, s, active, nb, count);
 }
 
+void cg_restart_on_drift(const c64* rr_new, const c64* rr_rec, c64* rz, const int* active,
+                         double factor, int nb, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_restart, dim3((nb + 255) / 256), dim3(256), 0, s, rr_new, rr_rec, rz,
+                     active, factor, nb);
+}
 void ir_stated_error(const c64* bd, const c64* rr_old, const c64* rr_new, const int* active,
                      c64* err, int nb, hipStream_t s) {
   hipLaunchKernelGGL(k_ir_err, dim3((nb + 255) / 256), dim3(256), 0, s, bd, rr_old, rr_new,

@@ -282,3 +282,34 @@ def test_full_size_graph_workload():
     R = B - est.apply(1, Yd)
     rr = torch.linalg.vector_norm(R, dim=1) / torch.linalg.vector_norm(B, dim=1)
     assert float(rr.max()) <= 2e-10
+
+
+def test_degenerate_inputs():
+    """A diagonal matrix (no neighbours: every unknown its own aggregate, one
+    colour class, P = I, so every level difference is exactly zero and the
+    trace is the coarsest term), batches of a single column, and a two-level
+    hierarchy whose coarsest level is a single unknown."""
+    import paper_2108_11281_amd as m
+    d = np.linspace(1.0, 3.0, 50)
+    D = sp.diags(d).tocsr()
+    est = _est(D, 2, precision="fp32_ir64", nb=1)
+    _, agg, col = est.export_csr(1)
+    assert np.array_equal(agg, np.arange(50)) and not col.any()
+    Al, _, _ = est.export_csr(2)
+    assert Al.shape == (50, 50) and np.allclose(Al.toarray(), D.toarray())
+    s = est.sample_level(1, 3, 0, 4)
+    assert np.all(np.abs(s) <= 1e-9 * np.sum(1.0 / d))
+    r = est.trace(1e-3, 2)
+    assert r["n_samples"] == [5] and abs(r["trace"].real - np.sum(1.0 / d)) <= 1e-9
+    # a 1D chain of 3 unknowns coarsens to one aggregate: a 1 x 1 coarsest level
+    T = sp.diags([-1.0, 2.5, -1.0], [-1, 0, 1], shape=(3, 3)).tocsr()
+    est = _est(T, 2, precision="fp64", nb=2)
+    assert est.level_size(2) == 1
+    orc = _oracle("chain3", T, 2)
+    s = est.sample_level(1, 4, 0, 3)
+    ref = orc.sample(1, 4, 0, 3)
+    scale = quad_scale(orc.sample_parts(1, 4, 0, 3))
+    assert np.all(np.abs(s - ref) <= 1e-8 * scale)
+    assert abs(est.coarse_trace() - orc.coarse()) <= 1e-13 * abs(orc.coarse())
+    with pytest.raises(m.MLMCError):      # the coarsest level cannot be sampled
+        est.sample_level(2, 4, 0, 1)
