@@ -938,7 +938,10 @@ int Context::pcg(int l, const T* b, T* x, int nb, int* act, double tol, c64* las
 // refinement (or reaches solve_tol), every active column is refined in FP64:
 // y64 += x32, x32 = 0, r = b - A y64 recomputed in FP64 (and rounded to FP32).
 // The search direction is kept, so the Krylov space is not discarded as in a
-// restarted refinement.  Only the FP64 residual marks a column converged.
+// restarted refinement, unless the new FP64 residual exceeds the recursion's
+// own by more than 100x in squared norm (the recursion ran below FP32
+// accuracy); then the next direction restarts from z.  Only the FP64 residual
+// marks a column converged.
 // Stated error of a column (err): the last correction's share |b^H x32| of
 // b^H y scaled by the residual reduction it achieved -- the linear-convergence
 // estimate of what a further correction would add.  On return scal_[kRres]
