@@ -171,9 +171,7 @@ void Context::invert_coarse(int level, double** inv_out, c64* trace_out) {
   MLMC_REQUIRE(L.n <= 16384, MLMC_EINVAL,
                "coarsest level too large for a dense inverse (n > 16384)");
   const int n = (int)L.n;
-  double* aug = dalloc_n<double>(2 * (int64_t)n * n);
-  double* rowbuf = dalloc_n<double>(2 * (int64_t)n);
-  double* colbuf = dalloc_n<double>(n);
+  double* aug = dalloc_n<double>(2 * (int64_t)n * n);  // the builders' layout: n x 2n
   switch (kind_) {
     case MLMC_POISSON2D:
       poisson_dense_build<double>(aug, L.side, L.d, L.c, s_);
@@ -187,19 +185,37 @@ void Context::invert_coarse(int level, double** inv_out, c64* trace_out) {
     default:
       throw Error(MLMC_EUNSUPPORTED, "dense build");
   }
-  dense_set_identity_right<double>(aug, n, s_);
-  dense_invert<double>(aug, n, rowbuf, colbuf, piv_, s_);
   double* inv = dalloc_n<double>((int64_t)n * n);
-  dense_extract_right<double>(aug, n, inv, s_);
+  dense_invert_checked<double>(aug, n, inv);
   dense_trace<double>(inv, n, scal_[kTmp], s_);
   MLMC_HIP(hipMemcpyAsync(host_c64_, scal_[kTmp], sizeof(c64), hipMemcpyDeviceToHost, s_));
   MLMC_HIP(hipStreamSynchronize(s_));
   *trace_out = host_c64_[0];
   *inv_out = inv;
-  dfree(colbuf);
-  dfree(rowbuf);
   dfree(aug);
 }
+
+// out = A^{-1} for the n x n matrix in the left half of aug (n x 2n, row-major;
+// overwritten); a singular A is an error
+template <typename T>
+void Context::dense_invert_checked(T* aug, int n, T* out) {
+  T* rowbuf = dalloc_n<T>(kGjPanel + 1);
+  T* colbuf = dalloc_n<T>(n);
+  T* tbuf = dalloc_n<T>((int64_t)kGjPanel * n);
+  int* ipiv = dalloc_n<int>(2 * (int64_t)n + 1);
+  dense_inverse<T>(aug, n, 2 * (int64_t)n, out, rowbuf, colbuf, tbuf, ipiv, s_);
+  int singular = 0;
+  MLMC_HIP(hipMemcpyAsync(&singular, ipiv + 2 * (int64_t)n, sizeof(int), hipMemcpyDeviceToHost,
+                          s_));
+  MLMC_HIP(hipStreamSynchronize(s_));
+  dfree(ipiv);
+  dfree(tbuf);
+  dfree(colbuf);
+  dfree(rowbuf);
+  MLMC_REQUIRE(!singular, MLMC_EINVAL, "coarsest-level matrix is singular (zero pivot)");
+}
+template void Context::dense_invert_checked<double>(double*, int, double*);
+template void Context::dense_invert_checked<c64>(c64*, int, c64*);
 
 // device/pinned buffers shared by every operator kind: reduction partials,
 // per-column scalars, flags and the FP64 sample-batch vectors (complex: two
@@ -220,7 +236,6 @@ void Context::alloc_common() {
   act_outer_ = dalloc_n<int>(nb_);
   act_inner_ = dalloc_n<int>(nb_);
   count_dev_ = dalloc_n<int>(4);
-  piv_ = dalloc_n<int>(4);
   MLMC_HIP(hipHostMalloc((void**)&count_host_, 4 * sizeof(int)));
   MLMC_HIP(hipHostMalloc((void**)&host_c64_, 8 * (size_t)nb_ * sizeof(c64)));
   b1_ = dalloc_n<double>(n1 * nb_ * elem);

@@ -219,6 +219,7 @@ class Context {
   void solve_complex(int l, const c64* b, c64* y, int nb, c64* err);
   template <typename T> Fgmres<T>& fg();
   void invert_coarse(int level, double** inv_out, c64* trace_out);
+  template <typename T> void dense_invert_checked(T* aug, int n, T* out);
   template <typename T> void alloc_work(Work<T>& w, int width = 0);
   // batches solved in plain FP64 although the mode is MLMC_FP32_IR64
   bool fp64_batch(int nb) const {
@@ -346,7 +347,6 @@ class Context {
   int *act_outer_ = nullptr, *act_inner_ = nullptr, *count_dev_ = nullptr;  // count_dev_: 4 ints
   int* count_host_ = nullptr;
   c64* host_c64_ = nullptr;  // pinned, 8*nb
-  int* piv_ = nullptr;
 };
 
 // splitmix64 finaliser (sampling of timed launches)

@@ -165,21 +165,15 @@ void Context::build_wilson(const double* theta) {
   auto invert = [&](int level, c64** inv_out, c64* tr) {
     const Level& L = lv_[level - 1];
     const int n = (int)L.n;
-    c64* aug = dalloc_n<c64>(2 * (int64_t)n * n);
-    c64* rowbuf = dalloc_n<c64>(2 * (int64_t)n);
-    c64* colbuf = dalloc_n<c64>(n);
+    c64* aug = dalloc_n<c64>(2 * (int64_t)n * n);  // the builder's layout: n x 2n
     dense_from_stencil(L.wilson ? nullptr : L.B64, L.U64, diag, L.side, L.dof, aug, s_);
-    dense_set_identity_right<c64>(aug, n, s_);
-    dense_invert<c64>(aug, n, rowbuf, colbuf, piv_, s_);
     c64* inv = dalloc_n<c64>((int64_t)n * n);
-    dense_extract_right<c64>(aug, n, inv, s_);
+    dense_invert_checked<c64>(aug, n, inv);
     dense_trace<c64>(inv, n, scal_[kTmp], s_);
     MLMC_HIP(hipMemcpyAsync(host_c64_, scal_[kTmp], sizeof(c64), hipMemcpyDeviceToHost, s_));
     MLMC_HIP(hipStreamSynchronize(s_));
     *tr = host_c64_[0];
     *inv_out = inv;
-    dfree(colbuf);
-    dfree(rowbuf);
     dfree(aug);
   };
   c64* inv_s = nullptr;

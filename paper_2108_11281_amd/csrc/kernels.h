@@ -122,14 +122,15 @@ void probe_dot_partials(const T* y, int64_t n, int nb, uint64_t seed, uint64_t p
                         c64* partials, hipStream_t s);
 
 // ----- dense coarsest level -------------------------------------------------
-// in-place Gauss-Jordan inverse with partial pivoting of the n x n matrix held
-// in the left half of aug (n x 2n, row-major); right half receives A^{-1}
+// inverse of the n x n matrix A held row-major with leading dimension lda in M
+// (overwritten) by blocked Gauss-Jordan with partial pivoting; out receives
+// A^{-1} row-major with leading dimension n.  Work: rowbuf kGjPanel + 1
+// elements, colbuf n, tbuf kGjPanel * n, ipiv 2n + 1 ints; ipiv[2n] is set to
+// 1 when a pivot is zero or not a number (A singular)
+constexpr int kGjPanel = 64;
 template <typename T>
-void dense_invert(T* aug, int n, T* rowbuf, T* colbuf, int* piv, hipStream_t s);
-template <typename T>
-void dense_extract_right(const T* aug, int n, T* out, hipStream_t s);
-template <typename T>
-void dense_set_identity_right(T* aug, int n, hipStream_t s);
+void dense_inverse(T* M, int n, int64_t lda, T* out, T* rowbuf, T* colbuf, T* tbuf, int* ipiv,
+                   hipStream_t s);
 // trace partial: out = sum_i A[i][i] (single block)
 template <typename T>
 void dense_trace(const T* A, int n, c64* out, hipStream_t s);

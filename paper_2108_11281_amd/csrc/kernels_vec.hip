@@ -336,17 +336,53 @@ __global__ __launch_bounds__(kThreads) void k_probe_dot(const T* y, int64_t n, P
   if (threadIdx.x == 0) partials[(int64_t)k * gridDim.x + blockIdx.x] = {re, im};
 }
 
-// ---- dense Gauss-Jordan with partial pivoting on [A | I] (n x 2n) ----------
+// ---- dense inverse: blocked Gauss-Jordan with partial pivoting -------------
+// Sweep form of the elimination.  Pivoting on (row p, column c) with a = M[p][c]
+// sets M[p][c] = 1/a, scales the rest of row p by 1/a, scales the rest of
+// column c by -1/a and subtracts M[i][c] M[p][j] / a from every other entry.
+// Column c's pivot p is its largest-modulus entry among the free rows (a row is
+// free until it has been a pivot; rows are never moved).  With phys[c] the
+// pivot row of column c, sweeping every column once leaves
+//   M[phys[r]][j] = A^{-1}[r][phys[j]].
+// Columns are swept in panels K of kGjPanel: the panel's own columns are swept
+// one at a time, and the other columns J receive the whole panel's effect as
+// one rank-|K| product with the panel's pivot rows as they stood before it,
+//   M[i][J] <- [i not a pivot of K] M[i][J] + M[i][K] Mold[phys[K]][J].
+// ipiv holds phys[0..n), then used[0..n) (0 = free, else the column it
+// pivoted + 1), then a flag set when a pivot is zero or not a number (A
+// singular).
+
+__device__ __forceinline__ double recip(double a) { return 1.0 / a; }
+__device__ __forceinline__ c64 recip(c64 a) {
+  double d = a.re * a.re + a.im * a.im;
+  return {a.re / d, -a.im / d};
+}
+
+__device__ __forceinline__ void gj_fma(double& acc, double a, double b) { acc = fma(a, b, acc); }
+__device__ __forceinline__ void gj_fma(c64& acc, c64 a, c64 b) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(-a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(a.im, b.re, acc.im);
+}
+
+__global__ void k_gj_init(int* ipiv, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i <= 2 * n; i += gridDim.x * blockDim.x)
+    ipiv[i] = 0;
+}
+
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_gj_pivot(const T* M, int n, int kcol, int* piv) {
+__global__ __launch_bounds__(kThreads) void k_gj_pivot(const T* M, int n, int64_t lda, int c,
+                                                       int* ipiv) {
   __shared__ double bv[kThreads];
   __shared__ int bi[kThreads];
-  const int64_t ld = 2 * (int64_t)n;
+  const int* used = ipiv + n;
   double best = -1.0;
-  int besti = kcol;
-  for (int i = kcol + threadIdx.x; i < n; i += kThreads) {
-    double v = abs2_of(M[(int64_t)i * ld + kcol]);
-    if (v > best) {
+  int besti = n;
+  for (int i = threadIdx.x; i < n; i += kThreads) {
+    if (used[i]) continue;
+    double v = abs2_of(M[(int64_t)i * lda + c]);
+    if (v > best || besti == n) {  // a NaN entry is taken only when nothing else is
       best = v;
       besti = i;
     }
@@ -358,89 +394,132 @@ __global__ __launch_bounds__(kThreads) void k_gj_pivot(const T* M, int n, int kc
     if (threadIdx.x < s) {
       double o = bv[threadIdx.x + s];
       int oi = bi[threadIdx.x + s];
-      if (o > bv[threadIdx.x] || (o == bv[threadIdx.x] && oi < bi[threadIdx.x])) {
+      const int mi = bi[threadIdx.x];
+      if (oi != n && (mi == n || o > bv[threadIdx.x] || (o == bv[threadIdx.x] && oi < mi))) {
         bv[threadIdx.x] = o;
         bi[threadIdx.x] = oi;
       }
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) *piv = bi[0];
-}
-
-template <typename T>
-__global__ void k_gj_swap(T* M, int n, int kcol, const int* piv) {
-  const int p = *piv;
-  if (p == kcol) return;
-  const int64_t ld = 2 * (int64_t)n;
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < ld;
-       j += (int64_t)gridDim.x * blockDim.x) {
-    T a = M[(int64_t)kcol * ld + j];
-    M[(int64_t)kcol * ld + j] = M[(int64_t)p * ld + j];
-    M[(int64_t)p * ld + j] = a;
+  if (threadIdx.x == 0) {
+    // a free row always exists (c < n rows have been used), so bi[0] < n; ties
+    // go to the smallest row index
+    ipiv[c] = bi[0];
+    ipiv[n + bi[0]] = c + 1;
+    if (!(bv[0] > 0.0)) ipiv[2 * n] = 1;
   }
 }
 
-HD double inv_re(double a) { return 1.0 / a; }
-
-__device__ __forceinline__ double recip(double a) { return 1.0 / a; }
-__device__ __forceinline__ c64 recip(c64 a) {
-  double d = a.re * a.re + a.im * a.im;
-  return {a.re / d, -a.im / d};
-}
-__device__ __forceinline__ float recip(float a) { return 1.f / a; }
-__device__ __forceinline__ c32 recip(c32 a) {
-  float d = a.re * a.re + a.im * a.im;
-  return {a.re / d, -a.im / d};
-}
-
+// colbuf = column c, rowbuf[0..bw) = the pivot row's panel entries over a,
+// rowbuf[bw] = 1/a
 template <typename T>
-__global__ void k_gj_extract(const T* M, int n, int kcol, T* rowbuf, T* colbuf) {
-  const int64_t ld = 2 * (int64_t)n;
-  const T inv = recip(M[(int64_t)kcol * ld + kcol]);
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < ld;
-       j += (int64_t)gridDim.x * blockDim.x) {
-    rowbuf[j] = inv * M[(int64_t)kcol * ld + j];
-    if (j < n) colbuf[j] = M[j * ld + kcol];
+__global__ void k_gj_extract(const T* M, int n, int64_t lda, int c, int k0, int bw,
+                             const int* ipiv, T* rowbuf, T* colbuf) {
+  const int p = ipiv[c];
+  const T inv = recip(M[(int64_t)p * lda + c]);
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+    colbuf[t] = M[(int64_t)t * lda + c];
+    if (t < bw) rowbuf[t] = M[(int64_t)p * lda + k0 + t] * inv;
+    if (t == 0) rowbuf[bw] = inv;
   }
 }
 
+// sweep of column c restricted to the panel columns [k0, k0 + bw)
 template <typename T>
-__global__ void k_gj_eliminate(T* M, int n, int kcol, const T* rowbuf, const T* colbuf) {
-  const int64_t ld = 2 * (int64_t)n;
-  const int i = blockIdx.y;
-  const T f = colbuf[i];
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < ld;
-       j += (int64_t)gridDim.x * blockDim.x) {
-    if (i == kcol)
-      M[(int64_t)i * ld + j] = rowbuf[j];
-    else
-      M[(int64_t)i * ld + j] = M[(int64_t)i * ld + j] - f * rowbuf[j];
-  }
+__global__ void k_gj_panel(T* M, int n, int64_t lda, int c, int k0, int bw, const int* ipiv,
+                           const T* rowbuf, const T* colbuf) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * bw) return;
+  const int i = (int)(t / bw), j = (int)(t % bw), col = k0 + j;
+  const int p = ipiv[c];
+  const T inv = rowbuf[bw];
+  T& m = M[(int64_t)i * lda + col];
+  if (i == p)
+    m = (col == c) ? inv : rowbuf[j];
+  else if (col == c)
+    m = -(colbuf[i] * inv);
+  else
+    m = m - colbuf[i] * rowbuf[j];
 }
 
+// tbuf[r][j] = M[phys[k0 + r]][j]: the panel's pivot rows before their sweep
+// reaches the columns outside the panel
 template <typename T>
-__global__ void k_set_identity_right(T* M, int n) {
-  const int64_t ld = 2 * (int64_t)n;
-  const int i = blockIdx.y;
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
-       j += (int64_t)gridDim.x * blockDim.x) {
-    T v = zero_of(T());
-    if (j == i) {
-      c64 one = {1.0, 0.0};
-      v = convert<T, c64>(one);
+__global__ void k_gj_gather(const T* M, int n, int64_t lda, int k0, const int* ipiv, T* tbuf) {
+  const int r = blockIdx.y;
+  const int64_t src = (int64_t)ipiv[k0 + r] * lda;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x)
+    tbuf[(int64_t)r * n + j] = M[src + j];
+}
+
+// the panel's rank-bw update of every column outside it; 64 x 64 output tile
+// per block, 4 x 4 per thread, the panel dimension staged through LDS 16 at a time
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_gj_update(T* M, int n, int64_t lda, int k0,
+                                                        int bw, const int* ipiv,
+                                                        const T* tbuf) {
+  constexpr int TR = 16;
+  __shared__ T As[64][TR + 1];
+  __shared__ T Ts[TR][64 + 1];
+  const int row0 = blockIdx.y * 64, col0 = blockIdx.x * 64;
+  if (col0 >= k0 && col0 + 64 <= k0 + bw) return;  // a tile inside the panel
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const T z = zero_of(T());
+  T acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = z;
+  for (int rb = 0; rb < bw; rb += TR) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + kThreads * q;
+      const int ii = e >> 4, rr = e & 15;
+      const int gi = row0 + ii;
+      As[ii][rr] = (gi < n && rb + rr < bw) ? M[(int64_t)gi * lda + k0 + rb + rr] : z;
+      const int jj = e & 63, r2 = e >> 6;
+      const int gj = col0 + jj;
+      Ts[r2][jj] = (gj < n && rb + r2 < bw) ? tbuf[(int64_t)(rb + r2) * n + gj] : z;
     }
-    M[(int64_t)i * ld + n + j] = v;
+    __syncthreads();
+#pragma unroll 4
+    for (int rr = 0; rr < TR; ++rr) {
+      T av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = As[ty + 16 * a][rr];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = Ts[rr][tx + 16 * b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) gj_fma(acc[a][b], av[a], bv[b]);
+    }
+    __syncthreads();
+  }
+  const int* used = ipiv + n;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int i = row0 + ty + 16 * a;
+    if (i >= n) continue;
+    const bool pivot_row = used[i] > k0;  // pivoted one of the panel's columns
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int j = col0 + tx + 16 * b;
+      if (j >= n || (j >= k0 && j < k0 + bw)) continue;
+      T& m = M[(int64_t)i * lda + j];
+      m = (pivot_row ? z : m) + acc[a][b];
+    }
   }
 }
 
+// out[r][phys[j]] = M[phys[r]][j]
 template <typename T>
-__global__ void k_extract_right(const T* M, int n, T* out) {
-  const int64_t ld = 2 * (int64_t)n;
-  const int i = blockIdx.y;
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
-       j += (int64_t)gridDim.x * blockDim.x)
-    out[(int64_t)i * n + j] = M[(int64_t)i * ld + n + j];
+__global__ void k_gj_unpermute(const T* M, int n, int64_t lda, const int* ipiv, T* out) {
+  const int r = blockIdx.y;
+  const int64_t src = (int64_t)ipiv[r] * lda;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x)
+    out[(int64_t)r * n + ipiv[j]] = M[src + j];
 }
 
 template <typename T>
@@ -728,29 +807,28 @@ void probe_dot_partials(const T* y, int64_t n, int nb, uint64_t seed, uint64_t p
 }
 
 template <typename T>
-void dense_set_identity_right(T* aug, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_set_identity_right<T>, dim3((n + 255) / 256, n), dim3(256), 0, s, aug,
-                     n);
-}
-
-template <typename T>
-void dense_invert(T* aug, int n, T* rowbuf, T* colbuf, int* piv, hipStream_t s) {
-  const int64_t ld = 2 * (int64_t)n;
-  const unsigned gx = (unsigned)((ld + 255) / 256);
-  for (int kcol = 0; kcol < n; ++kcol) {
-    hipLaunchKernelGGL(k_gj_pivot<T>, dim3(1), dim3(kThreads), 0, s, aug, n, kcol, piv);
-    hipLaunchKernelGGL(k_gj_swap<T>, dim3(gx), dim3(256), 0, s, aug, n, kcol, piv);
-    hipLaunchKernelGGL(k_gj_extract<T>, dim3(gx), dim3(256), 0, s, aug, n, kcol, rowbuf,
-                       colbuf);
-    hipLaunchKernelGGL(k_gj_eliminate<T>, dim3(gx, n), dim3(256), 0, s, aug, n, kcol,
-                       rowbuf, colbuf);
+void dense_inverse(T* M, int n, int64_t lda, T* out, T* rowbuf, T* colbuf, T* tbuf,
+                   int* ipiv, hipStream_t s) {
+  const unsigned gn = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(k_gj_init, dim3((2 * n + 256) / 256), dim3(256), 0, s, ipiv, n);
+  for (int k0 = 0; k0 < n; k0 += kGjPanel) {
+    const int bw = std::min(kGjPanel, n - k0);
+    const unsigned gp = (unsigned)(((int64_t)n * bw + 255) / 256);
+    for (int c = k0; c < k0 + bw; ++c) {
+      hipLaunchKernelGGL(k_gj_pivot<T>, dim3(1), dim3(kThreads), 0, s, M, n, lda, c, ipiv);
+      hipLaunchKernelGGL(k_gj_extract<T>, dim3(gn), dim3(256), 0, s, M, n, lda, c, k0, bw,
+                         ipiv, rowbuf, colbuf);
+      hipLaunchKernelGGL(k_gj_panel<T>, dim3(gp), dim3(256), 0, s, M, n, lda, c, k0, bw, ipiv,
+                         rowbuf, colbuf);
+    }
+    if (bw == n) continue;
+    hipLaunchKernelGGL(k_gj_gather<T>, dim3(gn, bw), dim3(256), 0, s, M, n, lda, k0, ipiv,
+                       tbuf);
+    const unsigned gt = (unsigned)((n + 63) / 64);
+    hipLaunchKernelGGL(k_gj_update<T>, dim3(gt, gt), dim3(kThreads), 0, s, M, n, lda, k0, bw,
+                       ipiv, tbuf);
   }
-}
-
-template <typename T>
-void dense_extract_right(const T* aug, int n, T* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_extract_right<T>, dim3((n + 255) / 256, n), dim3(256), 0, s, aug, n,
-                     out);
+  hipLaunchKernelGGL(k_gj_unpermute<T>, dim3(gn, n), dim3(256), 0, s, M, n, lda, ipiv, out);
 }
 
 template <typename T>
@@ -792,9 +870,6 @@ void dense_apply(const T* At, const T* B, T* Z, int n, int nb, const int* active
                                 uint64_t, hipStream_t);                                  \
   template void probe_dot_partials<T>(const T*, int64_t, int, uint64_t, uint64_t,        \
                                       uint64_t, uint64_t, uint64_t, c64*, hipStream_t);  \
-  template void dense_invert<T>(T*, int, T*, T*, int*, hipStream_t);                     \
-  template void dense_extract_right<T>(const T*, int, T*, hipStream_t);                  \
-  template void dense_set_identity_right<T>(T*, int, hipStream_t);                       \
   template void dense_trace<T>(const T*, int, c64*, hipStream_t);                        \
   template void dense_apply<T>(const T*, const T*, T*, int, int, const int*, hipStream_t, int);
 
@@ -802,6 +877,11 @@ MLMC_INST_T(float)
 MLMC_INST_T(double)
 MLMC_INST_T(c32)
 MLMC_INST_T(c64)
+
+template void dense_inverse<double>(double*, int, int64_t, double*, double*, double*, double*,
+                                    int*, hipStream_t);
+template void dense_inverse<c64>(c64*, int, int64_t, c64*, c64*, c64*, c64*, int*,
+                                 hipStream_t);
 
 template void vec_convert<float, double>(const double*, float*, int64_t, int, const int*,
                                          hipStream_t);
