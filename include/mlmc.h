@@ -223,8 +223,9 @@ int mlmc_default_options(mlmc_options* opt);
  * Remark 4.2, the solver level L_s for the V-cycle).  hip_stream: a
  * hipStream_t or NULL.  On success *out owns device memory until
  * mlmc_destroy.  Errors: EINVAL for inconsistent sizes (a grid side that is not
- * divisible by the aggregate side at every level, L > L_s, nb out of range),
- * EDEVICE/ENOMEM from the runtime. */
+ * divisible by the aggregate side at every level, L > L_s, nb out of range, a
+ * coarsest operator with a zero pivot in its partially pivoted Gauss-Jordan
+ * inverse), EDEVICE/ENOMEM from the runtime. */
 int mlmc_setup(const mlmc_operator* A, const mlmc_hierarchy* h,
                const mlmc_options* opt, void* hip_stream, void** out_ctx);
 
