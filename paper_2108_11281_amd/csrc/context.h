@@ -209,6 +209,8 @@ class Context {
   void cop_residual(int l, const Tb* b, const T* x, Tr* r, int nb, const int* act, c64* partials);
   template <typename T> void cop_smooth(int l, const T* b, T* x, int nb, const int* act,
                                         bool zero_init, bool reverse);
+  template <typename T> void cop_smooth_n(int l, const T* b, T* x, int nb, const int* act,
+                                          int count, bool zero_init, bool reverse);
   template <typename T> void cop_restrict(int l, const T* x, T* xc, int nb, const int* act);
   template <typename T> void cop_prolong(int l, const T* ec, T* x, int nb, const int* act,
                                          double omega, double beta);

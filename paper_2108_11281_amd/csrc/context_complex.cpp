@@ -280,6 +280,39 @@ void Context::cop_smooth(int l, const T* b, T* x, int nb, const int* act, bool z
   }
 }
 
+// count sweeps at level l (from x = 0 when zero_init).  On the Wilson level
+// they run as fused two-colour passes, out of place, alternating between x and
+// the level's residual scratch (free while the level smooths) so that the last
+// pass lands in x; an odd count from a given x starts with one in-place sweep.
+template <typename T>
+void Context::cop_smooth_n(int l, const T* b, T* x, int nb, const int* act, int count,
+                           bool zero_init, bool reverse) {
+  const Level& L = lv_[l - 1];
+  if (!L.wilson || !wilson_rbgs_fused_ok(L.side)) {
+    for (int i = 0; i < count; ++i) cop_smooth<T>(l, b, x, nb, act, zero_init && i == 0, reverse);
+    return;
+  }
+  int i = 0;
+  if (!zero_init && count % 2 == 1) {
+    cop_smooth<T>(l, b, x, nb, act, false, reverse);
+    i = 1;
+  }
+  T* tmp = work<T>().vt[l - 1];
+  // algorithmic bytes per column: b read and x written (x read unless from
+  // zero), links once per launch
+  const double es = 2.0 * sizeof(T) * (double)L.side * L.side;
+  for (; i < count; ++i) {
+    const bool z = zero_init && i == 0;
+    T* dst = ((count - 1 - i) % 2 == 0) ? x : tmp;
+    const T* src = z ? dst : (dst == x ? tmp : x);
+    const double bytes = es * (z ? 2.0 : 3.0) + es / (double)nb;
+    timed<T>(kTimGs, bytes, act, nb, [&] {
+      wilson_rbgs_fused<T>(b, src, dst, links<T>(l), L.side, op_.mass + 2.0, nb, act, z, reverse,
+                           s_);
+    });
+  }
+}
+
 template <typename T>
 void Context::cop_restrict(int l, const T* x, T* xc, int nb, const int* act) {
   const Level& L = lv_[l - 1];
@@ -335,13 +368,13 @@ void Context::cvcycle(int l, const T* b, T* x, int nb, const int* act) {
   }
   const int pre = opt_.nu_pre, post = opt_.nu_post;
   if (pre == 0) vec_zero<T>(x, n, nb, act, s_);
-  for (int i = 0; i < pre; ++i) cop_smooth<T>(l, b, x, nb, act, i == 0, false);
+  cop_smooth_n<T>(l, b, x, nb, act, pre, true, false);
   T* res = w.vt[l - 1];
   cop_residual<T, T, T>(l, b, x, res, nb, act, nullptr);
   cop_restrict<T>(l, res, w.vb[l], nb, act);
   cvcycle<T>(l + 1, w.vb[l], w.vx[l], nb, act);
   cop_prolong<T>(l, w.vx[l], x, nb, act, omega_, 1.0);
-  for (int i = 0; i < post; ++i) cop_smooth<T>(l, b, x, nb, act, false, true);
+  cop_smooth_n<T>(l, b, x, nb, act, post, false, true);
 }
 
 // ---------------------------------------------------------------------------

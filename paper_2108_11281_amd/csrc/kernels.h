@@ -293,6 +293,13 @@ void wilson_residual(const Tb* b, const T* x, Tr* r, const T* U, int N, double d
 template <typename T>
 void wilson_rbgs(const T* b, T* x, const T* U, int N, double diag, int nb, const int* active,
                  bool zero_init, bool reverse, hipStream_t s);
+// one red-black sweep with both colours in one launch, out of place: xout =
+// S(xin) (xin unread when zero_init, else it must differ from xout); needs
+// wilson_rbgs_fused_ok(N) (side divisible by 16)
+bool wilson_rbgs_fused_ok(int N);
+template <typename T>
+void wilson_rbgs_fused(const T* b, const T* xin, T* xout, const T* U, int N, double diag, int nb,
+                       const int* active, bool zero_init, bool reverse, hipStream_t s);
 // block stencils: form 0 = a thread per (site, column), 1 = a wave per site
 // and 64 columns with the site's blocks read wave-uniformly (a tuning choice;
 // results agree up to rounding); partial sums always come from form 0

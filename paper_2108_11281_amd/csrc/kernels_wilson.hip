@@ -23,7 +23,40 @@ template <typename T> __device__ __forceinline__ T cmul_conj(T u, T a) {  // con
   return mk(u.re * a.re + u.im * a.im, u.re * a.im - u.im * a.re);
 }
 
-// hop term H x at site s (the sum in D = (m0+2) I - H/2), 2 spins
+// hop term H x at a site (the sum in D = (m0+2) I - H/2), 2 spins, from the
+// links u (+x: U_0(s), -x: U_0(s-x), +y: U_1(s), -y: U_1(s-y)) and the
+// neighbours' spin pairs xp (s+x), xm (s-x), yp (s+y), ym (s-y)
+template <typename T>
+__device__ __forceinline__ void wilson_hop_sum(T upx, T xp0, T xp1, T umx, T xm0, T xm1, T upy,
+                                               T yp0, T yp1, T umy, T ym0, T ym1, T& h0,
+                                               T& h1) {
+  // +x: (I - s1) U_0(s) x_{s+x}
+  {
+    const T a0 = upx * xp0, a1 = upx * xp1;
+    h0 = a0 - a1;
+    h1 = a1 - a0;
+  }
+  // -x: (I + s1) conj(U_0(s-x)) x_{s-x}
+  {
+    const T a0 = cmul_conj(umx, xm0), a1 = cmul_conj(umx, xm1);
+    h0 += a0 + a1;
+    h1 += a1 + a0;
+  }
+  // +y: (I - s2) U_1(s) x_{s+y};  (I - s2) v = (v0 - i v1, v1 + i v0)
+  {
+    const T a0 = upy * yp0, a1 = upy * yp1;
+    h0 += a0 - times_i(a1);
+    h1 += a1 + times_i(a0);
+  }
+  // -y: (I + s2) conj(U_1(s-y)) x_{s-y};  (I + s2) v = (v0 + i v1, v1 - i v0)
+  {
+    const T a0 = cmul_conj(umy, ym0), a1 = cmul_conj(umy, ym1);
+    h0 += a0 + times_i(a1);
+    h1 += a1 - times_i(a0);
+  }
+}
+
+// hop term at site (sx, sy) with x read from the column's global vector
 template <typename T>
 __device__ __forceinline__ void wilson_hop(const T* __restrict__ x, const T* __restrict__ U, int N,
                                            int sx, int sy, T& h0, T& h1) {
@@ -31,38 +64,10 @@ __device__ __forceinline__ void wilson_hop(const T* __restrict__ x, const T* __r
   const int xp = sx + 1 == N ? 0 : sx + 1, xm = sx == 0 ? N - 1 : sx - 1;
   const int yp = sy + 1 == N ? 0 : sy + 1, ym = sy == 0 ? N - 1 : sy - 1;
   const int s = sy * N + sx;
-  // +x: (I - s1) U_0(s) x_{s+x}
-  {
-    const int t = sy * N + xp;
-    const T u = U[s];
-    const T a0 = u * x[2 * t], a1 = u * x[2 * t + 1];
-    h0 = a0 - a1;
-    h1 = a1 - a0;
-  }
-  // -x: (I + s1) conj(U_0(s-x)) x_{s-x}
-  {
-    const int t = sy * N + xm;
-    const T u = U[t];
-    const T a0 = cmul_conj(u, x[2 * t]), a1 = cmul_conj(u, x[2 * t + 1]);
-    h0 += a0 + a1;
-    h1 += a1 + a0;
-  }
-  // +y: (I - s2) U_1(s) x_{s+y};  (I - s2) v = (v0 - i v1, v1 + i v0)
-  {
-    const int t = yp * N + sx;
-    const T u = U[n2 + s];
-    const T a0 = u * x[2 * t], a1 = u * x[2 * t + 1];
-    h0 += a0 - times_i(a1);
-    h1 += a1 + times_i(a0);
-  }
-  // -y: (I + s2) conj(U_1(s-y)) x_{s-y};  (I + s2) v = (v0 + i v1, v1 - i v0)
-  {
-    const int t = ym * N + sx;
-    const T u = U[n2 + t];
-    const T a0 = cmul_conj(u, x[2 * t]), a1 = cmul_conj(u, x[2 * t + 1]);
-    h0 += a0 + times_i(a1);
-    h1 += a1 - times_i(a0);
-  }
+  const int tpx = sy * N + xp, tmx = sy * N + xm, tpy = yp * N + sx, tmy = ym * N + sx;
+  wilson_hop_sum(U[s], x[2 * tpx], x[2 * tpx + 1], U[tmx], x[2 * tmx], x[2 * tmx + 1],
+                 U[n2 + s], x[2 * tpy], x[2 * tpy + 1], U[n2 + tmy], x[2 * tmy], x[2 * tmy + 1],
+                 h0, h1);
 }
 
 // r = b - D x (or y = D x when b == nullptr); one thread per (site, column);
@@ -115,11 +120,14 @@ __global__ __launch_bounds__(kThreads) void k_wilson_gs(const T* __restrict__ b,
   const int k = blockIdx.y;
   if (tlog && blockIdx.x == 0 && threadIdx.x == 0) tlog[k] = active ? active[k] : 1;
   if (active && !active[k]) return;
-  const int n2 = N * N;
-  const int s = blockIdx.x * kThreads + threadIdx.x;
-  if (s >= n2) return;
-  const int sy = s / N, sx = s - sy * N;
-  if (((sx + sy) & 1) != colour) return;
+  const int n2 = N * N, half = N >> 1;
+  // thread t takes the t-th site of the colour in row-major order (N even):
+  // row sy holds the colour at sx = 2j + ((colour + sy) & 1)
+  const int t = blockIdx.x * kThreads + threadIdx.x;
+  if (t >= (n2 >> 1)) return;
+  const int sy = t / half;
+  const int sx = 2 * (t - sy * half) + ((colour + sy) & 1);
+  const int s = sy * N + sx;
   const int64_t off = (int64_t)k * 2 * n2;
   T v0 = b[off + 2 * s], v1 = b[off + 2 * s + 1];
   if (!zero_nbrs) {
@@ -131,6 +139,91 @@ __global__ __launch_bounds__(kThreads) void k_wilson_gs(const T* __restrict__ b,
   }
   x[off + 2 * s] = dinv * v0;
   x[off + 2 * s + 1] = dinv * v1;
+}
+
+// both colours of one red-black site Gauss-Seidel sweep in a single pass, out
+// of place (xin is not read when zero_init; otherwise xout != xin).  A block
+// takes a TS x TS tile of one column: the second-colour values of the tile
+// and of a two-site periodic halo go to LDS, the first colour is updated on
+// the tile and on its one-site halo ring (a ring site gets the value its own
+// tile computes: same inputs, same arithmetic), then the second colour on the
+// tile.  x is read and written once per sweep instead of once per colour.
+template <typename T, int TS>
+__global__ __launch_bounds__(kThreads) void k_wilson_gs2(const T* __restrict__ b,
+                                                         const T* __restrict__ xin,
+                                                         T* __restrict__ xout,
+                                                         const T* __restrict__ U, int N,
+                                                         R_t<T> dinv, int first, int zero_init,
+                                                         const int* active, int* tlog) {
+  constexpr int W = TS + 4;  // tile + two halo sites each side
+  __shared__ T xs[W * W * 2];
+  const int k = blockIdx.y;
+  if (tlog && blockIdx.x == 0 && threadIdx.x == 0) tlog[k] = active ? active[k] : 1;
+  if (active && !active[k]) return;
+  const int tiles = N / TS;
+  const int ox = (int)(blockIdx.x % tiles) * TS - 2, oy = (int)(blockIdx.x / tiles) * TS - 2;
+  const int n2 = N * N;
+  const int64_t off = (int64_t)k * 2 * n2;
+  const int second = 1 - first;
+  const R_t<T> half = (R_t<T>)0.5;
+  // W-space (lx, ly) -> lattice site; ox, oy and N are even, so the colour
+  // (lx + ly) & 1 is the lattice colour
+  auto gx_of = [&](int lx) { int g = ox + lx; return g < 0 ? g + N : (g >= N ? g - N : g); };
+  auto gy_of = [&](int ly) { int g = oy + ly; return g < 0 ? g + N : (g >= N ? g - N : g); };
+  auto update = [&](int lx, int ly, bool nbrs, T& v0, T& v1) {
+    const int gx = gx_of(lx), gy = gy_of(ly);
+    const int sidx = gy * N + gx;
+    v0 = b[off + 2 * sidx];
+    v1 = b[off + 2 * sidx + 1];
+    if (nbrs) {
+      const int gxm = gx == 0 ? N - 1 : gx - 1, gym = gy == 0 ? N - 1 : gy - 1;
+      const T* c = xs + 2 * (ly * W + lx);
+      T h0, h1;
+      wilson_hop_sum(U[sidx], c[2], c[3], U[gy * N + gxm], c[-2], c[-1], U[n2 + sidx],
+                     c[2 * W], c[2 * W + 1], U[n2 + gym * N + gx], c[-2 * W], c[-2 * W + 1],
+                     h0, h1);
+      v0 += half * h0;
+      v1 += half * h1;
+    }
+    v0 = dinv * v0;
+    v1 = dinv * v1;
+    return sidx;
+  };
+  if (!zero_init) {
+    // second-colour sites of the whole W x W window
+    for (int q = threadIdx.x; q < W * W / 2; q += kThreads) {
+      const int ly = q / (W / 2);
+      const int lx = 2 * (q - ly * (W / 2)) + ((second + ly) & 1);
+      const int sidx = gy_of(ly) * N + gx_of(lx);
+      xs[2 * (ly * W + lx)] = xin[off + 2 * sidx];
+      xs[2 * (ly * W + lx) + 1] = xin[off + 2 * sidx + 1];
+    }
+    __syncthreads();
+  }
+  // first colour on the tile and its one-site ring: rows and columns 1 .. TS+2
+  constexpr int E = TS + 2;
+  for (int q = threadIdx.x; q < E * E / 2; q += kThreads) {
+    const int ly = 1 + q / (E / 2);
+    const int lx = 1 + 2 * (q - (ly - 1) * (E / 2)) + ((first + ly + 1) & 1);
+    T v0, v1;
+    const int sidx = update(lx, ly, !zero_init, v0, v1);
+    xs[2 * (ly * W + lx)] = v0;
+    xs[2 * (ly * W + lx) + 1] = v1;
+    if (lx >= 2 && lx < TS + 2 && ly >= 2 && ly < TS + 2) {
+      xout[off + 2 * sidx] = v0;
+      xout[off + 2 * sidx + 1] = v1;
+    }
+  }
+  __syncthreads();
+  // second colour on the tile: rows and columns 2 .. TS+1
+  for (int q = threadIdx.x; q < TS * TS / 2; q += kThreads) {
+    const int ly = 2 + q / (TS / 2);
+    const int lx = 2 + 2 * (q - (ly - 2) * (TS / 2)) + ((second + ly) & 1);
+    T v0, v1;
+    const int sidx = update(lx, ly, true, v0, v1);
+    xout[off + 2 * sidx] = v0;
+    xout[off + 2 * sidx + 1] = v1;
+  }
 }
 
 // ---- 5-point block stencils (coarse operators) ------------------------------
@@ -706,12 +799,33 @@ void wilson_residual(const Tb* b, const T* x, Tr* r, const T* U, int N, double d
 template <typename T>
 void wilson_rbgs(const T* b, T* x, const T* U, int N, double diag, int nb, const int* active,
                  bool zero_init, bool reverse, hipStream_t s) {
-  const dim3 g = grid_sites((int64_t)N * N, nb);
+  MLMC_REQUIRE(N % 2 == 0, MLMC_EINVAL, "red-black sweep needs an even lattice side");
+  const dim3 g = grid_sites((int64_t)N * N / 2, nb);
   const int first = reverse ? 1 : 0;
   MLMC_LAUNCH(k_wilson_gs<T>, g, dim3(kThreads), 0, s, b, x, U, N, (R_t<T>)(1.0 / diag), first,
               zero_init ? 1 : 0, active, timing_log());
   MLMC_LAUNCH(k_wilson_gs<T>, g, dim3(kThreads), 0, s, b, x, U, N, (R_t<T>)(1.0 / diag),
               1 - first, 0, active, (int*)nullptr);
+}
+
+bool wilson_rbgs_fused_ok(int N) { return N % 16 == 0; }
+
+template <typename T>
+void wilson_rbgs_fused(const T* b, const T* xin, T* xout, const T* U, int N, double diag, int nb,
+                       const int* active, bool zero_init, bool reverse, hipStream_t s) {
+  MLMC_REQUIRE(wilson_rbgs_fused_ok(N), MLMC_EINVAL, "fused sweep needs a side divisible by 16");
+  MLMC_REQUIRE(zero_init || xin != xout, MLMC_EINVAL, "fused sweep is out of place");
+  const int first = reverse ? 1 : 0;
+  const R_t<T> dinv = (R_t<T>)(1.0 / diag);
+  if (N % 32 == 0) {
+    const dim3 g((unsigned)((N / 32) * (N / 32)), (unsigned)nb);
+    MLMC_LAUNCH((k_wilson_gs2<T, 32>), g, dim3(kThreads), 0, s, b, xin, xout, U, N, dinv, first,
+                zero_init ? 1 : 0, active, timing_log());
+  } else {
+    const dim3 g((unsigned)((N / 16) * (N / 16)), (unsigned)nb);
+    MLMC_LAUNCH((k_wilson_gs2<T, 16>), g, dim3(kThreads), 0, s, b, xin, xout, U, N, dinv, first,
+                zero_init ? 1 : 0, active, timing_log());
+  }
 }
 
 #define BSR_DISPATCH(DOFV, ...)                                                         \
@@ -825,6 +939,10 @@ template void wilson_residual<c64, c64, c32>(const c64*, const c64*, c32*, const
                                              double, int, const int*, c64*, hipStream_t);
 template void wilson_residual<c32, c32, c32>(const c32*, const c32*, c32*, const c32*, int,
                                              double, int, const int*, c64*, hipStream_t);
+template void wilson_rbgs_fused<c32>(const c32*, const c32*, c32*, const c32*, int, double, int,
+                                     const int*, bool, bool, hipStream_t);
+template void wilson_rbgs_fused<c64>(const c64*, const c64*, c64*, const c64*, int, double, int,
+                                     const int*, bool, bool, hipStream_t);
 template void wilson_rbgs<c32>(const c32*, c32*, const c32*, int, double, int, const int*, bool,
                                bool, hipStream_t);
 template void wilson_rbgs<c64>(const c64*, c64*, const c64*, int, double, int, const int*, bool,
