@@ -390,46 +390,61 @@ __global__ __launch_bounds__(kThreads) void k_bsr_residual_sites(const Tb* __res
 }
 
 // one colour of a red-black block Gauss-Seidel sweep:
-// x_S = Dinv_S (b_S - sum_{d != self} B[S][d] x_nbr)
+// x_S = Dinv_S (b_S - sum_{d != self} B[S][d] x_nbr).  A group of G lanes
+// (DOF rounded up to a power of two, so groups never straddle a wave) per
+// site of the colour, lane i < DOF takes row i: its rows of the four
+// neighbour blocks (contiguous across the group), then Dinv's row i against
+// the group's right-hand sides gathered by lane shuffles
+template <int DOF> constexpr int bsr_group() {
+  return DOF <= 1 ? 1 : DOF <= 2 ? 2 : DOF <= 4 ? 4 : DOF <= 8 ? 8 : DOF <= 16 ? 16 : 32;
+}
+__device__ __forceinline__ c32 shfl_c(c32 v, int src) {
+  return {__shfl(v.re, src, 64), __shfl(v.im, src, 64)};
+}
+__device__ __forceinline__ c64 shfl_c(c64 v, int src) {
+  return {__shfl(v.re, src, 64), __shfl(v.im, src, 64)};
+}
+
 template <int DOF, typename T>
-__global__ __launch_bounds__(kThreads) void k_bsr_gs_sites(const T* __restrict__ b, T* __restrict__ x,
-                                                     const T* __restrict__ B,
-                                                     const T* __restrict__ Dinv, int Nc,
-                                                     int colour, int zero_nbrs,
-                                                     const int* active, int* tlog) {
+__global__ __launch_bounds__(kThreads) void k_bsr_gs_rows(const T* __restrict__ b, T* __restrict__ x,
+                                                          const T* __restrict__ B,
+                                                          const T* __restrict__ Dinv, int Nc,
+                                                          int colour, int zero_nbrs,
+                                                          const int* active, int* tlog) {
+  constexpr int G = bsr_group<DOF>();
   const int k = blockIdx.y;
   if (tlog && blockIdx.x == 0 && threadIdx.x == 0) tlog[k] = active ? active[k] : 1;
   if (active && !active[k]) return;
-  const int ns = Nc * Nc;
-  const int S = blockIdx.x * kThreads + threadIdx.x;
-  if (S >= ns) return;
-  const int Y = S / Nc, X = S - Y * Nc;
-  if (((X + Y) & 1) != colour) return;
+  const int ns = Nc * Nc, half = Nc >> 1;
+  const int t = blockIdx.x * kThreads + threadIdx.x;
+  const int q = t / G, i = t % G;
+  if (q >= (ns >> 1)) return;  // whole groups: G divides kThreads
+  const int Y = q / half;
+  const int S = Y * Nc + 2 * (q - Y * half) + ((colour + Y) & 1);
   const int64_t off = (int64_t)k * DOF * ns;
-  T rhs[DOF];
+  const bool row = i < DOF;
+  T rhs = zero_of(T());
+  if (row) {
+    rhs = b[off + (int64_t)S * DOF + i];
+    if (!zero_nbrs) {
+      for (int d = 1; d < 5; ++d) {
+        const int tn = nbr_site(S, d, Nc);
+        const T* blk = B + (((int64_t)S * 5 + d) * DOF + i) * DOF;
+        const T* xv = x + off + (int64_t)tn * DOF;
 #pragma unroll
-  for (int i = 0; i < DOF; ++i) rhs[i] = b[off + (int64_t)S * DOF + i];
-  if (!zero_nbrs) {
-    for (int d = 1; d < 5; ++d) {
-      const int t = nbr_site(S, d, Nc);
-      const T* blk = B + ((int64_t)S * 5 + d) * DOF * DOF;
-      T xv[DOF];
-#pragma unroll
-      for (int j = 0; j < DOF; ++j) xv[j] = x[off + (int64_t)t * DOF + j];
-#pragma unroll
-      for (int i = 0; i < DOF; ++i)
-#pragma unroll
-        for (int j = 0; j < DOF; ++j) rhs[i] -= blk[i * DOF + j] * xv[j];
+        for (int j = 0; j < DOF; ++j) rhs -= blk[j] * xv[j];
+      }
     }
   }
-  const T* di = Dinv + (int64_t)S * DOF * DOF;
+  const int lane0 = (int)(threadIdx.x & 63) - i;
+  const T* di = Dinv + ((int64_t)S * DOF + (row ? i : 0)) * DOF;
+  T v = zero_of(T());
 #pragma unroll
-  for (int i = 0; i < DOF; ++i) {
-    T v = zero_of(T());
-#pragma unroll
-    for (int j = 0; j < DOF; ++j) v += di[i * DOF + j] * rhs[j];
-    x[off + (int64_t)S * DOF + i] = v;
+  for (int j = 0; j < DOF; ++j) {
+    const T rj = shfl_c(rhs, lane0 + j);
+    if (row) v += di[j] * rj;
   }
+  if (row) x[off + (int64_t)S * DOF + i] = v;
 }
 
 // ---- aggregation transfers --------------------------------------------------
@@ -866,11 +881,13 @@ void bsr_rbgs(const T* b, T* x, const T* B, const T* Dinv, int Nc, int dof, int 
     BSR_DISPATCH(dof, MLMC_LAUNCH((k_bsr_gs<D, T>), g, dim3(kThreads), 0, s, b, x, B, Dinv, Nc,
                                    1 - first, 0, nb, active, (int*)nullptr));
   } else {
-    const dim3 g = grid_sites((int64_t)Nc * Nc, nb);
-    BSR_DISPATCH(dof, MLMC_LAUNCH((k_bsr_gs_sites<D, T>), g, dim3(kThreads), 0, s, b, x, B, Dinv,
-                                   Nc, first, zero_init ? 1 : 0, active, timing_log()));
-    BSR_DISPATCH(dof, MLMC_LAUNCH((k_bsr_gs_sites<D, T>), g, dim3(kThreads), 0, s, b, x, B, Dinv,
-                                   Nc, 1 - first, 0, active, (int*)nullptr));
+    BSR_DISPATCH(dof, {
+      const dim3 g = grid_sites((int64_t)Nc * Nc / 2 * bsr_group<D>(), nb);
+      MLMC_LAUNCH((k_bsr_gs_rows<D, T>), g, dim3(kThreads), 0, s, b, x, B, Dinv, Nc, first,
+                  zero_init ? 1 : 0, active, timing_log());
+      MLMC_LAUNCH((k_bsr_gs_rows<D, T>), g, dim3(kThreads), 0, s, b, x, B, Dinv, Nc, 1 - first,
+                  0, active, (int*)nullptr);
+    });
   }
 }
 
