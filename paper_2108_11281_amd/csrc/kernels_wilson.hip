@@ -447,6 +447,35 @@ __global__ __launch_bounds__(kThreads) void k_bsr_gs_rows(const T* __restrict__ 
   if (row) x[off + (int64_t)S * DOF + i] = v;
 }
 
+// r = b - A x (b == nullptr: r = A x) without partial sums: a group of lanes
+// per site, one block row per lane, as in the sweep
+template <int DOF, typename Tb, typename T, typename Tr>
+__global__ __launch_bounds__(kThreads) void k_bsr_residual_rows(const Tb* __restrict__ b,
+                                                                const T* __restrict__ x,
+                                                                Tr* __restrict__ r,
+                                                                const T* __restrict__ B, int Nc,
+                                                                const int* active) {
+  constexpr int G = bsr_group<DOF>();
+  const int k = blockIdx.y;
+  if (active && !active[k]) return;
+  const int ns = Nc * Nc;
+  const int t = blockIdx.x * kThreads + threadIdx.x;
+  const int S = t / G, i = t % G;
+  if (S >= ns || i >= DOF) return;
+  const int64_t off = (int64_t)k * DOF * ns;
+  T acc = zero_of(T());
+  for (int d = 0; d < 5; ++d) {
+    const int tn = nbr_site(S, d, Nc);
+    const T* blk = B + (((int64_t)S * 5 + d) * DOF + i) * DOF;
+    const T* xv = x + off + (int64_t)tn * DOF;
+#pragma unroll
+    for (int j = 0; j < DOF; ++j) acc += blk[j] * xv[j];
+  }
+  T v = acc;
+  if (b) v = convert<T, Tb>(b[off + (int64_t)S * DOF + i]) - v;
+  r[off + (int64_t)S * DOF + i] = convert<Tr, T>(v);
+}
+
 // ---- aggregation transfers --------------------------------------------------
 // fine lattice Nf x Nf with dofF unknowns per site, aggregates of blk x blk
 // sites, DOFC coarse unknowns per coarse site; q[i][j] (i fine unknown).
@@ -862,6 +891,12 @@ void bsr_residual(const Tb* b, const T* x, Tr* r, const T* B, int Nc, int dof, i
     const dim3 g = grid_waves((int64_t)Nc * Nc, nb);
     BSR_DISPATCH(dof, hipLaunchKernelGGL((k_bsr_residual<D, Tb, T, Tr>), g, dim3(kThreads), 0, s,
                                           b, x, r, B, Nc, nb, active));
+  } else if (!partials) {
+    BSR_DISPATCH(dof, {
+      const dim3 g = grid_sites((int64_t)Nc * Nc * bsr_group<D>(), nb);
+      hipLaunchKernelGGL((k_bsr_residual_rows<D, Tb, T, Tr>), g, dim3(kThreads), 0, s, b, x, r,
+                         B, Nc, active);
+    });
   } else {
     const dim3 g = grid_sites((int64_t)Nc * Nc, nb);
     BSR_DISPATCH(dof, hipLaunchKernelGGL((k_bsr_residual_sites<D, Tb, T, Tr>), g, dim3(kThreads),
