@@ -352,8 +352,9 @@ def run_wilson(args, m, torch, N, learned):
                         avg_launch_us=round(1000.0 * ms / max(launches, 1), 2),
                         algorithmic_flops_per_launch=round(flops / max(launches, 1)))
     else:
-        roofline = hbm_roofline("smoother sweeps: k_wilson_gs<c32> (finest) and "
-                                "k_bsr_gs<8, c32> (coarse block stencils)", ks,
+        roofline = hbm_roofline("smoother sweeps: k_wilson_gs2<c32> (finest, both colours "
+                                "per pass) and k_bsr_gs / k_bsr_gs_rows<8, c32> (coarse block "
+                                "stencils)", ks,
                                 args.timing_stride)
     compare = {"learned_stats": list(est.learned_stats())} if learned else {}
     est.close()
@@ -677,8 +678,9 @@ def run_gauge(args, m, torch):
               "solve_tol": w["solve_tol"], "nu_pre": args.nu, "nu_post": args.nu}
     contract(args, round(ms_per_step / 1000.0, 4), "s", False, ms_per_step, "c64+c128ir",
              "synthetic (U(1) phases N(0,0.3^2), Z4 probes from Philox4x64-10)", config,
-             hbm_roofline("smoother sweeps: k_bsr_gs<1, c32> (finest, 1 x 1 blocks) and "
-                          "k_bsr_gs<n_vec, c32> (coarse block stencils)", ks, args.timing_stride),
+             hbm_roofline("smoother sweeps: k_bsr_gs / k_bsr_gs_rows<1, c32> (finest, 1 x 1 "
+                          "blocks) and <n_vec, c32> (coarse block stencils)", ks,
+                          args.timing_stride),
              None, accuracy={"n_samples": [r["n_samples"] for r in runs],
                              "rmsd_rel": [round(r["rmsd"] / abs(r["trace"].real), 7)
                                           for r in runs],
