@@ -925,8 +925,7 @@ int Context::pcg(int l, const T* b, T* x, int nb, int* act, double tol, c64* las
   for (it = 1; it <= opt_.max_iter; ++it) {
     timed<T>(kTimApply, 4.0 * en, act, nb,
              [&] { op_update_apply<T>(l, p_old, w.z, beta, p_new, w.q, nb, act); });
-    finish_sums(partials_, ntiles, nb, tmp, s_);
-    cg_alpha(rz, tmp, act, alpha, nb, s_);
+    finish_alpha(partials_, ntiles, nb, tmp, rz, act, alpha, s_);
     if (lastcorr) cg_lastcorr(alpha, rz, act, lastcorr, nb, s_);
     timed<T>(kTimCgXr, 6.0 * en, act, nb,
              [&] { cg_update_xr<T>(x, w.r, p_new, w.q, alpha, n, nb, act, partials_, s_); });
@@ -937,8 +936,7 @@ int Context::pcg(int l, const T* b, T* x, int nb, int* act, double tol, c64* las
       if (read_count() == 0) break;
     }
     vcycle<T>(l, w.r, w.z, nb, act, partials_);
-    finish_sums(partials_, nvp, nb, tmp, s_);
-    cg_beta(tmp, rz, act, beta, nb, s_);
+    finish_beta(partials_, nvp, nb, tmp, rz, act, beta, s_);
     // the new direction of this iteration is the old one of the next
     p_old = p_new;
     p_new = (p_new == w.p) ? w.p2 : w.p;
@@ -991,8 +989,7 @@ void Context::pcg_refined(int l, const double* b, double* y, int nb, double tol,
   auto core = [&](float* p_old, float* p_new) {
     timed<float>(kTimApply, 4.0 * en, act, nb,
                  [&] { op_update_apply<float>(l, p_old, w.z, beta, p_new, w.q, nb, act); });
-    finish_sums(partials_, ntiles, nb, tmp, s_);
-    cg_alpha(rz, tmp, act, alpha, nb, s_);
+    finish_alpha(partials_, ntiles, nb, tmp, rz, act, alpha, s_);
     timed<float>(kTimCgXr, 6.0 * en, act, nb,
                  [&] { cg_update_xr<float>(x32, r, p_new, w.q, alpha, n, nb, act, partials_, s_); });
     finish_sums(partials_, nblk, nb, tmp, s_);
@@ -1000,8 +997,7 @@ void Context::pcg_refined(int l, const double* b, double* y, int nb, double tol,
   // preconditioner and the next direction's beta
   auto tail = [&] {
     vcycle<float>(l, r, w.z, nb, act, partials_);
-    finish_sums(partials_, nvp, nb, tmp, s_);
-    cg_beta(tmp, rz, act, beta, nb, s_);
+    finish_beta(partials_, nvp, nb, tmp, rz, act, beta, s_);
   };
   // a refinement is due when some column's recursive residual has dropped by
   // inner_tol since its last refinement, or reached the tolerance

@@ -62,6 +62,12 @@ void cg_restart_on_drift(const c64* rr_new, const c64* rr_rec, c64* rz, const in
                          double factor, int nb, hipStream_t s);
 
 // ----- Krylov scalars (one thread per column) --------------------------------
+// finish_sums into pq, then cg_alpha from it, in one launch (same values)
+void finish_alpha(const c64* partials, int nblk, int nb, c64* pq, const c64* rz,
+                  const int* active, c64* alpha, hipStream_t s);
+// finish_sums into rz_new, then cg_beta from it, in one launch (same values)
+void finish_beta(const c64* partials, int nblk, int nb, c64* rz_new, c64* rz, const int* active,
+                 c64* beta, hipStream_t s);
 // alpha = active ? rz/pq : 0   (Hermitian CG, real rz and pq)
 void cg_alpha(const c64* rz, const c64* pq, const int* active, c64* alpha, int nb,
               hipStream_t s);

@@ -69,6 +69,50 @@ __global__ __launch_bounds__(kThreads) void k_finish(const c64* partials, int nb
   if (threadIdx.x == 0) out[k] = {re, im};
 }
 
+// k_finish followed by the CG step length (k_finish_alpha) or direction
+// coefficient (k_finish_beta) of the same column in one launch: the same sum
+// in the same order, then the scalar rule of k_cg_alpha / k_cg_beta
+__global__ __launch_bounds__(kThreads) void k_finish_alpha(const c64* partials, int nblk,
+                                                           c64* pq, const c64* rz,
+                                                           const int* active, c64* alpha) {
+  __shared__ double lds[16];
+  const int k = blockIdx.x;
+  double re = 0.0, im = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += kThreads) {
+    c64 v = partials[(int64_t)k * nblk + b];
+    re += v.re;
+    im += v.im;
+  }
+  block_sum2<kThreads>(re, im, lds);
+  if (threadIdx.x == 0) {
+    pq[k] = {re, im};
+    double a = 0.0;
+    if ((!active || active[k]) && re != 0.0 && isfinite(re)) a = rz[k].re / re;
+    alpha[k] = {a, 0.0};
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_finish_beta(const c64* partials, int nblk,
+                                                          c64* rz_new, c64* rz,
+                                                          const int* active, c64* beta) {
+  __shared__ double lds[16];
+  const int k = blockIdx.x;
+  double re = 0.0, im = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += kThreads) {
+    c64 v = partials[(int64_t)k * nblk + b];
+    re += v.re;
+    im += v.im;
+  }
+  block_sum2<kThreads>(re, im, lds);
+  if (threadIdx.x == 0) {
+    rz_new[k] = {re, im};
+    double b = 0.0;
+    if ((!active || active[k]) && rz[k].re != 0.0) b = re / rz[k].re;
+    beta[k] = {b, 0.0};
+    rz[k] = {re, im};
+  }
+}
+
 __global__ void k_cg_alpha(const c64* rz, const c64* pq, const int* active, c64* alpha,
                            int nb) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -708,6 +752,16 @@ void finish_sums(const c64* partials, int nblk, int nb, c64* out, hipStream_t s)
   hipLaunchKernelGGL(k_finish, dim3(nb), dim3(kThreads), 0, s, partials, nblk, out);
 }
 
+void finish_alpha(const c64* partials, int nblk, int nb, c64* pq, const c64* rz,
+                  const int* active, c64* alpha, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish_alpha, dim3(nb), dim3(kThreads), 0, s, partials, nblk, pq, rz,
+                     active, alpha);
+}
+void finish_beta(const c64* partials, int nblk, int nb, c64* rz_new, c64* rz, const int* active,
+                 c64* beta, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish_beta, dim3(nb), dim3(kThreads), 0, s, partials, nblk, rz_new, rz,
+                     active, beta);
+}
 void cg_alpha(const c64* rz, const c64* pq, const int* active, c64* alpha, int nb,
               hipStream_t s) {
   hipLaunchKernelGGL(k_cg_alpha, dim3((nb + 255) / 256), dim3(256), 0, s, rz, pq, active,
