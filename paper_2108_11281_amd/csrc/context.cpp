@@ -986,13 +986,15 @@ void Context::pcg_refined(int l, const double* b, double* y, int nb, double tol,
   float* P1 = w.p;
   float* P2 = w.p2;
   // one CG iteration: p_new = z + beta p_old, q = A p_new, alpha, x/r update
-  auto core = [&](float* p_old, float* p_new) {
+  // (|r|^2 lands in tmp only when a refinement check follows: otherwise the
+  // next tail overwrites tmp unread)
+  auto core = [&](float* p_old, float* p_new, bool checked) {
     timed<float>(kTimApply, 4.0 * en, act, nb,
                  [&] { op_update_apply<float>(l, p_old, w.z, beta, p_new, w.q, nb, act); });
     finish_alpha(partials_, ntiles, nb, tmp, rz, act, alpha, s_);
     timed<float>(kTimCgXr, 6.0 * en, act, nb,
                  [&] { cg_update_xr<float>(x32, r, p_new, w.q, alpha, n, nb, act, partials_, s_); });
-    finish_sums(partials_, nblk, nb, tmp, s_);
+    if (checked) finish_sums(partials_, nblk, nb, tmp, s_);
   };
   // preconditioner and the next direction's beta
   auto tail = [&] {
@@ -1031,7 +1033,7 @@ void Context::pcg_refined(int l, const double* b, double* y, int nb, double tol,
   // iterations between refinement checks: (p2 -> p), (p -> p2), which repeat
   // with fixed pointers and can be replayed from a graph
   int it = 1;
-  core(w.z, P1);
+  core(w.z, P1, it == max_it);
   counters[0] += 1;
   if (it == max_it) {
     due();
@@ -1039,7 +1041,7 @@ void Context::pcg_refined(int l, const double* b, double* y, int nb, double tol,
     return;
   }
   tail();
-  core(P1, P2);
+  core(P1, P2, true);
   counters[0] += 1;
   it = 2;
   due();
@@ -1049,9 +1051,9 @@ void Context::pcg_refined(int l, const double* b, double* y, int nb, double tol,
     if (it + 2 <= max_it) {
       auto pair = [&] {
         tail();
-        core(P2, P1);
+        core(P2, P1, false);
         tail();
-        core(P1, P2);
+        core(P1, P2, true);
         due();
       };
       if (use_graph) {
@@ -1066,7 +1068,7 @@ void Context::pcg_refined(int l, const double* b, double* y, int nb, double tol,
       if (refine(it == max_it)) return;
     } else {
       tail();
-      core(P2, P1);
+      core(P2, P1, true);
       counters[0] += 1;
       it += 1;
       due();
