@@ -1414,9 +1414,9 @@ void Context::smooth_fp64(int level, int nrhs, int sweeps, bool reverse, const d
     bool restricted = false;
     if (complex_) {
       using C = typename std::conditional<sizeof(T) == 4, c32, c64>::type;
-      for (int i = 0; i < sweeps; ++i)
-        cop_smooth<C>(level, reinterpret_cast<const C*>(bt), reinterpret_cast<C*>(xa), nrhs,
-                      nullptr, false, reverse);
+      // the V-cycle's sweep sequence (fused two-colour passes on the Wilson level)
+      cop_smooth_n<C>(level, reinterpret_cast<const C*>(bt), reinterpret_cast<C*>(xa), nrhs,
+                      nullptr, sweeps, false, reverse);
     } else if (csr_) {
       for (int i = 0; i < sweeps; ++i)
         csr_gs_sweep<T>(bt, xa, csr_sweep<T>(level), (int)n, nrhs, csr_cols(L, nrhs), nullptr,

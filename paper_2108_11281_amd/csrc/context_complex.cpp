@@ -510,6 +510,10 @@ template void Context::cop_residual<c32, c32, c32>(int, const c32*, const c32*, 
                                                    const int*, c64*);
 template void Context::cop_smooth<c64>(int, const c64*, c64*, int, const int*, bool, bool);
 template void Context::cop_smooth<c32>(int, const c32*, c32*, int, const int*, bool, bool);
+template void Context::cop_smooth_n<c64>(int, const c64*, c64*, int, const int*, int, bool,
+                                         bool);
+template void Context::cop_smooth_n<c32>(int, const c32*, c32*, int, const int*, int, bool,
+                                         bool);
 template void Context::cvcycle<c64>(int, const c64*, c64*, int, const int*);
 
 }  // namespace mlmc

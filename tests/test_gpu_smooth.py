@@ -108,12 +108,28 @@ def test_wilson_and_block_sweeps_match_oracle(precision):
     est = m.TraceEstimator("wilson2d", N, L, L, mass=m0, field=th, block=4, n_vec=8,
                            setup_sweeps=6, setup_seed=1, precision=precision, nb=8)
     A, _ = hierarchy.wilson_hierarchy(N, th, m0, L, block=4, n_vec=8, sweeps=6, seed=1)
-    # level 1: 2 spins per site; level 2: 8 coarse unknowns per 4 x 4 aggregate
-    _check(est, A[0], np.repeat(hierarchy.site_coloring(N), 2), 1, precision, True, (1, 2))
+    # level 1: 2 spins per site (1 sweep: the one-colour kernel pair; 2: two
+    # fused two-colour passes, x -> scratch -> x; 3: one in-place sweep, then
+    # two fused passes); level 2: 8 coarse unknowns per 4 x 4 aggregate
+    _check(est, A[0], np.repeat(hierarchy.site_coloring(N), 2), 1, precision, True, (1, 2, 3))
     # (the oracle's own test-vector basis agrees with the library's to ~1e-12,
     # so the coarse operator, and the sweep through it, to about 1e-9)
     _check(est, A[1], np.repeat(hierarchy.site_coloring(N // 4), 8), 2, precision, True, (1, 2),
            tol=1e-9)
+
+
+@pytest.mark.parametrize("precision", ["fp32_ir64", "fp64"])
+def test_wilson_sweeps_tile16_match_oracle(precision):
+    # side 16: the fused pass takes one 16 x 16 tile whose halo wraps onto the
+    # tile itself
+    require_gpu()
+    import paper_2108_11281_amd as m
+    N, L, m0 = 16, 2, 0.1
+    th = gauge_field(N, seed=3)
+    est = m.TraceEstimator("wilson2d", N, L, L, mass=m0, field=th, block=4, n_vec=4,
+                           setup_sweeps=4, setup_seed=1, precision=precision, nb=8)
+    A, _ = hierarchy.wilson_hierarchy(N, th, m0, L, block=4, n_vec=4, sweeps=4, seed=1)
+    _check(est, A[0], np.repeat(hierarchy.site_coloring(N), 2), 1, precision, True, (1, 2, 3, 4))
 
 
 # N = 20: the fused 3D sweep marches all planes (20, 10); N = 40: z segments of
