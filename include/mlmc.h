@@ -272,7 +272,8 @@ int mlmc_apply(void* ctx, int level, int nrhs, const double* x_dev, double* y_de
  * smoother, Section 4 multigrid setting; sites coloured by the parity of the sum
  * of their coordinates, first colour (even) first, reverse != 0: odd first, as
  * in post-smoothing), run in the working precision by the V-cycle's own kernels
- * (2D Poisson levels: passes of up to two fused sweeps).  With rc_dev non-NULL
+ * (2D Poisson levels: passes of up to two fused sweeps; the Wilson level: both
+ * colours of a sweep in one out-of-place pass).  With rc_dev non-NULL
  * (reverse == 0 only) also Rc = R_l (B - A_l X) of the final X, as the last
  * pre-smoothing pass of the V-cycle writes it (fused into that pass where the
  * V-cycle fuses it).  b_dev, x_dev: FP64 (complex: interleaved) RHS-major blocks
