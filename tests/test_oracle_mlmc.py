@@ -202,3 +202,57 @@ def test_dst_sampler_matches_sparse_sampler():
         assert np.allclose(dst.sample(l, 3, 5, 4), ref.sample(l, 3, 5, 4), rtol=1e-12, atol=1e-12)
     assert abs(dst.coarse() - ref.coarse()) < 1e-12 * abs(ref.coarse())
     assert np.allclose(dst.hutchinson(1, 0, 3), ref.hutchinson(1, 0, 3), rtol=1e-12)
+
+
+def _gaussian_regime_sampler(n=400, scale=0.2, seed=11):
+    """A = I + G with G a scaled symmetric Gaussian matrix (no dominant off-diagonal
+    direction), so x^T A^{-1} x for Rademacher x is close to normally distributed
+    (a second-order Rademacher chaos over a matrix with a spread-out spectrum)."""
+    rng = np.random.default_rng(seed)
+    G = rng.standard_normal((n, n))
+    G = (G + G.T) * (scale / math.sqrt(2 * n))
+    A = sp.csr_matrix(np.eye(n) + G)
+    smp = mlmc.LevelSampler([A, A], [sp.identity(n, format="csr")], complex_probe=False)
+    return smp, float(np.trace(np.linalg.inv(A.toarray())))
+
+
+def test_pilot_tau_is_a_one_sided_t4_bound():
+    # Sec. 5: tau = mean of five pilot estimates minus their RMSD (the standard error
+    # sqrt(s^2/5)).  For Gaussian estimates, (mean - T)/sqrt(s^2/5) follows Student's
+    # t with 4 degrees of freedom, so P(tau <= T) = F_t4(1) = 0.8130.  The standard
+    # deviation in place of the standard error gives F_t4(sqrt 5) = 0.96, no
+    # subtraction 0.5: both fall outside the window (800 seeds: binomial sd 0.014).
+    # (C0's Hutchinson samples are too skewed, skewness ~1.4, for the t4 level.)
+    import scipy.stats as st
+    smp, T = _gaussian_regime_sampler()
+    y = smp.hutchinson(1, 0, 2000, stream=philox.STREAM_PILOT).real
+    assert abs(st.skew(y)) < 0.3          # the Gaussian regime the t4 level needs
+    cover, stat = [], []
+    for seed in range(800):
+        tau, yp = mlmc.pilot_tau(smp, seed)
+        m = float(np.mean(yp.real))
+        cover.append(tau <= T)
+        stat.append((m - T) / (m - tau))  # (mean - T) / standard error
+    assert abs(st.t.cdf(1.0, 4) - 0.8130) < 1e-4
+    assert 0.77 <= np.mean(cover) <= 0.86
+    # the studentised mean is t4 distributed (a scaled statistic is rejected)
+    assert st.kstest(stat, st.t(4).cdf).pvalue > 1e-3
+    assert st.kstest(np.array(stat) * math.sqrt(5.0), st.t(4).cdf).pvalue < 1e-6
+
+
+def test_pilot_samples_independent_of_estimator_samples():
+    # Sec. 5 (reading): the five pilot estimates come from their own probe stream and
+    # are not reused by the estimator or by plain Hutchinson.  Over many seeds the pilot
+    # mean must be uncorrelated with the first five level-1 quadratic forms and with
+    # the first five plain-Hutchinson samples (a reused stream gives correlation 1).
+    smp, _ = _gaussian_regime_sampler()
+    pil, lev, hut = [], [], []
+    for seed in range(300):
+        _, yp = mlmc.pilot_tau(smp, seed)
+        pil.append(np.mean(yp.real))
+        a, _ = smp.sample_parts(1, seed, 0, 5)
+        lev.append(np.mean(a.real))
+        hut.append(np.mean(smp.hutchinson(seed, 0, 5).real))
+    for other in (lev, hut):
+        r = np.corrcoef(pil, other)[0, 1]
+        assert abs(r) < 4.0 / math.sqrt(300)
