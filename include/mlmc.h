@@ -268,19 +268,30 @@ int mlmc_solve(void* ctx, int level, int nrhs, const double* b_dev,
 /* Y = A_l X in FP64 (the FP64 operator of level l). */
 int mlmc_apply(void* ctx, int level, int nrhs, const double* x_dev, double* y_dev);
 
+/* Flags of mlmc_smooth. */
+enum mlmc_smooth_flags {
+  MLMC_SMOOTH_REVERSE = 1,    /* odd colour first, as in post-smoothing */
+  MLMC_SMOOTH_ZERO_START = 2  /* start from X = 0 (x_dev's input is not read) with
+                                 the zero-start kernel forms that the V-cycle's
+                                 pre-smoothing runs; forward sweeps only
+                                 (with MLMC_SMOOTH_REVERSE: MLMC_EINVAL) */
+};
+
 /* X <- `sweeps` red-black Gauss-Seidel sweeps of A_l X = B (the V-cycle's
  * smoother, Section 4 multigrid setting; sites coloured by the parity of the sum
- * of their coordinates, first colour (even) first, reverse != 0: odd first, as
- * in post-smoothing), run in the working precision by the V-cycle's own kernels
- * (2D Poisson levels: passes of up to two fused sweeps; the Wilson level: both
- * colours of a sweep in one out-of-place pass).  With rc_dev non-NULL
- * (reverse == 0 only) also Rc = R_l (B - A_l X) of the final X, as the last
- * pre-smoothing pass of the V-cycle writes it (fused into that pass where the
- * V-cycle fuses it).  b_dev, x_dev: FP64 (complex: interleaved) RHS-major blocks
- * of nrhs <= nb vectors of n_l, x_dev read and overwritten; rc_dev: nrhs
- * vectors of n_{l+1}.  1 <= l < L_s; sweeps >= 0.  The library allocates and
- * frees working-precision copies during the call.  For tests and inspection. */
-int mlmc_smooth(void* ctx, int level, int nrhs, int sweeps, int reverse, const double* b_dev,
+ * of their coordinates, first colour (even) first; flags: enum
+ * mlmc_smooth_flags), run in the working precision by the V-cycle's own kernels
+ * and sweep grouping (2D Poisson levels: passes of up to two fused sweeps, an
+ * odd remainder first for forward sweeps, last for reverse ones; the Wilson
+ * level: both colours of a sweep in one out-of-place pass).  With rc_dev
+ * non-NULL (forward sweeps only) also Rc = R_l (B - A_l X) of the final X, as
+ * the last pre-smoothing pass of the V-cycle writes it (fused into that pass
+ * where the V-cycle fuses it).  b_dev, x_dev: FP64 (complex: interleaved)
+ * RHS-major blocks of nrhs <= nb vectors of n_l; x_dev is read (unless
+ * MLMC_SMOOTH_ZERO_START) and overwritten; rc_dev: nrhs vectors of n_{l+1}.
+ * 1 <= l < L_s; sweeps >= 0.  The library allocates and frees
+ * working-precision copies during the call.  For tests and inspection. */
+int mlmc_smooth(void* ctx, int level, int nrhs, int sweeps, int flags, const double* b_dev,
                 double* x_dev, double* rc_dev);
 
 /* Xc = R_l X = P_l^H X (restriction to level l+1), FP64, 1 <= l < L_s. */
@@ -442,6 +453,22 @@ int mlmc_learned_stats(void* ctx, int64_t* out);
 int mlmc_nn_apply(void* ctx, int nrhs, const double* r, double* e);
 int mlmc_nn_loss_grad(void* ctx, int ncrops, const float* in, const float* target, double* loss,
                       float* grad);
+
+/* mlmc_nn_crops: the training-pair builder of mlmc_learned_train on given data.
+ * r, e: device, nrhs x n_1 complex as interleaved FP64 (residuals and errors,
+ * level 1, nrhs <= nb); origin: host int32 [ncrops][3] = (column, y0, x0) of
+ * each crop's input corner (0 <= y0, x0 < N; sites wrap periodically).  Writes
+ * in: host FP32 [ncrops][22][22][8], the BF16 network inputs (r / s for the
+ * column's RMS s = sqrt(|r|^2 / n_1), Re/Im of both spins, then cos/sin of the
+ * two link phases), and target: host FP32 [ncrops][16][16][4], e / s on the
+ * crop's interior (rows and columns 3..18).  1 <= ncrops <= 65536.
+ * mlmc_nn_adam_step: one Adam update (Kingma and Ba; betas 0.9, 0.999, eps
+ * 1e-8, bias-corrected with step count t >= 1) of the FP32 master weights with
+ * the given gradient (host FP32, MLMC_NN_WEIGHTS); t == 1 first zeroes the
+ * moments; the inference fragments are re-packed.  ESTATE without weights. */
+int mlmc_nn_crops(void* ctx, int nrhs, const double* r, const double* e, int ncrops,
+                  const int32_t* origin, float* in, float* target);
+int mlmc_nn_adam_step(void* ctx, const float* grad, double lr, int t);
 
 /* Description of the last error on ctx (or of the last failed mlmc_setup
  * when ctx is NULL).  Valid until the next call on ctx. */

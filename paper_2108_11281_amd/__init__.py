@@ -340,16 +340,20 @@ class TraceEstimator:
                                      self._ptr(y)))
         return y
 
-    def smooth(self, level, b, x, sweeps, reverse=False, restrict=False):
+    def smooth(self, level, b, x, sweeps, reverse=False, restrict=False, zero_start=False):
         """`sweeps` red-black Gauss-Seidel sweeps of A_level x = b, in the working
         precision with the V-cycle's own kernels; returns the new x (x is not
-        changed), and with restrict=True also R (b - A x) of it, as the V-cycle's
-        last pre-smoothing pass forms it.  reverse: second colour first, as in
-        post-smoothing."""
-        y = x.clone()
+        changed; with zero_start=True x may be None and the sweeps start from 0 with
+        the pre-smoothing's zero-start kernels), and with restrict=True also
+        R (b - A x) of it, as the V-cycle's last pre-smoothing pass forms it.
+        reverse: second colour first, as in post-smoothing."""
+        import torch
+        y = torch.empty_like(b) if x is None else x.clone()
         rc = self._vec(level + 1, b.shape[0], b.device) if restrict else None
-        self._c(self._lib.mlmc_smooth(self._ctx, int(level), int(b.shape[0]), int(sweeps),
-                                      1 if reverse else 0, self._ptr(b), self._ptr(y),
+        flags = (_capi.SMOOTH_REVERSE if reverse else 0) | \
+            (_capi.SMOOTH_ZERO_START if zero_start else 0)
+        self._c(self._lib.mlmc_smooth(self._ctx, int(level), int(b.shape[0]), int(sweeps), flags,
+                                      self._ptr(b), self._ptr(y),
                                       self._ptr(rc) if restrict else None))
         return (y, rc) if restrict else y
 
@@ -469,6 +473,30 @@ class TraceEstimator:
             ctypes.c_void_p(targets.data_ptr()),
             ctypes.byref(loss), grad.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
         return loss.value, grad
+
+    def nn_crops(self, r, e, origins):
+        """Training crops from residuals r and errors e (device FP64 complex-interleaved
+        [nrhs, 2 n_1]) at origins [ncrops, 3] = (column, y0, x0): (inputs
+        [ncrops, 22, 22, 8], targets [ncrops, 16, 16, 4]) as FP32 host arrays."""
+        assert tuple(r.shape) == tuple(e.shape) and r.shape[1] == 2 * self.level_size(1)
+        nrhs = int(r.shape[0])
+        org = np.ascontiguousarray(origins, dtype=np.int32)
+        nc = int(org.shape[0])
+        inp = np.zeros((nc, 22, 22, 8), dtype=np.float32)
+        tgt = np.zeros((nc, 16, 16, 4), dtype=np.float32)
+        self._c(self._lib.mlmc_nn_crops(
+            self._ctx, nrhs, self._ptr(r), self._ptr(e), nc,
+            org.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+            inp.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+            tgt.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return inp, tgt
+
+    def nn_adam_step(self, grad, lr, t):
+        """One Adam update of the network's master weights with gradient grad."""
+        g = np.ascontiguousarray(grad, dtype=np.float32)
+        assert g.size == _capi.NN_WEIGHTS
+        self._c(self._lib.mlmc_nn_adam_step(
+            self._ctx, g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), float(lr), int(t)))
 
 
 def batch_sample(estimators, level, seeds, first, nsamples, workers=4):

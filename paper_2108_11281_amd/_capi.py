@@ -28,6 +28,9 @@ ALLOC_GILES = 2
 
 MAX_LEVELS = 16
 
+SMOOTH_REVERSE = 1
+SMOOTH_ZERO_START = 2
+
 
 class Operator(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("n_side", ctypes.c_int),
@@ -152,6 +155,8 @@ SIGNATURES = {
     "mlmc_learned_stats": (ctypes.c_int, [_P, _I64]),
     "mlmc_nn_apply": (ctypes.c_int, [_P, ctypes.c_int, _P, _P]),
     "mlmc_nn_loss_grad": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _D, _F]),
+    "mlmc_nn_crops": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_int, _I32, _F, _F]),
+    "mlmc_nn_adam_step": (ctypes.c_int, [_P, _F, ctypes.c_double, ctypes.c_int]),
     "mlmc_last_error": (ctypes.c_char_p, [_P]),
     "mlmc_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "mlmc_destroy": (None, [_P]),

@@ -139,12 +139,15 @@ int mlmc_apply(void* c, int level, int nrhs, const double* x_dev, double* y_dev)
   return guarded(ctx, [&] { ctx->apply_fp64(level, nrhs, x_dev, y_dev); });
 }
 
-int mlmc_smooth(void* c, int level, int nrhs, int sweeps, int reverse, const double* b_dev,
+int mlmc_smooth(void* c, int level, int nrhs, int sweeps, int flags, const double* b_dev,
                 double* x_dev, double* rc_dev) {
   Context* ctx = as_ctx(c);
   if (!ctx || !b_dev || !x_dev) return MLMC_EINVAL;
   return guarded(ctx, [&] {
-    ctx->smooth_fp64(level, nrhs, sweeps, reverse != 0, b_dev, x_dev, rc_dev);
+    MLMC_REQUIRE((flags & ~(MLMC_SMOOTH_REVERSE | MLMC_SMOOTH_ZERO_START)) == 0, MLMC_EINVAL,
+                 "unknown smoother flags");
+    ctx->smooth_fp64(level, nrhs, sweeps, (flags & MLMC_SMOOTH_REVERSE) != 0,
+                     (flags & MLMC_SMOOTH_ZERO_START) != 0, b_dev, x_dev, rc_dev);
   });
 }
 
@@ -275,6 +278,23 @@ int mlmc_nn_loss_grad(void* c, int ncrops, const float* in, const float* target,
   Context* ctx = as_ctx(c);
   if (!ctx || !in || !target || !loss || !grad) return MLMC_EINVAL;
   return guarded(ctx, [&] { ctx->nn_loss_grad(ncrops, in, target, loss, grad); });
+}
+
+int mlmc_nn_crops(void* c, int nrhs, const double* r, const double* e, int ncrops,
+                  const int32_t* origin, float* in, float* target) {
+  Context* ctx = as_ctx(c);
+  if (!ctx || !r || !e || !origin || !in || !target) return MLMC_EINVAL;
+  return guarded(ctx, [&] { ctx->nn_crops_fp64(nrhs, r, e, ncrops, origin, in, target); });
+}
+
+int mlmc_nn_adam_step(void* c, const float* grad, double lr, int t) {
+  Context* ctx = as_ctx(c);
+  if (!ctx || !grad) return MLMC_EINVAL;
+  return guarded(ctx, [&] {
+    for (int i = 0; i < MLMC_NN_WEIGHTS; ++i)
+      MLMC_REQUIRE(std::isfinite(grad[i]), MLMC_EINVAL, "gradient must be finite");
+    ctx->nn_adam_step(grad, lr, t);
+  });
 }
 
 int mlmc_batch_sample(void* const* ctxs, int count, int level, const uint64_t* seeds,

@@ -1379,12 +1379,14 @@ void Context::apply_fp64(int level, int nrhs, const double* x, double* y) {
 // precision, with the V-cycle's own kernels (passes of fused sweeps on the 2D
 // Poisson levels); reverse: second colour first, as in post-smoothing.  rc
 // (nullable): R (b - A x) of the final x, as the V-cycle's last pre-pass forms it
-void Context::smooth_fp64(int level, int nrhs, int sweeps, bool reverse, const double* b,
-                          double* x, double* rc) {
+void Context::smooth_fp64(int level, int nrhs, int sweeps, bool reverse, bool zero_start,
+                          const double* b, double* x, double* rc, void* ws, size_t ws_bytes) {
   MLMC_REQUIRE(level >= 1 && level < Ls_, MLMC_EINVAL, "level out of range (no smoother on L_s)");
   MLMC_REQUIRE(nrhs >= 1 && nrhs <= nb_, MLMC_EINVAL, "nrhs must be in [1, nb]");
   MLMC_REQUIRE(sweeps >= 0, MLMC_EINVAL, "sweeps must be >= 0");
   MLMC_REQUIRE(!(rc && reverse), MLMC_EINVAL, "the restricted residual follows a forward pass");
+  MLMC_REQUIRE(!(zero_start && reverse), MLMC_EINVAL,
+               "a zero start is the forward pre-smoothing's (no reverse sweeps from zero)");
   const int64_t n = lv_[level - 1].n;
   const int64_t elem = complex_ ? 2 : 1;
   const int64_t m = n * nrhs * elem, mc = lv_[level].n * nrhs * elem;
@@ -1404,44 +1406,71 @@ void Context::smooth_fp64(int level, int nrhs, int sweeps, bool reverse, const d
   };
   auto run = [&](auto tag) {
     using T = decltype(tag);
-    T* bt = dalloc_n<T>(m);
-    T* xa = dalloc_n<T>(m);
-    T* xb = dalloc_n<T>(m);
-    T* rct = rc ? dalloc_n<T>(mc) : nullptr;
+    // working-precision copies: allocated here, or carved from the caller's
+    // workspace (256-byte aligned pieces)
+    T *bt, *xa, *xb, *rct = nullptr;
+    if (ws) {
+      auto piece = [](int64_t cnt) { return (((size_t)cnt * sizeof(T)) + 255) & ~(size_t)255; };
+      const size_t need = 3 * piece(m) + (rc ? piece(mc) : 0);
+      MLMC_REQUIRE(need <= ws_bytes, MLMC_EINVAL,
+                   "the smoother's working copies need " + std::to_string(need) +
+                       " bytes of workspace, more than the " + std::to_string(ws_bytes) +
+                       " available (fewer right-hand sides or a coarser level fit)");
+      char* p = static_cast<char*>(ws);
+      bt = reinterpret_cast<T*>(p);
+      xa = reinterpret_cast<T*>(p + piece(m));
+      xb = reinterpret_cast<T*>(p + 2 * piece(m));
+      if (rc) rct = reinterpret_cast<T*>(p + 3 * piece(m));
+    } else {
+      bt = dalloc_n<T>(m);
+      xa = dalloc_n<T>(m);
+      xb = dalloc_n<T>(m);
+      if (rc) rct = dalloc_n<T>(mc);
+    }
     to_t(bt, b, m);
-    to_t(xa, x, m);
+    if (!zero_start) to_t(xa, x, m);
+    else if (sweeps == 0) vec_zero<T>(xa, m, 1, nullptr, s_);
     const Level& L = lv_[level - 1];
     bool restricted = false;
     if (complex_) {
       using C = typename std::conditional<sizeof(T) == 4, c32, c64>::type;
-      // the V-cycle's sweep sequence (fused two-colour passes on the Wilson level)
+      // the V-cycle's sweep sequence (fused two-colour passes on the Wilson level;
+      // from zero: the zero-start form of the first pass)
       cop_smooth_n<C>(level, reinterpret_cast<const C*>(bt), reinterpret_cast<C*>(xa), nrhs,
-                      nullptr, sweeps, false, reverse);
+                      nullptr, sweeps, zero_start, reverse);
     } else if (csr_) {
+      if (zero_start) vec_zero<T>(xa, n, nrhs, nullptr, s_);  // as the V-cycle starts
       for (int i = 0; i < sweeps; ++i)
         csr_gs_sweep<T>(bt, xa, csr_sweep<T>(level), (int)n, nrhs, csr_cols(L, nrhs), nullptr,
                         reverse, s_);
     } else if (varcoef_) {
       for (int i = 0; i < sweeps; ++i) {
+        const bool z = zero_start && i == 0;
         if (L.mcols > 0) {
-          varcoef_rbgs_march<T>(xa, bt, xb, nullptr, 0.0, vc_faces<T>(level), vc_diag<T>(level),
-                                L.side, nrhs, L.mcols, nullptr, reverse, s_);
+          varcoef_rbgs_march<T>(z ? nullptr : xa, bt, xb, nullptr, 0.0, vc_faces<T>(level),
+                                vc_diag<T>(level), L.side, nrhs, L.mcols, nullptr, reverse, s_);
           std::swap(xa, xb);
         } else {
           varcoef_rbgs<T>(bt, xa, vc_faces<T>(level), vc_diag<T>(level), L.side, nrhs, L.cols,
-                          nullptr, false, reverse, nullptr, 0.0, s_);
+                          nullptr, z, reverse, nullptr, 0.0, s_);
         }
       }
     } else {
+      // passes of up to `per` fused sweeps in the V-cycle's grouping: forward
+      // (pre-smoothing) takes an odd remainder first so that the last pass is a
+      // full one that can write the restricted residual; reverse (post-smoothing)
+      // takes full passes first
       const int per = sweeps_per_pass(level);
       for (int i = 0; i < sweeps;) {
-        const int sw = std::min(per, sweeps - i);
+        const int sw = reverse ? std::min(per, sweeps - i)
+                               : ((sweeps - i) % per ? (sweeps - i) % per : per);
+        const T* in = (zero_start && i == 0) ? nullptr : xa;
         if (rct && sw == 2 && i + sw == sweeps) {
-          poisson_rbgs_restrict<T>(xa, bt, xb, rct, L.side, L.d, L.c, nrhs, nullptr,
+          poisson_rbgs_restrict<T>(in, bt, xb, rct, L.side, L.d, L.c, nrhs, nullptr,
                                    gs_rows<T>(level), s_);
           restricted = true;
         } else {
-          poisson_rbgs_fused<T>(xa, bt, xb, nullptr, 0.0, L.side, L.d, L.c, nrhs, nullptr,
+          poisson_rbgs_fused<T>(in, bt, xb, nullptr, 0.0, L.side, L.d, L.c, nrhs, nullptr,
                                 reverse, nullptr, gs_rows<T>(level), sw, s_);
         }
         std::swap(xa, xb);
@@ -1462,8 +1491,9 @@ void Context::smooth_fp64(int level, int nrhs, int sweeps, bool reverse, const d
     }
     from_t(xa, x, m);
     if (rct) from_t(rct, rc, mc);
-    MLMC_HIP(hipStreamSynchronize(s_));
     MLMC_HIP(hipGetLastError());
+    if (ws) return;  // the caller's workspace: no stream synchronisation needed
+    MLMC_HIP(hipStreamSynchronize(s_));
     dfree(bt);
     dfree(xa);
     dfree(xb);

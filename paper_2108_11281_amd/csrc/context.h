@@ -112,8 +112,11 @@ class Context {
   void solve_fp64(int level, int nrhs, const double* b, double* y, double* relres,
                   bool throw_on_noconv);
   void apply_fp64(int level, int nrhs, const double* x, double* y);
-  void smooth_fp64(int level, int nrhs, int sweeps, bool reverse, const double* b, double* x,
-                   double* rc);
+  // ws: nullptr (working copies allocated for the call) or a device workspace
+  // of ws_bytes that holds them
+  void smooth_fp64(int level, int nrhs, int sweeps, bool reverse, bool zero_start,
+                   const double* b, double* x, double* rc, void* ws = nullptr,
+                   size_t ws_bytes = 0);
   void restrict_fp64(int level, int nrhs, const double* x, double* xc);
   void prolong_fp64(int level, int nrhs, const double* xc, double* x);
   void probes_fp64(int level, uint64_t seed, int stream, int64_t first, int nrhs,
@@ -128,6 +131,9 @@ class Context {
   void nn_get_weights(float* w);
   void nn_apply_fp64(int nrhs, const double* r, double* e);
   void nn_loss_grad(int ncrops, const float* in, const float* tgt, double* loss, float* grad);
+  void nn_crops_fp64(int nrhs, const double* r, const double* e, int ncrops, const int* origin,
+                     float* in_host, float* tgt_host);
+  void nn_adam_step(const float* grad, double lr, int t);
   int64_t nn_stats[2] = {0, 0};  // network applications, fallbacks
 
   int levels_mlmc() const { return L_; }

@@ -117,6 +117,66 @@ void Context::nn_loss_grad(int ncrops, const float* in, const float* tgt, double
   dfree(inb);
 }
 
+void Context::nn_crops_fp64(int nrhs, const double* r, const double* e, int ncrops,
+                            const int* origin, float* in_host, float* tgt_host) {
+  nn_require();
+  MLMC_REQUIRE(nrhs >= 1 && nrhs <= nb_, MLMC_EINVAL, "nrhs must be in [1, nb]");
+  MLMC_REQUIRE(ncrops >= 1 && ncrops <= 65536, MLMC_EINVAL, "ncrops must be in [1, 65536]");
+  const Level& L = lv_[0];
+  const int N = L.side;
+  for (int c = 0; c < ncrops; ++c) {
+    MLMC_REQUIRE(origin[3 * c] >= 0 && origin[3 * c] < nrhs, MLMC_EINVAL,
+                 "crop column out of range");
+    MLMC_REQUIRE(origin[3 * c + 1] >= 0 && origin[3 * c + 1] < N && origin[3 * c + 2] >= 0 &&
+                     origin[3 * c + 2] < N,
+                 MLMC_EINVAL, "crop corner outside the lattice");
+  }
+  if (!nn_links_) {  // the link features exist once the network state does
+    nn_alloc();
+  }
+  const c64* r64 = reinterpret_cast<const c64*>(r);
+  const int64_t nin = (int64_t)ncrops * nn_crop_in_elems();
+  const int64_t nout = (int64_t)ncrops * nn_crop_out_elems();
+  void* inb = dalloc((size_t)nin * 2);
+  float* tg = dalloc_n<float>(nout);
+  int* org = dalloc_n<int>(3 * (int64_t)ncrops);
+  // the RMS of each residual column, as the training-pair generator forms it
+  vec_dot_partials<c64>(r64, r64, L.n, nrhs, nullptr, partials_, s_);
+  finish_sums(partials_, reduce_blocks(L.n), nrhs, scal_[kNn], s_);
+  MLMC_HIP(hipMemcpyAsync(org, origin, sizeof(int) * 3 * (size_t)ncrops, hipMemcpyHostToDevice,
+                          s_));
+  nn_crops(r64, reinterpret_cast<const c64*>(e), scal_[kNn], 1.0 / (double)L.n, nn_links_, org,
+           ncrops, N, inb, tg, s_);
+  std::vector<uint16_t> hb((size_t)nin);
+  MLMC_HIP(hipMemcpyAsync(hb.data(), inb, (size_t)nin * 2, hipMemcpyDeviceToHost, s_));
+  MLMC_HIP(hipMemcpyAsync(tgt_host, tg, sizeof(float) * (size_t)nout, hipMemcpyDeviceToHost, s_));
+  MLMC_HIP(hipStreamSynchronize(s_));
+  MLMC_HIP(hipGetLastError());
+  for (int64_t i = 0; i < nin; ++i) {  // BF16 is the upper half of an FP32
+    const uint32_t u = (uint32_t)hb[(size_t)i] << 16;
+    std::memcpy(in_host + i, &u, 4);
+  }
+  dfree(org);
+  dfree(tg);
+  dfree(inb);
+}
+
+void Context::nn_adam_step(const float* grad, double lr, int t) {
+  MLMC_REQUIRE(nn_w_ != nullptr, MLMC_ESTATE, "no network weights set or trained");
+  MLMC_REQUIRE(t >= 1, MLMC_EINVAL, "the Adam step count starts at 1");
+  MLMC_REQUIRE(lr > 0 && std::isfinite(lr), MLMC_EINVAL, "learning rate must be > 0");
+  const int nw = nn_num_weights();
+  if (t == 1) {  // first step: zero moments
+    vec_zero<float>(nn_m_, nw, 1, nullptr, s_);
+    vec_zero<float>(nn_v_, nw, 1, nullptr, s_);
+  }
+  MLMC_HIP(hipMemcpyAsync(nn_g_, grad, sizeof(float) * nw, hipMemcpyHostToDevice, s_));
+  nn_adam(nn_w_, nn_m_, nn_v_, nn_g_, lr, 0.9, 0.999, 1e-8, t, s_);
+  nn_pack(nn_w_, nn_frag_, s_);
+  MLMC_HIP(hipStreamSynchronize(s_));
+  MLMC_HIP(hipGetLastError());
+}
+
 // ---------------------------------------------------------------------------
 // training
 // ---------------------------------------------------------------------------

@@ -114,12 +114,19 @@ def test_learned_solves_are_judged_and_samples_unchanged(trained):
     est = trained["est"]
     plain = _est(N, levels, m0, th, learned=False, nb=32)
     B = est.probes(1, 21, 0, 16)
+    fb0 = est.learned_stats()[1]
     Y, rel = est.solve(1, B)
     assert np.all(rel <= 1e-12)
     it_learned = est.counters()[0]
+    fb_solve = est.learned_stats()[1] - fb0
     Yp, relp = plain.solve(1, B)
     it_plain = plain.counters()[0]
     assert np.all(relp <= 1e-12)
+    # what the trained network gains: fewer FGMRES iterations than the plain
+    # smoother on the same right-hand sides (fixed seeds, trained weights), with
+    # no fallback to the plain smoother during the solve
+    assert fb_solve == 0, fb_solve
+    assert it_learned < it_plain, (it_learned, it_plain)
     y, yp = from_dev(Y, True), from_dev(Yp, True)
     assert np.max(np.abs(y - yp)) <= 1e-9 * np.max(np.abs(yp))
     apps, fallbacks = est.learned_stats()
@@ -131,7 +138,6 @@ def test_learned_solves_are_judged_and_samples_unchanged(trained):
     ref = orc.sample(1, 7, 0, 8)
     scale = quad_scale(orc.sample_parts(1, 7, 0, 8))
     assert np.all(np.abs(s - ref) <= 1e-8 * scale)
-    # what the trained network gains (or loses) per solve on this operator
     out = dict(N=N, m0=m0, fgmres_iterations_plain=int(it_plain),
                fgmres_iterations_learned=int(it_learned), fallbacks=int(fallbacks),
                loss_first=trained["rep"]["loss_first"], loss_last=trained["rep"]["loss_last"])
@@ -161,3 +167,57 @@ def test_learned_option_is_validated():
     with pytest.raises(m.MLMCError):   # side not a multiple of 16
         m.TraceEstimator("wilson2d", 40, 2, 2, mass=0.1, field=gauge_field(40), block=4,
                          n_vec=8, learned=1)
+
+
+def test_training_crops_match_oracle_features():
+    # the training-pair builder: inputs are the oracle's features (residual over its
+    # RMS, link cos/sin) cut periodically from the crop corner and rounded to BF16;
+    # targets the error over the same RMS on the 16 x 16 interior
+    N = 32
+    th = gauge_field(N, seed=2)
+    est = _est(N, 2, 0.1, th, nb=4)
+    rng = np.random.default_rng(8)
+    R = rng.standard_normal((3, 2 * N * N)) + 1j * rng.standard_normal((3, 2 * N * N))
+    R[1] *= 1e-3   # columns of different scale
+    E = rng.standard_normal((3, 2 * N * N)) + 1j * rng.standard_normal((3, 2 * N * N))
+    org = np.array([[0, 0, 0], [1, 5, 7], [2, N - 3, N - 20], [0, N - 1, N - 1],
+                    [2, 13, 29], [1, 31, 0]], dtype=np.int32)
+    inp, tgt = est.nn_crops(to_dev(R), to_dev(E), org)
+    for c, (col, y0, x0) in enumerate(org):
+        x0f, s = nn.features(R[col], th, N)
+        rows = (y0 + np.arange(22)) % N
+        cols = (x0 + np.arange(22)) % N
+        ref_in = bf16_round(x0f[:, rows][:, :, cols].transpose(1, 2, 0).astype(np.float32))
+        d = np.abs(inp[c] - ref_in)
+        # BF16 of the same FP32 value: equal, up to one BF16 unit where the FP64
+        # scaling rounds differently on the two sides
+        assert np.all(d <= 2.0 ** -8 * np.abs(ref_in)), c
+        assert np.mean(d == 0) >= 0.999, c
+        e = (E[col] / s).reshape(N, N, 2)[rows[3:19]][:, cols[3:19]]
+        ref_t = np.stack([e[..., 0].real, e[..., 0].imag, e[..., 1].real, e[..., 1].imag], -1)
+        assert np.max(np.abs(tgt[c] - ref_t)) <= 2.0 ** -22 * np.max(np.abs(ref_t)), c
+
+
+def test_adam_steps_match_oracle():
+    # three consecutive Adam steps on the GPU's own loss gradients (as in training)
+    # against the oracle's FP64 Adam fed the same gradients
+    import torch
+    N = 32
+    est = _est(N, 2, 0.1, gauge_field(N, seed=2), nb=4)
+    rng = np.random.default_rng(9)
+    X = torch.tensor(bf16_round(rng.standard_normal((4, 22, 22, 8))), device="cuda")
+    T = torch.tensor(rng.standard_normal((4, 16, 16, 4)).astype(np.float32), device="cuda")
+    w = nn_init_weights(5).astype(np.float32)
+    est.set_nn_weights(w)
+    lr = 1e-3
+    wr = w.astype(np.float64)
+    m_ = np.zeros_like(wr)
+    v_ = np.zeros_like(wr)
+    for t in (1, 2, 3):
+        _, g = est.nn_loss_grad(X, T)
+        est.nn_adam_step(g, lr, t)
+        wg = est.get_nn_weights().astype(np.float64)
+        wr, m_, v_ = nn.adam_step(wr, g.astype(np.float64), m_, v_, t, lr)
+        assert np.all(np.abs(wg - wr) <= 4e-7 * np.abs(wr) + 1e-4 * lr), t
+    # the weights moved (by about lr per step where the gradient kept its sign)
+    assert np.mean(np.abs(wr - w) > 0.5 * lr) > 0.9

@@ -18,7 +18,8 @@ NRHS = 5
 TOL = {"fp64": 1e-13, "fp32_ir64": 1e-5}
 
 
-def _check(est, A, colour, level, precision, complex_=False, sweeps=(1, 2, 3), tol=None):
+def _check(est, A, colour, level, precision, complex_=False, sweeps=(1, 2, 3), tol=None,
+           zero_start=False):
     tol = TOL[precision] if tol is None else max(tol, TOL[precision])
     rng = np.random.default_rng(level)
     n = A.shape[0]
@@ -27,9 +28,14 @@ def _check(est, A, colour, level, precision, complex_=False, sweeps=(1, 2, 3), t
     if complex_:
         B = B + 1j * rng.standard_normal((NRHS, n))
         X = X + 1j * rng.standard_normal((NRHS, n))
+    if zero_start:   # the V-cycle's pre-smoothing: forward sweeps from X = 0
+        X = np.zeros_like(B)
     for sw in sweeps:
-        for reverse in (False, True):
-            got = from_dev(est.smooth(level, to_dev(B), to_dev(X), sw, reverse), complex_)
+        for reverse in ((False,) if zero_start else (False, True)):
+            if zero_start:
+                got = from_dev(est.smooth(level, to_dev(B), None, sw, zero_start=True), complex_)
+            else:
+                got = from_dev(est.smooth(level, to_dev(B), to_dev(X), sw, reverse), complex_)
             for k in range(NRHS):
                 ref = hierarchy.rbgs_sweeps(A, B[k], X[k], colour, sw, reverse)
                 err = np.max(np.abs(got[k] - ref))
@@ -196,3 +202,75 @@ def test_varcoef_in_place_sweep_above_side_128():
             ref = hierarchy.rbgs_sweeps(A, B[k], X[k], colour, 1, reverse)
             err = np.max(np.abs(got[k] - ref))
             assert err <= TOL["fp32_ir64"] * np.max(np.abs(ref)), (reverse, k, err)
+
+
+# The zero-start kernel forms that every V-cycle pre-smoothing runs (the first
+# pass reads no iterate): Poisson one- and two-sweep passes from zero (march and
+# tile sides, both precisions), the Wilson fused two-colour pass from zero (32^2
+# tiles and the 16^2 lattice whose halo wraps onto its one tile), the coarse
+# block-stencil sweep, and the 3D fused sweep from zero.
+@pytest.mark.parametrize("precision", ["fp32_ir64", "fp64"])
+@pytest.mark.parametrize("N,L", [(200, 4), (128, 3)])
+def test_poisson_zero_start_sweeps_match_oracle(N, L, precision):
+    est = _poisson(N, L, precision)
+    A, P = hierarchy.poisson_hierarchy(N, L)
+    rng = np.random.default_rng(21)
+    for level in range(1, L):
+        side = N >> (level - 1)
+        _check(est, A[level - 1], hierarchy.site_coloring(side), level, precision,
+               sweeps=(1, 2, 3, 4), zero_start=True)
+        # with the restricted residual of the pre-smoothing's last pass
+        n = est.level_size(level)
+        Bh = rng.standard_normal((NRHS, n))
+        for sw in (1, 2, 3, 4):
+            xr, rc = est.smooth(level, to_dev(Bh), None, sw, restrict=True, zero_start=True)
+            x, r = from_dev(xr), from_dev(rc)
+            Al, Pl = A[level - 1], P[level - 1]
+            for k in range(NRHS):
+                ref = hierarchy.rbgs_sweeps(Al, Bh[k], np.zeros(n),
+                                            hierarchy.site_coloring(side), sw, False)
+                assert np.max(np.abs(x[k] - ref)) <= TOL[precision] * np.max(np.abs(ref))
+                rref = Pl.T @ (Bh[k] - Al @ x[k])
+                bound = np.max(Pl.T @ (np.abs(Bh[k]) + abs(Al) @ np.abs(x[k])))
+                assert np.max(np.abs(r[k] - rref)) <= TOL[precision] * bound, (level, sw, k)
+
+
+@pytest.mark.parametrize("precision", ["fp32_ir64", "fp64"])
+@pytest.mark.parametrize("N,nvec", [(16, 4), (32, 8)])
+def test_wilson_zero_start_sweeps_match_oracle(N, nvec, precision):
+    require_gpu()
+    import paper_2108_11281_amd as m
+    L, m0 = (2 if N == 16 else 3), 0.1
+    th = gauge_field(N, seed=3 if N == 16 else 2)
+    sweeps = 4 if N == 16 else 6
+    est = m.TraceEstimator("wilson2d", N, L, L, mass=m0, field=th, block=4, n_vec=nvec,
+                           setup_sweeps=sweeps, setup_seed=1, precision=precision, nb=8)
+    A, _ = hierarchy.wilson_hierarchy(N, th, m0, L, block=4, n_vec=nvec, sweeps=sweeps, seed=1)
+    _check(est, A[0], np.repeat(hierarchy.site_coloring(N), 2), 1, precision, True,
+           (1, 2, 3, 4), zero_start=True)
+    if L > 2:
+        _check(est, A[1], np.repeat(hierarchy.site_coloring(N // 4), nvec), 2, precision, True,
+               (1, 2), tol=1e-9, zero_start=True)
+
+
+@pytest.mark.parametrize("precision", ["fp32_ir64", "fp64"])
+def test_varcoef_zero_start_sweeps_match_oracle(precision):
+    require_gpu()
+    import paper_2108_11281_amd as m
+    N, L = 40, 3
+    faces = varcoef_faces(N, seed=1000)
+    est = m.TraceEstimator("varcoef3d", N, L, L, shift=1e-3, field=faces, nb=8,
+                           precision=precision)
+    A, _ = hierarchy.varcoef_hierarchy(N, faces, 1e-3, L)
+    for level in (1, 2):
+        _check(est, A[level - 1], hierarchy.site_coloring_3d(N >> (level - 1)), level,
+               precision, sweeps=(1, 2, 3), zero_start=True)
+
+
+def test_zero_start_rejects_reverse():
+    import paper_2108_11281_amd as m
+    import torch
+    est = _poisson(64, 3, "fp32_ir64")
+    B = torch.zeros((2, est.level_size(1)), dtype=torch.float64, device="cuda")
+    with pytest.raises(m.MLMCError):
+        est.smooth(1, B, None, 2, reverse=True, zero_start=True)
