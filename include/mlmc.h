@@ -290,7 +290,8 @@ enum mlmc_smooth_flags {
  * RHS-major blocks of nrhs <= nb vectors of n_l; x_dev is read (unless
  * MLMC_SMOOTH_ZERO_START) and overwritten; rc_dev: nrhs vectors of n_{l+1}.
  * 1 <= l < L_s; sweeps >= 0.  The library allocates and frees
- * working-precision copies during the call.  For tests and inspection. */
+ * working-precision copies during the call (see mlmc_smooth_noalloc for the
+ * allocation-free form).  For tests and inspection. */
 int mlmc_smooth(void* ctx, int level, int nrhs, int sweeps, int flags, const double* b_dev,
                 double* x_dev, double* rc_dev);
 
@@ -469,6 +470,27 @@ int mlmc_nn_loss_grad(void* ctx, int ncrops, const float* in, const float* targe
 int mlmc_nn_crops(void* ctx, int nrhs, const double* r, const double* e, int ncrops,
                   const int32_t* origin, float* in, float* target);
 int mlmc_nn_adam_step(void* ctx, const float* grad, double lr, int t);
+
+/* ---------------------------------------------------------------------------
+ * Allocation-free entry point, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  mlmc_smooth_noalloc has the arguments, results and errors of
+ * mlmc_smooth (same kernels, bit-identical output) but calls no hipMalloc,
+ * hipFree or allocating routine: its working-precision copies (3 blocks of
+ * nrhs x n_l, plus nrhs x n_{l+1} with rc_dev, each rounded up to 256 bytes;
+ * 4 or 8 bytes per real unknown, twice that for complex ones) live in a fixed
+ * device array of MLMC_NOALLOC_SCRATCH_BYTES that every GPU the library runs on
+ * holds until the process ends (looked up at the first mlmc_setup on the
+ * device).  Larger requests return MLMC_EINVAL and name the size.  It does not
+ * synchronise the stream: the output is ready when the context's stream
+ * reaches it.  All calls on one GPU share its array, so calls that overlap in
+ * time on one GPU (contexts on different streams, or different threads) race
+ * and must be serialised by the caller; calls queued on one stream are
+ * ordered and safe.
+ * ------------------------------------------------------------------------- */
+#define MLMC_NOALLOC_SCRATCH_BYTES (64u << 20)
+int mlmc_smooth_noalloc(void* ctx, int level, int nrhs, int sweeps, int flags,
+                        const double* b_dev, double* x_dev, double* rc_dev);
 
 /* Description of the last error on ctx (or of the last failed mlmc_setup
  * when ctx is NULL).  Valid until the next call on ctx. */

@@ -340,21 +340,25 @@ class TraceEstimator:
                                      self._ptr(y)))
         return y
 
-    def smooth(self, level, b, x, sweeps, reverse=False, restrict=False, zero_start=False):
+    def smooth(self, level, b, x, sweeps, reverse=False, restrict=False, zero_start=False,
+               noalloc=False):
         """`sweeps` red-black Gauss-Seidel sweeps of A_level x = b, in the working
         precision with the V-cycle's own kernels; returns the new x (x is not
         changed; with zero_start=True x may be None and the sweeps start from 0 with
         the pre-smoothing's zero-start kernels), and with restrict=True also
         R (b - A x) of it, as the V-cycle's last pre-smoothing pass forms it.
-        reverse: second colour first, as in post-smoothing."""
+        reverse: second colour first, as in post-smoothing.  noalloc: through
+        mlmc_smooth_noalloc (working copies in the library's fixed workspace)."""
         import torch
         y = torch.empty_like(b) if x is None else x.clone()
         rc = self._vec(level + 1, b.shape[0], b.device) if restrict else None
         flags = (_capi.SMOOTH_REVERSE if reverse else 0) | \
             (_capi.SMOOTH_ZERO_START if zero_start else 0)
-        self._c(self._lib.mlmc_smooth(self._ctx, int(level), int(b.shape[0]), int(sweeps), flags,
-                                      self._ptr(b), self._ptr(y),
-                                      self._ptr(rc) if restrict else None))
+        fn = self._lib.mlmc_smooth_noalloc if noalloc else self._lib.mlmc_smooth
+        self._c(fn(self._ctx, int(level), int(b.shape[0]), int(sweeps), flags, self._ptr(b),
+                   self._ptr(y), self._ptr(rc) if restrict else None))
+        if noalloc:
+            self._sync()
         return (y, rc) if restrict else y
 
     def restrict(self, level, x):

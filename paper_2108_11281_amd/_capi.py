@@ -30,6 +30,7 @@ MAX_LEVELS = 16
 
 SMOOTH_REVERSE = 1
 SMOOTH_ZERO_START = 2
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class Operator(ctypes.Structure):
@@ -130,6 +131,8 @@ SIGNATURES = {
     "mlmc_apply": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P]),
     "mlmc_smooth": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                    _P, _P, _P]),
+    "mlmc_smooth_noalloc": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_int, _P, _P, _P]),
     "mlmc_restrict": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P]),
     "mlmc_prolong": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P]),
     "mlmc_probes": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_uint64, ctypes.c_int,

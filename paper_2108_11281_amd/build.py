@@ -23,6 +23,7 @@ SOURCES = [
     "context_csr.cpp",
     "estimator.cpp",
     "capi.cpp",
+    "noalloc.cpp",
 ]
 
 FLAGS = [

@@ -83,6 +83,9 @@ int mlmc_setup(const mlmc_operator* A, const mlmc_hierarchy* h, const mlmc_optio
   Context* ctx = nullptr;
   int rc = guarded(nullptr, [&] {
     ctx = new Context(*A, *h, o, static_cast<hipStream_t>(hip_stream));
+    // the device's copy of the fixed workspace of the allocation-free entry
+    // points, looked up once per device while it is current
+    mlmc::noalloc_init(ctx->device());
   });
   if (rc == MLMC_OK) *out_ctx = ctx;
   return rc;

@@ -405,6 +405,10 @@ struct SamplerIface {
   std::function<void(int64_t count, c64* out)> pilot;
 };
 
+// Fixed device workspace of the allocation-free entry points: looked up for
+// device `dev` (current) once, at the first mlmc_setup on it.
+void noalloc_init(int dev);
+
 void run_estimator(int L, const SamplerIface& smp, c64 coarse, const std::vector<double>& cost,
                    const mlmc_options& opt, double tol, mlmc_result* out);
 void run_hutchinson(const std::function<void(int64_t, int64_t, c64*)>& sample,
