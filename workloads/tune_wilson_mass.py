@@ -2,7 +2,7 @@
 of D is about 1e-2 (shift steps on m0; eigenvalues from shift-invert Arnoldi
 of the CPU oracle's operator).  Writes workloads/wilson_mass.json.
 
-Run:  python workloads/tune_wilson_mass.py 256 512
+Run:  python workloads/tune_wilson_mass.py 256 512:-0.1876
 """
 import json
 import os
@@ -29,14 +29,16 @@ def smallest_eig(D):
     return vals[np.argmin(np.abs(vals))]
 
 
-def tune(N, sigma=0.5, seed=1, max_steps=8):
+def tune(N, sigma=0.5, seed=1, max_steps=8, start=None):
     """m0 at which the smallest-modulus eigenvalue of D has modulus TARGET (and a
     positive real part).  The mass only shifts the spectrum, D(m) = D(m') +
     (m - m') I, so each step moves m0 by TARGET - Re(lambda_min): exact when the
     same eigenvalue stays the one nearest to zero, a few steps otherwise.
-    Starts from the free field, where lambda_min = m0."""
+    Starts from `start` (e.g. the value tuned on a smaller lattice of the same
+    field distribution, where the eigenvalue nearest zero is well separated) or
+    from the free field, where lambda_min = m0."""
     theta = gauge_field(N, sigma, seed)
-    m = TARGET
+    m = TARGET if start is None else float(start)
     lam = None
     for _ in range(max_steps):
         lam = smallest_eig(wilson2d(N, theta, m))
@@ -51,8 +53,10 @@ if __name__ == "__main__":
     path = os.path.join(HERE, "wilson_mass.json")
     table = json.load(open(path)) if os.path.exists(path) else {}
     for arg in sys.argv[1:]:
-        N = int(arg)
-        m0, f = tune(N)
+        # "N" or "N:start"
+        N, _, start = arg.partition(":")
+        N = int(N)
+        m0, f = tune(N, start=float(start) if start else None)
         table[str(N)] = {"m0": m0, "min_abs_eig": f, "theta_sigma": 0.5, "gauge_seed": 1}
         with open(path, "w") as fh:
             json.dump(table, fh, indent=1)
