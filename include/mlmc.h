@@ -383,11 +383,16 @@ int mlmc_set_timing(void* ctx, int mask, int stride);
  * correction when there is no post-smoothing (2.25e), 3 Krylov direction update
  * fused with the operator apply and its dot (4e: z, p in; p, q out), 4 CG x/r
  * update with |r|^2 (6e), 5 learned-smoother network (counts FLOPs, not
- * bytes: 2 x 4032 per site and column), 6 unused, 7 FP64 refinement residual
- * (20 bytes: FP64 b and y in, FP32 r out).  fp64 = 0 selects the FP32/complex64
+ * bytes: 2 x 4032 per site and column), 6 FP64 refinement fold y += x32 with
+ * its b^T x32 partial sums and x32 = 0 (32 bytes: FP64 y, b and FP32 x32 in; y
+ * and x32 out; fp64 slot), 7 FP64 refinement residual (20 bytes: FP64 b and y
+ * in, FP32 r out; fp64 slot).  fp64 = 0 selects the FP32/complex64
  * instantiation, 1 the FP64 one.  out: launches, total milliseconds, total
  * algorithmic bytes (active columns only). */
 int mlmc_kernel_stats(void* ctx, int kernel, int fp64, double* out);
+/* The same restricted to the launches on one level (1 <= level <= L_s; 0 = all
+ * levels, as mlmc_kernel_stats). */
+int mlmc_kernel_stats_level(void* ctx, int kernel, int fp64, int level, double* out);
 int mlmc_reset_kernel_stats(void* ctx);
 
 /* ---------------------------------------------------------------------------
@@ -491,6 +496,58 @@ int mlmc_nn_adam_step(void* ctx, const float* grad, double lr, int t);
 #define MLMC_NOALLOC_SCRATCH_BYTES (64u << 20)
 int mlmc_smooth_noalloc(void* ctx, int level, int nrhs, int sweeps, int flags,
                         const double* b_dev, double* x_dev, double* rc_dev);
+
+/* ---------------------------------------------------------------------------
+ * Deflated Hutchinson: the comparison method of Sec. 5 (Sec. 4.2, eqs.
+ * orth_proj and defl).  With Pi = U U^H for the n_defl eigenvectors of the
+ * smallest eigenvalues of a Hermitian A, tr(A^{-1}) = tr(A^{-1}(I - Pi)) +
+ * tr(A^{-1} Pi): the first trace is estimated from samples
+ * x^H A^{-1} (x - U (U^H x)) with the plain Hutchinson probes (RNG stream 3, so
+ * sample k shares its probe with mlmc_hutchinson's sample k), the second is
+ * computed once as tr(U^H A^{-1} U) (sum 1/lambda_i for exact eigenvectors;
+ * the split stays exact for approximate ones).  Real symmetric kinds (POISSON2D,
+ * VARCOEF3D, CSR); others return MLMC_EUNSUPPORTED.
+ * ------------------------------------------------------------------------- */
+typedef struct mlmc_deflation_options {
+  int n_defl;        /* deflated eigenpairs k (1..1024) */
+  int oversample;    /* extra block vectors p of the subspace iteration (0: max(8, k/2)) */
+  double eig_tol;    /* stop when every |A u_i - theta_i u_i| / theta_i <= eig_tol */
+  int max_iter;      /* subspace iterations (each: k + p solves, Rayleigh-Ritz) */
+  double solve_tol;  /* relative residual of the iteration's solves (0: 1e-8); the
+                        direct term is solved to the context's solve_tol */
+  uint64_t seed;     /* start block (Rademacher, RNG stream 6) */
+} mlmc_deflation_options;
+
+typedef struct mlmc_deflation_report {
+  int iterations;        /* subspace iterations run */
+  double seconds;        /* wall time of the setup (eigenpairs and direct term) */
+  double max_residual;   /* largest relative Ritz residual of the k pairs */
+  double direct_trace;   /* tr(U^H A^{-1} U) */
+  double sum_inv_eig;    /* sum of 1/theta_i over the k Ritz values */
+  int64_t solves;        /* right-hand sides solved by the setup */
+} mlmc_deflation_report;
+
+/* Compute the deflation space of level 1 (block subspace iteration with the
+ * library's own solves: W = A^{-1} V, two passes of Cholesky QR, Rayleigh-Ritz
+ * with a Jacobi eigensolver on the (k+p) x (k+p) projected matrix) and the
+ * direct term.  Replaces an earlier deflation space.  ENOCONV if a solve fails;
+ * the Ritz residuals reached are reported even when max_iter ran out. */
+int mlmc_deflation_setup(void* ctx, const mlmc_deflation_options* opt,
+                         mlmc_deflation_report* report);
+/* Deflated samples x_k^H A^{-1} (I - Pi) x_k, k = first..first+nsamples-1, as
+ * (re, im) pairs in out (host, nsamples x 2); out_err (nullable): stated FP64
+ * error per sample as for mlmc_sample_level.  ESTATE before mlmc_deflation_setup. */
+int mlmc_deflated_sample(void* ctx, uint64_t seed, int64_t first, int64_t nsamples,
+                         double* out, double* out_err);
+/* Deflated Hutchinson estimate to relative accuracy tol with the control of
+ * Sec. 5 (tau from the five plain pilot estimates, samples until their RMSD is
+ * at most tol * tau, batches of at most nb).  trace = sample mean + direct term;
+ * coarse_trace holds the direct term; n_samples[0] the sample count. */
+int mlmc_deflated_hutchinson(void* ctx, double tol, uint64_t seed, mlmc_result* out);
+/* Copy the deflation space: eigenvalues (host, k Ritz values ascending, or
+ * NULL), vectors_dev (device, k x n_1 FP64 RHS-major, or NULL), direct (host,
+ * 1 double, or NULL). */
+int mlmc_deflation_export(void* ctx, double* eigenvalues, double* vectors_dev, double* direct);
 
 /* Description of the last error on ctx (or of the last failed mlmc_setup
  * when ctx is NULL).  Valid until the next call on ctx. */

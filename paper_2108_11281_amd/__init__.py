@@ -255,6 +255,45 @@ class TraceEstimator:
         self._c(self._lib.mlmc_hutchinson(self._ctx, float(tol), int(seed), ctypes.byref(r)))
         return _result_dict(r)
 
+    # -- deflated Hutchinson (Sec. 4.2 / Sec. 5 comparison method) --
+    def deflation_setup(self, n_defl, *, oversample=0, eig_tol=1e-3, max_iter=60,
+                        solve_tol=1e-8, seed=1):
+        """Eigenpairs of the n_defl smallest eigenvalues (subspace iteration on the
+        library's solves) and the direct term tr(U^T A^-1 U); returns the report."""
+        o = _capi.DeflationOptions(int(n_defl), int(oversample), float(eig_tol), int(max_iter),
+                                   float(solve_tol), int(seed))
+        r = _capi.DeflationReport()
+        self._c(self._lib.mlmc_deflation_setup(self._ctx, ctypes.byref(o), ctypes.byref(r)))
+        return dict(iterations=r.iterations, seconds=r.seconds, max_residual=r.max_residual,
+                    direct_trace=r.direct_trace, sum_inv_eig=r.sum_inv_eig, solves=r.solves)
+
+    def deflated_sample(self, seed, first, count, with_error=False):
+        out = np.zeros((count, 2))
+        err = np.zeros(count)
+        self._c(self._lib.mlmc_deflated_sample(
+            self._ctx, int(seed), int(first), int(count),
+            out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            err.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        s = out[:, 0] + 1j * out[:, 1]
+        return (s, err) if with_error else s
+
+    def deflated_hutchinson(self, tol, seed):
+        r = _capi.Result()
+        self._c(self._lib.mlmc_deflated_hutchinson(self._ctx, float(tol), int(seed),
+                                                   ctypes.byref(r)))
+        return _result_dict(r)
+
+    def deflation_export(self, n_defl):
+        """(eigenvalues [k], U [k, n_1] device tensor, direct term)."""
+        import torch
+        lam = np.zeros(int(n_defl))
+        U = torch.empty((int(n_defl), self.level_size(1)), dtype=torch.float64, device="cuda")
+        d = ctypes.c_double()
+        self._c(self._lib.mlmc_deflation_export(
+            self._ctx, lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), self._ptr(U),
+            ctypes.byref(d)))
+        return lam, U, d.value
+
     def sample_level(self, level, seed, first, count, with_error=False):
         out = np.zeros((count, 2))
         err = np.zeros(count)
@@ -283,7 +322,7 @@ class TraceEstimator:
 
     # -- measurement --
     KERNELS = ["rbgs_sweep", "residual_restrict", "prolong_correct", "update_apply", "cg_xr",
-               "nn_apply", "unused6", "ir_residual"]
+               "nn_apply", "ir_fold", "ir_residual"]
 
     def set_timing(self, kernels=True, stride=1):
         """kernels: True (all), False (none) or a list of kernel names to time;
@@ -301,12 +340,14 @@ class TraceEstimator:
     def reset_kernel_stats(self):
         self._c(self._lib.mlmc_reset_kernel_stats(self._ctx))
 
-    def kernel_stats(self, kernel, fp64=False):
-        """(launches, total ms, total algorithmic bytes) of a timed kernel."""
+    def kernel_stats(self, kernel, fp64=False, level=0):
+        """(launches, total ms, total algorithmic bytes) of a timed kernel, over all
+        levels (level 0) or on one level."""
         kid = self.KERNELS.index(kernel) if isinstance(kernel, str) else int(kernel)
         out = np.zeros(3)
-        self._c(self._lib.mlmc_kernel_stats(self._ctx, kid, 1 if fp64 else 0,
-                                            out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        self._c(self._lib.mlmc_kernel_stats_level(
+            self._ctx, kid, 1 if fp64 else 0, int(level),
+            out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return int(out[0]), float(out[1]), float(out[2])
 
     # -- FP64 building blocks on torch device tensors --

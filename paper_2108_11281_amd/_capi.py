@@ -101,6 +101,18 @@ class TrainReport(ctypes.Structure):
                 ("gen_seconds", ctypes.c_double), ("train_seconds", ctypes.c_double)]
 
 
+class DeflationOptions(ctypes.Structure):
+    _fields_ = [("n_defl", ctypes.c_int), ("oversample", ctypes.c_int),
+                ("eig_tol", ctypes.c_double), ("max_iter", ctypes.c_int),
+                ("solve_tol", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
+class DeflationReport(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("seconds", ctypes.c_double),
+                ("max_residual", ctypes.c_double), ("direct_trace", ctypes.c_double),
+                ("sum_inv_eig", ctypes.c_double), ("solves", ctypes.c_int64)]
+
+
 SAMPLE_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int64,
                              ctypes.c_int64, ctypes.POINTER(ctypes.c_double))
 PILOT_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int64,
@@ -147,6 +159,7 @@ SIGNATURES = {
     "mlmc_counters": (ctypes.c_int, [_P, _I64, ctypes.c_int]),
     "mlmc_set_timing": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
     "mlmc_kernel_stats": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _D]),
+    "mlmc_kernel_stats_level": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _D]),
     "mlmc_reset_kernel_stats": (ctypes.c_int, [_P]),
     "mlmc_batch_sample": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_uint64), ctypes.c_int64,
@@ -160,6 +173,13 @@ SIGNATURES = {
     "mlmc_nn_loss_grad": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _D, _F]),
     "mlmc_nn_crops": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_int, _I32, _F, _F]),
     "mlmc_nn_adam_step": (ctypes.c_int, [_P, _F, ctypes.c_double, ctypes.c_int]),
+    "mlmc_deflation_setup": (ctypes.c_int, [_P, ctypes.POINTER(DeflationOptions),
+                                            ctypes.POINTER(DeflationReport)]),
+    "mlmc_deflated_sample": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64,
+                                            _D, _D]),
+    "mlmc_deflated_hutchinson": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_uint64,
+                                                ctypes.POINTER(Result)]),
+    "mlmc_deflation_export": (ctypes.c_int, [_P, _D, _P, _D]),
     "mlmc_last_error": (ctypes.c_char_p, [_P]),
     "mlmc_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "mlmc_destroy": (None, [_P]),

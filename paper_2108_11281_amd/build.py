@@ -17,10 +17,12 @@ SOURCES = [
     "kernels_varcoef.hip",
     "kernels_nn.hip",
     "kernels_csr.hip",
+    "kernels_defl.hip",
     "context.cpp",
     "context_complex.cpp",
     "context_nn.cpp",
     "context_csr.cpp",
+    "context_defl.cpp",
     "estimator.cpp",
     "capi.cpp",
     "noalloc.cpp",

@@ -300,6 +300,32 @@ int mlmc_nn_adam_step(void* c, const float* grad, double lr, int t) {
   });
 }
 
+int mlmc_deflation_setup(void* c, const mlmc_deflation_options* opt,
+                         mlmc_deflation_report* report) {
+  Context* ctx = as_ctx(c);
+  if (!ctx || !opt) return MLMC_EINVAL;
+  return guarded(ctx, [&] { ctx->deflation_setup(*opt, report); });
+}
+
+int mlmc_deflated_sample(void* c, uint64_t seed, int64_t first, int64_t nsamples, double* out,
+                         double* out_err) {
+  Context* ctx = as_ctx(c);
+  if (!ctx || !out) return MLMC_EINVAL;
+  return guarded(ctx, [&] { ctx->deflated_sample(seed, first, nsamples, out, out_err); });
+}
+
+int mlmc_deflated_hutchinson(void* c, double tol, uint64_t seed, mlmc_result* out) {
+  Context* ctx = as_ctx(c);
+  if (!ctx || !out) return MLMC_EINVAL;
+  return guarded(ctx, [&] { ctx->deflated_hutchinson(tol, seed, out); });
+}
+
+int mlmc_deflation_export(void* c, double* eigenvalues, double* vectors_dev, double* direct) {
+  Context* ctx = as_ctx(c);
+  if (!ctx) return MLMC_EINVAL;
+  return guarded(ctx, [&] { ctx->deflation_export(eigenvalues, vectors_dev, direct); });
+}
+
 int mlmc_batch_sample(void* const* ctxs, int count, int level, const uint64_t* seeds,
                       int64_t first, int64_t nsamples, int workers, double* out,
                       double* seconds) {
@@ -365,6 +391,12 @@ int mlmc_kernel_stats(void* c, int kernel, int fp64, double* out) {
   Context* ctx = as_ctx(c);
   if (!ctx || !out) return MLMC_EINVAL;
   return guarded(ctx, [&] { ctx->kernel_stats(kernel, fp64, out); });
+}
+
+int mlmc_kernel_stats_level(void* c, int kernel, int fp64, int level, double* out) {
+  Context* ctx = as_ctx(c);
+  if (!ctx || !out) return MLMC_EINVAL;
+  return guarded(ctx, [&] { ctx->kernel_stats(kernel, fp64, out, level); });
 }
 
 int mlmc_reset_kernel_stats(void* c) {

@@ -135,6 +135,12 @@ class Context {
                      float* in_host, float* tgt_host);
   void nn_adam_step(const float* grad, double lr, int t);
   int64_t nn_stats[2] = {0, 0};  // network applications, fallbacks
+  // deflated Hutchinson (real symmetric kinds)
+  void deflation_setup(const mlmc_deflation_options& o, mlmc_deflation_report* rep);
+  void deflated_sample(uint64_t seed, int64_t first, int64_t count, double* out,
+                       double* out_err);
+  void deflated_hutchinson(double tol, uint64_t seed, mlmc_result* out);
+  void deflation_export(double* eigenvalues, double* vectors_dev, double* direct);
 
   int levels_mlmc() const { return L_; }
   int levels_solver() const { return Ls_; }
@@ -148,10 +154,11 @@ class Context {
 
   // kernel timing (measurement mode)
   // kTimNn counts flops (not bytes) per column: the network is MFMA-bound
-  enum { kTimGs, kTimResRestrict, kTimProlong, kTimApply, kTimCgXr, kTimNn, kTimUnused6,
+  enum { kTimGs, kTimResRestrict, kTimProlong, kTimApply, kTimCgXr, kTimNn, kTimIrFold,
          kTimIrResidual, kNumTimers };
   void set_timing(unsigned mask, int stride);
-  void kernel_stats(int id, int fp64, double* out);
+  // level 0: all levels; 1..L_s: launches on that level only
+  void kernel_stats(int id, int fp64, double* out, int level = 0);
   void reset_kernel_stats();
 
   // level-difference samples and pilot/Hutchinson samples in batches <= nb
@@ -202,6 +209,12 @@ class Context {
   void finish_real_build();
   void build_wilson(const double* theta);
   void nn_alloc();
+  void defl_require() const;
+  void defl_gram(const double* A, int ma, const double* B, int mb, double* C);
+  std::vector<double> defl_gram_host(const double* A, int ma, const double* B, int mb);
+  bool defl_solve_block(const double* X, double* Y, int m);
+  void defl_apply_block(const double* X, double* Y, int m);
+  void deflated_batch(uint64_t seed, uint64_t first, int nbatch, c64* out, double* err_out);
   void nn_require() const;
   // r = b - A_1 x ; x += s * net(r / s)  (finest level, FP32 / complex64)
   void nn_step(const c32* b, c32* x, int nb, const int* act);
@@ -279,17 +292,19 @@ class Context {
                   const double* y, c64* out);
   hipEvent_t event();
   void collect_timing();
+  // launch() on level `level` (1-based), timed as kernel `id` in measurement mode
   template <typename T, typename F>
-  void timed(int id, double bytes_per_col, const int* act, int nb, F&& launch);
+  void timed(int level, int id, double bytes_per_col, const int* act, int nb, F&& launch);
   struct TimerStat {
     int64_t launches = 0;
     double ms = 0, bytes = 0;
   };
   struct Pending {
-    int slot, idx, nb;
+    int slot, idx, nb, level;
     double bytes_per_col;
     hipEvent_t a, b;
   };
+
   static constexpr int kTimingLog = 1 << 16;
   bool timing_ = false;
   unsigned timing_mask_ = 0;
@@ -300,6 +315,7 @@ class Context {
   std::vector<Pending> pending_;
   std::vector<hipEvent_t> ev_pool_;
   TimerStat tstat_[2 * kNumTimers];
+  TimerStat tstat_lv_[2 * kNumTimers][MLMC_MAX_LEVELS];
 
   int kind_;
   int device_ = 0;
@@ -355,6 +371,15 @@ class Context {
   int *act_outer_ = nullptr, *act_inner_ = nullptr, *count_dev_ = nullptr;  // count_dev_: 4 ints
   int* count_host_ = nullptr;
   c64* host_c64_ = nullptr;  // pinned, 8*nb
+  // deflation: Ritz block V (the first defl_k_ vectors are U), work blocks W
+  // and Z, small device matrices, Gram partial sums; eigenvalues and the direct
+  // term tr(U^T A^{-1} U)
+  double *defl_V_ = nullptr, *defl_W_ = nullptr, *defl_Z_ = nullptr, *defl_small_ = nullptr;
+  double* defl_part_ = nullptr;
+  int64_t defl_part_cap_ = 0;
+  int defl_k_ = 0;
+  std::vector<double> defl_lambda_;
+  double defl_direct_ = 0.0;
 };
 
 // splitmix64 finaliser (sampling of timed launches)
@@ -366,7 +391,8 @@ inline uint64_t mix64(uint64_t z) {
 }
 
 template <typename T, typename F>
-inline void Context::timed(int id, double bytes_per_col, const int* act, int nb, F&& launch) {
+inline void Context::timed(int level, int id, double bytes_per_col, const int* act, int nb,
+                           F&& launch) {
   (void)act;
   // with stride k, a launch is timed with probability 1/k, chosen by a hash of
   // its index so that the sample does not alias with the period of the V-cycle
@@ -394,7 +420,7 @@ inline void Context::timed(int id, double bytes_per_col, const int* act, int nb,
     ev_pool_.push_back(b);
     return;
   }
-  pending_.push_back({slot, idx, nb, bytes_per_col, a, b});
+  pending_.push_back({slot, idx, nb, level, bytes_per_col, a, b});
 }
 
 // ---------------------------------------------------------------------------

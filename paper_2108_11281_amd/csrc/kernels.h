@@ -40,6 +40,19 @@ LaunchEvents*& timing_events();
     }                                                                                        \
   } while (0)
 
+// ----- blocks of vectors (deflation): FP64, RHS-major [m][n] -----------------
+// row chunks of the Gram reduction over n for an ma x mb product
+int gram_chunks(int64_t n, int ma, int mb);
+// part[c][i][j] = sum over chunk c of A[i][r] B[j][r] (nchunks chunks of n)
+void gram_partials(const double* A, int ma, const double* B, int mb, int64_t n, int nchunks,
+                   double* part, hipStream_t s);
+// C[i][j] = sum_c part[c][i][j] in chunk order (row-major ma x mb)
+void gram_finish(const double* part, int nchunks, int ma, int mb, double* C, hipStream_t s);
+// Out[j][r] = beta X[j][r] + alpha sum_{m < kk} U[m][r] C[m * ldc + j], j < nc;
+// Out may equal X; X is not read when beta == 0
+void block_combine(const double* U, int kk, const double* C, int ldc, const double* X,
+                   double* Out, int nc, int64_t n, double alpha, double beta, hipStream_t s);
+
 // ----- vectors ---------------------------------------------------------------
 template <typename T>
 void vec_zero(T* x, int64_t n, int nb, const int* active, hipStream_t s);
