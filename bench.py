@@ -157,11 +157,13 @@ def stored_traffic():
 
 
 def kernel_table(est):
+    """Launches, time and achieved rate of every timed kernel; the FP64 refinement
+    kernels (residual, fold) are read from their FP64 instantiation."""
     out = {}
     for k in est.KERNELS:
         if k.startswith("unused"):
             continue
-        launches, ms, amount = est.kernel_stats(k)
+        launches, ms, amount = est.kernel_stats(k, fp64=k.startswith("ir_"))
         rate = amount / (ms * 1e-3) if ms > 0 else 0.0
         if k == "nn_apply":
             out[k] = dict(launches=launches, ms=round(ms, 2), tflops=round(rate / 1e12, 2))
@@ -178,6 +180,44 @@ def hbm_roofline(name, stats, stride, traffic=None):
                 launches_timed=launches, timing_stride=stride,
                 avg_launch_us=round(1000.0 * ms / max(launches, 1), 2),
                 algorithmic_bytes_per_launch=round(nbytes / max(launches, 1)))
+
+
+def per_level_fractions(est, kernel, levels, fp64=False):
+    """Achieved HBM fraction of one kernel family on each level (event-timed launches
+    of the timed steps)."""
+    out = []
+    for l in range(1, levels + 1):
+        launches, ms, nbytes = est.kernel_stats(kernel, fp64=fp64, level=l)
+        if launches == 0:
+            continue
+        gbs = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+        out.append(dict(level=l, n=est.level_size(l), launches_timed=launches,
+                        avg_launch_us=round(1000.0 * ms / launches, 2),
+                        gbs=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4),
+                        time_share=None, _ms=ms))
+    tot = sum(d["_ms"] for d in out) or 1.0
+    for d in out:
+        d["time_share"] = round(d.pop("_ms") / tot, 4)
+    return out
+
+
+def copy_bandwidth(torch, mib=1024, reps=20):
+    """Measured device-to-device copy rate (read + write bytes per second) of a
+    plain copy kernel on this GPU, beside the 8 TB/s vendor peak."""
+    n = mib * (1 << 20) // 4
+    a = torch.empty(n, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) * 1e-3 / reps
+    del a, b
+    return round(2.0 * n * 4 / s / 1e9, 1)
 
 
 def timed_traces(est, args, torch, method="trace"):
@@ -230,6 +270,7 @@ def run_poisson(args, m, torch):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     gs = est.kernel_stats("rbgs_sweep")
+    per_level = per_level_fractions(est, "rbgs_sweep", L)
     est.set_timing(True)
     est.reset_kernel_stats()
     est.trace(args.eps, 777)
@@ -237,6 +278,12 @@ def run_poisson(args, m, torch):
     est.set_timing(False)
     ms_per_step = 1000.0 * elapsed / args.steps
     roofline = hbm_roofline("rbgs_sweep<float>", gs, args.timing_stride, stored_traffic())
+    roofline["per_level"] = per_level
+    copy_gbs = copy_bandwidth(torch)
+    roofline["copy_kernel_gbs"] = copy_gbs
+    roofline["frac_of_copy"] = round(roofline["achieved"] / copy_gbs, 4)
+    log("per-level sweep fractions %s; copy kernel %.1f GB/s" % (
+        [(d["level"], d["frac"]) for d in per_level], copy_gbs))
 
     compare = {}
     if not args.no_compare:
@@ -270,6 +317,8 @@ def run_poisson(args, m, torch):
         e64.close()
         compare["speedup_vs_fp64_mlmc"] = round(t64 / (ms_per_step / 1000.0), 2)
         compare["speedup_vs_fp64_hutchinson"] = round(th / (ms_per_step / 1000.0), 2)
+        if not args.no_c4:
+            compare["c4_learned"] = c4_compare(args, m, torch)
 
     cpu, accuracy = None, {"n_samples": [r["n_samples"] for r in runs],
                            "rmsd_rel": [round(r["rmsd"] / abs(r["trace"].real), 7) for r in runs]}
@@ -304,6 +353,50 @@ def _wilson_est(m, N, Ls, L, precision, learned, nb, alloc, n_vec=8, spin_split=
                             spin_split=spin_split, setup_sweeps=20, setup_seed=1,
                             precision=precision, nb=nb, nu_pre=2, nu_post=2, solve_tol=1e-10,
                             alloc=alloc, learned=1 if learned else 0)
+
+
+def c4_compare(args, m, torch):
+    """The learned-smoother configuration (Wilson 512^2, 4 solver / 3 MLMC levels):
+    time per trace with the trained network + FP32, plain FP32 and plain FP64 MLMC
+    on the same seeds, training (pair generation from the method's own plain solves
+    and Adam) timed separately, and the number of traces after which training
+    pays for itself against plain FP32."""
+    from workloads import nn_init_weights
+    N, Ls, L = 512, 4, 3
+    steps = max(1, min(args.steps, args.c4_steps))
+    sub = argparse.Namespace(**vars(args))
+    sub.steps = steps
+    out = {"workload": "wilson2d_512x512_Ls4_L3_agg4x4x8_nb%d_c64ir128_eps%g_learned"
+                       % (args.nb, args.eps), "traces_timed": steps}
+    log("C4: learned smoother on Wilson 512^2 (training on %d plain solves)"
+        % (args.train_batches * args.nb))
+    est = _wilson_est(m, N, Ls, L, "fp32_ir64", True, args.nb, args.alloc)
+    t0 = time.perf_counter()
+    train = est.learned_train(nn_init_weights(1), n_batches=args.train_batches,
+                              crops_per_column=4, steps=args.train_steps, batch=256, lr=2e-3,
+                              seed=5)
+    train["wall_s"] = round(time.perf_counter() - t0, 3)
+    out["training"] = train
+    tl, nl = timed_traces(est, sub, torch)
+    out["learned_fp32_s"] = round(tl, 4)
+    out["learned_n_samples"] = nl
+    out["learned_stats"] = list(est.learned_stats())
+    est.close()
+    ep = _wilson_est(m, N, Ls, L, "fp32_ir64", False, args.nb, args.alloc)
+    tp, npl = timed_traces(ep, sub, torch)
+    ep.close()
+    e64 = _wilson_est(m, N, Ls, L, "fp64", False, args.nb, args.alloc)
+    t64, n64 = timed_traces(e64, sub, torch)
+    e64.close()
+    out.update(plain_fp32_s=round(tp, 4), plain_fp32_n_samples=npl, fp64_mlmc_s=round(t64, 4),
+               fp64_n_samples=n64, speedup_learned_vs_fp64=round(t64 / tl, 3),
+               speedup_learned_vs_plain_fp32=round(tp / tl, 3))
+    gain = tp - tl
+    out["training_break_even_traces"] = (round(train["wall_s"] / gain, 1) if gain > 0
+                                         else None)
+    log("C4: learned %.4fs, plain FP32 %.4fs, plain FP64 %.4fs per trace; training %.1fs"
+        % (tl, tp, t64, train["wall_s"]))
+    return out
 
 
 def run_wilson(args, m, torch, N, learned):
@@ -718,6 +811,10 @@ def main():
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the comparison runs after the timed region")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-c4", action="store_true",
+                    help="poisson1024: skip the learned-smoother (Wilson 512^2) comparison")
+    ap.add_argument("--c4-steps", type=int, default=5,
+                    help="poisson1024: traces per variant in the learned-smoother comparison")
     ap.add_argument("--timing-stride", type=int, default=8,
                     help="bracket about one launch in k of the timed kernel with HIP events")
     ap.add_argument("--copy-check", action="store_true",

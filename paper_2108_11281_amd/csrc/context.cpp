@@ -620,7 +620,7 @@ void Context::vcycle_vc(int l, const T* b, T* x, int nb, const int* act, c64* rz
     for (int i = 0; i < pre; ++i) {
       T* out = (i % 2 == 0) ? tmp : x;
       const T* in = u;
-      timed<T>(kTimGs, en * ((in ? 3.0 : 2.0) + 4.0 / (double)nb), act, nb, [&] {
+      timed<T>(l, kTimGs, en * ((in ? 3.0 : 2.0) + 4.0 / (double)nb), act, nb, [&] {
         varcoef_rbgs_march<T>(in, b, out, nullptr, 0.0, kf, dg, L.side, nb, L.mcols, act, false,
                               s_);
       });
@@ -631,12 +631,12 @@ void Context::vcycle_vc(int l, const T* b, T* x, int nb, const int* act, c64* rz
     if (u == nullptr)
       op_restrict<T>(l, b, bc, nb, act);
     else
-      timed<T>(kTimResRestrict, en * (2.0 + 0.125 + 4.0 / (double)nb), act, nb,
+      timed<T>(l, kTimResRestrict, en * (2.0 + 0.125 + 4.0 / (double)nb), act, nb,
                [&] { op_res_restrict<T>(l, b, u, bc, nb, act); });
     vcycle_vc<T>(l + 1, bc, ec, nb, act, nullptr);
     if (post == 0) {
       if (u != nullptr && u != x) vec_copy<T>(u, x, n, nb, act, s_);
-      timed<T>(kTimProlong, en * (2.0 + 0.125), act, nb, [&] {
+      timed<T>(l, kTimProlong, en * (2.0 + 0.125), act, nb, [&] {
         varcoef_prolong<T>(ec, x, L.side, omega_, u == nullptr ? 0.0 : 1.0, nb, act, s_);
       });
     }
@@ -646,7 +646,7 @@ void Context::vcycle_vc(int l, const T* b, T* x, int nb, const int* act, c64* rz
       if (out == u) out = (out == x) ? tmp : x;  // never sweep in place
       const T* in = u;
       const T* corr = (i == 0) ? ec : nullptr;
-      timed<T>(kTimGs,
+      timed<T>(l, kTimGs,
                en * ((in ? 3.0 : 2.0) + (corr ? 0.125 : 0.0) + 4.0 / (double)nb), act, nb, [&] {
                  varcoef_rbgs_march<T>(in, b, out, corr, omega_, kf, dg, L.side, nb, L.mcols,
                                        act, true, s_);
@@ -660,7 +660,7 @@ void Context::vcycle_vc(int l, const T* b, T* x, int nb, const int* act, c64* rz
     const T* dg = vc_diag<T>(l);
     const int pre = opt_.nu_pre, post = opt_.nu_post;
     for (int i = 0; i < pre; ++i)
-      timed<T>(kTimGs, en * ((i == 0 ? 2.0 : 3.0) + 4.0 / (double)nb), act, nb, [&] {
+      timed<T>(l, kTimGs, en * ((i == 0 ? 2.0 : 3.0) + 4.0 / (double)nb), act, nb, [&] {
         varcoef_rbgs<T>(b, x, kf, dg, L.side, nb, L.cols, act, i == 0, false, nullptr, 0.0, s_);
       });
     T* bc = w.vb[l];
@@ -668,18 +668,18 @@ void Context::vcycle_vc(int l, const T* b, T* x, int nb, const int* act, c64* rz
     if (pre == 0)
       op_restrict<T>(l, b, bc, nb, act);
     else
-      timed<T>(kTimResRestrict, en * (2.0 + 0.125 + 4.0 / (double)nb), act, nb,
+      timed<T>(l, kTimResRestrict, en * (2.0 + 0.125 + 4.0 / (double)nb), act, nb,
                [&] { op_res_restrict<T>(l, b, x, bc, nb, act); });
     vcycle_vc<T>(l + 1, bc, ec, nb, act, nullptr);
     if (post == 0 || pre == 0) {
-      timed<T>(kTimProlong, en * (2.0 + 0.125), act, nb, [&] {
+      timed<T>(l, kTimProlong, en * (2.0 + 0.125), act, nb, [&] {
         varcoef_prolong<T>(ec, x, L.side, omega_, pre == 0 ? 0.0 : 1.0, nb, act, s_);
       });
     }
     for (int i = 0; i < post; ++i) {
       // the first post-sweep reads the corrected iterate x + omega P ec on the fly
       const bool fold = (i == 0 && pre > 0);
-      timed<T>(kTimGs, en * (3.0 + (fold ? 0.125 : 0.0) + 4.0 / (double)nb), act, nb, [&] {
+      timed<T>(l, kTimGs, en * (3.0 + (fold ? 0.125 : 0.0) + 4.0 / (double)nb), act, nb, [&] {
         varcoef_rbgs<T>(b, x, kf, dg, L.side, nb, L.cols, act, false, true, fold ? ec : nullptr,
                         omega_, s_);
       });
@@ -731,12 +731,12 @@ void Context::vcycle(int l, const T* b, T* x, int nb, const int* act, c64* rz_pa
     T* out = (pass % 2 == 0) ? tmp : x;
     const T* in = u;
     if (sw == 2 && i + sw == pre) {
-      timed<T>(kTimGs, en * (2.25 + (in ? 1.0 : 0.0)), act, nb, [&] {
+      timed<T>(l, kTimGs, en * (2.25 + (in ? 1.0 : 0.0)), act, nb, [&] {
         poisson_rbgs_restrict<T>(in, b, out, bc, L.side, L.d, L.c, nb, act, rows, s_);
       });
       restricted = true;
     } else {
-      timed<T>(kTimGs, en * (2.0 + (in ? 1.0 : 0.0)), act, nb, [&] {
+      timed<T>(l, kTimGs, en * (2.0 + (in ? 1.0 : 0.0)), act, nb, [&] {
         poisson_rbgs_fused<T>(in, b, out, nullptr, 0.0, L.side, L.d, L.c, nb, act, false,
                               nullptr, rows, sw, s_);
       });
@@ -747,7 +747,7 @@ void Context::vcycle(int l, const T* b, T* x, int nb, const int* act, c64* rz_pa
   if (u == nullptr)
     op_restrict<T>(l, b, bc, nb, act);
   else if (!restricted)
-    timed<T>(kTimResRestrict, 2.25 * en, act, nb,
+    timed<T>(l, kTimResRestrict, 2.25 * en, act, nb,
              [&] { op_res_restrict<T>(l, b, u, bc, nb, act); });
   vcycle<T>(l + 1, bc, ec, nb, act, nullptr);
   if (post == 0) {
@@ -770,7 +770,7 @@ void Context::vcycle(int l, const T* b, T* x, int nb, const int* act, c64* rz_pa
     const T* in = u;
     const T* corr = (pass == 0) ? ec : nullptr;
     const bool last = (pass == passes - 1);
-    timed<T>(kTimGs, en * (2.0 + (in ? 1.0 : 0.0) + (corr ? 0.25 : 0.0)), act, nb, [&] {
+    timed<T>(l, kTimGs, en * (2.0 + (in ? 1.0 : 0.0) + (corr ? 0.25 : 0.0)), act, nb, [&] {
       poisson_rbgs_fused<T>(in, b, out, corr, omega_, L.side, L.d, L.c, nb, act, true,
                             last ? rz_partials : nullptr, rows, sw, s_);
     });
@@ -852,12 +852,14 @@ void Context::collect_timing() {
   for (const Pending& p : pending_) {
     float ms = 0.f;
     MLMC_HIP(hipEventElapsedTime(&ms, p.a, p.b));
-    TimerStat& t = tstat_[p.slot];
     int count = 0;
     for (int k = 0; k < p.nb; ++k) count += flags[(size_t)p.idx * nb_ + k] ? 1 : 0;
-    t.launches += 1;
-    t.ms += ms;
-    t.bytes += p.bytes_per_col * count;
+    for (TimerStat* t : {&tstat_[p.slot], &tstat_lv_[p.slot][std::min(std::max(p.level, 1),
+                                                                      MLMC_MAX_LEVELS) - 1]}) {
+      t->launches += 1;
+      t->ms += ms;
+      t->bytes += p.bytes_per_col * count;
+    }
     ev_pool_.push_back(p.a);
     ev_pool_.push_back(p.b);
   }
@@ -865,10 +867,12 @@ void Context::collect_timing() {
   tlog_next_ = 0;
 }
 
-void Context::kernel_stats(int id, int fp64, double* out) {
+void Context::kernel_stats(int id, int fp64, double* out, int level) {
   collect_timing();
   MLMC_REQUIRE(id >= 0 && id < kNumTimers, MLMC_EINVAL, "unknown kernel id");
-  const TimerStat& t = tstat_[2 * id + (fp64 ? 1 : 0)];
+  MLMC_REQUIRE(level >= 0 && level <= Ls_, MLMC_EINVAL, "level out of range");
+  const int slot = 2 * id + (fp64 ? 1 : 0);
+  const TimerStat& t = level == 0 ? tstat_[slot] : tstat_lv_[slot][level - 1];
   out[0] = (double)t.launches;
   out[1] = t.ms;
   out[2] = t.bytes;
@@ -877,6 +881,8 @@ void Context::kernel_stats(int id, int fp64, double* out) {
 void Context::reset_kernel_stats() {
   collect_timing();
   for (TimerStat& t : tstat_) t = TimerStat();
+  for (auto& row : tstat_lv_)
+    for (TimerStat& t : row) t = TimerStat();
 }
 
 int Context::read_count() {
@@ -923,11 +929,11 @@ int Context::pcg(int l, const T* b, T* x, int nb, int* act, double tol, c64* las
   const int check = 2;
   int it = 0;
   for (it = 1; it <= opt_.max_iter; ++it) {
-    timed<T>(kTimApply, 4.0 * en, act, nb,
+    timed<T>(l, kTimApply, 4.0 * en, act, nb,
              [&] { op_update_apply<T>(l, p_old, w.z, beta, p_new, w.q, nb, act); });
     finish_alpha(partials_, ntiles, nb, tmp, rz, act, alpha, s_);
     if (lastcorr) cg_lastcorr(alpha, rz, act, lastcorr, nb, s_);
-    timed<T>(kTimCgXr, 6.0 * en, act, nb,
+    timed<T>(l, kTimCgXr, 6.0 * en, act, nb,
              [&] { cg_update_xr<T>(x, w.r, p_new, w.q, alpha, n, nb, act, partials_, s_); });
     finish_sums(partials_, nblk, nb, tmp, s_);
     mark_converged(tmp, rr0, tol * tol, act, nb, count_dev_, s_);
@@ -989,10 +995,10 @@ void Context::pcg_refined(int l, const double* b, double* y, int nb, double tol,
   // (|r|^2 lands in tmp only when a refinement check follows: otherwise the
   // next tail overwrites tmp unread)
   auto core = [&](float* p_old, float* p_new, bool checked) {
-    timed<float>(kTimApply, 4.0 * en, act, nb,
+    timed<float>(l, kTimApply, 4.0 * en, act, nb,
                  [&] { op_update_apply<float>(l, p_old, w.z, beta, p_new, w.q, nb, act); });
     finish_alpha(partials_, ntiles, nb, tmp, rz, act, alpha, s_);
-    timed<float>(kTimCgXr, 6.0 * en, act, nb,
+    timed<float>(l, kTimCgXr, 6.0 * en, act, nb,
                  [&] { cg_update_xr<float>(x32, r, p_new, w.q, alpha, n, nb, act, partials_, s_); });
     if (checked) finish_sums(partials_, nblk, nb, tmp, s_);
   };
@@ -1012,10 +1018,12 @@ void Context::pcg_refined(int l, const double* b, double* y, int nb, double tol,
   auto refine = [&](bool force) {
     MLMC_HIP(hipStreamSynchronize(s_));
     if (count_host_[1] == 0 && !force) return false;
-    // y += x32, bd = b^T x32, x32 = 0 in one pass
-    ir_fold(y, x32, b, n, nb, act, partials_, s_);
+    // y += x32, bd = b^T x32, x32 = 0 in one pass (FP64 y, b and FP32 x32 in;
+    // y, x32 out: 32 bytes per unknown)
+    timed<double>(l, kTimIrFold, 32.0 * (double)n, act, nb,
+                  [&] { ir_fold(y, x32, b, n, nb, act, partials_, s_); });
     finish_sums(partials_, nblk, nb, bd, s_);
-    timed<double>(kTimIrResidual, 20.0 * (double)n, act, nb, [&] {
+    timed<double>(l, kTimIrResidual, 20.0 * (double)n, act, nb, [&] {
       op_residual<double, double, float>(l, b, y, r, nb, act, partials_);
     });
     finish_sums(partials_, ntiles, nb, rr_new, s_);

@@ -265,7 +265,7 @@ void Context::cop_smooth(int l, const T* b, T* x, int nb, const int* act, bool z
     // by the second colour unless from zero), links once per launch
     const double es = 2.0 * sizeof(T) * (double)L.side * L.side;
     const double bytes = es * (zero_init ? 2.5 : 3.0) + es / (double)nb;
-    timed<T>(kTimGs, bytes, act, nb, [&] {
+    timed<T>(l, kTimGs, bytes, act, nb, [&] {
       wilson_rbgs<T>(b, x, links<T>(l), L.side, op_.mass + 2.0, nb, act, zero_init, reverse, s_);
     });
   } else {
@@ -273,7 +273,7 @@ void Context::cop_smooth(int l, const T* b, T* x, int nb, const int* act, bool z
     // site's 5 stencil blocks and inverted diagonal block once per launch
     const double es = (double)sizeof(T) * L.dof * (double)L.side * L.side;
     const double bytes = es * (zero_init ? 2.5 : 3.0) + 6.0 * L.dof * es / (double)nb;
-    timed<T>(kTimGs, bytes, act, nb, [&] {
+    timed<T>(l, kTimGs, bytes, act, nb, [&] {
       bsr_rbgs<T>(b, x, blocks<T>(l), dinv<T>(l), L.side, L.dof, nb, act, zero_init, reverse,
                   bsr_form<T>(L, nb), s_);
     });
@@ -306,7 +306,7 @@ void Context::cop_smooth_n(int l, const T* b, T* x, int nb, const int* act, int 
     T* dst = ((count - 1 - i) % 2 == 0) ? x : tmp;
     const T* src = z ? dst : (dst == x ? tmp : x);
     const double bytes = es * (z ? 2.0 : 3.0) + es / (double)nb;
-    timed<T>(kTimGs, bytes, act, nb, [&] {
+    timed<T>(l, kTimGs, bytes, act, nb, [&] {
       wilson_rbgs_fused<T>(b, src, dst, links<T>(l), L.side, op_.mass + 2.0, nb, act, z, reverse,
                            s_);
     });

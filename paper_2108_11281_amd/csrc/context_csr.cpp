@@ -617,7 +617,7 @@ void Context::vcycle_csr(int l, const T* b, T* x, int nb, const int* act, c64* r
     const int cols = csr_cols(L, nb);
     if (pre > 0) vec_zero<T>(x, n, nb, act, s_);
     for (int i = 0; i < pre; ++i)
-      timed<T>(kTimGs, 3.0 * en + sweep_mat / nb, act, nb,
+      timed<T>(l, kTimGs, 3.0 * en + sweep_mat / nb, act, nb,
                [&] { csr_gs_sweep<T>(b, x, S, (int)n, nb, cols, act, false, s_); });
     T* bc = w.vb[l];
     T* ec = w.vx[l];
@@ -627,28 +627,28 @@ void Context::vcycle_csr(int l, const T* b, T* x, int nb, const int* act, c64* r
       if (pre == 0) {
         csr_spmm<T>(b, bc, Rm, 1.0, 0.0, nb, cols, act, s_);
       } else {
-        timed<T>(kTimResRestrict, 2.0 * en + enc + res_mat / nb, act, nb, [&] {
+        timed<T>(l, kTimResRestrict, 2.0 * en + enc + res_mat / nb, act, nb, [&] {
           csr_residual<T, T, T>(b, x, w.vt[l - 1], A, nb, cols, act, nullptr, s_);
           csr_spmm<T>(w.vt[l - 1], bc, Rm, 1.0, 0.0, nb, cols, act, s_);
         });
       }
       vcycle_csr<T>(l + 1, bc, ec, nb, act, nullptr);
-      timed<T>(kTimProlong, (pre == 0 ? 1.0 : 2.0) * en + enc, act, nb, [&] {
+      timed<T>(l, kTimProlong, (pre == 0 ? 1.0 : 2.0) * en + enc, act, nb, [&] {
         csr_spmm<T>(ec, x, Pm, omega_, pre == 0 ? 0.0 : 1.0, nb, cols, act, s_);
       });
     } else {
       if (pre == 0)
         csr_restrict<T>(nullptr, b, bc, nullptr, A, G, nb, cols, act, s_);
       else  // the residual passes through the level's scratch vector
-        timed<T>(kTimResRestrict, 2.0 * en + enc + res_mat / nb, act, nb,
+        timed<T>(l, kTimResRestrict, 2.0 * en + enc + res_mat / nb, act, nb,
                  [&] { csr_restrict<T>(b, x, bc, w.vt[l - 1], A, G, nb, cols, act, s_); });
       vcycle_csr<T>(l + 1, bc, ec, nb, act, nullptr);
-      timed<T>(kTimProlong, (pre == 0 ? 1.0 : 2.0) * en + enc, act, nb, [&] {
+      timed<T>(l, kTimProlong, (pre == 0 ? 1.0 : 2.0) * en + enc, act, nb, [&] {
         csr_prolong<T>(ec, x, G, (int)n, omega_, pre == 0 ? 0.0 : 1.0, nb, act, s_);
       });
     }
     for (int i = 0; i < post; ++i)
-      timed<T>(kTimGs, 3.0 * en + sweep_mat / nb, act, nb,
+      timed<T>(l, kTimGs, 3.0 * en + sweep_mat / nb, act, nb,
                [&] { csr_gs_sweep<T>(b, x, S, (int)n, nb, cols, act, true, s_); });
   }
   if (rz_partials) vec_dot_partials<T>(b, x, n, nb, act, rz_partials, s_);

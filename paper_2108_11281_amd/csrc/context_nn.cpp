@@ -69,7 +69,7 @@ void Context::nn_step(const c32* b, c32* x, int nb, const int* act) {
   finish_sums(partials_, wilson_residual_blocks(L.side), nb, scal_[kNn], s_);
   // 2 x 4032 flops per site and column (three 3x3 convolutions, no bias)
   const double flops = 2.0 * nn_num_weights() * (double)L.side * L.side;
-  timed<c32>(kTimNn, flops, act, nb, [&] {
+  timed<c32>(1, kTimNn, flops, act, nb, [&] {
     nn_apply(res, x, scal_[kNn], 1.0 / (double)L.n, nn_links_, nn_frag_, L.side, nb, act, s_);
   });
   nn_stats[0] += 1;

@@ -825,8 +825,8 @@ void cg_update_p(T* p, const T* z, const c64* beta, int64_t n, int nb, const int
 void ir_fold(double* y, float* d, const double* b, int64_t n, int nb, const int* active,
              c64* partials, hipStream_t s) {
   if (n <= 0 || nb <= 0) return;
-  hipLaunchKernelGGL(k_ir_fold, dim3(reduce_blocks(n), nb), dim3(kThreads), 0, s, y, d, b, n,
-                     active, partials);
+  MLMC_LAUNCH(k_ir_fold, dim3(reduce_blocks(n), nb), dim3(kThreads), 0, s, y, d, b, n, active,
+              partials);
 }
 template <typename T64, typename T32>
 void ir_accumulate(T64* y, const T32* d, int64_t n, int nb, const int* active,
