@@ -247,7 +247,11 @@ int mlmc_hutchinson(void* ctx, double tol, uint64_t seed, mlmc_result* out);
  * or NULL: the stated FP64 error of each sample (relative to |x^H y| +
  * |(Rx)^H z|) -- the contribution of the last refinement correction, or the
  * final relative residual in MLMC_FP64 mode.  Any nsamples >= 1 is accepted
- * (split into launches of at most nb). */
+ * (split into launches of at most nb).  MLMC_ENOCONV when a solve misses
+ * solve_tol: out and out_err then hold every sample of the batches before the
+ * failing one and that batch's converged samples, NaN for its failed ones, and
+ * mlmc_last_error names the level whose solve failed, the first failed sample
+ * index and its column in the batch; later batches are not run. */
 int mlmc_sample_level(void* ctx, int level, uint64_t seed, int64_t first,
                       int64_t nsamples, double* out, double* out_err);
 
@@ -325,6 +329,20 @@ int mlmc_export_prolongation(void* ctx, int level, double* out);
  * kinds: MLMC_EUNSUPPORTED. */
 int mlmc_export_csr(void* ctx, int level, int64_t* nnz, int64_t* row_ptr, int32_t* col_idx,
                     double* vals, int32_t* agg, int32_t* colour);
+
+/* Any kind: level `level` of the hierarchy as the library holds it, as a sparse
+ * matrix in canonical compressed-row form (columns ascending, repeated entries
+ * summed, zero entries dropped).  which = 0: the operator A_l (1 <= l <= L_s,
+ * n_l x n_l; Sec. 4.1, A_{l+1} = R_l A_l P_l); which = 1: the prolongation P_l
+ * (1 <= l < L_s, n_l x n_{l+1}; R_l = P_l^H): orthonormal aggregation
+ * (2D Poisson: entries 1/2 on the 2 x 2 aggregates, 3D: 1/sqrt(8) on 2 x 2 x 2,
+ * matrix-given: 1/sqrt|J|), the test-vector bases of the lattice kinds (row i
+ * holds unknown i's coefficients in its aggregate's basis), or the given P.
+ * Outputs (host, each may be NULL = not written): rows, cols, nnz; row_ptr
+ * (rows + 1), col_idx (nnz), vals (nnz doubles, or 2 nnz interleaved (re, im)
+ * for the complex kinds).  Call once with NULL arrays for the sizes. */
+int mlmc_export_level(void* ctx, int level, int which, int64_t* rows, int64_t* cols,
+                      int64_t* nnz, int64_t* row_ptr, int32_t* col_idx, double* vals);
 
 /* Host-side estimator driver over a caller-supplied sampler (no device use).
  * sample(user, level, first, count, out): write count samples of level l as

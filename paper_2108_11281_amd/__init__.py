@@ -420,6 +420,26 @@ class TraceEstimator:
                                       int(first), int(nrhs), self._ptr(y)))
         return y
 
+    def export_level(self, level, which="A"):
+        """A_l (which="A") or P_l (which="P") as a scipy.sparse CSR matrix."""
+        import scipy.sparse as sp
+        w = 0 if which == "A" else 1
+        rows, cols, nnz = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        self._c(self._lib.mlmc_export_level(self._ctx, int(level), w, ctypes.byref(rows),
+                                            ctypes.byref(cols), ctypes.byref(nnz), None, None,
+                                            None))
+        rp = np.zeros(rows.value + 1, dtype=np.int64)
+        ci = np.zeros(nnz.value, dtype=np.int32)
+        v = np.zeros(nnz.value * (2 if self.is_complex else 1))
+        self._c(self._lib.mlmc_export_level(
+            self._ctx, int(level), w, None, None, None,
+            rp.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+            ci.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+            v.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        if self.is_complex:
+            v = v[0::2] + 1j * v[1::2]
+        return sp.csr_matrix((v, ci, rp), shape=(rows.value, cols.value))
+
     def export_csr(self, level):
         """Level `level` of a csr hierarchy: (scipy CSR matrix A_level, aggregate
         map, or None on the coarsest level and with given prolongations, colour

@@ -151,6 +151,8 @@ SIGNATURES = {
                                    ctypes.c_int64, ctypes.c_int, _P]),
     "mlmc_export_coarse": (ctypes.c_int, [_P, ctypes.c_int, _D]),
     "mlmc_export_prolongation": (ctypes.c_int, [_P, ctypes.c_int, _D]),
+    "mlmc_export_level": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _I64, _I64, _I64, _I64,
+                                         _I32, _D]),
     "mlmc_export_csr": (ctypes.c_int, [_P, ctypes.c_int, _I64, _I64, _I32, _D, _I32, _I32]),
     "mlmc_run_estimator": (ctypes.c_int, [ctypes.c_int, SAMPLE_FN, PILOT_FN, _P, _D, _D,
                                           ctypes.POINTER(Options), ctypes.c_double,

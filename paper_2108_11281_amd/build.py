@@ -23,6 +23,7 @@ SOURCES = [
     "context_nn.cpp",
     "context_csr.cpp",
     "context_defl.cpp",
+    "context_export.cpp",
     "estimator.cpp",
     "capi.cpp",
     "noalloc.cpp",

@@ -192,6 +192,15 @@ int mlmc_export_csr(void* c, int level, int64_t* nnz, int64_t* row_ptr, int32_t*
   return guarded(ctx, [&] { ctx->export_csr(level, nnz, row_ptr, col_idx, vals, agg, colour); });
 }
 
+int mlmc_export_level(void* c, int level, int which, int64_t* rows, int64_t* cols,
+                      int64_t* nnz, int64_t* row_ptr, int32_t* col_idx, double* vals) {
+  Context* ctx = as_ctx(c);
+  if (!ctx) return MLMC_EINVAL;
+  return guarded(ctx, [&] {
+    ctx->export_level(level, which, rows, cols, nnz, row_ptr, col_idx, vals);
+  });
+}
+
 int mlmc_run_estimator(int levels, mlmc_sample_fn sample, mlmc_pilot_fn pilot, void* user,
                        const double* coarse, const double* cost, const mlmc_options* opt,
                        double tol, mlmc_result* out) {

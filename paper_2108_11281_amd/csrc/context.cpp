@@ -1171,11 +1171,15 @@ void Context::solve(int l, const double* b, double* y, int nb, c64* err, double*
   MLMC_HIP(hipMemcpyAsync(host_c64_ + nb, bb, sizeof(c64) * nb, hipMemcpyDeviceToHost, s_));
   MLMC_HIP(hipStreamSynchronize(s_));
   bool ok = true;
+  col_ok_.assign((size_t)nb, 1);
   for (int k = 0; k < nb; ++k) {
     const double bn = host_c64_[nb + k].re;
     const double rel = bn > 0 ? std::sqrt(host_c64_[k].re / bn) : std::sqrt(host_c64_[k].re);
     if (relres_host) relres_host[k] = rel;
-    if (!(rel <= tol)) ok = false;
+    if (!(rel <= tol)) {
+      ok = false;
+      col_ok_[(size_t)k] = 0;
+    }
   }
   if (converged) *converged = ok;
 }
@@ -1231,8 +1235,10 @@ void Context::samples_batch(int level, uint64_t seed, uint64_t first, int nbatch
   bool ok1 = true, ok2 = true;
   c64 *e1 = scal_[kErr1], *e2 = scal_[kErr2], *qa = scal_[kQa], *qb = scal_[kQb];
   solve(level, b1_, y1_, nbatch, e1, nullptr, &ok1);
+  const std::vector<char> okc1 = col_ok_;
   restrict64(level, b1_, b2_, nbatch);
   solve(level + 1, b2_, y2_, nbatch, e2, nullptr, &ok2);
+  const std::vector<char> okc2 = col_ok_;
   // x^H y with x regenerated, and (Rx)^H z
   probe_quad(level, seed, kStreamProbe, first, nbatch, y1_, qa);
   if (complex_) {
@@ -1242,33 +1248,45 @@ void Context::samples_batch(int level, uint64_t seed, uint64_t first, int nbatch
     vec_dot_partials<double>(b2_, y2_, n2, nbatch, nullptr, partials_, s_);
   }
   finish_sums(partials_, reduce_blocks(n2), nbatch, qb, s_);
-  finish_samples(level, nbatch, ok1, ok2, out, err_out);
+  finish_samples(level, nbatch, okc1.data(), okc2.data(), first, out, err_out);
 }
 
 // copy the batch's scalars (stated errors e1, e2 and quadratic forms qa, qb,
 // consecutive blocks of nb_ entries) to the host, form s = qa - qb and the
 // relative stated errors; throw if a solve missed solve_tol
-void Context::finish_samples(int level, int nbatch, bool ok1, bool ok2, c64* out,
-                             double* err_out) {
+void Context::finish_samples(int level, int nbatch, const char* ok1, const char* ok2,
+                             uint64_t first, c64* out, double* err_out) {
   MLMC_HIP(hipMemcpyAsync(host_c64_, scal_[kErr1], sizeof(c64) * 4 * nb_,
                           hipMemcpyDeviceToHost, s_));
   MLMC_HIP(hipStreamSynchronize(s_));
   MLMC_HIP(hipGetLastError());
   const c64 *he1 = host_c64_, *he2 = host_c64_ + nb_, *ha = host_c64_ + 2 * nb_,
             *hb = host_c64_ + 3 * nb_;
+  int failed = 0, first_bad = -1, bad_level = 0;
   for (int k = 0; k < nbatch; ++k) {
     const c64 a = ha[k], b = hb[k];
-    out[k] = {a.re - b.re, a.im - b.im};
+    const bool ok = ok1[k] && (!ok2 || ok2[k]);
+    out[k] = ok ? c64{a.re - b.re, a.im - b.im} : c64{NAN, NAN};
     if (err_out) {
       const double den = std::hypot(a.re, a.im) + std::hypot(b.re, b.im);
       const double num = std::hypot(he1[k].re, he1[k].im) + std::hypot(he2[k].re, he2[k].im);
-      err_out[k] = den > 0 ? num / den : num;
+      err_out[k] = ok ? (den > 0 ? num / den : num) : NAN;
+    }
+    if (!ok) {
+      if (failed++ == 0) {
+        first_bad = k;
+        bad_level = ok1[k] ? level + 1 : level;
+      }
     }
   }
   counters[3] += 1;
-  if (!ok1 || !ok2)
-    throw Error(MLMC_ENOCONV, "solve on level " + std::to_string(ok1 ? level + 1 : level) +
-                                  " missed solve_tol");
+  if (failed > 0)
+    throw Error(MLMC_ENOCONV,
+                "level " + std::to_string(level) + " samples: the solve on level " +
+                    std::to_string(bad_level) + " missed solve_tol for sample " +
+                    std::to_string(first + (uint64_t)first_bad) + " (column " +
+                    std::to_string(first_bad) + " of a batch of " + std::to_string(nbatch) +
+                    "; " + std::to_string(failed) + " of the batch failed, their samples NaN)");
 }
 
 void Context::hutch_batch(uint64_t seed, uint64_t stream, uint64_t first, int nbatch,
@@ -1294,12 +1312,21 @@ void Context::sample_level(int level, uint64_t seed, int64_t first, int64_t coun
   std::vector<double> eb(nb_);
   for (int64_t j = 0; j < count; j += nb_) {
     const int nbt = (int)std::min<int64_t>(nb_, count - j);
-    samples_batch(level, seed, (uint64_t)(first + j), nbt, buf.data(), eb.data());
-    for (int k = 0; k < nbt; ++k) {
-      out[2 * (j + k)] = buf[k].re;
-      out[2 * (j + k) + 1] = buf[k].im;
-      if (out_err) out_err[j + k] = eb[k];
+    auto copy_out = [&] {
+      for (int k = 0; k < nbt; ++k) {
+        out[2 * (j + k)] = buf[k].re;
+        out[2 * (j + k) + 1] = buf[k].im;
+        if (out_err) out_err[j + k] = eb[k];
+      }
+    };
+    try {
+      samples_batch(level, seed, (uint64_t)(first + j), nbt, buf.data(), eb.data());
+    } catch (const Error& e) {
+      // partial results: the batches before, and this batch's converged samples
+      if (e.code == MLMC_ENOCONV) copy_out();
+      throw;
     }
+    copy_out();
   }
 }
 

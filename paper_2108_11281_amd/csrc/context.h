@@ -125,6 +125,8 @@ class Context {
   void export_prolongation(int level, double* out);
   void export_csr(int level, int64_t* nnz, int64_t* row_ptr, int32_t* col_idx, double* vals,
                   int32_t* agg, int32_t* colour);
+  void export_level(int level, int which, int64_t* rows, int64_t* cols, int64_t* nnz,
+                    int64_t* row_ptr, int32_t* col_idx, double* vals);
   // learned smoother (WILSON2D)
   void nn_train(const float* w_init, const mlmc_train_options& o, mlmc_train_report* rep);
   void nn_set_weights(const float* w);
@@ -178,7 +180,12 @@ class Context {
   void csr_general_coarse_trace();
   void samples_batch_general(int level, uint64_t seed, uint64_t first, int nbatch, c64* out,
                              double* err);
-  void finish_samples(int level, int nbatch, bool ok1, bool ok2, c64* out, double* err);
+  // per-column convergence of the two solves of a sample batch (ok2 may be null:
+  // no second solve); writes every sample (NaN where a solve missed solve_tol) and
+  // then throws MLMC_ENOCONV naming the level and the first failed sample
+  void finish_samples(int level, int nbatch, const char* ok1, const char* ok2, uint64_t first,
+                      c64* out, double* err);
+  std::vector<char> col_ok_;  // per column of the last solve(): met solve_tol
   void csr_upload(Level& L, bool last);
   void tune_csr();
   template <typename T> const CsrMat<T>& csr_mat(int l) const;

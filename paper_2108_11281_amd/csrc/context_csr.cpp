@@ -538,14 +538,16 @@ void Context::samples_batch_general(int level, uint64_t seed, uint64_t first, in
   bool ok1 = true, ok2 = true;
   c64 *e1 = scal_[kErr1], *e2 = scal_[kErr2], *qa = scal_[kQa], *qb = scal_[kQb];
   solve(level, bl, y1_, nbatch, e1, nullptr, &ok1);
+  const std::vector<char> okc1 = col_ok_;
   op_restrict<double>(level, bl, b2_, nbatch, nullptr);
   solve(level + 1, b2_, y2_, nbatch, e2, nullptr, &ok2);
+  const std::vector<char> okc2 = col_ok_;
   const int64_t nl = lv_[level - 1].n, nl1 = lv_[level].n;
   vec_dot_partials<double>(bl, y1_, nl, nbatch, nullptr, partials_, s_);
   finish_sums(partials_, reduce_blocks(nl), nbatch, qa, s_);
   vec_dot_partials<double>(b2_, y2_, nl1, nbatch, nullptr, partials_, s_);
   finish_sums(partials_, reduce_blocks(nl1), nbatch, qb, s_);
-  finish_samples(level, nbatch, ok1, ok2, out, err_out);
+  finish_samples(level, nbatch, okc1.data(), okc2.data(), first, out, err_out);
 }
 
 // Autotuner of the CSR kernels: per smoothed level, time one Gauss-Seidel

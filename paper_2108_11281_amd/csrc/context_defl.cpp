@@ -307,11 +307,12 @@ void Context::deflated_batch(uint64_t seed, uint64_t first, int nbatch, c64* out
   block_combine(defl_V_, defl_k_, defl_small_, nbatch, b1_, b1_, nbatch, n, -1.0, 1.0, s_);
   bool ok = true;
   solve(1, b1_, y1_, nbatch, scal_[kErr1], nullptr, &ok);
+  const std::vector<char> okc = col_ok_;
   // x^H A^{-1} x_perp with x regenerated
   probe_quad(1, seed, kStreamHutch, first, nbatch, y1_, scal_[kQa]);
   vec_zero<c64>(scal_[kErr2], 1, nbatch, nullptr, s_);
   vec_zero<c64>(scal_[kQb], 1, nbatch, nullptr, s_);
-  finish_samples(1, nbatch, ok, true, out, err_out);
+  finish_samples(1, nbatch, okc.data(), nullptr, first, out, err_out);
 }
 
 void Context::deflated_sample(uint64_t seed, int64_t first, int64_t count, double* out,
@@ -322,12 +323,20 @@ void Context::deflated_sample(uint64_t seed, int64_t first, int64_t count, doubl
   std::vector<double> eb(nb_);
   for (int64_t j = 0; j < count; j += nb_) {
     const int nbt = (int)std::min<int64_t>(nb_, count - j);
-    deflated_batch(seed, (uint64_t)(first + j), nbt, buf.data(), eb.data());
-    for (int i = 0; i < nbt; ++i) {
-      out[2 * (j + i)] = buf[i].re;
-      out[2 * (j + i) + 1] = buf[i].im;
-      if (out_err) out_err[j + i] = eb[i];
+    auto copy_out = [&] {
+      for (int i = 0; i < nbt; ++i) {
+        out[2 * (j + i)] = buf[i].re;
+        out[2 * (j + i) + 1] = buf[i].im;
+        if (out_err) out_err[j + i] = eb[i];
+      }
+    };
+    try {
+      deflated_batch(seed, (uint64_t)(first + j), nbt, buf.data(), eb.data());
+    } catch (const Error& e) {
+      if (e.code == MLMC_ENOCONV) copy_out();  // partial results
+      throw;
     }
+    copy_out();
   }
 }
 

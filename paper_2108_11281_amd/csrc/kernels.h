@@ -344,6 +344,10 @@ void galerkin_blocks(const c64* Bf, const c64* U, double wdiag, const c64* q, in
 void dense_from_stencil(const c64* Bf, const c64* U, double wdiag, int Nf, int dof, c64* aug,
                         hipStream_t s);
 void block_diag_inverse(const c64* B, c64* Dinv64, c32* Dinv32, int ns, int dof, hipStream_t s);
+// the 5 dof-blocks of every row of a block stencil (or the Wilson operator) as
+// column indices and values, 5 * dof entries per row, direction-major
+void stencil_entries(const c64* Bf, const c64* U, double wdiag, int Nf, int dof, int* cols,
+                     c64* vals, hipStream_t s);
 
 // ----- batched flexible GMRES helpers ------------------------------------------
 template <typename T>

@@ -262,20 +262,41 @@ __global__ void k_ir_acc(T64* y, const T32* d, int64_t n, const int* active) {
 // d = 0.  Per column k; blocks as in k_dot.
 __global__ __launch_bounds__(kThreads) void k_ir_fold(double* y, float* d, const double* b,
                                                       int64_t n, const int* active,
-                                                      c64* partials) {
+                                                      c64* partials, int* tlog) {
   __shared__ double lds[16];
   const int k = blockIdx.y, nblk = gridDim.x;
+  if (tlog && blockIdx.x == 0 && threadIdx.x == 0) tlog[k] = active ? active[k] : 1;
   if (active && !active[k]) return;
   const int64_t chunk = (n + nblk - 1) / nblk;
   const int64_t lo = (int64_t)blockIdx.x * chunk;
   const int64_t hi = lo + chunk < n ? lo + chunk : n;
   const int64_t off = (int64_t)k * n;
   double re = 0.0, im = 0.0;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += kThreads) {
-    const double di = (double)d[off + i];
-    y[off + i] = y[off + i] + di;
-    cdot_acc(re, im, b[off + i], di);
-    d[off + i] = 0.0f;
+  // groups of four elements per thread with every load issued before the
+  // arithmetic (twelve loads in flight); the dot accumulates in the order of a
+  // plain strided loop
+  constexpr int U = 4;
+  for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += U * kThreads) {
+    float dv[U];
+    double yv[U], bv[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const int64_t i = i0 + (int64_t)j * kThreads;
+      const bool ok = i < hi;
+      dv[j] = ok ? d[off + i] : 0.0f;
+      yv[j] = ok ? y[off + i] : 0.0;
+      bv[j] = ok ? b[off + i] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const int64_t i = i0 + (int64_t)j * kThreads;
+      if (i < hi) {
+        const double di = (double)dv[j];
+        y[off + i] = yv[j] + di;
+        cdot_acc(re, im, bv[j], di);
+        d[off + i] = 0.0f;
+      }
+    }
   }
   block_sum2<kThreads>(re, im, lds);
   if (threadIdx.x == 0) partials[(int64_t)k * nblk + blockIdx.x] = {re, im};
@@ -826,7 +847,7 @@ void ir_fold(double* y, float* d, const double* b, int64_t n, int nb, const int*
              c64* partials, hipStream_t s) {
   if (n <= 0 || nb <= 0) return;
   MLMC_LAUNCH(k_ir_fold, dim3(reduce_blocks(n), nb), dim3(kThreads), 0, s, y, d, b, n, active,
-              partials);
+              partials, timing_log());
 }
 template <typename T64, typename T32>
 void ir_accumulate(T64* y, const T32* d, int64_t n, int nb, const int* active,

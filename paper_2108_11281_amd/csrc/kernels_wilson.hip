@@ -774,6 +774,30 @@ __global__ void k_dense_from_stencil(const c64* __restrict__ Bf, const c64* __re
   }
 }
 
+// the 5 dof x dof blocks of row r = s * dof + a of a block stencil (or of the
+// Wilson operator) as column indices and values, 5 * dof entries per row in
+// direction-major order (repeated columns where a small periodic lattice wraps
+// a hop onto the same site; the host sums them)
+__global__ void k_stencil_entries(const c64* __restrict__ Bf, const c64* __restrict__ U,
+                                  double wdiag, int Nf, int dof, int* __restrict__ cols,
+                                  c64* __restrict__ vals) {
+  const int64_t n = (int64_t)Nf * Nf * dof;
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= n) return;
+  const int s = (int)(row / dof), a = (int)(row - (int64_t)s * dof);
+  const int sy = s / Nf, sx = s - sy * Nf;
+  int64_t e = row * 5 * dof;
+  for (int d = 0; d < 5; ++d) {
+    int tx, ty;
+    fine_hop_target(sx, sy, d, Nf, tx, ty);
+    const int t = ty * Nf + tx;
+    for (int bcol = 0; bcol < dof; ++bcol, ++e) {
+      cols[e] = t * dof + bcol;
+      vals[e] = fine_coupling(Bf, U, wdiag, Nf, dof, s, d, a, bcol);
+    }
+  }
+}
+
 // Dinv[S] = (B[S][0])^{-1} by Gauss-Jordan with partial pivoting in registers
 // of one thread per site (dof <= 16, FP64)
 template <int DOF>
@@ -975,6 +999,13 @@ void dense_from_stencil(const c64* Bf, const c64* U, double wdiag, int Nf, int d
   const int64_t n = (int64_t)Nf * Nf * dof;
   hipLaunchKernelGGL(k_dense_from_stencil, dim3((unsigned)n), dim3(256), 0, s, Bf, U, wdiag, Nf,
                      dof, aug);
+}
+
+void stencil_entries(const c64* Bf, const c64* U, double wdiag, int Nf, int dof, int* cols,
+                     c64* vals, hipStream_t s) {
+  const int64_t n = (int64_t)Nf * Nf * dof;
+  hipLaunchKernelGGL(k_stencil_entries, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, Bf,
+                     U, wdiag, Nf, dof, cols, vals);
 }
 
 void block_diag_inverse(const c64* B, c64* Dinv64, c32* Dinv32, int ns, int dof,
