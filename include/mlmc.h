@@ -39,6 +39,10 @@
 extern "C" {
 #endif
 
+/* Opaque context handle: the hierarchy, work buffers and solvers of one operator
+ * (created by mlmc_setup, released by mlmc_destroy). */
+typedef struct mlmc_ctx mlmc_ctx;
+
 enum mlmc_status {
   MLMC_OK = 0,
   MLMC_EINVAL = -1,       /* invalid argument or descriptor */
@@ -227,18 +231,18 @@ int mlmc_default_options(mlmc_options* opt);
  * coarsest operator with a zero pivot in its partially pivoted Gauss-Jordan
  * inverse), EDEVICE/ENOMEM from the runtime. */
 int mlmc_setup(const mlmc_operator* A, const mlmc_hierarchy* h,
-               const mlmc_options* opt, void* hip_stream, void** out_ctx);
+               const mlmc_options* opt, void* hip_stream, mlmc_ctx** out_ctx);
 
 /* MLMC estimate of tr(A^{-1}) to relative accuracy tol (Sec. 5): tau from five
  * pilot Hutchinson estimates (or opt.tau), per-level RMSD targets rho_l with
  * sum rho_l^2 = (tol*tau)^2, at least min_samples per level difference,
  * batches of at most nb samples, coarsest term exact.  Fills *out. */
-int mlmc_trace(void* ctx, double tol, uint64_t seed, mlmc_result* out);
+int mlmc_trace(mlmc_ctx* ctx, double tol, uint64_t seed, mlmc_result* out);
 
 /* Plain Hutchinson estimate (eq. plain_tr_estimate) on level 1 with the same
  * tau rule and batch rule, for comparison.  Fills trace, rmsd, tau,
  * n_samples[0], solves, seconds. */
-int mlmc_hutchinson(void* ctx, double tol, uint64_t seed, mlmc_result* out);
+int mlmc_hutchinson(mlmc_ctx* ctx, double tol, uint64_t seed, mlmc_result* out);
 
 /* Level-difference samples s_{l,k}, k = first .. first+nsamples-1:
  *   s = x^H A_l^{-1} x - (R_l x)^H A_{l+1}^{-1} (R_l x),  x = probe(seed, l, k),
@@ -252,25 +256,25 @@ int mlmc_hutchinson(void* ctx, double tol, uint64_t seed, mlmc_result* out);
  * failing one and that batch's converged samples, NaN for its failed ones, and
  * mlmc_last_error names the level whose solve failed, the first failed sample
  * index and its column in the batch; later batches are not run. */
-int mlmc_sample_level(void* ctx, int level, uint64_t seed, int64_t first,
+int mlmc_sample_level(mlmc_ctx* ctx, int level, uint64_t seed, int64_t first,
                       int64_t nsamples, double* out, double* out_err);
 
 /* tr(A_L^{-1}) computed at setup by inverting A_L (Remark 4.2). out: 2 doubles. */
-int mlmc_coarse_trace(void* ctx, double* out);
+int mlmc_coarse_trace(mlmc_ctx* ctx, double* out);
 
 /* n_l, the number of unknowns of level l (1 <= l <= L_s). */
-int mlmc_level_size(void* ctx, int level, int64_t* n);
+int mlmc_level_size(mlmc_ctx* ctx, int level, int64_t* n);
 
 /* Y = A_l^{-1} B for nrhs <= nb vectors: the solver used by the samples
  * (precision and tolerance from the options).  b_dev, y_dev: FP64 (complex:
  * interleaved) RHS-major blocks of nrhs vectors of n_l.  relres: host, nrhs
  * doubles or NULL, final FP64 relative residuals.  ENOCONV if a column misses
  * solve_tol within max_refine x max_iter. */
-int mlmc_solve(void* ctx, int level, int nrhs, const double* b_dev,
+int mlmc_solve(mlmc_ctx* ctx, int level, int nrhs, const double* b_dev,
                double* y_dev, double* relres);
 
 /* Y = A_l X in FP64 (the FP64 operator of level l). */
-int mlmc_apply(void* ctx, int level, int nrhs, const double* x_dev, double* y_dev);
+int mlmc_apply(mlmc_ctx* ctx, int level, int nrhs, const double* x_dev, double* y_dev);
 
 /* Flags of mlmc_smooth. */
 enum mlmc_smooth_flags {
@@ -296,29 +300,29 @@ enum mlmc_smooth_flags {
  * 1 <= l < L_s; sweeps >= 0.  The library allocates and frees
  * working-precision copies during the call (see mlmc_smooth_noalloc for the
  * allocation-free form).  For tests and inspection. */
-int mlmc_smooth(void* ctx, int level, int nrhs, int sweeps, int flags, const double* b_dev,
+int mlmc_smooth(mlmc_ctx* ctx, int level, int nrhs, int sweeps, int flags, const double* b_dev,
                 double* x_dev, double* rc_dev);
 
 /* Xc = R_l X = P_l^H X (restriction to level l+1), FP64, 1 <= l < L_s. */
-int mlmc_restrict(void* ctx, int level, int nrhs, const double* x_dev, double* xc_dev);
+int mlmc_restrict(mlmc_ctx* ctx, int level, int nrhs, const double* x_dev, double* xc_dev);
 
 /* X = P_l Xc (prolongation from level l+1), FP64, 1 <= l < L_s. */
-int mlmc_prolong(void* ctx, int level, int nrhs, const double* xc_dev, double* x_dev);
+int mlmc_prolong(mlmc_ctx* ctx, int level, int nrhs, const double* xc_dev, double* x_dev);
 
 /* Probe block: vectors k = first..first+nrhs-1 of level l, stream `stream`
  * (0 level probes, 1 pilot, 3 Hutchinson), written as FP64 (complex:
  * interleaved) to out_dev [nrhs][n_l]. */
-int mlmc_probes(void* ctx, int level, uint64_t seed, int stream, int64_t first,
+int mlmc_probes(mlmc_ctx* ctx, int level, uint64_t seed, int stream, int64_t first,
                 int nrhs, double* out_dev);
 
 /* Copy the dense FP64 coarsest operator A_{L_s} (or A_L if which == 1) to host
  * memory, n x n row-major (complex: interleaved).  For inspection and tests. */
-int mlmc_export_coarse(void* ctx, int which, double* out);
+int mlmc_export_coarse(mlmc_ctx* ctx, int which, double* out);
 
 /* WILSON2D: copy the aggregation basis of level l (1 <= l < L_s) to host memory
  * as n_l x n_vec complex values: row i holds the n_vec coefficients of unknown
  * i in the basis of its aggregate (Example 4.3 aggregation sketch). */
-int mlmc_export_prolongation(void* ctx, int level, double* out);
+int mlmc_export_prolongation(mlmc_ctx* ctx, int level, double* out);
 
 /* MLMC_CSR: level `level` (1..L_s) of the hierarchy as the library holds it
  * (Sec. 4.1: A_{l+1} = P_l^T A_l P_l).  *nnz receives its entry count; row_ptr
@@ -327,7 +331,7 @@ int mlmc_export_prolongation(void* ctx, int level, double* out);
  * aggregate of every unknown; colour (n_l) its first-fit colour class, the
  * Gauss-Seidel order.  Host arrays, each may be NULL (not written).  Other
  * kinds: MLMC_EUNSUPPORTED. */
-int mlmc_export_csr(void* ctx, int level, int64_t* nnz, int64_t* row_ptr, int32_t* col_idx,
+int mlmc_export_csr(mlmc_ctx* ctx, int level, int64_t* nnz, int64_t* row_ptr, int32_t* col_idx,
                     double* vals, int32_t* agg, int32_t* colour);
 
 /* Any kind: level `level` of the hierarchy as the library holds it, as a sparse
@@ -341,7 +345,7 @@ int mlmc_export_csr(void* ctx, int level, int64_t* nnz, int64_t* row_ptr, int32_
  * Outputs (host, each may be NULL = not written): rows, cols, nnz; row_ptr
  * (rows + 1), col_idx (nnz), vals (nnz doubles, or 2 nnz interleaved (re, im)
  * for the complex kinds).  Call once with NULL arrays for the sizes. */
-int mlmc_export_level(void* ctx, int level, int which, int64_t* rows, int64_t* cols,
+int mlmc_export_level(mlmc_ctx* ctx, int level, int which, int64_t* rows, int64_t* cols,
                       int64_t* nnz, int64_t* row_ptr, int32_t* col_idx, double* vals);
 
 /* Host-side estimator driver over a caller-supplied sampler (no device use).
@@ -373,14 +377,14 @@ int mlmc_set_allocator(mlmc_alloc_fn alloc, mlmc_free_fn free_fn, void* user);
  * (re, im), problem-major; seconds (nullable): wall time per problem.  Every
  * context must be distinct; level must be sampleable on all of them.
  * Returns the first failing problem's status (its context holds the message). */
-int mlmc_batch_sample(void* const* ctxs, int count, int level, const uint64_t* seeds,
+int mlmc_batch_sample(mlmc_ctx* const* ctxs, int count, int level, const uint64_t* seeds,
                       int64_t first, int64_t nsamples, int workers, double* out,
                       double* seconds);
 
 /* Counters of the last mlmc_trace / mlmc_sample_level / mlmc_solve call:
  * out[0] Krylov iterations (per batch), out[1] refinement steps,
  * out[2] V-cycles, out[3] batches.  n: entries to copy (<= 4). */
-int mlmc_counters(void* ctx, int64_t* out, int n);
+int mlmc_counters(mlmc_ctx* ctx, int64_t* out, int n);
 
 /* Measurement mode.  mask: bit i set = launches of kernel id i (listed
  * below) are bracketed by HIP events on the context stream and record their
@@ -391,7 +395,7 @@ int mlmc_counters(void* ctx, int64_t* out, int n);
  * sample does not alias with the launch pattern of the V-cycle), which bounds
  * the cost of the two event records per timed launch.
  * Returns MLMC_EINVAL for stride < 1. */
-int mlmc_set_timing(void* ctx, int mask, int stride);
+int mlmc_set_timing(mlmc_ctx* ctx, int mask, int stride);
 
 /* Kernel ids for mlmc_kernel_stats (algorithmic bytes per unknown and RHS for
  * element size e; each operator kind reports its own smoother, residual and
@@ -407,11 +411,11 @@ int mlmc_set_timing(void* ctx, int mask, int stride);
  * in, FP32 r out; fp64 slot).  fp64 = 0 selects the FP32/complex64
  * instantiation, 1 the FP64 one.  out: launches, total milliseconds, total
  * algorithmic bytes (active columns only). */
-int mlmc_kernel_stats(void* ctx, int kernel, int fp64, double* out);
+int mlmc_kernel_stats(mlmc_ctx* ctx, int kernel, int fp64, double* out);
 /* The same restricted to the launches on one level (1 <= level <= L_s; 0 = all
  * levels, as mlmc_kernel_stats). */
-int mlmc_kernel_stats_level(void* ctx, int kernel, int fp64, int level, double* out);
-int mlmc_reset_kernel_stats(void* ctx);
+int mlmc_kernel_stats_level(mlmc_ctx* ctx, int kernel, int fp64, int level, double* out);
+int mlmc_reset_kernel_stats(mlmc_ctx* ctx);
 
 /* ---------------------------------------------------------------------------
  * Learned smoother (WILSON2D).  A 3-layer network of 3x3 periodic convolutions
@@ -461,21 +465,21 @@ typedef struct mlmc_train_report {
  * `seed`.  w_init: host MLMC_NN_WEIGHTS initial weights.  The trained weights
  * stay in ctx.  Errors: MLMC_EUNSUPPORTED for kinds other than WILSON2D or a
  * lattice side not a multiple of 16; MLMC_EINVAL for bad options. */
-int mlmc_learned_train(void* ctx, const float* w_init, const mlmc_train_options* opt,
+int mlmc_learned_train(mlmc_ctx* ctx, const float* w_init, const mlmc_train_options* opt,
                        mlmc_train_report* out);
 /* Set / read the network weights (host arrays of MLMC_NN_WEIGHTS floats). */
-int mlmc_learned_set_weights(void* ctx, const float* w);
-int mlmc_learned_get_weights(void* ctx, float* w);
+int mlmc_learned_set_weights(mlmc_ctx* ctx, const float* w);
+int mlmc_learned_get_weights(mlmc_ctx* ctx, float* w);
 /* out[0] network applications (launches) and out[1] fallbacks to the plain
  * smoother since setup. */
-int mlmc_learned_stats(void* ctx, int64_t* out);
+int mlmc_learned_stats(mlmc_ctx* ctx, int64_t* out);
 /* Building blocks for tests.  mlmc_nn_apply: e = correction of the network for
  * residuals r (device, nrhs x n_1 complex as interleaved FP64, level 1).
  * mlmc_nn_loss_grad: mean squared error and its gradient (host, FP32
  * MLMC_NN_WEIGHTS) over ncrops crops: in device FP32 [ncrops][22][22][8]
  * (rounded to BF16), target device FP32 [ncrops][16][16][4]. */
-int mlmc_nn_apply(void* ctx, int nrhs, const double* r, double* e);
-int mlmc_nn_loss_grad(void* ctx, int ncrops, const float* in, const float* target, double* loss,
+int mlmc_nn_apply(mlmc_ctx* ctx, int nrhs, const double* r, double* e);
+int mlmc_nn_loss_grad(mlmc_ctx* ctx, int ncrops, const float* in, const float* target, double* loss,
                       float* grad);
 
 /* mlmc_nn_crops: the training-pair builder of mlmc_learned_train on given data.
@@ -490,9 +494,9 @@ int mlmc_nn_loss_grad(void* ctx, int ncrops, const float* in, const float* targe
  * 1e-8, bias-corrected with step count t >= 1) of the FP32 master weights with
  * the given gradient (host FP32, MLMC_NN_WEIGHTS); t == 1 first zeroes the
  * moments; the inference fragments are re-packed.  ESTATE without weights. */
-int mlmc_nn_crops(void* ctx, int nrhs, const double* r, const double* e, int ncrops,
+int mlmc_nn_crops(mlmc_ctx* ctx, int nrhs, const double* r, const double* e, int ncrops,
                   const int32_t* origin, float* in, float* target);
-int mlmc_nn_adam_step(void* ctx, const float* grad, double lr, int t);
+int mlmc_nn_adam_step(mlmc_ctx* ctx, const float* grad, double lr, int t);
 
 /* ---------------------------------------------------------------------------
  * Allocation-free entry point, for callers that cannot allocate device memory
@@ -512,7 +516,7 @@ int mlmc_nn_adam_step(void* ctx, const float* grad, double lr, int t);
  * ordered and safe.
  * ------------------------------------------------------------------------- */
 #define MLMC_NOALLOC_SCRATCH_BYTES (64u << 20)
-int mlmc_smooth_noalloc(void* ctx, int level, int nrhs, int sweeps, int flags,
+int mlmc_smooth_noalloc(mlmc_ctx* ctx, int level, int nrhs, int sweeps, int flags,
                         const double* b_dev, double* x_dev, double* rc_dev);
 
 /* ---------------------------------------------------------------------------
@@ -550,31 +554,31 @@ typedef struct mlmc_deflation_report {
  * with a Jacobi eigensolver on the (k+p) x (k+p) projected matrix) and the
  * direct term.  Replaces an earlier deflation space.  ENOCONV if a solve fails;
  * the Ritz residuals reached are reported even when max_iter ran out. */
-int mlmc_deflation_setup(void* ctx, const mlmc_deflation_options* opt,
+int mlmc_deflation_setup(mlmc_ctx* ctx, const mlmc_deflation_options* opt,
                          mlmc_deflation_report* report);
 /* Deflated samples x_k^H A^{-1} (I - Pi) x_k, k = first..first+nsamples-1, as
  * (re, im) pairs in out (host, nsamples x 2); out_err (nullable): stated FP64
  * error per sample as for mlmc_sample_level.  ESTATE before mlmc_deflation_setup. */
-int mlmc_deflated_sample(void* ctx, uint64_t seed, int64_t first, int64_t nsamples,
+int mlmc_deflated_sample(mlmc_ctx* ctx, uint64_t seed, int64_t first, int64_t nsamples,
                          double* out, double* out_err);
 /* Deflated Hutchinson estimate to relative accuracy tol with the control of
  * Sec. 5 (tau from the five plain pilot estimates, samples until their RMSD is
  * at most tol * tau, batches of at most nb).  trace = sample mean + direct term;
  * coarse_trace holds the direct term; n_samples[0] the sample count. */
-int mlmc_deflated_hutchinson(void* ctx, double tol, uint64_t seed, mlmc_result* out);
+int mlmc_deflated_hutchinson(mlmc_ctx* ctx, double tol, uint64_t seed, mlmc_result* out);
 /* Copy the deflation space: eigenvalues (host, k Ritz values ascending, or
  * NULL), vectors_dev (device, k x n_1 FP64 RHS-major, or NULL), direct (host,
  * 1 double, or NULL). */
-int mlmc_deflation_export(void* ctx, double* eigenvalues, double* vectors_dev, double* direct);
+int mlmc_deflation_export(mlmc_ctx* ctx, double* eigenvalues, double* vectors_dev, double* direct);
 
 /* Description of the last error on ctx (or of the last failed mlmc_setup
  * when ctx is NULL).  Valid until the next call on ctx. */
-const char* mlmc_last_error(const void* ctx);
+const char* mlmc_last_error(const mlmc_ctx* ctx);
 
 const char* mlmc_status_string(int status);
 
 /* Free everything the context owns.  NULL is ignored. */
-void mlmc_destroy(void* ctx);
+void mlmc_destroy(mlmc_ctx* ctx);
 
 #ifdef __cplusplus
 }

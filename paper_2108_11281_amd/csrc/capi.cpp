@@ -39,7 +39,9 @@ int guarded(Context* ctx, F&& f) {
   }
 }
 
-Context* as_ctx(void* p) { return static_cast<Context*>(p); }
+// the opaque handle of the C ABI is the context object itself
+Context* as_ctx(mlmc_ctx* p) { return reinterpret_cast<Context*>(p); }
+mlmc_ctx* as_handle(Context* p) { return reinterpret_cast<mlmc_ctx*>(p); }
 
 }  // namespace
 
@@ -70,7 +72,7 @@ int mlmc_default_options(mlmc_options* opt) {
 }
 
 int mlmc_setup(const mlmc_operator* A, const mlmc_hierarchy* h, const mlmc_options* opt,
-               void* hip_stream, void** out_ctx) {
+               void* hip_stream, mlmc_ctx** out_ctx) {
   if (!out_ctx) return MLMC_EINVAL;
   *out_ctx = nullptr;
   if (!A || !h) {
@@ -87,30 +89,30 @@ int mlmc_setup(const mlmc_operator* A, const mlmc_hierarchy* h, const mlmc_optio
     // points, looked up once per device while it is current
     mlmc::noalloc_init(ctx->device());
   });
-  if (rc == MLMC_OK) *out_ctx = ctx;
+  if (rc == MLMC_OK) *out_ctx = as_handle(ctx);
   return rc;
 }
 
-int mlmc_trace(void* c, double tol, uint64_t seed, mlmc_result* out) {
+int mlmc_trace(mlmc_ctx* c, double tol, uint64_t seed, mlmc_result* out) {
   Context* ctx = as_ctx(c);
   if (!ctx || !out) return MLMC_EINVAL;
   return guarded(ctx, [&] { ctx->trace(tol, seed, out); });
 }
 
-int mlmc_hutchinson(void* c, double tol, uint64_t seed, mlmc_result* out) {
+int mlmc_hutchinson(mlmc_ctx* c, double tol, uint64_t seed, mlmc_result* out) {
   Context* ctx = as_ctx(c);
   if (!ctx || !out) return MLMC_EINVAL;
   return guarded(ctx, [&] { ctx->hutchinson(tol, seed, out); });
 }
 
-int mlmc_sample_level(void* c, int level, uint64_t seed, int64_t first, int64_t nsamples,
+int mlmc_sample_level(mlmc_ctx* c, int level, uint64_t seed, int64_t first, int64_t nsamples,
                       double* out, double* out_err) {
   Context* ctx = as_ctx(c);
   if (!ctx || !out) return MLMC_EINVAL;
   return guarded(ctx, [&] { ctx->sample_level(level, seed, first, nsamples, out, out_err); });
 }
 
-int mlmc_coarse_trace(void* c, double* out) {
+int mlmc_coarse_trace(mlmc_ctx* c, double* out) {
   Context* ctx = as_ctx(c);
   if (!ctx || !out) return MLMC_EINVAL;
   out[0] = ctx->coarse_trace_re();
@@ -118,7 +120,7 @@ int mlmc_coarse_trace(void* c, double* out) {
   return MLMC_OK;
 }
 
-int mlmc_level_size(void* c, int level, int64_t* n) {
+int mlmc_level_size(mlmc_ctx* c, int level, int64_t* n) {
   Context* ctx = as_ctx(c);
   if (!ctx || !n) return MLMC_EINVAL;
   if (level < 1 || level > ctx->levels_solver()) {
@@ -129,20 +131,20 @@ int mlmc_level_size(void* c, int level, int64_t* n) {
   return MLMC_OK;
 }
 
-int mlmc_solve(void* c, int level, int nrhs, const double* b_dev, double* y_dev,
+int mlmc_solve(mlmc_ctx* c, int level, int nrhs, const double* b_dev, double* y_dev,
                double* relres) {
   Context* ctx = as_ctx(c);
   if (!ctx || !b_dev || !y_dev) return MLMC_EINVAL;
   return guarded(ctx, [&] { ctx->solve_fp64(level, nrhs, b_dev, y_dev, relres, true); });
 }
 
-int mlmc_apply(void* c, int level, int nrhs, const double* x_dev, double* y_dev) {
+int mlmc_apply(mlmc_ctx* c, int level, int nrhs, const double* x_dev, double* y_dev) {
   Context* ctx = as_ctx(c);
   if (!ctx || !x_dev || !y_dev) return MLMC_EINVAL;
   return guarded(ctx, [&] { ctx->apply_fp64(level, nrhs, x_dev, y_dev); });
 }
 
-int mlmc_smooth(void* c, int level, int nrhs, int sweeps, int flags, const double* b_dev,
+int mlmc_smooth(mlmc_ctx* c, int level, int nrhs, int sweeps, int flags, const double* b_dev,
                 double* x_dev, double* rc_dev) {
   Context* ctx = as_ctx(c);
   if (!ctx || !b_dev || !x_dev) return MLMC_EINVAL;
@@ -154,45 +156,45 @@ int mlmc_smooth(void* c, int level, int nrhs, int sweeps, int flags, const doubl
   });
 }
 
-int mlmc_restrict(void* c, int level, int nrhs, const double* x_dev, double* xc_dev) {
+int mlmc_restrict(mlmc_ctx* c, int level, int nrhs, const double* x_dev, double* xc_dev) {
   Context* ctx = as_ctx(c);
   if (!ctx || !x_dev || !xc_dev) return MLMC_EINVAL;
   return guarded(ctx, [&] { ctx->restrict_fp64(level, nrhs, x_dev, xc_dev); });
 }
 
-int mlmc_prolong(void* c, int level, int nrhs, const double* xc_dev, double* x_dev) {
+int mlmc_prolong(mlmc_ctx* c, int level, int nrhs, const double* xc_dev, double* x_dev) {
   Context* ctx = as_ctx(c);
   if (!ctx || !x_dev || !xc_dev) return MLMC_EINVAL;
   return guarded(ctx, [&] { ctx->prolong_fp64(level, nrhs, xc_dev, x_dev); });
 }
 
-int mlmc_probes(void* c, int level, uint64_t seed, int stream, int64_t first, int nrhs,
+int mlmc_probes(mlmc_ctx* c, int level, uint64_t seed, int stream, int64_t first, int nrhs,
                 double* out_dev) {
   Context* ctx = as_ctx(c);
   if (!ctx || !out_dev) return MLMC_EINVAL;
   return guarded(ctx, [&] { ctx->probes_fp64(level, seed, stream, first, nrhs, out_dev); });
 }
 
-int mlmc_export_coarse(void* c, int which, double* out) {
+int mlmc_export_coarse(mlmc_ctx* c, int which, double* out) {
   Context* ctx = as_ctx(c);
   if (!ctx || !out) return MLMC_EINVAL;
   return guarded(ctx, [&] { ctx->export_coarse(which, out); });
 }
 
-int mlmc_export_prolongation(void* c, int level, double* out) {
+int mlmc_export_prolongation(mlmc_ctx* c, int level, double* out) {
   Context* ctx = as_ctx(c);
   if (!ctx || !out) return MLMC_EINVAL;
   return guarded(ctx, [&] { ctx->export_prolongation(level, out); });
 }
 
-int mlmc_export_csr(void* c, int level, int64_t* nnz, int64_t* row_ptr, int32_t* col_idx,
+int mlmc_export_csr(mlmc_ctx* c, int level, int64_t* nnz, int64_t* row_ptr, int32_t* col_idx,
                     double* vals, int32_t* agg, int32_t* colour) {
   Context* ctx = as_ctx(c);
   if (!ctx || !nnz) return MLMC_EINVAL;
   return guarded(ctx, [&] { ctx->export_csr(level, nnz, row_ptr, col_idx, vals, agg, colour); });
 }
 
-int mlmc_export_level(void* c, int level, int which, int64_t* rows, int64_t* cols,
+int mlmc_export_level(mlmc_ctx* c, int level, int which, int64_t* rows, int64_t* cols,
                       int64_t* nnz, int64_t* row_ptr, int32_t* col_idx, double* vals) {
   Context* ctx = as_ctx(c);
   if (!ctx) return MLMC_EINVAL;
@@ -244,7 +246,7 @@ int mlmc_set_allocator(mlmc_alloc_fn alloc, mlmc_free_fn free_fn, void* user) {
   return MLMC_OK;
 }
 
-int mlmc_learned_train(void* c, const float* w_init, const mlmc_train_options* opt,
+int mlmc_learned_train(mlmc_ctx* c, const float* w_init, const mlmc_train_options* opt,
                        mlmc_train_report* out) {
   Context* ctx = as_ctx(c);
   if (!ctx || !w_init || !opt) return MLMC_EINVAL;
@@ -255,7 +257,7 @@ int mlmc_learned_train(void* c, const float* w_init, const mlmc_train_options* o
   });
 }
 
-int mlmc_learned_set_weights(void* c, const float* w) {
+int mlmc_learned_set_weights(mlmc_ctx* c, const float* w) {
   Context* ctx = as_ctx(c);
   if (!ctx || !w) return MLMC_EINVAL;
   return guarded(ctx, [&] {
@@ -265,13 +267,13 @@ int mlmc_learned_set_weights(void* c, const float* w) {
   });
 }
 
-int mlmc_learned_get_weights(void* c, float* w) {
+int mlmc_learned_get_weights(mlmc_ctx* c, float* w) {
   Context* ctx = as_ctx(c);
   if (!ctx || !w) return MLMC_EINVAL;
   return guarded(ctx, [&] { ctx->nn_get_weights(w); });
 }
 
-int mlmc_learned_stats(void* c, int64_t* out) {
+int mlmc_learned_stats(mlmc_ctx* c, int64_t* out) {
   Context* ctx = as_ctx(c);
   if (!ctx || !out) return MLMC_EINVAL;
   out[0] = ctx->nn_stats[0];
@@ -279,27 +281,27 @@ int mlmc_learned_stats(void* c, int64_t* out) {
   return MLMC_OK;
 }
 
-int mlmc_nn_apply(void* c, int nrhs, const double* r, double* e) {
+int mlmc_nn_apply(mlmc_ctx* c, int nrhs, const double* r, double* e) {
   Context* ctx = as_ctx(c);
   if (!ctx || !r || !e) return MLMC_EINVAL;
   return guarded(ctx, [&] { ctx->nn_apply_fp64(nrhs, r, e); });
 }
 
-int mlmc_nn_loss_grad(void* c, int ncrops, const float* in, const float* target, double* loss,
+int mlmc_nn_loss_grad(mlmc_ctx* c, int ncrops, const float* in, const float* target, double* loss,
                       float* grad) {
   Context* ctx = as_ctx(c);
   if (!ctx || !in || !target || !loss || !grad) return MLMC_EINVAL;
   return guarded(ctx, [&] { ctx->nn_loss_grad(ncrops, in, target, loss, grad); });
 }
 
-int mlmc_nn_crops(void* c, int nrhs, const double* r, const double* e, int ncrops,
+int mlmc_nn_crops(mlmc_ctx* c, int nrhs, const double* r, const double* e, int ncrops,
                   const int32_t* origin, float* in, float* target) {
   Context* ctx = as_ctx(c);
   if (!ctx || !r || !e || !origin || !in || !target) return MLMC_EINVAL;
   return guarded(ctx, [&] { ctx->nn_crops_fp64(nrhs, r, e, ncrops, origin, in, target); });
 }
 
-int mlmc_nn_adam_step(void* c, const float* grad, double lr, int t) {
+int mlmc_nn_adam_step(mlmc_ctx* c, const float* grad, double lr, int t) {
   Context* ctx = as_ctx(c);
   if (!ctx || !grad) return MLMC_EINVAL;
   return guarded(ctx, [&] {
@@ -309,33 +311,33 @@ int mlmc_nn_adam_step(void* c, const float* grad, double lr, int t) {
   });
 }
 
-int mlmc_deflation_setup(void* c, const mlmc_deflation_options* opt,
+int mlmc_deflation_setup(mlmc_ctx* c, const mlmc_deflation_options* opt,
                          mlmc_deflation_report* report) {
   Context* ctx = as_ctx(c);
   if (!ctx || !opt) return MLMC_EINVAL;
   return guarded(ctx, [&] { ctx->deflation_setup(*opt, report); });
 }
 
-int mlmc_deflated_sample(void* c, uint64_t seed, int64_t first, int64_t nsamples, double* out,
+int mlmc_deflated_sample(mlmc_ctx* c, uint64_t seed, int64_t first, int64_t nsamples, double* out,
                          double* out_err) {
   Context* ctx = as_ctx(c);
   if (!ctx || !out) return MLMC_EINVAL;
   return guarded(ctx, [&] { ctx->deflated_sample(seed, first, nsamples, out, out_err); });
 }
 
-int mlmc_deflated_hutchinson(void* c, double tol, uint64_t seed, mlmc_result* out) {
+int mlmc_deflated_hutchinson(mlmc_ctx* c, double tol, uint64_t seed, mlmc_result* out) {
   Context* ctx = as_ctx(c);
   if (!ctx || !out) return MLMC_EINVAL;
   return guarded(ctx, [&] { ctx->deflated_hutchinson(tol, seed, out); });
 }
 
-int mlmc_deflation_export(void* c, double* eigenvalues, double* vectors_dev, double* direct) {
+int mlmc_deflation_export(mlmc_ctx* c, double* eigenvalues, double* vectors_dev, double* direct) {
   Context* ctx = as_ctx(c);
   if (!ctx) return MLMC_EINVAL;
   return guarded(ctx, [&] { ctx->deflation_export(eigenvalues, vectors_dev, direct); });
 }
 
-int mlmc_batch_sample(void* const* ctxs, int count, int level, const uint64_t* seeds,
+int mlmc_batch_sample(mlmc_ctx* const* ctxs, int count, int level, const uint64_t* seeds,
                       int64_t first, int64_t nsamples, int workers, double* out,
                       double* seconds) {
   if (!ctxs || count < 1 || !seeds || !out || nsamples < 1 || first < 0 || workers < 1)
@@ -383,39 +385,39 @@ int mlmc_batch_sample(void* const* ctxs, int count, int level, const uint64_t* s
   return MLMC_OK;
 }
 
-int mlmc_counters(void* c, int64_t* out, int n) {
+int mlmc_counters(mlmc_ctx* c, int64_t* out, int n) {
   Context* ctx = as_ctx(c);
   if (!ctx || !out || n < 0 || n > 4) return MLMC_EINVAL;
   for (int i = 0; i < n; ++i) out[i] = ctx->counters[i];
   return MLMC_OK;
 }
 
-int mlmc_set_timing(void* c, int mask, int stride) {
+int mlmc_set_timing(mlmc_ctx* c, int mask, int stride) {
   Context* ctx = as_ctx(c);
   if (!ctx || stride < 1) return MLMC_EINVAL;
   return guarded(ctx, [&] { ctx->set_timing((unsigned)mask, stride); });
 }
 
-int mlmc_kernel_stats(void* c, int kernel, int fp64, double* out) {
+int mlmc_kernel_stats(mlmc_ctx* c, int kernel, int fp64, double* out) {
   Context* ctx = as_ctx(c);
   if (!ctx || !out) return MLMC_EINVAL;
   return guarded(ctx, [&] { ctx->kernel_stats(kernel, fp64, out); });
 }
 
-int mlmc_kernel_stats_level(void* c, int kernel, int fp64, int level, double* out) {
+int mlmc_kernel_stats_level(mlmc_ctx* c, int kernel, int fp64, int level, double* out) {
   Context* ctx = as_ctx(c);
   if (!ctx || !out) return MLMC_EINVAL;
   return guarded(ctx, [&] { ctx->kernel_stats(kernel, fp64, out, level); });
 }
 
-int mlmc_reset_kernel_stats(void* c) {
+int mlmc_reset_kernel_stats(mlmc_ctx* c) {
   Context* ctx = as_ctx(c);
   if (!ctx) return MLMC_EINVAL;
   return guarded(ctx, [&] { ctx->reset_kernel_stats(); });
 }
 
-const char* mlmc_last_error(const void* c) {
-  const Context* ctx = static_cast<const Context*>(c);
+const char* mlmc_last_error(const mlmc_ctx* c) {
+  const Context* ctx = reinterpret_cast<const Context*>(c);
   if (!ctx) return g_setup_error.c_str();
   return ctx->last_error.c_str();
 }
@@ -433,7 +435,7 @@ const char* mlmc_status_string(int status) {
   }
 }
 
-void mlmc_destroy(void* c) {
+void mlmc_destroy(mlmc_ctx* c) {
   try {
     delete as_ctx(c);
   } catch (...) {

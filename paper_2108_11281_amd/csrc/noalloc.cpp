@@ -42,9 +42,9 @@ void noalloc_init(int dev) {
 
 }  // namespace mlmc
 
-extern "C" int mlmc_smooth_noalloc(void* c, int level, int nrhs, int sweeps, int flags,
+extern "C" int mlmc_smooth_noalloc(mlmc_ctx* c, int level, int nrhs, int sweeps, int flags,
                                    const double* b_dev, double* x_dev, double* rc_dev) {
-  mlmc::Context* ctx = static_cast<mlmc::Context*>(c);
+  mlmc::Context* ctx = reinterpret_cast<mlmc::Context*>(c);
   if (!ctx || !b_dev || !x_dev) return MLMC_EINVAL;
   try {
     const int dev = ctx->device();
