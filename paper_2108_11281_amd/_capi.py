@@ -69,7 +69,7 @@ class Options(ctypes.Structure):
                 ("krylov_restart", ctypes.c_int), ("min_samples", ctypes.c_int),
                 ("max_samples", ctypes.c_int64), ("tau", ctypes.c_double),
                 ("learned", ctypes.c_int), ("graphs", ctypes.c_int),
-                ("narrow_fp64", ctypes.c_int)]
+                ("narrow_fp64", ctypes.c_int), ("top_cycles", ctypes.c_int)]
 
 
 class Result(ctypes.Structure):

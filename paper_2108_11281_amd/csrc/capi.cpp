@@ -68,6 +68,7 @@ int mlmc_default_options(mlmc_options* opt) {
   opt->learned = 0;
   opt->graphs = 0;
   opt->narrow_fp64 = 0;
+  opt->top_cycles = 0;
   return MLMC_OK;
 }
 

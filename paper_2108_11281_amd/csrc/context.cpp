@@ -43,6 +43,10 @@ Context::Context(const mlmc_operator& A, const mlmc_hierarchy& h, const mlmc_opt
   // real operators, 1e-2 for the complex FGMRES restart cycles
   if (opt_.inner_tol == 0.0)
     opt_.inner_tol = (A.kind == MLMC_WILSON2D || A.kind == MLMC_GAUGE2D) ? 1e-2 : 1e-3;
+  MLMC_REQUIRE(o.top_cycles >= 0 && o.top_cycles <= 2, MLMC_EINVAL, "top_cycles must be 0, 1 or 2");
+  // top_cycles 0: two coarse-grid cycles below the top level for the 2D Poisson
+  // operator (measured faster), one elsewhere
+  top_cycles_ = o.top_cycles > 0 ? o.top_cycles : (A.kind == MLMC_POISSON2D ? 2 : 1);
   MLMC_REQUIRE(o.max_iter >= 1 && o.max_refine >= 1, MLMC_EINVAL, "iteration limits < 1");
   MLMC_REQUIRE(o.nu_pre >= 0 && o.nu_post >= 0, MLMC_EINVAL, "negative sweep count");
   MLMC_REQUIRE(o.min_samples >= 2, MLMC_EINVAL, "min_samples must be >= 2");
@@ -155,12 +159,18 @@ void Context::alloc_work(Work<T>& w, int width) {
   w.vb.assign(Ls_, nullptr);
   w.vx.assign(Ls_, nullptr);
   w.vt.assign(Ls_, nullptr);
+  w.vr2.assign(Ls_, nullptr);
+  w.ve2.assign(Ls_, nullptr);
   for (int m = 0; m < Ls_; ++m) {
     if (m > 0) {
       w.vb[m] = dalloc_n<T>(lv_[m].n * cols);
       w.vx[m] = dalloc_n<T>(lv_[m].n * cols);
     }
     if (m < Ls_ - 1) w.vt[m] = dalloc_n<T>(lv_[m].n * cols);
+    if (top_cycles_ == 2 && m > 0 && m < Ls_ - 1) {
+      w.vr2[m] = dalloc_n<T>(lv_[m].n * cols);
+      w.ve2[m] = dalloc_n<T>(lv_[m].n * cols);
+    }
   }
 }
 
@@ -696,7 +706,8 @@ void Context::vcycle_vc(int l, const T* b, T* x, int nb, const int* act, c64* rz
 // conj(b)^T x, fused into the last sweep.
 // ---------------------------------------------------------------------------
 template <typename T>
-void Context::vcycle(int l, const T* b, T* x, int nb, const int* act, c64* rz_partials) {
+void Context::vcycle(int l, const T* b, T* x, int nb, const int* act, c64* rz_partials,
+                     bool top) {
   if (varcoef_) {
     vcycle_vc<T>(l, b, x, nb, act, rz_partials);
     return;
@@ -750,6 +761,14 @@ void Context::vcycle(int l, const T* b, T* x, int nb, const int* act, c64* rz_pa
     timed<T>(l, kTimResRestrict, 2.25 * en, act, nb,
              [&] { op_res_restrict<T>(l, b, u, bc, nb, act); });
   vcycle<T>(l + 1, bc, ec, nb, act, nullptr);
+  if (top && top_cycles_ == 2 && l + 1 < Ls_) {
+    // second coarse-grid cycle on the residual of the first: ec += V(bc - A ec)
+    T* r2 = w.vr2[l];
+    T* e2 = w.ve2[l];
+    op_residual<T, T, T>(l + 1, bc, ec, r2, nb, act, nullptr);
+    vcycle<T>(l + 1, r2, e2, nb, act, nullptr);
+    vec_add_to<T>(ec, e2, lv_[l].n, nb, act, s_);
+  }
   if (post == 0) {
     if (u == nullptr) {
       agg2d_prolong<T>(ec, x, L.side, omega_, 0.0, nb, act, s_);
@@ -921,7 +940,7 @@ int Context::pcg(int l, const T* b, T* x, int nb, int* act, double tol, c64* las
   finish_sums(partials_, nblk, nb, rr0, s_);
   bool fused = false;
   const int nvp = vcycle_partials<T>(l, &fused);
-  vcycle<T>(l, w.r, w.z, nb, act, partials_);
+  vcycle<T>(l, w.r, w.z, nb, act, partials_, true);
   finish_sums(partials_, nvp, nb, rz, s_);
   vec_zero<c64>(beta, 1, nb, nullptr, s_);
   T* p_old = w.z;  // first direction: p = z + 0 * z
@@ -941,7 +960,7 @@ int Context::pcg(int l, const T* b, T* x, int nb, int* act, double tol, c64* las
     if (it % check == 0 || it == opt_.max_iter) {
       if (read_count() == 0) break;
     }
-    vcycle<T>(l, w.r, w.z, nb, act, partials_);
+    vcycle<T>(l, w.r, w.z, nb, act, partials_, true);
     finish_beta(partials_, nvp, nb, tmp, rz, act, beta, s_);
     // the new direction of this iteration is the old one of the next
     p_old = p_new;
@@ -984,7 +1003,7 @@ void Context::pcg_refined(int l, const double* b, double* y, int nb, double tol,
   vec_convert<float, double>(b, r, n, nb, nullptr, s_);
   bool fused = false;
   const int nvp = vcycle_partials<float>(l, &fused);
-  vcycle<float>(l, r, w.z, nb, act, partials_);
+  vcycle<float>(l, r, w.z, nb, act, partials_, true);
   finish_sums(partials_, nvp, nb, rz, s_);
   vec_zero<c64>(beta, 1, nb, nullptr, s_);
   const double delta2 = opt_.inner_tol * opt_.inner_tol;
@@ -1004,7 +1023,7 @@ void Context::pcg_refined(int l, const double* b, double* y, int nb, double tol,
   };
   // preconditioner and the next direction's beta
   auto tail = [&] {
-    vcycle<float>(l, r, w.z, nb, act, partials_);
+    vcycle<float>(l, r, w.z, nb, act, partials_, true);
     finish_beta(partials_, nvp, nb, tmp, rz, act, beta, s_);
   };
   // a refinement is due when some column's recursive residual has dropped by
@@ -1600,7 +1619,7 @@ void Context::export_prolongation(int level, double* out) {
   MLMC_HIP(hipStreamSynchronize(s_));
 }
 
-template void Context::vcycle<float>(int, const float*, float*, int, const int*, c64*);
-template void Context::vcycle<double>(int, const double*, double*, int, const int*, c64*);
+template void Context::vcycle<float>(int, const float*, float*, int, const int*, c64*, bool);
+template void Context::vcycle<double>(int, const double*, double*, int, const int*, c64*, bool);
 
 }  // namespace mlmc

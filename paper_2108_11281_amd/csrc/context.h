@@ -89,6 +89,9 @@ struct Work {
   T *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *p2 = nullptr, *q = nullptr;
   // V-cycle right-hand side / solution / sweep scratch per level (0-based)
   std::vector<T*> vb, vx, vt;
+  // residual and correction of the second coarse-grid cycle below a solve's
+  // top level (levels 2 .. L_s - 1, 0-based index; top_cycles = 2 only)
+  std::vector<T*> vr2, ve2;
   T* ainvT = nullptr;       // transposed inverse of the solver's coarsest operator
   int ld = 0;               // its leading dimension (n rounded up to 16, zero padded)
   // complex operators: its real representation (2n x 2n, transposed) for the
@@ -275,8 +278,10 @@ class Context {
   template <typename T> void vcycle_vc(int l, const T* b, T* x, int nb, const int* act,
                                        c64* rz_partials);
   template <typename T> Work<T>& work();
+  // top: l is the solve's top level (top_cycles_ coarse-grid cycles there)
   template <typename T> void vcycle(int l, const T* b, T* x, int nb, const int* act,
-                                    c64* rz_partials);
+                                    c64* rz_partials, bool top = false);
+  int top_cycles_ = 1;
   template <typename T> int vcycle_partials(int l, bool* fused) const;
   // CG on level l in precision T: x = A^-1 b to relative residual tol;
   // act: per-column flags (in: columns to solve; out: still unconverged)

@@ -124,6 +124,9 @@ void ir_accumulate(T64* y, const T32* d, int64_t n, int nb, const int* active,
 // out = a - b
 template <typename T>
 void vec_sub(const T* a, const T* b, T* out, int64_t n, int nb, hipStream_t s);
+// y += x (active columns)
+template <typename T>
+void vec_add_to(T* y, const T* x, int64_t n, int nb, const int* active, hipStream_t s);
 // y += a[k] * x  (column scalars)
 template <typename T>
 void vec_axpy_cols(T* y, const T* x, const c64* a, int64_t n, int nb,

@@ -37,6 +37,17 @@ __global__ void k_sub(const T* a, const T* b, T* out, int64_t n) {
   }
 }
 
+template <typename T>
+__global__ void k_add_to(T* y, const T* x, int64_t n, const int* active) {
+  const int k = blockIdx.y;
+  if (active && !active[k]) return;
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i < n) {
+    const int64_t j = (int64_t)k * n + i;
+    y[j] = y[j] + x[j];
+  }
+}
+
 // grid (nblk, nb): block b of column k reduces a contiguous chunk
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_dot(const T* x, const T* y, int64_t n,
@@ -738,6 +749,11 @@ void vec_sub(const T* a, const T* b, T* out, int64_t n, int nb, hipStream_t s) {
   if (n <= 0 || nb <= 0) return;
   hipLaunchKernelGGL(k_sub<T>, grid_cols(n, nb), dim3(kThreads), 0, s, a, b, out, n);
 }
+template <typename T>
+void vec_add_to(T* y, const T* x, int64_t n, int nb, const int* active, hipStream_t s) {
+  if (n <= 0 || nb <= 0) return;
+  hipLaunchKernelGGL(k_add_to<T>, grid_cols(n, nb), dim3(kThreads), 0, s, y, x, n, active);
+}
 template <typename To, typename From>
 void vec_convert(const From* x, To* y, int64_t n, int nb, const int* active, hipStream_t s) {
   if (n <= 0 || nb <= 0) return;
@@ -933,6 +949,7 @@ void dense_apply(const T* At, const T* B, T* Z, int n, int nb, const int* active
   template void vec_zero<T>(T*, int64_t, int, const int*, hipStream_t);                  \
   template void vec_copy<T>(const T*, T*, int64_t, int, const int*, hipStream_t);        \
   template void vec_sub<T>(const T*, const T*, T*, int64_t, int, hipStream_t);           \
+  template void vec_add_to<T>(T*, const T*, int64_t, int, const int*, hipStream_t);       \
   template void vec_dot_partials<T>(const T*, const T*, int64_t, int, const int*, c64*,  \
                                     hipStream_t);                                        \
   template void cg_update_xr<T>(T*, T*, const T*, const T*, const c64*, int64_t, int,    \

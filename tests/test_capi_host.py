@@ -35,7 +35,7 @@ def test_struct_sizes_match_header_layout():
     # mlmc_result: 2+1+1+2 doubles, int (+pad), 16 int64, 32+16+16+16 doubles, 2 int64,
     # 2 doubles
     assert ctypes.sizeof(_capi.Result) == 8 * (6 + 1 + 16 + 32 + 16 + 16 + 16 + 2 + 2)
-    assert ctypes.sizeof(_capi.Options) == 104  # ... learned, graphs, narrow_fp64 (+pad)
+    assert ctypes.sizeof(_capi.Options) == 104  # ... learned, graphs, narrow_fp64, top_cycles
     # mlmc_train_options: 4 ints, a double, a uint64; mlmc_train_report: 6 x 8 bytes
     assert ctypes.sizeof(_capi.TrainOptions) == 32
     assert ctypes.sizeof(_capi.TrainReport) == 48

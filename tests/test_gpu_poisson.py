@@ -145,3 +145,23 @@ def test_exit_handler_closes_live_estimators():
     m._close_live()
     assert not est._ctx
     est.close()  # idempotent
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir64"])
+def test_top_level_w_cycle_samples_and_iterations(precision):
+    # two coarse-grid V-cycles below each solve's top level (top_cycles = 2) keep
+    # the samples (same FP64 tolerance) and take fewer Krylov iterations than the
+    # plain V-cycle on a 6-level 256^2 hierarchy with 2 + 2 sweeps
+    N, L = 256, 6
+    A, P = hierarchy.poisson_hierarchy(N, L)
+    orc = mlmc.PoissonDSTSampler(N, L)
+    its = {}
+    for cyc in (1, 2):
+        est = _est(N, L, precision=precision, nb=16, top_cycles=cyc, nu_pre=2, nu_post=2)
+        s, err = est.sample_level(1, 5, 0, 16, with_error=True)
+        ref = orc.sample(1, 5, 0, 16)
+        scale = quad_scale(orc.sample_parts(1, 5, 0, 16))
+        assert np.all(np.abs(s - ref) <= 1e-8 * scale), (cyc, np.max(np.abs(s - ref) / scale))
+        assert np.all(err <= 1e-8)
+        its[cyc] = est.counters()[0]
+    assert its[2] < 0.8 * its[1], its
