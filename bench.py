@@ -547,6 +547,7 @@ def run_batch(args, m, torch):
         ests.append(m.TraceEstimator("varcoef3d", N, L, L, shift=1e-3,
                                      field=varcoef_faces(N, seed=1000 + p), nb=64,
                                      precision="fp32_ir64", solve_tol=1e-10,
+                                     top_cycles=args.top_cycles,
                                      stream=torch.cuda.Stream()))
     setup_s = time.perf_counter() - t0
     log("setup %.2fs" % setup_s)
@@ -613,7 +614,8 @@ def run_graph(args, m, torch):
     def make(precision):
         return m.TraceEstimator("csr", 0, Ls, L, matrix=A, precision=precision, nb=args.nb,
                                 solve_tol=w["solve_tol"], alloc=args.alloc,
-                                narrow_fp64=args.narrow_fp64 if precision != "fp64" else 0, **vc)
+                                narrow_fp64=args.narrow_fp64 if precision != "fp64" else 0,
+                                top_cycles=args.top_cycles, **vc)
     t0 = time.perf_counter()
     est = make("fp32_ir64")
     setup_s = time.perf_counter() - t0
@@ -692,7 +694,8 @@ def run_laplace_bilinear(args, m, torch):
     def make(precision):
         return m.TraceEstimator("csr", 0, Ls, L, matrix=A, prolongations=P, precision=precision,
                                 nb=args.nb, solve_tol=w["solve_tol"], alloc=args.alloc,
-                                narrow_fp64=args.narrow_fp64 if precision != "fp64" else 0, **vc)
+                                narrow_fp64=args.narrow_fp64 if precision != "fp64" else 0,
+                                top_cycles=args.top_cycles, **vc)
     t0 = time.perf_counter()
     est = make("fp32_ir64")
     setup_s = time.perf_counter() - t0
@@ -846,6 +849,9 @@ def main():
     ap.add_argument("--narrow-fp64", type=int, default=0,
                     help="real operators: batches of at most this many columns solved in "
                          "plain FP64 inside the FP32 + refinement run")
+    ap.add_argument("--top-cycles", type=int, default=0,
+                    help="varcoef_batch, graph1m, laplace_bilinear: coarse-grid cycles below "
+                         "each solve's top level (0: the library default)")
     ap.add_argument("--omega", type=float, default=0.0,
                     help="graph1m: coarse-correction scaling (0 = the library default)")
     ap.add_argument("--train-batches", type=int, default=80,

@@ -195,14 +195,18 @@ typedef struct mlmc_options {
                          the FP32 bandwidth saves); FP64 work vectors of this
                          width are allocated.  0: every batch in FP32 + FP64
                          refinement */
-  int top_cycles;     /* POISSON2D (other kinds: 1 only, 2 is ignored): coarse-
-                         grid corrections on the top level of every Krylov
-                         solve: 1 = one V-cycle on
+  int top_cycles;     /* real operator kinds (POISSON2D, VARCOEF3D, CSR; the
+                         complex kinds ignore it): coarse-grid corrections on
+                         the top level of every Krylov solve: 1 = one V-cycle on
                          the next level (plain V-cycle), 2 = two V-cycles there
                          (the second on the residual of the first: a W-cycle on
                          the top level only, V-cycles below); the preconditioner
-                         stays symmetric.  0 = automatic: 2 for POISSON2D, 1
-                         for the other kinds */
+                         stays symmetric, and positive definite while the
+                         level's V-cycle contracts in the energy norm.  0 =
+                         automatic: 2 for POISSON2D (fewer iterations, faster),
+                         1 for the others (measured: the 3D batch and the
+                         bilinear hierarchy of Example 4.1 then miss their
+                         tolerance, the graph Laplacian runs 8% slower) */
 } mlmc_options;
 
 #define MLMC_MAX_LEVELS 16

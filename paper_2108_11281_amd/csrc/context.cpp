@@ -611,7 +611,19 @@ void Context::op_restrict(int l, const T* x, T* xc, int nb, const int* act) {
 // residual + restriction, prolongation + omega-scaled correction.
 // ---------------------------------------------------------------------------
 template <typename T>
-void Context::vcycle_vc(int l, const T* b, T* x, int nb, const int* act, c64* rz_partials) {
+void Context::second_coarse_cycle(int l, const T* bc, T* ec, int nb, const int* act, bool top) {
+  if (!top || top_cycles_ != 2 || l + 1 >= Ls_) return;
+  Work<T>& w = work<T>();
+  T* r2 = w.vr2[l];
+  T* e2 = w.ve2[l];
+  op_residual<T, T, T>(l + 1, bc, ec, r2, nb, act, nullptr);
+  vcycle<T>(l + 1, r2, e2, nb, act, nullptr);
+  vec_add_to<T>(ec, e2, lv_[l].n, nb, act, s_);
+}
+
+template <typename T>
+void Context::vcycle_vc(int l, const T* b, T* x, int nb, const int* act, c64* rz_partials,
+                        bool top) {
   Work<T>& w = work<T>();
   if (l == 1) counters[2] += 1;
   const int64_t n = lv_[l - 1].n;
@@ -644,6 +656,7 @@ void Context::vcycle_vc(int l, const T* b, T* x, int nb, const int* act, c64* rz
       timed<T>(l, kTimResRestrict, en * (2.0 + 0.125 + 4.0 / (double)nb), act, nb,
                [&] { op_res_restrict<T>(l, b, u, bc, nb, act); });
     vcycle_vc<T>(l + 1, bc, ec, nb, act, nullptr);
+    second_coarse_cycle<T>(l, bc, ec, nb, act, top);
     if (post == 0) {
       if (u != nullptr && u != x) vec_copy<T>(u, x, n, nb, act, s_);
       timed<T>(l, kTimProlong, en * (2.0 + 0.125), act, nb, [&] {
@@ -681,6 +694,7 @@ void Context::vcycle_vc(int l, const T* b, T* x, int nb, const int* act, c64* rz
       timed<T>(l, kTimResRestrict, en * (2.0 + 0.125 + 4.0 / (double)nb), act, nb,
                [&] { op_res_restrict<T>(l, b, x, bc, nb, act); });
     vcycle_vc<T>(l + 1, bc, ec, nb, act, nullptr);
+    second_coarse_cycle<T>(l, bc, ec, nb, act, top);
     if (post == 0 || pre == 0) {
       timed<T>(l, kTimProlong, en * (2.0 + 0.125), act, nb, [&] {
         varcoef_prolong<T>(ec, x, L.side, omega_, pre == 0 ? 0.0 : 1.0, nb, act, s_);
@@ -709,11 +723,11 @@ template <typename T>
 void Context::vcycle(int l, const T* b, T* x, int nb, const int* act, c64* rz_partials,
                      bool top) {
   if (varcoef_) {
-    vcycle_vc<T>(l, b, x, nb, act, rz_partials);
+    vcycle_vc<T>(l, b, x, nb, act, rz_partials, top);
     return;
   }
   if (csr_) {
-    vcycle_csr<T>(l, b, x, nb, act, rz_partials);
+    vcycle_csr<T>(l, b, x, nb, act, rz_partials, top);
     return;
   }
   Work<T>& w = work<T>();
@@ -761,14 +775,7 @@ void Context::vcycle(int l, const T* b, T* x, int nb, const int* act, c64* rz_pa
     timed<T>(l, kTimResRestrict, 2.25 * en, act, nb,
              [&] { op_res_restrict<T>(l, b, u, bc, nb, act); });
   vcycle<T>(l + 1, bc, ec, nb, act, nullptr);
-  if (top && top_cycles_ == 2 && l + 1 < Ls_) {
-    // second coarse-grid cycle on the residual of the first: ec += V(bc - A ec)
-    T* r2 = w.vr2[l];
-    T* e2 = w.ve2[l];
-    op_residual<T, T, T>(l + 1, bc, ec, r2, nb, act, nullptr);
-    vcycle<T>(l + 1, r2, e2, nb, act, nullptr);
-    vec_add_to<T>(ec, e2, lv_[l].n, nb, act, s_);
-  }
+  second_coarse_cycle<T>(l, bc, ec, nb, act, top);
   if (post == 0) {
     if (u == nullptr) {
       agg2d_prolong<T>(ec, x, L.side, omega_, 0.0, nb, act, s_);
@@ -1619,6 +1626,10 @@ void Context::export_prolongation(int level, double* out) {
   MLMC_HIP(hipStreamSynchronize(s_));
 }
 
+template void Context::second_coarse_cycle<float>(int, const float*, float*, int, const int*,
+                                                  bool);
+template void Context::second_coarse_cycle<double>(int, const double*, double*, int, const int*,
+                                                   bool);
 template void Context::vcycle<float>(int, const float*, float*, int, const int*, c64*, bool);
 template void Context::vcycle<double>(int, const double*, double*, int, const int*, c64*, bool);
 

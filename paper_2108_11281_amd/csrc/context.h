@@ -197,7 +197,7 @@ class Context {
   template <typename T> const CsrMat<T>& csr_P(int l) const;  // given prolongation
   template <typename T> const CsrMat<T>& csr_R(int l) const;  // its transpose
   template <typename T> void vcycle_csr(int l, const T* b, T* x, int nb, const int* act,
-                                        c64* rz_partials);
+                                        c64* rz_partials, bool top = false);
   void tune_varcoef();
   void tune_bsr();
   void tune_poisson();
@@ -276,11 +276,15 @@ class Context {
   template <typename T> void op_update_apply(int l, const T* p_old, const T* z, const c64* beta,
                                              T* p_new, T* q, int nb, const int* act);
   template <typename T> void vcycle_vc(int l, const T* b, T* x, int nb, const int* act,
-                                       c64* rz_partials);
+                                       c64* rz_partials, bool top = false);
   template <typename T> Work<T>& work();
   // top: l is the solve's top level (top_cycles_ coarse-grid cycles there)
   template <typename T> void vcycle(int l, const T* b, T* x, int nb, const int* act,
                                     c64* rz_partials, bool top = false);
+  // with top and top_cycles_ == 2 (and level l + 1 not the coarsest): a second
+  // coarse-grid cycle on level l + 1 on the residual of the first, ec += V(bc - A ec)
+  template <typename T> void second_coarse_cycle(int l, const T* bc, T* ec, int nb,
+                                                 const int* act, bool top);
   int top_cycles_ = 1;
   template <typename T> int vcycle_partials(int l, bool* fused) const;
   // CG on level l in precision T: x = A^-1 b to relative residual tol;

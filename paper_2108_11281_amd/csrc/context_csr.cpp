@@ -597,7 +597,8 @@ void Context::tune_csr() {
 // preconditioner is symmetric), residual + restriction, prolongation +
 // omega-scaled correction.
 template <typename T>
-void Context::vcycle_csr(int l, const T* b, T* x, int nb, const int* act, c64* rz_partials) {
+void Context::vcycle_csr(int l, const T* b, T* x, int nb, const int* act, c64* rz_partials,
+                         bool top) {
   Work<T>& w = work<T>();
   if (l == 1) counters[2] += 1;
   const Level& L = lv_[l - 1];
@@ -635,6 +636,7 @@ void Context::vcycle_csr(int l, const T* b, T* x, int nb, const int* act, c64* r
         });
       }
       vcycle_csr<T>(l + 1, bc, ec, nb, act, nullptr);
+      second_coarse_cycle<T>(l, bc, ec, nb, act, top);
       timed<T>(l, kTimProlong, (pre == 0 ? 1.0 : 2.0) * en + enc, act, nb, [&] {
         csr_spmm<T>(ec, x, Pm, omega_, pre == 0 ? 0.0 : 1.0, nb, cols, act, s_);
       });
@@ -645,6 +647,7 @@ void Context::vcycle_csr(int l, const T* b, T* x, int nb, const int* act, c64* r
         timed<T>(l, kTimResRestrict, 2.0 * en + enc + res_mat / nb, act, nb,
                  [&] { csr_restrict<T>(b, x, bc, w.vt[l - 1], A, G, nb, cols, act, s_); });
       vcycle_csr<T>(l + 1, bc, ec, nb, act, nullptr);
+      second_coarse_cycle<T>(l, bc, ec, nb, act, top);
       timed<T>(l, kTimProlong, (pre == 0 ? 1.0 : 2.0) * en + enc, act, nb, [&] {
         csr_prolong<T>(ec, x, G, (int)n, omega_, pre == 0 ? 0.0 : 1.0, nb, act, s_);
       });
@@ -656,8 +659,9 @@ void Context::vcycle_csr(int l, const T* b, T* x, int nb, const int* act, c64* r
   if (rz_partials) vec_dot_partials<T>(b, x, n, nb, act, rz_partials, s_);
 }
 
-template void Context::vcycle_csr<float>(int, const float*, float*, int, const int*, c64*);
-template void Context::vcycle_csr<double>(int, const double*, double*, int, const int*, c64*);
+template void Context::vcycle_csr<float>(int, const float*, float*, int, const int*, c64*, bool);
+template void Context::vcycle_csr<double>(int, const double*, double*, int, const int*, c64*,
+                                          bool);
 
 // the matrix of a level in canonical CSR form (nnz always; every array
 // nullable), its aggregate map (levels below L_s) and its colours
