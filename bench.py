@@ -355,13 +355,14 @@ def run_poisson(args, m, torch):
              compare=compare)
 
 
-def _wilson_est(m, N, Ls, L, precision, learned, nb, alloc, n_vec=8, spin_split=False):
+def _wilson_est(m, N, Ls, L, precision, learned, nb, alloc, n_vec=8, spin_split=False,
+                top_cycles=0):
     from workloads import gauge_field, wilson_mass
     return m.TraceEstimator("wilson2d", N, Ls, L, mass=wilson_mass(N),
                             field=gauge_field(N, sigma=0.5, seed=1), block=4, n_vec=n_vec,
                             spin_split=spin_split, setup_sweeps=20, setup_seed=1,
                             precision=precision, nb=nb, nu_pre=2, nu_post=2, solve_tol=1e-10,
-                            alloc=alloc, learned=1 if learned else 0)
+                            alloc=alloc, learned=1 if learned else 0, top_cycles=top_cycles)
 
 
 def deflated_compare(args, m, torch, make):
@@ -448,7 +449,8 @@ def run_wilson(args, m, torch, N, learned):
     log("setup wilson2d N=%d Ls=%d L=%d nb=%d learned=%s" % (N, Ls, L, args.nb, learned))
     t0 = time.perf_counter()
     nv = args.n_vec if args.n_vec > 0 else (4 if args.spin_split else 8)
-    est = _wilson_est(m, N, Ls, L, "fp32_ir64", learned, args.nb, args.alloc, nv, args.spin_split)
+    est = _wilson_est(m, N, Ls, L, "fp32_ir64", learned, args.nb, args.alloc, nv, args.spin_split,
+                      args.top_cycles)
     setup_s = time.perf_counter() - t0
     log("setup %.2fs" % setup_s)
     train = None
@@ -498,14 +500,15 @@ def run_wilson(args, m, torch, N, learned):
         if learned:
             log("plain FP32 MLMC (no network), same workload")
             ep = _wilson_est(m, N, Ls, L, "fp32_ir64", False, args.nb, args.alloc, nv,
-                             args.spin_split)
+                             args.spin_split, args.top_cycles)
             tp, npl = timed_traces(ep, args, torch)
             ep.close()
             compare["plain_fp32_mlmc_s"] = round(tp, 3)
             compare["plain_fp32_mlmc_n_samples"] = npl
             log("plain FP32 MLMC %.3fs per trace, N_l=%s" % (tp, npl))
         log("plain FP64 MLMC, same workload")
-        e64 = _wilson_est(m, N, Ls, L, "fp64", False, args.nb, args.alloc, nv, args.spin_split)
+        e64 = _wilson_est(m, N, Ls, L, "fp64", False, args.nb, args.alloc, nv, args.spin_split,
+                          args.top_cycles)
         t64, n64 = timed_traces(e64, args, torch)
         e64.close()
         compare["fp64_mlmc_s"] = round(t64, 3)
@@ -850,8 +853,8 @@ def main():
                     help="real operators: batches of at most this many columns solved in "
                          "plain FP64 inside the FP32 + refinement run")
     ap.add_argument("--top-cycles", type=int, default=0,
-                    help="varcoef_batch, graph1m, laplace_bilinear: coarse-grid cycles below "
-                         "each solve's top level (0: the library default)")
+                    help="all but poisson1024: coarse-grid cycles below each solve's top "
+                         "level (0: the library default)")
     ap.add_argument("--omega", type=float, default=0.0,
                     help="graph1m: coarse-correction scaling (0 = the library default)")
     ap.add_argument("--train-batches", type=int, default=80,

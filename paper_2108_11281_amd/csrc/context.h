@@ -243,7 +243,11 @@ class Context {
   template <typename T> void cop_restrict(int l, const T* x, T* xc, int nb, const int* act);
   template <typename T> void cop_prolong(int l, const T* ec, T* x, int nb, const int* act,
                                          double omega, double beta);
-  template <typename T> void cvcycle(int l, const T* b, T* x, int nb, const int* act);
+  template <typename T> void cvcycle(int l, const T* b, T* x, int nb, const int* act,
+                                     bool top = false);
+  // the complex counterpart of second_coarse_cycle
+  template <typename T> void csecond_coarse_cycle(int l, const T* bc, T* ec, int nb,
+                                                  const int* act, bool top);
   template <typename T> void coarse_apply(const T* b, T* x, int nb, const int* act);
   template <typename T> void fgmres_cycle(int l, const T* r, T* d, int nb, int* act,
                                           double tol);

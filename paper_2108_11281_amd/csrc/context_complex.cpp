@@ -131,12 +131,18 @@ void Context::build_wilson(const double* theta) {
     w.vb.assign(Ls_, nullptr);
     w.vx.assign(Ls_, nullptr);
     w.vt.assign(Ls_, nullptr);
+    w.vr2.assign(Ls_, nullptr);
+    w.ve2.assign(Ls_, nullptr);
     for (int m = 0; m < Ls_; ++m) {
       if (m > 0) {
         w.vb[m] = dalloc_n<T>(lv_[m].n * nb_);
         w.vx[m] = dalloc_n<T>(lv_[m].n * nb_);
       }
       w.vt[m] = dalloc_n<T>(lv_[m].n * nb_);
+      if (top_cycles_ == 2 && m > 0 && m < Ls_ - 1) {  // second coarse-grid cycle
+        w.vr2[m] = dalloc_n<T>(lv_[m].n * nb_);
+        w.ve2[m] = dalloc_n<T>(lv_[m].n * nb_);
+      }
     }
   };
   auto alloc_fg = [&](auto& f) {
@@ -343,7 +349,18 @@ void Context::coarse_apply(const T* b, T* x, int nb, const int* act) {
 }
 
 template <typename T>
-void Context::cvcycle(int l, const T* b, T* x, int nb, const int* act) {
+void Context::csecond_coarse_cycle(int l, const T* bc, T* ec, int nb, const int* act, bool top) {
+  if (!top || top_cycles_ != 2 || l + 1 >= Ls_) return;
+  Work<T>& w = work<T>();
+  T* r2 = w.vr2[l];
+  T* e2 = w.ve2[l];
+  cop_residual<T, T, T>(l + 1, bc, ec, r2, nb, act, nullptr);
+  cvcycle<T>(l + 1, r2, e2, nb, act);
+  vec_add_to<T>(ec, e2, lv_[l].n, nb, act, s_);
+}
+
+template <typename T>
+void Context::cvcycle(int l, const T* b, T* x, int nb, const int* act, bool top) {
   Work<T>& w = work<T>();
   const int64_t n = lv_[l - 1].n;
   if (l == 1) counters[2] += 1;
@@ -360,6 +377,7 @@ void Context::cvcycle(int l, const T* b, T* x, int nb, const int* act) {
       cop_residual<T, T, T>(l, b, x, res, nb, act, nullptr);
       cop_restrict<T>(l, res, w.vb[1], nb, act);
       cvcycle<T>(2, w.vb[1], w.vx[1], nb, act);
+      csecond_coarse_cycle<T>(1, w.vb[1], w.vx[1], nb, act, top);
       cop_prolong<T>(l, w.vx[1], x, nb, act, omega_, 1.0);
       nn_step(b, x, nb, act);
       cop_smooth<T>(l, b, x, nb, act, false, true);
@@ -373,6 +391,7 @@ void Context::cvcycle(int l, const T* b, T* x, int nb, const int* act) {
   cop_residual<T, T, T>(l, b, x, res, nb, act, nullptr);
   cop_restrict<T>(l, res, w.vb[l], nb, act);
   cvcycle<T>(l + 1, w.vb[l], w.vx[l], nb, act);
+  csecond_coarse_cycle<T>(l, w.vb[l], w.vx[l], nb, act, top);
   cop_prolong<T>(l, w.vx[l], x, nb, act, omega_, 1.0);
   cop_smooth_n<T>(l, b, x, nb, act, post, false, true);
 }
@@ -400,7 +419,7 @@ void Context::fgmres_cycle(int l, const T* r, T* d, int nb, int* act, double tol
     T* vj = f.V + j * vs;
     T* zj = f.Z + j * vs;
     T* w = f.V + (j + 1) * vs;
-    cvcycle<T>(l, vj, zj, nb, act);
+    cvcycle<T>(l, vj, zj, nb, act, true);
     cop_residual<T, T, T>(l, (const T*)nullptr, zj, w, nb, act, nullptr);
     int mb = 0;
     krylov_mdot<T>(f.V, vs, j + 1, w, n, nb, act, partials_, &mb, s_);
@@ -514,6 +533,6 @@ template void Context::cop_smooth_n<c64>(int, const c64*, c64*, int, const int*,
                                          bool);
 template void Context::cop_smooth_n<c32>(int, const c32*, c32*, int, const int*, int, bool,
                                          bool);
-template void Context::cvcycle<c64>(int, const c64*, c64*, int, const int*);
+template void Context::cvcycle<c64>(int, const c64*, c64*, int, const int*, bool);
 
 }  // namespace mlmc
