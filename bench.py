@@ -53,7 +53,9 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0
 METRIC = "time-to-tr(A^-1) at rel err 1e-3 (learned+FP32 vs plain FP64 MLMC); HBM GB/s"
-GS_SOURCE = os.path.join(ROOT, "paper_2108_11281_amd", "csrc", "kernels_poisson.hip")
+# the sweep kernels and the V-cycle / Krylov code that sets their launch mix
+GS_SOURCES = [os.path.join(ROOT, "paper_2108_11281_amd", "csrc", f)
+              for f in ("kernels_poisson.hip", "context.cpp")]
 GS_TRAFFIC = os.path.join(ROOT, "profiles", "rbgs_sweep_poisson1024_traffic.md")
 
 
@@ -128,10 +130,13 @@ def cpu_baseline_varcoef(sides, seeds, nsamples, budget_s=20.0):
 
 
 # ---------------------------------------------------------------------------
-def source_digest(path):
+def source_digest(paths):
     import hashlib
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in paths:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def stored_traffic():
@@ -148,7 +153,7 @@ def stored_traffic():
         if line.startswith("traffic_bytes_per_launch:") or line.startswith("source_digest:"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("source_digest") != source_digest(GS_SOURCE):
+    if vals.get("source_digest") != source_digest(GS_SOURCES):
         return None
     try:
         return float(vals["traffic_bytes_per_launch"])

@@ -461,6 +461,9 @@ typedef struct mlmc_train_options {
   int batch;            /* crops per step (<= n_batches * nb * 2 * crops_per_column) */
   double lr;            /* Adam learning rate (betas 0.9, 0.999, eps 1e-8) */
   uint64_t seed;        /* probes (RNG stream 5) and crop positions */
+  double pair_tol;      /* relative residual of the plain solves that give the
+                           training targets (0: 1e-6; a target error of that size
+                           is far below the network's BF16 rounding) */
 } mlmc_train_options;
 
 typedef struct mlmc_train_report {

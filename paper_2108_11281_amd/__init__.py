@@ -482,7 +482,7 @@ class TraceEstimator:
 
     # -- learned smoother (wilson2d) --
     def learned_train(self, w_init, *, n_batches=8, crops_per_column=4, steps=500, batch=256,
-                      lr=1e-3, seed=1):
+                      lr=1e-3, seed=1, pair_tol=0.0):
         """Train the network on (residual, error) pairs from the plain solver;
         returns the training report as a dict."""
         w = np.ascontiguousarray(w_init, dtype=np.float32)
@@ -491,6 +491,7 @@ class TraceEstimator:
         o = _capi.TrainOptions()
         o.n_batches, o.crops_per_column = int(n_batches), int(crops_per_column)
         o.steps, o.batch, o.lr, o.seed = int(steps), int(batch), float(lr), int(seed)
+        o.pair_tol = float(pair_tol)
         rep = _capi.TrainReport()
         self._c(self._lib.mlmc_learned_train(
             self._ctx, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(o),

@@ -92,7 +92,7 @@ NN_CROP = 22
 class TrainOptions(ctypes.Structure):
     _fields_ = [("n_batches", ctypes.c_int), ("crops_per_column", ctypes.c_int),
                 ("steps", ctypes.c_int), ("batch", ctypes.c_int), ("lr", ctypes.c_double),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("pair_tol", ctypes.c_double)]
 
 
 class TrainReport(ctypes.Structure):

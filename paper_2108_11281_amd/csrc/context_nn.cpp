@@ -218,7 +218,18 @@ void Context::nn_train(const float* w_init, const mlmc_train_options& o,
   for (int j = 0; j < o.n_batches; ++j) {
     write_probes(1, o.seed, kStreamTrain, (uint64_t)j * nb_, nb_, b1_);
     bool ok = true;
-    solve(1, b1_, y1_, nb_, scal_[kErr1], nullptr, &ok);
+    {
+      // the targets need only the accuracy of BF16 training data
+      const double saved = opt_.solve_tol;
+      opt_.solve_tol = o.pair_tol > 0 ? o.pair_tol : 1e-6;
+      try {
+        solve(1, b1_, y1_, nb_, scal_[kErr1], nullptr, &ok);
+      } catch (...) {
+        opt_.solve_tol = saved;
+        throw;
+      }
+      opt_.solve_tol = saved;
+    }
     MLMC_REQUIRE(ok, MLMC_ENOCONV, "a training solve missed solve_tol");
     // state 1: one red-black sweep from zero
     cop_smooth<c64>(1, b, xs, nb_, nullptr, true, false);

@@ -36,8 +36,8 @@ def test_struct_sizes_match_header_layout():
     # 2 doubles
     assert ctypes.sizeof(_capi.Result) == 8 * (6 + 1 + 16 + 32 + 16 + 16 + 16 + 2 + 2)
     assert ctypes.sizeof(_capi.Options) == 104  # ... learned, graphs, narrow_fp64, top_cycles
-    # mlmc_train_options: 4 ints, a double, a uint64; mlmc_train_report: 6 x 8 bytes
-    assert ctypes.sizeof(_capi.TrainOptions) == 32
+    # mlmc_train_options: 4 ints, a double, a uint64, a double; mlmc_train_report: 6 x 8
+    assert ctypes.sizeof(_capi.TrainOptions) == 40
     assert ctypes.sizeof(_capi.TrainReport) == 48
     # mlmc_operator: 2 ints, 4 doubles, a pointer, an int64, 3 pointers;
     # mlmc_hierarchy: 5 ints (+pad), a uint64, a pointer, an int (+pad), a pointer;
