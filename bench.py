@@ -560,8 +560,18 @@ def run_batch(args, m, torch):
     setup_s = time.perf_counter() - t0
     log("setup %.2fs" % setup_s)
     ns = 64
+    grouped = args.workers == 0
+
+    def step(first, workers):
+        # workers 0: every problem in lockstep on one stream (grouped launches);
+        # else host worker threads, one HIP stream per problem
+        if workers == 0:
+            s, _ = m.batch_sample_grouped(ests, 1, seeds, first, ns)
+            return s, None
+        return m.batch_sample(ests, 1, seeds, first, ns, workers=workers)
+
     for i in range(args.warmup):
-        m.batch_sample(ests, 1, seeds, 10 ** 6 + i * ns, ns, workers=args.workers)
+        step(10 ** 6 + i * ns, args.workers)
     for e in ests:
         e.set_timing(["rbgs_sweep"], stride=args.timing_stride)
         e.reset_kernel_stats()
@@ -569,9 +579,10 @@ def run_batch(args, m, torch):
     t0 = time.perf_counter()
     per = []
     for i in range(args.steps):
-        _, sec = m.batch_sample(ests, 1, seeds, i * ns, ns, workers=args.workers)
+        t1 = time.perf_counter()
+        _, sec = step(i * ns, args.workers)
         per.append(sec)
-        log("step %d: %.3fs (slowest problem %.3fs)" % (i, max(sec), max(sec)))
+        log("step %d: %.3fs" % (i, time.perf_counter() - t1))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     tot = [0, 0.0, 0.0]
@@ -583,16 +594,29 @@ def run_batch(args, m, torch):
     value = solves / elapsed
     ms_per_step = 1000.0 * elapsed / args.steps
     import numpy as np
-    per_problem = [dict(N=N, solves_per_s=round(2 * ns / float(np.mean([s[p] for s in per])), 1))
-                   for p, N in enumerate(sides)]
+    per_problem = None
+    if not grouped:
+        per_problem = [dict(N=N, solves_per_s=round(2 * ns / float(np.mean([s[p] for s in per])),
+                                                    1)) for p, N in enumerate(sides)]
     compare = {}
     if not args.no_compare:
-        t1 = time.perf_counter()
-        m.batch_sample(ests, 1, seeds, 0, ns, workers=1)
-        torch.cuda.synchronize()
-        seq = time.perf_counter() - t1
-        compare = dict(sequential_one_worker_solves_per_s=round(2 * ns * len(ests) / seq, 1),
-                       concurrency_speedup=round(seq / (elapsed / args.steps), 2))
+        # the other schedules on the same samples: host workers on four streams,
+        # and one worker
+        for label, workers in (("grouped_lockstep", 0), ("four_workers", 4),
+                               ("one_worker", 1)):
+            if workers == args.workers:
+                continue
+            step(0, workers)  # warm-up of this schedule
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            step(0, workers)
+            torch.cuda.synchronize()
+            compare[label + "_solves_per_s"] = round(2 * ns * len(ests) /
+                                                     (time.perf_counter() - t1), 1)
+        if grouped:
+            s_g, _ = step(0, 0)
+            s_w, _ = step(0, 4)
+            compare["grouped_equals_workers_bitwise"] = bool(np.array_equal(s_g, s_w))
     for e in ests:
         e.close()
     cpu = None
@@ -601,12 +625,16 @@ def run_batch(args, m, torch):
         cpu = cpu_baseline_varcoef(sides, seeds, ns)
     config = {"workload": "varcoef3d_batch32_N32-128_agg2x2x2_nb64_fp32ir64",
               "problems": len(sides), "sides": sides, "probes_per_problem": ns,
-              "workers": args.workers, "solve_tol": 1e-10}
+              "schedule": ("grouped lockstep, one launch per V-cycle position" if grouped
+                           else "%d host workers, one stream per problem" % args.workers),
+              "solve_tol": 1e-10}
+    kname = ("V-cycle stage kernel kg_stages (3D sweeps, residual restriction, coarsest "
+             "solve of all problems)" if grouped
+             else "3D red-black sweep: k_vc_march<float> (both colours, one pass)")
     contract(args, round(value, 1), "solves/s", True, ms_per_step, "f32+f64ir",
              "synthetic (log-normal face coefficients sigma=1, Rademacher probes)", config,
-             hbm_roofline("3D red-black sweep: k_vc_march<float> (both colours, one pass)", tot,
-                          args.timing_stride),
-             cpu, per_problem=per_problem, setup_s=round(setup_s, 2), compare=compare)
+             hbm_roofline(kname, tot, args.timing_stride), cpu, per_problem=per_problem,
+             setup_s=round(setup_s, 2), compare=compare)
 
 
 def run_graph(args, m, torch):
@@ -849,7 +877,9 @@ def main():
     ap.add_argument("--nb", type=int, default=128)
     ap.add_argument("--alloc", default="giles")
     ap.add_argument("--nu", type=int, default=2, help="poisson1024: sweeps before and after")
-    ap.add_argument("--workers", type=int, default=4, help="varcoef_batch: host workers")
+    ap.add_argument("--workers", type=int, default=4,
+                    help="varcoef_batch: host workers (0: all problems grouped in lockstep "
+                         "on one stream)")
     ap.add_argument("--spin-split", action="store_true",
                     help="wilson*: spin-structure-preserving aggregation (Example 4.3)")
     ap.add_argument("--n-vec", type=int, default=0,

@@ -203,9 +203,14 @@ typedef struct mlmc_options {
                          (the second on the residual of the first: a W-cycle on
                          the top level only, V-cycles below); the preconditioner
                          stays symmetric, and positive definite while the
-                         level's V-cycle contracts in the energy norm.  0 =
-                         automatic: 2 for POISSON2D (fewer iterations, faster),
-                         1 for the others (measured: the 3D batch and the
+                         level's V-cycle contracts in the energy norm, i.e.
+                         while every eigenvalue of M A of the level's V-cycle
+                         M is below 2 (with 2 and one sweep on each side at
+                         omega 1.8 the 2D Poisson V-cycle exceeds it: about 2.4
+                         at 512^2, and solves then miss solve_tol).  0 =
+                         automatic: 2 for POISSON2D with nu_pre >= 2 and
+                         nu_post >= 2 (fewer iterations, faster), 1 otherwise
+                         and for the other kinds (measured: the 3D batch and the
                          bilinear hierarchy of Example 4.1 then miss their
                          tolerance, the graph Laplacian runs 8% slower; the
                          Wilson 256^2 trace takes 12% fewer FGMRES iterations
@@ -395,6 +400,28 @@ int mlmc_set_allocator(mlmc_alloc_fn alloc, mlmc_free_fn free_fn, void* user);
 int mlmc_batch_sample(mlmc_ctx* const* ctxs, int count, int level, const uint64_t* seeds,
                       int64_t first, int64_t nsamples, int workers, double* out,
                       double* seconds);
+
+/* Batch of independent problems (Sec. 4.1 samples of each) solved together on
+ * one GPU: the samples first..first+nsamples-1 of level `level` of every
+ * problem, identical to what mlmc_sample_level(ctxs[i], level, seeds[i], ...)
+ * returns.  All problems' solves run in lockstep on the first context's
+ * stream: each step of the refined CG is one launch over every problem still
+ * iterating, and each preconditioner application runs every problem's V-cycle
+ * position by position, one launch per position over the (problem, level,
+ * stage, tile) items of all problems at that position (mode 2).  Mode 1, one
+ * persistent launch per V-cycle with device-scope completion counts between
+ * its stages, is switched off and returns MLMC_EUNSUPPORTED.  Needs VARCOEF3D
+ * contexts with MLMC_FP32_IR64, equal nb and iteration limits, nu_pre and
+ * nu_post >= 1, one coarse-grid cycle (top_cycles 1), narrow_fp64 0, and the
+ * fused sweep on every smoothed level (even sides up to 128); otherwise
+ * MLMC_EUNSUPPORTED.  out: count x nsamples x 2 doubles (re, im),
+ * problem-major; status (count ints, caller-owned): per problem MLMC_OK, or
+ * the error of its first failing batch (the problem takes no further batches;
+ * its context names the sample, and out holds its samples as
+ * mlmc_sample_level leaves them).  Returns the first failing problem's status. */
+int mlmc_batch_sample_grouped(mlmc_ctx* const* ctxs, int count, int level,
+                              const uint64_t* seeds, int64_t first, int64_t nsamples, int mode,
+                              double* out, int* status);
 
 /* Counters of the last mlmc_trace / mlmc_sample_level / mlmc_solve call:
  * out[0] Krylov iterations (per batch), out[1] refinement steps,

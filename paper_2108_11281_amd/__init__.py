@@ -583,6 +583,27 @@ def batch_sample(estimators, level, seeds, first, nsamples, workers=4):
     return out[..., 0] + 1j * out[..., 1], sec
 
 
+def batch_sample_grouped(estimators, level, seeds, first, nsamples, persistent=False):
+    """Samples of one level on several problems solved in lockstep on one stream
+    (mlmc_batch_sample_grouped): each V-cycle of all problems as one launch per
+    stage position; persistent=True asks for the persistent form (switched off in
+    the library: MLMCError).  Returns (samples [count, nsamples] complex, status
+    per problem)."""
+    count = len(estimators)
+    ctxs = (ctypes.c_void_p * count)(*[e._ctx.value for e in estimators])
+    sd = (ctypes.c_uint64 * count)(*[int(v) for v in seeds])
+    out = np.zeros((count, int(nsamples), 2))
+    st = (ctypes.c_int * count)()
+    rc = lib().mlmc_batch_sample_grouped(ctxs, count, int(level), sd, int(first), int(nsamples),
+                                         1 if persistent else 2,
+                                         out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), st)
+    if rc != 0:
+        msgs = [e._lib.mlmc_last_error(e._ctx) for e in estimators]
+        msg = next((m.decode() for m in msgs if m), "")
+        raise MLMCError(rc, msg)
+    return out[..., 0] + 1j * out[..., 1], list(st)
+
+
 def run_estimator(levels, sample, tol, *, pilot=None, coarse=0.0, cost=None, **options):
     """Host-side estimator over a Python sampler (no device use).
 

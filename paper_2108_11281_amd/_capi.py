@@ -166,6 +166,10 @@ SIGNATURES = {
     "mlmc_batch_sample": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_uint64), ctypes.c_int64,
                                          ctypes.c_int64, ctypes.c_int, _D, _D]),
+    "mlmc_batch_sample_grouped": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.c_int,
+                                                 ctypes.POINTER(ctypes.c_uint64), ctypes.c_int64,
+                                                 ctypes.c_int64, ctypes.c_int, _D,
+                                                 ctypes.POINTER(ctypes.c_int)]),
     "mlmc_learned_train": (ctypes.c_int, [_P, _F, ctypes.POINTER(TrainOptions),
                                           ctypes.POINTER(TrainReport)]),
     "mlmc_learned_set_weights": (ctypes.c_int, [_P, _F]),

@@ -18,6 +18,7 @@ SOURCES = [
     "kernels_nn.hip",
     "kernels_csr.hip",
     "kernels_defl.hip",
+    "kernels_group.hip",
     "context.cpp",
     "context_complex.cpp",
     "context_nn.cpp",
@@ -27,6 +28,7 @@ SOURCES = [
     "estimator.cpp",
     "capi.cpp",
     "noalloc.cpp",
+    "group.cpp",
 ]
 
 FLAGS = [

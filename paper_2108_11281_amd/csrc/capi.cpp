@@ -386,6 +386,30 @@ int mlmc_batch_sample(mlmc_ctx* const* ctxs, int count, int level, const uint64_
   return MLMC_OK;
 }
 
+int mlmc_batch_sample_grouped(mlmc_ctx* const* ctxs, int count, int level,
+                              const uint64_t* seeds, int64_t first, int64_t nsamples, int mode,
+                              double* out, int* status) {
+  if (!ctxs || count < 1 || !seeds || !out || !status || nsamples < 1 || first < 0 ||
+      (mode != 1 && mode != 2))
+    return MLMC_EINVAL;
+  std::vector<Context*> cs(count);
+  for (int i = 0; i < count; ++i) {
+    cs[i] = as_ctx(ctxs[i]);
+    if (!cs[i]) return MLMC_EINVAL;
+    for (int j = 0; j < i; ++j)
+      if (cs[j] == cs[i]) return MLMC_EINVAL;
+    status[i] = MLMC_OK;
+  }
+  const int rc = guarded(cs[0], [&] {
+    MLMC_HIP(hipSetDevice(cs[0]->device()));
+    mlmc::group_batch_sample(cs, level, seeds, first, nsamples, mode, out, status);
+  });
+  if (rc != MLMC_OK) return rc;
+  for (int i = 0; i < count; ++i)
+    if (status[i] != MLMC_OK) return status[i];
+  return MLMC_OK;
+}
+
 int mlmc_counters(mlmc_ctx* c, int64_t* out, int n) {
   Context* ctx = as_ctx(c);
   if (!ctx || !out || n < 0 || n > 4) return MLMC_EINVAL;

@@ -45,8 +45,16 @@ Context::Context(const mlmc_operator& A, const mlmc_hierarchy& h, const mlmc_opt
     opt_.inner_tol = (A.kind == MLMC_WILSON2D || A.kind == MLMC_GAUGE2D) ? 1e-2 : 1e-3;
   MLMC_REQUIRE(o.top_cycles >= 0 && o.top_cycles <= 2, MLMC_EINVAL, "top_cycles must be 0, 1 or 2");
   // top_cycles 0: two coarse-grid cycles below the top level for the 2D Poisson
-  // operator (measured faster), one elsewhere
-  top_cycles_ = o.top_cycles > 0 ? o.top_cycles : (A.kind == MLMC_POISSON2D ? 2 : 1);
+  // operator with at least two pre- and post-smoothing sweeps (measured faster),
+  // one elsewhere.  The second cycle gives the coarse solve M2 = 2M - M A M, and
+  // M2 A = I - (I - M A)^2 is positive definite only while every eigenvalue of
+  // M A stays below 2: with one sweep on each side and over-correction 1.8 the
+  // 2D V-cycle's largest eigenvalue of M A is about 2.4 on hierarchies of five
+  // and more levels (1.45 with two sweeps), so CG would then run with an
+  // indefinite preconditioner and some columns stall
+  const bool two_sweeps = o.nu_pre >= 2 && o.nu_post >= 2;
+  top_cycles_ = o.top_cycles > 0 ? o.top_cycles
+                                 : (A.kind == MLMC_POISSON2D && two_sweeps ? 2 : 1);
   MLMC_REQUIRE(o.max_iter >= 1 && o.max_refine >= 1, MLMC_EINVAL, "iteration limits < 1");
   MLMC_REQUIRE(o.nu_pre >= 0 && o.nu_post >= 0, MLMC_EINVAL, "negative sweep count");
   MLMC_REQUIRE(o.min_samples >= 2, MLMC_EINVAL, "min_samples must be >= 2");

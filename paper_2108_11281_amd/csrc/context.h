@@ -101,7 +101,11 @@ struct Work {
 
 struct Estimate;
 
+class GroupSolver;
+
 class Context {
+  friend class GroupSolver;  // lockstep solves over several contexts
+
  public:
   Context(const mlmc_operator& A, const mlmc_hierarchy& h, const mlmc_options& o,
           hipStream_t s);
@@ -401,6 +405,12 @@ class Context {
   std::vector<double> defl_lambda_;
   double defl_direct_ = 0.0;
 };
+
+// level-difference samples of several VARCOEF3D problems solved in lockstep
+// (mode 1: persistent V-cycle stage kernel, 2: one launch per stage depth);
+// status: per problem MLMC_OK or its first failure
+void group_batch_sample(const std::vector<Context*>& cs, int level, const uint64_t* seeds,
+                        int64_t first, int64_t count, int mode, double* out, int* status);
 
 // splitmix64 finaliser (sampling of timed launches)
 inline uint64_t mix64(uint64_t z) {

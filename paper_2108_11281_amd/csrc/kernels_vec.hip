@@ -2,6 +2,7 @@
 #include <type_traits>
 
 #include "kernels.h"
+#include "vec_body.h"
 
 namespace mlmc {
 
@@ -53,31 +54,17 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void k_dot(const T* x, const T* y, int64_t n,
                                                   const int* active, c64* partials) {
   __shared__ double lds[16];
-  const int k = blockIdx.y, nblk = gridDim.x;
+  const int k = blockIdx.y;
   if (active && !active[k]) return;
-  const int64_t chunk = (n + nblk - 1) / nblk;
-  const int64_t lo = (int64_t)blockIdx.x * chunk;
-  const int64_t hi = lo + chunk < n ? lo + chunk : n;
-  const T* xc = x + (int64_t)k * n;
-  const T* yc = y + (int64_t)k * n;
-  double re = 0.0, im = 0.0;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += kThreads) cdot_acc(re, im, xc[i], yc[i]);
-  block_sum2<kThreads>(re, im, lds);
-  if (threadIdx.x == 0) partials[(int64_t)k * nblk + blockIdx.x] = {re, im};
+  body::dot(x, y, n, gridDim.x, blockIdx.x, k, true, partials, lds, threadIdx.x);
 }
 
 __global__ __launch_bounds__(kThreads) void k_finish(const c64* partials, int nblk,
                                                      c64* out) {
   __shared__ double lds[16];
   const int k = blockIdx.x;
-  double re = 0.0, im = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += kThreads) {
-    c64 v = partials[(int64_t)k * nblk + b];
-    re += v.re;
-    im += v.im;
-  }
-  block_sum2<kThreads>(re, im, lds);
-  if (threadIdx.x == 0) out[k] = {re, im};
+  const c64 v = body::finish(partials, nblk, k, lds);
+  if (threadIdx.x == 0) out[k] = v;
 }
 
 // k_finish followed by the CG step length (k_finish_alpha) or direction
@@ -88,18 +75,10 @@ __global__ __launch_bounds__(kThreads) void k_finish_alpha(const c64* partials, 
                                                            const int* active, c64* alpha) {
   __shared__ double lds[16];
   const int k = blockIdx.x;
-  double re = 0.0, im = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += kThreads) {
-    c64 v = partials[(int64_t)k * nblk + b];
-    re += v.re;
-    im += v.im;
-  }
-  block_sum2<kThreads>(re, im, lds);
+  const c64 v = body::finish(partials, nblk, k, lds);
   if (threadIdx.x == 0) {
-    pq[k] = {re, im};
-    double a = 0.0;
-    if ((!active || active[k]) && re != 0.0 && isfinite(re)) a = rz[k].re / re;
-    alpha[k] = {a, 0.0};
+    pq[k] = v;
+    body::alpha_rule(v, rz, active, k, alpha);
   }
 }
 
@@ -108,19 +87,10 @@ __global__ __launch_bounds__(kThreads) void k_finish_beta(const c64* partials, i
                                                           const int* active, c64* beta) {
   __shared__ double lds[16];
   const int k = blockIdx.x;
-  double re = 0.0, im = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += kThreads) {
-    c64 v = partials[(int64_t)k * nblk + b];
-    re += v.re;
-    im += v.im;
-  }
-  block_sum2<kThreads>(re, im, lds);
+  const c64 v = body::finish(partials, nblk, k, lds);
   if (threadIdx.x == 0) {
-    rz_new[k] = {re, im};
-    double b = 0.0;
-    if ((!active || active[k]) && rz[k].re != 0.0) b = re / rz[k].re;
-    beta[k] = {b, 0.0};
-    rz[k] = {re, im};
+    rz_new[k] = v;
+    body::beta_rule(v, rz, active, k, beta);
   }
 }
 
@@ -149,13 +119,8 @@ __global__ void k_mark(const c64* rr, const c64* ref, double tol2, int* active, 
   __shared__ int cnt;
   if (threadIdx.x == 0) cnt = 0;
   __syncthreads();
-  for (int k = threadIdx.x; k < nb; k += blockDim.x) {
-    int a = active[k];
-    if (a && rr[k].re <= tol2 * ref[k].re) a = 0;
-    if (a && !isfinite(rr[k].re)) a = 0;   // reported by the host as non-converged
-    active[k] = a;
-    if (a) atomicAdd(&cnt, 1);
-  }
+  for (int k = threadIdx.x; k < nb; k += blockDim.x)
+    if (body::mark_rule(rr, ref, tol2, active, k)) atomicAdd(&cnt, 1);
   __syncthreads();
   if (threadIdx.x == 0) *count = cnt;
 }
@@ -174,9 +139,7 @@ __global__ void k_ir_err(const c64* bd, const c64* rr_old, const c64* rr_new,
                          const int* active, c64* err, int nb) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nb || !active[k]) return;
-  const double mag = sqrt(bd[k].re * bd[k].re + bd[k].im * bd[k].im);
-  const double ratio = rr_old[k].re > 0.0 ? sqrt(rr_new[k].re / rr_old[k].re) : 1.0;
-  err[k] = {mag * ratio, 0.0};
+  body::ir_err_rule(bd, rr_old, rr_new, err, k);
 }
 
 // after a refinement: where the new FP64 residual exceeds the FP32 recursion's
@@ -186,7 +149,7 @@ __global__ void k_cg_restart(const c64* rr_new, const c64* rr_rec, c64* rz, cons
                              double factor, int nb) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nb || !active[k]) return;
-  if (!(rr_new[k].re <= factor * rr_rec[k].re)) rz[k] = {0.0, 0.0};
+  body::restart_rule(rr_new, rr_rec, rz, factor, k);
 }
 
 __global__ void k_set_count(int* c, int v) { *c = v; }
@@ -198,8 +161,7 @@ __global__ void k_refine_due(const c64* rr, const c64* rr_upd, const c64* bb, do
   __syncthreads();
   for (int k = threadIdx.x; k < nb; k += blockDim.x) {
     if (!active[k]) continue;
-    const double v = rr[k].re;
-    if (v <= delta2 * rr_upd[k].re || v <= tol2 * bb[k].re || !isfinite(v)) atomicAdd(&cnt, 1);
+    if (body::due_rule(rr, rr_upd, bb, delta2, tol2, k)) atomicAdd(&cnt, 1);
   }
   __syncthreads();
   if (threadIdx.x == 0) *count = cnt;
@@ -227,24 +189,10 @@ __global__ __launch_bounds__(kThreads) void k_cg_xr(T* x, T* r, const T* p, cons
                                                     const int* active, c64* partials,
                                                     int* tlog) {
   __shared__ double lds[16];
-  const int k = blockIdx.y, nblk = gridDim.x;
+  const int k = blockIdx.y;
   if (tlog && blockIdx.x == 0 && threadIdx.x == 0) tlog[k] = active ? active[k] : 1;
   if (active && !active[k]) return;
-  const c64 a = alpha[k];
-  const int64_t chunk = (n + nblk - 1) / nblk;
-  const int64_t lo = (int64_t)blockIdx.x * chunk;
-  const int64_t hi = lo + chunk < n ? lo + chunk : n;
-  const int64_t off = (int64_t)k * n;
-  double re = 0.0, im = 0.0;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += kThreads) {
-    T xi = x[off + i] + scale_by(a.re, a.im, p[off + i]);
-    T ri = r[off + i] - scale_by(a.re, a.im, q[off + i]);
-    x[off + i] = xi;
-    r[off + i] = ri;
-    cdot_acc(re, im, ri, ri);
-  }
-  block_sum2<kThreads>(re, im, lds);
-  if (threadIdx.x == 0) partials[(int64_t)k * nblk + blockIdx.x] = {re, im};
+  body::cg_xr(x, r, p, q, alpha[k], n, gridDim.x, blockIdx.x, k, partials, lds);
 }
 
 template <typename T>
@@ -268,49 +216,16 @@ __global__ void k_ir_acc(T64* y, const T32* d, int64_t n, const int* active) {
   y[j] = y[j] + convert<T64, T32>(d[j]);
 }
 
-// The FP64 refinement's fold of the FP32 correction, one pass: y += d,
-// partials of b^T d (the stated-error share, same blocks and order as k_dot),
-// d = 0.  Per column k; blocks as in k_dot.
+// The FP64 refinement's fold of the FP32 correction (one pass, per column k;
+// blocks as in k_dot)
 __global__ __launch_bounds__(kThreads) void k_ir_fold(double* y, float* d, const double* b,
                                                       int64_t n, const int* active,
                                                       c64* partials, int* tlog) {
   __shared__ double lds[16];
-  const int k = blockIdx.y, nblk = gridDim.x;
+  const int k = blockIdx.y;
   if (tlog && blockIdx.x == 0 && threadIdx.x == 0) tlog[k] = active ? active[k] : 1;
   if (active && !active[k]) return;
-  const int64_t chunk = (n + nblk - 1) / nblk;
-  const int64_t lo = (int64_t)blockIdx.x * chunk;
-  const int64_t hi = lo + chunk < n ? lo + chunk : n;
-  const int64_t off = (int64_t)k * n;
-  double re = 0.0, im = 0.0;
-  // groups of four elements per thread with every load issued before the
-  // arithmetic (twelve loads in flight); the dot accumulates in the order of a
-  // plain strided loop
-  constexpr int U = 4;
-  for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += U * kThreads) {
-    float dv[U];
-    double yv[U], bv[U];
-#pragma unroll
-    for (int j = 0; j < U; ++j) {
-      const int64_t i = i0 + (int64_t)j * kThreads;
-      const bool ok = i < hi;
-      dv[j] = ok ? d[off + i] : 0.0f;
-      yv[j] = ok ? y[off + i] : 0.0;
-      bv[j] = ok ? b[off + i] : 0.0;
-    }
-#pragma unroll
-    for (int j = 0; j < U; ++j) {
-      const int64_t i = i0 + (int64_t)j * kThreads;
-      if (i < hi) {
-        const double di = (double)dv[j];
-        y[off + i] = yv[j] + di;
-        cdot_acc(re, im, bv[j], di);
-        d[off + i] = 0.0f;
-      }
-    }
-  }
-  block_sum2<kThreads>(re, im, lds);
-  if (threadIdx.x == 0) partials[(int64_t)k * nblk + blockIdx.x] = {re, im};
+  body::ir_fold(y, d, b, n, gridDim.x, blockIdx.x, k, partials, lds);
 }
 
 template <typename T>
@@ -639,95 +554,15 @@ __global__ __launch_bounds__(kThreads) void k_dense_apply(const T* At, const T* 
   if (i < n && kok) Z[(int64_t)k * n + i] = acc;
 }
 
-// ---- coarsest solve as an MFMA GEMM: Z = B At (real types, n % 16 == 0) ----
-// One wave computes a 16 (RHS) x 16 (unknowns) tile of Z with
-// v_mfma_{f32,f64}_16x16x4.  Operand layout of these instructions (one block):
-// A (16x4): lane l holds A[l % 16][l / 16]; B (4x16): lane l holds
-// B[l / 16][l % 16]; D (16x16): lane l, register r holds D[row][l % 16] with
-// row = 4*(l/16) + r for the f32 form and row = 4*r + l/16 for the f64 form.
-// The reduction index is permuted inside each chunk of 16 (lane group g supplies
-// k = 4g + s at step s for both operands), which leaves the sum unchanged and
-// lets each lane load its A values as one vector.
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-
-template <typename T> struct Mfma;
-template <> struct Mfma<float> {
-  using acc_t = f32x4;
-  __device__ static acc_t step(float a, float b, acc_t c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  __device__ static int row(int g, int r) { return 4 * g + r; }
-};
-template <> struct Mfma<double> {
-  using acc_t = f64x4;
-  __device__ static acc_t step(double a, double b, acc_t c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  __device__ static int row(int g, int r) { return 4 * r + g; }
-};
-
-// A 256-thread block computes one 16 x 16 tile of Z; its four waves split the
-// reduction index (chunk ranges of 16), each keeping UNR chunks of loads in
-// flight, and the four partial tiles are summed in LDS in wave order.  At has
-// leading dimension ld (a multiple of 16; rows and columns n..ld-1 are zero);
-// B and Z columns have length n, so the tail of the last tile reads zeros and
-// writes nothing.
+// coarsest solve as an MFMA GEMM (the body's comment gives the tiling)
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_dense_apply_mfma(const T* __restrict__ At,
                                                                const T* __restrict__ B,
                                                                T* __restrict__ Z, int n, int ld,
                                                                int nb, const int* active) {
-  constexpr int UNR = 4;
-  __shared__ T part[4][4][64];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int i0 = blockIdx.x * 16;       // unknown tile
-  const int m0 = blockIdx.y * 16;       // RHS tile
-  const int g = lane >> 4, c = lane & 15;
-  const int row = m0 + c;               // RHS whose A-operand this lane supplies
-  const bool row_ok = row < nb;
-  const T* brow = B + (int64_t)(row_ok ? row : 0) * n;
-  const int chunks = ld / 16;
-  const int cbeg = wave * chunks / 4, cend = (wave + 1) * chunks / 4;
-  typename Mfma<T>::acc_t acc = {0, 0, 0, 0};
-  int ch = cbeg;
-  for (; ch + UNR <= cend; ch += UNR) {
-    T a[UNR][4], bv[UNR][4];
-#pragma unroll
-    for (int u = 0; u < UNR; ++u)
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int j = (ch + u) * 16 + 4 * g + s;
-        a[u][s] = (row_ok && j < n) ? brow[j] : (T)0;
-        bv[u][s] = At[(int64_t)j * ld + i0 + c];
-      }
-#pragma unroll
-    for (int u = 0; u < UNR; ++u)
-#pragma unroll
-      for (int s = 0; s < 4; ++s) acc = Mfma<T>::step(a[u][s], bv[u][s], acc);
-  }
-  for (; ch < cend; ++ch) {
-    T a[4], bv[4];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int j = ch * 16 + 4 * g + s;
-      a[s] = (row_ok && j < n) ? brow[j] : (T)0;
-      bv[s] = At[(int64_t)j * ld + i0 + c];
-    }
-#pragma unroll
-    for (int s = 0; s < 4; ++s) acc = Mfma<T>::step(a[s], bv[s], acc);
-  }
-#pragma unroll
-  for (int r = 0; r < 4; ++r) part[wave][r][lane] = acc[r];
-  __syncthreads();
-  if (wave == 0) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const T v = ((part[0][r][lane] + part[1][r][lane]) + part[2][r][lane]) + part[3][r][lane];
-      const int k = m0 + Mfma<T>::row(g, r);
-      if (k < nb && (!active || active[k]) && i0 + c < n) Z[(int64_t)k * n + i0 + c] = v;
-    }
-  }
+  __shared__ T part[4 * 4 * 64];
+  body::dense_apply_mfma(At, B, Z, n, ld, nb, active, blockIdx.x, blockIdx.y, true, part,
+                         (int)threadIdx.x);
 }
 
 }  // namespace

@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 SHIFT = 1e-3
 
 
-def _problems(sides, nb=16):
+def _problems(sides, nb=16, **opt):
     torch = require_gpu()
     import paper_2108_11281_amd as m
     ests = []
@@ -23,8 +23,13 @@ def _problems(sides, nb=16):
         ests.append(m.TraceEstimator("varcoef3d", N, L, L, shift=SHIFT,
                                      field=varcoef_faces(N, seed=1000 + p), nb=nb,
                                      precision="fp32_ir64", solve_tol=1e-12,
-                                     stream=torch.cuda.Stream()))
+                                     stream=torch.cuda.Stream(), **opt))
     return ests
+
+
+# the grouped tests bound the Krylov iterations (these solves take about 20),
+# so that a solver that stops converging fails with MLMC_ENOCONV at once
+BOUNDED = dict(max_iter=60, max_refine=2)
 
 
 def test_concurrent_batch_equals_sequential_and_oracle():
@@ -55,3 +60,66 @@ def test_batch_rejects_bad_arguments():
         m.batch_sample([ests[0], ests[0]], 1, [1, 2], 0, 4)     # same context twice
     with pytest.raises(m.MLMCError):
         m.batch_sample(ests, 5, [1, 2], 0, 4)                   # level not sampleable
+
+
+PERSISTENT_OFF = ("the persistent grouped V-cycle (workgroups waiting on device-scope "
+                  "completion counts) did not finish within the time limit on the GPU and "
+                  "is switched off in the library")
+
+
+@pytest.mark.parametrize("persistent", [
+    False, pytest.param(True, marks=pytest.mark.skip(reason=PERSISTENT_OFF))])
+def test_grouped_lockstep_equals_alone(persistent):
+    # all problems' solves in lockstep on one stream, V-cycles as one persistent
+    # launch (or one launch per stage depth): bit-identical to each problem
+    # sampled alone; two batches (16 + 4 columns), a two-level problem whose
+    # second solve is the coarsest direct solve
+    import paper_2108_11281_amd as m
+    sides = [16, 24, 8, 16]
+    ests = _problems(sides, **BOUNDED)
+    seeds = [1000 + p for p in range(len(sides))]
+    s_grp, st = m.batch_sample_grouped(ests, 1, seeds, 3, 20, persistent=persistent)
+    assert st == [0] * len(sides)
+    for p, e in enumerate(ests):
+        alone = e.sample_level(1, seeds[p], 3, 20)
+        assert np.array_equal(s_grp[p], alone), p
+
+
+def test_grouped_full_size_uneven_batch():
+    # the 3D batch's own configuration (nb 64, solve_tol 1e-10, coarsest levels
+    # of at most 512 cells) on four of its sizes, the largest 128^3: the grouped
+    # launches agree bit for bit with each problem alone
+    torch = require_gpu()
+    import paper_2108_11281_amd as m
+    sides = [128, 40, 72, 32]
+    ests = []
+    for p, N in enumerate(sides):
+        L = varcoef_levels(N)
+        ests.append(m.TraceEstimator("varcoef3d", N, L, L, shift=SHIFT,
+                                     field=varcoef_faces(N, seed=1000 + p), nb=64,
+                                     precision="fp32_ir64", solve_tol=1e-10,
+                                     nu_pre=2, nu_post=2, stream=torch.cuda.Stream(),
+                                     **BOUNDED))
+    seeds = [1000 + p for p in range(len(sides))]
+    s_d, st = m.batch_sample_grouped(ests, 1, seeds, 0, 64)
+    assert st == [0] * len(sides)
+    for p, e in enumerate(ests):
+        alone = e.sample_level(1, seeds[p], 0, 64)
+        assert np.array_equal(s_d[p], alone), p
+    for e in ests:
+        e.close()
+
+
+def test_grouped_rejects_unsupported():
+    import paper_2108_11281_amd as m
+    ests = _problems([8, 8])
+    with pytest.raises(m.MLMCError):
+        m.batch_sample_grouped([ests[0], ests[0]], 1, [1, 2], 0, 4)   # same context twice
+    with pytest.raises(m.MLMCError) as e:
+        m.batch_sample_grouped(ests, 1, [1, 2], 0, 4, persistent=True)  # switched off
+    assert e.value.code == -6
+    poisson = m.TraceEstimator("poisson2d", 32, 3, 3, nb=16)
+    with pytest.raises(m.MLMCError) as e:
+        m.batch_sample_grouped([ests[0], poisson], 1, [1, 2], 0, 4)   # not a 3D problem
+    assert e.value.code == -6
+    poisson.close()
