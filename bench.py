@@ -560,13 +560,15 @@ def run_batch(args, m, torch):
     setup_s = time.perf_counter() - t0
     log("setup %.2fs" % setup_s)
     ns = 64
-    grouped = args.workers == 0
+    grouped = args.workers <= 0
 
     def step(first, workers):
-        # workers 0: every problem in lockstep on one stream (grouped launches);
-        # else host worker threads, one HIP stream per problem
-        if workers == 0:
-            s, _ = m.batch_sample_grouped(ests, 1, seeds, first, ns)
+        # workers 0: every problem in lockstep on one stream, each V-cycle one
+        # launch per stage position; -1: the same with each V-cycle one
+        # persistent launch (a workgroup per problem and column pair); else host
+        # worker threads, one HIP stream per problem
+        if workers <= 0:
+            s, _ = m.batch_sample_grouped(ests, 1, seeds, first, ns, persistent=workers < 0)
             return s, None
         return m.batch_sample(ests, 1, seeds, first, ns, workers=workers)
 
@@ -602,8 +604,8 @@ def run_batch(args, m, torch):
     if not args.no_compare:
         # the other schedules on the same samples: host workers on four streams,
         # and one worker
-        for label, workers in (("grouped_lockstep", 0), ("four_workers", 4),
-                               ("one_worker", 1)):
+        for label, workers in (("grouped_positions", 0), ("grouped_persistent", -1),
+                               ("four_workers", 4), ("one_worker", 1)):
             if workers == args.workers:
                 continue
             step(0, workers)  # warm-up of this schedule
@@ -614,7 +616,7 @@ def run_batch(args, m, torch):
             compare[label + "_solves_per_s"] = round(2 * ns * len(ests) /
                                                      (time.perf_counter() - t1), 1)
         if grouped:
-            s_g, _ = step(0, 0)
+            s_g, _ = step(0, args.workers)
             s_w, _ = step(0, 4)
             compare["grouped_equals_workers_bitwise"] = bool(np.array_equal(s_g, s_w))
     for e in ests:
@@ -625,12 +627,15 @@ def run_batch(args, m, torch):
         cpu = cpu_baseline_varcoef(sides, seeds, ns)
     config = {"workload": "varcoef3d_batch32_N32-128_agg2x2x2_nb64_fp32ir64",
               "problems": len(sides), "sides": sides, "probes_per_problem": ns,
-              "schedule": ("grouped lockstep, one launch per V-cycle position" if grouped
-                           else "%d host workers, one stream per problem" % args.workers),
+              "schedule": ({0: "grouped lockstep, one launch per V-cycle position",
+                            -1: "grouped lockstep, one persistent launch per V-cycle"}
+                           .get(args.workers, "%d host workers, one stream per problem"
+                                % args.workers)),
               "solve_tol": 1e-10}
-    kname = ("V-cycle stage kernel kg_stages (3D sweeps, residual restriction, coarsest "
-             "solve of all problems)" if grouped
-             else "3D red-black sweep: k_vc_march<float> (both colours, one pass)")
+    kname = {0: "V-cycle stage kernels kg_stage (3D sweeps, residual restriction, coarsest "
+                "solve of all problems)",
+             -1: "persistent V-cycle kernel kg_vcycle_units (every stage of all problems)"}.get(
+        args.workers, "3D red-black sweep: k_vc_march<float> (both colours, one pass)")
     contract(args, round(value, 1), "solves/s", True, ms_per_step, "f32+f64ir",
              "synthetic (log-normal face coefficients sigma=1, Rademacher probes)", config,
              hbm_roofline(kname, tot, args.timing_stride), cpu, per_problem=per_problem,
@@ -879,7 +884,8 @@ def main():
     ap.add_argument("--nu", type=int, default=2, help="poisson1024: sweeps before and after")
     ap.add_argument("--workers", type=int, default=4,
                     help="varcoef_batch: host workers (0: all problems grouped in lockstep "
-                         "on one stream)")
+                         "on one stream, one launch per V-cycle position; -1: the same with "
+                         "one persistent launch per V-cycle)")
     ap.add_argument("--spin-split", action="store_true",
                     help="wilson*: spin-structure-preserving aggregation (Example 4.3)")
     ap.add_argument("--n-vec", type=int, default=0,

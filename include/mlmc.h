@@ -406,11 +406,13 @@ int mlmc_batch_sample(mlmc_ctx* const* ctxs, int count, int level, const uint64_
  * problem, identical to what mlmc_sample_level(ctxs[i], level, seeds[i], ...)
  * returns.  All problems' solves run in lockstep on the first context's
  * stream: each step of the refined CG is one launch over every problem still
- * iterating, and each preconditioner application runs every problem's V-cycle
- * position by position, one launch per position over the (problem, level,
- * stage, tile) items of all problems at that position (mode 2).  Mode 1, one
- * persistent launch per V-cycle with device-scope completion counts between
- * its stages, is switched off and returns MLMC_EUNSUPPORTED.  Needs VARCOEF3D
+ * iterating.  Each preconditioner application is, with mode 1, one persistent
+ * launch over the whole V-cycle of every problem: a workgroup per (problem,
+ * column pair) runs all levels and stages of its problem's V-cycle for its
+ * two columns (larger problems first), with no synchronisation between
+ * workgroups; with mode 2, one launch per V-cycle position and stage kernel
+ * over the (problem, level, stage, tile) items of all problems at that
+ * position.  Both give the same results.  Needs VARCOEF3D
  * contexts with MLMC_FP32_IR64, equal nb and iteration limits, nu_pre and
  * nu_post >= 1, one coarse-grid cycle (top_cycles 1), narrow_fp64 0, and the
  * fused sweep on every smoothed level (even sides up to 128); otherwise

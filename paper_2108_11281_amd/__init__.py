@@ -585,10 +585,10 @@ def batch_sample(estimators, level, seeds, first, nsamples, workers=4):
 
 def batch_sample_grouped(estimators, level, seeds, first, nsamples, persistent=False):
     """Samples of one level on several problems solved in lockstep on one stream
-    (mlmc_batch_sample_grouped): each V-cycle of all problems as one launch per
-    stage position; persistent=True asks for the persistent form (switched off in
-    the library: MLMCError).  Returns (samples [count, nsamples] complex, status
-    per problem)."""
+    (mlmc_batch_sample_grouped): persistent=True runs each V-cycle of all problems
+    as one persistent launch (a workgroup per problem and column pair), False as
+    one launch per stage position.  Returns (samples [count, nsamples] complex,
+    status per problem)."""
     count = len(estimators)
     ctxs = (ctypes.c_void_p * count)(*[e._ctx.value for e in estimators])
     sd = (ctypes.c_uint64 * count)(*[int(v) for v in seeds])

@@ -18,7 +18,7 @@ namespace mlmc {
 
 class GroupSolver {
  public:
-  explicit GroupSolver(std::vector<Context*> cs) : cs_(std::move(cs)) {}
+  GroupSolver(std::vector<Context*> cs, int mode) : cs_(std::move(cs)), mode_(mode) {}
   ~GroupSolver() { release(); }
   void batch_sample(int level, const uint64_t* seeds, int64_t first, int64_t count,
                     double* out, int* status);
@@ -53,6 +53,10 @@ class GroupSolver {
   void epilogue(Task& t);
 
   std::vector<Context*> cs_;
+  int mode_;  // 1: persistent V-cycle (a workgroup per problem and column pair), 2: per position
+  int* dunits_ = nullptr;  // persistent form: (first stage, end stage, column pair) per unit
+  int* hunits_ = nullptr;
+  int nunits_ = 0;
   hipStream_t s_ = nullptr;
   std::vector<hipStream_t> saved_;
   GTask* dtasks_ = nullptr;
@@ -65,8 +69,12 @@ class GroupSolver {
   int* dts_ = nullptr;       // item prefix sums
   int* hts_ = nullptr;
   int nst_ = 0, cap_st_ = 0, ntasks_cap_ = 0;
-  std::vector<int> depth_begin_;  // stage ranges per position
-  std::vector<int> depth_tbeg_;   // and their prefix arrays' offsets
+  // launches of a V-cycle: per position, one per stage kernel key; stages
+  // [s0, s1) of hst_, their prefix array at hts_[tbeg]
+  struct Launch {
+    int s0, s1, key, tbeg, total;
+  };
+  std::vector<Launch> launches_;
   // measurement (the first context's sweep timer on): stage-kernel launches
   // with their events and algorithmic bytes (active columns known on the host:
   // columns change state only at refinements)
@@ -121,9 +129,12 @@ void GroupSolver::alloc(int ntasks, int max_stages) {
     T->dev = c0->dalloc_n<int>(group_table_ints(ntasks));
     MLMC_HIP(hipHostMalloc((void**)&T->host, sizeof(int) * group_table_ints(ntasks)));
   }
+  const int max_units = ntasks * ((c0->nb_ + kGroupMarchCols - 1) / kGroupMarchCols);
+  dunits_ = c0->dalloc_n<int>(3 * max_units);
+  MLMC_HIP(hipHostMalloc((void**)&hunits_, sizeof(int) * 3 * max_units));
   dst_ = c0->dalloc_n<GStage>(max_stages);
   MLMC_HIP(hipHostMalloc((void**)&hst_, sizeof(GStage) * max_stages));
-  // prefix arrays: one per position, together at most 2 max_stages entries
+  // prefix arrays: one per launch, together at most 2 max_stages entries
   dts_ = c0->dalloc_n<int>(2 * max_stages + 2);
   MLMC_HIP(hipHostMalloc((void**)&hts_, sizeof(int) * (2 * max_stages + 2)));
 }
@@ -136,7 +147,7 @@ void GroupSolver::release() {
   };
   if (c0) {
     for (void* p : {(void*)dtasks_, (void*)dints_, (void*)A_.dev, (void*)R_.dev, (void*)dst_,
-                    (void*)dts_})
+                    (void*)dts_, (void*)dunits_})
       if (p) c0->dfree(p);
   }
   hf(htasks_);
@@ -145,6 +156,9 @@ void GroupSolver::release() {
   hf(R_.host);
   hf(hst_);
   hf(hts_);
+  hf(hunits_);
+  dunits_ = nullptr;
+  hunits_ = nullptr;
   dtasks_ = nullptr;
   dints_ = nullptr;
   A_.dev = R_.dev = nullptr;
@@ -299,36 +313,73 @@ void GroupSolver::build_stages(Task& t, int l, const float* b, float* x, const c
   (void)rz;
 }
 
-// stage arrays of the members' V-cycles, grouped by position in the V-cycle
-// (the stages of one position are independent: they belong to different
-// problems), with one prefix array of items per position
+// stage arrays of the members' V-cycles: position by position (the stages of
+// one position are independent: they belong to different problems), and
+// within a position grouped by stage kernel, one launch per group with its own
+// prefix array of items
 void GroupSolver::upload_stages(const std::vector<int>& members) {
   std::vector<Task>& tasks = *cur_;
+  if (mode_ == 1) {
+    // every member's stages in V-cycle order, one unit per column pair, the
+    // units of larger problems first (they take longest)
+    std::vector<int> order(members);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+      return htasks_[a].n > htasks_[b].n;
+    });
+    nst_ = 0;
+    nunits_ = 0;
+    stage_cols_.assign((size_t)cap_st_, 0);
+    for (int m : order) {
+      const Task& t = tasks[m];
+      const int s0 = nst_;
+      for (const GStage& g : t.seq) {
+        MLMC_REQUIRE(nst_ < cap_st_, MLMC_EINVAL, "grouped V-cycle: too many stages");
+        stage_cols_[(size_t)nst_] = active_cols_[(size_t)m];
+        hst_[nst_++] = g;
+      }
+      for (int p = 0; p * kGroupMarchCols < t.nb; ++p) {
+        hunits_[3 * nunits_] = s0;
+        hunits_[3 * nunits_ + 1] = nst_;
+        hunits_[3 * nunits_ + 2] = p;
+        ++nunits_;
+      }
+    }
+    MLMC_HIP(hipMemcpyAsync(dst_, hst_, sizeof(GStage) * nst_, hipMemcpyHostToDevice, s_));
+    MLMC_HIP(hipMemcpyAsync(dunits_, hunits_, sizeof(int) * 3 * nunits_, hipMemcpyHostToDevice,
+                            s_));
+    return;
+  }
   size_t maxlen = 0;
   for (int m : members) maxlen = std::max(maxlen, tasks[m].seq.size());
   nst_ = 0;
-  depth_begin_.assign(1, 0);
+  launches_.clear();
   stage_cols_.assign((size_t)cap_st_, 0);
-  for (size_t d = 0; d < maxlen; ++d) {
-    for (int m : members) {
-      const Task& t = tasks[m];
-      if (d >= t.seq.size()) continue;
-      MLMC_REQUIRE(nst_ < cap_st_, MLMC_EINVAL, "grouped V-cycle: too many stages");
-      stage_cols_[(size_t)nst_] = active_cols_[(size_t)m];
-      hst_[nst_++] = t.seq[d];
-    }
-    depth_begin_.push_back(nst_);
-  }
-  depth_tbeg_.clear();
   int off = 0;
-  for (size_t d = 0; d + 1 < depth_begin_.size(); ++d) {
-    depth_tbeg_.push_back(off);
-    int acc = 0;
-    for (int s = depth_begin_[d]; s < depth_begin_[d + 1]; ++s) {
+  for (size_t d = 0; d < maxlen; ++d) {
+    std::vector<std::pair<int, int>> pos;  // (key, member)
+    for (int m : members)
+      if (d < tasks[m].seq.size()) pos.push_back({group_stage_key(tasks[m].seq[d]), m});
+    std::stable_sort(pos.begin(), pos.end(),
+                     [](const std::pair<int, int>& a, const std::pair<int, int>& b) {
+                       return a.first < b.first;
+                     });
+    for (size_t i = 0; i < pos.size();) {
+      Launch L{nst_, nst_, pos[i].first, off, 0};
+      int acc = 0;
+      for (; i < pos.size() && pos[i].first == L.key; ++i) {
+        MLMC_REQUIRE(nst_ < cap_st_, MLMC_EINVAL, "grouped V-cycle: too many stages");
+        const int m = pos[i].second;
+        stage_cols_[(size_t)nst_] = active_cols_[(size_t)m];
+        hst_[nst_] = tasks[m].seq[d];
+        hts_[off++] = acc;
+        acc += hst_[nst_].tiles;
+        ++nst_;
+      }
       hts_[off++] = acc;
-      acc += hst_[s].tiles;
+      L.s1 = nst_;
+      L.total = acc;
+      launches_.push_back(L);
     }
-    hts_[off++] = acc;
   }
   MLMC_HIP(hipMemcpyAsync(dst_, hst_, sizeof(GStage) * nst_, hipMemcpyHostToDevice, s_));
   MLMC_HIP(hipMemcpyAsync(dts_, hts_, sizeof(int) * off, hipMemcpyHostToDevice, s_));
@@ -350,23 +401,40 @@ void GroupSolver::vcycle(const Tab& A) {
   (void)A;
   Context* c0 = cs_[0];
   const bool timing = c0->timing_ && (c0->timing_mask_ & (1u << Context::kTimGs));
-  for (size_t d = 0; d + 1 < depth_begin_.size(); ++d) {
-    const int s0 = depth_begin_[d], s1 = depth_begin_[d + 1];
-    const int total = hts_[depth_tbeg_[d] + (s1 - s0)];
+  if (mode_ == 1) {
     const bool sample =
         timing && (c0->timing_stride_ <= 1 ||
                    mix64((uint64_t)launch_seen_++) % (uint64_t)c0->timing_stride_ == 0);
     if (!sample) {
-      group_stages(dst_ + s0, s1 - s0, dts_ + depth_tbeg_[d], total, s_);
-      continue;
+      group_vcycle_units(dst_, dunits_, nunits_, s_);
+      return;
     }
     double bytes = 0.0;
-    for (int s = s0; s < s1; ++s) bytes += stage_bytes(hst_[s]) * stage_cols_[s];
+    for (int s = 0; s < nst_; ++s) bytes += stage_bytes(hst_[s]) * stage_cols_[s];
     LaunchEvents ev;
     ev.start = c0->event();
     ev.stop = c0->event();
     timing_events() = &ev;
-    group_stages(dst_ + s0, s1 - s0, dts_ + depth_tbeg_[d], total, s_);
+    group_vcycle_units(dst_, dunits_, nunits_, s_);
+    timing_events() = nullptr;
+    timed_.push_back({ev.start, ev.stop, bytes});
+    return;
+  }
+  for (const Launch& L : launches_) {
+    const bool sample =
+        timing && (c0->timing_stride_ <= 1 ||
+                   mix64((uint64_t)launch_seen_++) % (uint64_t)c0->timing_stride_ == 0);
+    if (!sample) {
+      group_stages(dst_ + L.s0, L.s1 - L.s0, dts_ + L.tbeg, L.total, L.key, s_);
+      continue;
+    }
+    double bytes = 0.0;
+    for (int s = L.s0; s < L.s1; ++s) bytes += stage_bytes(hst_[s]) * stage_cols_[s];
+    LaunchEvents ev;
+    ev.start = c0->event();
+    ev.stop = c0->event();
+    timing_events() = &ev;
+    group_stages(dst_ + L.s0, L.s1 - L.s0, dts_ + L.tbeg, L.total, L.key, s_);
     timing_events() = nullptr;
     timed_.push_back({ev.start, ev.stop, bytes});
   }
@@ -649,16 +717,16 @@ void GroupSolver::batch_sample(int level, const uint64_t* seeds, int64_t first, 
   release();
 }
 
-// entry from the C ABI.  mode 2: one stage-kernel launch per V-cycle position.
-// mode 1 (one persistent launch per V-cycle whose workgroups took items from a
-// queue and waited on device-scope completion counts of the previous stage)
-// is switched off: on the GPU its solves did not finish within the tests'
-// time limits.
+// entry from the C ABI.  mode 1: one persistent launch per V-cycle, a
+// workgroup per (problem, column pair) running all stages of its pair; mode 2:
+// one stage-kernel launch per V-cycle position and stage kernel.  (A form with
+// one workgroup per item of a shared queue, waiting on device-scope completion
+// counts of the previous stage, did not finish on the GPU within the tests'
+// time limits and was removed.)
 void group_batch_sample(const std::vector<Context*>& cs, int level, const uint64_t* seeds,
                         int64_t first, int64_t count, int mode, double* out, int* status) {
-  MLMC_REQUIRE(mode == 2, MLMC_EUNSUPPORTED,
-               "grouped solves: the persistent V-cycle (mode 1) is switched off; use mode 2");
-  GroupSolver g(cs);
+  MLMC_REQUIRE(mode == 1 || mode == 2, MLMC_EINVAL, "grouped solves: mode must be 1 or 2");
+  GroupSolver g(cs, mode);
   g.batch_sample(level, seeds, first, count, out, status);
 }
 

@@ -48,10 +48,20 @@ struct GStage {
   c64* partials;     // dot
 };
 
-// Runs a set of independent stages in one launch (grid = total items, item i
-// of the concatenated stages per workgroup).  tstart: prefix sums of the
-// stages' items (nst + 1 entries).
-void group_stages(const GStage* st, int nst, const int* tstart, int total, hipStream_t s);
+// kernel instance of a stage: its kind, or for sweeps one of 12 forms (rows
+// per wave 1, 2, 4 x from zero / from x / with correction / without)
+int group_stage_key(const GStage& g);
+// Runs a set of independent stages of one key in one launch (grid = total
+// items, item i of the concatenated stages per workgroup).  tstart: prefix
+// sums of the stages' items (nst + 1 entries).
+void group_stages(const GStage* st, int nst, const int* tstart, int total, int key,
+                  hipStream_t s);
+
+// Persistent V-cycle: one workgroup per unit (a problem's column pair) runs
+// every stage of that problem's V-cycle for its two columns.  units: nunits x
+// (first stage, end stage, column pair) into st; stage items and the bodies
+// are those of group_stages, restricted to the pair.
+void group_vcycle_units(const GStage* st, const int* units, int nunits, hipStream_t s);
 
 // ---- refined CG steps over several problems -----------------------------------
 struct GTask {

@@ -155,90 +155,177 @@ __global__ __launch_bounds__(kThreads) void kg_refine_rules(const GTask* tasks, 
 // ---------------------------------------------------------------------------
 // V-cycle stages
 // ---------------------------------------------------------------------------
-template <int RPW, int HX, int HE, int F>
-__device__ __forceinline__ void march(const GStage& g, int item, float* lds) {
-  const int bx = item % g.gx, rest = item / g.gx;
-  const int by = rest % g.gy, bz = rest / g.gy;
-  vcb::vc_march<float, kGroupMarchCols, RPW, HX != 0, HE != 0, F>(
-      g.in, g.b, g.out, g.ec, g.ws, g.kl, g.dg, g.N, g.sz, g.nb, g.act, nullptr, bx, by, bz,
-      lds);
-}
-
-template <int RPW>
-__device__ __forceinline__ void march_rpw(const GStage& g, int item, float* lds) {
-  // the sweeps of a V-cycle: pre-smoothing from zero (0,0,0) and from x
-  // (1,0,0); post-smoothing with the folded correction (1,1,1) and without
-  // (1,0,1); other forms are not generated
-  if (!g.hx) march<RPW, 0, 0, 0>(g, item, lds);
-  else if (!g.f) march<RPW, 1, 0, 0>(g, item, lds);
-  else if (g.he) march<RPW, 1, 1, 1>(g, item, lds);
-  else march<RPW, 1, 0, 1>(g, item, lds);
-}
-
-struct StageLds {
-  union {
-    float march[vcb::vc_march_lds<float, kGroupMarchCols, 1>()];
-    float part[2][4 * 4 * 64];
-    double red[2][16];
-  };
-};
-
-__device__ __forceinline__ void run_stage(const GStage& g, int item, StageLds& sm) {
-  const int tid = threadIdx.x;
-  switch (g.kind) {
-    case kGsMarch:
-      if (g.rpw == 1) march_rpw<1>(g, item, sm.march);
-      else if (g.rpw == 2) march_rpw<2>(g, item, sm.march);
-      else march_rpw<4>(g, item, sm.march);
-      break;
-    case kGsResRestrict:
-      vcb::vc_res_restrict<float, kGroupRrCols, kGroupThreads>(g.b, g.in, g.out, g.kl, g.dg, g.N,
-                                                               g.nb, g.act, nullptr,
-                                                               item % g.gx, item / g.gx, tid);
-      break;
-    case kGsDense: {
-      // two 256-thread blocks per item
-      const int half = tid >> 8;
-      const int vb = 2 * item + half;
-      const bool live = vb < g.gx * g.gy;
-      body::dense_apply_mfma<float>(g.At, g.in, g.out, (int)g.n, g.ld, g.nb, g.act, vb % g.gx,
-                                    vb / g.gx, live, sm.part[half], tid & 255);
-      break;
-    }
-    case kGsDot: {
-      const int half = tid >> 8;
-      const int vb = 2 * item + half;
-      const int k = vb / g.nblk;
-      const bool live = vb < g.nblk * g.nb && g.act[k];
-      body::dot(g.b, g.in, g.n, g.nblk, vb % g.nblk, live ? k : 0, live, g.partials,
-                sm.red[half], tid & 255);
-      break;
-    }
-    default: {  // kGsCopy
-      const int k = item / g.gx;
-      const int64_t i = (int64_t)(item % g.gx) * kGroupThreads + tid;
-      if (g.act[k] && i < g.n) g.out[(int64_t)k * g.n + i] = g.in[(int64_t)k * g.n + i];
-      break;
-    }
-  }
-}
-
-// One launch runs a set of independent stages: item i of the concatenated
-// stages per workgroup.
-__global__ __launch_bounds__(kGroupThreads) void kg_stages(const GStage* __restrict__ st, int nst,
-                                                         const int* __restrict__ tstart) {
-  __shared__ StageLds sm;
+// One launch runs stages of one kind and form (one kernel instance per kind,
+// rows per wave and sweep form, so that each has the registers of its own
+// body): item i of the concatenated stages per workgroup.
+template <int KIND, int RPW, int HX, int HE, int F>
+__global__ __launch_bounds__(kGroupThreads) void kg_stage(const GStage* __restrict__ st, int nst,
+                                                        const int* __restrict__ tstart) {
+  constexpr int kLds = KIND == kGsMarch ? vcb::vc_march_lds<float, kGroupMarchCols, RPW>()
+                                        : (KIND == kGsDense ? 2 * 4 * 4 * 64 : 64);
+  __shared__ __attribute__((aligned(16))) float lds[kLds];
   // item and stage indices are uniform over the workgroup
   const int t = blockIdx.x;
   const int s = __builtin_amdgcn_readfirstlane(find_slot(tstart, nst, t));
-  run_stage(st[s], __builtin_amdgcn_readfirstlane(t - tstart[s]), sm);
+  const GStage& g = st[s];
+  const int item = __builtin_amdgcn_readfirstlane(t - tstart[s]);
+  const int tid = threadIdx.x;
+  if constexpr (KIND == kGsMarch) {
+    const int bx = item % g.gx, rest = item / g.gx;
+    const int by = rest % g.gy, bz = rest / g.gy;
+    vcb::vc_march<float, kGroupMarchCols, RPW, HX != 0, HE != 0, F>(
+        g.in, g.b, g.out, g.ec, g.ws, g.kl, g.dg, g.N, g.sz, g.nb, g.act, nullptr, bx, by, bz,
+        lds);
+  } else if constexpr (KIND == kGsResRestrict) {
+    vcb::vc_res_restrict<float, kGroupRrCols, kGroupThreads>(g.b, g.in, g.out, g.kl, g.dg, g.N,
+                                                             g.nb, g.act, nullptr, item % g.gx,
+                                                             item / g.gx, tid);
+  } else if constexpr (KIND == kGsDense) {
+    // two 256-thread blocks per item
+    const int half = tid >> 8;
+    const int vb = 2 * item + half;
+    const bool live = vb < g.gx * g.gy;
+    body::dense_apply_mfma<float>(g.At, g.in, g.out, (int)g.n, g.ld, g.nb, g.act, vb % g.gx,
+                                  vb / g.gx, live, lds + half * 4 * 4 * 64, tid & 255);
+  } else if constexpr (KIND == kGsDot) {
+    const int half = tid >> 8;
+    const int vb = 2 * item + half;
+    const int k = vb / g.nblk;
+    const bool live = vb < g.nblk * g.nb && g.act[k];
+    body::dot(g.b, g.in, g.n, g.nblk, vb % g.nblk, live ? k : 0, live, g.partials,
+              reinterpret_cast<double*>(lds) + 16 * half, tid & 255);
+  } else {  // kGsCopy
+    const int k = item / g.gx;
+    const int64_t i = (int64_t)(item % g.gx) * kGroupThreads + tid;
+    if (g.act[k] && i < g.n) g.out[(int64_t)k * g.n + i] = g.in[(int64_t)k * g.n + i];
+  }
 }
 
 }  // namespace
 
-void group_stages(const GStage* st, int nst, const int* tstart, int total, hipStream_t s) {
+// ---------------------------------------------------------------------------
+// Persistent V-cycle: one workgroup per (problem, column pair) runs every
+// stage of that problem's V-cycle for its two columns, stage after stage,
+// with nothing shared between workgroups (a stage's items of other column
+// pairs belong to other workgroups, and no item reads another pair's columns),
+// so stages are ordered by the workgroup's own barriers.  Unit u: stages
+// [units[3u], units[3u+1]) of st, column pair units[3u+2].
+// ---------------------------------------------------------------------------
+template <int RPW, int HX, int HE, int F>
+__device__ __forceinline__ void unit_march(const GStage& g, int pair, float* lds) {
+  for (int bz = 0; bz < g.gz; ++bz)
+    for (int bx = 0; bx < g.gx; ++bx) {
+      vcb::vc_march<float, kGroupMarchCols, RPW, HX != 0, HE != 0, F>(
+          g.in, g.b, g.out, g.ec, g.ws, g.kl, g.dg, g.N, g.sz, g.nb, g.act, nullptr, bx, pair,
+          bz, lds);
+      __syncthreads();  // the next tile reuses the LDS rows
+    }
+}
+
+template <int RPW>
+__device__ __forceinline__ void unit_march_rpw(const GStage& g, int pair, float* lds) {
+  if (!g.hx) unit_march<RPW, 0, 0, 0>(g, pair, lds);
+  else if (!g.f) unit_march<RPW, 1, 0, 0>(g, pair, lds);
+  else if (g.he) unit_march<RPW, 1, 1, 1>(g, pair, lds);
+  else unit_march<RPW, 1, 0, 1>(g, pair, lds);
+}
+
+__global__ __launch_bounds__(kGroupThreads) void kg_vcycle_units(const GStage* __restrict__ st,
+                                                               const int* __restrict__ units) {
+  __shared__ __attribute__((aligned(16))) float lds[vcb::vc_march_lds<float, kGroupMarchCols, 1>()];
+  const int u = blockIdx.x;
+  const int s0 = units[3 * u], s1 = units[3 * u + 1], pair = units[3 * u + 2];
+  const int tid = threadIdx.x;
+  const int c0 = pair * kGroupMarchCols;
+  for (int s = s0; s < s1; ++s) {
+    const GStage& g = st[s];
+    switch (g.kind) {
+      case kGsMarch:
+        if (g.rpw == 1) unit_march_rpw<1>(g, pair, lds);
+        else if (g.rpw == 2) unit_march_rpw<2>(g, pair, lds);
+        else unit_march_rpw<4>(g, pair, lds);
+        break;
+      case kGsResRestrict:
+        // the pair is one column group of the restriction (kGroupRrCols == 2)
+        for (int bx = 0; bx < g.gx; ++bx)
+          vcb::vc_res_restrict<float, kGroupRrCols, kGroupThreads>(
+              g.b, g.in, g.out, g.kl, g.dg, g.N, g.nb, g.act, nullptr, bx, pair, tid);
+        break;
+      case kGsDense: {
+        // 16-column tile of the pair; only the pair's columns are computed
+        // and stored (the others belong to other workgroups)
+        const int by = c0 / 16;
+        const int half = tid >> 8;
+        for (int bx0 = 0; bx0 < g.gx; bx0 += 2) {
+          const int bx = bx0 + half;
+          body::dense_apply_mfma<float>(g.At, g.in, g.out, (int)g.n, g.ld, g.nb, g.act,
+                                        bx < g.gx ? bx : 0, by, bx < g.gx, lds + half * 1024,
+                                        tid & 255, c0, c0 + kGroupMarchCols);
+          __syncthreads();
+        }
+        break;
+      }
+      case kGsDot: {
+        const int half = tid >> 8;
+        for (int k = c0; k < c0 + kGroupMarchCols && k < g.nb; ++k) {
+          const bool on = g.act[k] != 0;
+          for (int b0 = 0; b0 < g.nblk; b0 += 2) {
+            const int bx = b0 + half;
+            const bool live = on && bx < g.nblk;
+            body::dot(g.b, g.in, g.n, g.nblk, live ? bx : 0, k, live, g.partials,
+                      reinterpret_cast<double*>(lds) + 16 * half, tid & 255);
+          }
+        }
+        break;
+      }
+      default:  // kGsCopy
+        for (int k = c0; k < c0 + kGroupMarchCols && k < g.nb; ++k) {
+          if (!g.act[k]) continue;
+          for (int64_t i = tid; i < g.n; i += kGroupThreads)
+            g.out[(int64_t)k * g.n + i] = g.in[(int64_t)k * g.n + i];
+        }
+        break;
+    }
+    // the next stage reads what this one wrote (other waves' stores included)
+    __syncthreads();
+  }
+}
+
+int group_stage_key(const GStage& g) {
+  if (g.kind != kGsMarch) return g.kind;
+  const int r = g.rpw == 1 ? 0 : (g.rpw == 2 ? 1 : 2);
+  const int v = !g.hx ? 0 : (!g.f ? 1 : (g.he ? 2 : 3));
+  return 16 + 4 * r + v;
+}
+
+void group_stages(const GStage* st, int nst, const int* tstart, int total, int key,
+                  hipStream_t s) {
   if (total <= 0) return;
-  MLMC_LAUNCH(kg_stages, dim3((unsigned)total), dim3(kGroupThreads), 0, s, st, nst, tstart);
+  const dim3 grid((unsigned)total), blk(kGroupThreads);
+#define KG(KIND, RPW, HX, HE, F) \
+  MLMC_LAUNCH((kg_stage<KIND, RPW, HX, HE, F>), grid, blk, 0, s, st, nst, tstart)
+#define KG_MARCH(R, RPW)                      \
+  case 16 + 4 * R + 0: KG(kGsMarch, RPW, 0, 0, 0); break; \
+  case 16 + 4 * R + 1: KG(kGsMarch, RPW, 1, 0, 0); break; \
+  case 16 + 4 * R + 2: KG(kGsMarch, RPW, 1, 1, 1); break; \
+  case 16 + 4 * R + 3: KG(kGsMarch, RPW, 1, 0, 1); break;
+  switch (key) {
+    case kGsResRestrict: KG(kGsResRestrict, 1, 0, 0, 0); break;
+    case kGsDense: KG(kGsDense, 1, 0, 0, 0); break;
+    case kGsDot: KG(kGsDot, 1, 0, 0, 0); break;
+    case kGsCopy: KG(kGsCopy, 1, 0, 0, 0); break;
+    KG_MARCH(0, 1)
+    KG_MARCH(1, 2)
+    KG_MARCH(2, 4)
+    default: throw Error(MLMC_EINVAL, "grouped V-cycle: unknown stage kernel");
+  }
+#undef KG_MARCH
+#undef KG
+}
+
+void group_vcycle_units(const GStage* st, const int* units, int nunits, hipStream_t s) {
+  if (nunits <= 0) return;
+  MLMC_LAUNCH(kg_vcycle_units, dim3((unsigned)nunits), dim3(kGroupThreads), 0, s, st, units);
 }
 
 void group_update_apply(const GTask* tasks, const int* tab, int blocks, int old_sel, int new_sel,

@@ -208,18 +208,21 @@ template <> struct Mfma<double> {
 // n..ld-1 are zero); B and Z columns have length n, so the tail of the last
 // tile reads zeros and writes nothing.  part: 4 x 4 x 64 T of LDS per block;
 // tid: thread within the block; `live` false: barriers only.
+// [klo, khi): the right-hand sides computed and stored (the others of the
+// tile are read as zero); the sums of the computed ones do not depend on it.
 template <typename T>
 __device__ __forceinline__ void dense_apply_mfma(const T* __restrict__ At, const T* __restrict__ B,
                                                  T* __restrict__ Z, int n, int ld, int nb,
                                                  const int* active, int bx, int by, bool live,
-                                                 T* part, int tid) {
+                                                 T* part, int tid, int klo = 0,
+                                                 int khi = 1 << 30) {
   constexpr int UNR = 4;
   const int wave = tid >> 6, lane = tid & 63;
   const int i0 = bx * 16;       // unknown tile
   const int m0 = by * 16;       // RHS tile
   const int g = lane >> 4, c = lane & 15;
   const int row = m0 + c;       // RHS whose A-operand this lane supplies
-  const bool row_ok = row < nb;
+  const bool row_ok = row < nb && row >= klo && row < khi;
   const T* brow = B + (int64_t)(row_ok ? row : 0) * n;
   const int chunks = live ? ld / 16 : 0;
   const int cbeg = wave * chunks / 4, cend = (wave + 1) * chunks / 4;
@@ -261,7 +264,8 @@ __device__ __forceinline__ void dense_apply_mfma(const T* __restrict__ At, const
                    part[(2 * 4 + r) * 64 + lane]) +
                   part[(3 * 4 + r) * 64 + lane];
       const int k = m0 + Mfma<T>::row(g, r);
-      if (k < nb && (!active || active[k]) && i0 + c < n) Z[(int64_t)k * n + i0 + c] = v;
+      if (k < nb && k >= klo && k < khi && (!active || active[k]) && i0 + c < n)
+        Z[(int64_t)k * n + i0 + c] = v;
     }
   }
 }

@@ -62,9 +62,11 @@ def test_batch_rejects_bad_arguments():
         m.batch_sample(ests, 5, [1, 2], 0, 4)                   # level not sampleable
 
 
-PERSISTENT_OFF = ("the persistent grouped V-cycle (workgroups waiting on device-scope "
-                  "completion counts) did not finish within the time limit on the GPU and "
-                  "is switched off in the library")
+PERSISTENT_OFF = ("the persistent grouped V-cycle with one workgroup per queue item, "
+                  "waiting on device-scope completion counts of the previous stage, did not "
+                  "finish within the time limit on the GPU and was removed from the library "
+                  "(the persistent form tested below gives each workgroup a problem's "
+                  "column pair instead)")
 
 
 @pytest.mark.parametrize("persistent", [
@@ -85,10 +87,26 @@ def test_grouped_lockstep_equals_alone(persistent):
         assert np.array_equal(s_grp[p], alone), p
 
 
+def test_grouped_persistent_units_equal_alone():
+    # the persistent V-cycle: one launch per preconditioner application, a
+    # workgroup per (problem, column pair) running every level and stage of its
+    # problem's V-cycle; odd column counts (a pair with one column), two
+    # batches, a two-level problem
+    import paper_2108_11281_amd as m
+    sides = [16, 24, 8, 16]
+    ests = _problems(sides, nb=15, **BOUNDED)
+    seeds = [1000 + p for p in range(len(sides))]
+    s_u, st = m.batch_sample_grouped(ests, 1, seeds, 3, 20, persistent=True)
+    assert st == [0] * len(sides)
+    for p, e in enumerate(ests):
+        alone = e.sample_level(1, seeds[p], 3, 20)
+        assert np.array_equal(s_u[p], alone), p
+
+
 def test_grouped_full_size_uneven_batch():
     # the 3D batch's own configuration (nb 64, solve_tol 1e-10, coarsest levels
-    # of at most 512 cells) on four of its sizes, the largest 128^3: the grouped
-    # launches agree bit for bit with each problem alone
+    # of at most 512 cells) on four of its sizes, the largest 128^3: both grouped
+    # schedules agree bit for bit with each problem alone
     torch = require_gpu()
     import paper_2108_11281_amd as m
     sides = [128, 40, 72, 32]
@@ -103,6 +121,9 @@ def test_grouped_full_size_uneven_batch():
     seeds = [1000 + p for p in range(len(sides))]
     s_d, st = m.batch_sample_grouped(ests, 1, seeds, 0, 64)
     assert st == [0] * len(sides)
+    s_u, st = m.batch_sample_grouped(ests, 1, seeds, 0, 64, persistent=True)
+    assert st == [0] * len(sides)
+    assert np.array_equal(s_u, s_d)
     for p, e in enumerate(ests):
         alone = e.sample_level(1, seeds[p], 0, 64)
         assert np.array_equal(s_d[p], alone), p
@@ -115,9 +136,6 @@ def test_grouped_rejects_unsupported():
     ests = _problems([8, 8])
     with pytest.raises(m.MLMCError):
         m.batch_sample_grouped([ests[0], ests[0]], 1, [1, 2], 0, 4)   # same context twice
-    with pytest.raises(m.MLMCError) as e:
-        m.batch_sample_grouped(ests, 1, [1, 2], 0, 4, persistent=True)  # switched off
-    assert e.value.code == -6
     poisson = m.TraceEstimator("poisson2d", 32, 3, 3, nb=16)
     with pytest.raises(m.MLMCError) as e:
         m.batch_sample_grouped([ests[0], poisson], 1, [1, 2], 0, 4)   # not a 3D problem
