@@ -50,9 +50,11 @@ def _poisson(N, L, precision):
 
 # sides 200 -> 100 -> 50 -> 25: the register-march kernels on 200 and 100
 # (ragged last wave of columns and last row segment), the LDS tile kernel on 50;
-# 128 -> 64 -> 32: power-of-two edges, the march kernel's smallest side (64)
+# 128 -> 64 -> 32: power-of-two edges, the march kernel's smallest side (64);
+# 512 -> 256 and 392 -> 196: five and three waves of 120 columns per row (512,
+# 256), the last one mostly outside the grid (392, 196)
 @pytest.mark.parametrize("precision", ["fp32_ir64", "fp64"])
-@pytest.mark.parametrize("N,L", [(200, 4), (128, 3)])
+@pytest.mark.parametrize("N,L", [(200, 4), (128, 3), (512, 3), (392, 3)])
 def test_poisson_sweeps_match_oracle(N, L, precision):
     est = _poisson(N, L, precision)
     A, _ = hierarchy.poisson_hierarchy(N, L)
@@ -62,8 +64,11 @@ def test_poisson_sweeps_match_oracle(N, L, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp32_ir64", "fp64"])
-def test_fused_two_sweep_pass_equals_two_passes_bitwise(precision):
-    est = _poisson(200, 3, precision)
+@pytest.mark.parametrize("N", [200, 512])
+def test_fused_two_sweep_pass_equals_two_passes_bitwise(precision, N):
+    # 200, 100: two waves of 120 columns per row, the second ragged, and one;
+    # 512, 256: five and three waves
+    est = _poisson(N, 3, precision)
     rng = np.random.default_rng(7)
     for level in (1, 2):
         n = est.level_size(level)
@@ -78,11 +83,13 @@ def test_fused_two_sweep_pass_equals_two_passes_bitwise(precision):
 
 
 @pytest.mark.parametrize("precision", ["fp32_ir64", "fp64"])
-def test_pre_pass_restricted_residual(precision):
+@pytest.mark.parametrize("N", [200, 384])
+def test_pre_pass_restricted_residual(precision, N):
     # the V-cycle's last pre-smoothing pass writes R (b - A x) with the swept x;
     # two fused sweeps do it in one pass, one sweep with the stand-alone kernel
-    est = _poisson(200, 3, precision)
-    A, P = hierarchy.poisson_hierarchy(200, 3)
+    # (384, 192: the restriction's 116-column waves, four and two per row)
+    est = _poisson(N, 3, precision)
+    A, P = hierarchy.poisson_hierarchy(N, 3)
     rng = np.random.default_rng(11)
     for level in (1, 2):
         n = est.level_size(level)
