@@ -461,6 +461,14 @@ int mlmc_kernel_stats(mlmc_ctx* ctx, int kernel, int fp64, double* out);
 int mlmc_kernel_stats_level(mlmc_ctx* ctx, int kernel, int fp64, int level, double* out);
 int mlmc_reset_kernel_stats(mlmc_ctx* ctx);
 
+/* Measurement of the sustained HBM rate (the practical peak beside the vendor
+ * figure): copies `bytes` from src_dev to dst_dev (device pointers, 16-byte
+ * aligned, bytes a multiple of 16, no overlap) with a streaming kernel of
+ * 16-byte loads and stores on hip_stream (NULL: the default stream); the copy
+ * moves 2 x bytes through HBM.  Asynchronous; MLMC_EINVAL on misaligned
+ * arguments. */
+int mlmc_stream_copy(const void* src_dev, void* dst_dev, size_t bytes, void* hip_stream);
+
 /* ---------------------------------------------------------------------------
  * Learned smoother (WILSON2D).  A 3-layer network of 3x3 periodic convolutions
  * without bias (8 -> 16 -> 16 -> 4 channels, ReLU after the first two) maps, per

@@ -583,6 +583,19 @@ def batch_sample(estimators, level, seeds, first, nsamples, workers=4):
     return out[..., 0] + 1j * out[..., 1], sec
 
 
+def stream_copy(src, dst):
+    """Device copy src -> dst (torch tensors of equal byte size, multiple of 16)
+    with the library's streaming kernel on torch's current stream."""
+    import torch
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nbytes
+    s = torch.cuda.current_stream().cuda_stream
+    rc = lib().mlmc_stream_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                nbytes, ctypes.c_void_p(s))
+    if rc != 0:
+        raise MLMCError(rc, "stream copy")
+
+
 def batch_sample_grouped(estimators, level, seeds, first, nsamples, persistent=False):
     """Samples of one level on several problems solved in lockstep on one stream
     (mlmc_batch_sample_grouped): persistent=True runs each V-cycle of all problems

@@ -166,6 +166,7 @@ SIGNATURES = {
     "mlmc_batch_sample": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_uint64), ctypes.c_int64,
                                          ctypes.c_int64, ctypes.c_int, _D, _D]),
+    "mlmc_stream_copy": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
     "mlmc_batch_sample_grouped": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.c_int,
                                                  ctypes.POINTER(ctypes.c_uint64), ctypes.c_int64,
                                                  ctypes.c_int64, ctypes.c_int, _D,

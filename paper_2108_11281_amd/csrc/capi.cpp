@@ -410,6 +410,15 @@ int mlmc_batch_sample_grouped(mlmc_ctx* const* ctxs, int count, int level,
   return MLMC_OK;
 }
 
+int mlmc_stream_copy(const void* src_dev, void* dst_dev, size_t bytes, void* hip_stream) {
+  if (!src_dev || !dst_dev || bytes % 16 != 0 || ((uintptr_t)src_dev | (uintptr_t)dst_dev) % 16)
+    return MLMC_EINVAL;
+  return guarded(nullptr, [&] {
+    mlmc::stream_copy(src_dev, dst_dev, bytes, static_cast<hipStream_t>(hip_stream));
+    MLMC_HIP(hipGetLastError());
+  });
+}
+
 int mlmc_counters(mlmc_ctx* c, int64_t* out, int n) {
   Context* ctx = as_ctx(c);
   if (!ctx || !out || n < 0 || n > 4) return MLMC_EINVAL;

@@ -53,6 +53,9 @@ void gram_finish(const double* part, int nchunks, int ma, int mb, double* C, hip
 void block_combine(const double* U, int kk, const double* C, int ldc, const double* X,
                    double* Out, int nc, int64_t n, double alpha, double beta, hipStream_t s);
 
+// streaming device copy of bytes (a multiple of 16, 16-byte aligned pointers)
+void stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
+
 // ----- vectors ---------------------------------------------------------------
 template <typename T>
 void vec_zero(T* x, int64_t n, int nb, const int* active, hipStream_t s);

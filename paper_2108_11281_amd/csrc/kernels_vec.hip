@@ -554,6 +554,25 @@ __global__ __launch_bounds__(kThreads) void k_dense_apply(const T* At, const T* 
   if (i < n && kok) Z[(int64_t)k * n + i] = acc;
 }
 
+// streaming copy (measurement of the sustained HBM rate): 16-byte loads and
+// stores, four per thread with all loads issued before the stores
+__global__ __launch_bounds__(kThreads) void k_stream_copy(const uint4* __restrict__ src,
+                                                          uint4* __restrict__ dst, int64_t n16) {
+  constexpr int U = 4;
+  const int64_t base = (int64_t)blockIdx.x * kThreads * U + threadIdx.x;
+  uint4 v[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t i = base + (int64_t)u * kThreads;
+    v[u] = i < n16 ? src[i] : uint4{0, 0, 0, 0};
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t i = base + (int64_t)u * kThreads;
+    if (i < n16) dst[i] = v[u];
+  }
+}
+
 // coarsest solve as an MFMA GEMM (the body's comment gives the tiling)
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_dense_apply_mfma(const T* __restrict__ At,
@@ -594,6 +613,15 @@ void vec_convert(const From* x, To* y, int64_t n, int nb, const int* active, hip
   if (n <= 0 || nb <= 0) return;
   hipLaunchKernelGGL((k_convert<To, From>), grid_cols(n, nb), dim3(kThreads), 0, s, x, y, n,
                      active);
+}
+
+void stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s) {
+  const int64_t n16 = (int64_t)(bytes / 16);
+  if (n16 == 0) return;
+  const int64_t per_block = (int64_t)kThreads * 4;
+  hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)((n16 + per_block - 1) / per_block)),
+                     dim3(kThreads), 0, s, static_cast<const uint4*>(src),
+                     static_cast<uint4*>(dst), n16);
 }
 
 int*& timing_log() {

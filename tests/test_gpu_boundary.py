@@ -136,3 +136,22 @@ def test_enoconv_keeps_partial_results_and_names_the_sample():
     ok = m.TraceEstimator("poisson2d", 64, 3, 3, nb=4, solve_tol=1e-12)
     s = ok.sample_level(1, 3, 10, 6)
     assert np.all(np.isfinite(s))
+
+
+def test_stream_copy_measurement_kernel():
+    # the streaming copy that measures the sustained HBM rate: exact copy of a
+    # multiple of 16 bytes (a ragged last group of four 16-byte words), and
+    # misaligned or ragged sizes rejected
+    torch = require_gpu()
+    import ctypes
+    import paper_2108_11281_amd as m
+    a = torch.arange(1 << 18, dtype=torch.float32, device="cuda") * 0.5 + 1.0
+    b = torch.zeros(a.numel() + 4, dtype=torch.float32, device="cuda")
+    m.stream_copy(a[: (1 << 18) - 12], b[: (1 << 18) - 12])
+    torch.cuda.synchronize()
+    assert torch.equal(b[: (1 << 18) - 12], a[: (1 << 18) - 12])
+    assert int(torch.count_nonzero(b[(1 << 18) - 12:])) == 0
+    lib = m.lib()
+    p = ctypes.c_void_p
+    assert lib.mlmc_stream_copy(p(a.data_ptr() + 4), p(b.data_ptr()), 64, None) == -1
+    assert lib.mlmc_stream_copy(p(a.data_ptr()), p(b.data_ptr()), 20, None) == -1
