@@ -45,11 +45,16 @@ __device__ __forceinline__ bf8 bf8_zero() {
 }
 
 // One forward convolution layer of a workgroup (4 waves): out region Ho x Wo
-// from the input region (Ho+2) x (Wo+2) in LDS ([site][CIN] BF16).  Output
-// either BF16 [site][16] (ReLU applied) or FP32 [site][4] (last layer).
-template <int CIN, int COUT, int NCH, bool RELU, bool F32OUT>
+// from the input region (Ho+2) x (Wo+2) in LDS ([site][CIN] BF16, or with PIN
+// two planes [CIN/8][site][8] of in_plane sites).  Output either BF16
+// [site][16] (ReLU applied; POUT: planes [2][site][8] of out_plane sites) or
+// FP32 [site][4] (last layer).  The planar form keeps the 16-byte operand
+// loads of 16 consecutive sites on consecutive LDS addresses (with [site][16]
+// they are 32 bytes apart and two of every eight lanes share banks).
+template <int CIN, int COUT, int NCH, bool RELU, bool F32OUT, bool PIN = false, bool POUT = false>
 __device__ void conv_fwd(const __bf16* __restrict__ in, int Wi, void* out, int Wo, int Ho,
-                         const bf8* __restrict__ frag, int wave, int lane) {
+                         const bf8* __restrict__ frag, int wave, int lane, int in_plane = 0,
+                         int out_plane = 0) {
   bf8 b[NCH];
 #pragma unroll
   for (int c = 0; c < NCH; ++c) b[c] = frag[c * 64 + lane];
@@ -68,7 +73,10 @@ __device__ void conv_fwd(const __bf16* __restrict__ in, int Wi, void* out, int W
       bf8 a = bf8_zero();
       if (pv && tap < 9) {
         const int ay = py + tap / 3, ax = px + tap % 3;
-        a = *reinterpret_cast<const bf8*>(in + (ay * Wi + ax) * CIN + ci0);
+        if constexpr (PIN)
+          a = *reinterpret_cast<const bf8*>(in + ((ci0 >> 3) * in_plane + ay * Wi + ax) * 8);
+        else
+          a = *reinterpret_cast<const bf8*>(in + (ay * Wi + ax) * CIN + ci0);
       }
       acc = mfma(a, b[c], acc);
     }
@@ -80,6 +88,8 @@ __device__ void conv_fwd(const __bf16* __restrict__ in, int Wi, void* out, int W
         if (RELU) v = fmaxf(v, 0.f);
         if (F32OUT)
           static_cast<float*>(out)[q * COUT + r16] = v;
+        else if (POUT)
+          static_cast<__bf16*>(out)[((r16 >> 3) * out_plane + q) * 8 + (r16 & 7)] = (__bf16)v;
         else
           static_cast<__bf16*>(out)[q * 16 + r16] = (__bf16)v;
       }
@@ -90,11 +100,17 @@ __device__ void conv_fwd(const __bf16* __restrict__ in, int Wi, void* out, int W
 // ---------------------------------------------------------------------------
 // inference
 // ---------------------------------------------------------------------------
+// the input region is dead once the first hidden layer is formed, and that
+// layer once the second is: each pair shares its LDS (two barriers between)
 struct NnApplyLds {
-  __bf16 x0[kT0 * kT0 * kC0];
-  __bf16 h1[kT1 * kT1 * 16];
-  __bf16 h2[kT2 * kT2 * 16];
-  float o[kTo * kTo * kC3];
+  union {
+    __bf16 x0[kT0 * kT0 * kC0];
+    __bf16 h2[2 * kT2 * kT2 * 8];  // planes [2][site][8]
+  };
+  union {
+    __bf16 h1[2 * kT1 * kT1 * 8];  // planes [2][site][8]
+    float o[kTo * kTo * kC3];
+  };
 };
 
 __global__ __launch_bounds__(256) void k_nn_apply(const c32* __restrict__ r, c32* __restrict__ x,
@@ -128,14 +144,16 @@ __global__ __launch_bounds__(256) void k_nn_apply(const c32* __restrict__ r, c32
     d[7] = links[site * 4 + 3];
   }
   __syncthreads();
-  conv_fwd<kC0, kC1, kCh1, true, false>(sm.x0, kT0, sm.h1, kT1, kT1, frag + kFragL1 * 64, wave,
-                                        lane);
+  conv_fwd<kC0, kC1, kCh1, true, false, false, true>(sm.x0, kT0, sm.h1, kT1, kT1,
+                                                     frag + kFragL1 * 64, wave, lane, 0,
+                                                     kT1 * kT1);
   __syncthreads();
-  conv_fwd<kC1, kC2, kCh2, true, false>(sm.h1, kT1, sm.h2, kT2, kT2, frag + kFragL2 * 64, wave,
-                                        lane);
+  conv_fwd<kC1, kC2, kCh2, true, false, true, true>(sm.h1, kT1, sm.h2, kT2, kT2,
+                                                    frag + kFragL2 * 64, wave, lane, kT1 * kT1,
+                                                    kT2 * kT2);
   __syncthreads();
-  conv_fwd<kC2, kC3, kCh3, false, true>(sm.h2, kT2, sm.o, kTo, kTo, frag + kFragL3 * 64, wave,
-                                        lane);
+  conv_fwd<kC2, kC3, kCh3, false, true, true, false>(sm.h2, kT2, sm.o, kTo, kTo,
+                                                     frag + kFragL3 * 64, wave, lane, kT2 * kT2);
   __syncthreads();
   {
     const int ly = tid / kTo, lx = tid - ly * kTo;
