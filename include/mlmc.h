@@ -299,10 +299,16 @@ int mlmc_apply(mlmc_ctx* ctx, int level, int nrhs, const double* x_dev, double* 
 /* Flags of mlmc_smooth. */
 enum mlmc_smooth_flags {
   MLMC_SMOOTH_REVERSE = 1,    /* odd colour first, as in post-smoothing */
-  MLMC_SMOOTH_ZERO_START = 2  /* start from X = 0 (x_dev's input is not read) with
+  MLMC_SMOOTH_ZERO_START = 2, /* start from X = 0 (x_dev's input is not read) with
                                  the zero-start kernel forms that the V-cycle's
                                  pre-smoothing runs; forward sweeps only
                                  (with MLMC_SMOOTH_REVERSE: MLMC_EINVAL) */
+  /* MLMC_CSR sweep schedule of this call instead of the level's autotuned one
+   * (the results do not depend on it; other kinds ignore these flags; both
+   * together: MLMC_EINVAL): */
+  MLMC_SMOOTH_CLASS_LAUNCHES = 4, /* one launch per colour class */
+  MLMC_SMOOTH_SHARED_TAIL = 8     /* the trailing colour classes of at most 16
+                                     slices (1024 rows) each share launches */
 };
 
 /* X <- `sweeps` red-black Gauss-Seidel sweeps of A_l X = B (the V-cycle's

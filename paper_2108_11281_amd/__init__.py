@@ -382,19 +382,24 @@ class TraceEstimator:
         return y
 
     def smooth(self, level, b, x, sweeps, reverse=False, restrict=False, zero_start=False,
-               noalloc=False):
+               noalloc=False, schedule=None):
         """`sweeps` red-black Gauss-Seidel sweeps of A_level x = b, in the working
         precision with the V-cycle's own kernels; returns the new x (x is not
         changed; with zero_start=True x may be None and the sweeps start from 0 with
         the pre-smoothing's zero-start kernels), and with restrict=True also
         R (b - A x) of it, as the V-cycle's last pre-smoothing pass forms it.
         reverse: second colour first, as in post-smoothing.  noalloc: through
-        mlmc_smooth_noalloc (working copies in the library's fixed workspace)."""
+        mlmc_smooth_noalloc (working copies in the library's fixed workspace).
+        schedule (CSR kind): None the level's tuned sweep schedule, "classes" a
+        launch per colour class, "shared_tail" the small trailing classes in
+        shared launches."""
         import torch
         y = torch.empty_like(b) if x is None else x.clone()
         rc = self._vec(level + 1, b.shape[0], b.device) if restrict else None
+        sched = {None: 0, "classes": _capi.SMOOTH_CLASS_LAUNCHES,
+                 "shared_tail": _capi.SMOOTH_SHARED_TAIL}[schedule]
         flags = (_capi.SMOOTH_REVERSE if reverse else 0) | \
-            (_capi.SMOOTH_ZERO_START if zero_start else 0)
+            (_capi.SMOOTH_ZERO_START if zero_start else 0) | sched
         fn = self._lib.mlmc_smooth_noalloc if noalloc else self._lib.mlmc_smooth
         self._c(fn(self._ctx, int(level), int(b.shape[0]), int(sweeps), flags, self._ptr(b),
                    self._ptr(y), self._ptr(rc) if restrict else None))

@@ -30,6 +30,8 @@ MAX_LEVELS = 16
 
 SMOOTH_REVERSE = 1
 SMOOTH_ZERO_START = 2
+SMOOTH_CLASS_LAUNCHES = 4
+SMOOTH_SHARED_TAIL = 8
 NOALLOC_SCRATCH_BYTES = 64 << 20
 
 

@@ -150,10 +150,10 @@ int mlmc_smooth(mlmc_ctx* c, int level, int nrhs, int sweeps, int flags, const d
   Context* ctx = as_ctx(c);
   if (!ctx || !b_dev || !x_dev) return MLMC_EINVAL;
   return guarded(ctx, [&] {
-    MLMC_REQUIRE((flags & ~(MLMC_SMOOTH_REVERSE | MLMC_SMOOTH_ZERO_START)) == 0, MLMC_EINVAL,
-                 "unknown smoother flags");
+    MLMC_REQUIRE(mlmc::smooth_flags_valid(flags), MLMC_EINVAL, "unknown smoother flags");
     ctx->smooth_fp64(level, nrhs, sweeps, (flags & MLMC_SMOOTH_REVERSE) != 0,
-                     (flags & MLMC_SMOOTH_ZERO_START) != 0, b_dev, x_dev, rc_dev);
+                     (flags & MLMC_SMOOTH_ZERO_START) != 0, b_dev, x_dev, rc_dev, nullptr, 0,
+                     mlmc::smooth_csr_tail(flags));
   });
 }
 

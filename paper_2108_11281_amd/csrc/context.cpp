@@ -1449,7 +1449,8 @@ void Context::apply_fp64(int level, int nrhs, const double* x, double* y) {
 // Poisson levels); reverse: second colour first, as in post-smoothing.  rc
 // (nullable): R (b - A x) of the final x, as the V-cycle's last pre-pass forms it
 void Context::smooth_fp64(int level, int nrhs, int sweeps, bool reverse, bool zero_start,
-                          const double* b, double* x, double* rc, void* ws, size_t ws_bytes) {
+                          const double* b, double* x, double* rc, void* ws, size_t ws_bytes,
+                          int csr_tail) {
   MLMC_REQUIRE(level >= 1 && level < Ls_, MLMC_EINVAL, "level out of range (no smoother on L_s)");
   MLMC_REQUIRE(nrhs >= 1 && nrhs <= nb_, MLMC_EINVAL, "nrhs must be in [1, nb]");
   MLMC_REQUIRE(sweeps >= 0, MLMC_EINVAL, "sweeps must be >= 0");
@@ -1510,8 +1511,9 @@ void Context::smooth_fp64(int level, int nrhs, int sweeps, bool reverse, bool ze
     } else if (csr_) {
       if (zero_start) vec_zero<T>(xa, n, nrhs, nullptr, s_);  // as the V-cycle starts
       for (int i = 0; i < sweeps; ++i)
-        csr_gs_sweep<T>(bt, xa, csr_sweep<T>(level), (int)n, nrhs, csr_cols(L, nrhs), nullptr,
-                        reverse, s_);
+        csr_gs_sweep<T>(bt, xa, csr_sweep<T>(level), (int)n, nrhs, csr_cols(L, nrhs),
+                        csr_tail >= 0 ? csr_tail : this->csr_tail(L, nrhs), nullptr, reverse,
+                        s_);
     } else if (varcoef_) {
       for (int i = 0; i < sweeps; ++i) {
         const bool z = zero_start && i == 0;

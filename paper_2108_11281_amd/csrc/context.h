@@ -47,6 +47,9 @@ struct Level {
   float *dg32 = nullptr, *kl32 = nullptr;
   int cols = 4;  // right-hand sides per thread of the stencil kernels (autotuned)
   int cols_narrow = 4;  // CSR kernels: the same for launches of at most 16 columns
+  // CSR sweep: largest class (in slices) of the trailing classes that share
+  // launches, full and narrow batches (autotuned; 0: a launch per class)
+  int tail_slices = 0, tail_slices_narrow = 0;
   int bsr_form[2] = {0, 0};  // block-stencil kernel form, complex64 / complex128 (autotuned)
   int mcols = 0;  // right-hand sides per wave of the fused 3D sweep (0: in-place sweeps)
   // POISSON2D: rows per segment of the fused sweep, FP32 and FP64 (autotuned)
@@ -121,9 +124,12 @@ class Context {
   void apply_fp64(int level, int nrhs, const double* x, double* y);
   // ws: nullptr (working copies allocated for the call) or a device workspace
   // of ws_bytes that holds them
+  // csr_tail (CSR levels): -1 the level's tuned sweep schedule, 0 a launch per
+  // colour class, > 0 the trailing classes of at most that many slices share
+  // launches
   void smooth_fp64(int level, int nrhs, int sweeps, bool reverse, bool zero_start,
                    const double* b, double* x, double* rc, void* ws = nullptr,
-                   size_t ws_bytes = 0);
+                   size_t ws_bytes = 0, int csr_tail = -1);
   void restrict_fp64(int level, int nrhs, const double* x, double* xc);
   void prolong_fp64(int level, int nrhs, const double* xc, double* x);
   void probes_fp64(int level, uint64_t seed, int stream, int64_t first, int nrhs,
@@ -215,6 +221,9 @@ class Context {
   // (narrow batches, such as the pilot and the first samples of a level, have
   // their own tuned value)
   int csr_cols(const Level& L, int nb) const { return nb <= 16 ? L.cols_narrow : L.cols; }
+  int csr_tail(const Level& L, int nb) const {
+    return nb <= 16 ? L.tail_slices_narrow : L.tail_slices;
+  }
   // red-black sweeps fused into one pass of the Poisson smoother on level l
   int sweeps_per_pass(int l) const { return lv_[l - 1].side >= 64 ? 2 : 1; }
   template <typename T> int gs_rows(int l) const {
@@ -411,6 +420,18 @@ class Context {
 // status: per problem MLMC_OK or its first failure
 void group_batch_sample(const std::vector<Context*>& cs, int level, const uint64_t* seeds,
                         int64_t first, int64_t count, int mode, double* out, int* status);
+
+// mlmc_smooth flags: known bits, at most one CSR sweep schedule; the schedule
+// as Context::smooth_fp64's csr_tail
+inline bool smooth_flags_valid(int flags) {
+  const int sched = MLMC_SMOOTH_CLASS_LAUNCHES | MLMC_SMOOTH_SHARED_TAIL;
+  return (flags & ~(MLMC_SMOOTH_REVERSE | MLMC_SMOOTH_ZERO_START | sched)) == 0 &&
+         (flags & sched) != sched;
+}
+inline int smooth_csr_tail(int flags) {
+  if (flags & MLMC_SMOOTH_CLASS_LAUNCHES) return 0;
+  return (flags & MLMC_SMOOTH_SHARED_TAIL) ? kTailWaves : -1;
+}
 
 // splitmix64 finaliser (sampling of timed launches)
 inline uint64_t mix64(uint64_t z) {

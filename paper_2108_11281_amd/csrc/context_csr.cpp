@@ -554,38 +554,60 @@ void Context::samples_batch_general(int level, uint64_t seed, uint64_t first, in
 // sweep with 1, 2, 4 and 8 right-hand sides per thread (the results are
 // identical; only the reuse of the row's indices and values and the
 // parallelism differ), once over all nb columns and once over a narrow batch
-// of 16, and keep the fastest of each for every CSR kernel of that level.
-// Runs once at setup on the library's own work vectors.
+// of 16, and keep the fastest of each for every CSR kernel of that level; then,
+// with that choice, the sweep's schedule of its trailing small colour classes
+// (a launch per class, or the trailing classes of at most 4, 16 or 64 slices
+// in shared launches: fewer launches, fewer compute units per class; the
+// results are identical).  Runs once at setup on the library's own work
+// vectors.
 void Context::tune_csr() {
   const bool fp32 = opt_.precision == MLMC_FP32_IR64;
   hipEvent_t a = event(), b = event();
+  auto time_sweep = [&](const Level& L, int ncols, int cols, int tail) {
+    float ms = 0.f;
+    for (int rep = 0; rep < 3; ++rep) {
+      MLMC_HIP(hipEventRecord(a, s_));
+      if (fp32)
+        csr_gs_sweep<float>(w32_.r, w32_.x, L.S32, (int)L.n, ncols, cols, tail, nullptr, false,
+                            s_);
+      else
+        csr_gs_sweep<double>(w64_.r, w64_.x, L.S64, (int)L.n, ncols, cols, tail, nullptr, false,
+                             s_);
+      MLMC_HIP(hipEventRecord(b, s_));
+      MLMC_HIP(hipEventSynchronize(b));
+      float t = 0.f;
+      MLMC_HIP(hipEventElapsedTime(&t, a, b));
+      if (rep > 0) ms += t;  // the first run warms caches and code
+    }
+    return ms;
+  };
   for (int l = 1; l < Ls_; ++l) {
     Level& L = lv_[l - 1];
+    const std::vector<int>& soff = L.S32.soff;
     for (int narrow = 0; narrow < 2; ++narrow) {
       const int ncols = narrow ? std::min(nb_, 16) : nb_;
       float best = 1e30f;
       int best_cols = 4;
       for (int cols : {1, 2, 4, 8}) {
-        float ms = 0.f;
-        for (int rep = 0; rep < 3; ++rep) {
-          MLMC_HIP(hipEventRecord(a, s_));
-          if (fp32)
-            csr_gs_sweep<float>(w32_.r, w32_.x, L.S32, (int)L.n, ncols, cols, nullptr, false, s_);
-          else
-            csr_gs_sweep<double>(w64_.r, w64_.x, L.S64, (int)L.n, ncols, cols, nullptr, false,
-                                 s_);
-          MLMC_HIP(hipEventRecord(b, s_));
-          MLMC_HIP(hipEventSynchronize(b));
-          float t = 0.f;
-          MLMC_HIP(hipEventElapsedTime(&t, a, b));
-          if (rep > 0) ms += t;  // the first run warms caches and code
-        }
+        const float ms = time_sweep(L, ncols, cols, 0);
         if (ms < best) {
           best = ms;
           best_cols = cols;
         }
       }
       (narrow ? L.cols_narrow : L.cols) = best_cols;
+      int best_tail = 0, last_start = csr_tail_start(soff, 0);
+      for (int tail : {4, 16, 64}) {
+        const int start = csr_tail_start(soff, tail);
+        if (start == last_start) continue;  // the same schedule as a smaller bound
+        last_start = start;
+        const float ms = time_sweep(L, ncols, best_cols, tail);
+        if (ms < best) {
+          best = ms;
+          best_tail = tail;
+        }
+      }
+      (narrow ? L.tail_slices_narrow : L.tail_slices) = best_tail;
     }
   }
   ev_pool_.push_back(a);
@@ -617,11 +639,11 @@ void Context::vcycle_csr(int l, const T* b, T* x, int nb, const int* act, c64* r
     const double res_mat = (double)nnz * (4.0 + sizeof(T)) + 4.0 * (double)n;
     const double enc = (double)sizeof(T) * (double)lv_[l].n;
     const int pre = opt_.nu_pre, post = opt_.nu_post;
-    const int cols = csr_cols(L, nb);
+    const int cols = csr_cols(L, nb), tail = csr_tail(L, nb);
     if (pre > 0) vec_zero<T>(x, n, nb, act, s_);
     for (int i = 0; i < pre; ++i)
       timed<T>(l, kTimGs, 3.0 * en + sweep_mat / nb, act, nb,
-               [&] { csr_gs_sweep<T>(b, x, S, (int)n, nb, cols, act, false, s_); });
+               [&] { csr_gs_sweep<T>(b, x, S, (int)n, nb, cols, tail, act, false, s_); });
     T* bc = w.vb[l];
     T* ec = w.vx[l];
     if (general_) {  // given P and R = P^T
@@ -654,7 +676,7 @@ void Context::vcycle_csr(int l, const T* b, T* x, int nb, const int* act, c64* r
     }
     for (int i = 0; i < post; ++i)
       timed<T>(l, kTimGs, 3.0 * en + sweep_mat / nb, act, nb,
-               [&] { csr_gs_sweep<T>(b, x, S, (int)n, nb, cols, act, true, s_); });
+               [&] { csr_gs_sweep<T>(b, x, S, (int)n, nb, cols, tail, act, true, s_); });
   }
   if (rz_partials) vec_dot_partials<T>(b, x, n, nb, act, rz_partials, s_);
 }

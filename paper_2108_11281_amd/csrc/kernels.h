@@ -425,11 +425,27 @@ template <typename T>
 void csr_update_apply(const T* p_old, const T* z, const c64* beta, T* p_new, T* q,
                       const CsrMat<T>& A, int nb, int cols, const int* active, c64* partials,
                       hipStream_t s);
-// one Gauss-Seidel sweep in place over the colour classes (reverse: last class
-// first); one launch per class
+// One Gauss-Seidel sweep in place over the colour classes (reverse: last class
+// first).  Each class is one launch, except the trailing run of classes of at
+// most tail_slices slices each (csr_tail_start; tail_slices 0: none), which
+// shares launches of up to kMaxTailClasses classes: one workgroup of
+// kTailWaves waves per column group, a barrier between classes.  The rows of a
+// class are independent, so both schedules give the same result.
+constexpr int kTailWaves = 16;
+constexpr int kMaxTailClasses = 64;
+struct CsrTail {
+  int count, reverse;
+  int soff[kMaxTailClasses + 1];
+};
+inline int csr_tail_start(const std::vector<int>& soff, int tail_slices) {
+  int c = (int)soff.size() - 1;
+  if (tail_slices <= 0) return c;
+  while (c > 0 && soff[c] - soff[c - 1] <= tail_slices) --c;
+  return c;
+}
 template <typename T>
 void csr_gs_sweep(const T* b, T* x, const CsrSweep<T>& S, int n, int nb, int cols,
-                  const int* active, bool reverse, hipStream_t s);
+                  int tail_slices, const int* active, bool reverse, hipStream_t s);
 // xc = R (b - A x) (b non-null; the residual goes through rtmp, n x nb) or
 // xc = R x (b null), R = P^T
 template <typename T>

@@ -177,10 +177,36 @@ __global__ __launch_bounds__(kThreads) void k_csr_update_apply(
   }
 }
 
-// one colour class of a Gauss-Seidel sweep, in place: the class owns slices
-// s0..s1-1; position k = 64 s + l holds row i = srow[k] (an independent set of
-// the matrix graph; -1 pads the last slice) and x_i = (b_i - sum_{j != i}
+// Row update of a Gauss-Seidel colour class, in place: position k = 64 sl +
+// lane of slice sl holds row i = srow[k] (an independent set of the matrix
+// graph; -1 pads the last slice of a class) and x_i = (b_i - sum_{j != i}
 // a_ij x_j) / a_ii with the off-diagonal entries of the slice
+template <typename T, int COLS>
+__device__ __forceinline__ void gs_row(const T* __restrict__ b, T* __restrict__ x,
+                                       const int* __restrict__ srow,
+                                       const int* __restrict__ sptr,
+                                       const int* __restrict__ sci, const T* __restrict__ sv,
+                                       const T* __restrict__ sdi, int sl, int lane, int n,
+                                       int col0, const bool* on) {
+  const int k = sl * 64 + lane;
+  const int i = srow[k];
+  if (i < 0) return;
+  T acc[COLS], sum[COLS];
+#pragma unroll
+  for (int q = 0; q < COLS; ++q) {
+    acc[q] = on[q] ? b[(int64_t)(col0 + q) * n + i] : T(0);
+    sum[q] = T(0);
+  }
+  sell_row_sum<T, COLS>(sci, sv, sptr[sl] + lane, (sptr[sl + 1] - sptr[sl]) >> 6, x, n, col0,
+                        on, sum);
+  const T d = sdi[k];
+#pragma unroll
+  for (int q = 0; q < COLS; ++q)
+    if (on[q]) x[(int64_t)(col0 + q) * n + i] = (acc[q] - sum[q]) * d;
+}
+
+// one colour class of a Gauss-Seidel sweep: the class owns slices s0..s1-1,
+// a wave per slice
 template <typename T, int COLS>
 __global__ __launch_bounds__(kThreads) void k_csr_gs(
     const T* __restrict__ b, T* __restrict__ x, const int* __restrict__ srow,
@@ -191,23 +217,40 @@ __global__ __launch_bounds__(kThreads) void k_csr_gs(
     tlog[col0 + threadIdx.x] = active ? active[col0 + threadIdx.x] : 1;
   const int sl = s0 + blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
   if (sl >= s1) return;
-  const int k = sl * 64 + (threadIdx.x & 63);
-  const int i = srow[k];
-  if (i < 0) return;
   bool on[COLS];
-  T acc[COLS], sum[COLS];
+#pragma unroll
+  for (int q = 0; q < COLS; ++q) on[q] = col_on(active, col0 + q, nb);
+  gs_row<T, COLS>(b, x, srow, sptr, sci, sv, sdi, sl, threadIdx.x & 63, n, col0, on);
+}
+
+// Several consecutive colour classes of a sweep in one launch (the small
+// classes a greedy colouring leaves at its end): one workgroup per column
+// group runs the classes one after another, in the sweep's direction, its
+// waves taking the slices of a class in turn; rows of one class are
+// independent, so only the class boundaries need the workgroup's barrier
+// (which also orders its waves' global stores before the next class's loads).
+template <typename T, int COLS>
+__global__ __launch_bounds__(kTailWaves * 64) void k_csr_gs_tail(
+    const T* __restrict__ b, T* __restrict__ x, const int* __restrict__ srow,
+    const int* __restrict__ sptr, const int* __restrict__ sci, const T* __restrict__ sv,
+    const T* __restrict__ sdi, CsrTail t, int n, int nb, const int* active, int* tlog) {
+  const int col0 = blockIdx.y * COLS;
+  if (tlog && threadIdx.x < COLS && col0 + (int)threadIdx.x < nb)
+    tlog[col0 + threadIdx.x] = active ? active[col0 + threadIdx.x] : 1;
+  bool on[COLS], any = false;
 #pragma unroll
   for (int q = 0; q < COLS; ++q) {
     on[q] = col_on(active, col0 + q, nb);
-    acc[q] = on[q] ? b[(int64_t)(col0 + q) * n + i] : T(0);
-    sum[q] = T(0);
+    any = any || on[q];
   }
-  sell_row_sum<T, COLS>(sci, sv, sptr[sl] + (threadIdx.x & 63), (sptr[sl + 1] - sptr[sl]) >> 6,
-                        x, n, col0, on, sum);
-  const T d = sdi[k];
-#pragma unroll
-  for (int q = 0; q < COLS; ++q)
-    if (on[q]) x[(int64_t)(col0 + q) * n + i] = (acc[q] - sum[q]) * d;
+  if (!any) return;  // the whole workgroup: its columns are all inactive
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int c = 0; c < t.count; ++c) {
+    const int cc = t.reverse ? t.count - 1 - c : c;
+    for (int sl = t.soff[cc] + wave; sl < t.soff[cc + 1]; sl += kTailWaves)
+      gs_row<T, COLS>(b, x, srow, sptr, sci, sv, sdi, sl, lane, n, col0, on);
+    __syncthreads();
+  }
 }
 
 // y = beta y + w M x, M rectangular (m rows, x of length nx per column)
@@ -335,17 +378,36 @@ void csr_update_apply(const T* p_old, const T* z, const c64* beta, T* p_new, T* 
 
 template <typename T>
 void csr_gs_sweep(const T* b, T* x, const CsrSweep<T>& S, int n, int nb, int cols,
-                  const int* active, bool reverse, hipStream_t s) {
+                  int tail_slices, const int* active, bool reverse, hipStream_t s) {
   const int classes = (int)S.soff.size() - 1;
-  for (int t = 0; t < classes; ++t) {
-    const int c = reverse ? classes - 1 - t : t;
+  const int tail = csr_tail_start(S.soff, tail_slices);
+  const unsigned gy = (unsigned)((nb + cols - 1) / cols);
+  auto one_class = [&](int c) {
     const int s0 = S.soff[c], s1 = S.soff[c + 1];
-    if (s1 == s0) continue;
+    if (s1 == s0) return;
     const int per = kThreads / 64;  // slices per block
-    const dim3 g((unsigned)((s1 - s0 + per - 1) / per), (unsigned)((nb + cols - 1) / cols));
+    const dim3 g((unsigned)((s1 - s0 + per - 1) / per), gy);
     CSR_COLS_DISPATCH(cols, MLMC_LAUNCH((k_csr_gs<T, C>), g, dim3(kThreads), 0, s, b, x, S.srow,
                                         S.sptr, S.sci, S.sv, S.sdi, s0, s1, n, nb, active,
                                         timing_log()));
+  };
+  auto fused = [&](int c0, int c1) {  // classes [c0, c1), at most kMaxTailClasses
+    CsrTail t;
+    t.count = c1 - c0;
+    t.reverse = reverse ? 1 : 0;
+    for (int c = c0; c <= c1; ++c) t.soff[c - c0] = S.soff[c];
+    CSR_COLS_DISPATCH(cols, MLMC_LAUNCH((k_csr_gs_tail<T, C>), dim3(1u, gy),
+                                        dim3(kTailWaves * 64), 0, s, b, x, S.srow, S.sptr,
+                                        S.sci, S.sv, S.sdi, t, n, nb, active, timing_log()));
+  };
+  if (!reverse) {
+    for (int c = 0; c < tail; ++c) one_class(c);
+    for (int c0 = tail; c0 < classes; c0 += kMaxTailClasses)
+      fused(c0, std::min(classes, c0 + kMaxTailClasses));
+  } else {
+    for (int c1 = classes; c1 > tail; c1 -= kMaxTailClasses)
+      fused(std::max(tail, c1 - kMaxTailClasses), c1);
+    for (int c = tail - 1; c >= 0; --c) one_class(c);
   }
 }
 
@@ -391,8 +453,8 @@ void csr_dense(const CsrMat<double>& A, double* aug, hipStream_t s) {
                             const int*, hipStream_t);                                         \
   template void csr_update_apply<T>(const T*, const T*, const c64*, T*, T*, const CsrMat<T>&,  \
                                     int, int, const int*, c64*, hipStream_t);                 \
-  template void csr_gs_sweep<T>(const T*, T*, const CsrSweep<T>&, int, int, int, const int*,   \
-                                bool, hipStream_t);                                           \
+  template void csr_gs_sweep<T>(const T*, T*, const CsrSweep<T>&, int, int, int, int,         \
+                                const int*, bool, hipStream_t);                               \
   template void csr_restrict<T>(const T*, const T*, T*, T*, const CsrMat<T>&,                  \
                                 const CsrAgg<T>&, int, int, const int*, hipStream_t);         \
   template void csr_prolong<T>(const T*, T*, const CsrAgg<T>&, int, double, double, int,       \

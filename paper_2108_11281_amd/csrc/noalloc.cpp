@@ -58,11 +58,10 @@ extern "C" int mlmc_smooth_noalloc(mlmc_ctx* c, int level, int nrhs, int sweeps,
                        hipGetErrorString(g_err[dev]));
       ws = g_ptr[dev];
     }
-    MLMC_REQUIRE((flags & ~(MLMC_SMOOTH_REVERSE | MLMC_SMOOTH_ZERO_START)) == 0, MLMC_EINVAL,
-                 "unknown smoother flags");
+    MLMC_REQUIRE(mlmc::smooth_flags_valid(flags), MLMC_EINVAL, "unknown smoother flags");
     ctx->smooth_fp64(level, nrhs, sweeps, (flags & MLMC_SMOOTH_REVERSE) != 0,
                      (flags & MLMC_SMOOTH_ZERO_START) != 0, b_dev, x_dev, rc_dev, ws,
-                     kScratchBytes);
+                     kScratchBytes, mlmc::smooth_csr_tail(flags));
     ctx->last_error.clear();
     return MLMC_OK;
   } catch (const mlmc::Error& e) {

@@ -224,21 +224,35 @@ def test_invalid_setup_is_rejected():
 @pytest.mark.parametrize("precision", ["fp64", "fp32_ir64"])
 def test_sweep_with_large_and_small_classes(precision):
     # 20000 unknowns: colour classes from 4332 rows (68 slices of 64) down to 2
-    # rows (one padded slice), thirteen launches per sweep
+    # rows (one padded slice); every schedule of the sweep (the tuned one, a
+    # launch per class, the small trailing classes in shared launches) gives the
+    # oracle's sweep, and the same bits
+    import paper_2108_11281_amd as m
     A = _graph(20000, isolated=0, seed=7)
     est = _est(A, 2, precision=precision, nb=4)
     col = hierarchy.first_fit_coloring(A)
     sizes = np.bincount(col)
     assert sizes.max() > 1024 and sizes.min() <= 1024
+    slices = (sizes + 63) // 64
+    tail = len(slices)
+    while tail > 0 and slices[tail - 1] <= 16:
+        tail -= 1
+    assert 0 < tail < len(slices) - 1   # both kernels, and a tail of several classes
     rng = np.random.default_rng(8)
     B = rng.standard_normal((3, A.shape[0]))
     X = rng.standard_normal((3, A.shape[0]))
     for rev in (False, True):
-        got = from_dev(est.smooth(1, to_dev(B), to_dev(X), 1, rev))
+        got = {sch: from_dev(est.smooth(1, to_dev(B), to_dev(X), 2, rev, schedule=sch))
+               for sch in (None, "classes", "shared_tail")}
+        assert np.array_equal(got["classes"], got["shared_tail"])
+        assert np.array_equal(got["classes"], got[None])
         for k in range(3):
-            ref = hierarchy.multicolour_gs_sweeps(A, B[k], X[k], col, 1, rev)
-            err = np.max(np.abs(got[k] - ref))
+            ref = hierarchy.multicolour_gs_sweeps(A, B[k], X[k], col, 2, rev)
+            err = np.max(np.abs(got[None][k] - ref))
             assert err <= TOL[precision] * np.max(np.abs(ref)), (rev, k, err)
+    Bd, Xd = to_dev(B), to_dev(X)
+    with pytest.raises(m.MLMCError):     # two schedules at once
+        est._c(est._lib.mlmc_smooth(est._ctx, 1, 3, 1, 4 | 8, est._ptr(Bd), est._ptr(Xd), None))
 
 
 def test_full_size_graph_workload():
