@@ -177,6 +177,10 @@ def kernel_table(est):
     return out
 
 
+CSR_SWEEP_LABEL = ("multicolour Gauss-Seidel sweep: k_csr_gs + k_csr_gs_tail<float> "
+                   "(all colour classes)")
+
+
 def hbm_roofline(name, stats, stride, traffic=None):
     launches, ms, nbytes = stats
     achieved = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
@@ -726,8 +730,7 @@ def run_graph(args, m, torch):
               "omega": args.omega if args.omega > 0 else 1.0}
     contract(args, round(ms_per_step / 1000.0, 4), "s", False, ms_per_step, "f32+f64ir",
              "synthetic (random geometric graph Laplacian + shift, Rademacher probes)", config,
-             hbm_roofline("multicolour Gauss-Seidel sweep: k_csr_gs<float> (all colour classes)",
-                          gs, args.timing_stride),
+             hbm_roofline(CSR_SWEEP_LABEL, gs, args.timing_stride),
              None, accuracy={"n_samples": [r["n_samples"] for r in runs],
                              "rmsd_rel": [round(r["rmsd"] / abs(r["trace"].real), 7)
                                           for r in runs]},
@@ -811,8 +814,7 @@ def run_laplace_bilinear(args, m, torch):
               "omega": args.omega if args.omega > 0 else 1.0}
     contract(args, round(ms_per_step / 1000.0, 4), "s", False, ms_per_step, "f32+f64ir",
              "synthetic (Example 4.1 Laplacian, Rademacher probes)", config,
-             hbm_roofline("multicolour Gauss-Seidel sweep: k_csr_gs<float> (all colour classes)",
-                          gs, args.timing_stride),
+             hbm_roofline(CSR_SWEEP_LABEL, gs, args.timing_stride),
              None, accuracy=accuracy, setup_s=round(setup_s, 3), kernels=kernels,
              compare=compare)
 
