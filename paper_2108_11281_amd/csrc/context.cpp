@@ -486,21 +486,26 @@ void Context::finish_real_build() {
   c64 tr_s;
   invert_coarse(Ls_, &ainv_solver_, &tr_s);
   // the transposed inverse, zero-padded to a multiple of 16 so that the MFMA
-  // tile kernel applies it for any coarsest size
+  // tile kernel applies it for any coarsest size, in that kernel's layout
   const int ns = (int)lv_[Ls_ - 1].n;
   const int ld = (ns + 15) / 16 * 16;
-  w64_.ainvT = dalloc_n<double>((int64_t)ld * ld);
+  double* plain = dalloc_n<double>((int64_t)ld * ld);
   w64_.ld = w32_.ld = ld;
   if (ld == ns) {
-    dense_transpose<double>(ainv_solver_, w64_.ainvT, ns, s_);
+    dense_transpose<double>(ainv_solver_, plain, ns, s_);
   } else {
     double* t = dalloc_n<double>((int64_t)ns * ns);
     dense_transpose<double>(ainv_solver_, t, ns, s_);
-    vec_zero<double>(w64_.ainvT, (int64_t)ld * ld, 1, nullptr, s_);
-    MLMC_HIP(hipMemcpy2DAsync(w64_.ainvT, sizeof(double) * ld, t, sizeof(double) * ns,
+    vec_zero<double>(plain, (int64_t)ld * ld, 1, nullptr, s_);
+    MLMC_HIP(hipMemcpy2DAsync(plain, sizeof(double) * ld, t, sizeof(double) * ns,
                               sizeof(double) * ns, ns, hipMemcpyDeviceToDevice, s_));
     dfree(t);
   }
+  static_assert(dense_mfma_layout<double>(16) && dense_mfma_layout<float>(16),
+                "the padded inverse is applied by the MFMA tile kernel");
+  w64_.ainvT = dalloc_n<double>((int64_t)ld * ld);
+  dense_pack4<double>(plain, w64_.ainvT, ld, s_);
+  dfree(plain);
   if (opt_.precision == MLMC_FP32_IR64) {
     w32_.ainvT = dalloc_n<float>((int64_t)ld * ld);
     vec_convert<float, double>(w64_.ainvT, w32_.ainvT, (int64_t)ld * ld, 1, nullptr, s_);

@@ -95,10 +95,12 @@ struct Work {
   // residual and correction of the second coarse-grid cycle below a solve's
   // top level (levels 2 .. L_s - 1, 0-based index; top_cycles = 2 only)
   std::vector<T*> vr2, ve2;
-  T* ainvT = nullptr;       // transposed inverse of the solver's coarsest operator
+  // transposed inverse of the solver's coarsest operator: real operators in
+  // the MFMA tile kernel's layout (dense_pack4), complex ones plain row-major
+  T* ainvT = nullptr;
   int ld = 0;               // its leading dimension (n rounded up to 16, zero padded)
   // complex operators: its real representation (2n x 2n, transposed) for the
-  // real MFMA product on interleaved vectors
+  // real MFMA product on interleaved vectors, in the tile kernel's layout
   typename Traits<T>::real* ainvR = nullptr;
 };
 

@@ -194,12 +194,19 @@ void Context::build_wilson(const double* theta) {
   }
   // the coarsest solve as a real MFMA product with the 2n x 2n real
   // representation (interleaved complex vectors are real vectors of length 2n)
-  if ((2 * ns) % 16 == 0) {
+  // (in the MFMA tile kernel's layout)
+  if (dense_mfma_layout<double>(2 * ns)) {
+    double* plain = dalloc_n<double>(4 * (int64_t)ns * ns);
+    dense_complex_to_real<c64, double>(wc64_.ainvT, plain, ns, s_);
     wc64_.ainvR = dalloc_n<double>(4 * (int64_t)ns * ns);
-    dense_complex_to_real<c64, double>(wc64_.ainvT, wc64_.ainvR, ns, s_);
+    dense_pack4<double>(plain, wc64_.ainvR, 2 * ns, s_);
+    dfree(plain);
     if (opt_.precision == MLMC_FP32_IR64) {
+      float* plain32 = dalloc_n<float>(4 * (int64_t)ns * ns);
+      dense_complex_to_real<c32, float>(wc32_.ainvT, plain32, ns, s_);
       wc32_.ainvR = dalloc_n<float>(4 * (int64_t)ns * ns);
-      dense_complex_to_real<c32, float>(wc32_.ainvT, wc32_.ainvR, ns, s_);
+      dense_pack4<float>(plain32, wc32_.ainvR, 2 * ns, s_);
+      dfree(plain32);
     }
   }
   if (L_ == Ls_) {

@@ -5,6 +5,7 @@
 
 #include <hip/hip_ext.h>
 
+#include <type_traits>
 #include <vector>
 
 #include "common.h"
@@ -160,11 +161,22 @@ void dense_inverse(T* M, int n, int64_t lda, T* out, T* rowbuf, T* colbuf, T* tb
 template <typename T>
 void dense_trace(const T* A, int n, c64* out, hipStream_t s);
 // Z[k][i] = sum_j At[j][i] B[k][j], k < nb: the coarsest solve z_k = A^{-1} b_k
-// with At the transposed inverse.  ld (0: n): leading dimension of At; with ld a
-// multiple of 16 (At zero-padded to ld x ld) the MFMA tile kernel runs for any n
+// with At the transposed inverse.  ld (0: n): leading dimension of At.  Real T
+// with ld a multiple of 16 (dense_mfma_layout): the MFMA tile kernel, for any
+// n, with At zero-padded to ld x ld and given in the layout of dense_pack4;
+// otherwise (ld == n) a plain row-major At.
 template <typename T>
 void dense_apply(const T* At, const T* B, T* Z, int n, int nb, const int* active,
                  hipStream_t s, int ld = 0);
+template <typename T>
+constexpr bool dense_mfma_layout(int ld) {
+  return (std::is_same<T, float>::value || std::is_same<T, double>::value) && ld % 16 == 0;
+}
+// the MFMA tile kernel's layout of an ld x ld row-major matrix At (ld a
+// multiple of 4): out[((j / 4) ld + i) 4 + j % 4] = At[j][i], so the four
+// consecutive rows j a lane reads for one column i are contiguous
+template <typename T>
+void dense_pack4(const T* At, T* out, int ld, hipStream_t s);
 // Mt (2n x 2n, real) = transposed real representation of the complex matrix
 // whose transpose is At, for dense_apply<R> on interleaved (re, im) vectors
 template <typename T, typename R>

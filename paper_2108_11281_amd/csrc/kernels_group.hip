@@ -12,6 +12,9 @@
 namespace mlmc {
 namespace {
 
+// LDS of one 16 x 16 coarsest-solve tile (its partial tiles)
+constexpr int kDenseTile = body::kDenseParts * 4 * 64;
+
 // task of block b: the last t with start[t] <= b
 __device__ __forceinline__ int find_slot(const int* start, int nt, int b) {
   int lo = 0, hi = nt;
@@ -162,7 +165,7 @@ template <int KIND, int RPW, int HX, int HE, int F>
 __global__ __launch_bounds__(kGroupThreads) void kg_stage(const GStage* __restrict__ st, int nst,
                                                         const int* __restrict__ tstart) {
   constexpr int kLds = KIND == kGsMarch ? vcb::vc_march_lds<float, kGroupMarchCols, RPW>()
-                                        : (KIND == kGsDense ? 2 * 4 * 4 * 64 : 64);
+                                        : (KIND == kGsDense ? 2 * kDenseTile : 64);
   __shared__ __attribute__((aligned(16))) float lds[kLds];
   // item and stage indices are uniform over the workgroup
   const int t = blockIdx.x;
@@ -186,7 +189,7 @@ __global__ __launch_bounds__(kGroupThreads) void kg_stage(const GStage* __restri
     const int vb = 2 * item + half;
     const bool live = vb < g.gx * g.gy;
     body::dense_apply_mfma<float>(g.At, g.in, g.out, (int)g.n, g.ld, g.nb, g.act, vb % g.gx,
-                                  vb / g.gx, live, lds + half * 4 * 4 * 64, tid & 255);
+                                  vb / g.gx, live, lds + half * kDenseTile, tid & 255);
   } else if constexpr (KIND == kGsDot) {
     const int half = tid >> 8;
     const int vb = 2 * item + half;
@@ -232,7 +235,9 @@ __device__ __forceinline__ void unit_march_rpw(const GStage& g, int pair, float*
 
 __global__ __launch_bounds__(kGroupThreads) void kg_vcycle_units(const GStage* __restrict__ st,
                                                                const int* __restrict__ units) {
-  __shared__ __attribute__((aligned(16))) float lds[vcb::vc_march_lds<float, kGroupMarchCols, 1>()];
+  constexpr int kMarchLds = vcb::vc_march_lds<float, kGroupMarchCols, 1>();
+  __shared__ __attribute__((aligned(16)))
+  float lds[kMarchLds > 2 * kDenseTile ? kMarchLds : 2 * kDenseTile];
   const int u = blockIdx.x;
   const int s0 = units[3 * u], s1 = units[3 * u + 1], pair = units[3 * u + 2];
   const int tid = threadIdx.x;
@@ -259,8 +264,9 @@ __global__ __launch_bounds__(kGroupThreads) void kg_vcycle_units(const GStage* _
         for (int bx0 = 0; bx0 < g.gx; bx0 += 2) {
           const int bx = bx0 + half;
           body::dense_apply_mfma<float>(g.At, g.in, g.out, (int)g.n, g.ld, g.nb, g.act,
-                                        bx < g.gx ? bx : 0, by, bx < g.gx, lds + half * 1024,
-                                        tid & 255, c0, c0 + kGroupMarchCols);
+                                        bx < g.gx ? bx : 0, by, bx < g.gx,
+                                        lds + half * kDenseTile, tid & 255, c0,
+                                        c0 + kGroupMarchCols);
           __syncthreads();
         }
         break;

@@ -573,15 +573,20 @@ __global__ __launch_bounds__(kThreads) void k_stream_copy(const uint4* __restric
   }
 }
 
-// coarsest solve as an MFMA GEMM (the body's comment gives the tiling)
+// coarsest solve as an MFMA GEMM (the body's comment gives the tiling): a
+// workgroup of kDenseParts waves per tile, one reduction range each, so every
+// wave has a single round of loads in flight for coarsest levels up to 1024
+// unknowns (the coarsest solves are latency-bound, not bandwidth-bound)
+constexpr int kDenseThreads = body::kDenseParts * 64;
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_dense_apply_mfma(const T* __restrict__ At,
-                                                               const T* __restrict__ B,
-                                                               T* __restrict__ Z, int n, int ld,
-                                                               int nb, const int* active) {
-  __shared__ T part[4 * 4 * 64];
-  body::dense_apply_mfma(At, B, Z, n, ld, nb, active, blockIdx.x, blockIdx.y, true, part,
-                         (int)threadIdx.x);
+__global__ __launch_bounds__(kDenseThreads) void k_dense_apply_mfma(const T* __restrict__ At,
+                                                                    const T* __restrict__ B,
+                                                                    T* __restrict__ Z, int n,
+                                                                    int ld, int nb,
+                                                                    const int* active) {
+  __shared__ T part[body::kDenseParts * 4 * 64];
+  body::dense_apply_mfma<T, body::kDenseParts>(At, B, Z, n, ld, nb, active, blockIdx.x,
+                                               blockIdx.y, true, part, (int)threadIdx.x);
 }
 
 }  // namespace
@@ -795,10 +800,10 @@ void dense_apply(const T* At, const T* B, T* Z, int n, int nb, const int* active
                  hipStream_t s, int ld) {
   if (ld == 0) ld = n;
   if constexpr (std::is_same<T, float>::value || std::is_same<T, double>::value) {
-    if (ld % 16 == 0) {
+    if (dense_mfma_layout<T>(ld)) {
       dim3 grid((unsigned)(ld / 16), (unsigned)((nb + 15) / 16));
-      hipLaunchKernelGGL(k_dense_apply_mfma<T>, grid, dim3(kThreads), 0, s, At, B, Z, n, ld, nb,
-                         active);
+      hipLaunchKernelGGL(k_dense_apply_mfma<T>, grid, dim3(kDenseThreads), 0, s, At, B, Z, n,
+                         ld, nb, active);
       return;
     }
   }
@@ -868,6 +873,19 @@ template <typename T>
 void dense_transpose(const T* in, T* out, int n, hipStream_t s) {
   hipLaunchKernelGGL(k_transpose<T>, dim3((n + 255) / 256, n), dim3(256), 0, s, in, out, n);
 }
+namespace {
+template <typename T>
+__global__ void k_pack4(const T* __restrict__ in, T* __restrict__ out, int ld) {
+  const int j = blockIdx.y;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ld; i += gridDim.x * blockDim.x)
+    out[((int64_t)(j >> 2) * ld + i) * 4 + (j & 3)] = in[(int64_t)j * ld + i];
+}
+}  // namespace
+template <typename T>
+void dense_pack4(const T* At, T* out, int ld, hipStream_t s) {
+  if (ld % 4 != 0) throw Error(MLMC_EINVAL, "dense_pack4: ld must be a multiple of 4");
+  hipLaunchKernelGGL(k_pack4<T>, dim3((ld + 255) / 256, ld), dim3(256), 0, s, At, out, ld);
+}
 // real representation of a complex matrix for the real MFMA product: with
 // A_ij = At[j][i] (complex, transposed), M (2n x 2n) acts on interleaved
 // (re, im) vectors -- M[2i+a][2j+c] = Re A_ij if a == c, -Im A_ij for (0, 1),
@@ -896,4 +914,6 @@ template void dense_transpose<float>(const float*, float*, int, hipStream_t);
 template void dense_transpose<double>(const double*, double*, int, hipStream_t);
 template void dense_transpose<c32>(const c32*, c32*, int, hipStream_t);
 template void dense_transpose<c64>(const c64*, c64*, int, hipStream_t);
+template void dense_pack4<float>(const float*, float*, int, hipStream_t);
+template void dense_pack4<double>(const double*, double*, int, hipStream_t);
 }  // namespace mlmc

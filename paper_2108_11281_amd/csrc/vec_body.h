@@ -201,22 +201,34 @@ template <> struct Mfma<double> {
   __device__ static int row(int g, int r) { return 4 * r + g; }
 };
 
-// A block of 256 threads computes the 16 x 16 tile (bx, by) of Z; its four
-// waves split the reduction index (chunk ranges of 16), each keeping UNR chunks
-// of loads in flight, and the four partial tiles are summed in LDS in wave
-// order.  At has leading dimension ld (a multiple of 16; rows and columns
-// n..ld-1 are zero); B and Z columns have length n, so the tail of the last
-// tile reads zeros and writes nothing.  part: 4 x 4 x 64 T of LDS per block;
-// tid: thread within the block; `live` false: barriers only.
-// [klo, khi): the right-hand sides computed and stored (the others of the
-// tile are read as zero); the sums of the computed ones do not depend on it.
-template <typename T>
-__device__ __forceinline__ void dense_apply_mfma(const T* __restrict__ At, const T* __restrict__ B,
+// The 16 x 16 tile (bx, by) of Z.  The reduction index, in chunks of 16, is
+// split into kDenseParts consecutive ranges; each range's partial tile is
+// accumulated in chunk order (UNR chunks of loads in flight), and the partial
+// tiles are summed in range order in LDS.  W waves per tile (W divides
+// kDenseParts): wave w computes its kDenseParts / W ranges one after another,
+// so the sums do not depend on W.  Pk is the transposed inverse in the packed
+// MFMA layout of dense_pack4 (leading dimension ld, a multiple of 16; rows and
+// columns n..ld-1 zero): the four reduction indices a lane supplies to one
+// chunk's four MFMA steps are 16 contiguous bytes (32 for FP64), as are its
+// four right-hand-side entries when n is a multiple of 4.  B and Z columns
+// have length n, so the tail of the last tile reads zeros and writes nothing.
+// part: kDenseParts x 4 x 64 T of LDS per tile; tid: thread within the tile's
+// W waves; `live` false: barriers only.  [klo, khi): the right-hand sides
+// computed and stored (the others of the tile are read as zero); the sums of
+// the computed ones do not depend on it.
+constexpr int kDenseParts = 16;
+template <typename T> struct Vec4 {
+  typedef T type __attribute__((ext_vector_type(4)));
+};
+template <typename T, int W = 4>
+__device__ __forceinline__ void dense_apply_mfma(const T* __restrict__ Pk, const T* __restrict__ B,
                                                  T* __restrict__ Z, int n, int ld, int nb,
                                                  const int* active, int bx, int by, bool live,
                                                  T* part, int tid, int klo = 0,
                                                  int khi = 1 << 30) {
-  constexpr int UNR = 4;
+  static_assert(kDenseParts % W == 0, "waves must divide the ranges");
+  using V4 = typename Vec4<T>::type;
+  constexpr int UNR = 4, PPW = kDenseParts / W;
   const int wave = tid >> 6, lane = tid & 63;
   const int i0 = bx * 16;       // unknown tile
   const int m0 = by * 16;       // RHS tile
@@ -224,45 +236,54 @@ __device__ __forceinline__ void dense_apply_mfma(const T* __restrict__ At, const
   const int row = m0 + c;       // RHS whose A-operand this lane supplies
   const bool row_ok = row < nb && row >= klo && row < khi;
   const T* brow = B + (int64_t)(row_ok ? row : 0) * n;
+  const bool bvec = (n & 3) == 0;  // B rows 16-byte aligned in groups of four
   const int chunks = live ? ld / 16 : 0;
-  const int cbeg = wave * chunks / 4, cend = (wave + 1) * chunks / 4;
-  typename Mfma<T>::acc_t acc = {0, 0, 0, 0};
-  int ch = cbeg;
-  for (; ch + UNR <= cend; ch += UNR) {
-    T a[UNR][4], bv[UNR][4];
+  // the four reduction indices 16 ch + 4 g + s (s = 0..3) of chunk ch
+  auto load = [&](int ch, T* a, T* bv) {
+    const int j = ch * 16 + 4 * g;
+    const V4 p = *reinterpret_cast<const V4*>(Pk + ((int64_t)(ch * 4 + g) * ld + i0 + c) * 4);
+    if (bvec) {
+      V4 q = {0, 0, 0, 0};
+      if (row_ok && j < n) q = *reinterpret_cast<const V4*>(brow + j);
 #pragma unroll
-    for (int u = 0; u < UNR; ++u)
+      for (int s = 0; s < 4; ++s) a[s] = q[s];
+    } else {
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int j = (ch + u) * 16 + 4 * g + s;
-        a[u][s] = (row_ok && j < n) ? brow[j] : (T)0;
-        bv[u][s] = At[(int64_t)j * ld + i0 + c];
-      }
-#pragma unroll
-    for (int u = 0; u < UNR; ++u)
-#pragma unroll
-      for (int s = 0; s < 4; ++s) acc = Mfma<T>::step(a[u][s], bv[u][s], acc);
-  }
-  for (; ch < cend; ++ch) {
-    T a[4], bv[4];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int j = ch * 16 + 4 * g + s;
-      a[s] = (row_ok && j < n) ? brow[j] : (T)0;
-      bv[s] = At[(int64_t)j * ld + i0 + c];
+      for (int s = 0; s < 4; ++s) a[s] = (row_ok && j + s < n) ? brow[j + s] : (T)0;
     }
 #pragma unroll
-    for (int s = 0; s < 4; ++s) acc = Mfma<T>::step(a[s], bv[s], acc);
-  }
+    for (int s = 0; s < 4; ++s) bv[s] = p[s];
+  };
+  for (int q = 0; q < PPW; ++q) {
+    const int p = wave * PPW + q;
+    const int cbeg = p * chunks / kDenseParts, cend = (p + 1) * chunks / kDenseParts;
+    typename Mfma<T>::acc_t acc = {0, 0, 0, 0};
+    int ch = cbeg;
+    for (; ch + UNR <= cend; ch += UNR) {
+      T a[UNR][4], bv[UNR][4];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) part[(wave * 4 + r) * 64 + lane] = acc[r];
+      for (int u = 0; u < UNR; ++u) load(ch + u, a[u], bv[u]);
+#pragma unroll
+      for (int u = 0; u < UNR; ++u)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc = Mfma<T>::step(a[u][s], bv[u][s], acc);
+    }
+    for (; ch < cend; ++ch) {
+      T a[4], bv[4];
+      load(ch, a, bv);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) acc = Mfma<T>::step(a[s], bv[s], acc);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) part[(p * 4 + r) * 64 + lane] = acc[r];
+  }
   __syncthreads();
   if (wave == 0 && live) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const T v = ((part[(0 * 4 + r) * 64 + lane] + part[(1 * 4 + r) * 64 + lane]) +
-                   part[(2 * 4 + r) * 64 + lane]) +
-                  part[(3 * 4 + r) * 64 + lane];
+      T v = part[r * 64 + lane];
+#pragma unroll
+      for (int p = 1; p < kDenseParts; ++p) v = v + part[(p * 4 + r) * 64 + lane];
       const int k = m0 + Mfma<T>::row(g, r);
       if (k < nb && k >= klo && k < khi && (!active || active[k]) && i0 + c < n)
         Z[(int64_t)k * n + i0 + c] = v;
