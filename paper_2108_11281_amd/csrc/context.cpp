@@ -175,7 +175,7 @@ void Context::alloc_work(Work<T>& w, int width) {
       w.vx[m] = dalloc_n<T>(lv_[m].n * cols);
     }
     if (m < Ls_ - 1) w.vt[m] = dalloc_n<T>(lv_[m].n * cols);
-    if (top_cycles_ == 2 && m > 0 && m < Ls_ - 1) {
+    if (top_cycles_ == 2 && m > 0 && m < Ls_ - 1 && (varcoef_ || csr_)) {
       w.vr2[m] = dalloc_n<T>(lv_[m].n * cols);
       w.ve2[m] = dalloc_n<T>(lv_[m].n * cols);
     }
@@ -618,14 +618,19 @@ void Context::op_restrict(int l, const T* x, T* xc, int nb, const int* act) {
     agg2d_restrict<T>(x, xc, L.side, nb, act, s_);
 }
 
-// ---------------------------------------------------------------------------
-// V-cycle of the 3D diffusion operator: in-place red-black sweeps (black first
-// after the coarse correction, so the preconditioner is symmetric), fused
-// residual + restriction, prolongation + omega-scaled correction.
-// ---------------------------------------------------------------------------
+// The second coarse-grid cycle, ec += V(bc - A ec) on level l + 1.  The 2D
+// Poisson V-cycle runs it as one V-cycle on bc whose pre-smoothing starts from
+// ec: Gauss-Seidel sweeps, the residual and the coarse correction are affine in
+// the iterate, so that V-cycle equals ec + V(bc - A ec) in exact arithmetic,
+// without the residual pass and the final addition (24 bytes per unknown and
+// column) at the cost of reading ec in the first pre-smoothing pass (4).
 template <typename T>
 void Context::second_coarse_cycle(int l, const T* bc, T* ec, int nb, const int* act, bool top) {
   if (!top || top_cycles_ != 2 || l + 1 >= Ls_) return;
+  if (!varcoef_ && !csr_) {
+    vcycle<T>(l + 1, bc, ec, nb, act, nullptr, false, ec);
+    return;
+  }
   Work<T>& w = work<T>();
   T* r2 = w.vr2[l];
   T* e2 = w.ve2[l];
@@ -633,6 +638,12 @@ void Context::second_coarse_cycle(int l, const T* bc, T* ec, int nb, const int* 
   vcycle<T>(l + 1, r2, e2, nb, act, nullptr);
   vec_add_to<T>(ec, e2, lv_[l].n, nb, act, s_);
 }
+
+// ---------------------------------------------------------------------------
+// V-cycle of the 3D diffusion operator: in-place red-black sweeps (black first
+// after the coarse correction, so the preconditioner is symmetric), fused
+// residual + restriction, prolongation + omega-scaled correction.
+// ---------------------------------------------------------------------------
 
 template <typename T>
 void Context::vcycle_vc(int l, const T* b, T* x, int nb, const int* act, c64* rz_partials,
@@ -734,7 +745,9 @@ void Context::vcycle_vc(int l, const T* b, T* x, int nb, const int* act, c64* rz
 // ---------------------------------------------------------------------------
 template <typename T>
 void Context::vcycle(int l, const T* b, T* x, int nb, const int* act, c64* rz_partials,
-                     bool top) {
+                     bool top, const T* x0) {
+  MLMC_REQUIRE(!x0 || (!varcoef_ && !csr_ && l < Ls_), MLMC_EINVAL,
+               "a V-cycle from a given iterate is the 2D Poisson smoothed levels' only");
   if (varcoef_) {
     vcycle_vc<T>(l, b, x, nb, act, rz_partials, top);
     return;
@@ -761,7 +774,7 @@ void Context::vcycle(int l, const T* b, T* x, int nb, const int* act, c64* rz_pa
   T* ec = w.vx[l];
   // pre-smoothing in passes of up to `per` sweeps: outputs alternate tmp, x, tmp,
   // ...; a last pass of two fused sweeps also writes the restricted residual
-  const T* u = nullptr;  // current iterate (nullptr = 0)
+  const T* u = x0;  // current iterate (nullptr = 0); the first pass never writes it
   bool restricted = false;
   for (int i = 0, pass = 0; i < pre; ++pass) {
     // an odd remainder goes first, so the last pass is a full one
@@ -1645,7 +1658,9 @@ template void Context::second_coarse_cycle<float>(int, const float*, float*, int
                                                   bool);
 template void Context::second_coarse_cycle<double>(int, const double*, double*, int, const int*,
                                                    bool);
-template void Context::vcycle<float>(int, const float*, float*, int, const int*, c64*, bool);
-template void Context::vcycle<double>(int, const double*, double*, int, const int*, c64*, bool);
+template void Context::vcycle<float>(int, const float*, float*, int, const int*, c64*, bool,
+                                      const float*);
+template void Context::vcycle<double>(int, const double*, double*, int, const int*, c64*, bool,
+                                       const double*);
 
 }  // namespace mlmc

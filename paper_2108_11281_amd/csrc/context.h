@@ -93,7 +93,8 @@ struct Work {
   // V-cycle right-hand side / solution / sweep scratch per level (0-based)
   std::vector<T*> vb, vx, vt;
   // residual and correction of the second coarse-grid cycle below a solve's
-  // top level (levels 2 .. L_s - 1, 0-based index; top_cycles = 2 only)
+  // top level (levels 2 .. L_s - 1, 0-based index; top_cycles = 2 of the 3D
+  // and CSR kinds only: the 2D Poisson V-cycle starts that cycle from ec)
   std::vector<T*> vr2, ve2;
   // transposed inverse of the solver's coarsest operator: real operators in
   // the MFMA tile kernel's layout (dense_pack4), complex ones plain row-major
@@ -297,9 +298,12 @@ class Context {
   template <typename T> void vcycle_vc(int l, const T* b, T* x, int nb, const int* act,
                                        c64* rz_partials, bool top = false);
   template <typename T> Work<T>& work();
-  // top: l is the solve's top level (top_cycles_ coarse-grid cycles there)
+  // top: l is the solve's top level (top_cycles_ coarse-grid cycles there).
+  // x0 (POISSON2D, not the coarsest level; nullable): the pre-smoothing starts
+  // from x0 instead of 0 (x0 may be x), which gives x0 + V(b - A x0)
   template <typename T> void vcycle(int l, const T* b, T* x, int nb, const int* act,
-                                    c64* rz_partials, bool top = false);
+                                    c64* rz_partials, bool top = false,
+                                    const T* x0 = nullptr);
   // with top and top_cycles_ == 2 (and level l + 1 not the coarsest): a second
   // coarse-grid cycle on level l + 1 on the residual of the first, ec += V(bc - A ec)
   template <typename T> void second_coarse_cycle(int l, const T* bc, T* ec, int nb,

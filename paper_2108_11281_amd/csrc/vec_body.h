@@ -204,7 +204,8 @@ template <> struct Mfma<double> {
 // The 16 x 16 tile (bx, by) of Z.  The reduction index, in chunks of 16, is
 // split into kDenseParts consecutive ranges; each range's partial tile is
 // accumulated in chunk order (UNR chunks of loads in flight), and the partial
-// tiles are summed in range order in LDS.  W waves per tile (W divides
+// tiles are summed in range order in LDS (wave r sums accumulator row r).  W
+// waves per tile (W >= 4 divides
 // kDenseParts): wave w computes its kDenseParts / W ranges one after another,
 // so the sums do not depend on W.  Pk is the transposed inverse in the packed
 // MFMA layout of dense_pack4 (leading dimension ld, a multiple of 16; rows and
@@ -226,7 +227,7 @@ __device__ __forceinline__ void dense_apply_mfma(const T* __restrict__ Pk, const
                                                  const int* active, int bx, int by, bool live,
                                                  T* part, int tid, int klo = 0,
                                                  int khi = 1 << 30) {
-  static_assert(kDenseParts % W == 0, "waves must divide the ranges");
+  static_assert(kDenseParts % W == 0 && W >= 4, "waves must divide the ranges (at least 4)");
   using V4 = typename Vec4<T>::type;
   constexpr int UNR = 4, PPW = kDenseParts / W;
   const int wave = tid >> 6, lane = tid & 63;
@@ -278,16 +279,14 @@ __device__ __forceinline__ void dense_apply_mfma(const T* __restrict__ Pk, const
     for (int r = 0; r < 4; ++r) part[(p * 4 + r) * 64 + lane] = acc[r];
   }
   __syncthreads();
-  if (wave == 0 && live) {
+  if (wave < 4 && live) {  // wave r sums accumulator row r of the partial tiles
+    const int r = wave;
+    T v = part[r * 64 + lane];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      T v = part[r * 64 + lane];
-#pragma unroll
-      for (int p = 1; p < kDenseParts; ++p) v = v + part[(p * 4 + r) * 64 + lane];
-      const int k = m0 + Mfma<T>::row(g, r);
-      if (k < nb && k >= klo && k < khi && (!active || active[k]) && i0 + c < n)
-        Z[(int64_t)k * n + i0 + c] = v;
-    }
+    for (int p = 1; p < kDenseParts; ++p) v = v + part[(p * 4 + r) * 64 + lane];
+    const int k = m0 + Mfma<T>::row(g, r);
+    if (k < nb && k >= klo && k < khi && (!active || active[k]) && i0 + c < n)
+      Z[(int64_t)k * n + i0 + c] = v;
   }
 }
 
