@@ -253,8 +253,8 @@ void Context::alloc_common() {
   for (int i = 0; i < kNumScalars; ++i) scal_[i] = sc + (int64_t)i * nb_;
   act_outer_ = dalloc_n<int>(nb_);
   act_inner_ = dalloc_n<int>(nb_);
-  count_dev_ = dalloc_n<int>(4);
-  MLMC_HIP(hipHostMalloc((void**)&count_host_, 4 * sizeof(int)));
+  count_dev_ = dalloc_n<int>(8);
+  MLMC_HIP(hipHostMalloc((void**)&count_host_, 8 * sizeof(int)));
   MLMC_HIP(hipHostMalloc((void**)&host_c64_, 8 * (size_t)nb_ * sizeof(c64)));
   b1_ = dalloc_n<double>(n1 * nb_ * elem);
   y1_ = dalloc_n<double>(n1 * nb_ * elem);
@@ -480,6 +480,7 @@ void Context::finish_real_build() {
     alloc_work(w32_);
     r32_ = dalloc_n<float>(n1 * nb_);
     d32_ = dalloc_n<float>(n1 * nb_);
+    if (kind_ == MLMC_POISSON2D) b32_ = dalloc_n<float>(n1 * nb_);
   }
 
   // coarsest inverses (FP64 on the device), the direct trace term (Remark 4.2)
@@ -1033,7 +1034,19 @@ void Context::pcg_refined(int l, const double* b, double* y, int nb, double tol,
   vec_copy<c64>(bb, rr_upd, 1, nb, nullptr, s_);
   vec_zero<double>(y, n, nb, nullptr, s_);
   vec_zero<float>(x32, n, nb, nullptr, s_);
-  vec_convert<float, double>(b, r, n, nb, nullptr, s_);
+  // The refinements read b from an FP32 copy when every entry of b is an FP32
+  // number (the 2D Poisson probes and their 2x2 restrictions, multiples of 1/2
+  // of small integers): the same values for 4 instead of 8 bytes per unknown
+  // in the fold and the residual.  Any other b keeps the FP64 reads (the check
+  // runs on the device; its flag is read at the first refinement check).
+  const bool try32 = b32_ != nullptr;
+  if (try32) {
+    rhs_fp32(b, r, b32_, n, nb, count_dev_ + 4, s_);
+    MLMC_HIP(hipMemcpyAsync(count_host_ + 4, count_dev_ + 4, sizeof(int), hipMemcpyDeviceToHost,
+                            s_));
+  } else {
+    vec_convert<float, double>(b, r, n, nb, nullptr, s_);
+  }
   bool fused = false;
   const int nvp = vcycle_partials<float>(l, &fused);
   vcycle<float>(l, r, w.z, nb, act, partials_, true);
@@ -1070,13 +1083,23 @@ void Context::pcg_refined(int l, const double* b, double* y, int nb, double tol,
   auto refine = [&](bool force) {
     MLMC_HIP(hipStreamSynchronize(s_));
     if (count_host_[1] == 0 && !force) return false;
+    const bool b_fp32 = try32 && count_host_[4] == 0;
+    const double bbytes = b_fp32 ? 4.0 : 8.0;
     // y += x32, bd = b^T x32, x32 = 0 in one pass (FP64 y, b and FP32 x32 in;
-    // y, x32 out: 32 bytes per unknown)
-    timed<double>(l, kTimIrFold, 32.0 * (double)n, act, nb,
-                  [&] { ir_fold(y, x32, b, n, nb, act, partials_, s_); });
+    // y, x32 out: 32 bytes per unknown, 28 with b in FP32)
+    timed<double>(l, kTimIrFold, (24.0 + bbytes) * (double)n, act, nb, [&] {
+      if (b_fp32)
+        ir_fold(y, x32, b32_, n, nb, act, partials_, s_);
+      else
+        ir_fold(y, x32, b, n, nb, act, partials_, s_);
+    });
     finish_sums(partials_, nblk, nb, bd, s_);
-    timed<double>(l, kTimIrResidual, 20.0 * (double)n, act, nb, [&] {
-      op_residual<double, double, float>(l, b, y, r, nb, act, partials_);
+    timed<double>(l, kTimIrResidual, (12.0 + bbytes) * (double)n, act, nb, [&] {
+      if (b_fp32)
+        poisson_residual<float, double, float>(b32_, y, r, L.side, L.d, L.c, nb, act, partials_,
+                                               s_);
+      else
+        op_residual<double, double, float>(l, b, y, r, nb, act, partials_);
     });
     finish_sums(partials_, ntiles, nb, rr_new, s_);
     ir_stated_error(bd, rr_upd, rr_new, act, err, nb, s_);

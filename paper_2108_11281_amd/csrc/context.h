@@ -401,13 +401,16 @@ class Context {
   double *b1_ = nullptr, *y1_ = nullptr, *b2_ = nullptr, *y2_ = nullptr, *r64_ = nullptr;
   float* r32_ = nullptr;
   float* d32_ = nullptr;
+  // POISSON2D with MLMC_FP32_IR64: the refined solve's right-hand side in FP32
+  // when every entry is an FP32 number (probes and their 2x2 restrictions)
+  float* b32_ = nullptr;
   c64* partials_ = nullptr;
   int64_t partials_cap_ = 0;
   // per-column scalar arrays (nb_ entries each); kErr1..kQb are consecutive
   enum { kRr0, kRz, kTmp, kAlpha, kBeta, kBb, kBd, kRres, kRres2, kErr1, kErr2, kQa, kQb,
          kNn, kNumScalars };
   c64* scal_[kNumScalars] = {};
-  int *act_outer_ = nullptr, *act_inner_ = nullptr, *count_dev_ = nullptr;  // count_dev_: 4 ints
+  int *act_outer_ = nullptr, *act_inner_ = nullptr, *count_dev_ = nullptr;  // count_dev_: 8 ints
   int* count_host_ = nullptr;
   c64* host_c64_ = nullptr;  // pinned, 8*nb
   // deflation: Ritz block V (the first defl_k_ vectors are U), work blocks W

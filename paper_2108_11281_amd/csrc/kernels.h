@@ -121,6 +121,13 @@ void cg_update_p(T* p, const T* z, const c64* beta, int64_t n, int nb,
 // blocks per column, as vec_dot_partials(b, d)), d = 0
 void ir_fold(double* y, float* d, const double* b, int64_t n, int nb, const int* active,
              c64* partials, hipStream_t s);
+// the same with b given in FP32 (exactly: the values of the FP64 b)
+void ir_fold(double* y, float* d, const float* b, int64_t n, int nb, const int* active,
+             c64* partials, hipStream_t s);
+// r = b32 = b rounded to FP32 (nb columns of n); *inexact = 0 when every entry of
+// b is an FP32 number (b32 then holds b exactly), else 1
+void rhs_fp32(const double* b, float* r, float* b32, int64_t n, int nb, int* inexact,
+              hipStream_t s);
 // y64 += convert(d)
 template <typename T64, typename T32>
 void ir_accumulate(T64* y, const T32* d, int64_t n, int nb, const int* active,

@@ -536,7 +536,12 @@ __global__ __launch_bounds__(kThreads) void k_residual_march(const Tb* __restric
   Tr* rc = r + (int64_t)m.k * n;
   const bool col_ok = m.x < N;
   const int xs = col_ok ? m.x : 0;
-  Tx cx[MY + 2], lx[MY], rx[MY];
+  // the wave's 64 lanes hold 64 consecutive columns: left and right neighbours
+  // come from lane shifts, and only lanes 0 and 63 load their outer neighbour
+  const int lane = threadIdx.x & 63;
+  const int xe = lane == 0 ? m.x - 1 : m.x + 1;
+  const bool edge = (lane == 0 || lane == 63) && xe >= 0 && xe < N;
+  Tx cx[MY + 2], ex[MY];
   Tb bb[MY];
 #pragma unroll
   for (int j = 0; j < MY + 2; ++j) {
@@ -547,15 +552,17 @@ __global__ __launch_bounds__(kThreads) void k_residual_march(const Tb* __restric
   for (int j = 0; j < MY; ++j) {
     const int yy = m.ybeg + j;
     const bool ok = col_ok && yy < m.yend;
-    lx[j] = ldz(xc, yy * N + xs - 1, ok && m.x > 0);
-    rx[j] = ldz(xc, yy * N + xs + 1, ok && m.x + 1 < N);
+    ex[j] = ldz(xc, yy * N + (edge ? xe : 0), ok && edge);
     bb[j] = ldz(bc, yy * N + xs, ok);
   }
   double dre = 0.0, dim = 0.0;
 #pragma unroll
   for (int j = 0; j < MY; ++j) {
     const int yy = m.ybeg + j;
-    const Tx ax = d * cx[j + 1] - c * (cx[j] + cx[j + 2] + lx[j] + rx[j]);
+    // columns at or beyond N hold zeros, as the Dirichlet boundary needs
+    const Tx sl = wave_shr1(cx[j + 1]), sr = wave_shl1(cx[j + 1]);
+    const Tx lxj = lane == 0 ? ex[j] : sl, rxj = lane == 63 ? ex[j] : sr;
+    const Tx ax = d * cx[j + 1] - c * (cx[j] + cx[j + 2] + lxj + rxj);
     const Tx v = convert<Tx, Tb>(bb[j]) - ax;
     if (col_ok && yy < m.yend) {
       rc[yy * N + m.x] = convert<Tr, Tx>(v);
@@ -891,5 +898,8 @@ template void poisson_residual<double, double, float>(const double*, const doubl
 template void poisson_residual<float, float, float>(const float*, const float*, float*, int,
                                                     double, double, int, const int*, c64*,
                                                     hipStream_t);
+template void poisson_residual<float, double, float>(const float*, const double*, float*, int,
+                                                     double, double, int, const int*, c64*,
+                                                     hipStream_t);
 
 }  // namespace mlmc

@@ -218,7 +218,8 @@ __global__ void k_ir_acc(T64* y, const T32* d, int64_t n, const int* active) {
 
 // The FP64 refinement's fold of the FP32 correction (one pass, per column k;
 // blocks as in k_dot)
-__global__ __launch_bounds__(kThreads) void k_ir_fold(double* y, float* d, const double* b,
+template <typename Tb>
+__global__ __launch_bounds__(kThreads) void k_ir_fold(double* y, float* d, const Tb* b,
                                                       int64_t n, const int* active,
                                                       c64* partials, int* tlog) {
   __shared__ double lds[16];
@@ -226,6 +227,24 @@ __global__ __launch_bounds__(kThreads) void k_ir_fold(double* y, float* d, const
   if (tlog && blockIdx.x == 0 && threadIdx.x == 0) tlog[k] = active ? active[k] : 1;
   if (active && !active[k]) return;
   body::ir_fold(y, d, b, n, gridDim.x, blockIdx.x, k, partials, lds);
+}
+
+// r = b32 = (float)b, and *inexact = 1 when some b_i is not an FP32 number
+__global__ void k_rhs_fp32(const double* __restrict__ b, float* __restrict__ r,
+                           float* __restrict__ b32, int64_t n, int* inexact) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  const int64_t j = (int64_t)blockIdx.y * n + i;
+  const double v = b[j];
+  const float f = (float)v;
+  r[j] = f;
+  b32[j] = f;
+  if ((double)f != v) *inexact = 1;
+}
+
+__global__ void k_fill_ints(int* p, int count, int v) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i < count) p[i] = v;
 }
 
 template <typename T>
@@ -730,8 +749,20 @@ void cg_update_p(T* p, const T* z, const c64* beta, int64_t n, int nb, const int
 void ir_fold(double* y, float* d, const double* b, int64_t n, int nb, const int* active,
              c64* partials, hipStream_t s) {
   if (n <= 0 || nb <= 0) return;
-  MLMC_LAUNCH(k_ir_fold, dim3(reduce_blocks(n), nb), dim3(kThreads), 0, s, y, d, b, n, active,
-              partials, timing_log());
+  MLMC_LAUNCH(k_ir_fold<double>, dim3(reduce_blocks(n), nb), dim3(kThreads), 0, s, y, d, b, n,
+              active, partials, timing_log());
+}
+void ir_fold(double* y, float* d, const float* b, int64_t n, int nb, const int* active,
+             c64* partials, hipStream_t s) {
+  if (n <= 0 || nb <= 0) return;
+  MLMC_LAUNCH(k_ir_fold<float>, dim3(reduce_blocks(n), nb), dim3(kThreads), 0, s, y, d, b, n,
+              active, partials, timing_log());
+}
+void rhs_fp32(const double* b, float* r, float* b32, int64_t n, int nb, int* inexact,
+              hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_ints, dim3(1), dim3(kThreads), 0, s, inexact, 1, 0);
+  if (n <= 0 || nb <= 0) return;
+  hipLaunchKernelGGL(k_rhs_fp32, grid_cols(n, nb), dim3(kThreads), 0, s, b, r, b32, n, inexact);
 }
 template <typename T64, typename T32>
 void ir_accumulate(T64* y, const T32* d, int64_t n, int nb, const int* active,

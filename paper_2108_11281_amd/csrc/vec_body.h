@@ -112,7 +112,8 @@ __device__ __forceinline__ void cg_xr(T* x, T* r, const T* p, const T* q, c64 a,
 // The FP64 refinement's fold of the FP32 correction, one pass: y += d,
 // partials of b^T d (the stated-error share, same blocks and order as the
 // dot), d = 0.  Column k, block bx of nblk.
-__device__ __forceinline__ void ir_fold(double* y, float* d, const double* b, int64_t n, int nblk,
+template <typename Tb>
+__device__ __forceinline__ void ir_fold(double* y, float* d, const Tb* b, int64_t n, int nblk,
                                         int bx, int k, c64* partials, double* lds) {
   int64_t lo = 0, hi = 0;
   chunk_of(n, nblk, bx, lo, hi);
@@ -131,7 +132,7 @@ __device__ __forceinline__ void ir_fold(double* y, float* d, const double* b, in
       const bool ok = i < hi;
       dv[j] = ok ? d[off + i] : 0.0f;
       yv[j] = ok ? y[off + i] : 0.0;
-      bv[j] = ok ? b[off + i] : 0.0;
+      bv[j] = ok ? (double)b[off + i] : 0.0;
     }
 #pragma unroll
     for (int j = 0; j < U; ++j) {
