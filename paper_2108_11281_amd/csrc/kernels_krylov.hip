@@ -122,19 +122,21 @@ __global__ void k_givens_step(GState st, const c64* h, const c64* wn2, const c64
   for (int k = threadIdx.x; k < nb; k += blockDim.x) {
     if (!active[k]) continue;
     c64* Hk = st.H + (int64_t)k * (m + 1) * m;
-    c64 col[kMaxBasis];
-    for (int i = 0; i <= j; ++i) col[i] = h[(int64_t)k * (j + 1) + i];
-    col[j + 1] = {sqrt(wn2[k].re), 0.0};
+    const c64* hk = h + (int64_t)k * (j + 1);
+    // rotation i acts on entries i (already rotated by rotation i - 1) and i + 1
+    // (still as formed): the column streams through `a`, and entry i is final
+    // after rotation i (no indexed local array, which would live in scratch)
+    c64 a = hk[0];
     for (int i = 0; i < j; ++i) {
       const double c = st.cs[(int64_t)k * m + i].re;
       const c64 s = st.sn[(int64_t)k * m + i];
-      const c64 a = col[i], b = col[i + 1];
+      const c64 b = hk[i + 1];
       // [a; b] <- [c a + s b; -conj(s) a + c b]
-      col[i] = c * a + s * b;
+      Hk[(int64_t)i * m + j] = c * a + s * b;
       const c64 sc = {s.re, -s.im};
-      col[i + 1] = c * b - sc * a;
+      a = c * b - sc * a;
     }
-    const c64 a = col[j], b = col[j + 1];
+    const c64 b = {sqrt(wn2[k].re), 0.0};
     const double na = sqrt(a.re * a.re + a.im * a.im), nbv = sqrt(b.re * b.re + b.im * b.im);
     const double r = sqrt(na * na + nbv * nbv);
     double c;
@@ -153,9 +155,7 @@ __global__ void k_givens_step(GState st, const c64* h, const c64* wn2, const c64
     }
     st.cs[(int64_t)k * m + j] = {c, 0.0};
     st.sn[(int64_t)k * m + j] = s;
-    col[j] = c * a + s * b;
-    col[j + 1] = {0.0, 0.0};
-    for (int i = 0; i <= j; ++i) Hk[(int64_t)i * m + j] = col[i];
+    Hk[(int64_t)j * m + j] = c * a + s * b;
     c64* gk = st.g + (int64_t)k * (m + 1);
     const c64 gj = gk[j];
     const c64 sc = {s.re, -s.im};
