@@ -380,13 +380,14 @@ def run_poisson(args, m, torch):
 
 
 def _wilson_est(m, N, Ls, L, precision, learned, nb, alloc, n_vec=8, spin_split=False,
-                top_cycles=0):
+                top_cycles=0, graphs=0):
     from workloads import gauge_field, wilson_mass
     return m.TraceEstimator("wilson2d", N, Ls, L, mass=wilson_mass(N),
                             field=gauge_field(N, sigma=0.5, seed=1), block=4, n_vec=n_vec,
                             spin_split=spin_split, setup_sweeps=20, setup_seed=1,
                             precision=precision, nb=nb, nu_pre=2, nu_post=2, solve_tol=1e-10,
-                            alloc=alloc, learned=1 if learned else 0, top_cycles=top_cycles)
+                            alloc=alloc, learned=1 if learned else 0, top_cycles=top_cycles,
+                            graphs=graphs)
 
 
 def deflated_compare(args, m, torch, make):
@@ -519,8 +520,19 @@ def run_wilson(args, m, torch, N, learned):
                                 "stencils)", ks,
                                 args.timing_stride)
     compare = {"learned_stats": list(est.learned_stats())} if learned else {}
+    weights = est.get_nn_weights() if learned else None
     est.close()
     if not args.no_compare:
+        # the same configuration with every FGMRES iteration replayed from a HIP
+        # graph (no kernel timing), the trained weights set
+        eg = _wilson_est(m, N, Ls, L, "fp32_ir64", learned, args.nb, args.alloc, nv,
+                         args.spin_split, args.top_cycles, graphs=1)
+        if learned:
+            eg.set_nn_weights(weights)
+        tg, _ = timed_traces(eg, args, torch)
+        eg.close()
+        compare["graphs_s_per_trace"] = round(tg, 4)
+        log("graphs: %.3fs per trace" % tg)
         if learned:
             log("plain FP32 MLMC (no network), same workload")
             ep = _wilson_est(m, N, Ls, L, "fp32_ir64", False, args.nb, args.alloc, nv,
@@ -708,6 +720,11 @@ def run_graph(args, m, torch):
     ms_per_step = 1000.0 * elapsed / args.steps
     compare = {}
     if not args.no_compare:
+        eg = make("fp32_ir64", graphs=1)  # FGMRES iterations replayed from HIP graphs
+        tg, _ = timed_traces(eg, args, torch)
+        eg.close()
+        compare["graphs_s_per_trace"] = round(tg, 4)
+        log("graphs: %.3fs per trace" % tg)
         log("plain FP64 MLMC, same workload")
         e64 = make("fp64")
         t64, n64 = timed_traces(e64, args, torch)
@@ -787,6 +804,11 @@ def run_laplace_bilinear(args, m, torch):
     ms_per_step = 1000.0 * elapsed / args.steps
     compare = {}
     if not args.no_compare:
+        eg = make("fp32_ir64", graphs=1)  # FGMRES iterations replayed from HIP graphs
+        tg, _ = timed_traces(eg, args, torch)
+        eg.close()
+        compare["graphs_s_per_trace"] = round(tg, 4)
+        log("graphs: %.3fs per trace" % tg)
         log("plain FP64 MLMC, same workload")
         e64 = make("fp64")
         t64, n64 = timed_traces(e64, args, torch)
@@ -828,11 +850,12 @@ def run_gauge(args, m, torch):
     nv = args.n_vec if args.n_vec > 0 else w["n_vec"]
     th = gauge_field(N, sigma=w["theta_sigma"], seed=w["gauge_seed"])
 
-    def make(precision):
+    def make(precision, graphs=0):
         return m.TraceEstimator("gauge2d", N, Ls, L, mass=w["mass"], field=th, block=4,
                                 n_vec=nv, setup_sweeps=w["setup_sweeps"], setup_seed=1,
                                 precision=precision, nb=args.nb, nu_pre=args.nu,
-                                nu_post=args.nu, solve_tol=w["solve_tol"], alloc=args.alloc)
+                                nu_post=args.nu, solve_tol=w["solve_tol"], alloc=args.alloc,
+                                graphs=graphs)
     t0 = time.perf_counter()
     est = make("fp32_ir64")
     setup_s = time.perf_counter() - t0
@@ -859,6 +882,11 @@ def run_gauge(args, m, torch):
     ms_per_step = 1000.0 * elapsed / args.steps
     compare = {}
     if not args.no_compare:
+        eg = make("fp32_ir64", graphs=1)  # FGMRES iterations replayed from HIP graphs
+        tg, _ = timed_traces(eg, args, torch)
+        eg.close()
+        compare["graphs_s_per_trace"] = round(tg, 4)
+        log("graphs: %.3fs per trace" % tg)
         log("plain FP64 MLMC, same workload")
         e64 = make("fp64")
         t64, n64 = timed_traces(e64, args, torch)

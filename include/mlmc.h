@@ -186,8 +186,12 @@ typedef struct mlmc_options {
   int graphs;         /* 1: the FP32 refined CG of the real operators replays the
                          two iterations between refinement checks (V-cycles,
                          direction update, x/r update, refinement test) from a
-                         HIP graph captured once per (level, batch width);
-                         results are bitwise identical.  Bypassed while
+                         HIP graph captured once per (level, batch width), and
+                         the FGMRES of the complex operators replays every
+                         iteration (V-cycle, operator, Gram-Schmidt, Givens
+                         step) from a graph captured once per (precision,
+                         level, batch width, iteration, learned smoother on or
+                         off); results are bitwise identical.  Bypassed while
                          per-kernel timing is on.  0: direct launches */
   int narrow_fp64;    /* MLMC_FP32_IR64, real operators: solves of batches of at
                          most this many columns run in plain FP64 CG (for a few

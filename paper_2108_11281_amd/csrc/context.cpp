@@ -104,7 +104,7 @@ Context::Context(const mlmc_operator& A, const mlmc_hierarchy& h, const mlmc_opt
 
 Context::~Context() {
   (void)hipStreamSynchronize(s_);
-  for (auto& kv : graphs_) (void)hipGraphExecDestroy(kv.second);
+  for (auto& kv : graphs_) (void)hipGraphExecDestroy(kv.second.ex);
   if (cap_s_) (void)hipStreamDestroy(cap_s_);
   for (const Pending& p : pending_) {
     (void)hipEventDestroy(p.a);
@@ -645,7 +645,6 @@ void Context::second_coarse_cycle(int l, const T* bc, T* ec, int nb, const int* 
 // after the coarse correction, so the preconditioner is symmetric), fused
 // residual + restriction, prolongation + omega-scaled correction.
 // ---------------------------------------------------------------------------
-
 template <typename T>
 void Context::vcycle_vc(int l, const T* b, T* x, int nb, const int* act, c64* rz_partials,
                         bool top) {
@@ -1139,13 +1138,10 @@ void Context::pcg_refined(int l, const double* b, double* y, int nb, double tol,
         core(P1, P2, true);
         due();
       };
-      if (use_graph) {
-        hipGraphExec_t ex = graph_for({l, nb}, pair);
-        MLMC_HIP(hipGraphLaunch(ex, s_));
-        if (l == 1) counters[2] += 2;
-      } else {
+      if (use_graph)
+        replay({0, l, nb, 0}, pair);
+      else
         pair();
-      }
       counters[0] += 2;
       it += 2;
       if (refine(it == max_it)) return;
@@ -1161,36 +1157,48 @@ void Context::pcg_refined(int l, const double* b, double* y, int nb, double tol,
   }
 }
 
-hipGraphExec_t Context::graph_for(std::pair<int, int> key, const std::function<void()>& body) {
+void Context::replay(const std::array<int, 4>& key, const std::function<void()>& body) {
   auto found = graphs_.find(key);
-  if (found != graphs_.end()) return found->second;
-  // capture on a stream of our own (the caller's stream may be the legacy
-  // default stream, which cannot be captured): the launches of `body` go to s_,
-  // so s_ points at the capture stream while recording
-  if (!cap_s_) MLMC_HIP(hipStreamCreateWithFlags(&cap_s_, hipStreamNonBlocking));
-  int64_t saved[4];
-  std::memcpy(saved, counters, sizeof(saved));
-  hipGraph_t g = nullptr;
-  hipStream_t caller = s_;
-  MLMC_HIP(hipStreamBeginCapture(cap_s_, hipStreamCaptureModeThreadLocal));
-  s_ = cap_s_;
-  try {
-    body();
-  } catch (...) {
+  if (found == graphs_.end()) {
+    // capture on a stream of our own (the caller's stream may be the legacy
+    // default stream, which cannot be captured): the launches of `body` go to
+    // s_, so s_ points at the capture stream while recording
+    if (!cap_s_) MLMC_HIP(hipStreamCreateWithFlags(&cap_s_, hipStreamNonBlocking));
+    int64_t c0[4], n0[2];
+    std::memcpy(c0, counters, sizeof(c0));
+    std::memcpy(n0, nn_stats, sizeof(n0));
+    auto restore = [&] {  // capture only recorded the launches
+      std::memcpy(counters, c0, sizeof(c0));
+      std::memcpy(nn_stats, n0, sizeof(n0));
+    };
+    hipGraph_t g = nullptr;
+    hipStream_t caller = s_;
+    MLMC_HIP(hipStreamBeginCapture(cap_s_, hipStreamCaptureModeThreadLocal));
+    s_ = cap_s_;
+    try {
+      body();
+    } catch (...) {
+      s_ = caller;
+      (void)hipStreamEndCapture(cap_s_, &g);
+      if (g) (void)hipGraphDestroy(g);
+      restore();
+      throw;
+    }
     s_ = caller;
-    (void)hipStreamEndCapture(cap_s_, &g);
-    if (g) (void)hipGraphDestroy(g);
-    throw;
+    MLMC_HIP(hipStreamEndCapture(cap_s_, &g));
+    Graph gr;
+    for (int i = 0; i < 4; ++i) gr.counters[i] = counters[i] - c0[i];
+    for (int i = 0; i < 2; ++i) gr.nn_stats[i] = nn_stats[i] - n0[i];
+    restore();
+    const hipError_t e = hipGraphInstantiate(&gr.ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    MLMC_HIP(e);
+    found = graphs_.emplace(key, gr).first;
   }
-  s_ = caller;
-  MLMC_HIP(hipStreamEndCapture(cap_s_, &g));
-  std::memcpy(counters, saved, sizeof(saved));  // capture only recorded the launches
-  hipGraphExec_t ex = nullptr;
-  const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(g);
-  MLMC_HIP(e);
-  graphs_[key] = ex;
-  return ex;
+  const Graph& gr = found->second;
+  MLMC_HIP(hipGraphLaunch(gr.ex, s_));
+  for (int i = 0; i < 4; ++i) counters[i] += gr.counters[i];
+  for (int i = 0; i < 2; ++i) nn_stats[i] += gr.nn_stats[i];
 }
 
 // ---------------------------------------------------------------------------

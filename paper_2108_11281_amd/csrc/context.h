@@ -1,6 +1,7 @@
 // Library context: the hierarchy, work buffers and the solvers.
 #pragma once
 
+#include <array>
 #include <functional>
 #include <map>
 #include <string>
@@ -315,9 +316,19 @@ class Context {
   template <typename T> int pcg(int l, const T* b, T* x, int nb, int* act, double tol,
                                 c64* lastcorr);
   void pcg_refined(int l, const double* b, double* y, int nb, double tol, c64* err);
-  // HIP graph of `body` captured on the context stream once per key
-  hipGraphExec_t graph_for(std::pair<int, int> key, const std::function<void()>& body);
-  std::map<std::pair<int, int>, hipGraphExec_t> graphs_;
+  // Launches the HIP graph of `body`, captured on the context stream at the
+  // key's first use; the host-side counters the body advances (recorded while
+  // capturing) advance by the same amounts at every launch.  Keys: {0, level,
+  // batch width, 0} the refined CG's iteration pairs; {1 (complex64) or 2
+  // (complex128), level, batch width, iteration + 64 (learned smoother on)}
+  // the FGMRES iterations.
+  void replay(const std::array<int, 4>& key, const std::function<void()>& body);
+  struct Graph {
+    hipGraphExec_t ex = nullptr;
+    int64_t counters[4] = {0, 0, 0, 0};
+    int64_t nn_stats[2] = {0, 0};
+  };
+  std::map<std::array<int, 4>, Graph> graphs_;
   hipStream_t cap_s_ = nullptr;  // library-owned stream that graphs are captured on
   // FP64 solve of level l for nb columns; b, y FP64; err: per-column stated error
   // contributions (device c64 nb), relres host (nullable)

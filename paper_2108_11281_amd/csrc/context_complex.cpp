@@ -422,21 +422,32 @@ void Context::fgmres_cycle(int l, const T* r, T* d, int nb, int* act, double tol
   finish_sums(partials_, nblk, nb, beta2, s_);
   vec_scale_inv_norm<T>(f.V, r, beta2, n, nb, act, s_);
   givens_init(gH_, gcs_, gsn_, gg_, gdims_, beta2, act, m_, nb, s_);
+  // with opts.graphs (and no kernel timing) every iteration replays a HIP graph
+  // captured once per (precision, level, batch width, iteration, smoother):
+  // its launches, pointers and scalars (tol is the context's fixed inner
+  // tolerance) are the same at every visit
+  const bool use_graph = opt_.graphs && !timing_;
   for (int j = 0; j < m_; ++j) {
-    T* vj = f.V + j * vs;
-    T* zj = f.Z + j * vs;
-    T* w = f.V + (j + 1) * vs;
-    cvcycle<T>(l, vj, zj, nb, act, true);
-    cop_residual<T, T, T>(l, (const T*)nullptr, zj, w, nb, act, nullptr);
-    int mb = 0;
-    krylov_mdot<T>(f.V, vs, j + 1, w, n, nb, act, partials_, &mb, s_);
-    finish_sums(partials_, mb, nb * (j + 1), ghcol_, s_);
-    krylov_maxpy<T>(f.V, vs, j + 1, ghcol_, w, n, nb, act, s_);
-    vec_dot_partials<T>(w, w, n, nb, act, partials_, s_);
-    finish_sums(partials_, nblk, nb, wn2, s_);
-    vec_scale_inv_norm<T>(w, w, wn2, n, nb, act, s_);
-    givens_step(gH_, gcs_, gsn_, gg_, gdims_, ghcol_, wn2, beta2, tol, j, m_, act, nb,
-                count_dev_, s_);
+    auto iteration = [&] {
+      T* vj = f.V + j * vs;
+      T* zj = f.Z + j * vs;
+      T* w = f.V + (j + 1) * vs;
+      cvcycle<T>(l, vj, zj, nb, act, true);
+      cop_residual<T, T, T>(l, (const T*)nullptr, zj, w, nb, act, nullptr);
+      int mb = 0;
+      krylov_mdot<T>(f.V, vs, j + 1, w, n, nb, act, partials_, &mb, s_);
+      finish_sums(partials_, mb, nb * (j + 1), ghcol_, s_);
+      krylov_maxpy<T>(f.V, vs, j + 1, ghcol_, w, n, nb, act, s_);
+      vec_dot_partials<T>(w, w, n, nb, act, partials_, s_);
+      finish_sums(partials_, nblk, nb, wn2, s_);
+      vec_scale_inv_norm<T>(w, w, wn2, n, nb, act, s_);
+      givens_step(gH_, gcs_, gsn_, gg_, gdims_, ghcol_, wn2, beta2, tol, j, m_, act, nb,
+                  count_dev_, s_);
+    };
+    if (use_graph)
+      replay({sizeof(T) == sizeof(c32) ? 1 : 2, l, nb, j + (nn_use_ ? 64 : 0)}, iteration);
+    else
+      iteration();
     counters[0] += 1;
     if (read_count() == 0) break;
   }
