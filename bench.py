@@ -683,11 +683,11 @@ def run_graph(args, m, torch):
     if args.omega > 0:
         vc["omega"] = args.omega
 
-    def make(precision):
+    def make(precision, graphs=0):
         return m.TraceEstimator("csr", 0, Ls, L, matrix=A, precision=precision, nb=args.nb,
                                 solve_tol=w["solve_tol"], alloc=args.alloc,
                                 narrow_fp64=args.narrow_fp64 if precision != "fp64" else 0,
-                                top_cycles=args.top_cycles, **vc)
+                                top_cycles=args.top_cycles, graphs=graphs, **vc)
     t0 = time.perf_counter()
     est = make("fp32_ir64")
     setup_s = time.perf_counter() - t0
@@ -720,7 +720,7 @@ def run_graph(args, m, torch):
     ms_per_step = 1000.0 * elapsed / args.steps
     compare = {}
     if not args.no_compare:
-        eg = make("fp32_ir64", graphs=1)  # FGMRES iterations replayed from HIP graphs
+        eg = make("fp32_ir64", graphs=1)  # CG iteration pairs replayed from HIP graphs
         tg, _ = timed_traces(eg, args, torch)
         eg.close()
         compare["graphs_s_per_trace"] = round(tg, 4)
@@ -767,11 +767,11 @@ def run_laplace_bilinear(args, m, torch):
     if args.omega > 0:
         vc["omega"] = args.omega
 
-    def make(precision):
+    def make(precision, graphs=0):
         return m.TraceEstimator("csr", 0, Ls, L, matrix=A, prolongations=P, precision=precision,
                                 nb=args.nb, solve_tol=w["solve_tol"], alloc=args.alloc,
                                 narrow_fp64=args.narrow_fp64 if precision != "fp64" else 0,
-                                top_cycles=args.top_cycles, **vc)
+                                top_cycles=args.top_cycles, graphs=graphs, **vc)
     t0 = time.perf_counter()
     est = make("fp32_ir64")
     setup_s = time.perf_counter() - t0
@@ -804,7 +804,7 @@ def run_laplace_bilinear(args, m, torch):
     ms_per_step = 1000.0 * elapsed / args.steps
     compare = {}
     if not args.no_compare:
-        eg = make("fp32_ir64", graphs=1)  # FGMRES iterations replayed from HIP graphs
+        eg = make("fp32_ir64", graphs=1)  # CG iteration pairs replayed from HIP graphs
         tg, _ = timed_traces(eg, args, torch)
         eg.close()
         compare["graphs_s_per_trace"] = round(tg, 4)
