@@ -558,14 +558,14 @@ void Context::samples_batch_general(int level, uint64_t seed, uint64_t first, in
 // with that choice, the sweep's schedule of its trailing small colour classes
 // (a launch per class, or the trailing classes of at most 4, 16 or 64 slices
 // in shared launches: fewer launches, fewer compute units per class; the
-// results are identical).  Runs once at setup on the library's own work
-// vectors.
+// results are identical).  Each candidate is timed as the best of five sweeps
+// after a warm-up.  Runs once at setup on the library's own work vectors.
 void Context::tune_csr() {
   const bool fp32 = opt_.precision == MLMC_FP32_IR64;
   hipEvent_t a = event(), b = event();
   auto time_sweep = [&](const Level& L, int ncols, int cols, int tail) {
-    float ms = 0.f;
-    for (int rep = 0; rep < 3; ++rep) {
+    float ms = 1e30f;  // best of 5 after a warm-up run (robust to noise)
+    for (int rep = 0; rep < 6; ++rep) {
       MLMC_HIP(hipEventRecord(a, s_));
       if (fp32)
         csr_gs_sweep<float>(w32_.r, w32_.x, L.S32, (int)L.n, ncols, cols, tail, nullptr, false,
@@ -577,7 +577,7 @@ void Context::tune_csr() {
       MLMC_HIP(hipEventSynchronize(b));
       float t = 0.f;
       MLMC_HIP(hipEventElapsedTime(&t, a, b));
-      if (rep > 0) ms += t;  // the first run warms caches and code
+      if (rep > 0) ms = std::min(ms, t);  // the first run warms caches and code
     }
     return ms;
   };
@@ -596,13 +596,16 @@ void Context::tune_csr() {
         }
       }
       (narrow ? L.cols_narrow : L.cols) = best_cols;
+      // shared launches only where they are at least 5% faster than a launch
+      // per class, so that the choice does not follow timing noise
+      const float t_classes = best;
       int best_tail = 0, last_start = csr_tail_start(soff, 0);
       for (int tail : {4, 16, 64}) {
         const int start = csr_tail_start(soff, tail);
         if (start == last_start) continue;  // the same schedule as a smaller bound
         last_start = start;
         const float ms = time_sweep(L, ncols, best_cols, tail);
-        if (ms < best) {
+        if (ms < best && ms < 0.95f * t_classes) {
           best = ms;
           best_tail = tail;
         }
