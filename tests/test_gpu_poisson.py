@@ -77,6 +77,15 @@ def test_solve_matches_exact(precision, c0_oracle):
             assert iters <= 60, (iters, refine)
         ref = c0_oracle.solver(l).solve(B.T).T
         assert np.max(np.abs(from_dev(Y) - ref)) <= 1e-9 * np.max(np.abs(ref))
+    # right-hand sides of FP32 numbers (entries +-1/2, as the probes and their
+    # restrictions): the FP32 refinement reads them from an exact FP32 copy,
+    # the normal ones above through the FP64 path; both meet the exact solve
+    for l in (1, 2):
+        B = 0.5 * np.sign(rng.standard_normal((5, est.level_size(l))))
+        Y, rel = est.solve(l, to_dev(B))
+        assert np.all(rel <= 1e-12)
+        ref = c0_oracle.solver(l).solve(B.T).T
+        assert np.max(np.abs(from_dev(Y) - ref)) <= 1e-9 * np.max(np.abs(ref))
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_ir64"])
