@@ -83,7 +83,7 @@ struct GTask {
 // indices into the GTask array, then four prefix arrays of t + 1 entries:
 // blocks of the stencil shape (ntiles x ceil(nb / kGroupStencilCols)), of the
 // reduction shape (nblk x nb), of the per-column shape (nb) and one per task.
-constexpr int kGroupStencilCols = 4;
+constexpr int kGroupStencilCols = 8;
 enum { kShStencil = 0, kShReduce = 1, kShColumn = 2, kShTask = 3 };
 inline int group_table_ints(int t) { return 1 + t + 4 * (t + 1); }
 
