@@ -254,7 +254,8 @@ void Context::alloc_common() {
   act_outer_ = dalloc_n<int>(nb_);
   act_inner_ = dalloc_n<int>(nb_);
   count_dev_ = dalloc_n<int>(8);
-  MLMC_HIP(hipHostMalloc((void**)&count_host_, 8 * sizeof(int)));
+  MLMC_HIP(hipHostMalloc((void**)&count_host_, 8 * sizeof(int), hipHostMallocMapped));
+  MLMC_HIP(hipHostGetDevicePointer((void**)&count_map_, count_host_, 0));
   MLMC_HIP(hipHostMalloc((void**)&host_c64_, 8 * (size_t)nb_ * sizeof(c64)));
   b1_ = dalloc_n<double>(n1 * nb_ * elem);
   y1_ = dalloc_n<double>(n1 * nb_ * elem);
@@ -937,8 +938,9 @@ void Context::reset_kernel_stats() {
     for (TimerStat& t : row) t = TimerStat();
 }
 
+// the count of active columns, stored in count_map_[0] by the last
+// convergence test on the stream
 int Context::read_count() {
-  MLMC_HIP(hipMemcpyAsync(count_host_, count_dev_, sizeof(int), hipMemcpyDeviceToHost, s_));
   MLMC_HIP(hipStreamSynchronize(s_));
   return count_host_[0];
 }
@@ -988,7 +990,7 @@ int Context::pcg(int l, const T* b, T* x, int nb, int* act, double tol, c64* las
     timed<T>(l, kTimCgXr, 6.0 * en, act, nb,
              [&] { cg_update_xr<T>(x, w.r, p_new, w.q, alpha, n, nb, act, partials_, s_); });
     finish_sums(partials_, nblk, nb, tmp, s_);
-    mark_converged(tmp, rr0, tol * tol, act, nb, count_dev_, s_);
+    mark_converged(tmp, rr0, tol * tol, act, nb, count_map_, s_);
     counters[0] += 1;
     if (it % check == 0 || it == opt_.max_iter) {
       if (read_count() == 0) break;
@@ -1074,9 +1076,7 @@ void Context::pcg_refined(int l, const double* b, double* y, int nb, double tol,
   // a refinement is due when some column's recursive residual has dropped by
   // inner_tol since its last refinement, or reached the tolerance
   auto due = [&] {
-    refine_due(tmp, rr_upd, bb, delta2, tol * tol, act, nb, count_dev_ + 1, s_);
-    MLMC_HIP(hipMemcpyAsync(count_host_ + 1, count_dev_ + 1, sizeof(int), hipMemcpyDeviceToHost,
-                            s_));
+    refine_due(tmp, rr_upd, bb, delta2, tol * tol, act, nb, count_map_ + 1, s_);
   };
   // after due(): refine in FP64 if needed; true when every column converged
   auto refine = [&](bool force) {
@@ -1107,7 +1107,7 @@ void Context::pcg_refined(int l, const double* b, double* y, int nb, double tol,
     // run far below FP32 accuracy (a nearly exact preconditioner) restart it
     cg_restart_on_drift(rr_new, tmp, rz, act, 100.0, nb, s_);
     select_active(rr_upd, rr_new, act, nb, s_);
-    mark_converged(rr_new, bb, tol * tol, act, nb, count_dev_, s_);
+    mark_converged(rr_new, bb, tol * tol, act, nb, count_map_, s_);
     counters[1] += 1;
     return read_count() == 0;
   };

@@ -422,7 +422,11 @@ class Context {
          kNn, kNumScalars };
   c64* scal_[kNumScalars] = {};
   int *act_outer_ = nullptr, *act_inner_ = nullptr, *count_dev_ = nullptr;  // count_dev_: 8 ints
+  // pinned host counts (8 ints) and their device address: the single-thread
+  // count kernels whose results the host tests store there directly, so a
+  // check needs no copy, only the stream synchronisation
   int* count_host_ = nullptr;
+  int* count_map_ = nullptr;
   c64* host_c64_ = nullptr;  // pinned, 8*nb
   // deflation: Ritz block V (the first defl_k_ vectors are U), work blocks W
   // and Z, small device matrices, Gram partial sums; eigenvalues and the direct

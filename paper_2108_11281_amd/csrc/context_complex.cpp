@@ -442,7 +442,7 @@ void Context::fgmres_cycle(int l, const T* r, T* d, int nb, int* act, double tol
       finish_sums(partials_, nblk, nb, wn2, s_);
       vec_scale_inv_norm<T>(w, w, wn2, n, nb, act, s_);
       givens_step(gH_, gcs_, gsn_, gg_, gdims_, ghcol_, wn2, beta2, tol, j, m_, act, nb,
-                  count_dev_, s_);
+                  count_map_, s_);
     };
     if (use_graph)
       replay({sizeof(T) == sizeof(c32) ? 1 : 2, l, nb, j + (nn_use_ ? 64 : 0)}, iteration);
@@ -503,15 +503,13 @@ void Context::solve_complex(int l, const c64* b, c64* y, int nb, c64* err) {
     const bool guard = nn_use_ && have_corr;
     if (guard) {
       // columns that met a 2x norm reduction (or the tolerance) vs. all active
-      refine_due(rr_new, rr_old, bb, 0.25, tol * tol, act_outer_, nb, count_dev_ + 2, s_);
-      count_active(act_outer_, nb, count_dev_ + 3, s_);
+      refine_due(rr_new, rr_old, bb, 0.25, tol * tol, act_outer_, nb, count_map_ + 2, s_);
+      count_active(act_outer_, nb, count_map_ + 3, s_);
     }
     select_active(rr_old, rr_new, act_outer_, nb, s_);
-    mark_converged(rr_new, bb, tol * tol, act_outer_, nb, count_dev_, s_);
+    mark_converged(rr_new, bb, tol * tol, act_outer_, nb, count_map_, s_);
     counters[1] += 1;
     if (guard) {
-      MLMC_HIP(hipMemcpyAsync(count_host_, count_dev_, 4 * sizeof(int), hipMemcpyDeviceToHost,
-                              s_));
       MLMC_HIP(hipStreamSynchronize(s_));
       if (count_host_[2] < count_host_[3]) {
         nn_use_ = false;
