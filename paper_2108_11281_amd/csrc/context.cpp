@@ -1033,8 +1033,10 @@ void Context::pcg_refined(int l, const double* b, double* y, int nb, double tol,
   float* r = w.r;
   const double en = 4.0 * (double)n;
   vec_copy<c64>(bb, rr_upd, 1, nb, nullptr, s_);
-  vec_zero<double>(y, n, nb, nullptr, s_);
-  vec_zero<float>(x32, n, nb, nullptr, s_);
+  // y and x32 start at zero without a clearing pass: the first x/r update
+  // writes x32 = 0 + alpha p without reading it, and the first fold writes
+  // y = 0 + x32 without reading y (every column is active until then)
+  bool y_written = false;
   // The refinements read b from an FP32 copy when every entry of b is an FP32
   // number (the 2D Poisson probes and their 2x2 restrictions, multiples of 1/2
   // of small integers): the same values for 4 instead of 8 bytes per unknown
@@ -1060,12 +1062,13 @@ void Context::pcg_refined(int l, const double* b, double* y, int nb, double tol,
   // one CG iteration: p_new = z + beta p_old, q = A p_new, alpha, x/r update
   // (|r|^2 lands in tmp only when a refinement check follows: otherwise the
   // next tail overwrites tmp unread)
-  auto core = [&](float* p_old, float* p_new, bool checked) {
+  auto core = [&](float* p_old, float* p_new, bool checked, bool x_zero = false) {
     timed<float>(l, kTimApply, 4.0 * en, act, nb,
                  [&] { op_update_apply<float>(l, p_old, w.z, beta, p_new, w.q, nb, act); });
     finish_alpha(partials_, ntiles, nb, tmp, rz, act, alpha, s_);
-    timed<float>(l, kTimCgXr, 6.0 * en, act, nb,
-                 [&] { cg_update_xr<float>(x32, r, p_new, w.q, alpha, n, nb, act, partials_, s_); });
+    timed<float>(l, kTimCgXr, (x_zero ? 5.0 : 6.0) * en, act, nb, [&] {
+      cg_update_xr<float>(x32, r, p_new, w.q, alpha, n, nb, act, partials_, s_, x_zero);
+    });
     if (checked) finish_sums(partials_, nblk, nb, tmp, s_);
   };
   // preconditioner and the next direction's beta
@@ -1085,13 +1088,16 @@ void Context::pcg_refined(int l, const double* b, double* y, int nb, double tol,
     const bool b_fp32 = try32 && count_host_[4] == 0;
     const double bbytes = b_fp32 ? 4.0 : 8.0;
     // y += x32, bd = b^T x32, x32 = 0 in one pass (FP64 y, b and FP32 x32 in;
-    // y, x32 out: 32 bytes per unknown, 28 with b in FP32)
-    timed<double>(l, kTimIrFold, (24.0 + bbytes) * (double)n, act, nb, [&] {
+    // y, x32 out: 32 bytes per unknown, 28 with b in FP32; 8 fewer on the
+    // first fold, which does not read y)
+    const bool y_zero = !y_written;
+    timed<double>(l, kTimIrFold, ((y_zero ? 16.0 : 24.0) + bbytes) * (double)n, act, nb, [&] {
       if (b_fp32)
-        ir_fold(y, x32, b32_, n, nb, act, partials_, s_);
+        ir_fold(y, x32, b32_, n, nb, act, partials_, s_, y_zero);
       else
-        ir_fold(y, x32, b, n, nb, act, partials_, s_);
+        ir_fold(y, x32, b, n, nb, act, partials_, s_, y_zero);
     });
+    y_written = true;
     finish_sums(partials_, nblk, nb, bd, s_);
     timed<double>(l, kTimIrResidual, (12.0 + bbytes) * (double)n, act, nb, [&] {
       if (b_fp32)
@@ -1115,7 +1121,7 @@ void Context::pcg_refined(int l, const double* b, double* y, int nb, double tol,
   // iterations between refinement checks: (p2 -> p), (p -> p2), which repeat
   // with fixed pointers and can be replayed from a graph
   int it = 1;
-  core(w.z, P1, it == max_it);
+  core(w.z, P1, it == max_it, true);
   counters[0] += 1;
   if (it == max_it) {
     due();

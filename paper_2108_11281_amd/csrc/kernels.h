@@ -109,21 +109,24 @@ void select_active(c64* dst, const c64* src, const int* active, int nb, hipStrea
 void cg_lastcorr(const c64* alpha, const c64* rz, const int* active, c64* lastcorr, int nb,
                  hipStream_t s);
 
-// x += alpha p ; r -= alpha q ; partials of |r|^2
+// x += alpha p ; r -= alpha q ; partials of |r|^2.  x_zero: x is taken as zero
+// and not read (the first update of a solve), x = alpha p
 template <typename T>
 void cg_update_xr(T* x, T* r, const T* p, const T* q, const c64* alpha, int64_t n,
-                  int nb, const int* active, c64* partials, hipStream_t s);
+                  int nb, const int* active, c64* partials, hipStream_t s,
+                  bool x_zero = false);
 // p = z + beta p
 template <typename T>
 void cg_update_p(T* p, const T* z, const c64* beta, int64_t n, int nb,
                  const int* active, hipStream_t s);
 // refinement fold in one pass: y += d, partials of b^T d (reduce_blocks(n)
-// blocks per column, as vec_dot_partials(b, d)), d = 0
+// blocks per column, as vec_dot_partials(b, d)), d = 0.  y_zero: y is taken as
+// zero and not read (the first fold of a solve), y = 0 + d
 void ir_fold(double* y, float* d, const double* b, int64_t n, int nb, const int* active,
-             c64* partials, hipStream_t s);
+             c64* partials, hipStream_t s, bool y_zero = false);
 // the same with b given in FP32 (exactly: the values of the FP64 b)
 void ir_fold(double* y, float* d, const float* b, int64_t n, int nb, const int* active,
-             c64* partials, hipStream_t s);
+             c64* partials, hipStream_t s, bool y_zero = false);
 // r = b32 = b rounded to FP32 (nb columns of n); *inexact = 0 when every entry of
 // b is an FP32 number (b32 then holds b exactly), else 1
 void rhs_fp32(const double* b, float* r, float* b32, int64_t n, int nb, int* inexact,

@@ -187,12 +187,12 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void k_cg_xr(T* x, T* r, const T* p, const T* q,
                                                     const c64* alpha, int64_t n,
                                                     const int* active, c64* partials,
-                                                    int* tlog) {
+                                                    int* tlog, int x_zero) {
   __shared__ double lds[16];
   const int k = blockIdx.y;
   if (tlog && blockIdx.x == 0 && threadIdx.x == 0) tlog[k] = active ? active[k] : 1;
   if (active && !active[k]) return;
-  body::cg_xr(x, r, p, q, alpha[k], n, gridDim.x, blockIdx.x, k, partials, lds);
+  body::cg_xr(x, r, p, q, alpha[k], n, gridDim.x, blockIdx.x, k, partials, lds, x_zero != 0);
 }
 
 template <typename T>
@@ -221,12 +221,12 @@ __global__ void k_ir_acc(T64* y, const T32* d, int64_t n, const int* active) {
 template <typename Tb>
 __global__ __launch_bounds__(kThreads) void k_ir_fold(double* y, float* d, const Tb* b,
                                                       int64_t n, const int* active,
-                                                      c64* partials, int* tlog) {
+                                                      c64* partials, int* tlog, int y_zero) {
   __shared__ double lds[16];
   const int k = blockIdx.y;
   if (tlog && blockIdx.x == 0 && threadIdx.x == 0) tlog[k] = active ? active[k] : 1;
   if (active && !active[k]) return;
-  body::ir_fold(y, d, b, n, gridDim.x, blockIdx.x, k, partials, lds);
+  body::ir_fold(y, d, b, n, gridDim.x, blockIdx.x, k, partials, lds, y_zero != 0);
 }
 
 // r = b32 = (float)b, and *inexact = 1 when some b_i is not an FP32 number
@@ -736,9 +736,9 @@ void cg_lastcorr(const c64* alpha, const c64* rz, const int* active, c64* lastco
 
 template <typename T>
 void cg_update_xr(T* x, T* r, const T* p, const T* q, const c64* alpha, int64_t n, int nb,
-                  const int* active, c64* partials, hipStream_t s) {
+                  const int* active, c64* partials, hipStream_t s, bool x_zero) {
   MLMC_LAUNCH(k_cg_xr<T>, dim3(reduce_blocks(n), nb), dim3(kThreads), 0, s, x, r, p, q, alpha,
-              n, active, partials, timing_log());
+              n, active, partials, timing_log(), x_zero ? 1 : 0);
 }
 template <typename T>
 void cg_update_p(T* p, const T* z, const c64* beta, int64_t n, int nb, const int* active,
@@ -747,16 +747,16 @@ void cg_update_p(T* p, const T* z, const c64* beta, int64_t n, int nb, const int
                      active);
 }
 void ir_fold(double* y, float* d, const double* b, int64_t n, int nb, const int* active,
-             c64* partials, hipStream_t s) {
+             c64* partials, hipStream_t s, bool y_zero) {
   if (n <= 0 || nb <= 0) return;
   MLMC_LAUNCH(k_ir_fold<double>, dim3(reduce_blocks(n), nb), dim3(kThreads), 0, s, y, d, b, n,
-              active, partials, timing_log());
+              active, partials, timing_log(), y_zero ? 1 : 0);
 }
 void ir_fold(double* y, float* d, const float* b, int64_t n, int nb, const int* active,
-             c64* partials, hipStream_t s) {
+             c64* partials, hipStream_t s, bool y_zero) {
   if (n <= 0 || nb <= 0) return;
   MLMC_LAUNCH(k_ir_fold<float>, dim3(reduce_blocks(n), nb), dim3(kThreads), 0, s, y, d, b, n,
-              active, partials, timing_log());
+              active, partials, timing_log(), y_zero ? 1 : 0);
 }
 void rhs_fp32(const double* b, float* r, float* b32, int64_t n, int nb, int* inexact,
               hipStream_t s) {
@@ -852,7 +852,7 @@ void dense_apply(const T* At, const T* B, T* Z, int n, int nb, const int* active
   template void vec_dot_partials<T>(const T*, const T*, int64_t, int, const int*, c64*,  \
                                     hipStream_t);                                        \
   template void cg_update_xr<T>(T*, T*, const T*, const T*, const c64*, int64_t, int,    \
-                                const int*, c64*, hipStream_t);                          \
+                                const int*, c64*, hipStream_t, bool);                    \
   template void cg_update_p<T>(T*, const T*, const c64*, int64_t, int, const int*,       \
                                hipStream_t);                                             \
   template void vec_axpy_cols<T>(T*, const T*, const c64*, int64_t, int, const int*,     \

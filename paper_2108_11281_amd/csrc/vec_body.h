@@ -90,16 +90,19 @@ __device__ __forceinline__ void beta_rule(c64 rzn, c64* rz, const int* active, i
   rz[k] = rzn;
 }
 
-// x += alpha p ; r -= alpha q ; partials of |r|^2 (column k, block bx of nblk)
+// x += alpha p ; r -= alpha q ; partials of |r|^2 (column k, block bx of nblk).
+// x_zero: x holds no values yet and is taken as zero (not read): x = 0 + alpha p
 template <typename T>
 __device__ __forceinline__ void cg_xr(T* x, T* r, const T* p, const T* q, c64 a, int64_t n,
-                                      int nblk, int bx, int k, c64* partials, double* lds) {
+                                      int nblk, int bx, int k, c64* partials, double* lds,
+                                      bool x_zero = false) {
   int64_t lo = 0, hi = 0;
   chunk_of(n, nblk, bx, lo, hi);
   const int64_t off = (int64_t)k * n;
   double re = 0.0, im = 0.0;
   for (int64_t i = lo + threadIdx.x; i < hi; i += kNT) {
-    T xi = x[off + i] + scale_by(a.re, a.im, p[off + i]);
+    const T x0 = x_zero ? zero_of(T()) : x[off + i];
+    T xi = x0 + scale_by(a.re, a.im, p[off + i]);
     T ri = r[off + i] - scale_by(a.re, a.im, q[off + i]);
     x[off + i] = xi;
     r[off + i] = ri;
@@ -111,10 +114,12 @@ __device__ __forceinline__ void cg_xr(T* x, T* r, const T* p, const T* q, c64 a,
 
 // The FP64 refinement's fold of the FP32 correction, one pass: y += d,
 // partials of b^T d (the stated-error share, same blocks and order as the
-// dot), d = 0.  Column k, block bx of nblk.
+// dot), d = 0.  Column k, block bx of nblk.  y_zero: y holds no values yet and
+// is taken as zero (not read): y = 0 + d
 template <typename Tb>
 __device__ __forceinline__ void ir_fold(double* y, float* d, const Tb* b, int64_t n, int nblk,
-                                        int bx, int k, c64* partials, double* lds) {
+                                        int bx, int k, c64* partials, double* lds,
+                                        bool y_zero = false) {
   int64_t lo = 0, hi = 0;
   chunk_of(n, nblk, bx, lo, hi);
   const int64_t off = (int64_t)k * n;
@@ -131,7 +136,7 @@ __device__ __forceinline__ void ir_fold(double* y, float* d, const Tb* b, int64_
       const int64_t i = i0 + (int64_t)j * kNT;
       const bool ok = i < hi;
       dv[j] = ok ? d[off + i] : 0.0f;
-      yv[j] = ok ? y[off + i] : 0.0;
+      yv[j] = ok && !y_zero ? y[off + i] : 0.0;
       bv[j] = ok ? (double)b[off + i] : 0.0;
     }
 #pragma unroll
