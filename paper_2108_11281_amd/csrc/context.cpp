@@ -1032,7 +1032,6 @@ void Context::pcg_refined(int l, const double* b, double* y, int nb, double tol,
   float* x32 = d32_;
   float* r = w.r;
   const double en = 4.0 * (double)n;
-  vec_copy<c64>(bb, rr_upd, 1, nb, nullptr, s_);
   // y and x32 start at zero without a clearing pass: the first x/r update
   // writes x32 = 0 + alpha p without reading it, and the first fold writes
   // y = 0 + x32 without reading y (every column is active until then)
@@ -1042,14 +1041,18 @@ void Context::pcg_refined(int l, const double* b, double* y, int nb, double tol,
   // of small integers): the same values for 4 instead of 8 bytes per unknown
   // in the fold and the residual.  Any other b keeps the FP64 reads (the check
   // runs on the device; its flag is read at the first refinement check).
+  // With the FP32 copy, |b|^2 comes from the same pass (solve() leaves it to
+  // this function then).
   const bool try32 = b32_ != nullptr;
   if (try32) {
-    rhs_fp32(b, r, b32_, n, nb, count_dev_ + 4, s_);
+    rhs_fp32(b, r, b32_, n, nb, count_dev_ + 4, partials_, s_);
+    finish_sums(partials_, nblk, nb, bb, s_);
     MLMC_HIP(hipMemcpyAsync(count_host_ + 4, count_dev_ + 4, sizeof(int), hipMemcpyDeviceToHost,
                             s_));
   } else {
     vec_convert<float, double>(b, r, n, nb, nullptr, s_);
   }
+  vec_copy<c64>(bb, rr_upd, 1, nb, nullptr, s_);
   bool fused = false;
   const int nvp = vcycle_partials<float>(l, &fused);
   vcycle<float>(l, r, w.z, nb, act, partials_, true);
@@ -1233,8 +1236,11 @@ void Context::solve(int l, const double* b, double* y, int nb, c64* err, double*
                           nb, nullptr, partials_, s_);
     finish_sums(partials_, nblk, nb, bb, s_);
   } else {
-  vec_dot_partials<double>(b, b, n, nb, nullptr, partials_, s_);
-  finish_sums(partials_, nblk, nb, bb, s_);
+  const bool refined = l != Ls_ && opt_.precision != MLMC_FP64 && !fp64_batch(nb);
+  if (!(refined && b32_)) {  // else pcg_refined forms |b|^2 with the FP32 copy of b
+    vec_dot_partials<double>(b, b, n, nb, nullptr, partials_, s_);
+    finish_sums(partials_, nblk, nb, bb, s_);
+  }
   set_all_active(act_outer_, nb, s_);
   vec_zero<c64>(err, 1, nb, nullptr, s_);
   const double tol = opt_.solve_tol;

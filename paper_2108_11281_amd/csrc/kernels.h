@@ -128,9 +128,10 @@ void ir_fold(double* y, float* d, const double* b, int64_t n, int nb, const int*
 void ir_fold(double* y, float* d, const float* b, int64_t n, int nb, const int* active,
              c64* partials, hipStream_t s, bool y_zero = false);
 // r = b32 = b rounded to FP32 (nb columns of n); *inexact = 0 when every entry of
-// b is an FP32 number (b32 then holds b exactly), else 1
+// b is an FP32 number (b32 then holds b exactly), else 1; partials of b^T b as
+// vec_dot_partials(b, b) writes them (reduce_blocks(n) per column, same sums)
 void rhs_fp32(const double* b, float* r, float* b32, int64_t n, int nb, int* inexact,
-              hipStream_t s);
+              c64* partials, hipStream_t s);
 // y64 += convert(d)
 template <typename T64, typename T32>
 void ir_accumulate(T64* y, const T32* d, int64_t n, int nb, const int* active,

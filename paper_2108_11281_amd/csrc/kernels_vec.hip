@@ -229,17 +229,31 @@ __global__ __launch_bounds__(kThreads) void k_ir_fold(double* y, float* d, const
   body::ir_fold(y, d, b, n, gridDim.x, blockIdx.x, k, partials, lds, y_zero != 0);
 }
 
-// r = b32 = (float)b, and *inexact = 1 when some b_i is not an FP32 number
-__global__ void k_rhs_fp32(const double* __restrict__ b, float* __restrict__ r,
-                           float* __restrict__ b32, int64_t n, int* inexact) {
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (i >= n) return;
-  const int64_t j = (int64_t)blockIdx.y * n + i;
-  const double v = b[j];
-  const float f = (float)v;
-  r[j] = f;
-  b32[j] = f;
-  if ((double)f != v) *inexact = 1;
+// r = b32 = (float)b, *inexact = 1 when some b_i is not an FP32 number, and the
+// partials of b^T b (the blocks and per-thread order of k_dot on (b, b), so the
+// sums equal vec_dot_partials' bit for bit)
+__global__ __launch_bounds__(kThreads) void k_rhs_fp32(const double* __restrict__ b,
+                                                       float* __restrict__ r,
+                                                       float* __restrict__ b32, int64_t n,
+                                                       int* inexact, c64* partials) {
+  __shared__ double lds[16];
+  const int k = blockIdx.y;
+  int64_t lo = 0, hi = 0;
+  body::chunk_of(n, gridDim.x, blockIdx.x, lo, hi);
+  const int64_t off = (int64_t)k * n;
+  double re = 0.0, im = 0.0;
+  bool exact = true;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += body::kNT) {
+    const double v = b[off + i];
+    const float f = (float)v;
+    r[off + i] = f;
+    b32[off + i] = f;
+    exact = exact && (double)f == v;
+    cdot_acc(re, im, v, v);
+  }
+  if (!exact) *inexact = 1;
+  body::vsum2<body::kNT>(re, im, lds, threadIdx.x);
+  if (threadIdx.x == 0) partials[(int64_t)k * gridDim.x + blockIdx.x] = {re, im};
 }
 
 __global__ void k_fill_ints(int* p, int count, int v) {
@@ -759,10 +773,11 @@ void ir_fold(double* y, float* d, const float* b, int64_t n, int nb, const int* 
               active, partials, timing_log(), y_zero ? 1 : 0);
 }
 void rhs_fp32(const double* b, float* r, float* b32, int64_t n, int nb, int* inexact,
-              hipStream_t s) {
+              c64* partials, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_ints, dim3(1), dim3(kThreads), 0, s, inexact, 1, 0);
   if (n <= 0 || nb <= 0) return;
-  hipLaunchKernelGGL(k_rhs_fp32, grid_cols(n, nb), dim3(kThreads), 0, s, b, r, b32, n, inexact);
+  hipLaunchKernelGGL(k_rhs_fp32, dim3(reduce_blocks(n), nb), dim3(kThreads), 0, s, b, r, b32,
+                     n, inexact, partials);
 }
 template <typename T64, typename T32>
 void ir_accumulate(T64* y, const T32* d, int64_t n, int nb, const int* active,
