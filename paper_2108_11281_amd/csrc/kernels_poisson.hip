@@ -578,6 +578,174 @@ __global__ __launch_bounds__(kThreads) void k_residual_march(const Tb* __restric
   }
 }
 
+// Column-pair forms of the two marches above for even N: a lane holds two
+// adjacent columns (one 8-byte load per row and vector in FP32, 16 bytes in
+// FP64), a wave 128 columns.  The neighbour across the pair is the lane's own
+// other column, the ones across lanes come from lane shifts, and only lanes 0
+// and 63 load the column beyond the wave.  Every entry is formed by the same
+// operations in the same order as in the one-column forms; only the grouping
+// of the partial sums differs (tiles of 128 x 4*MY).
+constexpr int PX = 128;
+
+__device__ __forceinline__ MarchTile pair_tile(int N, int nb, const int* active) {
+  const int nbx = (N + PX - 1) / PX, nby = (N + MTY - 1) / MTY;
+  const int t = xcd_tile_index(nbx * nby * nb);
+  MarchTile m;
+  m.k = t / (nbx * nby);
+  m.rem = t - m.k * nbx * nby;
+  const int by = m.rem / nbx, bx = m.rem - by * nbx;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  m.x = bx * PX + 2 * lane;  // even column of the lane's pair
+  m.ybeg = by * MTY + w * MY;
+  m.yend = m.ybeg + MY < N ? m.ybeg + MY : N;
+  m.ok = m.k < nb && !(active && !active[m.k]);
+  return m;
+}
+
+template <typename T, bool UPD>
+__global__ __launch_bounds__(kThreads) void k_apply_pair(const T* __restrict__ x,
+                                                         const T* __restrict__ z,
+                                                         const c64* beta, T* __restrict__ xnew,
+                                                         T* __restrict__ y, int N, R_t<T> d,
+                                                         R_t<T> c, int nb, const int* active,
+                                                         c64* partials, int* tlog) {
+  __shared__ double red[16];
+  const MarchTile m = pair_tile(N, nb, active);
+  if (tlog && m.rem == 0 && threadIdx.x == 0) tlog[m.k] = active ? active[m.k] : 1;
+  if (!m.ok) return;
+  const int64_t n = (int64_t)N * N;
+  const int half = N >> 1;
+  const T* xs = x + (int64_t)m.k * n;
+  const T* zs = z + (UPD ? (int64_t)m.k * n : 0);
+  const Pair<T>* xc = reinterpret_cast<const Pair<T>*>(xs);
+  const Pair<T>* zc = reinterpret_cast<const Pair<T>*>(zs);
+  Pair<T>* xn = reinterpret_cast<Pair<T>*>(xnew + (UPD ? (int64_t)m.k * n : 0));
+  Pair<T>* yc = reinterpret_cast<Pair<T>*>(y + (int64_t)m.k * n);
+  const T zero = zero_of(T());
+  double dre = 0.0, dim = 0.0;
+  c64 bt = {0.0, 0.0};
+  if (UPD) bt = beta[m.k];
+  const bool col_ok = m.x < N;
+  const int px = col_ok ? (m.x >> 1) : 0;
+  const int lane = threadIdx.x & 63;
+  Pair<T> cz[MY + 2], cx[MY + 2];
+  T ez[MY], ex[MY];
+#pragma unroll
+  for (int j = 0; j < MY + 2; ++j) {
+    const int yy = m.ybeg - 1 + j;
+    const bool ok = col_ok && yy >= 0 && yy < N && yy <= m.yend;
+    const Pair<T> a = xc[ok ? yy * half + px : 0];
+    cx[j] = ok ? a : Pair<T>{zero, zero};
+    if (UPD) {
+      const Pair<T> q = zc[ok ? yy * half + px : 0];
+      cz[j] = ok ? q : Pair<T>{zero, zero};
+    } else {
+      cz[j] = Pair<T>{zero, zero};
+    }
+  }
+  const int xe = lane == 0 ? m.x - 1 : m.x + 2;  // edge lanes' outer column
+  const bool edge = (lane == 0 || lane == 63) && xe >= 0 && xe < N;
+#pragma unroll
+  for (int j = 0; j < MY; ++j) {
+    const int yy = m.ybeg + j;
+    const bool ok = edge && yy < m.yend;
+    ex[j] = ldz(xs, yy * N + xe, ok);
+    ez[j] = UPD ? ldz(zs, yy * N + xe, ok) : zero;
+  }
+  auto P = [&](T zz, T xx) -> T { return UPD ? zz + scale_by(bt.re, bt.im, xx) : xx; };
+#pragma unroll
+  for (int j = 0; j < MY; ++j) {
+    const int yy = m.ybeg + j;
+    const T m0 = P(cz[j + 1].e0, cx[j + 1].e0), m1 = P(cz[j + 1].e1, cx[j + 1].e1);
+    const T pe = P(ez[j], ex[j]);
+    const T sl = wave_shr1(m1), sr = wave_shl1(m0);
+    const T left = lane == 0 ? pe : sl;    // column x - 1
+    const T right = lane == 63 ? pe : sr;  // column x + 2
+    const T v0 = d * m0 - c * (P(cz[j].e0, cx[j].e0) + P(cz[j + 2].e0, cx[j + 2].e0) + left + m1);
+    const T v1 = d * m1 - c * (P(cz[j].e1, cx[j].e1) + P(cz[j + 2].e1, cx[j + 2].e1) + m0 + right);
+    if (col_ok && yy < m.yend) {
+      yc[yy * half + px] = Pair<T>{v0, v1};
+      if (UPD) xn[yy * half + px] = Pair<T>{m0, m1};
+      cdot_acc(dre, dim, m0, v0);
+      cdot_acc(dre, dim, m1, v1);
+    }
+  }
+  if (partials) {
+    block_sum2<kThreads>(dre, dim, red);
+    if (threadIdx.x == 0) {
+      const int tiles = ((N + PX - 1) / PX) * ((N + MTY - 1) / MTY);
+      partials[(int64_t)m.k * tiles + m.rem] = {dre, dim};
+    }
+  }
+}
+
+template <typename Tb, typename Tx, typename Tr>
+__global__ __launch_bounds__(kThreads) void k_residual_pair(const Tb* __restrict__ b,
+                                                            const Tx* __restrict__ x,
+                                                            Tr* __restrict__ r, int N,
+                                                            R_t<Tx> d, R_t<Tx> c, int nb,
+                                                            const int* active, c64* partials,
+                                                            int* tlog) {
+  __shared__ double red[16];
+  const MarchTile m = pair_tile(N, nb, active);
+  if (tlog && m.rem == 0 && threadIdx.x == 0) tlog[m.k] = active ? active[m.k] : 1;
+  if (!m.ok) return;
+  const int64_t n = (int64_t)N * N;
+  const int half = N >> 1;
+  const Tx* xs = x + (int64_t)m.k * n;
+  const Pair<Tx>* xc = reinterpret_cast<const Pair<Tx>*>(xs);
+  const Pair<Tb>* bc = reinterpret_cast<const Pair<Tb>*>(b + (int64_t)m.k * n);
+  Pair<Tr>* rc = reinterpret_cast<Pair<Tr>*>(r + (int64_t)m.k * n);
+  const bool col_ok = m.x < N;
+  const int px = col_ok ? (m.x >> 1) : 0;
+  const int lane = threadIdx.x & 63;
+  const int xe = lane == 0 ? m.x - 1 : m.x + 2;
+  const bool edge = (lane == 0 || lane == 63) && xe >= 0 && xe < N;
+  const Tx zx = zero_of(Tx());
+  const Tb zb = zero_of(Tb());
+  Pair<Tx> cx[MY + 2];
+  Tx ex[MY];
+  Pair<Tb> bb[MY];
+#pragma unroll
+  for (int j = 0; j < MY + 2; ++j) {
+    const int yy = m.ybeg - 1 + j;
+    const bool ok = col_ok && yy >= 0 && yy < N && yy <= m.yend;
+    const Pair<Tx> a = xc[ok ? yy * half + px : 0];
+    cx[j] = ok ? a : Pair<Tx>{zx, zx};
+  }
+#pragma unroll
+  for (int j = 0; j < MY; ++j) {
+    const int yy = m.ybeg + j;
+    const bool ok = col_ok && yy < m.yend;
+    ex[j] = ldz(xs, yy * N + (edge ? xe : 0), ok && edge);
+    const Pair<Tb> q = bc[ok ? yy * half + px : 0];
+    bb[j] = ok ? q : Pair<Tb>{zb, zb};
+  }
+  double dre = 0.0, dim = 0.0;
+#pragma unroll
+  for (int j = 0; j < MY; ++j) {
+    const int yy = m.ybeg + j;
+    const Tx sl = wave_shr1(cx[j + 1].e1), sr = wave_shl1(cx[j + 1].e0);
+    const Tx l0 = lane == 0 ? ex[j] : sl, r1 = lane == 63 ? ex[j] : sr;
+    const Tx a0 = d * cx[j + 1].e0 - c * (cx[j].e0 + cx[j + 2].e0 + l0 + cx[j + 1].e1);
+    const Tx a1 = d * cx[j + 1].e1 - c * (cx[j].e1 + cx[j + 2].e1 + cx[j + 1].e0 + r1);
+    const Tx v0 = convert<Tx, Tb>(bb[j].e0) - a0;
+    const Tx v1 = convert<Tx, Tb>(bb[j].e1) - a1;
+    if (col_ok && yy < m.yend) {
+      rc[yy * half + px] = Pair<Tr>{convert<Tr, Tx>(v0), convert<Tr, Tx>(v1)};
+      cdot_acc(dre, dim, v0, v0);
+      cdot_acc(dre, dim, v1, v1);
+    }
+  }
+  if (partials) {
+    block_sum2<kThreads>(dre, dim, red);
+    if (threadIdx.x == 0) {
+      const int tiles = ((N + PX - 1) / PX) * ((N + MTY - 1) / MTY);
+      partials[(int64_t)m.k * tiles + m.rem] = {dre, dim};
+    }
+  }
+}
+
 // rc = R (b - A x): one thread per coarse column, RR coarse rows (2*RR fine
 // rows); all loads of a thread are issued before the arithmetic
 constexpr int RR = 4;
@@ -700,7 +868,15 @@ inline int march_blocks(int N, int nb, int ry = MY) {
 
 }  // namespace
 
-int poisson_march_tiles(int N) { return ((N + MX - 1) / MX) * ((N + MTY - 1) / MTY); }
+// the column-pair forms serve every even side from 64 up
+inline bool pair_march(int N) { return (N & 1) == 0 && N >= 64; }
+int poisson_march_tiles(int N) {
+  const int cols = pair_march(N) ? PX : MX;
+  return ((N + cols - 1) / cols) * ((N + MTY - 1) / MTY);
+}
+inline int pair_blocks(int N, int nb) {
+  return ((N + PX - 1) / PX) * ((N + MTY - 1) / MTY) * nb;
+}
 // partial sums per column of the fused sweep: blocks of 4 column-marching waves
 // for N >= 64, LDS tiles below
 template <typename T>
@@ -728,25 +904,38 @@ void poisson_dense_build(T* aug, int N, double d, double c, hipStream_t s) {
 template <typename T>
 void poisson_apply(const T* x, T* y, int N, double d, double c, int nb, const int* active,
                    c64* partials, hipStream_t s) {
-  MLMC_LAUNCH((k_apply_march<T, false>), dim3(march_blocks(N, nb)), dim3(kThreads), 0,
-                     s, x, x, (const c64*)nullptr, y, y, N, (R_t<T>)d, (R_t<T>)c, nb, active,
-                     partials, timing_log());
+  if (pair_march(N))
+    MLMC_LAUNCH((k_apply_pair<T, false>), dim3(pair_blocks(N, nb)), dim3(kThreads), 0, s, x, x,
+                (const c64*)nullptr, y, y, N, (R_t<T>)d, (R_t<T>)c, nb, active, partials,
+                timing_log());
+  else
+    MLMC_LAUNCH((k_apply_march<T, false>), dim3(march_blocks(N, nb)), dim3(kThreads), 0, s, x,
+                x, (const c64*)nullptr, y, y, N, (R_t<T>)d, (R_t<T>)c, nb, active, partials,
+                timing_log());
 }
 
 template <typename T>
 void poisson_update_apply(const T* p_old, const T* z, const c64* beta, T* p_new, T* q, int N,
                           double d, double c, int nb, const int* active, c64* partials,
                           hipStream_t s) {
-  MLMC_LAUNCH((k_apply_march<T, true>), dim3(march_blocks(N, nb)), dim3(kThreads), 0, s,
-                     p_old, z, beta, p_new, q, N, (R_t<T>)d, (R_t<T>)c, nb, active, partials, timing_log());
+  if (pair_march(N))
+    MLMC_LAUNCH((k_apply_pair<T, true>), dim3(pair_blocks(N, nb)), dim3(kThreads), 0, s, p_old,
+                z, beta, p_new, q, N, (R_t<T>)d, (R_t<T>)c, nb, active, partials, timing_log());
+  else
+    MLMC_LAUNCH((k_apply_march<T, true>), dim3(march_blocks(N, nb)), dim3(kThreads), 0, s,
+                p_old, z, beta, p_new, q, N, (R_t<T>)d, (R_t<T>)c, nb, active, partials,
+                timing_log());
 }
 
 template <typename Tb, typename Tx, typename Tr>
 void poisson_residual(const Tb* b, const Tx* x, Tr* r, int N, double d, double c, int nb,
                       const int* active, c64* partials, hipStream_t s) {
-  MLMC_LAUNCH((k_residual_march<Tb, Tx, Tr>), dim3(march_blocks(N, nb)),
-                     dim3(kThreads), 0, s, b, x, r, N, (R_t<Tx>)d, (R_t<Tx>)c, nb, active,
-                     partials, timing_log());
+  if (pair_march(N))
+    MLMC_LAUNCH((k_residual_pair<Tb, Tx, Tr>), dim3(pair_blocks(N, nb)), dim3(kThreads), 0, s,
+                b, x, r, N, (R_t<Tx>)d, (R_t<Tx>)c, nb, active, partials, timing_log());
+  else
+    MLMC_LAUNCH((k_residual_march<Tb, Tx, Tr>), dim3(march_blocks(N, nb)), dim3(kThreads), 0, s,
+                b, x, r, N, (R_t<Tx>)d, (R_t<Tx>)c, nb, active, partials, timing_log());
 }
 
 template <typename T, int SR, int NSW>
