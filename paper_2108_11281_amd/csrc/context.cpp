@@ -111,6 +111,8 @@ Context::~Context() {
     (void)hipEventDestroy(p.b);
   }
   for (hipEvent_t e : ev_pool_) (void)hipEventDestroy(e);
+  for (hipEvent_t e : fg_ev_)
+    if (e) (void)hipEventDestroy(e);
   for (void* p : allocs_) {
     if (hooks_.free_fn) hooks_.free_fn(p, hooks_.user);
     else (void)hipFree(p);

@@ -330,6 +330,9 @@ class Context {
   };
   std::map<std::array<int, 4>, Graph> graphs_;
   hipStream_t cap_s_ = nullptr;  // library-owned stream that graphs are captured on
+  // ends of the last two FGMRES iterations: the host reads an iteration's
+  // convergence count while the next one runs
+  hipEvent_t fg_ev_[2] = {nullptr, nullptr};
   // FP64 solve of level l for nb columns; b, y FP64; err: per-column stated error
   // contributions (device c64 nb), relres host (nullable)
   void solve(int l, const double* b, double* y, int nb, c64* err, double* relres_host,

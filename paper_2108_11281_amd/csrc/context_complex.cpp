@@ -427,6 +427,13 @@ void Context::fgmres_cycle(int l, const T* r, T* d, int nb, int* act, double tol
   // its launches, pointers and scalars (tol is the context's fixed inner
   // tolerance) are the same at every visit
   const bool use_graph = opt_.graphs && !timing_;
+  for (hipEvent_t& e : fg_ev_)
+    if (!e) MLMC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  // Iteration j stores its count of active columns in count slot 5 + j % 2.
+  // The host reads iteration j-1's count once iteration j is queued, so the
+  // GPU does not drain between iterations; when that count is zero, iteration
+  // j has run on no column (every kernel skips inactive columns) and the cycle
+  // ends with the same state as if it had stopped after j-1.
   for (int j = 0; j < m_; ++j) {
     auto iteration = [&] {
       T* vj = f.V + j * vs;
@@ -442,14 +449,18 @@ void Context::fgmres_cycle(int l, const T* r, T* d, int nb, int* act, double tol
       finish_sums(partials_, nblk, nb, wn2, s_);
       vec_scale_inv_norm<T>(w, w, wn2, n, nb, act, s_);
       givens_step(gH_, gcs_, gsn_, gg_, gdims_, ghcol_, wn2, beta2, tol, j, m_, act, nb,
-                  count_map_, s_);
+                  count_map_ + 5 + (j & 1), s_);
     };
     if (use_graph)
       replay({sizeof(T) == sizeof(c32) ? 1 : 2, l, nb, j + (nn_use_ ? 64 : 0)}, iteration);
     else
       iteration();
+    MLMC_HIP(hipEventRecord(fg_ev_[j & 1], s_));
+    if (j > 0) {
+      MLMC_HIP(hipEventSynchronize(fg_ev_[(j - 1) & 1]));
+      if (count_host_[5 + ((j - 1) & 1)] == 0) break;
+    }
     counters[0] += 1;
-    if (read_count() == 0) break;
   }
   givens_solve(gH_, gcs_, gsn_, gg_, gdims_, gy_, gstart_, m_, nb, s_);
   krylov_combine<T>(f.Z, vs, gy_, m_, gdims_, d, n, nb, gstart_, s_);
