@@ -352,9 +352,23 @@ __global__ __launch_bounds__(kThreads) void k_probe_dot(const T* y, int64_t n, P
   const int64_t base = (int64_t)blockIdx.x * probe_chunk<T>();
   const T* yc = y + (int64_t)k * n;
   double re = 0.0, im = 0.0;
-  for (int64_t l = threadIdx.x; l < probe_chunk<T>(); l += kThreads) {
-    int64_t i = base + l;
-    if (i < n) cdot_acc(re, im, probe_from_words<T>(words, l), yc[i]);
+  // four loads of y in flight per thread, then the products in the order of a
+  // plain strided loop (the chunk is a multiple of 4 * kThreads)
+  constexpr int U = 4;
+  static_assert(probe_chunk<T>() % (U * kThreads) == 0, "probe chunk");
+  for (int64_t l0 = threadIdx.x; l0 < probe_chunk<T>(); l0 += U * kThreads) {
+    T yv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = base + l0 + (int64_t)u * kThreads;
+      const T v = yc[i < n ? i : 0];
+      yv[u] = i < n ? v : zero_of(T());
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t l = l0 + (int64_t)u * kThreads;
+      if (base + l < n) cdot_acc(re, im, probe_from_words<T>(words, l), yv[u]);
+    }
   }
   block_sum2<kThreads>(re, im, lds);
   if (threadIdx.x == 0) partials[(int64_t)k * gridDim.x + blockIdx.x] = {re, im};
