@@ -27,12 +27,27 @@ __global__ __launch_bounds__(kThreads) void k_mdot(const T* __restrict__ V, int6
   for (int i0 = 0; i0 < nv; i0 += 4) {
     double re[4] = {0, 0, 0, 0}, im[4] = {0, 0, 0, 0};
     const int gcount = nv - i0 < 4 ? nv - i0 : 4;
-    for (int64_t e = lo + threadIdx.x; e < hi; e += kThreads) {
-      const T we = wk[e];
+    // two elements per step, their ten loads issued before the products, which
+    // accumulate in element order as in a plain strided loop
+    for (int64_t e0 = lo + threadIdx.x; e0 < hi; e0 += 2 * kThreads) {
+      T we[2], ve[2][4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (u < gcount)
-          cdot_acc(re[u], im[u], V[(i0 + u) * vstride + (int64_t)k * n + e], we);
+      for (int q = 0; q < 2; ++q) {
+        const int64_t e = e0 + (int64_t)q * kThreads;
+        const int64_t ec = e < hi ? e : lo;
+        we[q] = wk[ec];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          ve[q][u] = V[(i0 + (u < gcount ? u : 0)) * vstride + (int64_t)k * n + ec];
+      }
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        if (e0 + (int64_t)q * kThreads < hi) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (u < gcount) cdot_acc(re[u], im[u], ve[q][u], we[q]);
+        }
+      }
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -56,6 +71,7 @@ __global__ __launch_bounds__(kThreads) void k_maxpy(const T* __restrict__ V, int
   const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (e >= n) return;
   T acc = w[(int64_t)k * n + e];
+#pragma unroll 4
   for (int i = 0; i < nv; ++i) {
     const c64 c = h[(int64_t)k * nv + i];
     acc -= scale_by(c.re, c.im, V[i * vstride + (int64_t)k * n + e]);
@@ -76,6 +92,7 @@ __global__ __launch_bounds__(kThreads) void k_combine(const T* __restrict__ Z, i
   if (e >= n) return;
   T acc = zero_of(T());
   const int m = dims[k];
+#pragma unroll 4
   for (int i = 0; i < m; ++i) {
     const c64 c = y[(int64_t)k * ldy + i];
     acc += scale_by(c.re, c.im, Z[i * vstride + (int64_t)k * n + e]);
