@@ -508,6 +508,8 @@ __global__ __launch_bounds__(kThreads) void k_agg_restrict(const T* __restrict__
   if (on) {
     for (int yy = w; yy < blk; yy += W) {
       const int64_t i0 = ((int64_t)(Y * blk + yy) * Nf + X * blk) * dofF;
+      // unrolled so that several loads of x are in flight (same order of sums)
+#pragma unroll 4
       for (int a = 0; a < wr; ++a) {
         const T v = xk[i0 + a];
         const T* qi = q + (i0 + a) * DOFC;
